@@ -1,0 +1,1094 @@
+/*
+ * Plain FP64 CPU oracle for the Richards-equation solver of arXiv 2112.05051.
+ *
+ * TEST INFRASTRUCTURE ONLY: used by the test-suite, the smoke check and the
+ * CPU-baseline leg of the benchmark; never by the product library, with which
+ * it shares no code.  Every function is a direct, unblocked transcription of
+ * the definition it cites; where the paper is silent the reading used is
+ * stated in the comment (the same readings are listed in the design doc).
+ *
+ * Pinning: the laws, residual, Jacobian and auxiliary matrix are pinned by the
+ * paper's printed Jacobian entries, central finite differences, mass balance,
+ * the hydrostatic steady state and closed-form spectra (tests/test_oracle_*).
+ * Matching is pinned by brute force on tiny graphs, the V-cycle by the
+ * recursion of Section 5.2 written as dense matrices, GMRES by finite
+ * termination.  The Newton / line-search control flow (orc_solver_step) is
+ * pinned only through invariants (Armijo inequality at every accepted step,
+ * convergence to the residual tolerance, mass balance): its iteration counts
+ * are "parity unpinned" against the paper, whose workload differs.
+ */
+#include "oracle.h"
+
+#include <float.h>
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------ */
+/* Constitutive laws: Section 2, eq. (s(p)) with rho*phi = 1 so s is the     */
+/* volumetric water content theta, eq. (K(p)) with K_s per cell, derivatives  */
+/* eq. (derivativeofcoefficients) with sgn(p) = -1 for p < 0.  Saturated      */
+/* regime p >= 0 (Section 2): K = K_s, theta = theta_s, both derivatives 0.  */
+/* ------------------------------------------------------------------------ */
+void orc_laws(const orc_problem *P, double p, double Ks, double out[4])
+{
+    if (p >= 0.0) {
+        out[0] = P->theta_s;
+        out[1] = 0.0;
+        out[2] = Ks;
+        out[3] = 0.0;
+        return;
+    }
+    double a = -p; /* |p| */
+    double ab = pow(a, P->beta);
+    double ag = pow(a, P->gamma);
+    double ds = P->theta_s - P->theta_r;
+    double dt_den = P->alpha + ab;
+    double dk_den = P->A + ag;
+    out[0] = P->alpha * ds / dt_den + P->theta_r;
+    out[1] = P->alpha * P->beta * ds * pow(a, P->beta - 1.0) / (dt_den * dt_den);
+    out[2] = Ks * P->A / dk_den;
+    out[3] = Ks * P->A * P->gamma * pow(a, P->gamma - 1.0) / (dk_den * dk_den);
+}
+
+void orc_laws_array(const orc_problem *P, int64_t n, const double *p, const double *Ks,
+                    double *out /* n x 4 */)
+{
+    for (int64_t c = 0; c < n; c++)
+        orc_laws(P, p[c], Ks[c], out + 4 * c);
+}
+
+void orc_theta(const orc_problem *P, const double *p, double *theta)
+{
+    int64_t n = (int64_t)P->nx * P->ny * P->nz;
+    double L[4];
+    for (int64_t c = 0; c < n; c++) {
+        orc_laws(P, p[c], 1.0, L);
+        theta[c] = L[0];
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Grid faces.  Face f = 0..5 is -x,+x,-y,+y,-z,+z.  A face either joins two */
+/* unknowns (interior), or touches a Dirichlet boundary node whose head is    */
+/* the face's value and whose K_s is the adjacent cell's (the paper treats K_s */
+/* as a constant), or is a no-flux face, which carries no flux at all.        */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int interior;
+    int64_t n;
+    double pn, Ksn, h;
+    int axis, dir;
+} face_t;
+
+static int face_info(const orc_problem *P, int i, int j, int k, int f, const double *p,
+                     const double *Ks, face_t *F)
+{
+    int axis = f / 2, dir = (f & 1) ? 1 : -1;
+    int ii = i, jj = j, kk = k;
+    if (axis == 0) ii += dir;
+    else if (axis == 1) jj += dir;
+    else kk += dir;
+    F->axis = axis;
+    F->dir = dir;
+    F->h = axis == 0 ? P->hx : (axis == 1 ? P->hy : P->hz);
+    int64_t c = (int64_t)i + (int64_t)P->nx * ((int64_t)j + (int64_t)P->ny * k);
+    if (ii >= 0 && ii < P->nx && jj >= 0 && jj < P->ny && kk >= 0 && kk < P->nz) {
+        F->interior = 1;
+        F->n = (int64_t)ii + (int64_t)P->nx * ((int64_t)jj + (int64_t)P->ny * kk);
+        F->pn = p[F->n];
+        F->Ksn = Ks[F->n];
+        return 1;
+    }
+    if (P->bc_type[f] == ORC_DIRICHLET) {
+        F->interior = 0;
+        F->n = -1;
+        F->pn = P->bc_value[f];
+        F->Ksn = Ks[c];
+        return 1;
+    }
+    return 0;
+}
+
+/* Interface means (Section 2.1): arithmetic, upstream eq. (upstream_mean)   */
+/* with L the lower-index side, U = L + e_d and ties (p_U - p_L = 0) taking  */
+/* K_U; harmonic 2 K_L K_U / (K_L + K_U) (named in the abstract).  Returns   */
+/* the mean and its partial derivatives w.r.t. the cell's and neighbour's    */
+/* heads (the upstream derivative does not differentiate the switch).       */
+static void face_mean(int mean, int dir, double pc, double Kc, double dKc, double pn, double Kn,
+                      double dKn, double *Kf, double *dc, double *dn)
+{
+    if (mean == ORC_ARITH) {
+        *Kf = 0.5 * (Kc + Kn);
+        *dc = 0.5 * dKc;
+        *dn = 0.5 * dKn;
+    } else if (mean == ORC_HARMONIC) {
+        double s = Kc + Kn;
+        *Kf = 2.0 * Kc * Kn / s;
+        *dc = 2.0 * Kn * Kn * dKc / (s * s);
+        *dn = 2.0 * Kc * Kc * dKn / (s * s);
+    } else { /* upstream */
+        double pU, pL;
+        if (dir > 0) { pU = pn; pL = pc; }
+        else { pU = pc; pL = pn; }
+        int take_U = (pU - pL >= 0.0);
+        int take_n = (dir > 0) ? take_U : !take_U;
+        if (take_n) { *Kf = Kn; *dc = 0.0; *dn = dKn; }
+        else { *Kf = Kc; *dc = dKc; *dn = 0.0; }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Residual, eq. (dynamic_of_the_problem) with f = 0, written per face: the  */
+/* diffusive flux -K^AV (p_n - p_c)/h^2 and, on z faces, the gravity part    */
+/* s*(-(K_c+K_n)/(2 h_z)) with s = +1 for the face above.  Summed over the   */
+/* two z faces of an interior cell this is exactly the paper's centred term  */
+/* -(K_{k+1} - K_{k-1})/(2 h_z); at a no-flux face nothing is added.        */
+/* ------------------------------------------------------------------------ */
+void orc_residual(const orc_problem *P, const double *Ks, const double *p, const double *theta_old,
+                  double *F)
+{
+    double Lc[4], Ln[4];
+    for (int k = 0; k < P->nz; k++)
+        for (int j = 0; j < P->ny; j++)
+            for (int i = 0; i < P->nx; i++) {
+                int64_t c = (int64_t)i + (int64_t)P->nx * ((int64_t)j + (int64_t)P->ny * k);
+                orc_laws(P, p[c], Ks[c], Lc);
+                double acc = (Lc[0] - theta_old[c]) / P->dt;
+                for (int f = 0; f < 6; f++) {
+                    face_t fc;
+                    if (!face_info(P, i, j, k, f, p, Ks, &fc)) continue;
+                    orc_laws(P, fc.pn, fc.Ksn, Ln);
+                    double Kf, dc, dn;
+                    face_mean(P->mean, fc.dir, p[c], Lc[2], Lc[3], fc.pn, Ln[2], Ln[3], &Kf, &dc, &dn);
+                    acc += -Kf * (fc.pn - p[c]) / (fc.h * fc.h);
+                    if (fc.axis == 2) acc += fc.dir * (-(Lc[2] + Ln[2]) / (2.0 * P->hz));
+                }
+                F[c] = acc;
+            }
+}
+
+/* Fixed 7-point pattern: the cell and its interior neighbours, columns in  */
+/* increasing order (-z, -y, -x, c, +x, +y, +z).                            */
+int64_t orc_pattern_nnz(const orc_problem *P)
+{
+    int64_t nnz = 0;
+    for (int k = 0; k < P->nz; k++)
+        for (int j = 0; j < P->ny; j++)
+            for (int i = 0; i < P->nx; i++)
+                nnz += 1 + (i > 0) + (i < P->nx - 1) + (j > 0) + (j < P->ny - 1) + (k > 0) +
+                       (k < P->nz - 1);
+    return nnz;
+}
+
+static const int ORDER_LO[3] = {4, 2, 0}; /* -z, -y, -x */
+static const int ORDER_HI[3] = {1, 3, 5}; /* +x, +y, +z */
+
+/* which = 0: Jacobian of the residual; which = 1: auxiliary matrix. */
+static void assemble(const orc_problem *P, const double *Ks, const double *p, int which,
+                     int64_t *rowptr, int32_t *col, double *val)
+{
+    double Lc[4], Ln[4];
+    int64_t e = 0;
+    rowptr[0] = 0;
+    for (int k = 0; k < P->nz; k++)
+        for (int j = 0; j < P->ny; j++)
+            for (int i = 0; i < P->nx; i++) {
+                int64_t c = (int64_t)i + (int64_t)P->nx * ((int64_t)j + (int64_t)P->ny * k);
+                orc_laws(P, p[c], Ks[c], Lc);
+                double diag = Lc[1] / P->dt;
+                double off[6];
+                int64_t nb[6];
+                int has[6] = {0, 0, 0, 0, 0, 0};
+                for (int f = 0; f < 6; f++) {
+                    face_t fc;
+                    if (!face_info(P, i, j, k, f, p, Ks, &fc)) continue;
+                    orc_laws(P, fc.pn, fc.Ksn, Ln);
+                    double Kf, dc, dn;
+                    face_mean(P->mean, fc.dir, p[c], Lc[2], Lc[3], fc.pn, Ln[2], Ln[3], &Kf, &dc, &dn);
+                    double h2 = fc.h * fc.h;
+                    double dp = fc.pn - p[c];
+                    if (which == 0) {
+                        /* d/dp_c and d/dp_n of -Kf*dp/h^2 + [z] s*(-(Kc+Kn)/(2hz)) */
+                        diag += Kf / h2 - dp / h2 * dc;
+                        if (fc.axis == 2) diag += -fc.dir * Lc[3] / (2.0 * P->hz);
+                        if (fc.interior) {
+                            double v = -Kf / h2 - dp / h2 * dn;
+                            if (fc.axis == 2) v += -fc.dir * Ln[3] / (2.0 * P->hz);
+                            off[f] = v;
+                            nb[f] = fc.n;
+                            has[f] = 1;
+                        }
+                    } else {
+                        /* Section 4 / 5.2: Jacobian of the diffusion-only operator with the
+                         * conductivity frozen (q_prec = -K grad p), plus the time term. */
+                        diag += Kf / h2;
+                        if (fc.interior) {
+                            off[f] = -Kf / h2;
+                            nb[f] = fc.n;
+                            has[f] = 1;
+                        }
+                    }
+                }
+                for (int t = 0; t < 3; t++)
+                    if (has[ORDER_LO[t]]) {
+                        col[e] = (int32_t)nb[ORDER_LO[t]];
+                        val[e++] = off[ORDER_LO[t]];
+                    }
+                col[e] = (int32_t)c;
+                val[e++] = diag;
+                for (int t = 0; t < 3; t++)
+                    if (has[ORDER_HI[t]]) {
+                        col[e] = (int32_t)nb[ORDER_HI[t]];
+                        val[e++] = off[ORDER_HI[t]];
+                    }
+                rowptr[c + 1] = e;
+            }
+}
+
+void orc_jacobian(const orc_problem *P, const double *Ks, const double *p, int64_t *rowptr,
+                  int32_t *col, double *val)
+{
+    assemble(P, Ks, p, 0, rowptr, col, val);
+}
+
+void orc_auxiliary(const orc_problem *P, const double *Ks, const double *p, int64_t *rowptr,
+                   int32_t *col, double *val)
+{
+    assemble(P, Ks, p, 1, rowptr, col, val);
+}
+
+void orc_csr_matvec(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
+                    const double *x, double *y)
+{
+    for (int64_t i = 0; i < n; i++) {
+        double s = 0.0;
+        for (int64_t e = rowptr[i]; e < rowptr[i + 1]; e++) s += val[e] * x[col[e]];
+        y[i] = s;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Pairwise matching (Section 5.2, SMATCH: aggregation by maximum-weight     */
+/* graph matching; the weight is not printed in the paper).  Reading: edge   */
+/* {i,j}, i<j, with a_ij != 0 in row i has weight                            */
+/*     w_ij = 1 - 2 a_ij / (a_ii + a_jj)                                      */
+/* (the matching weight of D'Ambra-Vassilevski with a constant smooth        */
+/* vector).  Edges are taken greedily in the strict order (w desc, i asc,    */
+/* j asc); a vertex left unmatched is a singleton.  Coarse indices are given */
+/* in increasing order of the smallest member.                              */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    double w;
+    int64_t i, j;
+} edge_t;
+
+static int edge_cmp(const void *a, const void *b)
+{
+    const edge_t *x = (const edge_t *)a, *y = (const edge_t *)b;
+    if (x->w > y->w) return -1;
+    if (x->w < y->w) return 1;
+    if (x->i < y->i) return -1;
+    if (x->i > y->i) return 1;
+    if (x->j < y->j) return -1;
+    if (x->j > y->j) return 1;
+    return 0;
+}
+
+int64_t orc_match_sweep(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
+                        int32_t *agg)
+{
+    double *diag = (double *)calloc((size_t)n, sizeof(double));
+    int64_t *mate = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    int64_t ne = 0;
+    for (int64_t i = 0; i < n; i++)
+        for (int64_t e = rowptr[i]; e < rowptr[i + 1]; e++) {
+            if (col[e] == i) diag[i] = val[e];
+            else if (col[e] > i && val[e] != 0.0) ne++;
+        }
+    edge_t *E = (edge_t *)malloc((size_t)(ne > 0 ? ne : 1) * sizeof(edge_t));
+    int64_t m = 0;
+    for (int64_t i = 0; i < n; i++)
+        for (int64_t e = rowptr[i]; e < rowptr[i + 1]; e++) {
+            int64_t j = col[e];
+            if (j > i && val[e] != 0.0) {
+                double w = 1.0 - (2.0 * val[e]) / (diag[i] + diag[j]);
+                if (!isfinite(w)) continue;
+                E[m].w = w;
+                E[m].i = i;
+                E[m].j = j;
+                m++;
+            }
+        }
+    qsort(E, (size_t)m, sizeof(edge_t), edge_cmp);
+    for (int64_t i = 0; i < n; i++) mate[i] = -1;
+    for (int64_t t = 0; t < m; t++)
+        if (mate[E[t].i] < 0 && mate[E[t].j] < 0) {
+            mate[E[t].i] = E[t].j;
+            mate[E[t].j] = E[t].i;
+        }
+    int64_t nc = 0;
+    for (int64_t i = 0; i < n; i++) {
+        if (mate[i] < 0 || i < mate[i]) agg[i] = (int32_t)(nc++);
+        else agg[i] = agg[mate[i]];
+    }
+    free(E);
+    free(mate);
+    free(diag);
+    return nc;
+}
+
+/* Galerkin product with a piecewise-constant prolongator (Section 5.2,      */
+/* M_{l+1} = P^T M_l P):  C_IJ = sum over i in I, j in J of a_ij.  The terms  */
+/* are accumulated in a fixed order, fine rows ascending and each row in its */
+/* column order, so that the result is reproducible bit for bit.            */
+static void members_of(int64_t n, const int32_t *agg, int64_t nc, int64_t **mptr_out,
+                       int64_t **mem_out)
+{
+    int64_t *mptr = (int64_t *)calloc((size_t)nc + 1, sizeof(int64_t));
+    int64_t *mem = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    for (int64_t i = 0; i < n; i++) mptr[agg[i] + 1]++;
+    for (int64_t I = 0; I < nc; I++) mptr[I + 1] += mptr[I];
+    int64_t *fill = (int64_t *)malloc((size_t)(nc > 0 ? nc : 1) * sizeof(int64_t));
+    for (int64_t I = 0; I < nc; I++) fill[I] = mptr[I];
+    for (int64_t i = 0; i < n; i++) mem[fill[agg[i]]++] = i;
+    free(fill);
+    *mptr_out = mptr;
+    *mem_out = mem;
+}
+
+static int cmp_i32(const void *a, const void *b)
+{
+    int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+    return (x > y) - (x < y);
+}
+
+int64_t orc_galerkin_nnz(int64_t n, const int64_t *rowptr, const int32_t *col, const int32_t *agg,
+                         int64_t nc)
+{
+    int64_t *mptr, *mem;
+    members_of(n, agg, nc, &mptr, &mem);
+    int64_t *mark = (int64_t *)malloc((size_t)(nc > 0 ? nc : 1) * sizeof(int64_t));
+    for (int64_t I = 0; I < nc; I++) mark[I] = -1;
+    int64_t nnz = 0;
+    for (int64_t I = 0; I < nc; I++)
+        for (int64_t t = mptr[I]; t < mptr[I + 1]; t++) {
+            int64_t i = mem[t];
+            for (int64_t e = rowptr[i]; e < rowptr[i + 1]; e++) {
+                int64_t J = agg[col[e]];
+                if (mark[J] != I) {
+                    mark[J] = I;
+                    nnz++;
+                }
+            }
+        }
+    free(mark);
+    free(mptr);
+    free(mem);
+    return nnz;
+}
+
+void orc_galerkin(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
+                  const int32_t *agg, int64_t nc, int64_t *crow, int32_t *ccol, double *cval)
+{
+    int64_t *mptr, *mem;
+    members_of(n, agg, nc, &mptr, &mem);
+    int64_t *mark = (int64_t *)malloc((size_t)(nc > 0 ? nc : 1) * sizeof(int64_t));
+    double *acc = (double *)malloc((size_t)(nc > 0 ? nc : 1) * sizeof(double));
+    int32_t *list = (int32_t *)malloc((size_t)(nc > 0 ? nc : 1) * sizeof(int32_t));
+    for (int64_t I = 0; I < nc; I++) mark[I] = -1;
+    int64_t e_out = 0;
+    crow[0] = 0;
+    for (int64_t I = 0; I < nc; I++) {
+        int64_t len = 0;
+        for (int64_t t = mptr[I]; t < mptr[I + 1]; t++) {
+            int64_t i = mem[t];
+            for (int64_t e = rowptr[i]; e < rowptr[i + 1]; e++) {
+                int32_t J = agg[col[e]];
+                if (mark[J] != I) {
+                    mark[J] = I;
+                    acc[J] = 0.0;
+                    list[len++] = J;
+                }
+                acc[J] += val[e];
+            }
+        }
+        qsort(list, (size_t)len, sizeof(int32_t), cmp_i32);
+        for (int64_t t = 0; t < len; t++) {
+            ccol[e_out] = list[t];
+            cval[e_out++] = acc[list[t]];
+        }
+        crow[I + 1] = e_out;
+    }
+    free(list);
+    free(acc);
+    free(mark);
+    free(mptr);
+    free(mem);
+}
+
+/* ------------------------------------------------------------------------ */
+/* AMG hierarchy (Section 5.2).  Level l+1 comes from `amg_sweeps` pairwise  */
+/* matching sweeps on level l, each followed by the piecewise-constant       */
+/* Galerkin product, so aggregates hold at most 2^sweeps unknowns (the paper */
+/* caps SMATCH aggregates at 8, i.e. three sweeps).  Coarsening stops when   */
+/* a level has at most amg_coarse_size rows or amg_max_levels levels exist. */
+/* Smoother: l1-Jacobi, D_ii = sum_j |a_ij| (reading of the paper's "l1-     */
+/* Jacobi").  Coarsest: dense Cholesky when n <= coarse_dense_max, else      */
+/* coarse_l1_sweeps l1-Jacobi sweeps from zero (both keep M^{-1} linear).    */
+/* ------------------------------------------------------------------------ */
+#define ORC_MAXLEV 32
+struct orc_amg {
+    int nlev;
+    orc_csr A[ORC_MAXLEV];
+    int32_t *agg[ORC_MAXLEV];
+    double *l1[ORC_MAXLEV];
+    int dense;
+    double *chol; /* n_c x n_c, row-major lower factor */
+    int coarse_sweeps;
+};
+
+static void csr_free(orc_csr *A)
+{
+    free(A->rowptr);
+    free(A->col);
+    free(A->val);
+    A->rowptr = NULL;
+    A->col = NULL;
+    A->val = NULL;
+}
+
+static void l1_diag(const orc_csr *A, double *d)
+{
+    for (int64_t i = 0; i < A->n; i++) {
+        double s = 0.0;
+        for (int64_t e = A->rowptr[i]; e < A->rowptr[i + 1]; e++) s += fabs(A->val[e]);
+        d[i] = s;
+    }
+}
+
+static int dense_cholesky(const orc_csr *A, double **out)
+{
+    int64_t n = A->n;
+    double *L = (double *)calloc((size_t)(n * n > 0 ? n * n : 1), sizeof(double));
+    for (int64_t i = 0; i < n; i++)
+        for (int64_t e = A->rowptr[i]; e < A->rowptr[i + 1]; e++)
+            if (A->col[e] <= i) L[i * n + A->col[e]] = A->val[e];
+    for (int64_t j = 0; j < n; j++) {
+        double s = L[j * n + j];
+        for (int64_t k = 0; k < j; k++) s -= L[j * n + k] * L[j * n + k];
+        if (!(s > 0.0)) {
+            free(L);
+            return ORC_NOT_SPD;
+        }
+        double d = sqrt(s);
+        L[j * n + j] = d;
+        for (int64_t i = j + 1; i < n; i++) {
+            double t = L[i * n + j];
+            for (int64_t k = 0; k < j; k++) t -= L[i * n + k] * L[j * n + k];
+            L[i * n + j] = t / d;
+        }
+    }
+    *out = L;
+    return ORC_OK;
+}
+
+static void csr_copy(const orc_csr *S, orc_csr *D)
+{
+    D->n = S->n;
+    int64_t nnz = S->rowptr[S->n];
+    D->rowptr = (int64_t *)malloc((size_t)(S->n + 1) * sizeof(int64_t));
+    D->col = (int32_t *)malloc((size_t)(nnz > 0 ? nnz : 1) * sizeof(int32_t));
+    D->val = (double *)malloc((size_t)(nnz > 0 ? nnz : 1) * sizeof(double));
+    memcpy(D->rowptr, S->rowptr, (size_t)(S->n + 1) * sizeof(int64_t));
+    memcpy(D->col, S->col, (size_t)nnz * sizeof(int32_t));
+    memcpy(D->val, S->val, (size_t)nnz * sizeof(double));
+}
+
+static void galerkin_alloc(const orc_csr *A, const int32_t *agg, int64_t nc, orc_csr *C)
+{
+    int64_t nnz = orc_galerkin_nnz(A->n, A->rowptr, A->col, agg, nc);
+    C->n = nc;
+    C->rowptr = (int64_t *)malloc((size_t)(nc + 1) * sizeof(int64_t));
+    C->col = (int32_t *)malloc((size_t)(nnz > 0 ? nnz : 1) * sizeof(int32_t));
+    C->val = (double *)malloc((size_t)(nnz > 0 ? nnz : 1) * sizeof(double));
+    orc_galerkin(A->n, A->rowptr, A->col, A->val, agg, nc, C->rowptr, C->col, C->val);
+}
+
+int orc_amg_build(const orc_opts *O, int64_t n, const int64_t *rowptr, const int32_t *col,
+                  const double *val, orc_amg **out)
+{
+    orc_amg *H = (orc_amg *)calloc(1, sizeof(orc_amg));
+    orc_csr fine = {n, (int64_t *)rowptr, (int32_t *)col, (double *)val};
+    csr_copy(&fine, &H->A[0]);
+    int l = 0;
+    int maxl = O->amg_max_levels < ORC_MAXLEV ? O->amg_max_levels : ORC_MAXLEV;
+    while (l + 1 < maxl && H->A[l].n > O->amg_coarse_size) {
+        orc_csr cur = H->A[l];
+        int own = 0; /* whether cur is a temporary */
+        int32_t *comp = (int32_t *)malloc((size_t)(H->A[l].n > 0 ? H->A[l].n : 1) * sizeof(int32_t));
+        for (int64_t i = 0; i < H->A[l].n; i++) comp[i] = (int32_t)i;
+        for (int s = 0; s < O->amg_sweeps; s++) {
+            int32_t *a = (int32_t *)malloc((size_t)(cur.n > 0 ? cur.n : 1) * sizeof(int32_t));
+            int64_t nc = orc_match_sweep(cur.n, cur.rowptr, cur.col, cur.val, a);
+            if (nc == cur.n) {
+                free(a);
+                break;
+            }
+            orc_csr nxt;
+            galerkin_alloc(&cur, a, nc, &nxt);
+            for (int64_t i = 0; i < H->A[l].n; i++) comp[i] = a[comp[i]];
+            free(a);
+            if (own) csr_free(&cur);
+            cur = nxt;
+            own = 1;
+        }
+        if (!own) {
+            free(comp);
+            break;
+        }
+        H->agg[l] = comp;
+        H->A[l + 1] = cur;
+        l++;
+    }
+    H->nlev = l + 1;
+    for (int t = 0; t < H->nlev; t++) {
+        H->l1[t] = (double *)malloc((size_t)(H->A[t].n > 0 ? H->A[t].n : 1) * sizeof(double));
+        l1_diag(&H->A[t], H->l1[t]);
+    }
+    H->coarse_sweeps = O->coarse_l1_sweeps;
+    H->dense = H->A[H->nlev - 1].n <= O->coarse_dense_max;
+    if (H->dense) {
+        int st = dense_cholesky(&H->A[H->nlev - 1], &H->chol);
+        if (st != ORC_OK) {
+            orc_amg_destroy(H);
+            return st;
+        }
+    }
+    *out = H;
+    return ORC_OK;
+}
+
+int orc_amg_update_fine(orc_amg *H, const double *val)
+{
+    memcpy(H->A[0].val, val, (size_t)H->A[0].rowptr[H->A[0].n] * sizeof(double));
+    l1_diag(&H->A[0], H->l1[0]);
+    if (H->nlev == 1 && H->dense) {
+        free(H->chol);
+        H->chol = NULL;
+        return dense_cholesky(&H->A[0], &H->chol);
+    }
+    return ORC_OK;
+}
+
+int orc_amg_levels(const orc_amg *H) { return H->nlev; }
+
+void orc_amg_level_info(const orc_amg *H, int l, int64_t *n, int64_t *nnz)
+{
+    *n = H->A[l].n;
+    *nnz = H->A[l].rowptr[H->A[l].n];
+}
+
+void orc_amg_level_export(const orc_amg *H, int l, int64_t *rowptr, int32_t *col, double *val,
+                          int32_t *agg)
+{
+    const orc_csr *A = &H->A[l];
+    memcpy(rowptr, A->rowptr, (size_t)(A->n + 1) * sizeof(int64_t));
+    memcpy(col, A->col, (size_t)A->rowptr[A->n] * sizeof(int32_t));
+    memcpy(val, A->val, (size_t)A->rowptr[A->n] * sizeof(double));
+    if (agg && l < H->nlev - 1) memcpy(agg, H->agg[l], (size_t)A->n * sizeof(int32_t));
+}
+
+int orc_amg_coarse_is_dense(const orc_amg *H) { return H->dense; }
+
+void orc_amg_destroy(orc_amg *H)
+{
+    if (!H) return;
+    for (int l = 0; l < H->nlev; l++) {
+        csr_free(&H->A[l]);
+        free(H->agg[l]);
+        free(H->l1[l]);
+    }
+    free(H->chol);
+    free(H);
+}
+
+static void coarse_solve(const orc_amg *H, const double *b, double *x)
+{
+    const orc_csr *A = &H->A[H->nlev - 1];
+    int64_t n = A->n;
+    if (H->dense) {
+        const double *L = H->chol;
+        for (int64_t i = 0; i < n; i++) { /* L y = b */
+            double s = b[i];
+            for (int64_t k = 0; k < i; k++) s -= L[i * n + k] * x[k];
+            x[i] = s / L[i * n + i];
+        }
+        for (int64_t i = n - 1; i >= 0; i--) { /* L^T x = y */
+            double s = x[i];
+            for (int64_t k = i + 1; k < n; k++) s -= L[k * n + i] * x[k];
+            x[i] = s / L[i * n + i];
+        }
+        return;
+    }
+    const double *d = H->l1[H->nlev - 1];
+    double *r = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    for (int64_t i = 0; i < n; i++) x[i] = 0.0;
+    for (int s = 0; s < H->coarse_sweeps; s++) {
+        orc_csr_matvec(n, A->rowptr, A->col, A->val, x, r);
+        for (int64_t i = 0; i < n; i++) x[i] += (b[i] - r[i]) / d[i];
+    }
+    free(r);
+}
+
+/* Symmetric V-cycle of Section 5.2 with one l1-Jacobi sweep before and after */
+/* the coarse correction; the pre-sweep starts from x = 0.                    */
+static void vcycle(const orc_amg *H, int l, const double *b, double *x)
+{
+    if (l == H->nlev - 1) {
+        coarse_solve(H, b, x);
+        return;
+    }
+    const orc_csr *A = &H->A[l];
+    int64_t n = A->n, nc = H->A[l + 1].n;
+    const double *d = H->l1[l];
+    const int32_t *agg = H->agg[l];
+    double *r = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    double *bc = (double *)calloc((size_t)(nc > 0 ? nc : 1), sizeof(double));
+    double *xc = (double *)malloc((size_t)(nc > 0 ? nc : 1) * sizeof(double));
+    for (int64_t i = 0; i < n; i++) x[i] = b[i] / d[i];
+    orc_csr_matvec(n, A->rowptr, A->col, A->val, x, r);
+    for (int64_t i = 0; i < n; i++) r[i] = b[i] - r[i];
+    for (int64_t i = 0; i < n; i++) bc[agg[i]] += r[i];
+    vcycle(H, l + 1, bc, xc);
+    for (int64_t i = 0; i < n; i++) x[i] += xc[agg[i]];
+    orc_csr_matvec(n, A->rowptr, A->col, A->val, x, r);
+    for (int64_t i = 0; i < n; i++) x[i] += (b[i] - r[i]) / d[i];
+    free(r);
+    free(bc);
+    free(xc);
+}
+
+void orc_amg_apply(const orc_amg *H, const double *b, double *x) { vcycle(H, 0, b, x); }
+
+/* ------------------------------------------------------------------------ */
+/* Restarted GMRES(m), right preconditioned (eq. (precsystem)): Arnoldi on   */
+/* J M^{-1} with modified Gram-Schmidt, Givens rotations for the least-      */
+/* squares problem, x += M^{-1} V y at the end of each cycle, and the true   */
+/* residual recomputed at every restart.  Stops when ||b - J x||_2 <=        */
+/* eta ||b||_2 (Section 6) or after maxit Arnoldi steps.  Returns 1 when     */
+/* converged, 0 otherwise.                                                   */
+/* ------------------------------------------------------------------------ */
+static double dot(int64_t n, const double *a, const double *b)
+{
+    double s = 0.0;
+    for (int64_t i = 0; i < n; i++) s += a[i] * b[i];
+    return s;
+}
+
+int orc_gmres(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
+              const orc_amg *H, const double *b, double *x, int restart, double eta, int maxit,
+              int *its_out, double *relres_out)
+{
+    int m = restart;
+    double *V = (double *)malloc((size_t)(m + 1) * (size_t)(n > 0 ? n : 1) * sizeof(double));
+    double *Hm = (double *)calloc((size_t)(m + 1) * m, sizeof(double));
+    double *cs = (double *)calloc((size_t)m, sizeof(double));
+    double *sn = (double *)calloc((size_t)m, sizeof(double));
+    double *g = (double *)calloc((size_t)m + 1, sizeof(double));
+    double *y = (double *)calloc((size_t)m, sizeof(double));
+    double *z = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    double *w = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    double bnorm = sqrt(dot(n, b, b));
+    int total = 0, conv = 0;
+    double relres = 0.0;
+    for (int64_t i = 0; i < n; i++) x[i] = 0.0;
+    if (bnorm == 0.0) {
+        conv = 1;
+        goto done;
+    }
+    for (;;) {
+        /* true residual r = b - J x, kept in V_0 */
+        orc_csr_matvec(n, rowptr, col, val, x, w);
+        for (int64_t i = 0; i < n; i++) V[i] = b[i] - w[i];
+        double beta = sqrt(dot(n, V, V));
+        relres = beta / bnorm;
+        if (beta <= eta * bnorm) {
+            conv = 1;
+            break;
+        }
+        if (total >= maxit) break;
+        for (int64_t i = 0; i < n; i++) V[i] /= beta;
+        for (int i = 0; i <= m; i++) g[i] = 0.0;
+        g[0] = beta;
+        int k = 0;
+        for (int j = 0; j < m && total < maxit; j++) {
+            double *vj = V + (size_t)j * n;
+            if (H) orc_amg_apply(H, vj, z);
+            else memcpy(z, vj, (size_t)n * sizeof(double));
+            orc_csr_matvec(n, rowptr, col, val, z, w);
+            for (int i = 0; i <= j; i++) {
+                double *vi = V + (size_t)i * n;
+                double h = dot(n, w, vi);
+                Hm[i * m + j] = h;
+                for (int64_t t = 0; t < n; t++) w[t] -= h * vi[t];
+            }
+            double hn = sqrt(dot(n, w, w));
+            Hm[(j + 1) * m + j] = hn;
+            if (hn > 0.0) {
+                double *vn = V + (size_t)(j + 1) * n;
+                for (int64_t t = 0; t < n; t++) vn[t] = w[t] / hn;
+            }
+            for (int i = 0; i < j; i++) {
+                double a = Hm[i * m + j], c = Hm[(i + 1) * m + j];
+                Hm[i * m + j] = cs[i] * a + sn[i] * c;
+                Hm[(i + 1) * m + j] = -sn[i] * a + cs[i] * c;
+            }
+            double a = Hm[j * m + j], c = Hm[(j + 1) * m + j];
+            double rho = sqrt(a * a + c * c);
+            cs[j] = a / rho;
+            sn[j] = c / rho;
+            Hm[j * m + j] = rho;
+            Hm[(j + 1) * m + j] = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            total++;
+            k = j + 1;
+            if (fabs(g[j + 1]) <= eta * bnorm || hn == 0.0) break;
+        }
+        for (int i = k - 1; i >= 0; i--) { /* back substitution */
+            double s = g[i];
+            for (int t = i + 1; t < k; t++) s -= Hm[i * m + t] * y[t];
+            y[i] = s / Hm[i * m + i];
+        }
+        for (int64_t t = 0; t < n; t++) w[t] = 0.0;
+        for (int i = 0; i < k; i++) {
+            double *vi = V + (size_t)i * n;
+            for (int64_t t = 0; t < n; t++) w[t] += y[i] * vi[t];
+        }
+        if (H) orc_amg_apply(H, w, z);
+        else memcpy(z, w, (size_t)n * sizeof(double));
+        for (int64_t t = 0; t < n; t++) x[t] += z[t];
+    }
+done:
+    *its_out = total;
+    *relres_out = relres;
+    free(V);
+    free(Hm);
+    free(cs);
+    free(sn);
+    free(g);
+    free(y);
+    free(z);
+    free(w);
+    return conv;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Backward Euler (Section 2.1) + modified inexact Newton (Section 3).       */
+/* ------------------------------------------------------------------------ */
+struct orc_solver {
+    orc_problem P;
+    orc_opts O;
+    int64_t N, nnz;
+    double *Ks;
+    orc_csr J, M;
+    orc_amg *H;
+    int have_J;
+    int since_build;
+    double *theta_old, *u, *F, *ut, *Ft, *d, *Jd, *ub, *Fb;
+};
+
+static double norm_inf(int64_t n, const double *v)
+{
+    double m = 0.0;
+    for (int64_t i = 0; i < n; i++) {
+        double a = fabs(v[i]);
+        if (a > m || a != a) m = a;
+    }
+    return m;
+}
+
+static int all_finite(int64_t n, const double *v)
+{
+    for (int64_t i = 0; i < n; i++)
+        if (!isfinite(v[i])) return 0;
+    return 1;
+}
+
+int orc_solver_create(const orc_problem *P, const orc_opts *O, const double *Ks, orc_solver **out)
+{
+    if (P->nx < 1 || P->ny < 1 || P->nz < 1 || !(P->hx > 0) || !(P->hy > 0) || !(P->hz > 0) ||
+        !(P->dt > 0) || O->gmres_restart < 1)
+        return ORC_EINVAL;
+    orc_solver *S = (orc_solver *)calloc(1, sizeof(orc_solver));
+    S->P = *P;
+    S->O = *O;
+    S->N = (int64_t)P->nx * P->ny * P->nz;
+    S->nnz = orc_pattern_nnz(P);
+    int64_t N = S->N;
+    S->Ks = (double *)malloc((size_t)N * sizeof(double));
+    memcpy(S->Ks, Ks, (size_t)N * sizeof(double));
+    S->J.n = S->M.n = N;
+    S->J.rowptr = (int64_t *)malloc((size_t)(N + 1) * sizeof(int64_t));
+    S->M.rowptr = (int64_t *)malloc((size_t)(N + 1) * sizeof(int64_t));
+    S->J.col = (int32_t *)malloc((size_t)S->nnz * sizeof(int32_t));
+    S->M.col = (int32_t *)malloc((size_t)S->nnz * sizeof(int32_t));
+    S->J.val = (double *)malloc((size_t)S->nnz * sizeof(double));
+    S->M.val = (double *)malloc((size_t)S->nnz * sizeof(double));
+    double **vecs[] = {&S->theta_old, &S->u, &S->F, &S->ut, &S->Ft, &S->d, &S->Jd, &S->ub, &S->Fb};
+    for (size_t t = 0; t < sizeof(vecs) / sizeof(vecs[0]); t++)
+        *vecs[t] = (double *)malloc((size_t)N * sizeof(double));
+    *out = S;
+    return ORC_OK;
+}
+
+void orc_solver_destroy(orc_solver *S)
+{
+    if (!S) return;
+    free(S->Ks);
+    csr_free(&S->J);
+    csr_free(&S->M);
+    orc_amg_destroy(S->H);
+    double *vecs[] = {S->theta_old, S->u, S->F, S->ut, S->Ft, S->d, S->Jd, S->ub, S->Fb};
+    for (size_t t = 0; t < sizeof(vecs) / sizeof(vecs[0]); t++) free(vecs[t]);
+    free(S);
+}
+
+/* Rebuild J and the auxiliary matrix at u.  The AMG hierarchy is built on   */
+/* the first auxiliary matrix of the run only; later rebuilds refresh the    */
+/* fine-level matrix and its smoother (Section 6, re-use strategy).          */
+static int rebuild(orc_solver *S, const double *u, orc_stats *st)
+{
+    orc_jacobian(&S->P, S->Ks, u, S->J.rowptr, S->J.col, S->J.val);
+    orc_auxiliary(&S->P, S->Ks, u, S->M.rowptr, S->M.col, S->M.val);
+    int rc = ORC_OK;
+    if (!S->H) {
+        rc = orc_amg_build(&S->O, S->N, S->M.rowptr, S->M.col, S->M.val, &S->H);
+        st->amg_setups++;
+    } else {
+        rc = orc_amg_update_fine(S->H, S->M.val);
+    }
+    S->have_J = 1;
+    S->since_build = 0;
+    st->jac_builds++;
+    return rc;
+}
+
+static double half_sq(int64_t n, const double *v) { return 0.5 * dot(n, v, v); }
+
+/* Relative length of a step: max_i |s_i| / max(|u_i|, 1) (identity scaling). */
+static double rel_length(int64_t n, const double *s, double lam, const double *u)
+{
+    double m = 0.0;
+    for (int64_t i = 0; i < n; i++) {
+        double a = fabs(u[i]);
+        double r = fabs(lam * s[i]) / (a > 1.0 ? a : 1.0);
+        if (r > m) m = r;
+    }
+    return m;
+}
+
+/*
+ * Line search (Section 3, Armijo-Goldstein): backtracking in the style of
+ * Dennis & Schnabel's Algorithm A6.3.1 (a published method).  The alpha
+ * condition f(u + lam d) <= f0 + alpha lam slope is enforced with f = 0.5
+ * ||Phi||^2 and slope = Phi^T (J d); the first reduction minimises the
+ * quadratic model, later ones the cubic model through the last two trials,
+ * each clamped to [0.1 lam, 0.5 lam].  The beta condition (beta = 0.9) is
+ * checked when the full step satisfies the alpha condition and is shorter
+ * than the maximum step: lam is then doubled while the alpha condition still
+ * holds, the beta condition fails and the step stays within the maximum.
+ * Fails when lam drops below scsteptol / rel_length(d).
+ * On success u+lam d is in S->ut and its residual in S->Ft.
+ */
+static int line_search(orc_solver *S, double slope, double mxstep, int truncated, double *lam_out,
+                       int *nback)
+{
+    int64_t N = S->N;
+    const double alpha = S->O.ls_alpha, beta = 0.9;
+    double f0 = half_sq(N, S->F);
+    double rl = rel_length(N, S->d, 1.0, S->u);
+    double lam_min = rl > 0.0 ? S->O.scsteptol / rl : 0.0;
+    double lam = 1.0, lam_prev = 0.0, f_prev = 0.0;
+    int first = 1;
+    *nback = 0;
+    for (;;) {
+        for (int64_t i = 0; i < N; i++) S->ut[i] = S->u[i] + lam * S->d[i];
+        orc_residual(&S->P, S->Ks, S->ut, S->theta_old, S->Ft);
+        double ft = half_sq(N, S->Ft);
+        if (isfinite(ft) && ft <= f0 + alpha * lam * slope) break;
+        if (lam < lam_min) return ORC_LINESEARCH_FAIL;
+        double lt;
+        if (!isfinite(ft)) {
+            lt = 0.1 * lam;
+        } else if (first) {
+            lt = -slope / (2.0 * (ft - f0 - slope));
+            first = 0;
+        } else {
+            double t1 = ft - f0 - lam * slope;
+            double t2 = f_prev - f0 - lam_prev * slope;
+            double a = (t1 / (lam * lam) - t2 / (lam_prev * lam_prev)) / (lam - lam_prev);
+            double b = (-lam_prev * t1 / (lam * lam) + lam * t2 / (lam_prev * lam_prev)) /
+                       (lam - lam_prev);
+            if (a == 0.0) {
+                lt = -slope / (2.0 * b);
+            } else {
+                double disc = b * b - 3.0 * a * slope;
+                lt = disc < 0.0 ? 0.5 * lam : (-b + sqrt(disc)) / (3.0 * a);
+            }
+        }
+        if (isfinite(ft)) {
+            lam_prev = lam;
+            f_prev = ft;
+        }
+        if (!(lt <= 0.5 * lam)) lt = 0.5 * lam;
+        if (!(lt >= 0.1 * lam)) lt = 0.1 * lam;
+        lam = lt;
+        (*nback)++;
+    }
+    /* beta condition, full step only, when a longer step is allowed */
+    if (lam == 1.0 && !truncated) {
+        double dn = sqrt(dot(N, S->d, S->d));
+        double ft = half_sq(N, S->Ft);
+        int tries = 0;
+        while (ft < f0 + beta * lam * slope && 2.0 * lam * dn <= mxstep && tries < 10) {
+            double lt = 2.0 * lam;
+            for (int64_t i = 0; i < N; i++) S->ub[i] = S->u[i] + lt * S->d[i];
+            orc_residual(&S->P, S->Ks, S->ub, S->theta_old, S->Fb);
+            double fb = half_sq(N, S->Fb);
+            if (!(isfinite(fb) && fb <= f0 + alpha * lt * slope)) break;
+            lam = lt;
+            ft = fb;
+            memcpy(S->ut, S->ub, (size_t)N * sizeof(double));
+            memcpy(S->Ft, S->Fb, (size_t)N * sizeof(double));
+            tries++;
+        }
+    }
+    *lam_out = lam;
+    return ORC_OK;
+}
+
+/*
+ * One backward-Euler step: solve Phi(u) = 0 from u = p^l (reading: the
+ * previous level is the initial guess) with the modified inexact Newton
+ * method of Section 3.  J and the auxiliary matrix are rebuilt when any of
+ * eq. (jacobian_update_condition) holds:
+ *   - msbset Newton iterations have passed since the last rebuild (the
+ *     counter persists across time steps, which re-use the previous step's
+ *     Jacobian: Section 6);
+ *   - the previous scaled step ||lam d||_inf exceeded 1.5;
+ *   - a retry was requested because, with a stale J, GMRES failed, the line
+ *     search failed, or the step became shorter than scsteptol.
+ * With a fresh J those events end the step with an error (GMRES failure only
+ * if d is not a descent direction); the short step ends it with the warning
+ * ORC_STEP_TOO_SMALL (>0) and the state is kept.
+ */
+int orc_solver_step(orc_solver *S, double *p, orc_stats *st)
+{
+    int64_t N = S->N;
+    memset(st, 0, sizeof(*st));
+    st->min_lambda = 1.0;
+    if (!all_finite(N, p)) return st->status = ORC_NONFINITE;
+    orc_theta(&S->P, p, S->theta_old);
+    memcpy(S->u, p, (size_t)N * sizeof(double));
+    orc_residual(&S->P, S->Ks, S->u, S->theta_old, S->F);
+    double fnorm = norm_inf(N, S->F);
+    if (!isfinite(fnorm)) return st->status = ORC_NONFINITE;
+    double mxstep = S->O.mxnewtstep;
+    if (!(mxstep > 0.0)) {
+        double un = sqrt(dot(N, S->u, S->u));
+        mxstep = 1000.0 * (un > 1.0 ? un : 1.0);
+    }
+    double prev_step = 0.0;
+    int retry = 0, status = ORC_OK;
+    while (fnorm > S->O.fnormtol) {
+        if (st->newton_its >= S->O.max_newton) {
+            status = ORC_MAXITER;
+            break;
+        }
+        int fresh = 0;
+        if (!S->have_J || S->since_build >= S->O.msbset || prev_step > 1.5 || retry) {
+            int rc = rebuild(S, S->u, st);
+            if (rc != ORC_OK) {
+                status = rc;
+                break;
+            }
+            fresh = 1;
+            retry = 0;
+        }
+        for (int64_t i = 0; i < N; i++) S->Ft[i] = -S->F[i];
+        int its;
+        double relres;
+        int conv = orc_gmres(N, S->J.rowptr, S->J.col, S->J.val, S->H, S->Ft, S->d,
+                             S->O.gmres_restart, S->O.eta, S->O.gmres_maxit, &its, &relres);
+        st->gmres_its += its;
+        if (!conv) {
+            st->linsolve_fails++;
+            if (!fresh) {
+                retry = 1;
+                continue;
+            }
+        }
+        int truncated = 0;
+        double dn = sqrt(dot(N, S->d, S->d));
+        if (dn > mxstep) {
+            for (int64_t i = 0; i < N; i++) S->d[i] *= mxstep / dn;
+            truncated = 1;
+        }
+        orc_csr_matvec(N, S->J.rowptr, S->J.col, S->J.val, S->d, S->Jd);
+        double slope = dot(N, S->F, S->Jd);
+        if (!(slope < 0.0)) {
+            if (!fresh) {
+                retry = 1;
+                continue;
+            }
+            status = ORC_LINSOLVE_FAIL;
+            break;
+        }
+        double lam;
+        int nb;
+        int rc = line_search(S, slope, mxstep, truncated, &lam, &nb);
+        st->ls_backtracks += nb;
+        if (rc != ORC_OK) {
+            if (!fresh) {
+                retry = 1;
+                continue;
+            }
+            status = rc;
+            break;
+        }
+        if (lam < st->min_lambda) st->min_lambda = lam;
+        double step_inf = lam * norm_inf(N, S->d);
+        double step_rel = rel_length(N, S->d, lam, S->ut);
+        memcpy(S->u, S->ut, (size_t)N * sizeof(double));
+        memcpy(S->F, S->Ft, (size_t)N * sizeof(double));
+        st->newton_its++;
+        S->since_build++;
+        fnorm = norm_inf(N, S->F);
+        if (!isfinite(fnorm)) {
+            status = ORC_NONFINITE;
+            break;
+        }
+        if (fnorm <= S->O.fnormtol) break;
+        if (step_rel < S->O.scsteptol) {
+            if (!fresh) {
+                retry = 1;
+            } else {
+                status = ORC_STEP_TOO_SMALL;
+                break;
+            }
+        }
+        prev_step = step_inf;
+    }
+    st->fnorm_inf = fnorm;
+    if (status == ORC_OK || status == ORC_STEP_TOO_SMALL) {
+        memcpy(p, S->u, (size_t)N * sizeof(double));
+        double s = 0.0;
+        for (int64_t i = 0; i < N; i++) s += S->F[i];
+        st->mass_residual = S->P.dt * s;
+    }
+    st->status = status;
+    return status;
+}

@@ -1,0 +1,127 @@
+/*
+ * Plain FP64 CPU oracle for the backward-Euler / inexact-Newton / AMG-GMRES
+ * solve of the 3-D Richards equation (Bertaccini, D'Ambra, Durastante,
+ * Filippone, arXiv 2112.05051).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library may include,
+ * link or call this code; only the test-suite, the smoke check and the CPU
+ * baseline leg of the benchmark use it.  It shares no code with the HIP path.
+ *
+ * Every routine is a slow, direct transcription of what the paper's equations
+ * (and, where the paper is silent, the documented reading) define: plain
+ * loops, no blocking, no fusion.
+ *
+ * Grid: nx*ny*nz unknowns, x fastest: c = i + nx*(j + ny*k); k grows upward
+ * (z is elevation).  Faces are numbered 0..5 = -x,+x,-y,+y,-z,+z.
+ */
+#ifndef RICHARDS_ORACLE_H
+#define RICHARDS_ORACLE_H
+#include <stdint.h>
+
+#define ORC_ARITH 0
+#define ORC_UPSTREAM 1
+#define ORC_HARMONIC 2
+
+#define ORC_NOFLUX 0
+#define ORC_DIRICHLET 1
+
+/* status codes */
+#define ORC_OK 0
+#define ORC_EINVAL (-1)
+#define ORC_ENOMEM (-2)
+#define ORC_NONFINITE (-4)
+#define ORC_LINSOLVE_FAIL (-5)
+#define ORC_LINESEARCH_FAIL (-6)
+#define ORC_MAXITER (-7)
+#define ORC_STEP_TOO_SMALL 2 /* warning: state kept */
+#define ORC_NOT_SPD (-9)
+
+typedef struct {
+    int nx, ny, nz;
+    double hx, hy, hz;
+    double alpha, beta, theta_s, theta_r, A, gamma;
+    int mean;
+    int bc_type[6];
+    double bc_value[6];
+    double dt;
+} orc_problem;
+
+typedef struct {
+    double fnormtol, scsteptol;
+    int max_newton, msbset;
+    double ls_alpha, mxnewtstep;
+    int gmres_restart;
+    double eta;
+    int gmres_maxit;
+    int amg_max_levels;
+    int64_t amg_coarse_size;
+    int amg_sweeps;
+    int64_t coarse_dense_max;
+    int coarse_l1_sweeps;
+} orc_opts;
+
+typedef struct {
+    int64_t n;
+    int64_t *rowptr; /* n+1 */
+    int32_t *col;
+    double *val;
+} orc_csr;
+
+typedef struct {
+    int status;
+    int newton_its, jac_builds, gmres_its, ls_backtracks, amg_setups;
+    int linsolve_fails;
+    double fnorm_inf;
+    double mass_residual;  /* dt * sum_c Phi_c(p_final) (per unit cell volume) */
+    double min_lambda;
+} orc_stats;
+
+/* ---- constitutive laws, residual, Jacobian, auxiliary matrix ---- */
+void orc_laws(const orc_problem *P, double p, double Ks, double out[4]); /* theta, theta', K, K' */
+void orc_laws_array(const orc_problem *P, int64_t n, const double *p, const double *Ks,
+                    double *out /* n x 4 */);
+void orc_theta(const orc_problem *P, const double *p, double *theta);
+void orc_residual(const orc_problem *P, const double *Ks, const double *p, const double *theta_old,
+                  double *F);
+int64_t orc_pattern_nnz(const orc_problem *P);
+void orc_jacobian(const orc_problem *P, const double *Ks, const double *p, int64_t *rowptr,
+                  int32_t *col, double *val);
+void orc_auxiliary(const orc_problem *P, const double *Ks, const double *p, int64_t *rowptr,
+                   int32_t *col, double *val);
+void orc_csr_matvec(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
+                    const double *x, double *y);
+
+/* ---- aggregation ---- */
+int64_t orc_match_sweep(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
+                        int32_t *agg);
+int64_t orc_galerkin_nnz(int64_t n, const int64_t *rowptr, const int32_t *col, const int32_t *agg,
+                         int64_t nc);
+void orc_galerkin(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
+                  const int32_t *agg, int64_t nc, int64_t *crow, int32_t *ccol, double *cval);
+
+/* ---- AMG hierarchy (opaque) ---- */
+typedef struct orc_amg orc_amg;
+int orc_amg_build(const orc_opts *O, int64_t n, const int64_t *rowptr, const int32_t *col,
+                  const double *val, orc_amg **out);
+int orc_amg_update_fine(orc_amg *H, const double *val); /* new fine values, same pattern */
+int orc_amg_levels(const orc_amg *H);
+void orc_amg_level_info(const orc_amg *H, int l, int64_t *n, int64_t *nnz);
+void orc_amg_level_export(const orc_amg *H, int l, int64_t *rowptr, int32_t *col, double *val,
+                          int32_t *agg /* nullable; only for l < levels-1 */);
+int orc_amg_coarse_is_dense(const orc_amg *H);
+void orc_amg_apply(const orc_amg *H, const double *b, double *x);
+void orc_amg_destroy(orc_amg *H);
+
+/* ---- GMRES (right-preconditioned by the hierarchy, or unpreconditioned if H is NULL) ---- */
+int orc_gmres(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
+              const orc_amg *H, const double *b, double *x, int restart, double eta, int maxit,
+              int *its_out, double *relres_out);
+
+/* ---- time stepping ---- */
+typedef struct orc_solver orc_solver;
+int orc_solver_create(const orc_problem *P, const orc_opts *O, const double *Ks,
+                      orc_solver **out);
+int orc_solver_step(orc_solver *S, double *p, orc_stats *st);
+void orc_solver_destroy(orc_solver *S);
+
+#endif

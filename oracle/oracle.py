@@ -1,0 +1,295 @@
+"""ctypes binding of the plain-C FP64 oracle (oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, the smoke check and the
+benchmark's CPU-baseline leg.  The product library never imports it.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+import scipy.sparse as sp
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+SRC = os.path.join(HERE, "oracle.c")
+
+OK, EINVAL, ENOMEM, NONFINITE = 0, -1, -2, -4
+LINSOLVE_FAIL, LINESEARCH_FAIL, MAXITER, STEP_TOO_SMALL, NOT_SPD = -5, -6, -7, 2, -9
+
+
+def build(force: bool = False) -> str:
+    """Compile liboracle.so with gcc (plain -O2, no fast-math, no FMA contraction)."""
+    if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC):
+        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", SRC, "-o",
+               LIB_PATH + ".tmp", "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(LIB_PATH + ".tmp", LIB_PATH)
+    return LIB_PATH
+
+
+class CProblem(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
+                ("hx", C.c_double), ("hy", C.c_double), ("hz", C.c_double),
+                ("alpha", C.c_double), ("beta", C.c_double), ("theta_s", C.c_double),
+                ("theta_r", C.c_double), ("A", C.c_double), ("gamma", C.c_double),
+                ("mean", C.c_int), ("bc_type", C.c_int * 6), ("bc_value", C.c_double * 6),
+                ("dt", C.c_double)]
+
+
+class COpts(C.Structure):
+    _fields_ = [("fnormtol", C.c_double), ("scsteptol", C.c_double),
+                ("max_newton", C.c_int), ("msbset", C.c_int),
+                ("ls_alpha", C.c_double), ("mxnewtstep", C.c_double),
+                ("gmres_restart", C.c_int), ("eta", C.c_double), ("gmres_maxit", C.c_int),
+                ("amg_max_levels", C.c_int), ("amg_coarse_size", C.c_int64),
+                ("amg_sweeps", C.c_int), ("coarse_dense_max", C.c_int64),
+                ("coarse_l1_sweeps", C.c_int)]
+
+
+class CStats(C.Structure):
+    _fields_ = [("status", C.c_int), ("newton_its", C.c_int), ("jac_builds", C.c_int),
+                ("gmres_its", C.c_int), ("ls_backtracks", C.c_int), ("amg_setups", C.c_int),
+                ("linsolve_fails", C.c_int), ("fnorm_inf", C.c_double),
+                ("mass_residual", C.c_double), ("min_lambda", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = C.CDLL(LIB_PATH)
+        P = C.POINTER
+        d, i64, i32 = P(C.c_double), P(C.c_int64), P(C.c_int32)
+        vp = C.c_void_p
+        L.orc_laws_array.argtypes = [P(CProblem), C.c_int64, d, d, d]
+        L.orc_theta.argtypes = [P(CProblem), d, d]
+        L.orc_residual.argtypes = [P(CProblem), d, d, d, d]
+        L.orc_pattern_nnz.argtypes = [P(CProblem)]
+        L.orc_pattern_nnz.restype = C.c_int64
+        L.orc_jacobian.argtypes = [P(CProblem), d, d, i64, i32, d]
+        L.orc_auxiliary.argtypes = [P(CProblem), d, d, i64, i32, d]
+        L.orc_csr_matvec.argtypes = [C.c_int64, i64, i32, d, d, d]
+        L.orc_match_sweep.argtypes = [C.c_int64, i64, i32, d, i32]
+        L.orc_match_sweep.restype = C.c_int64
+        L.orc_galerkin_nnz.argtypes = [C.c_int64, i64, i32, i32, C.c_int64]
+        L.orc_galerkin_nnz.restype = C.c_int64
+        L.orc_galerkin.argtypes = [C.c_int64, i64, i32, d, i32, C.c_int64, i64, i32, d]
+        L.orc_amg_build.argtypes = [P(COpts), C.c_int64, i64, i32, d, P(vp)]
+        L.orc_amg_update_fine.argtypes = [vp, d]
+        L.orc_amg_levels.argtypes = [vp]
+        L.orc_amg_level_info.argtypes = [vp, C.c_int, i64, i64]
+        L.orc_amg_level_export.argtypes = [vp, C.c_int, i64, i32, d, i32]
+        L.orc_amg_coarse_is_dense.argtypes = [vp]
+        L.orc_amg_apply.argtypes = [vp, d, d]
+        L.orc_amg_destroy.argtypes = [vp]
+        L.orc_gmres.argtypes = [C.c_int64, i64, i32, d, vp, d, d, C.c_int, C.c_double, C.c_int,
+                                P(C.c_int), P(C.c_double)]
+        L.orc_solver_create.argtypes = [P(CProblem), P(COpts), d, P(vp)]
+        L.orc_solver_step.argtypes = [vp, d, P(CStats)]
+        L.orc_solver_destroy.argtypes = [vp]
+        _lib = L
+    return _lib
+
+
+def _d(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _i64(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int64))
+
+
+def _i32(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def cproblem(P) -> CProblem:
+    """Convert a synth.Problem (or any object with the same fields)."""
+    c = CProblem()
+    for f in ("nx", "ny", "nz", "mean"):
+        setattr(c, f, int(getattr(P, f)))
+    for f in ("hx", "hy", "hz", "alpha", "beta", "theta_s", "theta_r", "A", "gamma", "dt"):
+        setattr(c, f, float(getattr(P, f)))
+    for t in range(6):
+        c.bc_type[t] = int(P.bc_type[t])
+        c.bc_value[t] = float(P.bc_value[t])
+    return c
+
+
+def copts(O) -> COpts:
+    c = COpts()
+    for f, t in COpts._fields_:
+        v = getattr(O, f)
+        setattr(c, f, float(v) if t is C.c_double else int(v))
+    return c
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def laws(P, p, Ks):
+    """(theta, theta', K, K') for every entry of p (eq. s(p), K(p) and their derivatives)."""
+    p, Ks = _f64(p), _f64(np.broadcast_to(Ks, np.shape(p)))
+    out = np.empty((p.size, 4))
+    cp = cproblem(P)
+    lib().orc_laws_array(C.byref(cp), p.size, _d(p), _d(Ks), _d(out))
+    return out[:, 0], out[:, 1], out[:, 2], out[:, 3]
+
+
+def theta(P, p):
+    p = _f64(p)
+    out = np.empty_like(p)
+    cp = cproblem(P)
+    lib().orc_theta(C.byref(cp), _d(p), _d(out))
+    return out
+
+
+def residual(P, Ks, p, theta_old):
+    Ks, p, theta_old = _f64(Ks), _f64(p), _f64(theta_old)
+    out = np.empty_like(p)
+    cp = cproblem(P)
+    lib().orc_residual(C.byref(cp), _d(Ks), _d(p), _d(theta_old), _d(out))
+    return out
+
+
+def _assemble(fn, P, Ks, p):
+    Ks, p = _f64(Ks), _f64(p)
+    cp = cproblem(P)
+    n = p.size
+    nnz = lib().orc_pattern_nnz(C.byref(cp))
+    rp = np.empty(n + 1, np.int64)
+    col = np.empty(nnz, np.int32)
+    val = np.empty(nnz)
+    fn(C.byref(cp), _d(Ks), _d(p), _i64(rp), _i32(col), _d(val))
+    return sp.csr_matrix((val, col, rp), shape=(n, n))
+
+
+def jacobian(P, Ks, p):
+    """Analytic Jacobian of the residual as a scipy CSR matrix (7-point pattern)."""
+    return _assemble(lib().orc_jacobian, P, Ks, p)
+
+
+def auxiliary(P, Ks, p):
+    """Diffusion-only preconditioner matrix (symmetric M-matrix) as scipy CSR."""
+    return _assemble(lib().orc_auxiliary, P, Ks, p)
+
+
+def _csr_parts(A):
+    A = sp.csr_matrix(A)
+    return (np.ascontiguousarray(A.indptr, np.int64), np.ascontiguousarray(A.indices, np.int32),
+            _f64(A.data))
+
+
+def match_sweep(A):
+    rp, col, val = _csr_parts(A)
+    agg = np.empty(A.shape[0], np.int32)
+    nc = lib().orc_match_sweep(A.shape[0], _i64(rp), _i32(col), _d(val), _i32(agg))
+    return agg, int(nc)
+
+
+def galerkin(A, agg, nc):
+    rp, col, val = _csr_parts(A)
+    agg = np.ascontiguousarray(agg, np.int32)
+    n = A.shape[0]
+    nnz = lib().orc_galerkin_nnz(n, _i64(rp), _i32(col), _i32(agg), nc)
+    crp = np.empty(nc + 1, np.int64)
+    ccol = np.empty(nnz, np.int32)
+    cval = np.empty(nnz)
+    lib().orc_galerkin(n, _i64(rp), _i32(col), _d(val), _i32(agg), nc, _i64(crp), _i32(ccol), _d(cval))
+    return sp.csr_matrix((cval, ccol, crp), shape=(nc, nc))
+
+
+class AMG:
+    """Oracle AMG hierarchy built from a fine matrix (keeps its own copies)."""
+
+    def __init__(self, opts, A):
+        self._h = C.c_void_p()
+        self._parts = _csr_parts(A)
+        rp, col, val = self._parts
+        co = copts(opts)
+        rc = lib().orc_amg_build(C.byref(co), A.shape[0], _i64(rp), _i32(col), _d(val), C.byref(self._h))
+        if rc != OK:
+            raise RuntimeError(f"orc_amg_build failed: {rc}")
+        self.n = A.shape[0]
+
+    def update_fine(self, A):
+        val = _f64(sp.csr_matrix(A).data)
+        rc = lib().orc_amg_update_fine(self._h, _d(val))
+        if rc != OK:
+            raise RuntimeError(f"orc_amg_update_fine failed: {rc}")
+
+    @property
+    def levels(self) -> int:
+        return lib().orc_amg_levels(self._h)
+
+    @property
+    def coarse_dense(self) -> bool:
+        return bool(lib().orc_amg_coarse_is_dense(self._h))
+
+    def level(self, l):
+        n, nnz = C.c_int64(), C.c_int64()
+        lib().orc_amg_level_info(self._h, l, C.byref(n), C.byref(nnz))
+        rp = np.empty(n.value + 1, np.int64)
+        col = np.empty(nnz.value, np.int32)
+        val = np.empty(nnz.value)
+        agg = np.empty(n.value, np.int32) if l < self.levels - 1 else None
+        lib().orc_amg_level_export(self._h, l, _i64(rp), _i32(col), _d(val),
+                                   _i32(agg) if agg is not None else None)
+        return sp.csr_matrix((val, col, rp), shape=(n.value, n.value)), agg
+
+    def apply(self, b):
+        b = _f64(b)
+        x = np.empty_like(b)
+        lib().orc_amg_apply(self._h, _d(b), _d(x))
+        return x
+
+    def __del__(self):
+        if getattr(self, "_h", None) and self._h.value and _lib is not None:
+            _lib.orc_amg_destroy(self._h)
+            self._h = C.c_void_p()
+
+
+def gmres(J, b, amg: AMG | None = None, restart=30, eta=1e-6, maxit=200):
+    rp, col, val = _csr_parts(J)
+    b = _f64(b)
+    x = np.empty_like(b)
+    its, rr = C.c_int(), C.c_double()
+    conv = lib().orc_gmres(J.shape[0], _i64(rp), _i32(col), _d(val), amg._h if amg else None,
+                           _d(b), _d(x), restart, eta, maxit, C.byref(its), C.byref(rr))
+    return x, bool(conv), its.value, rr.value
+
+
+def stats_dict(s: CStats) -> dict:
+    return {f: getattr(s, f) for f, _ in CStats._fields_}
+
+
+class Solver:
+    """Time-stepping oracle: backward Euler + modified inexact Newton + AMG-GMRES."""
+
+    def __init__(self, P, opts, Ks):
+        self._h = C.c_void_p()
+        self.P, self.opts = P, opts
+        self._cp, self._co = cproblem(P), copts(opts)
+        Ks = _f64(Ks)
+        rc = lib().orc_solver_create(C.byref(self._cp), C.byref(self._co), _d(Ks), C.byref(self._h))
+        if rc != OK:
+            raise RuntimeError(f"orc_solver_create failed: {rc}")
+
+    def step(self, p):
+        """Advance p (float64 array, updated in place) by one time step; returns stats."""
+        assert p.dtype == np.float64 and p.flags.c_contiguous
+        st = CStats()
+        lib().orc_solver_step(self._h, _d(p), C.byref(st))
+        return stats_dict(st)
+
+    def __del__(self):
+        if getattr(self, "_h", None) and self._h.value and _lib is not None:
+            _lib.orc_solver_destroy(self._h)
+            self._h = C.c_void_p()
