@@ -1,0 +1,186 @@
+/*
+ * richards.h -- C-ABI of the MI355X (gfx950) solver for the 3-D Richards
+ * equation, following Bertaccini, D'Ambra, Durastante and Filippone,
+ * "Why diffusion-based preconditioning of Richards equation works: spectral
+ * analysis and computational experiments at very large scale" (arXiv
+ * 2112.05051).
+ *
+ * What is computed (paper references are sections and labelled equations):
+ *   - backward Euler in time on a cell-centred 7-point finite-difference grid
+ *     (Section 2.1, eq. (dynamic_of_the_problem));
+ *   - each time step solved by a modified inexact Newton method with an
+ *     Armijo-Goldstein line search and the Jacobian re-use rules of
+ *     eq. (jacobian_update_condition) (Section 3);
+ *   - every Newton correction J d = -Phi solved by restarted GMRES, right
+ *     preconditioned (eq. (precsystem)) with an aggregation AMG V-cycle
+ *     (Section 5.2) built on the diffusion-only operator (end of Section 4).
+ *
+ * Conventions
+ *   - Grid: nx*ny*nz unknowns, index c = i + nx*(j + ny*k), x fastest, k
+ *     upward (z is elevation).  Faces are ordered -x,+x,-y,+y,-z,+z.
+ *   - Every array argument named *_dev is DEVICE memory (hipMalloc'd, e.g. a
+ *     torch tensor's data pointer) holding `double` values in that order,
+ *     owned by the caller, only accessed during the call.  Arguments named
+ *     *_host are host memory owned by the caller.
+ *   - A handle is bound to the HIP stream given at creation; every kernel of
+ *     a call is launched on it.  Calls return after their work is complete
+ *     unless stated otherwise.  Distinct handles share no state.
+ *   - Every function returns a rich_status; RICH_OK = 0, errors < 0,
+ *     warnings > 0.  On an error inside rich_step the state stays at the last
+ *     accepted time level.
+ */
+#ifndef RICHARDS_H
+#define RICHARDS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int rich_status;
+#define RICH_OK 0
+#define RICH_EINVAL (-1)          /* bad size, spacing, dt, parameter or pointer */
+#define RICH_ENOMEM (-2)          /* device allocation failed */
+#define RICH_EBUDGET (-3)         /* request does not fit the memory budget */
+#define RICH_NONFINITE (-4)       /* NaN/Inf in an input or an iterate */
+#define RICH_LINSOLVE_FAIL (-5)   /* GMRES failed with a fresh J and d is no descent direction */
+#define RICH_LINESEARCH_FAIL (-6) /* line search failed with a fresh J */
+#define RICH_MAXITER (-7)         /* Newton iteration limit reached */
+#define RICH_NOT_SPD (-9)         /* coarsest matrix not positive definite */
+#define RICH_EHIP (-10)           /* HIP runtime error */
+#define RICH_ESTATE (-11)         /* call not valid in the handle's current state */
+#define RICH_STEP_TOO_SMALL 2     /* warning: Newton stalled with a fresh J; state kept */
+
+/* interface means of K (Section 2.1; harmonic: named in the abstract) */
+#define RICH_MEAN_ARITH 0
+#define RICH_MEAN_UPSTREAM 1
+#define RICH_MEAN_HARMONIC 2
+/* boundary face types */
+#define RICH_BC_NOFLUX 0
+#define RICH_BC_DIRICHLET 1
+/* arithmetic of the AMG V-cycle (the Newton/GMRES outer loop is always FP64) */
+#define RICH_PREC_FP64 0
+#define RICH_PREC_MIXED 1
+
+/* The problem statement of Sections 2 and 2.1. */
+typedef struct rich_problem {
+    int nx, ny, nz;      /* unknowns per axis (>= 1) */
+    double hx, hy, hz;   /* grid spacing [cm] (> 0) */
+    /* eq. (s(p)): theta = alpha (theta_s - theta_r) / (alpha + |p|^beta) + theta_r
+       eq. (K(p)): K = K_s A / (A + |p|^gamma); p >= 0 is saturated */
+    double alpha, beta, theta_s, theta_r, A, gamma;
+    int mean;            /* RICH_MEAN_* */
+    int bc_type[6];      /* RICH_BC_* per face -x,+x,-y,+y,-z,+z */
+    double bc_value[6];  /* Dirichlet head [cm] per face */
+    double dt;           /* time step [s] (> 0) */
+} rich_problem_t;
+
+/* Solver controls (Sections 3 and 6). */
+typedef struct rich_solver_opts {
+    double fnormtol;     /* Newton stops at ||Phi||_inf <= fnormtol */
+    double scsteptol;    /* minimum relative step (eps^(2/3) in the paper) */
+    int max_newton;      /* Newton iteration limit per time step */
+    int msbset;          /* rebuild J after this many Newton iterations (10) */
+    double ls_alpha;     /* Armijo constant (1e-4) */
+    double mxnewtstep;   /* maximum ||d||_2; <= 0 -> 1000 max(||p_init||_2, 1) */
+    int gmres_restart;   /* m of GMRES(m), 1..64 */
+    double eta;          /* GMRES stops at ||J d + Phi||_2 <= eta ||Phi||_2 */
+    int gmres_maxit;     /* GMRES iteration limit per Newton correction */
+    int amg_max_levels;  /* <= 16 */
+    int64_t amg_coarse_size;  /* stop coarsening at <= this many rows */
+    int amg_sweeps;      /* pairwise matching sweeps per level (3 -> aggregates <= 8) */
+    int64_t coarse_dense_max; /* coarsest solved directly when n <= this (<= 8192) */
+    int coarse_l1_sweeps;     /* otherwise this many l1-Jacobi sweeps */
+    int precision;       /* RICH_PREC_* */
+} rich_solver_opts_t;
+
+/* Per-time-step counters and timings (host wall seconds of each phase). */
+typedef struct rich_step_stats {
+    int status;
+    int newton_its, jac_builds, gmres_its, ls_backtracks, amg_setups, linsolve_fails, levels;
+    double fnorm_inf;     /* ||Phi||_inf at the accepted state */
+    double mass_residual; /* dt * sum_c Phi_c at the accepted state */
+    double min_lambda;    /* smallest accepted line-search step */
+    double opc;           /* operator complexity sum nnz(A_l) / nnz(A_0) */
+    double t_feval, t_jac, t_setup, t_linsol, t_total;
+} rich_step_stats_t;
+
+typedef struct rich_ctx *rich_handle_t;
+
+/* ---------------------------------------------------------------- core -- */
+
+/* Device bytes a handle for (prob, opts) will hold, before the AMG
+ * hierarchy (whose size depends on the matrix) -- plus an upper bound for
+ * the hierarchy assuming operator complexity <= 3. */
+rich_status rich_query_bytes(const rich_problem_t *prob, const rich_solver_opts_t *opts,
+                             size_t *bytes);
+
+/* Create a handle.  Ks_dev: N saturated conductivities [cm/s] (> 0), copied.
+ * hip_stream: a hipStream_t (NULL = default stream).  The state is
+ * undefined until rich_set_state. */
+rich_status rich_create(const rich_problem_t *prob, const rich_solver_opts_t *opts,
+                        const double *Ks_dev, void *hip_stream, rich_handle_t *out);
+rich_status rich_destroy(rich_handle_t h);
+
+/* Copy the head field p (N values) in / out of the handle. */
+rich_status rich_set_state(rich_handle_t h, const double *p_dev);
+rich_status rich_get_state(rich_handle_t h, double *p_dev);
+
+/* Advance nsteps backward-Euler steps.  stats_host: nsteps entries or NULL.
+ * Returns the first non-OK status (the state is then the last good level). */
+rich_status rich_step(rich_handle_t h, int nsteps, rich_step_stats_t *stats_host);
+
+const char *rich_status_string(rich_status s);
+
+/* ------------------------------------------------ inspection / parity -- */
+
+/* theta(p) per cell (eq. (s(p)) with rho*phi = 1). */
+rich_status rich_eval_theta(rich_handle_t h, const double *p_dev, double *theta_dev);
+/* Phi(p) of eq. (dynamic_of_the_problem) with f = 0 and the given theta at
+ * the previous level. */
+rich_status rich_eval_residual(rich_handle_t h, const double *p_dev, const double *theta_old_dev,
+                               double *F_dev);
+/* Assemble J(p) and the auxiliary matrix M(p) into the handle and refresh
+ * the fine-level smoother; builds the AMG hierarchy if none exists yet. */
+rich_status rich_assemble(rich_handle_t h, const double *p_dev);
+/* (Re)build the AMG hierarchy from the current auxiliary matrix. */
+rich_status rich_setup_hierarchy(rich_handle_t h);
+/* y = J x and y = M x with the assembled matrices (FP64). */
+rich_status rich_apply_jacobian(rich_handle_t h, const double *x_dev, double *y_dev);
+rich_status rich_apply_aux(rich_handle_t h, const double *x_dev, double *y_dev);
+/* x = one V-cycle applied to b, in the handle's precision. */
+rich_status rich_apply_prec(rich_handle_t h, const double *b_dev, double *x_dev);
+/* Solve J x = b by right-preconditioned GMRES(m) from x = 0.  Returns RICH_OK
+ * when ||b - J x||_2 <= eta ||b||_2, RICH_LINSOLVE_FAIL otherwise. */
+rich_status rich_gmres(rich_handle_t h, const double *b_dev, double *x_dev, int *its_host,
+                       double *relres_host);
+
+/* Hierarchy shape.  Level 0 is the auxiliary matrix. */
+rich_status rich_levels(rich_handle_t h, int *nlev_host);
+rich_status rich_level_size(rich_handle_t h, int level, int64_t *n_host, int64_t *nnz_host);
+#define RICH_WHICH_J 0  /* the Jacobian (level ignored) */
+#define RICH_WHICH_A 1  /* the level-l AMG matrix, FP64 (level 0 = auxiliary M) */
+/* Copy a matrix to host CSR (columns ascending).  *nnz_inout: capacity in,
+ * entries written out; RICH_EINVAL if the capacity is too small. */
+rich_status rich_export_csr(rich_handle_t h, int which, int level, int64_t *rowptr_host,
+                            int32_t *col_host, double *val_host, int64_t *nnz_inout);
+/* Aggregate index (level l -> l+1) of every level-l row, to host. */
+rich_status rich_export_aggregates(rich_handle_t h, int level, int32_t *agg_host,
+                                   int64_t *n_coarse_host);
+
+/* One pairwise matching sweep on a device CSR matrix (int64 rowptr, int32
+ * columns ascending, double values): the matching of Section 5.2 (SMATCH),
+ * weights w_ij = 1 - 2 a_ij / (a_ii + a_jj) from the row min(i,j), greedy in
+ * the strict order (w desc, i asc, j asc), singletons for unmatched rows,
+ * coarse indices in increasing order of the smallest member.  agg_dev: n
+ * int32 outputs.  Runs on hip_stream and returns when done. */
+rich_status rich_match_sweep(int64_t n, const int64_t *rowptr_dev, const int32_t *col_dev,
+                             const double *val_dev, int32_t *agg_dev, int64_t *n_coarse_host,
+                             void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

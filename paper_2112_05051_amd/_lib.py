@@ -1,0 +1,297 @@
+"""ctypes binding of librichards.so (include/richards.h).
+
+Argument marshalling only: every step of the solver runs in the HIP library.
+Device arrays are torch tensors on the GPU (float64 unless stated); PyTorch
+supplies device memory and the stream, nothing else.  If the library has not
+been built, or no GPU is present, calls fail loudly: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librichards.so")
+
+OK = 0
+EINVAL, ENOMEM, EBUDGET, NONFINITE = -1, -2, -3, -4
+LINSOLVE_FAIL, LINESEARCH_FAIL, MAXITER, NOT_SPD, EHIP, ESTATE = -5, -6, -7, -9, -10, -11
+STEP_TOO_SMALL = 2
+PREC_FP64, PREC_MIXED = 0, 1
+WHICH_J, WHICH_A = 0, 1
+
+
+class RichError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {status_string(status)} ({status})")
+
+
+class Problem(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
+                ("hx", C.c_double), ("hy", C.c_double), ("hz", C.c_double),
+                ("alpha", C.c_double), ("beta", C.c_double), ("theta_s", C.c_double),
+                ("theta_r", C.c_double), ("A", C.c_double), ("gamma", C.c_double),
+                ("mean", C.c_int), ("bc_type", C.c_int * 6), ("bc_value", C.c_double * 6),
+                ("dt", C.c_double)]
+
+
+class Opts(C.Structure):
+    _fields_ = [("fnormtol", C.c_double), ("scsteptol", C.c_double),
+                ("max_newton", C.c_int), ("msbset", C.c_int),
+                ("ls_alpha", C.c_double), ("mxnewtstep", C.c_double),
+                ("gmres_restart", C.c_int), ("eta", C.c_double), ("gmres_maxit", C.c_int),
+                ("amg_max_levels", C.c_int), ("amg_coarse_size", C.c_int64),
+                ("amg_sweeps", C.c_int), ("coarse_dense_max", C.c_int64),
+                ("coarse_l1_sweeps", C.c_int), ("precision", C.c_int)]
+
+
+class StepStats(C.Structure):
+    _fields_ = [("status", C.c_int), ("newton_its", C.c_int), ("jac_builds", C.c_int),
+                ("gmres_its", C.c_int), ("ls_backtracks", C.c_int), ("amg_setups", C.c_int),
+                ("linsolve_fails", C.c_int), ("levels", C.c_int),
+                ("fnorm_inf", C.c_double), ("mass_residual", C.c_double),
+                ("min_lambda", C.c_double), ("opc", C.c_double),
+                ("t_feval", C.c_double), ("t_jac", C.c_double), ("t_setup", C.c_double),
+                ("t_linsol", C.c_double), ("t_total", C.c_double)]
+
+
+EXPORTS = ["rich_query_bytes", "rich_create", "rich_destroy", "rich_set_state", "rich_get_state",
+           "rich_step", "rich_status_string", "rich_eval_theta", "rich_eval_residual",
+           "rich_assemble", "rich_setup_hierarchy", "rich_apply_jacobian", "rich_apply_aux",
+           "rich_apply_prec", "rich_gmres", "rich_levels", "rich_level_size", "rich_export_csr",
+           "rich_export_aggregates", "rich_match_sweep"]
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load librichards.so (torch is imported first so the library binds to its HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    import torch  # noqa: F401  (one HIP runtime per process: torch's)
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with paper_2112_05051_amd.build.build()")
+    L = C.CDLL(path)
+    P = C.POINTER
+    vp, i64p, i32p, dp = C.c_void_p, P(C.c_int64), P(C.c_int32), P(C.c_double)
+    L.rich_query_bytes.argtypes = [P(Problem), P(Opts), P(C.c_size_t)]
+    L.rich_create.argtypes = [P(Problem), P(Opts), vp, vp, P(vp)]
+    L.rich_destroy.argtypes = [vp]
+    L.rich_set_state.argtypes = [vp, vp]
+    L.rich_get_state.argtypes = [vp, vp]
+    L.rich_step.argtypes = [vp, C.c_int, P(StepStats)]
+    L.rich_status_string.argtypes = [C.c_int]
+    L.rich_status_string.restype = C.c_char_p
+    L.rich_eval_theta.argtypes = [vp, vp, vp]
+    L.rich_eval_residual.argtypes = [vp, vp, vp, vp]
+    L.rich_assemble.argtypes = [vp, vp]
+    L.rich_setup_hierarchy.argtypes = [vp]
+    L.rich_apply_jacobian.argtypes = [vp, vp, vp]
+    L.rich_apply_aux.argtypes = [vp, vp, vp]
+    L.rich_apply_prec.argtypes = [vp, vp, vp]
+    L.rich_gmres.argtypes = [vp, vp, vp, P(C.c_int), dp]
+    L.rich_levels.argtypes = [vp, P(C.c_int)]
+    L.rich_level_size.argtypes = [vp, C.c_int, i64p, i64p]
+    L.rich_export_csr.argtypes = [vp, C.c_int, C.c_int, i64p, i32p, dp, i64p]
+    L.rich_export_aggregates.argtypes = [vp, C.c_int, i32p, i64p]
+    L.rich_match_sweep.argtypes = [C.c_int64, vp, vp, vp, vp, i64p, vp]
+    for name in EXPORTS:
+        getattr(L, name).restype = C.c_int if name != "rich_status_string" else C.c_char_p
+    _lib = L
+    return L
+
+
+def status_string(s: int) -> str:
+    try:
+        return load().rich_status_string(s).decode()
+    except Exception:  # library not loadable: still report the number
+        return "status"
+
+
+def _check(rc: int, what: str, ok=(OK,)):
+    if rc not in ok:
+        raise RichError(rc, what)
+    return rc
+
+
+def make_problem(p) -> Problem:
+    """From any object with the rich_problem_t fields (e.g. synth.Problem)."""
+    c = Problem()
+    for f in ("nx", "ny", "nz", "mean"):
+        setattr(c, f, int(getattr(p, f)))
+    for f in ("hx", "hy", "hz", "alpha", "beta", "theta_s", "theta_r", "A", "gamma", "dt"):
+        setattr(c, f, float(getattr(p, f)))
+    for t in range(6):
+        c.bc_type[t] = int(p.bc_type[t])
+        c.bc_value[t] = float(p.bc_value[t])
+    return c
+
+
+def make_opts(o) -> Opts:
+    c = Opts()
+    for f, t in Opts._fields_:
+        v = getattr(o, f)
+        setattr(c, f, float(v) if t is C.c_double else int(v))
+    return c
+
+
+def _ptr(t, dtype=None):
+    import torch
+    if not t.is_cuda:
+        raise ValueError("device tensor required")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"expected {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError("contiguous tensor required")
+    return C.c_void_p(t.data_ptr())
+
+
+def query_bytes(problem, options) -> int:
+    L = load()
+    b = C.c_size_t()
+    _check(L.rich_query_bytes(C.byref(make_problem(problem)), C.byref(make_opts(options)), C.byref(b)),
+           "rich_query_bytes")
+    return b.value
+
+
+def stats_dict(s: StepStats) -> dict:
+    return {f: getattr(s, f) for f, _ in StepStats._fields_}
+
+
+class Solver:
+    """A device-resident Richards simulation (one rich_handle_t)."""
+
+    def __init__(self, problem, options, Ks, stream=None):
+        import torch
+        L = load()
+        self._L = L
+        self.problem, self.options = problem, options
+        self.n = int(problem.nx) * int(problem.ny) * int(problem.nz)
+        if Ks.numel() != self.n:
+            raise ValueError("Ks has the wrong size")
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self._h = C.c_void_p()
+        self._cp, self._co = make_problem(problem), make_opts(options)
+        _check(L.rich_create(C.byref(self._cp), C.byref(self._co), _ptr(Ks, torch.float64),
+                             C.c_void_p(self.stream.cuda_stream), C.byref(self._h)), "rich_create")
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._L.rich_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _new(self):
+        import torch
+        return torch.empty(self.n, dtype=torch.float64, device="cuda")
+
+    def set_state(self, p):
+        import torch
+        _check(self._L.rich_set_state(self._h, _ptr(p, torch.float64)), "rich_set_state")
+
+    def get_state(self):
+        p = self._new()
+        _check(self._L.rich_get_state(self._h, _ptr(p)), "rich_get_state")
+        return p
+
+    def step(self, nsteps: int = 1, raise_on_error: bool = True):
+        st = (StepStats * max(1, nsteps))()
+        rc = self._L.rich_step(self._h, nsteps, st)
+        out = [stats_dict(st[i]) for i in range(nsteps)]
+        if raise_on_error and rc < 0:
+            raise RichError(rc, "rich_step")
+        return out
+
+    def theta(self, p):
+        out = self._new()
+        _check(self._L.rich_eval_theta(self._h, _ptr(p), _ptr(out)), "rich_eval_theta")
+        return out
+
+    def residual(self, p, theta_old):
+        out = self._new()
+        _check(self._L.rich_eval_residual(self._h, _ptr(p), _ptr(theta_old), _ptr(out)), "rich_eval_residual")
+        return out
+
+    def assemble(self, p):
+        _check(self._L.rich_assemble(self._h, _ptr(p)), "rich_assemble")
+
+    def setup_hierarchy(self):
+        _check(self._L.rich_setup_hierarchy(self._h), "rich_setup_hierarchy")
+
+    def apply_jacobian(self, x):
+        y = self._new()
+        _check(self._L.rich_apply_jacobian(self._h, _ptr(x), _ptr(y)), "rich_apply_jacobian")
+        return y
+
+    def apply_aux(self, x):
+        y = self._new()
+        _check(self._L.rich_apply_aux(self._h, _ptr(x), _ptr(y)), "rich_apply_aux")
+        return y
+
+    def apply_prec(self, b):
+        x = self._new()
+        _check(self._L.rich_apply_prec(self._h, _ptr(b), _ptr(x)), "rich_apply_prec")
+        return x
+
+    def gmres(self, b):
+        x = self._new()
+        its, rr = C.c_int(), C.c_double()
+        rc = self._L.rich_gmres(self._h, _ptr(b), _ptr(x), C.byref(its), C.byref(rr))
+        _check(rc, "rich_gmres", ok=(OK, LINSOLVE_FAIL))
+        return x, its.value, rr.value, rc == OK
+
+    def levels(self) -> int:
+        n = C.c_int()
+        _check(self._L.rich_levels(self._h, C.byref(n)), "rich_levels")
+        return n.value
+
+    def level_size(self, level: int):
+        n, nnz = C.c_int64(), C.c_int64()
+        _check(self._L.rich_level_size(self._h, level, C.byref(n), C.byref(nnz)), "rich_level_size")
+        return n.value, nnz.value
+
+    def export_csr(self, which: int, level: int = 0):
+        """(indptr int64, indices int32, data float64) numpy arrays."""
+        if which == WHICH_J or level == 0:
+            n, cap = self.n, 7 * self.n
+        else:
+            n, cap = self.level_size(level)
+        rp = np.empty(n + 1, np.int64)
+        col = np.empty(max(cap, 1), np.int32)
+        val = np.empty(max(cap, 1), np.float64)
+        nnz = C.c_int64(cap)
+        _check(self._L.rich_export_csr(self._h, which, level, rp.ctypes.data_as(C.POINTER(C.c_int64)),
+                                       col.ctypes.data_as(C.POINTER(C.c_int32)),
+                                       val.ctypes.data_as(C.POINTER(C.c_double)), C.byref(nnz)),
+               "rich_export_csr")
+        return rp, col[:nnz.value], val[:nnz.value]
+
+    def export_aggregates(self, level: int):
+        n, _ = self.level_size(level)
+        agg = np.empty(n, np.int32)
+        nc = C.c_int64()
+        _check(self._L.rich_export_aggregates(self._h, level, agg.ctypes.data_as(C.POINTER(C.c_int32)),
+                                              C.byref(nc)), "rich_export_aggregates")
+        return agg, nc.value
+
+
+def match_sweep(rowptr, col, val, stream=None):
+    """One pairwise matching sweep on a device CSR matrix -> (agg int32 tensor, n_coarse)."""
+    import torch
+    L = load()
+    n = rowptr.numel() - 1
+    agg = torch.empty(max(n, 1), dtype=torch.int32, device="cuda")
+    nc = C.c_int64()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    _check(L.rich_match_sweep(n, _ptr(rowptr, torch.int64), _ptr(col, torch.int32), _ptr(val, torch.float64),
+                              _ptr(agg), C.byref(nc), C.c_void_p(s.cuda_stream)), "rich_match_sweep")
+    return agg[:n], nc.value

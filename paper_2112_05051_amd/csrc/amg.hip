@@ -1,0 +1,596 @@
+// Aggregation AMG (Section 5.2): parallel pairwise matching, piecewise-
+// constant Galerkin products, l1 smoother data, the CSR pieces of the
+// V-cycle and the dense coarsest-level solve.
+#include "common.hpp"
+
+#include <algorithm>
+
+namespace rich {
+
+namespace {
+
+constexpr int TPB = 256;
+constexpr int GAL_CAP = 160;  // distinct coarse columns one pairwise-merged row may hold
+
+inline unsigned nblocks(int64_t n, int tpb = TPB) { return (unsigned)((n + tpb - 1) / tpb); }
+
+// --------------------------------------------------------------- matching
+// Edge {i,j} (i != j) carries the value a_{lo,hi} of row lo = min(i,j) and
+// weight w = 1 - 2 a_{lo,hi} / (a_lolo + a_hihi); edges with a zero value or
+// a non-finite weight do not exist.  The strict order is (w desc, lo asc,
+// hi asc).  A vertex matches its best free neighbour when that neighbour's
+// best free neighbour is the vertex itself (locally dominant edge): repeated
+// until no free vertex has a free neighbour, this gives exactly the greedy
+// matching that scans all edges in the strict order.
+
+__device__ inline double find_entry(const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+                                    const double *__restrict__ val, int64_t row, int32_t c, bool *found) {
+    int64_t lo = rowptr[row], hi = rowptr[row + 1] - 1;
+    while (lo <= hi) {
+        int64_t mid = (lo + hi) >> 1;
+        int32_t cm = col[mid];
+        if (cm == c) {
+            *found = true;
+            return val[mid];
+        }
+        if (cm < c) lo = mid + 1;
+        else hi = mid - 1;
+    }
+    *found = false;
+    return 0.0;
+}
+
+__global__ void k_diag(int64_t n, const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+                       const double *__restrict__ val, double *__restrict__ diag) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double d = 0.0;
+    for (int64_t e = rowptr[i]; e < rowptr[i + 1]; e++)
+        if (col[e] == i) d = val[e];
+    diag[i] = d;
+}
+
+__global__ void k_candidates(int64_t n, const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+                             const double *__restrict__ val, const double *__restrict__ diag,
+                             const int32_t *__restrict__ mate, int32_t *__restrict__ cand) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (mate[i] != -1) {
+        cand[i] = -1;
+        return;
+    }
+    int32_t best = -1;
+    double bw = 0.0;
+    int64_t blo = 0, bhi = 0;
+    for (int64_t e = rowptr[i]; e < rowptr[i + 1]; e++) {
+        int32_t j = col[e];
+        if (j == i || mate[j] != -1) continue;
+        int64_t lo = j < i ? j : i, hi = j < i ? i : j;
+        double a;
+        if (lo == i) {
+            a = val[e];
+        } else {
+            bool found;
+            a = find_entry(rowptr, col, val, lo, (int32_t)hi, &found);
+            if (!found) continue;
+        }
+        if (a == 0.0) continue;
+        double w = 1.0 - (2.0 * a) / (diag[lo] + diag[hi]);
+        if (!isfinite(w)) continue;
+        bool better = best < 0 || w > bw || (w == bw && (lo < blo || (lo == blo && hi < bhi)));
+        if (better) {
+            best = j;
+            bw = w;
+            blo = lo;
+            bhi = hi;
+        }
+    }
+    cand[i] = best;
+}
+
+__global__ void k_commit(int64_t n, const int32_t *__restrict__ cand, int32_t *__restrict__ mate,
+                         int *__restrict__ still_free) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (mate[i] != -1) return;
+    int32_t c = cand[i];
+    if (c < 0) {
+        mate[i] = -2;  // no free neighbour left: a singleton for good
+    } else if (cand[c] == (int32_t)i) {
+        mate[i] = c;
+    } else {
+        *still_free = 1;
+    }
+}
+
+__global__ void k_leaders(int64_t n, const int32_t *__restrict__ mate, int64_t *__restrict__ flag) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int32_t m = mate[i];
+    flag[i] = (m < 0 || i < m) ? 1 : 0;
+}
+
+__global__ void k_number(int64_t n, const int32_t *__restrict__ mate, const int64_t *__restrict__ id,
+                         int32_t *__restrict__ agg) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int32_t m = mate[i];
+    agg[i] = (int32_t)((m < 0 || i < m) ? id[i] : id[m]);
+}
+
+// ---------------------------------------------------------------- Galerkin
+__global__ void k_count_members(int64_t n, const int32_t *__restrict__ agg, int64_t *__restrict__ cnt) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    atomicAdd((unsigned long long *)&cnt[agg[i]], 1ull);
+}
+
+__global__ void k_place_members(int64_t n, const int32_t *__restrict__ agg, const int64_t *__restrict__ mptr,
+                                unsigned int *__restrict__ cursor, int32_t *__restrict__ mem) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int32_t I = agg[i];
+    unsigned int pos = atomicAdd(&cursor[I], 1u);
+    mem[mptr[I] + pos] = (int32_t)i;
+}
+
+// Members were placed in arbitrary order; sort each (small) list ascending.
+__global__ void k_sort_members(int64_t nc, const int64_t *__restrict__ mptr, int32_t *__restrict__ mem) {
+    int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= nc) return;
+    int64_t a = mptr[I], b = mptr[I + 1];
+    for (int64_t t = a + 1; t < b; t++) {
+        int32_t v = mem[t];
+        int64_t u = t - 1;
+        while (u >= a && mem[u] > v) {
+            mem[u + 1] = mem[u];
+            u--;
+        }
+        mem[u + 1] = v;
+    }
+}
+
+// Coarse row I: members ascending, each fine row in column order, values of
+// equal coarse column J summed in that order (the oracle's order).
+// pass 0: count distinct J into cnt[I]; pass 1: write sorted row.
+template <int PASS>
+__global__ void __launch_bounds__(64) k_galerkin(int64_t nc, const int64_t *__restrict__ mptr,
+                                                 const int32_t *__restrict__ mem, const int64_t *__restrict__ rowptr,
+                                                 const int32_t *__restrict__ col, const double *__restrict__ val,
+                                                 const int32_t *__restrict__ agg, int64_t *__restrict__ cnt,
+                                                 const int64_t *__restrict__ crow, int32_t *__restrict__ ccol,
+                                                 double *__restrict__ cval, int *__restrict__ overflow) {
+    int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= nc) return;
+    int32_t cols[GAL_CAP];
+    double vals[GAL_CAP];
+    int len = 0;
+    for (int64_t t = mptr[I]; t < mptr[I + 1]; t++) {
+        int32_t i = mem[t];
+        for (int64_t e = rowptr[i]; e < rowptr[i + 1]; e++) {
+            int32_t J = agg[col[e]];
+            int u = 0;
+            while (u < len && cols[u] != J) u++;
+            if (u == len) {
+                if (len == GAL_CAP) {
+                    *overflow = 1;
+                    return;
+                }
+                cols[len] = J;
+                vals[len] = 0.0;
+                len++;
+            }
+            vals[u] += val[e];
+        }
+    }
+    if (PASS == 0) {
+        cnt[I] = len;
+        return;
+    }
+    // insertion sort by column
+    for (int a = 1; a < len; a++) {
+        int32_t cj = cols[a];
+        double vj = vals[a];
+        int b = a - 1;
+        while (b >= 0 && cols[b] > cj) {
+            cols[b + 1] = cols[b];
+            vals[b + 1] = vals[b];
+            b--;
+        }
+        cols[b + 1] = cj;
+        vals[b + 1] = vj;
+    }
+    int64_t o = crow[I];
+    for (int a = 0; a < len; a++) {
+        ccol[o + a] = cols[a];
+        cval[o + a] = vals[a];
+    }
+}
+
+__global__ void k_csr_invd(int64_t n, const int64_t *__restrict__ rowptr, const double *__restrict__ val,
+                           double *__restrict__ invd, float *__restrict__ invdf) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+    for (int64_t e = rowptr[i]; e < rowptr[i + 1]; e++) s += fabs(val[e]);
+    if (invd) invd[i] = 1.0 / s;
+    if (invdf) invdf[i] = (float)(1.0 / s);
+}
+
+__global__ void k_compose(int64_t n, int32_t *__restrict__ comp, const int32_t *__restrict__ a) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) comp[i] = a[comp[i]];
+}
+
+__global__ void k_iota(int64_t n, int32_t *__restrict__ x) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = (int32_t)i;
+}
+
+// ----------------------------------------------------- V-cycle, CSR levels
+// Rows are processed by groups of G lanes (G = 8) that stride over the row's
+// entries; the group sum is formed with shuffles in a fixed lane order.
+constexpr int G = 8;
+
+template <class T>
+__device__ inline T group_sum(T v) {
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) v += __shfl_down(v, o, G);
+    return v;
+}
+
+template <class TB, class T>
+__global__ void k_csr_pre(int64_t n, const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+                          const T *__restrict__ val, const T *__restrict__ invd, const TB *__restrict__ b,
+                          T *__restrict__ r) {
+    int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+    int lane = threadIdx.x % G;
+    if (row >= n) return;
+    T s = 0;
+    for (int64_t e = rowptr[row] + lane; e < rowptr[row + 1]; e += G) {
+        int32_t j = col[e];
+        s += val[e] * ((T)b[j] * invd[j]);
+    }
+    s = group_sum(s);
+    if (lane == 0) r[row] = (T)b[row] - s;
+}
+
+template <class TB, class T>
+__global__ void k_csr_post(int64_t n, const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+                           const T *__restrict__ val, const T *__restrict__ invd, const TB *__restrict__ b,
+                           const T *__restrict__ xc, const int32_t *__restrict__ agg, T *__restrict__ x) {
+    int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+    int lane = threadIdx.x % G;
+    if (row >= n) return;
+    T s = 0;
+    for (int64_t e = rowptr[row] + lane; e < rowptr[row + 1]; e += G) {
+        int32_t j = col[e];
+        s += val[e] * ((T)b[j] * invd[j] + xc[agg[j]]);
+    }
+    s = group_sum(s);
+    if (lane == 0) {
+        T xr = (T)b[row] * invd[row] + xc[agg[row]];
+        x[row] = xr + invd[row] * ((T)b[row] - s);
+    }
+}
+
+template <class TB, class T>
+__global__ void k_csr_sweep(int64_t n, const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+                            const T *__restrict__ val, const T *__restrict__ invd, const TB *__restrict__ b,
+                            const T *__restrict__ xin, T *__restrict__ xout, int zero) {
+    int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+    int lane = threadIdx.x % G;
+    if (row >= n) return;
+    if (zero) {
+        if (lane == 0) xout[row] = (T)b[row] * invd[row];
+        return;
+    }
+    T s = 0;
+    for (int64_t e = rowptr[row] + lane; e < rowptr[row + 1]; e += G) s += val[e] * xin[col[e]];
+    s = group_sum(s);
+    if (lane == 0) xout[row] = xin[row] + invd[row] * ((T)b[row] - s);
+}
+
+// bc[I] = sum over the members of I (ascending) of r
+template <class T>
+__global__ void k_restrict(int64_t nc, const int64_t *__restrict__ mptr, const int32_t *__restrict__ mem,
+                           const T *__restrict__ r, T *__restrict__ bc) {
+    int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= nc) return;
+    T s = 0;
+    for (int64_t t = mptr[I]; t < mptr[I + 1]; t++) s += r[mem[t]];
+    bc[I] = s;
+}
+
+// x = Ainv b, one wavefront per row (row-major Ainv)
+template <class TB, class T>
+__global__ void k_dense_gemv(const T *__restrict__ Ainv, const TB *__restrict__ b, T *__restrict__ x, int64_t n) {
+    int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
+    int lane = threadIdx.x % 64;
+    if (row >= n) return;
+    T s = 0;
+    for (int64_t j = lane; j < n; j += 64) s += Ainv[row * n + j] * (T)b[j];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+    if (lane == 0) x[row] = s;
+}
+
+__global__ void k_csr_spmv(int64_t n, const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+                           const double *__restrict__ val, const double *__restrict__ x, double *__restrict__ y) {
+    int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+    int lane = threadIdx.x % G;
+    if (row >= n) return;
+    double s = 0;
+    for (int64_t e = rowptr[row] + lane; e < rowptr[row + 1]; e += G) s += val[e] * x[col[e]];
+    s = group_sum(s);
+    if (lane == 0) y[row] = s;
+}
+
+// ----------------------------------------------- dense coarsest inverse
+__global__ void k_csr_to_dense(int64_t n, const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+                               const double *__restrict__ val, double *__restrict__ D) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int64_t e = rowptr[i]; e < rowptr[i + 1]; e++) D[i * n + col[e]] = val[e];
+}
+
+// Gauss-Jordan step k (no pivoting; an SPD matrix keeps every pivot > 0).
+__global__ void k_gj_save(int64_t n, int64_t k, const double *__restrict__ D, double *__restrict__ rowk,
+                          double *__restrict__ colk) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    rowk[t] = D[k * n + t];
+    colk[t] = D[t * n + k];
+}
+
+__global__ void k_gj_update(int64_t n, int64_t k, double *__restrict__ D, const double *__restrict__ rowk,
+                            const double *__restrict__ colk, int *__restrict__ bad) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * n) return;
+    int64_t i = t / n, j = t - i * n;
+    double p = rowk[k];
+    if (!(p > 0.0)) {
+        if (t == 0) *bad = 1;
+        return;
+    }
+    double v;
+    if (i == k) v = (j == k) ? 1.0 / p : rowk[j] / p;
+    else if (j == k) v = -colk[i] / p;
+    else v = D[t] - colk[i] * rowk[j] / p;
+    D[t] = v;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ host
+rich_status match_sweep(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val, int32_t *agg,
+                        int64_t *nc_out, hipStream_t s) {
+    DevAlloc tmp;
+    double *diag;
+    int32_t *mate, *cand;
+    int64_t *flag, *id, *stmp;
+    int *still;
+    RICH_TRY(tmp.get(&diag, n));
+    RICH_TRY(tmp.get(&mate, n));
+    RICH_TRY(tmp.get(&cand, n));
+    RICH_TRY(tmp.get(&flag, n));
+    RICH_TRY(tmp.get(&id, n + 1));
+    RICH_TRY(tmp.get(&stmp, scan_tmp_size(n)));
+    RICH_TRY(tmp.get(&still, 1));
+    if (n == 0) {
+        *nc_out = 0;
+        return RICH_OK;
+    }
+    k_diag<<<nblocks(n), TPB, 0, s>>>(n, rowptr, col, val, diag);
+    LAUNCH_CHECK();
+    RICH_TRY(launch_fill_i32(mate, -1, n, s));
+    int *h_still = nullptr;
+    HIP_TRY(hipHostMalloc((void **)&h_still, sizeof(int)));
+    rich_status st = RICH_OK;
+    for (int64_t round = 0;; round++) {
+        HIP_TRY(hipMemsetAsync(still, 0, sizeof(int), s));
+        // a few rounds per host check; extra rounds after completion are no-ops
+        for (int t = 0; t < 4; t++) {
+            k_candidates<<<nblocks(n), TPB, 0, s>>>(n, rowptr, col, val, diag, mate, cand);
+            k_commit<<<nblocks(n), TPB, 0, s>>>(n, cand, mate, still);
+        }
+        LAUNCH_CHECK();
+        HIP_TRY(hipMemcpyAsync(h_still, still, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (!*h_still) break;
+        if (round > 4 * n + 16) {  // every round matches or retires at least one vertex
+            st = RICH_EHIP;
+            break;
+        }
+    }
+    (void)hipHostFree(h_still);
+    RICH_TRY(st);
+    k_leaders<<<nblocks(n), TPB, 0, s>>>(n, mate, flag);
+    LAUNCH_CHECK();
+    RICH_TRY(scan_exclusive_i64(flag, id, n, stmp, s));
+    k_number<<<nblocks(n), TPB, 0, s>>>(n, mate, id, agg);
+    LAUNCH_CHECK();
+    int64_t nc = 0;
+    HIP_TRY(hipMemcpyAsync(&nc, id + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *nc_out = nc;
+    return RICH_OK;
+}
+
+rich_status members(const int32_t *agg, int64_t n, int64_t nc, int64_t *mptr, int32_t *mem, hipStream_t s) {
+    DevAlloc tmp;
+    int64_t *cnt, *stmp;
+    unsigned int *cursor;
+    RICH_TRY(tmp.get(&cnt, nc));
+    RICH_TRY(tmp.get(&cursor, nc));
+    RICH_TRY(tmp.get(&stmp, scan_tmp_size(nc)));
+    HIP_TRY(hipMemsetAsync(cnt, 0, nc * sizeof(int64_t), s));
+    HIP_TRY(hipMemsetAsync(cursor, 0, nc * sizeof(unsigned int), s));
+    if (n > 0) {
+        k_count_members<<<nblocks(n), TPB, 0, s>>>(n, agg, cnt);
+        LAUNCH_CHECK();
+    }
+    RICH_TRY(scan_exclusive_i64(cnt, mptr, nc, stmp, s));
+    if (n > 0) {
+        k_place_members<<<nblocks(n), TPB, 0, s>>>(n, agg, mptr, cursor, mem);
+        LAUNCH_CHECK();
+    }
+    if (nc > 0) {
+        k_sort_members<<<nblocks(nc), TPB, 0, s>>>(nc, mptr, mem);
+        LAUNCH_CHECK();
+    }
+    HIP_TRY(hipStreamSynchronize(s));  // tmp is freed on return
+    return RICH_OK;
+}
+
+rich_status galerkin(const CsrDev &A, const int32_t *agg, int64_t nc, CsrDev *C, DevAlloc &mem_out,
+                     hipStream_t s) {
+    DevAlloc tmp;
+    int64_t *mptr, *cnt, *stmp;
+    int32_t *mem;
+    int *overflow;
+    RICH_TRY(tmp.get(&mptr, nc + 1));
+    RICH_TRY(tmp.get(&mem, A.n));
+    RICH_TRY(tmp.get(&cnt, nc));
+    RICH_TRY(tmp.get(&stmp, scan_tmp_size(nc)));
+    RICH_TRY(tmp.get(&overflow, 1));
+    HIP_TRY(hipMemsetAsync(overflow, 0, sizeof(int), s));
+    RICH_TRY(members(agg, A.n, nc, mptr, mem, s));
+    C->n = nc;
+    RICH_TRY(mem_out.get(&C->rowptr, nc + 1));
+    if (nc > 0) {
+        k_galerkin<0><<<nblocks(nc, 64), 64, 0, s>>>(nc, mptr, mem, A.rowptr, A.col, A.val, agg, cnt, nullptr,
+                                                     nullptr, nullptr, overflow);
+        LAUNCH_CHECK();
+    }
+    RICH_TRY(scan_exclusive_i64(cnt, C->rowptr, nc, stmp, s));
+    int64_t nnz = 0;
+    int ovf = 0;
+    HIP_TRY(hipMemcpyAsync(&nnz, C->rowptr + nc, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&ovf, overflow, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (ovf) return RICH_EINVAL;
+    C->nnz = nnz;
+    RICH_TRY(mem_out.get(&C->col, nnz));
+    RICH_TRY(mem_out.get(&C->val, nnz));
+    if (nc > 0) {
+        k_galerkin<1><<<nblocks(nc, 64), 64, 0, s>>>(nc, mptr, mem, A.rowptr, A.col, A.val, agg, nullptr, C->rowptr,
+                                                     C->col, C->val, overflow);
+        LAUNCH_CHECK();
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    return RICH_OK;
+}
+
+rich_status csr_invd(const CsrDev &A, double *invd, float *invdf, hipStream_t s) {
+    if (A.n == 0) return RICH_OK;
+    k_csr_invd<<<nblocks(A.n), TPB, 0, s>>>(A.n, A.rowptr, A.val, invd, invdf);
+    LAUNCH_CHECK();
+    return RICH_OK;
+}
+
+rich_status compose_agg(int32_t *comp, const int32_t *a, int64_t n, hipStream_t s) {
+    if (n == 0) return RICH_OK;
+    if (a == nullptr) {
+        k_iota<<<nblocks(n), TPB, 0, s>>>(n, comp);
+    } else {
+        k_compose<<<nblocks(n), TPB, 0, s>>>(n, comp, a);
+    }
+    LAUNCH_CHECK();
+    return RICH_OK;
+}
+
+// Inverse of an SPD CSR matrix into a dense row-major n x n buffer.
+rich_status dense_inverse(const CsrDev &A, double *D, hipStream_t s) {
+    int64_t n = A.n;
+    DevAlloc tmp;
+    double *rowk, *colk;
+    int *bad;
+    RICH_TRY(tmp.get(&rowk, n));
+    RICH_TRY(tmp.get(&colk, n));
+    RICH_TRY(tmp.get(&bad, 1));
+    HIP_TRY(hipMemsetAsync(bad, 0, sizeof(int), s));
+    HIP_TRY(hipMemsetAsync(D, 0, (size_t)n * n * sizeof(double), s));
+    k_csr_to_dense<<<nblocks(n), TPB, 0, s>>>(n, A.rowptr, A.col, A.val, D);
+    LAUNCH_CHECK();
+    for (int64_t k = 0; k < n; k++) {
+        k_gj_save<<<nblocks(n), TPB, 0, s>>>(n, k, D, rowk, colk);
+        k_gj_update<<<nblocks(n * n), TPB, 0, s>>>(n, k, D, rowk, colk, bad);
+    }
+    LAUNCH_CHECK();
+    int hb = 0;
+    HIP_TRY(hipMemcpyAsync(&hb, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return hb ? RICH_NOT_SPD : RICH_OK;
+}
+
+template <class TB, class T>
+rich_status launch_csr_pre(const Level &Lv, const T *val, const T *invd, const TB *b, T *r, hipStream_t s) {
+    if (Lv.n == 0) return RICH_OK;
+    k_csr_pre<TB, T><<<nblocks(Lv.n * G), TPB, 0, s>>>(Lv.n, Lv.rowptr, Lv.col, val, invd, b, r);
+    LAUNCH_CHECK();
+    return RICH_OK;
+}
+
+template <class TB, class T>
+rich_status launch_csr_post(const Level &Lv, const T *val, const T *invd, const TB *b, const T *xc, T *x,
+                            hipStream_t s) {
+    if (Lv.n == 0) return RICH_OK;
+    k_csr_post<TB, T><<<nblocks(Lv.n * G), TPB, 0, s>>>(Lv.n, Lv.rowptr, Lv.col, val, invd, b, xc, Lv.agg, x);
+    LAUNCH_CHECK();
+    return RICH_OK;
+}
+
+template <class T>
+rich_status launch_restrict(const Level &Lv, const T *r, T *bc, int64_t nc, hipStream_t s) {
+    if (nc == 0) return RICH_OK;
+    k_restrict<T><<<nblocks(nc), TPB, 0, s>>>(nc, Lv.mptr, Lv.mem, r, bc);
+    LAUNCH_CHECK();
+    return RICH_OK;
+}
+
+template <class TB, class T>
+rich_status launch_dense_gemv(const T *Ainv, const TB *b, T *x, int64_t n, hipStream_t s) {
+    if (n == 0) return RICH_OK;
+    k_dense_gemv<TB, T><<<nblocks(n * 64), TPB, 0, s>>>(Ainv, b, x, n);
+    LAUNCH_CHECK();
+    return RICH_OK;
+}
+
+template <class TB, class T>
+rich_status launch_csr_sweeps(const Level &Lv, const T *val, const T *invd, const TB *b, T *x, T *tmp, int sweeps,
+                              hipStream_t s) {
+    if (Lv.n == 0) return RICH_OK;
+    T *cur = (sweeps % 2 == 1) ? x : tmp;
+    k_csr_sweep<TB, T><<<nblocks(Lv.n * G), TPB, 0, s>>>(Lv.n, Lv.rowptr, Lv.col, val, invd, b, nullptr, cur, 1);
+    LAUNCH_CHECK();
+    for (int t = 1; t < sweeps; t++) {
+        T *nxt = (cur == x) ? tmp : x;
+        k_csr_sweep<TB, T><<<nblocks(Lv.n * G), TPB, 0, s>>>(Lv.n, Lv.rowptr, Lv.col, val, invd, b, cur, nxt, 0);
+        LAUNCH_CHECK();
+        cur = nxt;
+    }
+    return RICH_OK;
+}
+
+rich_status launch_csr_spmv(const CsrDev &A, const double *x, double *y, hipStream_t s) {
+    if (A.n == 0) return RICH_OK;
+    k_csr_spmv<<<nblocks(A.n * G), TPB, 0, s>>>(A.n, A.rowptr, A.col, A.val, x, y);
+    LAUNCH_CHECK();
+    return RICH_OK;
+}
+
+#define INST_CSR(TB, T)                                                                                         \
+    template rich_status launch_csr_pre<TB, T>(const Level &, const T *, const T *, const TB *, T *, hipStream_t); \
+    template rich_status launch_csr_post<TB, T>(const Level &, const T *, const T *, const TB *, const T *, T *,   \
+                                                hipStream_t);                                                     \
+    template rich_status launch_dense_gemv<TB, T>(const T *, const TB *, T *, int64_t, hipStream_t);               \
+    template rich_status launch_csr_sweeps<TB, T>(const Level &, const T *, const T *, const TB *, T *, T *, int,  \
+                                                  hipStream_t);
+INST_CSR(double, double)
+INST_CSR(double, float)
+INST_CSR(float, float)
+template rich_status launch_restrict<double>(const Level &, const double *, double *, int64_t, hipStream_t);
+template rich_status launch_restrict<float>(const Level &, const float *, float *, int64_t, hipStream_t);
+
+}  // namespace rich

@@ -1,0 +1,212 @@
+// Internal declarations shared by the HIP translation units of librichards.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/richards.h"
+
+namespace rich {
+
+void set_error(const char *what, const char *file, int line, hipError_t e);
+const char *last_error();
+
+#define HIP_TRY(...)                                                    \
+    do {                                                                \
+        hipError_t e_ = (__VA_ARGS__);                                  \
+        if (e_ != hipSuccess) {                                         \
+            ::rich::set_error(#__VA_ARGS__, __FILE__, __LINE__, e_);    \
+            return RICH_EHIP;                                           \
+        }                                                               \
+    } while (0)
+
+#define RICH_TRY(...)                   \
+    do {                                \
+        rich_status s_ = (__VA_ARGS__); \
+        if (s_ != RICH_OK) return s_;   \
+    } while (0)
+
+#define LAUNCH_CHECK() HIP_TRY(hipGetLastError())
+
+// Problem parameters passed by value to the stencil kernels.
+struct Phys {
+    int nx, ny, nz;
+    double hx, hy, hz;
+    double alpha, beta, theta_s, theta_r, A, gamma;
+    int mean;
+    int bc_type[6];
+    double bc_value[6];
+    double dt;
+};
+
+// Device buffer owned by a context (raw hipMalloc, freed in the context's destructor).
+struct DevAlloc {
+    std::vector<void *> ptrs;
+    size_t bytes = 0;
+    template <class T>
+    rich_status get(T **out, size_t count) {
+        void *p = nullptr;
+        size_t b = count * sizeof(T);
+        if (b == 0) b = 16;
+        if (hipMalloc(&p, b) != hipSuccess) {
+            (void)hipGetLastError();
+            return RICH_ENOMEM;
+        }
+        ptrs.push_back(p);
+        bytes += b;
+        *out = static_cast<T *>(p);
+        return RICH_OK;
+    }
+    void release(void *p) {
+        for (auto &q : ptrs)
+            if (q == p) {
+                (void)hipFree(q);
+                q = nullptr;
+            }
+    }
+    ~DevAlloc() {
+        for (void *p : ptrs)
+            if (p) (void)hipFree(p);
+    }
+};
+
+// ---------------------------------------------------------------- fine level
+// Jacobian: 7 FP64 coefficient arrays of N, slot t*N + c, t = diag,-x,+x,-y,+y,-z,+z.
+// Auxiliary M: 4 arrays, t = diag, +x, +y, +z (symmetric; the -d coupling of
+// cell c is the +d coupling stored at its lower neighbour).
+enum { J_D = 0, J_XM, J_XP, J_YM, J_YP, J_ZM, J_ZP };
+enum { M_D = 0, M_XP, M_YP, M_ZP };
+
+rich_status launch_theta(const Phys &P, const double *p, double *theta, hipStream_t s);
+rich_status launch_residual(const Phys &P, const double *Ks, const double *p, const double *theta_old,
+                            double *F, hipStream_t s);
+// Assemble J (7N) and M (4N, FP64) plus M's FP32 copy (may be null) and the
+// l1 inverse diagonal of M in FP64 and FP32 (either may be null).
+rich_status launch_assemble(const Phys &P, const double *Ks, const double *p, double *J7, double *M4,
+                            float *M4f, double *invd, float *invdf, hipStream_t s);
+template <class TX>
+rich_status launch_spmv_J(const Phys &P, const double *J7, const TX *x, double *y, hipStream_t s);
+rich_status launch_spmv_M(const Phys &P, const double *M4, const double *x, double *y, hipStream_t s);
+rich_status launch_stencil_to_csr(const Phys &P, const double *M4, const int64_t *rowptr,
+                                  int32_t *col, double *val, hipStream_t s);
+rich_status launch_J_to_csr(const Phys &P, const double *J7, const int64_t *rowptr, int32_t *col,
+                            double *val, hipStream_t s);
+rich_status launch_stencil_rowcounts(const Phys &P, int64_t *rowptr_plus1, hipStream_t s);
+
+// fine-level V-cycle pieces (TB: type of the right-hand side, T: arithmetic)
+template <class TB, class T>
+rich_status launch_st_pre(const Phys &P, const T *M4, const T *invd, const TB *b, T *r, hipStream_t s);
+template <class TB, class T>
+rich_status launch_st_post(const Phys &P, const T *M4, const T *invd, const TB *b, const T *xc,
+                           const int32_t *agg, T *x, hipStream_t s);
+template <class TB, class T>
+rich_status launch_st_sweeps(const Phys &P, const T *M4, const T *invd, const TB *b, T *x, T *tmp,
+                             int sweeps, hipStream_t s);
+
+// ------------------------------------------------------------ vector kernels
+constexpr int RED_BLOCKS = 1024;   // fixed block count of every reduction (deterministic order)
+constexpr int RED_THREADS = 256;
+
+// partial[blk*(k+1) + i] for i < k: V_i . w ; slot k: w . w.  Then reduced in fixed order.
+rich_status launch_multidot(const double *V, int64_t ldv, int k, const double *w, int64_t n,
+                            double *partial, double *out, hipStream_t s);
+// w -= sum_i h_i V_i (i < k, h on device); out[0] = ||w||^2 (after update)
+rich_status launch_update_norm(const double *V, int64_t ldv, int k, const double *h, double *w,
+                               int64_t n, double *partial, double *out, hipStream_t s);
+// out[0] = x.y (deterministic)
+rich_status launch_dot(const double *x, const double *y, int64_t n, double *partial, double *out,
+                       hipStream_t s);
+// out[0] = max |x_i| (NaN propagates), out[1] = sum x_i, out[2] = x.x
+rich_status launch_norms(const double *x, int64_t n, double *partial, double *out, hipStream_t s);
+// out[0] = max_i |a*d_i| / max(|u_i|, 1)
+rich_status launch_rel_length(const double *d, const double *u, int64_t n, double *partial,
+                              double *out, hipStream_t s);
+rich_status launch_scale(double *x, double a, int64_t n, hipStream_t s);
+rich_status launch_scale_dev(double *x, const double *inv_of, int64_t n, hipStream_t s);
+// y = a*x + b*y
+rich_status launch_axpby(double a, const double *x, double b, double *y, int64_t n, hipStream_t s);
+// z = x + a*y
+rich_status launch_xpay_to(const double *x, double a, const double *y, double *z, int64_t n,
+                           hipStream_t s);
+template <class TX>
+rich_status launch_add_to(double *y, const TX *x, int64_t n, hipStream_t s);
+// y = sum_i c_i V_i, c on device (k entries)
+rich_status launch_lincomb(const double *V, int64_t ldv, int k, const double *c, double *y, int64_t n,
+                           hipStream_t s);
+// y = b - y
+rich_status launch_b_minus(const double *b, double *y, int64_t n, hipStream_t s);
+rich_status launch_negate_to(const double *x, double *y, int64_t n, hipStream_t s);
+template <class TA, class TB>
+rich_status launch_cast(const TA *a, TB *b, int64_t n, hipStream_t s);
+rich_status launch_fill_i32(int32_t *x, int32_t v, int64_t n, hipStream_t s);
+rich_status launch_fill_f64(double *x, double v, int64_t n, hipStream_t s);
+
+// exclusive scan of int64 counts in place: out[0] = 0, out[i] = sum_{k<i} in[k];
+// out has n+1 entries; tmp needs scan_tmp_size(n) int64 entries.
+int64_t scan_tmp_size(int64_t n);
+rich_status scan_exclusive_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *tmp,
+                               hipStream_t s);
+
+// ---------------------------------------------------------------------- AMG
+struct Level {
+    int64_t n = 0, nnz = 0;
+    int64_t *rowptr = nullptr;  // CSR (levels >= 1 only)
+    int32_t *col = nullptr;
+    double *val = nullptr;
+    float *valf = nullptr;
+    double *invd = nullptr;     // 1 / sum_j |a_ij|
+    float *invdf = nullptr;
+    int32_t *agg = nullptr;     // to level+1 (n)
+    int64_t *mptr = nullptr;    // members of each coarse row (n_{l+1} + 1)
+    int32_t *mem = nullptr;     // (n)
+    // V-cycle work vectors, in the cycle's precision
+    void *b = nullptr, *x = nullptr, *r = nullptr;
+};
+
+struct Hierarchy {
+    int nlev = 0;
+    Level L[16];
+    bool dense = false;          // coarsest solved by dense inverse
+    double *cinv = nullptr;      // n_c x n_c inverse (row-major), FP64
+    float *cinvf = nullptr;
+    int64_t nnz_total = 0;
+    DevAlloc mem;
+};
+
+// one matching sweep on a device CSR (setup-time); returns n_coarse
+rich_status match_sweep(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
+                        int32_t *agg, int64_t *nc_out, hipStream_t s);
+// C = P^T A P for piecewise-constant P given by agg (canonical summation order)
+struct CsrDev {
+    int64_t n = 0, nnz = 0;
+    int64_t *rowptr = nullptr;
+    int32_t *col = nullptr;
+    double *val = nullptr;
+};
+rich_status galerkin(const CsrDev &A, const int32_t *agg, int64_t nc, CsrDev *C, DevAlloc &mem,
+                     hipStream_t s);
+rich_status members(const int32_t *agg, int64_t n, int64_t nc, int64_t *mptr, int32_t *mem,
+                    hipStream_t s);
+rich_status csr_invd(const CsrDev &A, double *invd, float *invdf, hipStream_t s);
+// dense row-major inverse of an SPD CSR matrix (Gauss-Jordan; RICH_NOT_SPD on a non-positive pivot)
+rich_status dense_inverse(const CsrDev &A, double *D, hipStream_t s);
+rich_status compose_agg(int32_t *comp, const int32_t *a, int64_t n, hipStream_t s);
+
+template <class TB, class T>
+rich_status launch_csr_pre(const Level &Lv, const T *val, const T *invd, const TB *b, T *r, hipStream_t s);
+template <class TB, class T>
+rich_status launch_csr_post(const Level &Lv, const T *val, const T *invd, const TB *b, const T *xc,
+                            T *x, hipStream_t s);
+template <class T>
+rich_status launch_restrict(const Level &Lv, const T *r, T *bc, int64_t nc, hipStream_t s);
+template <class TB, class T>
+rich_status launch_dense_gemv(const T *Ainv, const TB *b, T *x, int64_t n, hipStream_t s);
+template <class TB, class T>
+rich_status launch_csr_sweeps(const Level &Lv, const T *val, const T *invd, const TB *b, T *x, T *tmp,
+                              int sweeps, hipStream_t s);
+rich_status launch_csr_spmv(const CsrDev &A, const double *x, double *y, hipStream_t s);
+
+}  // namespace rich

@@ -1,0 +1,453 @@
+// Fine-grid kernels: constitutive laws, residual Phi, Jacobian / auxiliary
+// matrix assembly, 7-point stencil products and the fine-level pieces of the
+// AMG V-cycle.  One thread per cell, x-fastest cell order, SoA coefficient
+// arrays (every load and store of a wavefront is one contiguous run).
+#include "common.hpp"
+
+namespace rich {
+
+namespace {
+
+constexpr int TPB = 256;
+
+inline unsigned nblocks(int64_t n, int tpb = TPB) { return (unsigned)((n + tpb - 1) / tpb); }
+
+struct Cell {
+    int i, j, k;
+};
+
+__device__ inline Cell cell_of(const Phys &P, uint32_t c) {
+    uint32_t nxy = (uint32_t)P.nx * (uint32_t)P.ny;
+    uint32_t k = c / nxy;
+    uint32_t rem = c - k * nxy;
+    uint32_t j = rem / (uint32_t)P.nx;
+    uint32_t i = rem - j * (uint32_t)P.nx;
+    return {(int)i, (int)j, (int)k};
+}
+
+// Section 2, eq. (s(p)) and eq. (K(p)) with rho*phi = 1 and K_s per cell;
+// derivatives eq. (derivativeofcoefficients) for p < 0.  p >= 0 is the
+// saturated regime (K = K_s, theta = theta_s, derivatives 0).
+// |p|^beta and |p|^gamma share one log: exp(beta*log|p|), exp(gamma*log|p|).
+struct Law {
+    double th, dth, K, dK;
+};
+
+__device__ inline Law laws(const Phys &P, double p, double Ks) {
+    Law L;
+    if (p >= 0.0) {
+        L.th = P.theta_s;
+        L.dth = 0.0;
+        L.K = Ks;
+        L.dK = 0.0;
+        return L;
+    }
+    double a = -p;
+    double la = log(a);
+    double ab = exp(P.beta * la);
+    double ag = exp(P.gamma * la);
+    double ds = P.theta_s - P.theta_r;
+    double tden = P.alpha + ab;
+    double kden = P.A + ag;
+    L.th = P.alpha * ds / tden + P.theta_r;
+    L.dth = P.alpha * P.beta * ds * (ab / a) / (tden * tden);
+    L.K = Ks * P.A / kden;
+    L.dK = Ks * P.A * P.gamma * (ag / a) / (kden * kden);
+    return L;
+}
+
+// One face of cell c.  kind: 0 = none (no-flux face), 1 = interior neighbour,
+// 2 = Dirichlet boundary node (head = face value, K_s = the cell's).
+struct Face {
+    int kind;
+    uint32_t n;
+    double pn, Ksn, h;
+};
+
+__device__ inline Face face(const Phys &P, const Cell &q, uint32_t c, int f, const double *p,
+                            const double *Ks) {
+    Face F;
+    int axis = f >> 1;
+    int dir = (f & 1) ? 1 : -1;
+    int ii = q.i + (axis == 0 ? dir : 0);
+    int jj = q.j + (axis == 1 ? dir : 0);
+    int kk = q.k + (axis == 2 ? dir : 0);
+    F.h = axis == 0 ? P.hx : (axis == 1 ? P.hy : P.hz);
+    int inside = (axis == 0) ? (ii >= 0 && ii < P.nx) : (axis == 1) ? (jj >= 0 && jj < P.ny) : (kk >= 0 && kk < P.nz);
+    if (inside) {
+        uint32_t stride = axis == 0 ? 1u : (axis == 1 ? (uint32_t)P.nx : (uint32_t)P.nx * (uint32_t)P.ny);
+        F.n = dir > 0 ? c + stride : c - stride;
+        F.kind = 1;
+        F.pn = p[F.n];
+        F.Ksn = Ks[F.n];
+    } else if (P.bc_type[f] == RICH_BC_DIRICHLET) {
+        F.kind = 2;
+        F.n = c;
+        F.pn = P.bc_value[f];
+        F.Ksn = Ks[c];
+    } else {
+        F.kind = 0;
+        F.n = c;
+        F.pn = 0.0;
+        F.Ksn = 0.0;
+    }
+    return F;
+}
+
+// Interface mean of K and its partial derivatives (Section 2.1).  dir > 0:
+// the neighbour is the higher-index side U; upstream takes K_U when
+// p_U - p_L >= 0, else K_L.
+__device__ inline void mean_of(int mean, int dir, double pc, const Law &Lc, double pn, const Law &Ln,
+                               double &Kf, double &dc, double &dn) {
+    if (mean == RICH_MEAN_ARITH) {
+        Kf = 0.5 * (Lc.K + Ln.K);
+        dc = 0.5 * Lc.dK;
+        dn = 0.5 * Ln.dK;
+    } else if (mean == RICH_MEAN_HARMONIC) {
+        double s = Lc.K + Ln.K;
+        Kf = 2.0 * Lc.K * Ln.K / s;
+        dc = 2.0 * Ln.K * Ln.K * Lc.dK / (s * s);
+        dn = 2.0 * Lc.K * Lc.K * Ln.dK / (s * s);
+    } else {
+        bool take_n = dir > 0 ? (pn - pc >= 0.0) : !(pc - pn >= 0.0);
+        if (take_n) {
+            Kf = Ln.K;
+            dc = 0.0;
+            dn = Ln.dK;
+        } else {
+            Kf = Lc.K;
+            dc = Lc.dK;
+            dn = 0.0;
+        }
+    }
+}
+
+__global__ void k_theta(Phys P, uint32_t n, const double *__restrict__ p, double *__restrict__ th) {
+    uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    th[c] = laws(P, p[c], 1.0).th;
+}
+
+// eq. (dynamic_of_the_problem), f = 0: time term plus, per face, the
+// diffusive flux -K^AV (p_n - p_c)/h^2 and on z faces the gravity part
+// +-(K_c + K_n)/(2 h_z) (the paper's centred -(K_{k+1} - K_{k-1})/(2 h_z)
+// written face by face; a no-flux face contributes nothing).
+__global__ void k_residual(Phys P, uint32_t n, const double *__restrict__ Ks, const double *__restrict__ p,
+                           const double *__restrict__ th_old, double *__restrict__ F) {
+    uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    Cell q = cell_of(P, c);
+    double pc = p[c];
+    Law Lc = laws(P, pc, Ks[c]);
+    double acc = (Lc.th - th_old[c]) / P.dt;
+#pragma unroll
+    for (int f = 0; f < 6; f++) {
+        Face fc = face(P, q, c, f, p, Ks);
+        if (fc.kind == 0) continue;
+        Law Ln = laws(P, fc.pn, fc.Ksn);
+        double Kf, dc, dn;
+        int dir = (f & 1) ? 1 : -1;
+        mean_of(P.mean, dir, pc, Lc, fc.pn, Ln, Kf, dc, dn);
+        acc += -Kf * (fc.pn - pc) / (fc.h * fc.h);
+        if ((f >> 1) == 2) acc += dir * (-(Lc.K + Ln.K) / (2.0 * P.hz));
+    }
+    F[c] = acc;
+}
+
+// Jacobian rows (analytic derivatives of the residual above) and the
+// auxiliary matrix of Section 4's closing construction: the Jacobian of the
+// diffusion-only flux q = -K grad p with the conductivity frozen, plus the
+// time term.  Also the l1 row sums of M (diag + sum |off|) as inverses.
+__global__ void k_assemble(Phys P, uint32_t n, const double *__restrict__ Ks, const double *__restrict__ p,
+                           double *__restrict__ J7, double *__restrict__ M4, float *__restrict__ M4f,
+                           double *__restrict__ invd, float *__restrict__ invdf) {
+    uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    Cell q = cell_of(P, c);
+    double pc = p[c];
+    Law Lc = laws(P, pc, Ks[c]);
+    double jd = Lc.dth / P.dt;
+    double md = Lc.dth / P.dt;
+    double joff[6] = {0, 0, 0, 0, 0, 0};
+    double moff[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int f = 0; f < 6; f++) {
+        Face fc = face(P, q, c, f, p, Ks);
+        if (fc.kind == 0) continue;
+        Law Ln = laws(P, fc.pn, fc.Ksn);
+        double Kf, dc, dn;
+        int dir = (f & 1) ? 1 : -1;
+        mean_of(P.mean, dir, pc, Lc, fc.pn, Ln, Kf, dc, dn);
+        double h2 = fc.h * fc.h;
+        double dp = fc.pn - pc;
+        bool zf = (f >> 1) == 2;
+        jd += Kf / h2 - dp / h2 * dc;
+        if (zf) jd += -dir * Lc.dK / (2.0 * P.hz);
+        md += Kf / h2;
+        if (fc.kind == 1) {
+            double v = -Kf / h2 - dp / h2 * dn;
+            if (zf) v += -dir * Ln.dK / (2.0 * P.hz);
+            joff[f] = v;
+            moff[f] = -Kf / h2;
+        }
+    }
+    J7[(size_t)J_D * n + c] = jd;
+    J7[(size_t)J_XM * n + c] = joff[0];
+    J7[(size_t)J_XP * n + c] = joff[1];
+    J7[(size_t)J_YM * n + c] = joff[2];
+    J7[(size_t)J_YP * n + c] = joff[3];
+    J7[(size_t)J_ZM * n + c] = joff[4];
+    J7[(size_t)J_ZP * n + c] = joff[5];
+    M4[(size_t)M_D * n + c] = md;
+    M4[(size_t)M_XP * n + c] = moff[1];
+    M4[(size_t)M_YP * n + c] = moff[3];
+    M4[(size_t)M_ZP * n + c] = moff[5];
+    double l1 = md;
+#pragma unroll
+    for (int f = 0; f < 6; f++) l1 += fabs(moff[f]);
+    if (M4f) {
+        M4f[(size_t)M_D * n + c] = (float)md;
+        M4f[(size_t)M_XP * n + c] = (float)moff[1];
+        M4f[(size_t)M_YP * n + c] = (float)moff[3];
+        M4f[(size_t)M_ZP * n + c] = (float)moff[5];
+    }
+    if (invd) invd[c] = 1.0 / l1;
+    if (invdf) invdf[c] = (float)(1.0 / l1);
+}
+
+// y = J x, J in the 7-array stencil form; x may be FP32 (mixed path).
+template <class TX>
+__global__ void k_spmv_J(Phys P, uint32_t n, const double *__restrict__ J7, const TX *__restrict__ x,
+                         double *__restrict__ y) {
+    uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    Cell q = cell_of(P, c);
+    uint32_t nx = P.nx, nxy = (uint32_t)P.nx * (uint32_t)P.ny;
+    double s = J7[(size_t)J_D * n + c] * (double)x[c];
+    if (q.i > 0) s += J7[(size_t)J_XM * n + c] * (double)x[c - 1];
+    if (q.i < P.nx - 1) s += J7[(size_t)J_XP * n + c] * (double)x[c + 1];
+    if (q.j > 0) s += J7[(size_t)J_YM * n + c] * (double)x[c - nx];
+    if (q.j < P.ny - 1) s += J7[(size_t)J_YP * n + c] * (double)x[c + nx];
+    if (q.k > 0) s += J7[(size_t)J_ZM * n + c] * (double)x[c - nxy];
+    if (q.k < P.nz - 1) s += J7[(size_t)J_ZP * n + c] * (double)x[c + nxy];
+    y[c] = s;
+}
+
+// Symmetric stencil M: sum_j m_cj * v_j with the -d couplings read at the lower neighbour.
+template <class T, class F>
+__device__ inline T mstencil(const Phys &P, const Cell &q, uint32_t c, uint32_t n, const T *__restrict__ M4,
+                             F v) {
+    uint32_t nx = P.nx, nxy = (uint32_t)P.nx * (uint32_t)P.ny;
+    T s = M4[(size_t)M_D * n + c] * v(c);
+    if (q.i > 0) s += M4[(size_t)M_XP * n + c - 1] * v(c - 1);
+    if (q.i < P.nx - 1) s += M4[(size_t)M_XP * n + c] * v(c + 1);
+    if (q.j > 0) s += M4[(size_t)M_YP * n + c - nx] * v(c - nx);
+    if (q.j < P.ny - 1) s += M4[(size_t)M_YP * n + c] * v(c + nx);
+    if (q.k > 0) s += M4[(size_t)M_ZP * n + c - nxy] * v(c - nxy);
+    if (q.k < P.nz - 1) s += M4[(size_t)M_ZP * n + c] * v(c + nxy);
+    return s;
+}
+
+__global__ void k_spmv_M(Phys P, uint32_t n, const double *__restrict__ M4, const double *__restrict__ x,
+                         double *__restrict__ y) {
+    uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    Cell q = cell_of(P, c);
+    y[c] = mstencil<double>(P, q, c, n, M4, [&](uint32_t t) { return x[t]; });
+}
+
+// V-cycle, fine level, pre-smoothing from x = 0 and residual in one pass:
+// x0 = D^{-1} b (never stored), r = b - M x0.
+template <class TB, class T>
+__global__ void k_st_pre(Phys P, uint32_t n, const T *__restrict__ M4, const T *__restrict__ invd,
+                         const TB *__restrict__ b, T *__restrict__ r) {
+    uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    Cell q = cell_of(P, c);
+    T s = mstencil<T>(P, q, c, n, M4, [&](uint32_t t) { return (T)b[t] * invd[t]; });
+    r[c] = (T)b[c] - s;
+}
+
+// V-cycle, fine level, prolongation and post-smoothing in one pass:
+// xt = D^{-1} b + P xc (recomputed for the neighbours), x = xt + D^{-1}(b - M xt).
+template <class TB, class T>
+__global__ void k_st_post(Phys P, uint32_t n, const T *__restrict__ M4, const T *__restrict__ invd,
+                          const TB *__restrict__ b, const T *__restrict__ xc, const int32_t *__restrict__ agg,
+                          T *__restrict__ x) {
+    uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    Cell q = cell_of(P, c);
+    auto xt = [&](uint32_t t) { return (T)b[t] * invd[t] + xc[agg[t]]; };
+    T s = mstencil<T>(P, q, c, n, M4, xt);
+    T xc0 = xt(c);
+    x[c] = xc0 + invd[c] * ((T)b[c] - s);
+}
+
+// Plain l1-Jacobi sweep x_out = x_in + D^{-1}(b - M x_in) (used when the
+// fine level is also the coarsest and too large for a direct solve).
+template <class TB, class T>
+__global__ void k_st_sweep(Phys P, uint32_t n, const T *__restrict__ M4, const T *__restrict__ invd,
+                           const TB *__restrict__ b, const T *__restrict__ xin, T *__restrict__ xout, int zero) {
+    uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    if (zero) {
+        xout[c] = (T)b[c] * invd[c];
+        return;
+    }
+    Cell q = cell_of(P, c);
+    T s = mstencil<T>(P, q, c, n, M4, [&](uint32_t t) { return xin[t]; });
+    xout[c] = xin[c] + invd[c] * ((T)b[c] - s);
+}
+
+__global__ void k_stencil_rowcounts(Phys P, uint32_t n, int64_t *__restrict__ cnt) {
+    uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    Cell q = cell_of(P, c);
+    cnt[c] = 1 + (q.i > 0) + (q.i < P.nx - 1) + (q.j > 0) + (q.j < P.ny - 1) + (q.k > 0) + (q.k < P.nz - 1);
+}
+
+// Stencil -> CSR with ascending columns (-z,-y,-x,c,+x,+y,+z).
+__global__ void k_M_to_csr(Phys P, uint32_t n, const double *__restrict__ M4, const int64_t *__restrict__ rowptr,
+                           int32_t *__restrict__ col, double *__restrict__ val) {
+    uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    Cell q = cell_of(P, c);
+    uint32_t nx = P.nx, nxy = (uint32_t)P.nx * (uint32_t)P.ny;
+    int64_t e = rowptr[c];
+    if (q.k > 0) { col[e] = c - nxy; val[e++] = M4[(size_t)M_ZP * n + c - nxy]; }
+    if (q.j > 0) { col[e] = c - nx; val[e++] = M4[(size_t)M_YP * n + c - nx]; }
+    if (q.i > 0) { col[e] = c - 1; val[e++] = M4[(size_t)M_XP * n + c - 1]; }
+    col[e] = c; val[e++] = M4[(size_t)M_D * n + c];
+    if (q.i < P.nx - 1) { col[e] = c + 1; val[e++] = M4[(size_t)M_XP * n + c]; }
+    if (q.j < P.ny - 1) { col[e] = c + nx; val[e++] = M4[(size_t)M_YP * n + c]; }
+    if (q.k < P.nz - 1) { col[e] = c + nxy; val[e++] = M4[(size_t)M_ZP * n + c]; }
+}
+
+__global__ void k_J_to_csr(Phys P, uint32_t n, const double *__restrict__ J7, const int64_t *__restrict__ rowptr,
+                           int32_t *__restrict__ col, double *__restrict__ val) {
+    uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    Cell q = cell_of(P, c);
+    uint32_t nx = P.nx, nxy = (uint32_t)P.nx * (uint32_t)P.ny;
+    int64_t e = rowptr[c];
+    if (q.k > 0) { col[e] = c - nxy; val[e++] = J7[(size_t)J_ZM * n + c]; }
+    if (q.j > 0) { col[e] = c - nx; val[e++] = J7[(size_t)J_YM * n + c]; }
+    if (q.i > 0) { col[e] = c - 1; val[e++] = J7[(size_t)J_XM * n + c]; }
+    col[e] = c; val[e++] = J7[(size_t)J_D * n + c];
+    if (q.i < P.nx - 1) { col[e] = c + 1; val[e++] = J7[(size_t)J_XP * n + c]; }
+    if (q.j < P.ny - 1) { col[e] = c + nx; val[e++] = J7[(size_t)J_YP * n + c]; }
+    if (q.k < P.nz - 1) { col[e] = c + nxy; val[e++] = J7[(size_t)J_ZP * n + c]; }
+}
+
+}  // namespace
+
+static inline uint32_t ncells(const Phys &P) { return (uint32_t)((int64_t)P.nx * P.ny * P.nz); }
+
+rich_status launch_theta(const Phys &P, const double *p, double *theta, hipStream_t s) {
+    uint32_t n = ncells(P);
+    k_theta<<<nblocks(n), TPB, 0, s>>>(P, n, p, theta);
+    LAUNCH_CHECK();
+    return RICH_OK;
+}
+
+rich_status launch_residual(const Phys &P, const double *Ks, const double *p, const double *theta_old,
+                            double *F, hipStream_t s) {
+    uint32_t n = ncells(P);
+    k_residual<<<nblocks(n), TPB, 0, s>>>(P, n, Ks, p, theta_old, F);
+    LAUNCH_CHECK();
+    return RICH_OK;
+}
+
+rich_status launch_assemble(const Phys &P, const double *Ks, const double *p, double *J7, double *M4,
+                            float *M4f, double *invd, float *invdf, hipStream_t s) {
+    uint32_t n = ncells(P);
+    k_assemble<<<nblocks(n), TPB, 0, s>>>(P, n, Ks, p, J7, M4, M4f, invd, invdf);
+    LAUNCH_CHECK();
+    return RICH_OK;
+}
+
+template <class TX>
+rich_status launch_spmv_J(const Phys &P, const double *J7, const TX *x, double *y, hipStream_t s) {
+    uint32_t n = ncells(P);
+    k_spmv_J<TX><<<nblocks(n), TPB, 0, s>>>(P, n, J7, x, y);
+    LAUNCH_CHECK();
+    return RICH_OK;
+}
+template rich_status launch_spmv_J<double>(const Phys &, const double *, const double *, double *, hipStream_t);
+template rich_status launch_spmv_J<float>(const Phys &, const double *, const float *, double *, hipStream_t);
+
+rich_status launch_spmv_M(const Phys &P, const double *M4, const double *x, double *y, hipStream_t s) {
+    uint32_t n = ncells(P);
+    k_spmv_M<<<nblocks(n), TPB, 0, s>>>(P, n, M4, x, y);
+    LAUNCH_CHECK();
+    return RICH_OK;
+}
+
+template <class TB, class T>
+rich_status launch_st_pre(const Phys &P, const T *M4, const T *invd, const TB *b, T *r, hipStream_t s) {
+    uint32_t n = ncells(P);
+    k_st_pre<TB, T><<<nblocks(n), TPB, 0, s>>>(P, n, M4, invd, b, r);
+    LAUNCH_CHECK();
+    return RICH_OK;
+}
+
+template <class TB, class T>
+rich_status launch_st_post(const Phys &P, const T *M4, const T *invd, const TB *b, const T *xc,
+                           const int32_t *agg, T *x, hipStream_t s) {
+    uint32_t n = ncells(P);
+    k_st_post<TB, T><<<nblocks(n), TPB, 0, s>>>(P, n, M4, invd, b, xc, agg, x);
+    LAUNCH_CHECK();
+    return RICH_OK;
+}
+
+template <class TB, class T>
+rich_status launch_st_sweeps(const Phys &P, const T *M4, const T *invd, const TB *b, T *x, T *tmp,
+                             int sweeps, hipStream_t s) {
+    uint32_t n = ncells(P);
+    // x <- D^{-1} b is the first sweep from zero; then ping-pong x <-> tmp.
+    T *cur = (sweeps % 2 == 1) ? x : tmp;
+    k_st_sweep<TB, T><<<nblocks(n), TPB, 0, s>>>(P, n, M4, invd, b, nullptr, cur, 1);
+    LAUNCH_CHECK();
+    for (int t = 1; t < sweeps; t++) {
+        T *nxt = (cur == x) ? tmp : x;
+        k_st_sweep<TB, T><<<nblocks(n), TPB, 0, s>>>(P, n, M4, invd, b, cur, nxt, 0);
+        LAUNCH_CHECK();
+        cur = nxt;
+    }
+    return RICH_OK;
+}
+
+#define INST_ST(TB, T)                                                                                    \
+    template rich_status launch_st_pre<TB, T>(const Phys &, const T *, const T *, const TB *, T *, hipStream_t); \
+    template rich_status launch_st_post<TB, T>(const Phys &, const T *, const T *, const TB *, const T *,      \
+                                               const int32_t *, T *, hipStream_t);                              \
+    template rich_status launch_st_sweeps<TB, T>(const Phys &, const T *, const T *, const TB *, T *, T *, int, \
+                                                 hipStream_t);
+INST_ST(double, double)
+INST_ST(double, float)
+INST_ST(float, float)
+
+rich_status launch_stencil_rowcounts(const Phys &P, int64_t *cnt, hipStream_t s) {
+    uint32_t n = ncells(P);
+    k_stencil_rowcounts<<<nblocks(n), TPB, 0, s>>>(P, n, cnt);
+    LAUNCH_CHECK();
+    return RICH_OK;
+}
+
+rich_status launch_stencil_to_csr(const Phys &P, const double *M4, const int64_t *rowptr, int32_t *col,
+                                  double *val, hipStream_t s) {
+    uint32_t n = ncells(P);
+    k_M_to_csr<<<nblocks(n), TPB, 0, s>>>(P, n, M4, rowptr, col, val);
+    LAUNCH_CHECK();
+    return RICH_OK;
+}
+
+rich_status launch_J_to_csr(const Phys &P, const double *J7, const int64_t *rowptr, int32_t *col,
+                            double *val, hipStream_t s) {
+    uint32_t n = ncells(P);
+    k_J_to_csr<<<nblocks(n), TPB, 0, s>>>(P, n, J7, rowptr, col, val);
+    LAUNCH_CHECK();
+    return RICH_OK;
+}
+
+}  // namespace rich

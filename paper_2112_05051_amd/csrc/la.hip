@@ -1,0 +1,448 @@
+// Vector kernels for the Krylov and Newton loops: deterministic reductions
+// (fixed grid, per-block partials, then one fixed-order pass), the fused
+// classical Gram-Schmidt dot block and update, axpy-type updates, casts and
+// an exclusive scan for the setup phase.
+#include "common.hpp"
+
+namespace rich {
+
+namespace {
+
+constexpr int TPB = 256;
+constexpr int WAVE = 64;
+constexpr int KMAX = 66;  // GMRES restart (<= 64) + 2
+
+inline unsigned nblocks(int64_t n, int tpb = TPB) { return (unsigned)((n + tpb - 1) / tpb); }
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_down(v, o, WAVE);
+    return v;
+}
+
+__device__ inline double wave_max(double v) {
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) {
+        double u = __shfl_down(v, o, WAVE);
+        v = (u > v || u != u) ? u : v;
+    }
+    return v;
+}
+
+// Block sum of one value per thread, result valid in thread 0.
+__device__ inline double block_sum(double v, double *sh) {
+    v = wave_sum(v);
+    int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+    __syncthreads();
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0)
+        for (int t = 0; t < (int)(blockDim.x / WAVE); t++) r += sh[t];
+    return r;
+}
+
+__device__ inline double block_max(double v, double *sh) {
+    v = wave_max(v);
+    int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+    __syncthreads();
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0)
+        for (int t = 0; t < (int)(blockDim.x / WAVE); t++) r = (sh[t] > r || sh[t] != sh[t]) ? sh[t] : r;
+    return r;
+}
+
+// Dot products of w with V_0..V_{k-1} and w.w, partial per block.  Every
+// thread keeps k+1 running sums over its grid-stride rows.
+template <int KC>
+__global__ void __launch_bounds__(RED_THREADS) k_multidot(const double *__restrict__ V, int64_t ldv, int k,
+                                                          const double *__restrict__ w, int64_t n,
+                                                          double *__restrict__ partial) {
+    __shared__ double sh[RED_THREADS / WAVE];
+    double acc[KC + 1];
+#pragma unroll
+    for (int i = 0; i <= KC; i++) acc[i] = 0.0;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x) {
+        double wc = w[c];
+#pragma unroll
+        for (int i = 0; i < KC; i++)
+            if (i < k) acc[i] += V[(size_t)i * ldv + c] * wc;
+        acc[KC] += wc * wc;
+    }
+    for (int i = 0; i < k; i++) {
+        double r = block_sum(acc[i], sh);
+        if (threadIdx.x == 0) partial[(size_t)blockIdx.x * (k + 1) + i] = r;
+    }
+    double r = block_sum(acc[KC], sh);
+    if (threadIdx.x == 0) partial[(size_t)blockIdx.x * (k + 1) + k] = r;
+}
+
+// out[i] = sum_b partial[b*(m) + i], b ascending (one block per output).
+__global__ void k_reduce_partials(const double *__restrict__ partial, int m, int nb, double *__restrict__ out) {
+    __shared__ double sh[RED_THREADS / WAVE];
+    int i = blockIdx.x;
+    double a = 0.0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) a += partial[(size_t)b * m + i];
+    double r = block_sum(a, sh);
+    if (threadIdx.x == 0) out[i] = r;
+}
+
+__global__ void k_reduce_max(const double *__restrict__ partial, int m, int nb, double *__restrict__ out) {
+    __shared__ double sh[RED_THREADS / WAVE];
+    double a = 0.0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+        double v = partial[(size_t)b * m];
+        a = (v > a || v != v) ? v : a;
+    }
+    double r = block_max(a, sh);
+    if (threadIdx.x == 0) out[0] = r;
+}
+
+template <int KC>
+__global__ void __launch_bounds__(RED_THREADS) k_update_norm(const double *__restrict__ V, int64_t ldv, int k,
+                                                             const double *__restrict__ h, double *__restrict__ w,
+                                                             int64_t n, double *__restrict__ partial) {
+    __shared__ double sh[RED_THREADS / WAVE];
+    __shared__ double hs[KMAX];
+    for (int i = threadIdx.x; i < k; i += blockDim.x) hs[i] = h[i];
+    __syncthreads();
+    double acc = 0.0;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x) {
+        double wc = w[c];
+#pragma unroll
+        for (int i = 0; i < KC; i++)
+            if (i < k) wc -= hs[i] * V[(size_t)i * ldv + c];
+        w[c] = wc;
+        acc += wc * wc;
+    }
+    double r = block_sum(acc, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = r;
+}
+
+__global__ void k_dot(const double *__restrict__ x, const double *__restrict__ y, int64_t n,
+                      double *__restrict__ partial) {
+    __shared__ double sh[RED_THREADS / WAVE];
+    double acc = 0.0;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x)
+        acc += x[c] * y[c];
+    double r = block_sum(acc, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = r;
+}
+
+// partial[b*3 + 0] = max |x|, +1 = sum x, +2 = sum x^2
+__global__ void k_norms(const double *__restrict__ x, int64_t n, double *__restrict__ partial) {
+    __shared__ double sh[RED_THREADS / WAVE];
+    double mx = 0.0, s = 0.0, s2 = 0.0;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x) {
+        double v = x[c];
+        double a = fabs(v);
+        mx = (a > mx || a != a) ? a : mx;
+        s += v;
+        s2 += v * v;
+    }
+    double r0 = block_max(mx, sh);
+    double r1 = block_sum(s, sh);
+    double r2 = block_sum(s2, sh);
+    if (threadIdx.x == 0) {
+        partial[(size_t)blockIdx.x * 3 + 0] = r0;
+        partial[(size_t)blockIdx.x * 3 + 1] = r1;
+        partial[(size_t)blockIdx.x * 3 + 2] = r2;
+    }
+}
+
+__global__ void k_rel_length(const double *__restrict__ d, const double *__restrict__ u, int64_t n,
+                             double *__restrict__ partial) {
+    __shared__ double sh[RED_THREADS / WAVE];
+    double mx = 0.0;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x) {
+        double a = fabs(u[c]);
+        double r = fabs(d[c]) / (a > 1.0 ? a : 1.0);
+        mx = (r > mx || r != r) ? r : mx;
+    }
+    double r0 = block_max(mx, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = r0;
+}
+
+__global__ void k_scale(double *__restrict__ x, double a, int64_t n) {
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < n) x[c] *= a;
+}
+
+__global__ void k_scale_dev(double *__restrict__ x, const double *__restrict__ s, int64_t n) {
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < n) x[c] /= s[0];
+}
+
+__global__ void k_axpby(double a, const double *__restrict__ x, double b, double *__restrict__ y, int64_t n) {
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < n) y[c] = a * x[c] + b * y[c];
+}
+
+__global__ void k_xpay_to(const double *__restrict__ x, double a, const double *__restrict__ y,
+                          double *__restrict__ z, int64_t n) {
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < n) z[c] = x[c] + a * y[c];
+}
+
+template <class TX>
+__global__ void k_add_to(double *__restrict__ y, const TX *__restrict__ x, int64_t n) {
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < n) y[c] += (double)x[c];
+}
+
+__global__ void k_lincomb(const double *__restrict__ V, int64_t ldv, int k, const double *__restrict__ cf,
+                          double *__restrict__ y, int64_t n) {
+    __shared__ double cs[KMAX];
+    for (int i = threadIdx.x; i < k; i += blockDim.x) cs[i] = cf[i];
+    __syncthreads();
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    double s = 0.0;
+    for (int i = 0; i < k; i++) s += cs[i] * V[(size_t)i * ldv + c];
+    y[c] = s;
+}
+
+__global__ void k_b_minus(const double *__restrict__ b, double *__restrict__ y, int64_t n) {
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < n) y[c] = b[c] - y[c];
+}
+
+__global__ void k_negate_to(const double *__restrict__ x, double *__restrict__ y, int64_t n) {
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < n) y[c] = -x[c];
+}
+
+template <class TA, class TB>
+__global__ void k_cast(const TA *__restrict__ a, TB *__restrict__ b, int64_t n) {
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < n) b[c] = (TB)a[c];
+}
+
+__global__ void k_fill_i32(int32_t *x, int32_t v, int64_t n) {
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < n) x[c] = v;
+}
+
+__global__ void k_fill_f64(double *x, double v, int64_t n) {
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < n) x[c] = v;
+}
+
+// ---- exclusive scan (3 phases: block sums, scan of block sums, add) ----
+constexpr int SCAN_TPB = 256;
+constexpr int SCAN_PER_THREAD = 8;
+constexpr int SCAN_CHUNK = SCAN_TPB * SCAN_PER_THREAD;
+
+__device__ inline int64_t block_scan_excl(int64_t v, int64_t *sh, int64_t *total) {
+    // Hillis-Steele in LDS (SCAN_TPB entries)
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 1; o < SCAN_TPB; o <<= 1) {
+        int64_t t = threadIdx.x >= (unsigned)o ? sh[threadIdx.x - o] : 0;
+        __syncthreads();
+        sh[threadIdx.x] += t;
+        __syncthreads();
+    }
+    int64_t incl = sh[threadIdx.x];
+    *total = sh[SCAN_TPB - 1];
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ void k_scan_blocksums(const int64_t *__restrict__ in, int64_t n, int64_t *__restrict__ bsum) {
+    __shared__ int64_t sh[SCAN_TPB];
+    int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK + (int64_t)threadIdx.x * SCAN_PER_THREAD;
+    int64_t s = 0;
+    for (int t = 0; t < SCAN_PER_THREAD; t++)
+        if (base + t < n) s += in[base + t];
+    int64_t tot;
+    (void)block_scan_excl(s, sh, &tot);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+__global__ void k_scan_top(int64_t *__restrict__ bsum, int64_t nb) {
+    // single block: exclusive scan of nb block sums, in place
+    __shared__ int64_t sh[SCAN_TPB];
+    int64_t carry = 0;
+    for (int64_t base = 0; base < nb; base += SCAN_TPB) {
+        int64_t i = base + threadIdx.x;
+        int64_t v = i < nb ? bsum[i] : 0;
+        int64_t tot;
+        int64_t ex = block_scan_excl(v, sh, &tot);
+        if (i < nb) bsum[i] = carry + ex;
+        carry += tot;
+        __syncthreads();
+    }
+}
+
+__global__ void k_scan_final(const int64_t *__restrict__ in, int64_t n, const int64_t *__restrict__ boff,
+                             int64_t *__restrict__ out) {
+    __shared__ int64_t sh[SCAN_TPB];
+    int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK + (int64_t)threadIdx.x * SCAN_PER_THREAD;
+    int64_t vals[SCAN_PER_THREAD];
+    int64_t s = 0;
+    for (int t = 0; t < SCAN_PER_THREAD; t++) {
+        vals[t] = (base + t < n) ? in[base + t] : 0;
+        s += vals[t];
+    }
+    int64_t tot;
+    int64_t ex = block_scan_excl(s, sh, &tot);
+    int64_t run = boff[blockIdx.x] + ex;
+    for (int t = 0; t < SCAN_PER_THREAD; t++) {
+        if (base + t < n) out[base + t] = run;
+        run += vals[t];
+    }
+    if (base + SCAN_PER_THREAD >= n && base < n) out[n] = run;  // the thread holding the last element
+}
+
+}  // namespace
+
+rich_status launch_multidot(const double *V, int64_t ldv, int k, const double *w, int64_t n, double *partial,
+                            double *out, hipStream_t s) {
+    // the template width bounds the register count: 8, 16, 32 or 64 sums
+    if (k <= 8) k_multidot<8><<<RED_BLOCKS, RED_THREADS, 0, s>>>(V, ldv, k, w, n, partial);
+    else if (k <= 16) k_multidot<16><<<RED_BLOCKS, RED_THREADS, 0, s>>>(V, ldv, k, w, n, partial);
+    else if (k <= 32) k_multidot<32><<<RED_BLOCKS, RED_THREADS, 0, s>>>(V, ldv, k, w, n, partial);
+    else k_multidot<64><<<RED_BLOCKS, RED_THREADS, 0, s>>>(V, ldv, k, w, n, partial);
+    LAUNCH_CHECK();
+    k_reduce_partials<<<k + 1, RED_THREADS, 0, s>>>(partial, k + 1, RED_BLOCKS, out);
+    LAUNCH_CHECK();
+    return RICH_OK;
+}
+
+rich_status launch_update_norm(const double *V, int64_t ldv, int k, const double *h, double *w, int64_t n,
+                               double *partial, double *out, hipStream_t s) {
+    if (k <= 8) k_update_norm<8><<<RED_BLOCKS, RED_THREADS, 0, s>>>(V, ldv, k, h, w, n, partial);
+    else if (k <= 16) k_update_norm<16><<<RED_BLOCKS, RED_THREADS, 0, s>>>(V, ldv, k, h, w, n, partial);
+    else if (k <= 32) k_update_norm<32><<<RED_BLOCKS, RED_THREADS, 0, s>>>(V, ldv, k, h, w, n, partial);
+    else k_update_norm<64><<<RED_BLOCKS, RED_THREADS, 0, s>>>(V, ldv, k, h, w, n, partial);
+    LAUNCH_CHECK();
+    k_reduce_partials<<<1, RED_THREADS, 0, s>>>(partial, 1, RED_BLOCKS, out);
+    LAUNCH_CHECK();
+    return RICH_OK;
+}
+
+rich_status launch_dot(const double *x, const double *y, int64_t n, double *partial, double *out, hipStream_t s) {
+    k_dot<<<RED_BLOCKS, RED_THREADS, 0, s>>>(x, y, n, partial);
+    LAUNCH_CHECK();
+    k_reduce_partials<<<1, RED_THREADS, 0, s>>>(partial, 1, RED_BLOCKS, out);
+    LAUNCH_CHECK();
+    return RICH_OK;
+}
+
+rich_status launch_norms(const double *x, int64_t n, double *partial, double *out, hipStream_t s) {
+    k_norms<<<RED_BLOCKS, RED_THREADS, 0, s>>>(x, n, partial);
+    LAUNCH_CHECK();
+    k_reduce_max<<<1, RED_THREADS, 0, s>>>(partial, 3, RED_BLOCKS, out);
+    LAUNCH_CHECK();
+    k_reduce_partials<<<2, RED_THREADS, 0, s>>>(partial + 1, 3, RED_BLOCKS, out + 1);
+    LAUNCH_CHECK();
+    return RICH_OK;
+}
+
+rich_status launch_rel_length(const double *d, const double *u, int64_t n, double *partial, double *out,
+                              hipStream_t s) {
+    k_rel_length<<<RED_BLOCKS, RED_THREADS, 0, s>>>(d, u, n, partial);
+    LAUNCH_CHECK();
+    k_reduce_max<<<1, RED_THREADS, 0, s>>>(partial, 1, RED_BLOCKS, out);
+    LAUNCH_CHECK();
+    return RICH_OK;
+}
+
+rich_status launch_scale(double *x, double a, int64_t n, hipStream_t s) {
+    k_scale<<<nblocks(n), TPB, 0, s>>>(x, a, n);
+    LAUNCH_CHECK();
+    return RICH_OK;
+}
+
+rich_status launch_scale_dev(double *x, const double *inv_of, int64_t n, hipStream_t s) {
+    k_scale_dev<<<nblocks(n), TPB, 0, s>>>(x, inv_of, n);
+    LAUNCH_CHECK();
+    return RICH_OK;
+}
+
+rich_status launch_axpby(double a, const double *x, double b, double *y, int64_t n, hipStream_t s) {
+    k_axpby<<<nblocks(n), TPB, 0, s>>>(a, x, b, y, n);
+    LAUNCH_CHECK();
+    return RICH_OK;
+}
+
+rich_status launch_xpay_to(const double *x, double a, const double *y, double *z, int64_t n, hipStream_t s) {
+    k_xpay_to<<<nblocks(n), TPB, 0, s>>>(x, a, y, z, n);
+    LAUNCH_CHECK();
+    return RICH_OK;
+}
+
+template <class TX>
+rich_status launch_add_to(double *y, const TX *x, int64_t n, hipStream_t s) {
+    k_add_to<TX><<<nblocks(n), TPB, 0, s>>>(y, x, n);
+    LAUNCH_CHECK();
+    return RICH_OK;
+}
+template rich_status launch_add_to<double>(double *, const double *, int64_t, hipStream_t);
+template rich_status launch_add_to<float>(double *, const float *, int64_t, hipStream_t);
+
+rich_status launch_lincomb(const double *V, int64_t ldv, int k, const double *c, double *y, int64_t n,
+                           hipStream_t s) {
+    k_lincomb<<<nblocks(n), TPB, 0, s>>>(V, ldv, k, c, y, n);
+    LAUNCH_CHECK();
+    return RICH_OK;
+}
+
+rich_status launch_b_minus(const double *b, double *y, int64_t n, hipStream_t s) {
+    k_b_minus<<<nblocks(n), TPB, 0, s>>>(b, y, n);
+    LAUNCH_CHECK();
+    return RICH_OK;
+}
+
+rich_status launch_negate_to(const double *x, double *y, int64_t n, hipStream_t s) {
+    k_negate_to<<<nblocks(n), TPB, 0, s>>>(x, y, n);
+    LAUNCH_CHECK();
+    return RICH_OK;
+}
+
+template <class TA, class TB>
+rich_status launch_cast(const TA *a, TB *b, int64_t n, hipStream_t s) {
+    k_cast<TA, TB><<<nblocks(n), TPB, 0, s>>>(a, b, n);
+    LAUNCH_CHECK();
+    return RICH_OK;
+}
+template rich_status launch_cast<double, float>(const double *, float *, int64_t, hipStream_t);
+template rich_status launch_cast<float, double>(const float *, double *, int64_t, hipStream_t);
+template rich_status launch_cast<double, double>(const double *, double *, int64_t, hipStream_t);
+template rich_status launch_cast<float, float>(const float *, float *, int64_t, hipStream_t);
+
+rich_status launch_fill_i32(int32_t *x, int32_t v, int64_t n, hipStream_t s) {
+    if (n == 0) return RICH_OK;
+    k_fill_i32<<<nblocks(n), TPB, 0, s>>>(x, v, n);
+    LAUNCH_CHECK();
+    return RICH_OK;
+}
+
+rich_status launch_fill_f64(double *x, double v, int64_t n, hipStream_t s) {
+    if (n == 0) return RICH_OK;
+    k_fill_f64<<<nblocks(n), TPB, 0, s>>>(x, v, n);
+    LAUNCH_CHECK();
+    return RICH_OK;
+}
+
+int64_t scan_tmp_size(int64_t n) { return (n + SCAN_CHUNK - 1) / SCAN_CHUNK + 1; }
+
+rich_status scan_exclusive_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *tmp, hipStream_t s) {
+    if (n == 0) {
+        HIP_TRY(hipMemsetAsync(out, 0, sizeof(int64_t), s));
+        return RICH_OK;
+    }
+    int64_t nb = (n + SCAN_CHUNK - 1) / SCAN_CHUNK;
+    k_scan_blocksums<<<(unsigned)nb, SCAN_TPB, 0, s>>>(in, n, tmp);
+    LAUNCH_CHECK();
+    k_scan_top<<<1, SCAN_TPB, 0, s>>>(tmp, nb);
+    LAUNCH_CHECK();
+    k_scan_final<<<(unsigned)nb, SCAN_TPB, 0, s>>>(in, n, tmp, out);
+    LAUNCH_CHECK();
+    return RICH_OK;
+}
+
+}  // namespace rich

@@ -1,0 +1,1000 @@
+// Host control of the solver and the C-ABI entry points: the backward-Euler
+// time loop, the modified inexact Newton method with line search (Section
+// 3), restarted right-preconditioned GMRES (eq. (precsystem)), the AMG
+// V-cycle driver and hierarchy set-up (Section 5.2).  Every vector operation
+// runs on the GPU; the host only reads back the few scalars each decision
+// needs.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+
+#include "common.hpp"
+
+namespace rich {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char *what, const char *file, int line, hipError_t e) {
+    snprintf(g_err, sizeof(g_err), "%s failed at %s:%d: %s", what, file, line, hipGetErrorString(e));
+}
+const char *last_error() { return g_err; }
+
+static double now_s() {
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace rich
+
+using namespace rich;
+
+struct rich_ctx {
+    Phys P;
+    rich_solver_opts_t O;
+    int64_t N = 0;
+    hipStream_t s = nullptr;
+    bool mixed = false;
+    DevAlloc mem;
+    // fields
+    double *Ks = nullptr, *p = nullptr, *theta_old = nullptr;
+    double *u = nullptr, *F = nullptr, *ut = nullptr, *Ft = nullptr, *d = nullptr, *Jd = nullptr;
+    double *ub = nullptr, *Fb = nullptr, *rhs = nullptr, *work = nullptr;
+    // fine matrices
+    double *J7 = nullptr, *M4 = nullptr, *invd0 = nullptr;
+    float *M4f = nullptr, *invd0f = nullptr;
+    // GMRES
+    int m = 0;
+    double *V = nullptr;       // (m+1) x N
+    void *z = nullptr;         // N, V-cycle output (FP32 or FP64)
+    void *ztmp = nullptr;      // N, sweep scratch for a one-level hierarchy
+    double *partial = nullptr; // RED_BLOCKS * (m + 2)
+    double *dres = nullptr;    // device scalars (m + 8)
+    double *dres2 = nullptr;
+    double *hres = nullptr;    // pinned host mirror (2 * (m + 8))
+    // AMG
+    Hierarchy *H = nullptr;
+    bool have_J = false;
+    int since_build = 0;
+    // stats of the step in progress
+    rich_step_stats_t *cur = nullptr;
+    ~rich_ctx() {
+        delete H;
+        if (hres) (void)hipHostFree(hres);
+    }
+};
+
+namespace {
+
+rich_status sync(rich_ctx *h) {
+    HIP_TRY(hipStreamSynchronize(h->s));
+    return RICH_OK;
+}
+
+// read n device doubles into the pinned mirror
+rich_status readback(rich_ctx *h, const double *dev, int n, double *out) {
+    HIP_TRY(hipMemcpyAsync(h->hres, dev, n * sizeof(double), hipMemcpyDeviceToHost, h->s));
+    HIP_TRY(hipStreamSynchronize(h->s));
+    memcpy(out, h->hres, n * sizeof(double));
+    return RICH_OK;
+}
+
+// ||x||_inf, sum x, ||x||_2^2
+rich_status norms(rich_ctx *h, const double *x, double out[3]) {
+    RICH_TRY(launch_norms(x, h->N, h->partial, h->dres, h->s));
+    return readback(h, h->dres, 3, out);
+}
+
+rich_status dotp(rich_ctx *h, const double *x, const double *y, double *out) {
+    RICH_TRY(launch_dot(x, y, h->N, h->partial, h->dres, h->s));
+    return readback(h, h->dres, 1, out);
+}
+
+// ------------------------------------------------------------- hierarchy
+rich_status build_hierarchy(rich_ctx *h) {
+    delete h->H;
+    h->H = new Hierarchy();
+    Hierarchy &H = *h->H;
+    hipStream_t s = h->s;
+    const Phys &P = h->P;
+    int64_t N = h->N;
+    DevAlloc tmp;  // level-0 CSR and intermediate matrices
+    // level-0 CSR of M (set-up only)
+    CsrDev A0;
+    A0.n = N;
+    int64_t *cnt, *stmp;
+    RICH_TRY(tmp.get(&cnt, N));
+    RICH_TRY(tmp.get(&stmp, scan_tmp_size(N)));
+    RICH_TRY(tmp.get(&A0.rowptr, N + 1));
+    RICH_TRY(launch_stencil_rowcounts(P, cnt, s));
+    RICH_TRY(scan_exclusive_i64(cnt, A0.rowptr, N, stmp, s));
+    HIP_TRY(hipMemcpyAsync(&A0.nnz, A0.rowptr + N, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    RICH_TRY(sync(h));
+    RICH_TRY(tmp.get(&A0.col, A0.nnz));
+    RICH_TRY(tmp.get(&A0.val, A0.nnz));
+    RICH_TRY(launch_stencil_to_csr(P, h->M4, A0.rowptr, A0.col, A0.val, s));
+
+    H.L[0].n = N;
+    H.L[0].nnz = A0.nnz;
+    H.nnz_total = A0.nnz;
+    CsrDev levA = A0;
+    int l = 0;
+    int maxl = h->O.amg_max_levels < 16 ? h->O.amg_max_levels : 16;
+    while (l + 1 < maxl && levA.n > h->O.amg_coarse_size) {
+        CsrDev cur = levA;
+        bool own = false;
+        DevAlloc *cur_mem = nullptr;
+        int32_t *comp;
+        RICH_TRY(H.mem.get(&comp, levA.n));
+        RICH_TRY(compose_agg(comp, nullptr, levA.n, s));
+        for (int sw = 0; sw < h->O.amg_sweeps; sw++) {
+            DevAlloc *am = new DevAlloc();
+            int32_t *a;
+            rich_status st = am->get(&a, cur.n);
+            int64_t nc = 0;
+            if (st == RICH_OK) st = match_sweep(cur.n, cur.rowptr, cur.col, cur.val, a, &nc, s);
+            if (st != RICH_OK) {
+                delete am;
+                delete cur_mem;
+                return st;
+            }
+            if (nc == cur.n) {
+                delete am;
+                break;
+            }
+            DevAlloc *nm = new DevAlloc();
+            CsrDev nxt;
+            st = galerkin(cur, a, nc, &nxt, *nm, s);
+            if (st == RICH_OK) st = compose_agg(comp, a, levA.n, s);
+            if (st == RICH_OK) st = sync(h);
+            delete am;
+            if (st != RICH_OK) {
+                delete nm;
+                delete cur_mem;
+                return st;
+            }
+            delete cur_mem;  // previous intermediate
+            cur_mem = nm;
+            cur = nxt;
+            own = true;
+        }
+        if (!own) {
+            H.mem.release(comp);
+            break;
+        }
+        Level &Lf = H.L[l];
+        Lf.agg = comp;
+        RICH_TRY(H.mem.get(&Lf.mptr, cur.n + 1));
+        RICH_TRY(H.mem.get(&Lf.mem, levA.n));
+        RICH_TRY(members(comp, levA.n, cur.n, Lf.mptr, Lf.mem, s));
+        // keep the coarse matrix in the hierarchy's own memory
+        Level &Lc = H.L[l + 1];
+        Lc.n = cur.n;
+        Lc.nnz = cur.nnz;
+        RICH_TRY(H.mem.get(&Lc.rowptr, cur.n + 1));
+        RICH_TRY(H.mem.get(&Lc.col, cur.nnz));
+        RICH_TRY(H.mem.get(&Lc.val, cur.nnz));
+        HIP_TRY(hipMemcpyAsync(Lc.rowptr, cur.rowptr, (cur.n + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(Lc.col, cur.col, cur.nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(Lc.val, cur.val, cur.nnz * sizeof(double), hipMemcpyDeviceToDevice, s));
+        RICH_TRY(sync(h));
+        delete cur_mem;
+        H.nnz_total += cur.nnz;
+        levA.n = Lc.n;
+        levA.nnz = Lc.nnz;
+        levA.rowptr = Lc.rowptr;
+        levA.col = Lc.col;
+        levA.val = Lc.val;
+        l++;
+    }
+    H.nlev = l + 1;
+    // smoother data, FP32 copies, work vectors
+    size_t esz = h->mixed ? sizeof(float) : sizeof(double);
+    for (int t = 0; t < H.nlev; t++) {
+        Level &Lv = H.L[t];
+        if (t > 0) {
+            CsrDev A{Lv.n, Lv.nnz, Lv.rowptr, Lv.col, Lv.val};
+            RICH_TRY(H.mem.get(&Lv.invd, Lv.n));
+            if (h->mixed) {
+                RICH_TRY(H.mem.get(&Lv.invdf, Lv.n));
+                RICH_TRY(H.mem.get(&Lv.valf, Lv.nnz));
+                RICH_TRY(launch_cast(Lv.val, Lv.valf, Lv.nnz, s));
+            }
+            RICH_TRY(csr_invd(A, Lv.invd, Lv.invdf, s));
+        }
+        char *b, *x, *r;
+        RICH_TRY(H.mem.get(&b, Lv.n * esz));
+        RICH_TRY(H.mem.get(&x, Lv.n * esz));
+        RICH_TRY(H.mem.get(&r, Lv.n * esz));
+        Lv.b = b;
+        Lv.x = x;
+        Lv.r = r;
+    }
+    // coarsest solver
+    Level &Lc = H.L[H.nlev - 1];
+    H.dense = Lc.n <= h->O.coarse_dense_max;
+    if (H.dense) {
+        RICH_TRY(H.mem.get(&H.cinv, Lc.n * Lc.n));
+        CsrDev A = (H.nlev == 1) ? A0 : CsrDev{Lc.n, Lc.nnz, Lc.rowptr, Lc.col, Lc.val};
+        RICH_TRY(dense_inverse(A, H.cinv, s));
+        if (h->mixed) {
+            RICH_TRY(H.mem.get(&H.cinvf, Lc.n * Lc.n));
+            RICH_TRY(launch_cast(H.cinv, H.cinvf, Lc.n * Lc.n, s));
+        }
+    }
+    RICH_TRY(sync(h));
+    return RICH_OK;
+}
+
+// refresh what depends on the fine matrix when the hierarchy is a single level
+rich_status refresh_single_level(rich_ctx *h) {
+    Hierarchy &H = *h->H;
+    if (H.nlev != 1 || !H.dense) return RICH_OK;
+    DevAlloc tmp;
+    CsrDev A0;
+    A0.n = h->N;
+    int64_t *cnt, *stmp;
+    RICH_TRY(tmp.get(&cnt, h->N));
+    RICH_TRY(tmp.get(&stmp, scan_tmp_size(h->N)));
+    RICH_TRY(tmp.get(&A0.rowptr, h->N + 1));
+    RICH_TRY(launch_stencil_rowcounts(h->P, cnt, h->s));
+    RICH_TRY(scan_exclusive_i64(cnt, A0.rowptr, h->N, stmp, h->s));
+    HIP_TRY(hipMemcpyAsync(&A0.nnz, A0.rowptr + h->N, sizeof(int64_t), hipMemcpyDeviceToHost, h->s));
+    RICH_TRY(sync(h));
+    RICH_TRY(tmp.get(&A0.col, A0.nnz));
+    RICH_TRY(tmp.get(&A0.val, A0.nnz));
+    RICH_TRY(launch_stencil_to_csr(h->P, h->M4, A0.rowptr, A0.col, A0.val, h->s));
+    RICH_TRY(dense_inverse(A0, H.cinv, h->s));
+    if (h->mixed) RICH_TRY(launch_cast(H.cinv, H.cinvf, h->N * h->N, h->s));
+    return sync(h);
+}
+
+// ---------------------------------------------------------------- V-cycle
+template <class T>
+const T *lvval(const Level &L);
+template <>
+const double *lvval<double>(const Level &L) { return L.val; }
+template <>
+const float *lvval<float>(const Level &L) { return L.valf; }
+template <class T>
+const T *lvinvd(const Level &L);
+template <>
+const double *lvinvd<double>(const Level &L) { return L.invd; }
+template <>
+const float *lvinvd<float>(const Level &L) { return L.invdf; }
+
+// z = V-cycle(b): one l1-Jacobi sweep before and after each coarse
+// correction, the pre-sweep from zero (Section 5.2, symmetric V-cycle).
+template <class T>
+rich_status vcycle(rich_ctx *h, const double *b, T *z) {
+    Hierarchy &H = *h->H;
+    hipStream_t s = h->s;
+    const T *M4 = h->mixed ? (const T *)(const void *)h->M4f : (const T *)(const void *)h->M4;
+    const T *invd0 = h->mixed ? (const T *)(const void *)h->invd0f : (const T *)(const void *)h->invd0;
+    const T *cinv = h->mixed ? (const T *)(const void *)H.cinvf : (const T *)(const void *)H.cinv;
+    if (H.nlev == 1) {
+        if (H.dense) return launch_dense_gemv<double, T>(cinv, b, z, h->N, s);
+        return launch_st_sweeps<double, T>(h->P, M4, invd0, b, z, (T *)h->ztmp, h->O.coarse_l1_sweeps, s);
+    }
+    // down
+    RICH_TRY(launch_st_pre<double, T>(h->P, M4, invd0, b, (T *)H.L[0].r, s));
+    RICH_TRY(launch_restrict<T>(H.L[0], (const T *)H.L[0].r, (T *)H.L[1].b, H.L[1].n, s));
+    for (int l = 1; l < H.nlev - 1; l++) {
+        Level &Lv = H.L[l];
+        RICH_TRY(launch_csr_pre<T, T>(Lv, lvval<T>(Lv), lvinvd<T>(Lv), (const T *)Lv.b, (T *)Lv.r, s));
+        RICH_TRY(launch_restrict<T>(Lv, (const T *)Lv.r, (T *)H.L[l + 1].b, H.L[l + 1].n, s));
+    }
+    // coarsest
+    Level &Lc = H.L[H.nlev - 1];
+    if (H.dense) {
+        RICH_TRY(launch_dense_gemv<T, T>(cinv, (const T *)Lc.b, (T *)Lc.x, Lc.n, s));
+    } else {
+        RICH_TRY(launch_csr_sweeps<T, T>(Lc, lvval<T>(Lc), lvinvd<T>(Lc), (const T *)Lc.b, (T *)Lc.x, (T *)Lc.r,
+                                         h->O.coarse_l1_sweeps, s));
+    }
+    // up
+    for (int l = H.nlev - 2; l >= 1; l--) {
+        Level &Lv = H.L[l];
+        RICH_TRY(launch_csr_post<T, T>(Lv, lvval<T>(Lv), lvinvd<T>(Lv), (const T *)Lv.b, (const T *)H.L[l + 1].x,
+                                       (T *)Lv.x, s));
+    }
+    return launch_st_post<double, T>(h->P, M4, invd0, b, (const T *)H.L[1].x, H.L[0].agg, z, s);
+}
+
+rich_status apply_prec(rich_ctx *h, const double *b) {
+    if (h->mixed) return vcycle<float>(h, b, (float *)h->z);
+    return vcycle<double>(h, b, (double *)h->z);
+}
+
+rich_status spmv_J_z(rich_ctx *h, double *y) {
+    if (h->mixed) return launch_spmv_J<float>(h->P, h->J7, (const float *)h->z, y, h->s);
+    return launch_spmv_J<double>(h->P, h->J7, (const double *)h->z, y, h->s);
+}
+
+rich_status add_z(rich_ctx *h, double *x) {
+    if (h->mixed) return launch_add_to<float>(x, (const float *)h->z, h->N, h->s);
+    return launch_add_to<double>(x, (const double *)h->z, h->N, h->s);
+}
+
+// ------------------------------------------------------------------ GMRES
+// Right-preconditioned restarted GMRES(m) on J M^{-1}: classical Gram-Schmidt
+// with a second pass when the norm drops below 0.7 of its value (Daniel-
+// Gragg-Kaufman-Stewart criterion), Givens rotations on the host,
+// x += M^{-1} V y at the end of each cycle, true residual at every restart.
+// Stops at ||b - J x||_2 <= eta ||b||_2 or after maxit Arnoldi steps.
+rich_status gmres(rich_ctx *h, const double *b, double *x, int *its_out, double *relres_out, bool *conv_out) {
+    int64_t N = h->N;
+    int m = h->m;
+    hipStream_t s = h->s;
+    double eta = h->O.eta;
+    std::vector<double> Hm((m + 1) * m), cs(m), sn(m), g(m + 1), y(m), hv(m + 8);
+    double nb[3];
+    RICH_TRY(norms(h, b, nb));
+    double bnorm = std::sqrt(nb[2]);
+    RICH_TRY(launch_fill_f64(x, 0.0, N, s));
+    int total = 0;
+    bool conv = false;
+    double relres = 0.0;
+    if (bnorm == 0.0) {
+        *its_out = 0;
+        *relres_out = 0.0;
+        *conv_out = true;
+        return RICH_OK;
+    }
+    if (!std::isfinite(bnorm)) return RICH_NONFINITE;
+    bool first = true;
+    for (;;) {
+        // true residual into V_0
+        if (first) {
+            HIP_TRY(hipMemcpyAsync(h->V, b, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+        } else {
+            RICH_TRY(launch_spmv_J<double>(h->P, h->J7, x, h->V, s));
+            RICH_TRY(launch_b_minus(b, h->V, N, s));
+        }
+        first = false;
+        double rn[3];
+        RICH_TRY(norms(h, h->V, rn));
+        double beta = std::sqrt(rn[2]);
+        if (!std::isfinite(beta)) return RICH_NONFINITE;
+        relres = beta / bnorm;
+        if (beta <= eta * bnorm) {
+            conv = true;
+            break;
+        }
+        if (total >= h->O.gmres_maxit) break;
+        RICH_TRY(launch_scale(h->V, 1.0 / beta, N, s));
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int k = 0;
+        for (int j = 0; j < m && total < h->O.gmres_maxit; j++) {
+            double *vj = h->V + (size_t)j * N;
+            double *w = h->V + (size_t)(j + 1) * N;
+            RICH_TRY(apply_prec(h, vj));
+            RICH_TRY(spmv_J_z(h, w));
+            RICH_TRY(launch_multidot(h->V, N, j + 1, w, N, h->partial, h->dres, s));
+            RICH_TRY(launch_update_norm(h->V, N, j + 1, h->dres, w, N, h->partial, h->dres2, s));
+            HIP_TRY(hipMemcpyAsync(h->hres, h->dres, (j + 2) * sizeof(double), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipMemcpyAsync(h->hres + (m + 8), h->dres2, sizeof(double), hipMemcpyDeviceToHost, s));
+            RICH_TRY(sync(h));
+            for (int i = 0; i <= j; i++) hv[i] = h->hres[i];
+            double ww0 = h->hres[j + 1];
+            double ww1 = h->hres[m + 8];
+            if (std::sqrt(ww1) < 0.7 * std::sqrt(ww0)) {
+                // second Gram-Schmidt pass
+                RICH_TRY(launch_multidot(h->V, N, j + 1, w, N, h->partial, h->dres, s));
+                RICH_TRY(launch_update_norm(h->V, N, j + 1, h->dres, w, N, h->partial, h->dres2, s));
+                HIP_TRY(hipMemcpyAsync(h->hres, h->dres, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+                HIP_TRY(hipMemcpyAsync(h->hres + (m + 8), h->dres2, sizeof(double), hipMemcpyDeviceToHost, s));
+                RICH_TRY(sync(h));
+                for (int i = 0; i <= j; i++) hv[i] += h->hres[i];
+                ww1 = h->hres[m + 8];
+            }
+            double hn = std::sqrt(ww1);
+            if (!std::isfinite(hn)) return RICH_NONFINITE;
+            for (int i = 0; i <= j; i++) Hm[i * m + j] = hv[i];
+            Hm[(j + 1) * m + j] = hn;
+            if (hn > 0.0) RICH_TRY(launch_scale(w, 1.0 / hn, N, s));
+            for (int i = 0; i < j; i++) {
+                double a = Hm[i * m + j], c = Hm[(i + 1) * m + j];
+                Hm[i * m + j] = cs[i] * a + sn[i] * c;
+                Hm[(i + 1) * m + j] = -sn[i] * a + cs[i] * c;
+            }
+            double a = Hm[j * m + j], c = Hm[(j + 1) * m + j];
+            double rho = std::sqrt(a * a + c * c);
+            cs[j] = a / rho;
+            sn[j] = c / rho;
+            Hm[j * m + j] = rho;
+            Hm[(j + 1) * m + j] = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            total++;
+            k = j + 1;
+            if (std::fabs(g[j + 1]) <= eta * bnorm || hn == 0.0) break;
+        }
+        for (int i = k - 1; i >= 0; i--) {
+            double sum = g[i];
+            for (int t = i + 1; t < k; t++) sum -= Hm[i * m + t] * y[t];
+            y[i] = sum / Hm[i * m + i];
+        }
+        memcpy(h->hres, y.data(), k * sizeof(double));
+        HIP_TRY(hipMemcpyAsync(h->dres, h->hres, k * sizeof(double), hipMemcpyHostToDevice, s));
+        RICH_TRY(launch_lincomb(h->V, N, k, h->dres, h->work, N, s));
+        RICH_TRY(apply_prec(h, h->work));
+        RICH_TRY(add_z(h, x));
+        RICH_TRY(sync(h));  // hres is reused before the next read
+    }
+    *its_out = total;
+    *relres_out = relres;
+    *conv_out = conv;
+    return RICH_OK;
+}
+
+// ----------------------------------------------------------------- Newton
+rich_status feval(rich_ctx *h, const double *u, double *F) {
+    double t0 = now_s();
+    RICH_TRY(launch_residual(h->P, h->Ks, u, h->theta_old, F, h->s));
+    if (h->cur) {
+        RICH_TRY(sync(h));
+        h->cur->t_feval += now_s() - t0;
+    }
+    return RICH_OK;
+}
+
+rich_status rebuild(rich_ctx *h, const double *u) {
+    double t0 = now_s();
+    RICH_TRY(launch_assemble(h->P, h->Ks, u, h->J7, h->M4, h->mixed ? h->M4f : nullptr, h->invd0,
+                             h->mixed ? h->invd0f : nullptr, h->s));
+    RICH_TRY(sync(h));
+    double t1 = now_s();
+    if (h->cur) {
+        h->cur->t_jac += t1 - t0;
+        h->cur->jac_builds++;
+    }
+    if (!h->H) {
+        RICH_TRY(build_hierarchy(h));
+        if (h->cur) h->cur->amg_setups++;
+    } else {
+        RICH_TRY(refresh_single_level(h));
+    }
+    if (h->cur) h->cur->t_setup += now_s() - t1;
+    h->have_J = true;
+    h->since_build = 0;
+    return RICH_OK;
+}
+
+// f = 0.5 ||F||^2 and ||F||_inf
+rich_status fnorms(rich_ctx *h, const double *F, double *f_half, double *finf) {
+    double n3[3];
+    RICH_TRY(norms(h, F, n3));
+    *f_half = 0.5 * n3[2];
+    *finf = n3[0];
+    return RICH_OK;
+}
+
+// Line search of Section 3 (Armijo-Goldstein), backtracking as in Dennis &
+// Schnabel's Algorithm A6.3.1: quadratic then cubic model minimisers clamped
+// to [0.1, 0.5] of the last step; the beta condition lengthens a full step
+// shorter than the maximum step.  On success ut/Ft hold the accepted point.
+rich_status line_search(rich_ctx *h, double slope, double mxstep, bool truncated, double f0, double *lam_out,
+                        int *nback) {
+    int64_t N = h->N;
+    const double alpha = h->O.ls_alpha, beta = 0.9;
+    RICH_TRY(launch_rel_length(h->d, h->u, N, h->partial, h->dres, h->s));
+    double rl;
+    RICH_TRY(readback(h, h->dres, 1, &rl));
+    double lam_min = rl > 0.0 ? h->O.scsteptol / rl : 0.0;
+    double lam = 1.0, lam_prev = 0.0, f_prev = 0.0;
+    bool first = true;
+    *nback = 0;
+    for (;;) {
+        RICH_TRY(launch_xpay_to(h->u, lam, h->d, h->ut, N, h->s));
+        RICH_TRY(feval(h, h->ut, h->Ft));
+        double ft, finf;
+        RICH_TRY(fnorms(h, h->Ft, &ft, &finf));
+        if (std::isfinite(ft) && ft <= f0 + alpha * lam * slope) break;
+        if (lam < lam_min) return RICH_LINESEARCH_FAIL;
+        double lt;
+        if (!std::isfinite(ft)) {
+            lt = 0.1 * lam;
+        } else if (first) {
+            lt = -slope / (2.0 * (ft - f0 - slope));
+            first = false;
+        } else {
+            double t1 = ft - f0 - lam * slope;
+            double t2 = f_prev - f0 - lam_prev * slope;
+            double a = (t1 / (lam * lam) - t2 / (lam_prev * lam_prev)) / (lam - lam_prev);
+            double b = (-lam_prev * t1 / (lam * lam) + lam * t2 / (lam_prev * lam_prev)) / (lam - lam_prev);
+            if (a == 0.0) {
+                lt = -slope / (2.0 * b);
+            } else {
+                double disc = b * b - 3.0 * a * slope;
+                lt = disc < 0.0 ? 0.5 * lam : (-b + std::sqrt(disc)) / (3.0 * a);
+            }
+        }
+        if (std::isfinite(ft)) {
+            lam_prev = lam;
+            f_prev = ft;
+        }
+        if (!(lt <= 0.5 * lam)) lt = 0.5 * lam;
+        if (!(lt >= 0.1 * lam)) lt = 0.1 * lam;
+        lam = lt;
+        (*nback)++;
+    }
+    if (lam == 1.0 && !truncated) {
+        double nd[3];
+        RICH_TRY(norms(h, h->d, nd));
+        double dn = std::sqrt(nd[2]);
+        double ft, finf;
+        RICH_TRY(fnorms(h, h->Ft, &ft, &finf));
+        int tries = 0;
+        while (ft < f0 + beta * lam * slope && 2.0 * lam * dn <= mxstep && tries < 10) {
+            double lt = 2.0 * lam;
+            RICH_TRY(launch_xpay_to(h->u, lt, h->d, h->ub, N, h->s));
+            RICH_TRY(feval(h, h->ub, h->Fb));
+            double fb, fbinf;
+            RICH_TRY(fnorms(h, h->Fb, &fb, &fbinf));
+            if (!(std::isfinite(fb) && fb <= f0 + alpha * lt * slope)) break;
+            lam = lt;
+            ft = fb;
+            std::swap(h->ut, h->ub);
+            std::swap(h->Ft, h->Fb);
+            tries++;
+        }
+    }
+    *lam_out = lam;
+    return RICH_OK;
+}
+
+// One backward-Euler step (Section 2.1) by the modified inexact Newton
+// method of Section 3; the Jacobian re-use rules of eq.
+// (jacobian_update_condition) with the counter persisting across steps.
+struct CurGuard {
+    rich_ctx *h;
+    ~CurGuard() { h->cur = nullptr; }
+};
+
+rich_status newton_step(rich_ctx *h, rich_step_stats_t *st) {
+    int64_t N = h->N;
+    hipStream_t s = h->s;
+    memset(st, 0, sizeof(*st));
+    st->min_lambda = 1.0;
+    h->cur = st;
+    CurGuard guard{h};
+    double t_start = now_s();
+    double pn[3];
+    RICH_TRY(norms(h, h->p, pn));
+    if (!std::isfinite(pn[0])) return st->status = RICH_NONFINITE;
+    RICH_TRY(launch_theta(h->P, h->p, h->theta_old, s));
+    HIP_TRY(hipMemcpyAsync(h->u, h->p, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    RICH_TRY(feval(h, h->u, h->F));
+    double f0, fnorm;
+    RICH_TRY(fnorms(h, h->F, &f0, &fnorm));
+    if (!std::isfinite(fnorm)) return st->status = RICH_NONFINITE;
+    double mxstep = h->O.mxnewtstep;
+    if (!(mxstep > 0.0)) {
+        double un = std::sqrt(pn[2]);
+        mxstep = 1000.0 * (un > 1.0 ? un : 1.0);
+    }
+    double prev_step = 0.0;
+    bool retry = false;
+    rich_status status = RICH_OK;
+    while (fnorm > h->O.fnormtol) {
+        if (st->newton_its >= h->O.max_newton) {
+            status = RICH_MAXITER;
+            break;
+        }
+        bool fresh = false;
+        if (!h->have_J || h->since_build >= h->O.msbset || prev_step > 1.5 || retry) {
+            rich_status rc = rebuild(h, h->u);
+            if (rc != RICH_OK) {
+                status = rc;
+                break;
+            }
+            fresh = true;
+            retry = false;
+        }
+        double t0 = now_s();
+        RICH_TRY(launch_negate_to(h->F, h->rhs, N, s));
+        int its;
+        double relres;
+        bool conv;
+        RICH_TRY(gmres(h, h->rhs, h->d, &its, &relres, &conv));
+        st->gmres_its += its;
+        st->t_linsol += now_s() - t0;
+        if (!conv) {
+            st->linsolve_fails++;
+            if (!fresh) {
+                retry = true;
+                continue;
+            }
+        }
+        bool truncated = false;
+        double dn3[3];
+        RICH_TRY(norms(h, h->d, dn3));
+        double dn = std::sqrt(dn3[2]);
+        if (dn > mxstep) {
+            RICH_TRY(launch_scale(h->d, mxstep / dn, N, s));
+            truncated = true;
+        }
+        RICH_TRY(launch_spmv_J<double>(h->P, h->J7, h->d, h->Jd, s));
+        double slope;
+        RICH_TRY(dotp(h, h->F, h->Jd, &slope));
+        if (!(slope < 0.0)) {
+            if (!fresh) {
+                retry = true;
+                continue;
+            }
+            status = RICH_LINSOLVE_FAIL;
+            break;
+        }
+        double fcur = f0;
+        double lam;
+        int nb;
+        rich_status rc = line_search(h, slope, mxstep, truncated, fcur, &lam, &nb);
+        st->ls_backtracks += nb;
+        if (rc == RICH_LINESEARCH_FAIL) {
+            if (!fresh) {
+                retry = true;
+                continue;
+            }
+            status = rc;
+            break;
+        }
+        RICH_TRY(rc);
+        if (lam < st->min_lambda) st->min_lambda = lam;
+        double dinf[3];
+        RICH_TRY(norms(h, h->d, dinf));
+        double step_inf = lam * dinf[0];
+        RICH_TRY(launch_rel_length(h->d, h->ut, N, h->partial, h->dres, s));
+        double rl;
+        RICH_TRY(readback(h, h->dres, 1, &rl));
+        double step_rel = lam * rl;
+        std::swap(h->u, h->ut);
+        std::swap(h->F, h->Ft);
+        st->newton_its++;
+        h->since_build++;
+        RICH_TRY(fnorms(h, h->F, &f0, &fnorm));
+        if (!std::isfinite(fnorm)) {
+            status = RICH_NONFINITE;
+            break;
+        }
+        if (fnorm <= h->O.fnormtol) break;
+        if (step_rel < h->O.scsteptol) {
+            if (!fresh) {
+                retry = true;
+            } else {
+                status = RICH_STEP_TOO_SMALL;
+                break;
+            }
+        }
+        prev_step = step_inf;
+    }
+    st->fnorm_inf = fnorm;
+    if (status == RICH_OK || status == RICH_STEP_TOO_SMALL) {
+        HIP_TRY(hipMemcpyAsync(h->p, h->u, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+        double fn[3];
+        RICH_TRY(norms(h, h->F, fn));
+        st->mass_residual = h->P.dt * fn[1];
+    }
+    if (h->H) {
+        st->levels = h->H->nlev;
+        st->opc = (double)h->H->nnz_total / (double)h->H->L[0].nnz;
+    }
+    RICH_TRY(sync(h));
+    st->t_total = now_s() - t_start;
+    st->status = status;
+    h->cur = nullptr;
+    return status;
+}
+
+rich_status validate(const rich_problem_t *P, const rich_solver_opts_t *O) {
+    if (!P || !O) return RICH_EINVAL;
+    if (P->nx < 1 || P->ny < 1 || P->nz < 1) return RICH_EINVAL;
+    int64_t n = (int64_t)P->nx * P->ny * P->nz;
+    if (n >= (int64_t)1 << 31) return RICH_EINVAL;
+    if (!(P->hx > 0) || !(P->hy > 0) || !(P->hz > 0) || !(P->dt > 0)) return RICH_EINVAL;
+    if (P->mean < 0 || P->mean > 2) return RICH_EINVAL;
+    for (int f = 0; f < 6; f++)
+        if (P->bc_type[f] != RICH_BC_NOFLUX && P->bc_type[f] != RICH_BC_DIRICHLET) return RICH_EINVAL;
+    if (!(P->alpha > 0) || !(P->A > 0) || !(P->beta > 1) || !(P->gamma > 1)) return RICH_EINVAL;
+    if (O->gmres_restart < 1 || O->gmres_restart > 64 || O->gmres_maxit < 1) return RICH_EINVAL;
+    if (O->amg_max_levels < 1 || O->amg_sweeps < 1 || O->amg_sweeps > 6) return RICH_EINVAL;
+    if (O->coarse_dense_max < 0 || O->coarse_dense_max > 8192 || O->coarse_l1_sweeps < 1) return RICH_EINVAL;
+    if (O->precision != RICH_PREC_FP64 && O->precision != RICH_PREC_MIXED) return RICH_EINVAL;
+    if (!(O->eta > 0) || !(O->fnormtol > 0) || O->max_newton < 1 || O->msbset < 1) return RICH_EINVAL;
+    return RICH_OK;
+}
+
+Phys to_phys(const rich_problem_t *P) {
+    Phys q;
+    q.nx = P->nx;
+    q.ny = P->ny;
+    q.nz = P->nz;
+    q.hx = P->hx;
+    q.hy = P->hy;
+    q.hz = P->hz;
+    q.alpha = P->alpha;
+    q.beta = P->beta;
+    q.theta_s = P->theta_s;
+    q.theta_r = P->theta_r;
+    q.A = P->A;
+    q.gamma = P->gamma;
+    q.mean = P->mean;
+    for (int f = 0; f < 6; f++) {
+        q.bc_type[f] = P->bc_type[f];
+        q.bc_value[f] = P->bc_value[f];
+    }
+    q.dt = P->dt;
+    return q;
+}
+
+}  // namespace
+
+// ============================================================== C-ABI ====
+extern "C" {
+
+const char *rich_status_string(rich_status s) {
+    switch (s) {
+    case RICH_OK: return "ok";
+    case RICH_EINVAL: return "invalid argument";
+    case RICH_ENOMEM: return "device allocation failed";
+    case RICH_EBUDGET: return "memory budget exceeded";
+    case RICH_NONFINITE: return "non-finite value";
+    case RICH_LINSOLVE_FAIL: return "linear solver failed with a fresh Jacobian";
+    case RICH_LINESEARCH_FAIL: return "line search failed with a fresh Jacobian";
+    case RICH_MAXITER: return "Newton iteration limit reached";
+    case RICH_NOT_SPD: return "coarsest matrix not positive definite";
+    case RICH_EHIP: return rich::last_error()[0] ? rich::last_error() : "HIP runtime error";
+    case RICH_ESTATE: return "call not valid in the current state";
+    case RICH_STEP_TOO_SMALL: return "Newton step below scsteptol with a fresh Jacobian";
+    default: return "unknown status";
+    }
+}
+
+rich_status rich_query_bytes(const rich_problem_t *prob, const rich_solver_opts_t *opts, size_t *bytes) {
+    RICH_TRY(validate(prob, opts));
+    if (!bytes) return RICH_EINVAL;
+    size_t N = (size_t)prob->nx * prob->ny * prob->nz;
+    size_t m = opts->gmres_restart;
+    bool mixed = opts->precision == RICH_PREC_MIXED;
+    size_t b = 0;
+    b += N * 8 * 15;                    // fields and Newton work vectors
+    b += N * 8 * 7 + N * 8 * 5;         // J, M, l1 diagonal
+    if (mixed) b += N * 4 * 5;          // FP32 copies
+    b += (m + 1) * N * 8;               // Krylov basis
+    b += N * 8 * 2;                     // preconditioner output and scratch
+    size_t esz = mixed ? 4 : 8;
+    // hierarchy bound: operator complexity <= 3, 12-byte CSR entries plus value copies
+    size_t nnz0 = 7 * N;
+    b += 2 * nnz0 * (12 + esz) + N * (8 + esz + 3 * esz + 8) * 2;
+    size_t nc = (size_t)(opts->coarse_dense_max);
+    b += nc * nc * (8 + esz);
+    *bytes = b;
+    return RICH_OK;
+}
+
+rich_status rich_create(const rich_problem_t *prob, const rich_solver_opts_t *opts, const double *Ks_dev,
+                        void *hip_stream, rich_handle_t *out) {
+    RICH_TRY(validate(prob, opts));
+    if (!Ks_dev || !out) return RICH_EINVAL;
+    rich_ctx *h = new rich_ctx();
+    h->P = to_phys(prob);
+    h->O = *opts;
+    h->N = (int64_t)prob->nx * prob->ny * prob->nz;
+    h->s = (hipStream_t)hip_stream;
+    h->mixed = opts->precision == RICH_PREC_MIXED;
+    h->m = opts->gmres_restart;
+    int64_t N = h->N;
+    rich_status st = RICH_OK;
+    auto G = [&](auto **p, size_t n) {
+        if (st == RICH_OK) st = h->mem.get(p, n);
+    };
+    G(&h->Ks, N);
+    G(&h->p, N);
+    G(&h->theta_old, N);
+    G(&h->u, N);
+    G(&h->F, N);
+    G(&h->ut, N);
+    G(&h->Ft, N);
+    G(&h->d, N);
+    G(&h->Jd, N);
+    G(&h->ub, N);
+    G(&h->Fb, N);
+    G(&h->rhs, N);
+    G(&h->work, N);
+    G(&h->J7, 7 * N);
+    G(&h->M4, 4 * N);
+    G(&h->invd0, N);
+    if (h->mixed) {
+        G(&h->M4f, 4 * N);
+        G(&h->invd0f, N);
+    }
+    G(&h->V, (size_t)(h->m + 1) * N);
+    char *z = nullptr, *zt = nullptr;
+    G(&z, N * 8);
+    G(&zt, N * 8);
+    h->z = z;
+    h->ztmp = zt;
+    G(&h->partial, (size_t)RED_BLOCKS * (h->m + 2) * 3);
+    G(&h->dres, h->m + 8);
+    G(&h->dres2, 8);
+    if (st == RICH_OK && hipHostMalloc((void **)&h->hres, 2 * (h->m + 8) * sizeof(double)) != hipSuccess)
+        st = RICH_ENOMEM;
+    if (st == RICH_OK && hipMemcpyAsync(h->Ks, Ks_dev, N * sizeof(double), hipMemcpyDeviceToDevice, h->s) != hipSuccess)
+        st = RICH_EHIP;
+    if (st == RICH_OK) st = launch_fill_f64(h->p, 0.0, N, h->s);
+    if (st == RICH_OK && hipStreamSynchronize(h->s) != hipSuccess) st = RICH_EHIP;
+    if (st != RICH_OK) {
+        delete h;
+        return st;
+    }
+    *out = h;
+    return RICH_OK;
+}
+
+rich_status rich_destroy(rich_handle_t h) {
+    if (!h) return RICH_EINVAL;
+    (void)hipStreamSynchronize(h->s);
+    delete h;
+    return RICH_OK;
+}
+
+rich_status rich_set_state(rich_handle_t h, const double *p_dev) {
+    if (!h || !p_dev) return RICH_EINVAL;
+    HIP_TRY(hipMemcpyAsync(h->p, p_dev, h->N * sizeof(double), hipMemcpyDeviceToDevice, h->s));
+    return sync(h);
+}
+
+rich_status rich_get_state(rich_handle_t h, double *p_dev) {
+    if (!h || !p_dev) return RICH_EINVAL;
+    HIP_TRY(hipMemcpyAsync(p_dev, h->p, h->N * sizeof(double), hipMemcpyDeviceToDevice, h->s));
+    return sync(h);
+}
+
+rich_status rich_step(rich_handle_t h, int nsteps, rich_step_stats_t *stats_host) {
+    if (!h || nsteps < 0) return RICH_EINVAL;
+    for (int t = 0; t < nsteps; t++) {
+        rich_step_stats_t st;
+        rich_status rc = newton_step(h, &st);
+        if (stats_host) stats_host[t] = st;
+        if (rc < 0) return rc;
+    }
+    return RICH_OK;
+}
+
+rich_status rich_eval_theta(rich_handle_t h, const double *p_dev, double *theta_dev) {
+    if (!h || !p_dev || !theta_dev) return RICH_EINVAL;
+    RICH_TRY(launch_theta(h->P, p_dev, theta_dev, h->s));
+    return sync(h);
+}
+
+rich_status rich_eval_residual(rich_handle_t h, const double *p_dev, const double *theta_old_dev, double *F_dev) {
+    if (!h || !p_dev || !theta_old_dev || !F_dev) return RICH_EINVAL;
+    RICH_TRY(launch_residual(h->P, h->Ks, p_dev, theta_old_dev, F_dev, h->s));
+    return sync(h);
+}
+
+rich_status rich_assemble(rich_handle_t h, const double *p_dev) {
+    if (!h || !p_dev) return RICH_EINVAL;
+    return rebuild(h, p_dev);
+}
+
+rich_status rich_setup_hierarchy(rich_handle_t h) {
+    if (!h) return RICH_EINVAL;
+    if (!h->have_J) return RICH_ESTATE;
+    return build_hierarchy(h);
+}
+
+rich_status rich_apply_jacobian(rich_handle_t h, const double *x_dev, double *y_dev) {
+    if (!h || !x_dev || !y_dev) return RICH_EINVAL;
+    if (!h->have_J) return RICH_ESTATE;
+    RICH_TRY(launch_spmv_J<double>(h->P, h->J7, x_dev, y_dev, h->s));
+    return sync(h);
+}
+
+rich_status rich_apply_aux(rich_handle_t h, const double *x_dev, double *y_dev) {
+    if (!h || !x_dev || !y_dev) return RICH_EINVAL;
+    if (!h->have_J) return RICH_ESTATE;
+    RICH_TRY(launch_spmv_M(h->P, h->M4, x_dev, y_dev, h->s));
+    return sync(h);
+}
+
+rich_status rich_apply_prec(rich_handle_t h, const double *b_dev, double *x_dev) {
+    if (!h || !b_dev || !x_dev) return RICH_EINVAL;
+    if (!h->H) return RICH_ESTATE;
+    RICH_TRY(apply_prec(h, b_dev));
+    if (h->mixed) RICH_TRY(launch_cast<float, double>((const float *)h->z, x_dev, h->N, h->s));
+    else HIP_TRY(hipMemcpyAsync(x_dev, h->z, h->N * sizeof(double), hipMemcpyDeviceToDevice, h->s));
+    return sync(h);
+}
+
+rich_status rich_gmres(rich_handle_t h, const double *b_dev, double *x_dev, int *its_host, double *relres_host) {
+    if (!h || !b_dev || !x_dev) return RICH_EINVAL;
+    if (!h->H) return RICH_ESTATE;
+    int its;
+    double rr;
+    bool conv;
+    RICH_TRY(gmres(h, b_dev, x_dev, &its, &rr, &conv));
+    if (its_host) *its_host = its;
+    if (relres_host) *relres_host = rr;
+    RICH_TRY(sync(h));
+    return conv ? RICH_OK : RICH_LINSOLVE_FAIL;
+}
+
+rich_status rich_levels(rich_handle_t h, int *nlev_host) {
+    if (!h || !nlev_host) return RICH_EINVAL;
+    *nlev_host = h->H ? h->H->nlev : 0;
+    return RICH_OK;
+}
+
+rich_status rich_level_size(rich_handle_t h, int level, int64_t *n_host, int64_t *nnz_host) {
+    if (!h || !h->H || level < 0 || level >= h->H->nlev) return RICH_EINVAL;
+    if (n_host) *n_host = h->H->L[level].n;
+    if (nnz_host) *nnz_host = h->H->L[level].nnz;
+    return RICH_OK;
+}
+
+rich_status rich_export_csr(rich_handle_t h, int which, int level, int64_t *rowptr_host, int32_t *col_host,
+                            double *val_host, int64_t *nnz_inout) {
+    if (!h || !rowptr_host || !col_host || !val_host || !nnz_inout) return RICH_EINVAL;
+    if (!h->have_J) return RICH_ESTATE;
+    int64_t N = h->N;
+    if (which == RICH_WHICH_J || (which == RICH_WHICH_A && level == 0)) {
+        DevAlloc tmp;
+        int64_t *cnt, *stmp, *rp;
+        int32_t *col;
+        double *val;
+        RICH_TRY(tmp.get(&cnt, N));
+        RICH_TRY(tmp.get(&stmp, scan_tmp_size(N)));
+        RICH_TRY(tmp.get(&rp, N + 1));
+        RICH_TRY(launch_stencil_rowcounts(h->P, cnt, h->s));
+        RICH_TRY(scan_exclusive_i64(cnt, rp, N, stmp, h->s));
+        int64_t nnz;
+        HIP_TRY(hipMemcpyAsync(&nnz, rp + N, sizeof(int64_t), hipMemcpyDeviceToHost, h->s));
+        RICH_TRY(sync(h));
+        if (*nnz_inout < nnz) {
+            *nnz_inout = nnz;
+            return RICH_EINVAL;
+        }
+        RICH_TRY(tmp.get(&col, nnz));
+        RICH_TRY(tmp.get(&val, nnz));
+        if (which == RICH_WHICH_J) RICH_TRY(launch_J_to_csr(h->P, h->J7, rp, col, val, h->s));
+        else RICH_TRY(launch_stencil_to_csr(h->P, h->M4, rp, col, val, h->s));
+        HIP_TRY(hipMemcpyAsync(rowptr_host, rp, (N + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, h->s));
+        HIP_TRY(hipMemcpyAsync(col_host, col, nnz * sizeof(int32_t), hipMemcpyDeviceToHost, h->s));
+        HIP_TRY(hipMemcpyAsync(val_host, val, nnz * sizeof(double), hipMemcpyDeviceToHost, h->s));
+        RICH_TRY(sync(h));
+        *nnz_inout = nnz;
+        return RICH_OK;
+    }
+    if (which != RICH_WHICH_A || !h->H || level < 0 || level >= h->H->nlev) return RICH_EINVAL;
+    const Level &Lv = h->H->L[level];
+    if (*nnz_inout < Lv.nnz) {
+        *nnz_inout = Lv.nnz;
+        return RICH_EINVAL;
+    }
+    HIP_TRY(hipMemcpyAsync(rowptr_host, Lv.rowptr, (Lv.n + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, h->s));
+    HIP_TRY(hipMemcpyAsync(col_host, Lv.col, Lv.nnz * sizeof(int32_t), hipMemcpyDeviceToHost, h->s));
+    HIP_TRY(hipMemcpyAsync(val_host, Lv.val, Lv.nnz * sizeof(double), hipMemcpyDeviceToHost, h->s));
+    RICH_TRY(sync(h));
+    *nnz_inout = Lv.nnz;
+    return RICH_OK;
+}
+
+rich_status rich_export_aggregates(rich_handle_t h, int level, int32_t *agg_host, int64_t *n_coarse_host) {
+    if (!h || !h->H || !agg_host || level < 0 || level >= h->H->nlev - 1) return RICH_EINVAL;
+    const Level &Lv = h->H->L[level];
+    HIP_TRY(hipMemcpyAsync(agg_host, Lv.agg, Lv.n * sizeof(int32_t), hipMemcpyDeviceToHost, h->s));
+    RICH_TRY(sync(h));
+    if (n_coarse_host) *n_coarse_host = h->H->L[level + 1].n;
+    return RICH_OK;
+}
+
+rich_status rich_match_sweep(int64_t n, const int64_t *rowptr_dev, const int32_t *col_dev, const double *val_dev,
+                             int32_t *agg_dev, int64_t *n_coarse_host, void *hip_stream) {
+    if (n < 0 || n >= ((int64_t)1 << 31) || !rowptr_dev || !col_dev || !val_dev || !agg_dev || !n_coarse_host)
+        return RICH_EINVAL;
+    return match_sweep(n, rowptr_dev, col_dev, val_dev, agg_dev, n_coarse_host, (hipStream_t)hip_stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,194 @@
+"""HIP library vs the FP64 oracle, element by element, through the C-ABI.
+
+Tolerances (FP64): the two sides evaluate the same formulas with different
+pow/exp/log implementations and summation orders, so agreement is at the
+level of a few ulps of the largest term; 1e-12 of the row / vector scale is
+used.  Integer outputs (patterns, aggregates) must be bit-exact.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import synth
+from tests.helpers import (all_dirichlet, box_problem, csr_close, random_heads, random_ks,
+                           random_spd_graph, smooth_recipe)
+
+pytestmark = pytest.mark.gpu
+
+MEANS = [synth.ARITH, synth.UPSTREAM, synth.HARMONIC]
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a GPU"
+    return t
+
+
+@pytest.fixture(scope="module")
+def rich():
+    import paper_2112_05051_amd as r
+    r.load()
+    return r
+
+
+def dev(torch, a, dtype=None):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def make_solver(rich, torch, P, ks, opts=None):
+    opts = opts or synth.Options()
+    return rich.Solver(P, opts, dev(torch, ks))
+
+
+@pytest.mark.parametrize("mean", MEANS)
+@pytest.mark.parametrize("shape", [(13, 11, 9), (1, 1, 40), (64, 3, 5)])
+def test_theta_residual(rich, torch, orc, mean, shape):
+    P = box_problem(*shape, mean=mean, dt=7.0)
+    if shape == (64, 3, 5):
+        P.bc_type, P.bc_value = all_dirichlet()
+    n = P.n
+    ks = random_ks(P, 11)
+    p = random_heads(n, 12, saturated_fraction=0.05)
+    pold = random_heads(n, 13)
+    s = make_solver(rich, torch, P, ks)
+    th_g = s.theta(dev(torch, pold)).cpu().numpy()
+    th_o = orc.theta(P, pold)
+    assert np.max(np.abs(th_g - th_o)) <= 1e-13 * np.max(np.abs(th_o))
+    F_g = s.residual(dev(torch, p), dev(torch, th_o)).cpu().numpy()
+    F_o = orc.residual(P, ks, p, th_o)
+    assert np.max(np.abs(F_g - F_o)) <= 1e-12 * np.max(np.abs(F_o))
+
+
+@pytest.mark.parametrize("mean", MEANS)
+def test_jacobian_aux_spmv(rich, torch, orc, mean):
+    P = box_problem(13, 11, 9, mean=mean, dt=3.0)
+    n = P.n
+    ks = random_ks(P, 21)
+    p = random_heads(n, 22, saturated_fraction=0.03)
+    s = make_solver(rich, torch, P, ks)
+    s.assemble(dev(torch, p))
+    rp, col, val = s.export_csr(rich.WHICH_J)
+    J = orc.jacobian(P, ks, p)
+    csr_close(rp, col, val, J, 1e-12)
+    rp, col, val = s.export_csr(rich.WHICH_A, 0)
+    M = orc.auxiliary(P, ks, p)
+    csr_close(rp, col, val, M, 1e-12)
+    x = np.random.default_rng(23).standard_normal(n)
+    y = s.apply_jacobian(dev(torch, x)).cpu().numpy()
+    yo = J @ x
+    assert np.max(np.abs(y - yo)) <= 1e-12 * np.max(np.abs(yo))
+    y = s.apply_aux(dev(torch, x)).cpu().numpy()
+    yo = M @ x
+    assert np.max(np.abs(y - yo)) <= 1e-12 * np.max(np.abs(yo))
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_match_sweep_bitexact_random(rich, torch, orc, seed):
+    n = [1, 2, 17, 300, 1000, 5000][seed]
+    A = random_spd_graph(n, min(1.0, 6.0 / max(n, 1)), 100 + seed)
+    if seed == 3:  # many exact ties in the weights
+        A.data = np.round(A.data * 4) / 4
+        A.data[A.data == 0] = -0.25
+    agg_o, nc_o = orc.match_sweep(A)
+    agg_g, nc_g = rich.match_sweep(dev(torch, A.indptr.astype(np.int64)), dev(torch, A.indices.astype(np.int32)),
+                                   dev(torch, A.data.astype(np.float64)))
+    assert nc_g == nc_o
+    assert np.array_equal(agg_g.cpu().numpy(), agg_o)
+
+
+def test_match_sweep_empty(rich, torch):
+    z64 = torch.zeros(1, dtype=torch.int64, device="cuda")
+    agg, nc = rich.match_sweep(z64, torch.zeros(1, dtype=torch.int32, device="cuda"),
+                               torch.zeros(1, dtype=torch.float64, device="cuda"))
+    assert nc == 0 and agg.numel() == 0
+
+
+@pytest.mark.parametrize("mean", MEANS)
+def test_hierarchy_bitexact(rich, torch, orc, mean):
+    """The GPU's set-up on its own M == the oracle's set-up on that same M."""
+    P = box_problem(37, 29, 23, mean=mean, dt=10.0)
+    n = P.n
+    ks = random_ks(P, 31)
+    p = random_heads(n, 32, -70, -30)
+    opts = synth.Options(amg_coarse_size=200, coarse_dense_max=600)
+    s = make_solver(rich, torch, P, ks, opts)
+    s.assemble(dev(torch, p))
+    rp, col, val = s.export_csr(rich.WHICH_A, 0)
+    M = sp.csr_matrix((val, col, rp), shape=(n, n))
+    amg = orc.AMG(opts, M)
+    assert s.levels() == amg.levels >= 3
+    for l in range(amg.levels):
+        Ao, aggo = amg.level(l)
+        rp, col, val = s.export_csr(rich.WHICH_A, l)
+        csr_close(rp, col, val, Ao, 1e-12)
+        if l < amg.levels - 1:
+            agg_g, nc = s.export_aggregates(l)
+            assert np.array_equal(agg_g, aggo)
+            assert np.bincount(agg_g).max() <= 8
+    # one V-cycle (FP64) vs the oracle's on the same hierarchy
+    b = np.random.default_rng(33).standard_normal(n)
+    xg = s.apply_prec(dev(torch, b)).cpu().numpy()
+    xo = amg.apply(b)
+    assert np.linalg.norm(xg - xo) <= 1e-10 * np.linalg.norm(xo)
+
+
+def test_gmres_parity(rich, torch, orc):
+    r = smooth_recipe("c3", 24, precision=synth.FP64)
+    P = r.problem
+    ks, p0 = r.ks(), r.p0()
+    s = make_solver(rich, torch, P, ks, r.options)
+    th = orc.theta(P, p0)
+    F = orc.residual(P, ks, p0, th)
+    s.assemble(dev(torch, p0))
+    x, its, rr, conv = s.gmres(dev(torch, -F))
+    x = x.cpu().numpy()
+    rp, col, val = s.export_csr(rich.WHICH_A, 0)
+    M = sp.csr_matrix((val, col, rp), shape=(P.n, P.n))
+    amg = orc.AMG(r.options, M)
+    J = orc.jacobian(P, ks, p0)
+    xo, conv_o, its_o, rr_o = orc.gmres(J, -F, amg, r.options.gmres_restart, r.options.eta, r.options.gmres_maxit)
+    assert conv and conv_o
+    assert abs(its - its_o) <= 1
+    assert np.linalg.norm(J @ x + F) <= r.options.eta * np.linalg.norm(F) * (1 + 1e-6)
+    # both are eta-accurate solutions of the same system: their difference is
+    # bounded by the two residuals through ||J^{-1}||; in practice it is far below eta.
+    assert np.linalg.norm(x - xo) <= 10 * r.options.eta * np.linalg.norm(xo)
+
+
+@pytest.mark.parametrize("name,n,mean", [("c1", 12, None), ("c1", 16, None), ("c2", 20, None)])
+def test_full_steps_fp64(rich, torch, orc, name, n, mean):
+    r = smooth_recipe(name, n)
+    r.options.fnormtol = 1e-12
+    r.options.precision = synth.FP64
+    P = r.problem
+    ks, p = r.ks(), r.p0()
+    s = make_solver(rich, torch, P, ks, r.options)
+    s.set_state(dev(torch, p))
+    o = orc.Solver(P, r.options, ks)
+    po = p.copy()
+    for step in range(2):
+        sg = s.step(1)[0]
+        so = o.step(po)
+        assert sg["status"] == 0 and so["status"] == 0
+        pg = s.get_state().cpu().numpy()
+        err = np.linalg.norm(pg - po) / np.linalg.norm(po)
+        assert err <= 1e-8, (step, err, sg, so)
+
+
+def test_full_steps_mixed(rich, torch, orc):
+    r = smooth_recipe("c3", 24)
+    assert r.options.precision == synth.MIXED
+    P = r.problem
+    ks, p = r.ks(), r.p0()
+    s = make_solver(rich, torch, P, ks, r.options)
+    s.set_state(dev(torch, p))
+    o = orc.Solver(P, r.options, ks)
+    po = p.copy()
+    for step in range(2):
+        sg = s.step(1)[0]
+        so = o.step(po)
+        assert sg["status"] == 0 and so["status"] == 0
+        pg = s.get_state().cpu().numpy()
+        err = np.linalg.norm(pg - po) / np.linalg.norm(po)
+        assert err <= 1e-6, (step, err, sg, so)
