@@ -1,0 +1,219 @@
+#!/usr/bin/env python
+"""Benchmark: backward-Euler time steps per second on the 256^3 workload.
+
+Workload: 256^3 cells (16.8 M unknowns) on a 64 cm cube, seeded log-normal
+K_s (sigma_lnK 2.5, correlation 16/16/4 cells), upstream interface mean,
+dt = 10 s, initial head -61.5 cm, top face held at -20.7 cm, Newton
+tolerance 1e-8, GMRES(30) with eta 1e-6, AMG V(1,1) with l1-Jacobi.
+The mixed-precision run (AMG hierarchy stored and applied in FP32, all
+else FP64) is the headline; the all-FP64 run of the same steps is reported
+beside it.  One "step" is one full backward-Euler step: Newton iterations,
+residuals, Jacobian rebuilds and every AMG-preconditioned GMRES solve.
+
+The first `--warmup` steps (which include the one-time AMG set-up on the
+first Jacobian) are untimed; the next `--steps` steps are timed.  Inputs are
+resident on the GPU before timing starts.  Kernel times inside the timed
+region come from HIP events recorded by the library on its own stream.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "time-steps/s at 256^3 (FP64 vs mixed AMG); SpMV HBM GB/s; p50/p99 step ms"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def run_gpu(rec, precision, warmup, steps, ks_dev, p0_dev, profile):
+    import copy
+
+    import torch
+
+    import paper_2112_05051_amd as rich
+    opts = copy.deepcopy(rec.options)
+    opts.precision = precision
+    s = rich.Solver(rec.problem, opts, ks_dev)
+    s.set_state(p0_dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    warm = s.step(warmup) if warmup > 0 else []
+    torch.cuda.synchronize()
+    t_warm = time.perf_counter() - t0
+    log(f"[bench] precision={'mixed' if precision else 'fp64'} warmup {warmup} steps {t_warm:.2f}s")
+    if profile:
+        s.profile(True)
+    p_prev = None
+    per_step = []
+    stats = []
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for k in range(steps):
+        if k == steps - 1:
+            p_prev = s.get_state()
+        ts = time.perf_counter()
+        st = s.step(1)[0]
+        torch.cuda.synchronize()
+        per_step.append(time.perf_counter() - ts)
+        stats.append(st)
+        log(f"[bench]   step {k}: {per_step[-1] * 1e3:.1f} ms newton {st['newton_its']} gmres {st['gmres_its']} "
+            f"jac {st['jac_builds']} status {st['status']}")
+    torch.cuda.synchronize()
+    t_timed = time.perf_counter() - t1
+    prof = s.profile_read() if profile else None
+    if profile:
+        s.profile(False)
+    p_final = s.get_state()
+    return dict(solver=s, t_warm=t_warm, t_timed=t_timed, per_step=per_step, stats=stats, warm=warm,
+                prof=prof, p_final=p_final, p_prev=p_prev)
+
+
+def percentile(xs, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(xs), q)) if xs else float("nan")
+
+
+def cpu_baseline(n_sample=64):
+    """The oracle, single-threaded, on one step of the same recipe at n_sample^3
+    (field statistics in cells unchanged), scaled by cell count to 256^3."""
+    import dataclasses
+
+    import synth
+    from oracle import oracle as orc
+    full = synth.recipe("c3")
+    rec = dataclasses.replace(synth.recipe("c3", n=n_sample), ks_ell=full.ks_ell)
+    ks, p = rec.ks(), rec.p0()
+    S = orc.Solver(rec.problem, rec.options, ks)
+    t0 = time.perf_counter()
+    st = S.step(p)
+    dt = time.perf_counter() - t0
+    scale = (n_sample ** 3) / (256 ** 3)
+    return {"value": scale / dt, "unit": "time-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"1 backward-Euler step of the 256^3 recipe's statistics on a {n_sample}^3 grid "
+                      f"({dt:.1f} s, {st['newton_its']} Newton, {st['gmres_its']} GMRES its, status "
+                      f"{st['status']}), rate scaled by the cell ratio {n_sample}^3/256^3"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=9)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=256, help="cube size (256 = the benchmark workload)")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the all-FP64 comparison run")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-profile", action="store_true", help="no per-kernel event timing")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              f"(the multi-GPU decomposition is described in DESIGN.md, not implemented)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2112_05051_amd as rich
+    import synth
+    from oracle import oracle as orc
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    rich.load()
+    rec = synth.recipe("c3") if args.n == 256 else __import__("dataclasses").replace(
+        synth.recipe("c3", n=args.n), ks_ell=synth.recipe("c3").ks_ell)
+    t = time.perf_counter()
+    ks = rec.ks()
+    p0 = rec.p0()
+    log(f"[bench] K_s field {rec.problem.nx}^3 generated in {time.perf_counter() - t:.1f}s")
+    ks_dev = torch.from_numpy(ks).cuda()
+    p0_dev = torch.from_numpy(p0).cuda()
+    torch.cuda.synchronize()
+
+    mixed = run_gpu(rec, rich.PREC_MIXED, args.warmup, args.steps, ks_dev, p0_dev, not args.no_profile)
+    mixed["solver"].close()
+    fp64 = None
+    if not args.no_fp64:
+        fp64 = run_gpu(rec, rich.PREC_FP64, args.warmup, args.steps, ks_dev, p0_dev, False)
+        fp64["solver"].close()
+
+    steps = args.steps
+    value = steps / mixed["t_timed"] if steps else 0.0
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "time-steps/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * mixed["t_timed"] / max(steps, 1),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64 (Newton, GMRES) + f32 (AMG V-cycle)",
+        "data": "synthetic",
+        "config": {"workload": rec.name, "cells": rec.problem.n, "grid": [rec.problem.nx] * 3,
+                   "mean": "upstream", "dt_s": rec.problem.dt, "ks_sigma_ln": rec.ks_sigma,
+                   "ks_corr_cells": list(rec.ks_ell), "newton_tol": rec.options.fnormtol,
+                   "gmres": f"GMRES({rec.options.gmres_restart}) eta {rec.options.eta}",
+                   "amg": "matching aggregation (<=8), V(1,1) l1-Jacobi, dense coarsest"},
+        "p50_step_ms": 1e3 * percentile(mixed["per_step"], 50),
+        "p99_step_ms": 1e3 * percentile(mixed["per_step"], 99),
+        "run_incl_warmup_s": mixed["t_warm"] + mixed["t_timed"],
+        "newton_its": sum(s["newton_its"] for s in mixed["stats"]),
+        "gmres_its": sum(s["gmres_its"] for s in mixed["stats"]),
+        "jac_builds": sum(s["jac_builds"] for s in mixed["stats"]),
+        "levels": mixed["stats"][-1]["levels"] if mixed["stats"] else None,
+        "opc": mixed["stats"][-1]["opc"] if mixed["stats"] else None,
+        "statuses": sorted({s["status"] for s in mixed["stats"]}),
+    }
+    if fp64 is not None:
+        out["fp64"] = {"value": steps / fp64["t_timed"], "ms_per_step": 1e3 * fp64["t_timed"] / max(steps, 1),
+                       "p50_step_ms": 1e3 * percentile(fp64["per_step"], 50),
+                       "p99_step_ms": 1e3 * percentile(fp64["per_step"], 99),
+                       "newton_its": sum(s["newton_its"] for s in fp64["stats"]),
+                       "gmres_its": sum(s["gmres_its"] for s in fp64["stats"])}
+        out["mixed_over_fp64"] = out["value"] / out["fp64"]["value"]
+        a, b = mixed["p_final"].cpu().numpy(), fp64["p_final"].cpu().numpy()
+        out["mixed_vs_fp64_rel_l2"] = float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+    # Property that holds at any size: the oracle's residual at the GPU's final
+    # state (with the GPU's previous state as theta_old) is below the tolerance.
+    if mixed["p_prev"] is not None:
+        pp = mixed["p_prev"].cpu().numpy()
+        pf = mixed["p_final"].cpu().numpy()
+        F = orc.residual(rec.problem, ks, pf, orc.theta(rec.problem, pp))
+        out["oracle_residual_inf_at_gpu_state"] = float(np.max(np.abs(F)))
+
+    prof = mixed["prof"]
+    if prof:
+        kern = {}
+        for name, (n, ms, by) in prof.items():
+            if n:
+                kern[name] = {"launches": n, "avg_us": 1e3 * ms / n, "total_ms": ms,
+                              "gbs": by / (ms * 1e-3) / 1e9 if ms > 0 else None,
+                              "bytes_per_launch": by / n}
+        out["kernels"] = kern
+        dom = max(kern, key=lambda k: kern[k]["total_ms"])
+        d = kern[dom]
+        out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": d["gbs"], "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": d["gbs"] / HBM_PEAK_GBS, "traffic": None,
+                           "avg_us": d["avg_us"], "bytes_per_launch": d["bytes_per_launch"]}
+        if "spmv_J" in kern:
+            out["spmv_hbm_gbs"] = kern["spmv_J"]["gbs"]
+    if not args.no_cpu:
+        log("[bench] oracle CPU baseline ...")
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

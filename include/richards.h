@@ -94,6 +94,9 @@ typedef struct rich_solver_opts {
     int64_t coarse_dense_max; /* coarsest solved directly when n <= this (<= 8192) */
     int coarse_l1_sweeps;     /* otherwise this many l1-Jacobi sweeps */
     int precision;       /* RICH_PREC_* */
+    int amg_refresh;     /* on every rebuild after the first: 0 = refresh the fine level and its
+                            smoother only (coarse matrices frozen, Section 6); 1 = also recompute
+                            every coarse matrix from the new fine one, aggregates kept */
 } rich_solver_opts_t;
 
 /* Per-time-step counters and timings (host wall seconds of each phase). */
@@ -179,6 +182,28 @@ rich_status rich_export_aggregates(rich_handle_t h, int level, int32_t *agg_host
 rich_status rich_match_sweep(int64_t n, const int64_t *rowptr_dev, const int32_t *col_dev,
                              const double *val_dev, int32_t *agg_dev, int64_t *n_coarse_host,
                              void *hip_stream);
+
+/* ----------------------------------------------------------- profiling -- */
+/* Hot kernels whose launches can be timed with HIP events on the handle's
+ * stream while profiling is on.  Each launch also adds its algorithmic HBM
+ * bytes (the data the operation must move: coefficients, vectors in and
+ * out, index arrays of the AMG levels; neighbour re-reads excluded). */
+#define RICH_K_SPMV_J 0       /* y = J z inside GMRES (7 FP64 coefficient arrays) */
+#define RICH_K_VC0_PRE 1      /* fine level: pre-smooth from zero + residual */
+#define RICH_K_VC0_POST 2     /* fine level: prolongation + post-smooth */
+#define RICH_K_VC0_RESTRICT 3 /* fine -> level 1 restriction */
+#define RICH_K_VC1_PRE 4      /* level 1 (CSR): pre-smooth + residual */
+#define RICH_K_VC1_POST 5     /* level 1 (CSR): prolongation + post-smooth */
+#define RICH_K_MULTIDOT 6     /* Gram-Schmidt dot block V^T w (first pass) */
+#define RICH_K_UPDATE 7       /* w -= V h with ||w||^2 (first pass) */
+#define RICH_K_RESIDUAL 8     /* Phi(p) */
+#define RICH_K_COUNT 9
+/* enable != 0: clear the counters and start timing; 0: stop. */
+rich_status rich_profile(rich_handle_t h, int enable);
+/* Launch count, summed kernel milliseconds and summed algorithmic bytes of
+ * one kernel since profiling was enabled (waits for the stream). */
+rich_status rich_profile_read(rich_handle_t h, int kernel, int64_t *launches_host, double *ms_host,
+                              double *bytes_host);
 
 #ifdef __cplusplus
 }

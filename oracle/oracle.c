@@ -429,11 +429,18 @@ void orc_galerkin(int64_t n, const int64_t *rowptr, const int32_t *col, const do
 }
 
 /* ------------------------------------------------------------------------ */
-/* AMG hierarchy (Section 5.2).  Level l+1 comes from `amg_sweeps` pairwise  */
-/* matching sweeps on level l, each followed by the piecewise-constant       */
-/* Galerkin product, so aggregates hold at most 2^sweeps unknowns (the paper */
-/* caps SMATCH aggregates at 8, i.e. three sweeps).  Coarsening stops when   */
-/* a level has at most amg_coarse_size rows or amg_max_levels levels exist. */
+/* AMG hierarchy (Section 5.2).  The aggregates of level l come from        */
+/* `amg_sweeps` pairwise matching sweeps, each sweep matching the Galerkin  */
+/* product of the previous one, so aggregates hold at most 2^sweeps         */
+/* unknowns (the paper caps SMATCH aggregates at 8, i.e. three sweeps).     */
+/* The stored coarse matrix is the Galerkin product of level l with the     */
+/* composed aggregates (M_{l+1} = P^T M_l P, piecewise-constant P).         */
+/* Coarsening stops when a level has at most amg_coarse_size rows or        */
+/* amg_max_levels levels exist.                                             */
+/* Re-use (Section 6): the aggregates are kept for the whole run; later     */
+/* rebuilds refresh the fine matrix and its smoother and, when amg_refresh  */
+/* is set (the reading used by default, see DESIGN), recompute every coarse */
+/* matrix from the new fine one with the same aggregates.                   */
 /* Smoother: l1-Jacobi, D_ii = sum_j |a_ij| (reading of the paper's "l1-     */
 /* Jacobi").  Coarsest: dense Cholesky when n <= coarse_dense_max, else      */
 /* coarse_l1_sweeps l1-Jacobi sweeps from zero (both keep M^{-1} linear).    */
@@ -441,6 +448,7 @@ void orc_galerkin(int64_t n, const int64_t *rowptr, const int32_t *col, const do
 #define ORC_MAXLEV 32
 struct orc_amg {
     int nlev;
+    int refresh;
     orc_csr A[ORC_MAXLEV];
     int32_t *agg[ORC_MAXLEV];
     double *l1[ORC_MAXLEV];
@@ -548,8 +556,10 @@ int orc_amg_build(const orc_opts *O, int64_t n, const int64_t *rowptr, const int
             free(comp);
             break;
         }
+        int64_t ncomp = cur.n;
+        csr_free(&cur);
         H->agg[l] = comp;
-        H->A[l + 1] = cur;
+        galerkin_alloc(&H->A[l], comp, ncomp, &H->A[l + 1]);
         l++;
     }
     H->nlev = l + 1;
@@ -558,6 +568,7 @@ int orc_amg_build(const orc_opts *O, int64_t n, const int64_t *rowptr, const int
         l1_diag(&H->A[t], H->l1[t]);
     }
     H->coarse_sweeps = O->coarse_l1_sweeps;
+    H->refresh = O->amg_refresh;
     H->dense = H->A[H->nlev - 1].n <= O->coarse_dense_max;
     if (H->dense) {
         int st = dense_cholesky(&H->A[H->nlev - 1], &H->chol);
@@ -574,10 +585,21 @@ int orc_amg_update_fine(orc_amg *H, const double *val)
 {
     memcpy(H->A[0].val, val, (size_t)H->A[0].rowptr[H->A[0].n] * sizeof(double));
     l1_diag(&H->A[0], H->l1[0]);
-    if (H->nlev == 1 && H->dense) {
+    int last = 0; /* last level whose matrix changed */
+    if (H->refresh) {
+        for (int l = 0; l + 1 < H->nlev; l++) {
+            const orc_csr *A = &H->A[l];
+            orc_csr *C = &H->A[l + 1];
+            /* same aggregates, so the same pattern: recompute the values */
+            orc_galerkin(A->n, A->rowptr, A->col, A->val, H->agg[l], C->n, C->rowptr, C->col, C->val);
+            l1_diag(C, H->l1[l + 1]);
+        }
+        last = H->nlev - 1;
+    }
+    if (H->dense && last == H->nlev - 1) {
         free(H->chol);
         H->chol = NULL;
-        return dense_cholesky(&H->A[0], &H->chol);
+        return dense_cholesky(&H->A[H->nlev - 1], &H->chol);
     }
     return ORC_OK;
 }

@@ -58,6 +58,7 @@ typedef struct {
     int amg_sweeps;
     int64_t coarse_dense_max;
     int coarse_l1_sweeps;
+    int amg_refresh; /* 0: later rebuilds refresh the smoother only; 1: also the coarse matrices */
 } orc_opts;
 
 typedef struct {

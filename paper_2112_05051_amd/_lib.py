@@ -45,7 +45,7 @@ class Opts(C.Structure):
                 ("gmres_restart", C.c_int), ("eta", C.c_double), ("gmres_maxit", C.c_int),
                 ("amg_max_levels", C.c_int), ("amg_coarse_size", C.c_int64),
                 ("amg_sweeps", C.c_int), ("coarse_dense_max", C.c_int64),
-                ("coarse_l1_sweeps", C.c_int), ("precision", C.c_int)]
+                ("coarse_l1_sweeps", C.c_int), ("precision", C.c_int), ("amg_refresh", C.c_int)]
 
 
 class StepStats(C.Structure):
@@ -62,7 +62,10 @@ EXPORTS = ["rich_query_bytes", "rich_create", "rich_destroy", "rich_set_state", 
            "rich_step", "rich_status_string", "rich_eval_theta", "rich_eval_residual",
            "rich_assemble", "rich_setup_hierarchy", "rich_apply_jacobian", "rich_apply_aux",
            "rich_apply_prec", "rich_gmres", "rich_levels", "rich_level_size", "rich_export_csr",
-           "rich_export_aggregates", "rich_match_sweep"]
+           "rich_export_aggregates", "rich_match_sweep", "rich_profile", "rich_profile_read"]
+
+KERNELS = ["spmv_J", "vc0_pre", "vc0_post", "vc0_restrict", "vc1_pre", "vc1_post", "multidot", "update",
+           "residual"]
 
 _lib = None
 
@@ -99,6 +102,8 @@ def load(path: str = LIB_PATH):
     L.rich_export_csr.argtypes = [vp, C.c_int, C.c_int, i64p, i32p, dp, i64p]
     L.rich_export_aggregates.argtypes = [vp, C.c_int, i32p, i64p]
     L.rich_match_sweep.argtypes = [C.c_int64, vp, vp, vp, vp, i64p, vp]
+    L.rich_profile.argtypes = [vp, C.c_int]
+    L.rich_profile_read.argtypes = [vp, C.c_int, i64p, dp, dp]
     for name in EXPORTS:
         getattr(L, name).restype = C.c_int if name != "rich_status_string" else C.c_char_p
     _lib = L
@@ -274,6 +279,18 @@ class Solver:
                                        val.ctypes.data_as(C.POINTER(C.c_double)), C.byref(nnz)),
                "rich_export_csr")
         return rp, col[:nnz.value], val[:nnz.value]
+
+    def profile(self, enable: bool):
+        _check(self._L.rich_profile(self._h, 1 if enable else 0), "rich_profile")
+
+    def profile_read(self) -> dict:
+        """{kernel name: (launches, total ms, total algorithmic bytes)}"""
+        out = {}
+        for k, name in enumerate(KERNELS):
+            n, ms, b = C.c_int64(), C.c_double(), C.c_double()
+            _check(self._L.rich_profile_read(self._h, k, C.byref(n), C.byref(ms), C.byref(b)), "rich_profile_read")
+            out[name] = (n.value, ms.value, b.value)
+        return out
 
     def export_aggregates(self, level: int):
         n, _ = self.level_size(level)

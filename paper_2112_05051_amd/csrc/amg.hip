@@ -10,7 +10,6 @@ namespace rich {
 namespace {
 
 constexpr int TPB = 256;
-constexpr int GAL_CAP = 160;  // distinct coarse columns one pairwise-merged row may hold
 
 inline unsigned nblocks(int64_t n, int tpb = TPB) { return (unsigned)((n + tpb - 1) / tpb); }
 
@@ -150,60 +149,75 @@ __global__ void k_sort_members(int64_t nc, const int64_t *__restrict__ mptr, int
     }
 }
 
-// Coarse row I: members ascending, each fine row in column order, values of
-// equal coarse column J summed in that order (the oracle's order).
-// pass 0: count distinct J into cnt[I]; pass 1: write sorted row.
-template <int PASS>
-__global__ void __launch_bounds__(64) k_galerkin(int64_t nc, const int64_t *__restrict__ mptr,
-                                                 const int32_t *__restrict__ mem, const int64_t *__restrict__ rowptr,
-                                                 const int32_t *__restrict__ col, const double *__restrict__ val,
-                                                 const int32_t *__restrict__ agg, int64_t *__restrict__ cnt,
-                                                 const int64_t *__restrict__ crow, int32_t *__restrict__ ccol,
-                                                 double *__restrict__ cval, int *__restrict__ overflow) {
+// Symbolic product: the coarse columns J = agg[j] reached from the member
+// rows of coarse row I, sorted and unique.  Each coarse row owns a scratch
+// segment as long as the sum of its members' row lengths (an upper bound).
+__global__ void k_seg_len(int64_t nc, const int64_t *__restrict__ mptr, const int32_t *__restrict__ mem,
+                          const int64_t *__restrict__ rowptr, int64_t *__restrict__ seg) {
     int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (I >= nc) return;
-    int32_t cols[GAL_CAP];
-    double vals[GAL_CAP];
-    int len = 0;
+    int64_t s = 0;
+    for (int64_t t = mptr[I]; t < mptr[I + 1]; t++) s += rowptr[mem[t] + 1] - rowptr[mem[t]];
+    seg[I] = s;
+}
+
+__global__ void k_sym_collect(int64_t nc, const int64_t *__restrict__ mptr, const int32_t *__restrict__ mem,
+                              const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+                              const int32_t *__restrict__ agg, const int64_t *__restrict__ segptr,
+                              int32_t *__restrict__ scratch, int64_t *__restrict__ cnt) {
+    int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= nc) return;
+    int32_t *buf = scratch + segptr[I];
+    int64_t len = 0;
+    for (int64_t t = mptr[I]; t < mptr[I + 1]; t++) {
+        int32_t i = mem[t];
+        for (int64_t e = rowptr[i]; e < rowptr[i + 1]; e++) {
+            // insert agg[col] into the sorted unique prefix buf[0..len)
+            int32_t J = agg[col[e]];
+            int64_t u = len;
+            while (u > 0 && buf[u - 1] > J) u--;
+            if (u > 0 && buf[u - 1] == J) continue;
+            for (int64_t v = len; v > u; v--) buf[v] = buf[v - 1];
+            buf[u] = J;
+            len++;
+        }
+    }
+    cnt[I] = len;
+}
+
+__global__ void k_sym_write(int64_t nc, const int64_t *__restrict__ segptr, const int32_t *__restrict__ scratch,
+                            const int64_t *__restrict__ crow, int32_t *__restrict__ ccol) {
+    int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= nc) return;
+    const int32_t *buf = scratch + segptr[I];
+    int64_t o = crow[I], n = crow[I + 1] - o;
+    for (int64_t a = 0; a < n; a++) ccol[o + a] = buf[a];
+}
+
+// Numeric product on a fixed pattern: members ascending, each fine row in
+// column order, every term added to its coarse entry in that order (the
+// oracle's order), starting from zero.
+__global__ void k_gal_numeric(int64_t nc, const int64_t *__restrict__ mptr, const int32_t *__restrict__ mem,
+                              const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+                              const double *__restrict__ val, const int32_t *__restrict__ agg,
+                              const int64_t *__restrict__ crow, const int32_t *__restrict__ ccol,
+                              double *__restrict__ cval) {
+    int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= nc) return;
+    int64_t a = crow[I], b = crow[I + 1];
+    for (int64_t e = a; e < b; e++) cval[e] = 0.0;
     for (int64_t t = mptr[I]; t < mptr[I + 1]; t++) {
         int32_t i = mem[t];
         for (int64_t e = rowptr[i]; e < rowptr[i + 1]; e++) {
             int32_t J = agg[col[e]];
-            int u = 0;
-            while (u < len && cols[u] != J) u++;
-            if (u == len) {
-                if (len == GAL_CAP) {
-                    *overflow = 1;
-                    return;
-                }
-                cols[len] = J;
-                vals[len] = 0.0;
-                len++;
+            int64_t lo = a, hi = b - 1;
+            while (lo < hi) {
+                int64_t mid = (lo + hi) >> 1;
+                if (ccol[mid] < J) lo = mid + 1;
+                else hi = mid;
             }
-            vals[u] += val[e];
+            cval[lo] += val[e];
         }
-    }
-    if (PASS == 0) {
-        cnt[I] = len;
-        return;
-    }
-    // insertion sort by column
-    for (int a = 1; a < len; a++) {
-        int32_t cj = cols[a];
-        double vj = vals[a];
-        int b = a - 1;
-        while (b >= 0 && cols[b] > cj) {
-            cols[b + 1] = cols[b];
-            vals[b + 1] = vals[b];
-            b--;
-        }
-        cols[b + 1] = cj;
-        vals[b + 1] = vj;
-    }
-    int64_t o = crow[I];
-    for (int a = 0; a < len; a++) {
-        ccol[o + a] = cols[a];
-        cval[o + a] = vals[a];
     }
 }
 
@@ -334,29 +348,23 @@ __global__ void k_csr_to_dense(int64_t n, const int64_t *__restrict__ rowptr, co
     for (int64_t e = rowptr[i]; e < rowptr[i + 1]; e++) D[i * n + col[e]] = val[e];
 }
 
-// Gauss-Jordan step k (no pivoting; an SPD matrix keeps every pivot > 0).
-__global__ void k_gj_save(int64_t n, int64_t k, const double *__restrict__ D, double *__restrict__ rowk,
-                          double *__restrict__ colk) {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n) return;
-    rowk[t] = D[k * n + t];
-    colk[t] = D[t * n + k];
-}
-
-__global__ void k_gj_update(int64_t n, int64_t k, double *__restrict__ D, const double *__restrict__ rowk,
-                            const double *__restrict__ colk, int *__restrict__ bad) {
+// Gauss-Jordan step k (no pivoting; an SPD matrix keeps every pivot > 0),
+// reading S and writing D so that every entry of step k sees step k-1.
+__global__ void k_gj_step(int64_t n, int64_t k, const double *__restrict__ S, double *__restrict__ D,
+                          int *__restrict__ bad) {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n * n) return;
     int64_t i = t / n, j = t - i * n;
-    double p = rowk[k];
+    double p = S[k * n + k];
     if (!(p > 0.0)) {
         if (t == 0) *bad = 1;
+        D[t] = S[t];
         return;
     }
     double v;
-    if (i == k) v = (j == k) ? 1.0 / p : rowk[j] / p;
-    else if (j == k) v = -colk[i] / p;
-    else v = D[t] - colk[i] * rowk[j] / p;
+    if (i == k) v = (j == k) ? 1.0 / p : S[k * n + j] / p;
+    else if (j == k) v = -S[i * n + k] / p;
+    else v = S[t] - S[i * n + k] * S[k * n + j] / p;
     D[t] = v;
 }
 
@@ -443,41 +451,61 @@ rich_status members(const int32_t *agg, int64_t n, int64_t nc, int64_t *mptr, in
     return RICH_OK;
 }
 
-rich_status galerkin(const CsrDev &A, const int32_t *agg, int64_t nc, CsrDev *C, DevAlloc &mem_out,
-                     hipStream_t s) {
+rich_status galerkin_symbolic(const CsrDev &A, const int32_t *agg, int64_t nc, const int64_t *mptr,
+                              const int32_t *mem, CsrDev *C, DevAlloc &mem_out, hipStream_t s) {
     DevAlloc tmp;
-    int64_t *mptr, *cnt, *stmp;
-    int32_t *mem;
-    int *overflow;
-    RICH_TRY(tmp.get(&mptr, nc + 1));
-    RICH_TRY(tmp.get(&mem, A.n));
+    int64_t *seg, *segptr, *cnt, *stmp;
+    int32_t *scratch;
+    RICH_TRY(tmp.get(&seg, nc));
+    RICH_TRY(tmp.get(&segptr, nc + 1));
     RICH_TRY(tmp.get(&cnt, nc));
     RICH_TRY(tmp.get(&stmp, scan_tmp_size(nc)));
-    RICH_TRY(tmp.get(&overflow, 1));
-    HIP_TRY(hipMemsetAsync(overflow, 0, sizeof(int), s));
-    RICH_TRY(members(agg, A.n, nc, mptr, mem, s));
+    RICH_TRY(tmp.get(&scratch, A.nnz));
     C->n = nc;
     RICH_TRY(mem_out.get(&C->rowptr, nc + 1));
     if (nc > 0) {
-        k_galerkin<0><<<nblocks(nc, 64), 64, 0, s>>>(nc, mptr, mem, A.rowptr, A.col, A.val, agg, cnt, nullptr,
-                                                     nullptr, nullptr, overflow);
+        k_seg_len<<<nblocks(nc), TPB, 0, s>>>(nc, mptr, mem, A.rowptr, seg);
+        LAUNCH_CHECK();
+    }
+    RICH_TRY(scan_exclusive_i64(seg, segptr, nc, stmp, s));
+    if (nc > 0) {
+        k_sym_collect<<<nblocks(nc, 64), 64, 0, s>>>(nc, mptr, mem, A.rowptr, A.col, agg, segptr, scratch, cnt);
         LAUNCH_CHECK();
     }
     RICH_TRY(scan_exclusive_i64(cnt, C->rowptr, nc, stmp, s));
     int64_t nnz = 0;
-    int ovf = 0;
     HIP_TRY(hipMemcpyAsync(&nnz, C->rowptr + nc, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(&ovf, overflow, sizeof(int), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    if (ovf) return RICH_EINVAL;
     C->nnz = nnz;
     RICH_TRY(mem_out.get(&C->col, nnz));
     RICH_TRY(mem_out.get(&C->val, nnz));
     if (nc > 0) {
-        k_galerkin<1><<<nblocks(nc, 64), 64, 0, s>>>(nc, mptr, mem, A.rowptr, A.col, A.val, agg, nullptr, C->rowptr,
-                                                     C->col, C->val, overflow);
+        k_sym_write<<<nblocks(nc), TPB, 0, s>>>(nc, segptr, scratch, C->rowptr, C->col);
         LAUNCH_CHECK();
     }
+    HIP_TRY(hipStreamSynchronize(s));  // tmp is freed on return
+    return RICH_OK;
+}
+
+rich_status galerkin_numeric(const CsrDev &A, const int32_t *agg, const int64_t *mptr, const int32_t *mem,
+                             const CsrDev &C, hipStream_t s) {
+    if (C.n == 0) return RICH_OK;
+    k_gal_numeric<<<nblocks(C.n, 64), 64, 0, s>>>(C.n, mptr, mem, A.rowptr, A.col, A.val, agg, C.rowptr, C.col,
+                                                  C.val);
+    LAUNCH_CHECK();
+    return RICH_OK;
+}
+
+rich_status galerkin(const CsrDev &A, const int32_t *agg, int64_t nc, CsrDev *C, DevAlloc &mem_out,
+                     hipStream_t s) {
+    DevAlloc tmp;
+    int64_t *mptr;
+    int32_t *mem;
+    RICH_TRY(tmp.get(&mptr, nc + 1));
+    RICH_TRY(tmp.get(&mem, A.n));
+    RICH_TRY(members(agg, A.n, nc, mptr, mem, s));
+    RICH_TRY(galerkin_symbolic(A, agg, nc, mptr, mem, C, mem_out, s));
+    RICH_TRY(galerkin_numeric(A, agg, mptr, mem, *C, s));
     HIP_TRY(hipStreamSynchronize(s));
     return RICH_OK;
 }
@@ -503,19 +531,21 @@ rich_status compose_agg(int32_t *comp, const int32_t *a, int64_t n, hipStream_t 
 // Inverse of an SPD CSR matrix into a dense row-major n x n buffer.
 rich_status dense_inverse(const CsrDev &A, double *D, hipStream_t s) {
     int64_t n = A.n;
+    if (n == 0) return RICH_OK;
     DevAlloc tmp;
-    double *rowk, *colk;
+    double *W;
     int *bad;
-    RICH_TRY(tmp.get(&rowk, n));
-    RICH_TRY(tmp.get(&colk, n));
+    RICH_TRY(tmp.get(&W, n * n));
     RICH_TRY(tmp.get(&bad, 1));
     HIP_TRY(hipMemsetAsync(bad, 0, sizeof(int), s));
-    HIP_TRY(hipMemsetAsync(D, 0, (size_t)n * n * sizeof(double), s));
-    k_csr_to_dense<<<nblocks(n), TPB, 0, s>>>(n, A.rowptr, A.col, A.val, D);
+    double *src = (n % 2 == 0) ? D : W;  // the last step writes D
+    HIP_TRY(hipMemsetAsync(src, 0, (size_t)n * n * sizeof(double), s));
+    k_csr_to_dense<<<nblocks(n), TPB, 0, s>>>(n, A.rowptr, A.col, A.val, src);
     LAUNCH_CHECK();
     for (int64_t k = 0; k < n; k++) {
-        k_gj_save<<<nblocks(n), TPB, 0, s>>>(n, k, D, rowk, colk);
-        k_gj_update<<<nblocks(n * n), TPB, 0, s>>>(n, k, D, rowk, colk, bad);
+        double *dst = (src == D) ? W : D;
+        k_gj_step<<<nblocks(n * n), TPB, 0, s>>>(n, k, src, dst, bad);
+        src = dst;
     }
     LAUNCH_CHECK();
     int hb = 0;

@@ -188,6 +188,11 @@ struct CsrDev {
 };
 rich_status galerkin(const CsrDev &A, const int32_t *agg, int64_t nc, CsrDev *C, DevAlloc &mem,
                      hipStream_t s);
+// pattern of P^T A P given the members of every coarse row; values by galerkin_numeric
+rich_status galerkin_symbolic(const CsrDev &A, const int32_t *agg, int64_t nc, const int64_t *mptr,
+                              const int32_t *mem, CsrDev *C, DevAlloc &mem_out, hipStream_t s);
+rich_status galerkin_numeric(const CsrDev &A, const int32_t *agg, const int64_t *mptr, const int32_t *mem,
+                             const CsrDev &C, hipStream_t s);
 rich_status members(const int32_t *agg, int64_t n, int64_t nc, int64_t *mptr, int32_t *mem,
                     hipStream_t s);
 rich_status csr_invd(const CsrDev &A, double *invd, float *invdf, hipStream_t s);

@@ -58,9 +58,24 @@ struct rich_ctx {
     int since_build = 0;
     // stats of the step in progress
     rich_step_stats_t *cur = nullptr;
+    // optional per-kernel event timing
+    struct KProf {
+        int64_t launches = 0;
+        double bytes = 0.0, ms = 0.0;
+        std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+    };
+    bool profiling = false;
+    KProf prof[RICH_K_COUNT];
+    std::vector<hipEvent_t> event_pool;
     ~rich_ctx() {
         delete H;
         if (hres) (void)hipHostFree(hres);
+        for (auto &k : prof)
+            for (auto &e : k.pending) {
+                (void)hipEventDestroy(e.first);
+                (void)hipEventDestroy(e.second);
+            }
+        for (auto e : event_pool) (void)hipEventDestroy(e);
     }
 };
 
@@ -90,6 +105,51 @@ rich_status dotp(rich_ctx *h, const double *x, const double *y, double *out) {
     return readback(h, h->dres, 1, out);
 }
 
+// ---------------------------------------------------------- profiling
+// Collect the elapsed time of every pending (start, stop) event pair.
+rich_status prof_harvest(rich_ctx *h) {
+    HIP_TRY(hipStreamSynchronize(h->s));
+    for (auto &k : h->prof) {
+        for (auto &e : k.pending) {
+            float ms = 0.0f;
+            HIP_TRY(hipEventElapsedTime(&ms, e.first, e.second));
+            k.ms += ms;
+            h->event_pool.push_back(e.first);
+            h->event_pool.push_back(e.second);
+        }
+        k.pending.clear();
+    }
+    return RICH_OK;
+}
+
+rich_status prof_event(rich_ctx *h, hipEvent_t *e) {
+    if (!h->event_pool.empty()) {
+        *e = h->event_pool.back();
+        h->event_pool.pop_back();
+        return RICH_OK;
+    }
+    HIP_TRY(hipEventCreate(e));
+    return RICH_OK;
+}
+
+// Launch through `f`, bracketed by events when profiling is on.
+template <class F>
+rich_status timed(rich_ctx *h, int id, double bytes, F &&f) {
+    if (!h->profiling || id >= RICH_K_COUNT) return f();
+    hipEvent_t a, b;
+    RICH_TRY(prof_event(h, &a));
+    RICH_TRY(prof_event(h, &b));
+    HIP_TRY(hipEventRecord(a, h->s));
+    rich_status st = f();
+    HIP_TRY(hipEventRecord(b, h->s));
+    auto &k = h->prof[id];
+    k.pending.push_back({a, b});
+    k.launches++;
+    k.bytes += bytes;
+    if (k.pending.size() >= 2048) RICH_TRY(prof_harvest(h));
+    return st;
+}
+
 // ------------------------------------------------------------- hierarchy
 rich_status build_hierarchy(rich_ctx *h) {
     delete h->H;
@@ -98,21 +158,24 @@ rich_status build_hierarchy(rich_ctx *h) {
     hipStream_t s = h->s;
     const Phys &P = h->P;
     int64_t N = h->N;
-    DevAlloc tmp;  // level-0 CSR and intermediate matrices
-    // level-0 CSR of M (set-up only)
+    DevAlloc tmp;
+    // level-0 CSR of M, kept for the numeric refreshes of the coarse matrices
     CsrDev A0;
     A0.n = N;
     int64_t *cnt, *stmp;
     RICH_TRY(tmp.get(&cnt, N));
     RICH_TRY(tmp.get(&stmp, scan_tmp_size(N)));
-    RICH_TRY(tmp.get(&A0.rowptr, N + 1));
+    RICH_TRY(H.mem.get(&A0.rowptr, N + 1));
     RICH_TRY(launch_stencil_rowcounts(P, cnt, s));
     RICH_TRY(scan_exclusive_i64(cnt, A0.rowptr, N, stmp, s));
     HIP_TRY(hipMemcpyAsync(&A0.nnz, A0.rowptr + N, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     RICH_TRY(sync(h));
-    RICH_TRY(tmp.get(&A0.col, A0.nnz));
-    RICH_TRY(tmp.get(&A0.val, A0.nnz));
+    RICH_TRY(H.mem.get(&A0.col, A0.nnz));
+    RICH_TRY(H.mem.get(&A0.val, A0.nnz));
     RICH_TRY(launch_stencil_to_csr(P, h->M4, A0.rowptr, A0.col, A0.val, s));
+    H.L[0].rowptr = A0.rowptr;
+    H.L[0].col = A0.col;
+    H.L[0].val = A0.val;
 
     H.L[0].n = N;
     H.L[0].nnz = A0.nnz;
@@ -164,22 +227,23 @@ rich_status build_hierarchy(rich_ctx *h) {
         }
         Level &Lf = H.L[l];
         Lf.agg = comp;
-        RICH_TRY(H.mem.get(&Lf.mptr, cur.n + 1));
+        int64_t nc = cur.n;
+        delete cur_mem;  // the pairwise products served the matching only
+        RICH_TRY(H.mem.get(&Lf.mptr, nc + 1));
         RICH_TRY(H.mem.get(&Lf.mem, levA.n));
-        RICH_TRY(members(comp, levA.n, cur.n, Lf.mptr, Lf.mem, s));
-        // keep the coarse matrix in the hierarchy's own memory
-        Level &Lc = H.L[l + 1];
-        Lc.n = cur.n;
-        Lc.nnz = cur.nnz;
-        RICH_TRY(H.mem.get(&Lc.rowptr, cur.n + 1));
-        RICH_TRY(H.mem.get(&Lc.col, cur.nnz));
-        RICH_TRY(H.mem.get(&Lc.val, cur.nnz));
-        HIP_TRY(hipMemcpyAsync(Lc.rowptr, cur.rowptr, (cur.n + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
-        HIP_TRY(hipMemcpyAsync(Lc.col, cur.col, cur.nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
-        HIP_TRY(hipMemcpyAsync(Lc.val, cur.val, cur.nnz * sizeof(double), hipMemcpyDeviceToDevice, s));
+        RICH_TRY(members(comp, levA.n, nc, Lf.mptr, Lf.mem, s));
+        // the coarse matrix: Galerkin product with the composed aggregates
+        CsrDev C;
+        RICH_TRY(galerkin_symbolic(levA, comp, nc, Lf.mptr, Lf.mem, &C, H.mem, s));
+        RICH_TRY(galerkin_numeric(levA, comp, Lf.mptr, Lf.mem, C, s));
         RICH_TRY(sync(h));
-        delete cur_mem;
-        H.nnz_total += cur.nnz;
+        Level &Lc = H.L[l + 1];
+        Lc.n = C.n;
+        Lc.nnz = C.nnz;
+        Lc.rowptr = C.rowptr;
+        Lc.col = C.col;
+        Lc.val = C.val;
+        H.nnz_total += C.nnz;
         levA.n = Lc.n;
         levA.nnz = Lc.nnz;
         levA.rowptr = Lc.rowptr;
@@ -215,7 +279,7 @@ rich_status build_hierarchy(rich_ctx *h) {
     H.dense = Lc.n <= h->O.coarse_dense_max;
     if (H.dense) {
         RICH_TRY(H.mem.get(&H.cinv, Lc.n * Lc.n));
-        CsrDev A = (H.nlev == 1) ? A0 : CsrDev{Lc.n, Lc.nnz, Lc.rowptr, Lc.col, Lc.val};
+        CsrDev A{Lc.n, Lc.nnz, Lc.rowptr, Lc.col, Lc.val};
         RICH_TRY(dense_inverse(A, H.cinv, s));
         if (h->mixed) {
             RICH_TRY(H.mem.get(&H.cinvf, Lc.n * Lc.n));
@@ -226,26 +290,33 @@ rich_status build_hierarchy(rich_ctx *h) {
     return RICH_OK;
 }
 
-// refresh what depends on the fine matrix when the hierarchy is a single level
-rich_status refresh_single_level(rich_ctx *h) {
+// After a rebuild of M: the fine level's smoother data come with the
+// assembly; with amg_refresh every coarse matrix is recomputed from the new
+// fine matrix through the fixed aggregates (values only; the patterns do not
+// change), then its smoother data and the coarsest inverse.  Without it
+// (the paper's re-use) only a one-level hierarchy needs its inverse redone.
+rich_status refresh_hierarchy(rich_ctx *h) {
     Hierarchy &H = *h->H;
-    if (H.nlev != 1 || !H.dense) return RICH_OK;
-    DevAlloc tmp;
-    CsrDev A0;
-    A0.n = h->N;
-    int64_t *cnt, *stmp;
-    RICH_TRY(tmp.get(&cnt, h->N));
-    RICH_TRY(tmp.get(&stmp, scan_tmp_size(h->N)));
-    RICH_TRY(tmp.get(&A0.rowptr, h->N + 1));
-    RICH_TRY(launch_stencil_rowcounts(h->P, cnt, h->s));
-    RICH_TRY(scan_exclusive_i64(cnt, A0.rowptr, h->N, stmp, h->s));
-    HIP_TRY(hipMemcpyAsync(&A0.nnz, A0.rowptr + h->N, sizeof(int64_t), hipMemcpyDeviceToHost, h->s));
-    RICH_TRY(sync(h));
-    RICH_TRY(tmp.get(&A0.col, A0.nnz));
-    RICH_TRY(tmp.get(&A0.val, A0.nnz));
-    RICH_TRY(launch_stencil_to_csr(h->P, h->M4, A0.rowptr, A0.col, A0.val, h->s));
-    RICH_TRY(dense_inverse(A0, H.cinv, h->s));
-    if (h->mixed) RICH_TRY(launch_cast(H.cinv, H.cinvf, h->N * h->N, h->s));
+    hipStream_t s = h->s;
+    bool all = h->O.amg_refresh != 0;
+    if (!all && H.nlev > 1) return RICH_OK;
+    RICH_TRY(launch_stencil_to_csr(h->P, h->M4, H.L[0].rowptr, H.L[0].col, H.L[0].val, s));
+    if (all) {
+        for (int l = 0; l + 1 < H.nlev; l++) {
+            Level &Lf = H.L[l], &Lc = H.L[l + 1];
+            CsrDev A{Lf.n, Lf.nnz, Lf.rowptr, Lf.col, Lf.val};
+            CsrDev C{Lc.n, Lc.nnz, Lc.rowptr, Lc.col, Lc.val};
+            RICH_TRY(galerkin_numeric(A, Lf.agg, Lf.mptr, Lf.mem, C, s));
+            RICH_TRY(csr_invd(C, Lc.invd, Lc.invdf, s));
+            if (h->mixed) RICH_TRY(launch_cast(Lc.val, Lc.valf, Lc.nnz, s));
+        }
+    }
+    if (H.dense) {
+        Level &Lc = H.L[H.nlev - 1];
+        CsrDev A{Lc.n, Lc.nnz, Lc.rowptr, Lc.col, Lc.val};
+        RICH_TRY(dense_inverse(A, H.cinv, s));
+        if (h->mixed) RICH_TRY(launch_cast(H.cinv, H.cinvf, Lc.n * Lc.n, s));
+    }
     return sync(h);
 }
 
@@ -276,12 +347,19 @@ rich_status vcycle(rich_ctx *h, const double *b, T *z) {
         if (H.dense) return launch_dense_gemv<double, T>(cinv, b, z, h->N, s);
         return launch_st_sweeps<double, T>(h->P, M4, invd0, b, z, (T *)h->ztmp, h->O.coarse_l1_sweeps, s);
     }
+    const double t = sizeof(T), n0 = (double)h->N, n1 = (double)H.L[1].n;
     // down
-    RICH_TRY(launch_st_pre<double, T>(h->P, M4, invd0, b, (T *)H.L[0].r, s));
-    RICH_TRY(launch_restrict<T>(H.L[0], (const T *)H.L[0].r, (T *)H.L[1].b, H.L[1].n, s));
+    RICH_TRY(timed(h, RICH_K_VC0_PRE, n0 * (8 + 6 * t),
+                   [&] { return launch_st_pre<double, T>(h->P, M4, invd0, b, (T *)H.L[0].r, s); }));
+    RICH_TRY(timed(h, RICH_K_VC0_RESTRICT, n0 * (t + 4) + n1 * (8 + t), [&] {
+        return launch_restrict<T>(H.L[0], (const T *)H.L[0].r, (T *)H.L[1].b, H.L[1].n, s);
+    }));
     for (int l = 1; l < H.nlev - 1; l++) {
         Level &Lv = H.L[l];
-        RICH_TRY(launch_csr_pre<T, T>(Lv, lvval<T>(Lv), lvinvd<T>(Lv), (const T *)Lv.b, (T *)Lv.r, s));
+        double bytes = (double)Lv.nnz * (4 + t) + (double)Lv.n * (8 + 3 * t);
+        RICH_TRY(timed(h, l == 1 ? RICH_K_VC1_PRE : RICH_K_COUNT, bytes, [&] {
+            return launch_csr_pre<T, T>(Lv, lvval<T>(Lv), lvinvd<T>(Lv), (const T *)Lv.b, (T *)Lv.r, s);
+        }));
         RICH_TRY(launch_restrict<T>(Lv, (const T *)Lv.r, (T *)H.L[l + 1].b, H.L[l + 1].n, s));
     }
     // coarsest
@@ -295,10 +373,15 @@ rich_status vcycle(rich_ctx *h, const double *b, T *z) {
     // up
     for (int l = H.nlev - 2; l >= 1; l--) {
         Level &Lv = H.L[l];
-        RICH_TRY(launch_csr_post<T, T>(Lv, lvval<T>(Lv), lvinvd<T>(Lv), (const T *)Lv.b, (const T *)H.L[l + 1].x,
-                                       (T *)Lv.x, s));
+        double bytes = (double)Lv.nnz * (4 + t) + (double)Lv.n * (12 + 4 * t) + (double)H.L[l + 1].n * t;
+        RICH_TRY(timed(h, l == 1 ? RICH_K_VC1_POST : RICH_K_COUNT, bytes, [&] {
+            return launch_csr_post<T, T>(Lv, lvval<T>(Lv), lvinvd<T>(Lv), (const T *)Lv.b,
+                                         (const T *)H.L[l + 1].x, (T *)Lv.x, s);
+        }));
     }
-    return launch_st_post<double, T>(h->P, M4, invd0, b, (const T *)H.L[1].x, H.L[0].agg, z, s);
+    return timed(h, RICH_K_VC0_POST, n0 * (12 + 6 * t) + n1 * t, [&] {
+        return launch_st_post<double, T>(h->P, M4, invd0, b, (const T *)H.L[1].x, H.L[0].agg, z, s);
+    });
 }
 
 rich_status apply_prec(rich_ctx *h, const double *b) {
@@ -307,8 +390,11 @@ rich_status apply_prec(rich_ctx *h, const double *b) {
 }
 
 rich_status spmv_J_z(rich_ctx *h, double *y) {
-    if (h->mixed) return launch_spmv_J<float>(h->P, h->J7, (const float *)h->z, y, h->s);
-    return launch_spmv_J<double>(h->P, h->J7, (const double *)h->z, y, h->s);
+    double bytes = (double)h->N * (56 + 8 + (h->mixed ? 4 : 8));
+    return timed(h, RICH_K_SPMV_J, bytes, [&] {
+        if (h->mixed) return launch_spmv_J<float>(h->P, h->J7, (const float *)h->z, y, h->s);
+        return launch_spmv_J<double>(h->P, h->J7, (const double *)h->z, y, h->s);
+    });
 }
 
 rich_status add_z(rich_ctx *h, double *x) {
@@ -371,8 +457,11 @@ rich_status gmres(rich_ctx *h, const double *b, double *x, int *its_out, double 
             double *w = h->V + (size_t)(j + 1) * N;
             RICH_TRY(apply_prec(h, vj));
             RICH_TRY(spmv_J_z(h, w));
-            RICH_TRY(launch_multidot(h->V, N, j + 1, w, N, h->partial, h->dres, s));
-            RICH_TRY(launch_update_norm(h->V, N, j + 1, h->dres, w, N, h->partial, h->dres2, s));
+            RICH_TRY(timed(h, RICH_K_MULTIDOT, (double)N * 8 * (j + 2),
+                           [&] { return launch_multidot(h->V, N, j + 1, w, N, h->partial, h->dres, s); }));
+            RICH_TRY(timed(h, RICH_K_UPDATE, (double)N * 8 * (j + 3), [&] {
+                return launch_update_norm(h->V, N, j + 1, h->dres, w, N, h->partial, h->dres2, s);
+            }));
             HIP_TRY(hipMemcpyAsync(h->hres, h->dres, (j + 2) * sizeof(double), hipMemcpyDeviceToHost, s));
             HIP_TRY(hipMemcpyAsync(h->hres + (m + 8), h->dres2, sizeof(double), hipMemcpyDeviceToHost, s));
             RICH_TRY(sync(h));
@@ -432,7 +521,8 @@ rich_status gmres(rich_ctx *h, const double *b, double *x, int *its_out, double 
 // ----------------------------------------------------------------- Newton
 rich_status feval(rich_ctx *h, const double *u, double *F) {
     double t0 = now_s();
-    RICH_TRY(launch_residual(h->P, h->Ks, u, h->theta_old, F, h->s));
+    RICH_TRY(timed(h, RICH_K_RESIDUAL, (double)h->N * 32,
+                   [&] { return launch_residual(h->P, h->Ks, u, h->theta_old, F, h->s); }));
     if (h->cur) {
         RICH_TRY(sync(h));
         h->cur->t_feval += now_s() - t0;
@@ -454,7 +544,7 @@ rich_status rebuild(rich_ctx *h, const double *u) {
         RICH_TRY(build_hierarchy(h));
         if (h->cur) h->cur->amg_setups++;
     } else {
-        RICH_TRY(refresh_single_level(h));
+        RICH_TRY(refresh_hierarchy(h));
     }
     if (h->cur) h->cur->t_setup += now_s() - t1;
     h->have_J = true;
@@ -701,6 +791,7 @@ rich_status validate(const rich_problem_t *P, const rich_solver_opts_t *O) {
     if (O->amg_max_levels < 1 || O->amg_sweeps < 1 || O->amg_sweeps > 6) return RICH_EINVAL;
     if (O->coarse_dense_max < 0 || O->coarse_dense_max > 8192 || O->coarse_l1_sweeps < 1) return RICH_EINVAL;
     if (O->precision != RICH_PREC_FP64 && O->precision != RICH_PREC_MIXED) return RICH_EINVAL;
+    if (O->amg_refresh != 0 && O->amg_refresh != 1) return RICH_EINVAL;
     if (!(O->eta > 0) || !(O->fnormtol > 0) || O->max_newton < 1 || O->msbset < 1) return RICH_EINVAL;
     return RICH_OK;
 }
@@ -987,6 +1078,31 @@ rich_status rich_export_aggregates(rich_handle_t h, int level, int32_t *agg_host
     HIP_TRY(hipMemcpyAsync(agg_host, Lv.agg, Lv.n * sizeof(int32_t), hipMemcpyDeviceToHost, h->s));
     RICH_TRY(sync(h));
     if (n_coarse_host) *n_coarse_host = h->H->L[level + 1].n;
+    return RICH_OK;
+}
+
+rich_status rich_profile(rich_handle_t h, int enable) {
+    if (!h) return RICH_EINVAL;
+    RICH_TRY(prof_harvest(h));
+    if (enable) {
+        for (auto &k : h->prof) {
+            k.launches = 0;
+            k.bytes = 0.0;
+            k.ms = 0.0;
+        }
+    }
+    h->profiling = enable != 0;
+    return RICH_OK;
+}
+
+rich_status rich_profile_read(rich_handle_t h, int kernel, int64_t *launches_host, double *ms_host,
+                              double *bytes_host) {
+    if (!h || kernel < 0 || kernel >= RICH_K_COUNT) return RICH_EINVAL;
+    RICH_TRY(prof_harvest(h));
+    const auto &k = h->prof[kernel];
+    if (launches_host) *launches_host = k.launches;
+    if (ms_host) *ms_host = k.ms;
+    if (bytes_host) *bytes_host = k.bytes;
     return RICH_OK;
 }
 

@@ -66,10 +66,11 @@ class Options:
     eta: float = 1e-6
     gmres_maxit: int = 200
     amg_max_levels: int = 10
-    amg_coarse_size: int = 2048
+    amg_coarse_size: int = 512
     amg_sweeps: int = 3                # pairwise matching sweeps -> aggregates <= 2**sweeps
-    coarse_dense_max: int = 4096
+    coarse_dense_max: int = 1024
     coarse_l1_sweeps: int = 4
+    amg_refresh: int = 1               # 1: every rebuild recomputes the coarse matrices (aggregates kept)
     precision: int = FP64
 
 
@@ -128,17 +129,13 @@ RECIPES = {"c1": _c1, "c2": _c2, "c3": _c3, "c5": _c5}
 
 
 def recipe(name: str, n: int | None = None, **kw) -> Recipe:
-    """Build a named recipe; ``n`` shrinks the cube (same statistics scaled in cells)."""
+    """Build a named recipe; ``n`` changes the cube size and keeps every other
+    statistic, the K_s correlation lengths in cells included (so a smaller
+    grid sees the same local smoothness of the field as the full one)."""
     f = RECIPES[name]
     if n is None:
         return f(**kw)
-    r = f(n, **kw) if name != "c1" else f(n)
-    full = f(**kw) if name != "c1" else f()
-    nfull = full.problem.nx
-    if n != nfull and r.ks_sigma > 0:
-        s = n / nfull
-        r = replace(r, ks_ell=tuple(max(1.0, e * s) for e in r.ks_ell))
-    return r
+    return f(n, **kw) if name != "c1" else f(n)
 
 
 def serving_stream(count: int = 64, rate: float = 4.0, seed: int = 20211204,

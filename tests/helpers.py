@@ -35,10 +35,8 @@ def random_ks(P, seed, sigma=1.5, ell=(2.0, 2.0, 1.0)):
 
 
 def smooth_recipe(name, n, **kw):
-    """A recipe at a reduced cube size that keeps the full-size correlation lengths in cells."""
-    full = synth.recipe(name, **kw) if name != "c1" else synth.recipe(name)
-    r = synth.recipe(name, n=n, **kw) if name != "c1" else synth.recipe(name, n=n)
-    return dataclasses.replace(r, ks_ell=full.ks_ell)
+    """A recipe at a reduced cube size (correlation lengths in cells unchanged)."""
+    return synth.recipe(name, n=n, **kw) if name != "c1" else synth.recipe(name, n=n)
 
 
 def random_spd_graph(n, density, seed):

@@ -192,3 +192,47 @@ def test_full_steps_mixed(rich, torch, orc):
         pg = s.get_state().cpu().numpy()
         err = np.linalg.norm(pg - po) / np.linalg.norm(po)
         assert err <= 1e-6, (step, err, sg, so)
+
+
+@pytest.mark.parametrize("refresh", [0, 1])
+def test_hierarchy_refresh(rich, torch, orc, refresh):
+    """After a second assembly the GPU's refreshed hierarchy equals the oracle's
+    (aggregates kept; coarse matrices recomputed when refresh = 1)."""
+    P = box_problem(33, 27, 21, mean=synth.UPSTREAM, dt=10.0)
+    n = P.n
+    ks = random_ks(P, 41)
+    opts = synth.Options(amg_coarse_size=150, coarse_dense_max=400, amg_refresh=refresh)
+    s = make_solver(rich, torch, P, ks, opts)
+    s.assemble(dev(torch, random_heads(n, 42, -70, -30)))
+    rp, col, val = s.export_csr(rich.WHICH_A, 0)
+    amg = orc.AMG(opts, sp.csr_matrix((val, col, rp), shape=(n, n)))
+    s.assemble(dev(torch, random_heads(n, 43, -60, -10)))
+    rp, col, val = s.export_csr(rich.WHICH_A, 0)
+    amg.update_fine(sp.csr_matrix((val, col, rp), shape=(n, n)))
+    assert s.levels() == amg.levels >= 3
+    for l in range(amg.levels):
+        Ao, aggo = amg.level(l)
+        rp, col, val = s.export_csr(rich.WHICH_A, l)
+        csr_close(rp, col, val, Ao, 1e-12)
+        if l < amg.levels - 1:
+            assert np.array_equal(s.export_aggregates(l)[0], aggo)
+    b = np.random.default_rng(44).standard_normal(n)
+    xg = s.apply_prec(dev(torch, b)).cpu().numpy()
+    xo = amg.apply(b)
+    assert np.linalg.norm(xg - xo) <= 1e-10 * np.linalg.norm(xo)
+
+
+def test_mixed_vcycle_close_to_fp64(rich, torch, orc):
+    """The FP32 V-cycle agrees with the FP64 one to single-precision accuracy."""
+    r = smooth_recipe("c3", 20)
+    P = r.problem
+    ks, p0 = r.ks(), r.p0()
+    b = np.random.default_rng(45).standard_normal(P.n)
+    out = {}
+    for prec in (synth.FP64, synth.MIXED):
+        r.options.precision = prec
+        s = make_solver(rich, torch, P, ks, r.options)
+        s.assemble(dev(torch, p0))
+        out[prec] = s.apply_prec(dev(torch, b)).cpu().numpy()
+    err = np.linalg.norm(out[synth.MIXED] - out[synth.FP64]) / np.linalg.norm(out[synth.FP64])
+    assert err <= 1e-5
