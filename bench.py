@@ -74,8 +74,9 @@ def run_gpu(rec, precision, warmup, steps, ks_dev, p0_dev, profile):
     if profile:
         s.profile(False)
     p_final = s.get_state()
+    levels = [list(s.level_size(l)) for l in range(s.levels())]
     return dict(solver=s, t_warm=t_warm, t_timed=t_timed, per_step=per_step, stats=stats, warm=warm,
-                prof=prof, p_final=p_final, p_prev=p_prev)
+                prof=prof, p_final=p_final, p_prev=p_prev, levels=levels)
 
 
 def percentile(xs, q):
@@ -174,6 +175,9 @@ def main():
         "levels": mixed["stats"][-1]["levels"] if mixed["stats"] else None,
         "opc": mixed["stats"][-1]["opc"] if mixed["stats"] else None,
         "statuses": sorted({s["status"] for s in mixed["stats"]}),
+        "linsolve_fails": sum(s["linsolve_fails"] for s in mixed["stats"]),
+        "ls_backtracks": sum(s["ls_backtracks"] for s in mixed["stats"]),
+        "hierarchy_n_nnz": mixed["levels"],
     }
     if fp64 is not None:
         out["fp64"] = {"value": steps / fp64["t_timed"], "ms_per_step": 1e3 * fp64["t_timed"] / max(steps, 1),

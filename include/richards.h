@@ -89,7 +89,9 @@ typedef struct rich_solver_opts {
     double eta;          /* GMRES stops at ||J d + Phi||_2 <= eta ||Phi||_2 */
     int gmres_maxit;     /* GMRES iteration limit per Newton correction */
     int amg_max_levels;  /* <= 16 */
-    int64_t amg_coarse_size;  /* stop coarsening at <= this many rows */
+    int64_t amg_coarse_size;  /* stop coarsening at <= this many rows (also stops when a level
+                                 would keep more than half of the rows and the current level
+                                 is at most coarse_dense_max) */
     int amg_sweeps;      /* pairwise matching sweeps per level (3 -> aggregates <= 8) */
     int64_t coarse_dense_max; /* coarsest solved directly when n <= this (<= 8192) */
     int coarse_l1_sweeps;     /* otherwise this many l1-Jacobi sweeps */

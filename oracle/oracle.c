@@ -435,8 +435,9 @@ void orc_galerkin(int64_t n, const int64_t *rowptr, const int32_t *col, const do
 /* unknowns (the paper caps SMATCH aggregates at 8, i.e. three sweeps).     */
 /* The stored coarse matrix is the Galerkin product of level l with the     */
 /* composed aggregates (M_{l+1} = P^T M_l P, piecewise-constant P).         */
-/* Coarsening stops when a level has at most amg_coarse_size rows or        */
-/* amg_max_levels levels exist.                                             */
+/* Coarsening stops when a level has at most amg_coarse_size rows, when     */
+/* amg_max_levels levels exist, or when the next level would keep more than  */
+/* half of the rows while the current one fits the dense coarsest solver.   */
 /* Re-use (Section 6): the aggregates are kept for the whole run; later     */
 /* rebuilds refresh the fine matrix and its smoother and, when amg_refresh  */
 /* is set (the reading used by default, see DESIGN), recompute every coarse */
@@ -558,6 +559,12 @@ int orc_amg_build(const orc_opts *O, int64_t n, const int64_t *rowptr, const int
         }
         int64_t ncomp = cur.n;
         csr_free(&cur);
+        /* a level that shrinks by less than half is not worth its cost when the
+         * current level can already be solved directly: stop here instead */
+        if (2 * ncomp > H->A[l].n && H->A[l].n <= O->coarse_dense_max) {
+            free(comp);
+            break;
+        }
         H->agg[l] = comp;
         galerkin_alloc(&H->A[l], comp, ncomp, &H->A[l + 1]);
         l++;

@@ -54,29 +54,41 @@ __device__ inline double block_max(double v, double *sh) {
     return r;
 }
 
-// Dot products of w with V_0..V_{k-1} and w.w, partial per block.  Every
-// thread keeps k+1 running sums over its grid-stride rows.
-template <int KC>
-__global__ void __launch_bounds__(RED_THREADS) k_multidot(const double *__restrict__ V, int64_t ldv, int k,
+// Dot products of w with V_0..V_{K-1} and w.w, partial per block.  K is a
+// compile-time constant so every load of a row pair is issued before its
+// use; rows are taken in pairs with 16-byte loads (the basis stride ldv is a
+// multiple of 2 and the vectors are 16-byte aligned).  The odd last row of
+// an odd n is added by the first thread of block 0.
+template <int K>
+__global__ void __launch_bounds__(RED_THREADS) k_multidot(const double *__restrict__ V, int64_t ldv,
                                                           const double *__restrict__ w, int64_t n,
                                                           double *__restrict__ partial) {
     __shared__ double sh[RED_THREADS / WAVE];
-    double acc[KC + 1];
+    double acc[K + 1];
 #pragma unroll
-    for (int i = 0; i <= KC; i++) acc[i] = 0.0;
-    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x) {
-        double wc = w[c];
+    for (int i = 0; i <= K; i++) acc[i] = 0.0;
+    const int64_t n2 = n >> 1;
+    const double2 *__restrict__ w2 = reinterpret_cast<const double2 *>(w);
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n2; c += (int64_t)gridDim.x * blockDim.x) {
+        double2 wc = w2[c];
+        double2 v[K];
 #pragma unroll
-        for (int i = 0; i < KC; i++)
-            if (i < k) acc[i] += V[(size_t)i * ldv + c] * wc;
-        acc[KC] += wc * wc;
+        for (int i = 0; i < K; i++) v[i] = reinterpret_cast<const double2 *>(V + (size_t)i * ldv)[c];
+#pragma unroll
+        for (int i = 0; i < K; i++) acc[i] += v[i].x * wc.x + v[i].y * wc.y;
+        acc[K] += wc.x * wc.x + wc.y * wc.y;
     }
-    for (int i = 0; i < k; i++) {
+    if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+        double wc = w[n - 1];
+#pragma unroll
+        for (int i = 0; i < K; i++) acc[i] += V[(size_t)i * ldv + n - 1] * wc;
+        acc[K] += wc * wc;
+    }
+#pragma unroll
+    for (int i = 0; i <= K; i++) {
         double r = block_sum(acc[i], sh);
-        if (threadIdx.x == 0) partial[(size_t)blockIdx.x * (k + 1) + i] = r;
+        if (threadIdx.x == 0) partial[(size_t)blockIdx.x * (K + 1) + i] = r;
     }
-    double r = block_sum(acc[KC], sh);
-    if (threadIdx.x == 0) partial[(size_t)blockIdx.x * (k + 1) + k] = r;
 }
 
 // out[i] = sum_b partial[b*(m) + i], b ascending (one block per output).
@@ -100,21 +112,36 @@ __global__ void k_reduce_max(const double *__restrict__ partial, int m, int nb, 
     if (threadIdx.x == 0) out[0] = r;
 }
 
-template <int KC>
-__global__ void __launch_bounds__(RED_THREADS) k_update_norm(const double *__restrict__ V, int64_t ldv, int k,
+// w -= sum_i h_i V_i and the partial sums of ||w||^2, K compile-time, row pairs.
+template <int K>
+__global__ void __launch_bounds__(RED_THREADS) k_update_norm(const double *__restrict__ V, int64_t ldv,
                                                              const double *__restrict__ h, double *__restrict__ w,
                                                              int64_t n, double *__restrict__ partial) {
     __shared__ double sh[RED_THREADS / WAVE];
-    __shared__ double hs[KMAX];
-    for (int i = threadIdx.x; i < k; i += blockDim.x) hs[i] = h[i];
-    __syncthreads();
-    double acc = 0.0;
-    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x) {
-        double wc = w[c];
+    double hr[K];
 #pragma unroll
-        for (int i = 0; i < KC; i++)
-            if (i < k) wc -= hs[i] * V[(size_t)i * ldv + c];
-        w[c] = wc;
+    for (int i = 0; i < K; i++) hr[i] = h[i];
+    double acc = 0.0;
+    const int64_t n2 = n >> 1;
+    double2 *__restrict__ w2 = reinterpret_cast<double2 *>(w);
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n2; c += (int64_t)gridDim.x * blockDim.x) {
+        double2 wc = w2[c];
+        double2 v[K];
+#pragma unroll
+        for (int i = 0; i < K; i++) v[i] = reinterpret_cast<const double2 *>(V + (size_t)i * ldv)[c];
+#pragma unroll
+        for (int i = 0; i < K; i++) {
+            wc.x -= hr[i] * v[i].x;
+            wc.y -= hr[i] * v[i].y;
+        }
+        w2[c] = wc;
+        acc += wc.x * wc.x + wc.y * wc.y;
+    }
+    if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+        double wc = w[n - 1];
+#pragma unroll
+        for (int i = 0; i < K; i++) wc -= hr[i] * V[(size_t)i * ldv + n - 1];
+        w[n - 1] = wc;
         acc += wc * wc;
     }
     double r = block_sum(acc, sh);
@@ -299,13 +326,23 @@ __global__ void k_scan_final(const int64_t *__restrict__ in, int64_t n, const in
 
 }  // namespace
 
+#define RICH_CASES_1_64(X)                                                                                    \
+    X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) X(17) X(18) X(19) \
+    X(20) X(21) X(22) X(23) X(24) X(25) X(26) X(27) X(28) X(29) X(30) X(31) X(32) X(33) X(34) X(35) X(36)   \
+    X(37) X(38) X(39) X(40) X(41) X(42) X(43) X(44) X(45) X(46) X(47) X(48) X(49) X(50) X(51) X(52) X(53)   \
+    X(54) X(55) X(56) X(57) X(58) X(59) X(60) X(61) X(62) X(63) X(64)
+
 rich_status launch_multidot(const double *V, int64_t ldv, int k, const double *w, int64_t n, double *partial,
                             double *out, hipStream_t s) {
-    // the template width bounds the register count: 8, 16, 32 or 64 sums
-    if (k <= 8) k_multidot<8><<<RED_BLOCKS, RED_THREADS, 0, s>>>(V, ldv, k, w, n, partial);
-    else if (k <= 16) k_multidot<16><<<RED_BLOCKS, RED_THREADS, 0, s>>>(V, ldv, k, w, n, partial);
-    else if (k <= 32) k_multidot<32><<<RED_BLOCKS, RED_THREADS, 0, s>>>(V, ldv, k, w, n, partial);
-    else k_multidot<64><<<RED_BLOCKS, RED_THREADS, 0, s>>>(V, ldv, k, w, n, partial);
+    if (k < 1 || k > 64 || (ldv & 1)) return RICH_EINVAL;
+    switch (k) {
+#define X(K)                                                                         \
+    case K:                                                                          \
+        k_multidot<K><<<RED_BLOCKS, RED_THREADS, 0, s>>>(V, ldv, w, n, partial);     \
+        break;
+        RICH_CASES_1_64(X)
+#undef X
+    }
     LAUNCH_CHECK();
     k_reduce_partials<<<k + 1, RED_THREADS, 0, s>>>(partial, k + 1, RED_BLOCKS, out);
     LAUNCH_CHECK();
@@ -314,10 +351,15 @@ rich_status launch_multidot(const double *V, int64_t ldv, int k, const double *w
 
 rich_status launch_update_norm(const double *V, int64_t ldv, int k, const double *h, double *w, int64_t n,
                                double *partial, double *out, hipStream_t s) {
-    if (k <= 8) k_update_norm<8><<<RED_BLOCKS, RED_THREADS, 0, s>>>(V, ldv, k, h, w, n, partial);
-    else if (k <= 16) k_update_norm<16><<<RED_BLOCKS, RED_THREADS, 0, s>>>(V, ldv, k, h, w, n, partial);
-    else if (k <= 32) k_update_norm<32><<<RED_BLOCKS, RED_THREADS, 0, s>>>(V, ldv, k, h, w, n, partial);
-    else k_update_norm<64><<<RED_BLOCKS, RED_THREADS, 0, s>>>(V, ldv, k, h, w, n, partial);
+    if (k < 1 || k > 64 || (ldv & 1)) return RICH_EINVAL;
+    switch (k) {
+#define X(K)                                                                            \
+    case K:                                                                             \
+        k_update_norm<K><<<RED_BLOCKS, RED_THREADS, 0, s>>>(V, ldv, h, w, n, partial);  \
+        break;
+        RICH_CASES_1_64(X)
+#undef X
+    }
     LAUNCH_CHECK();
     k_reduce_partials<<<1, RED_THREADS, 0, s>>>(partial, 1, RED_BLOCKS, out);
     LAUNCH_CHECK();

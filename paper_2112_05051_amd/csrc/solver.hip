@@ -45,7 +45,8 @@ struct rich_ctx {
     float *M4f = nullptr, *invd0f = nullptr;
     // GMRES
     int m = 0;
-    double *V = nullptr;       // (m+1) x N
+    int64_t ldv = 0;           // basis stride: N rounded up to 64 (aligned vectors)
+    double *V = nullptr;       // (m+1) x ldv
     void *z = nullptr;         // N, V-cycle output (FP32 or FP64)
     void *ztmp = nullptr;      // N, sweep scratch for a one-level hierarchy
     double *partial = nullptr; // RED_BLOCKS * (m + 2)
@@ -225,10 +226,16 @@ rich_status build_hierarchy(rich_ctx *h) {
             H.mem.release(comp);
             break;
         }
-        Level &Lf = H.L[l];
-        Lf.agg = comp;
         int64_t nc = cur.n;
         delete cur_mem;  // the pairwise products served the matching only
+        // a level that keeps more than half of the rows is not worth its cost
+        // once the current level fits the dense coarsest solver: stop here
+        if (2 * nc > levA.n && levA.n <= h->O.coarse_dense_max) {
+            H.mem.release(comp);
+            break;
+        }
+        Level &Lf = H.L[l];
+        Lf.agg = comp;
         RICH_TRY(H.mem.get(&Lf.mptr, nc + 1));
         RICH_TRY(H.mem.get(&Lf.mem, levA.n));
         RICH_TRY(members(comp, levA.n, nc, Lf.mptr, Lf.mem, s));
@@ -453,14 +460,14 @@ rich_status gmres(rich_ctx *h, const double *b, double *x, int *its_out, double 
         g[0] = beta;
         int k = 0;
         for (int j = 0; j < m && total < h->O.gmres_maxit; j++) {
-            double *vj = h->V + (size_t)j * N;
-            double *w = h->V + (size_t)(j + 1) * N;
+            double *vj = h->V + (size_t)j * h->ldv;
+            double *w = h->V + (size_t)(j + 1) * h->ldv;
             RICH_TRY(apply_prec(h, vj));
             RICH_TRY(spmv_J_z(h, w));
             RICH_TRY(timed(h, RICH_K_MULTIDOT, (double)N * 8 * (j + 2),
-                           [&] { return launch_multidot(h->V, N, j + 1, w, N, h->partial, h->dres, s); }));
+                           [&] { return launch_multidot(h->V, h->ldv, j + 1, w, N, h->partial, h->dres, s); }));
             RICH_TRY(timed(h, RICH_K_UPDATE, (double)N * 8 * (j + 3), [&] {
-                return launch_update_norm(h->V, N, j + 1, h->dres, w, N, h->partial, h->dres2, s);
+                return launch_update_norm(h->V, h->ldv, j + 1, h->dres, w, N, h->partial, h->dres2, s);
             }));
             HIP_TRY(hipMemcpyAsync(h->hres, h->dres, (j + 2) * sizeof(double), hipMemcpyDeviceToHost, s));
             HIP_TRY(hipMemcpyAsync(h->hres + (m + 8), h->dres2, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -470,8 +477,8 @@ rich_status gmres(rich_ctx *h, const double *b, double *x, int *its_out, double 
             double ww1 = h->hres[m + 8];
             if (std::sqrt(ww1) < 0.7 * std::sqrt(ww0)) {
                 // second Gram-Schmidt pass
-                RICH_TRY(launch_multidot(h->V, N, j + 1, w, N, h->partial, h->dres, s));
-                RICH_TRY(launch_update_norm(h->V, N, j + 1, h->dres, w, N, h->partial, h->dres2, s));
+                RICH_TRY(launch_multidot(h->V, h->ldv, j + 1, w, N, h->partial, h->dres, s));
+                RICH_TRY(launch_update_norm(h->V, h->ldv, j + 1, h->dres, w, N, h->partial, h->dres2, s));
                 HIP_TRY(hipMemcpyAsync(h->hres, h->dres, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
                 HIP_TRY(hipMemcpyAsync(h->hres + (m + 8), h->dres2, sizeof(double), hipMemcpyDeviceToHost, s));
                 RICH_TRY(sync(h));
@@ -507,7 +514,7 @@ rich_status gmres(rich_ctx *h, const double *b, double *x, int *its_out, double 
         }
         memcpy(h->hres, y.data(), k * sizeof(double));
         HIP_TRY(hipMemcpyAsync(h->dres, h->hres, k * sizeof(double), hipMemcpyHostToDevice, s));
-        RICH_TRY(launch_lincomb(h->V, N, k, h->dres, h->work, N, s));
+        RICH_TRY(launch_lincomb(h->V, h->ldv, k, h->dres, h->work, N, s));
         RICH_TRY(apply_prec(h, h->work));
         RICH_TRY(add_z(h, x));
         RICH_TRY(sync(h));  // hres is reused before the next read
@@ -900,7 +907,8 @@ rich_status rich_create(const rich_problem_t *prob, const rich_solver_opts_t *op
         G(&h->M4f, 4 * N);
         G(&h->invd0f, N);
     }
-    G(&h->V, (size_t)(h->m + 1) * N);
+    h->ldv = (N + 63) / 64 * 64;
+    G(&h->V, (size_t)(h->m + 1) * h->ldv);
     char *z = nullptr, *zt = nullptr;
     G(&z, N * 8);
     G(&zt, N * 8);

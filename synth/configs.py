@@ -68,7 +68,7 @@ class Options:
     amg_max_levels: int = 10
     amg_coarse_size: int = 512
     amg_sweeps: int = 3                # pairwise matching sweeps -> aggregates <= 2**sweeps
-    coarse_dense_max: int = 1024
+    coarse_dense_max: int = 4096
     coarse_l1_sweeps: int = 4
     amg_refresh: int = 1               # 1: every rebuild recomputes the coarse matrices (aggregates kept)
     precision: int = FP64
