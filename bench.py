@@ -87,12 +87,9 @@ def percentile(xs, q):
 def cpu_baseline(n_sample=64):
     """The oracle, single-threaded, on one step of the same recipe at n_sample^3
     (field statistics in cells unchanged), scaled by cell count to 256^3."""
-    import dataclasses
-
     import synth
     from oracle import oracle as orc
-    full = synth.recipe("c3")
-    rec = dataclasses.replace(synth.recipe("c3", n=n_sample), ks_ell=full.ks_ell)
+    rec = synth.recipe("c3", n=n_sample)
     ks, p = rec.ks(), rec.p0()
     S = orc.Solver(rec.problem, rec.options, ks)
     t0 = time.perf_counter()
@@ -114,6 +111,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the all-FP64 comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-profile", action="store_true", help="no per-kernel event timing")
+    ap.add_argument("--set", action="append", default=[], metavar="OPT=VALUE",
+                    help="override a solver option (experiments; the headline uses the defaults)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -129,8 +128,10 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     rich.load()
-    rec = synth.recipe("c3") if args.n == 256 else __import__("dataclasses").replace(
-        synth.recipe("c3", n=args.n), ks_ell=synth.recipe("c3").ks_ell)
+    rec = synth.recipe("c3", n=args.n)
+    for kv in args.set:
+        k, v = kv.split("=")
+        setattr(rec.options, k, type(getattr(rec.options, k))(float(v)))
     t = time.perf_counter()
     ks = rec.ks()
     p0 = rec.p0()
@@ -178,6 +179,7 @@ def main():
         "linsolve_fails": sum(s["linsolve_fails"] for s in mixed["stats"]),
         "ls_backtracks": sum(s["ls_backtracks"] for s in mixed["stats"]),
         "hierarchy_n_nnz": mixed["levels"],
+        "options": {k: getattr(rec.options, k) for k in vars(rec.options)},
     }
     if fp64 is not None:
         out["fp64"] = {"value": steps / fp64["t_timed"], "ms_per_step": 1e3 * fp64["t_timed"] / max(steps, 1),

@@ -96,6 +96,8 @@ typedef struct rich_solver_opts {
     int64_t coarse_dense_max; /* coarsest solved directly when n <= this (<= 8192) */
     int coarse_l1_sweeps;     /* otherwise this many l1-Jacobi sweeps */
     int precision;       /* RICH_PREC_* */
+    double gmres_reorth; /* second Gram-Schmidt pass when ||w_after|| < gmres_reorth ||w_before||
+                            (0 = never, 0.7071 = always-safe DGKS rule) */
     int amg_refresh;     /* on every rebuild after the first: 0 = refresh the fine level and its
                             smoother only (coarse matrices frozen, Section 6); 1 = also recompute
                             every coarse matrix from the new fine one, aggregates kept */

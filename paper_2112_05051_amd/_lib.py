@@ -45,7 +45,8 @@ class Opts(C.Structure):
                 ("gmres_restart", C.c_int), ("eta", C.c_double), ("gmres_maxit", C.c_int),
                 ("amg_max_levels", C.c_int), ("amg_coarse_size", C.c_int64),
                 ("amg_sweeps", C.c_int), ("coarse_dense_max", C.c_int64),
-                ("coarse_l1_sweeps", C.c_int), ("precision", C.c_int), ("amg_refresh", C.c_int)]
+                ("coarse_l1_sweeps", C.c_int), ("precision", C.c_int), ("gmres_reorth", C.c_double),
+                ("amg_refresh", C.c_int)]
 
 
 class StepStats(C.Structure):

@@ -348,24 +348,113 @@ __global__ void k_csr_to_dense(int64_t n, const int64_t *__restrict__ rowptr, co
     for (int64_t e = rowptr[i]; e < rowptr[i + 1]; e++) D[i * n + col[e]] = val[e];
 }
 
-// Gauss-Jordan step k (no pivoting; an SPD matrix keeps every pivot > 0),
-// reading S and writing D so that every entry of step k sees step k-1.
-__global__ void k_gj_step(int64_t n, int64_t k, const double *__restrict__ S, double *__restrict__ D,
-                          int *__restrict__ bad) {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n * n) return;
-    int64_t i = t / n, j = t - i * n;
-    double p = S[k * n + k];
-    if (!(p > 0.0)) {
-        if (t == 0) *bad = 1;
-        D[t] = S[t];
-        return;
+// Blocked Gauss-Jordan inversion of an SPD matrix (no pivoting: every
+// leading block of an SPD matrix and every Schur complement stay SPD).  For
+// the pivot block K = [k0, k0+b):  P = D_KK,  R_K: = P^{-1} D_K: (with P^{-1}
+// itself in the K columns),  S_:K = D_:K (old), then
+//   D_ij <- R_{i-k0, j}                                  for i in K,
+//   D_ij <- [j not in K] D_ij - sum_t S_it R_tj          otherwise.
+constexpr int GJB = 64;  // pivot block
+
+// P^{-1} by scalar Gauss-Jordan in LDS (one workgroup, b <= 64).
+__global__ void __launch_bounds__(256) k_bgj_pivot(const double *__restrict__ D, int64_t n, int64_t k0, int b,
+                                                    double *__restrict__ Pinv, int *__restrict__ bad) {
+    __shared__ double A[GJB][GJB + 1];
+    __shared__ double rowk[GJB], colk[GJB];
+    for (int t = threadIdx.x; t < b * b; t += blockDim.x) {
+        int r = t / b, c = t - r * b;
+        A[r][c] = D[(k0 + r) * n + k0 + c];
     }
-    double v;
-    if (i == k) v = (j == k) ? 1.0 / p : S[k * n + j] / p;
-    else if (j == k) v = -S[i * n + k] / p;
-    else v = S[t] - S[i * n + k] * S[k * n + j] / p;
-    D[t] = v;
+    __syncthreads();
+    for (int k = 0; k < b; k++) {
+        for (int t = threadIdx.x; t < b; t += blockDim.x) {
+            rowk[t] = A[k][t];
+            colk[t] = A[t][k];
+        }
+        __syncthreads();
+        double p = rowk[k];
+        if (!(p > 0.0)) {
+            if (threadIdx.x == 0) *bad = 1;
+            p = 1.0;  // keep going; the caller reports the failure
+        }
+        for (int t = threadIdx.x; t < b * b; t += blockDim.x) {
+            int i = t / b, j = t - i * b;
+            double v;
+            if (i == k) v = (j == k) ? 1.0 / p : rowk[j] / p;
+            else if (j == k) v = -colk[i] / p;
+            else v = A[i][j] - colk[i] * rowk[j] / p;
+            A[i][j] = v;
+        }
+        __syncthreads();
+    }
+    for (int t = threadIdx.x; t < b * b; t += blockDim.x) {
+        int r = t / b, c = t - r * b;
+        Pinv[r * GJB + c] = A[r][c];
+    }
+}
+
+// R (b x n) and S (n x b, old column block).
+__global__ void k_bgj_panels(const double *__restrict__ D, int64_t n, int64_t k0, int b,
+                             const double *__restrict__ Pinv, double *__restrict__ R, double *__restrict__ S) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    bool inK = j >= k0 && j < k0 + b;
+    for (int r = 0; r < b; r++) {
+        double v;
+        if (inK) {
+            v = Pinv[r * GJB + (j - k0)];
+        } else {
+            v = 0.0;
+            for (int t = 0; t < b; t++) v += Pinv[r * GJB + t] * D[(k0 + t) * n + j];
+        }
+        R[(int64_t)r * n + j] = v;
+    }
+    for (int t = 0; t < b; t++) S[j * GJB + t] = D[j * n + k0 + t];
+}
+
+// Rank-b update on 64x64 tiles, 4x4 outputs per thread, operands in LDS.
+__global__ void __launch_bounds__(256) k_bgj_update(double *__restrict__ D, int64_t n, int64_t k0, int b,
+                                                     const double *__restrict__ R, const double *__restrict__ S) {
+    __shared__ double Ss[GJB][GJB + 1];  // [row in tile][t]
+    __shared__ double Rs[GJB][GJB + 1];  // [t][col in tile]
+    int64_t i0 = (int64_t)blockIdx.y * GJB, j0 = (int64_t)blockIdx.x * GJB;
+    for (int t = threadIdx.x; t < GJB * GJB; t += blockDim.x) {
+        int r = t / GJB, c = t - r * GJB;
+        int64_t gi = i0 + r, gj = j0 + c;
+        Ss[r][c] = (gi < n && c < b) ? S[gi * GJB + c] : 0.0;
+        Rs[r][c] = (r < b && gj < n) ? R[(int64_t)r * n + gj] : 0.0;
+    }
+    __syncthreads();
+    int tr = (threadIdx.x / 16) * 4, tc = (threadIdx.x % 16) * 4;
+    double acc[4][4] = {};
+    for (int t = 0; t < b; t++) {
+        double a[4], r4[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            a[u] = Ss[tr + u][t];
+            r4[u] = Rs[t][tc + u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++)
+#pragma unroll
+            for (int v = 0; v < 4; v++) acc[u][v] += a[u] * r4[v];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+        int64_t gi = i0 + tr + u;
+        if (gi >= n) continue;
+        bool rowK = gi >= k0 && gi < k0 + b;
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+            int64_t gj = j0 + tc + v;
+            if (gj >= n) continue;
+            bool colK = gj >= k0 && gj < k0 + b;
+            double out;
+            if (rowK) out = R[(gi - k0) * n + gj];
+            else out = (colK ? 0.0 : D[gi * n + gj]) - acc[u][v];
+            D[gi * n + gj] = out;
+        }
+    }
 }
 
 }  // namespace
@@ -533,19 +622,22 @@ rich_status dense_inverse(const CsrDev &A, double *D, hipStream_t s) {
     int64_t n = A.n;
     if (n == 0) return RICH_OK;
     DevAlloc tmp;
-    double *W;
+    double *Pinv, *R, *S;
     int *bad;
-    RICH_TRY(tmp.get(&W, n * n));
+    RICH_TRY(tmp.get(&Pinv, GJB * GJB));
+    RICH_TRY(tmp.get(&R, GJB * n));
+    RICH_TRY(tmp.get(&S, n * GJB));
     RICH_TRY(tmp.get(&bad, 1));
     HIP_TRY(hipMemsetAsync(bad, 0, sizeof(int), s));
-    double *src = (n % 2 == 0) ? D : W;  // the last step writes D
-    HIP_TRY(hipMemsetAsync(src, 0, (size_t)n * n * sizeof(double), s));
-    k_csr_to_dense<<<nblocks(n), TPB, 0, s>>>(n, A.rowptr, A.col, A.val, src);
+    HIP_TRY(hipMemsetAsync(D, 0, (size_t)n * n * sizeof(double), s));
+    k_csr_to_dense<<<nblocks(n), TPB, 0, s>>>(n, A.rowptr, A.col, A.val, D);
     LAUNCH_CHECK();
-    for (int64_t k = 0; k < n; k++) {
-        double *dst = (src == D) ? W : D;
-        k_gj_step<<<nblocks(n * n), TPB, 0, s>>>(n, k, src, dst, bad);
-        src = dst;
+    unsigned tiles = (unsigned)((n + GJB - 1) / GJB);
+    for (int64_t k0 = 0; k0 < n; k0 += GJB) {
+        int b = (int)std::min<int64_t>(GJB, n - k0);
+        k_bgj_pivot<<<1, 256, 0, s>>>(D, n, k0, b, Pinv, bad);
+        k_bgj_panels<<<nblocks(n), TPB, 0, s>>>(D, n, k0, b, Pinv, R, S);
+        k_bgj_update<<<dim3(tiles, tiles), 256, 0, s>>>(D, n, k0, b, R, S);
     }
     LAUNCH_CHECK();
     int hb = 0;

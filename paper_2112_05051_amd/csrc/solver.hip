@@ -475,7 +475,7 @@ rich_status gmres(rich_ctx *h, const double *b, double *x, int *its_out, double 
             for (int i = 0; i <= j; i++) hv[i] = h->hres[i];
             double ww0 = h->hres[j + 1];
             double ww1 = h->hres[m + 8];
-            if (std::sqrt(ww1) < 0.7 * std::sqrt(ww0)) {
+            if (std::sqrt(ww1) < h->O.gmres_reorth * std::sqrt(ww0)) {
                 // second Gram-Schmidt pass
                 RICH_TRY(launch_multidot(h->V, h->ldv, j + 1, w, N, h->partial, h->dres, s));
                 RICH_TRY(launch_update_norm(h->V, h->ldv, j + 1, h->dres, w, N, h->partial, h->dres2, s));
@@ -799,6 +799,7 @@ rich_status validate(const rich_problem_t *P, const rich_solver_opts_t *O) {
     if (O->coarse_dense_max < 0 || O->coarse_dense_max > 8192 || O->coarse_l1_sweeps < 1) return RICH_EINVAL;
     if (O->precision != RICH_PREC_FP64 && O->precision != RICH_PREC_MIXED) return RICH_EINVAL;
     if (O->amg_refresh != 0 && O->amg_refresh != 1) return RICH_EINVAL;
+    if (!(O->gmres_reorth >= 0.0 && O->gmres_reorth < 1.0)) return RICH_EINVAL;
     if (!(O->eta > 0) || !(O->fnormtol > 0) || O->max_newton < 1 || O->msbset < 1) return RICH_EINVAL;
     return RICH_OK;
 }

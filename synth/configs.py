@@ -72,6 +72,7 @@ class Options:
     coarse_l1_sweeps: int = 4
     amg_refresh: int = 1               # 1: every rebuild recomputes the coarse matrices (aggregates kept)
     precision: int = FP64
+    gmres_reorth: float = 0.01          # second Gram-Schmidt pass only on severe cancellation
 
 
 @dataclass
