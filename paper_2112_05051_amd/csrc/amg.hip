@@ -242,22 +242,21 @@ __global__ void k_iota(int64_t n, int32_t *__restrict__ x) {
 }
 
 // ----------------------------------------------------- V-cycle, CSR levels
-// Rows are processed by groups of G lanes (G = 8) that stride over the row's
-// entries; the group sum is formed with shuffles in a fixed lane order.
-constexpr int G = 8;
-
-template <class T>
+// Rows are processed by groups of G lanes (4 or 8, by the level's mean row
+// length) that stride over the row's entries; the group sum is formed with
+// shuffles in a fixed lane order.
+template <int G, class T>
 __device__ inline T group_sum(T v) {
 #pragma unroll
     for (int o = G / 2; o > 0; o >>= 1) v += __shfl_down(v, o, G);
     return v;
 }
 
-template <class TB, class T>
+template <int G, class TB, class T>
 __global__ void k_csr_pre(int64_t n, const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
                           const T *__restrict__ val, const T *__restrict__ invd, const TB *__restrict__ b,
                           T *__restrict__ r) {
-    int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+    int64_t row = ((int64_t)xcd_block() * blockDim.x + threadIdx.x) / G;
     int lane = threadIdx.x % G;
     if (row >= n) return;
     T s = 0;
@@ -265,34 +264,38 @@ __global__ void k_csr_pre(int64_t n, const int64_t *__restrict__ rowptr, const i
         int32_t j = col[e];
         s += val[e] * ((T)b[j] * invd[j]);
     }
-    s = group_sum(s);
+    s = group_sum<G>(s);
     if (lane == 0) r[row] = (T)b[row] - s;
 }
 
+// prolongation: xt = D^{-1} b + P xc
 template <class TB, class T>
+__global__ void k_csr_prolong(int64_t n, const T *__restrict__ invd, const TB *__restrict__ b,
+                              const T *__restrict__ xc, const int32_t *__restrict__ agg, T *__restrict__ xt) {
+    int64_t row = (int64_t)xcd_block() * blockDim.x + threadIdx.x;
+    if (row >= n) return;
+    xt[row] = (T)b[row] * invd[row] + xc[agg[row]];
+}
+
+// post-smoothing: x = xt + D^{-1}(b - A xt)
+template <int G, class TB, class T>
 __global__ void k_csr_post(int64_t n, const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
                            const T *__restrict__ val, const T *__restrict__ invd, const TB *__restrict__ b,
-                           const T *__restrict__ xc, const int32_t *__restrict__ agg, T *__restrict__ x) {
-    int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+                           const T *__restrict__ xt, T *__restrict__ x) {
+    int64_t row = ((int64_t)xcd_block() * blockDim.x + threadIdx.x) / G;
     int lane = threadIdx.x % G;
     if (row >= n) return;
     T s = 0;
-    for (int64_t e = rowptr[row] + lane; e < rowptr[row + 1]; e += G) {
-        int32_t j = col[e];
-        s += val[e] * ((T)b[j] * invd[j] + xc[agg[j]]);
-    }
-    s = group_sum(s);
-    if (lane == 0) {
-        T xr = (T)b[row] * invd[row] + xc[agg[row]];
-        x[row] = xr + invd[row] * ((T)b[row] - s);
-    }
+    for (int64_t e = rowptr[row] + lane; e < rowptr[row + 1]; e += G) s += val[e] * xt[col[e]];
+    s = group_sum<G>(s);
+    if (lane == 0) x[row] = xt[row] + invd[row] * ((T)b[row] - s);
 }
 
-template <class TB, class T>
+template <int G, class TB, class T>
 __global__ void k_csr_sweep(int64_t n, const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
                             const T *__restrict__ val, const T *__restrict__ invd, const TB *__restrict__ b,
                             const T *__restrict__ xin, T *__restrict__ xout, int zero) {
-    int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+    int64_t row = ((int64_t)xcd_block() * blockDim.x + threadIdx.x) / G;
     int lane = threadIdx.x % G;
     if (row >= n) return;
     if (zero) {
@@ -301,7 +304,7 @@ __global__ void k_csr_sweep(int64_t n, const int64_t *__restrict__ rowptr, const
     }
     T s = 0;
     for (int64_t e = rowptr[row] + lane; e < rowptr[row + 1]; e += G) s += val[e] * xin[col[e]];
-    s = group_sum(s);
+    s = group_sum<G>(s);
     if (lane == 0) xout[row] = xin[row] + invd[row] * ((T)b[row] - s);
 }
 
@@ -309,7 +312,7 @@ __global__ void k_csr_sweep(int64_t n, const int64_t *__restrict__ rowptr, const
 template <class T>
 __global__ void k_restrict(int64_t nc, const int64_t *__restrict__ mptr, const int32_t *__restrict__ mem,
                            const T *__restrict__ r, T *__restrict__ bc) {
-    int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t I = (int64_t)xcd_block() * blockDim.x + threadIdx.x;
     if (I >= nc) return;
     T s = 0;
     for (int64_t t = mptr[I]; t < mptr[I + 1]; t++) s += r[mem[t]];
@@ -331,12 +334,12 @@ __global__ void k_dense_gemv(const T *__restrict__ Ainv, const TB *__restrict__ 
 
 __global__ void k_csr_spmv(int64_t n, const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
                            const double *__restrict__ val, const double *__restrict__ x, double *__restrict__ y) {
-    int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
-    int lane = threadIdx.x % G;
+    int64_t row = ((int64_t)xcd_block() * blockDim.x + threadIdx.x) / 8;
+    int lane = threadIdx.x % 8;
     if (row >= n) return;
     double s = 0;
-    for (int64_t e = rowptr[row] + lane; e < rowptr[row + 1]; e += G) s += val[e] * x[col[e]];
-    s = group_sum(s);
+    for (int64_t e = rowptr[row] + lane; e < rowptr[row + 1]; e += 8) s += val[e] * x[col[e]];
+    s = group_sum<8>(s);
     if (lane == 0) y[row] = s;
 }
 
@@ -646,10 +649,16 @@ rich_status dense_inverse(const CsrDev &A, double *D, hipStream_t s) {
     return hb ? RICH_NOT_SPD : RICH_OK;
 }
 
+// lanes per row: 4 for short rows, 8 otherwise
+static inline bool short_rows(const Level &Lv) { return Lv.nnz < 16 * Lv.n; }
+
 template <class TB, class T>
 rich_status launch_csr_pre(const Level &Lv, const T *val, const T *invd, const TB *b, T *r, hipStream_t s) {
     if (Lv.n == 0) return RICH_OK;
-    k_csr_pre<TB, T><<<nblocks(Lv.n * G), TPB, 0, s>>>(Lv.n, Lv.rowptr, Lv.col, val, invd, b, r);
+    if (short_rows(Lv))
+        k_csr_pre<4, TB, T><<<xcd_grid(Lv.n * 4, TPB), TPB, 0, s>>>(Lv.n, Lv.rowptr, Lv.col, val, invd, b, r);
+    else
+        k_csr_pre<8, TB, T><<<xcd_grid(Lv.n * 8, TPB), TPB, 0, s>>>(Lv.n, Lv.rowptr, Lv.col, val, invd, b, r);
     LAUNCH_CHECK();
     return RICH_OK;
 }
@@ -658,7 +667,13 @@ template <class TB, class T>
 rich_status launch_csr_post(const Level &Lv, const T *val, const T *invd, const TB *b, const T *xc, T *x,
                             hipStream_t s) {
     if (Lv.n == 0) return RICH_OK;
-    k_csr_post<TB, T><<<nblocks(Lv.n * G), TPB, 0, s>>>(Lv.n, Lv.rowptr, Lv.col, val, invd, b, xc, Lv.agg, x);
+    T *xt = (T *)Lv.r;  // the residual of this level is dead by now
+    k_csr_prolong<TB, T><<<xcd_grid(Lv.n, TPB), TPB, 0, s>>>(Lv.n, invd, b, xc, Lv.agg, xt);
+    LAUNCH_CHECK();
+    if (short_rows(Lv))
+        k_csr_post<4, TB, T><<<xcd_grid(Lv.n * 4, TPB), TPB, 0, s>>>(Lv.n, Lv.rowptr, Lv.col, val, invd, b, xt, x);
+    else
+        k_csr_post<8, TB, T><<<xcd_grid(Lv.n * 8, TPB), TPB, 0, s>>>(Lv.n, Lv.rowptr, Lv.col, val, invd, b, xt, x);
     LAUNCH_CHECK();
     return RICH_OK;
 }
@@ -666,7 +681,7 @@ rich_status launch_csr_post(const Level &Lv, const T *val, const T *invd, const 
 template <class T>
 rich_status launch_restrict(const Level &Lv, const T *r, T *bc, int64_t nc, hipStream_t s) {
     if (nc == 0) return RICH_OK;
-    k_restrict<T><<<nblocks(nc), TPB, 0, s>>>(nc, Lv.mptr, Lv.mem, r, bc);
+    k_restrict<T><<<xcd_grid(nc, TPB), TPB, 0, s>>>(nc, Lv.mptr, Lv.mem, r, bc);
     LAUNCH_CHECK();
     return RICH_OK;
 }
@@ -684,11 +699,12 @@ rich_status launch_csr_sweeps(const Level &Lv, const T *val, const T *invd, cons
                               hipStream_t s) {
     if (Lv.n == 0) return RICH_OK;
     T *cur = (sweeps % 2 == 1) ? x : tmp;
-    k_csr_sweep<TB, T><<<nblocks(Lv.n * G), TPB, 0, s>>>(Lv.n, Lv.rowptr, Lv.col, val, invd, b, nullptr, cur, 1);
+    unsigned g = xcd_grid(Lv.n * 8, TPB);
+    k_csr_sweep<8, TB, T><<<g, TPB, 0, s>>>(Lv.n, Lv.rowptr, Lv.col, val, invd, b, nullptr, cur, 1);
     LAUNCH_CHECK();
     for (int t = 1; t < sweeps; t++) {
         T *nxt = (cur == x) ? tmp : x;
-        k_csr_sweep<TB, T><<<nblocks(Lv.n * G), TPB, 0, s>>>(Lv.n, Lv.rowptr, Lv.col, val, invd, b, cur, nxt, 0);
+        k_csr_sweep<8, TB, T><<<g, TPB, 0, s>>>(Lv.n, Lv.rowptr, Lv.col, val, invd, b, cur, nxt, 0);
         LAUNCH_CHECK();
         cur = nxt;
     }
@@ -697,7 +713,7 @@ rich_status launch_csr_sweeps(const Level &Lv, const T *val, const T *invd, cons
 
 rich_status launch_csr_spmv(const CsrDev &A, const double *x, double *y, hipStream_t s) {
     if (A.n == 0) return RICH_OK;
-    k_csr_spmv<<<nblocks(A.n * G), TPB, 0, s>>>(A.n, A.rowptr, A.col, A.val, x, y);
+    k_csr_spmv<<<xcd_grid(A.n * 8, TPB), TPB, 0, s>>>(A.n, A.rowptr, A.col, A.val, x, y);
     LAUNCH_CHECK();
     return RICH_OK;
 }

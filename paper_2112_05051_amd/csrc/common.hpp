@@ -31,6 +31,20 @@ const char *last_error();
 
 #define LAUNCH_CHECK() HIP_TRY(hipGetLastError())
 
+// XCD-aware block order.  Workgroups are dealt round-robin over the 8 XCDs
+// (each with its own L2); this maps them so that XCD x processes one
+// contiguous range of logical blocks, keeping the +-nx and +-nx*ny stencil
+// neighbours of a row in the same L2.  The grid must be a multiple of 8.
+constexpr unsigned NXCD = 8;
+__device__ inline unsigned xcd_block() {
+    unsigned q = gridDim.x / NXCD;
+    return (blockIdx.x % NXCD) * q + blockIdx.x / NXCD;
+}
+inline unsigned xcd_grid(int64_t n, int tpb) {
+    int64_t b = (n + tpb - 1) / tpb;
+    return (unsigned)((b + NXCD - 1) / NXCD * NXCD);
+}
+
 // Problem parameters passed by value to the stencil kernels.
 struct Phys {
     int nx, ny, nz;
@@ -99,9 +113,10 @@ rich_status launch_stencil_rowcounts(const Phys &P, int64_t *rowptr_plus1, hipSt
 // fine-level V-cycle pieces (TB: type of the right-hand side, T: arithmetic)
 template <class TB, class T>
 rich_status launch_st_pre(const Phys &P, const T *M4, const T *invd, const TB *b, T *r, hipStream_t s);
+// xt (scratch, N) receives the prolongated iterate before post-smoothing
 template <class TB, class T>
 rich_status launch_st_post(const Phys &P, const T *M4, const T *invd, const TB *b, const T *xc,
-                           const int32_t *agg, T *x, hipStream_t s);
+                           const int32_t *agg, T *x, T *xt, hipStream_t s);
 template <class TB, class T>
 rich_status launch_st_sweeps(const Phys &P, const T *M4, const T *invd, const TB *b, T *x, T *tmp,
                              int sweeps, hipStream_t s);
@@ -202,6 +217,7 @@ rich_status compose_agg(int32_t *comp, const int32_t *a, int64_t n, hipStream_t 
 
 template <class TB, class T>
 rich_status launch_csr_pre(const Level &Lv, const T *val, const T *invd, const TB *b, T *r, hipStream_t s);
+// x = post-smooth(prolong(xc)); the level's r buffer holds the prolongated iterate
 template <class TB, class T>
 rich_status launch_csr_post(const Level &Lv, const T *val, const T *invd, const TB *b, const T *xc,
                             T *x, hipStream_t s);

@@ -10,7 +10,7 @@ namespace {
 
 constexpr int TPB = 256;
 
-inline unsigned nblocks(int64_t n, int tpb = TPB) { return (unsigned)((n + tpb - 1) / tpb); }
+inline unsigned nblocks(int64_t n, int tpb = TPB) { return xcd_grid(n, tpb); }
 
 struct Cell {
     int i, j, k;
@@ -123,7 +123,7 @@ __device__ inline void mean_of(int mean, int dir, double pc, const Law &Lc, doub
 }
 
 __global__ void k_theta(Phys P, uint32_t n, const double *__restrict__ p, double *__restrict__ th) {
-    uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t c = xcd_block() * blockDim.x + threadIdx.x;
     if (c >= n) return;
     th[c] = laws(P, p[c], 1.0).th;
 }
@@ -134,7 +134,7 @@ __global__ void k_theta(Phys P, uint32_t n, const double *__restrict__ p, double
 // written face by face; a no-flux face contributes nothing).
 __global__ void k_residual(Phys P, uint32_t n, const double *__restrict__ Ks, const double *__restrict__ p,
                            const double *__restrict__ th_old, double *__restrict__ F) {
-    uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t c = xcd_block() * blockDim.x + threadIdx.x;
     if (c >= n) return;
     Cell q = cell_of(P, c);
     double pc = p[c];
@@ -161,7 +161,7 @@ __global__ void k_residual(Phys P, uint32_t n, const double *__restrict__ Ks, co
 __global__ void k_assemble(Phys P, uint32_t n, const double *__restrict__ Ks, const double *__restrict__ p,
                            double *__restrict__ J7, double *__restrict__ M4, float *__restrict__ M4f,
                            double *__restrict__ invd, float *__restrict__ invdf) {
-    uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t c = xcd_block() * blockDim.x + threadIdx.x;
     if (c >= n) return;
     Cell q = cell_of(P, c);
     double pc = p[c];
@@ -250,7 +250,7 @@ __device__ inline T mstencil(const Phys &P, const Cell &q, uint32_t c, uint32_t 
 
 __global__ void k_spmv_M(Phys P, uint32_t n, const double *__restrict__ M4, const double *__restrict__ x,
                          double *__restrict__ y) {
-    uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t c = xcd_block() * blockDim.x + threadIdx.x;
     if (c >= n) return;
     Cell q = cell_of(P, c);
     y[c] = mstencil<double>(P, q, c, n, M4, [&](uint32_t t) { return x[t]; });
@@ -261,26 +261,32 @@ __global__ void k_spmv_M(Phys P, uint32_t n, const double *__restrict__ M4, cons
 template <class TB, class T>
 __global__ void k_st_pre(Phys P, uint32_t n, const T *__restrict__ M4, const T *__restrict__ invd,
                          const TB *__restrict__ b, T *__restrict__ r) {
-    uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t c = xcd_block() * blockDim.x + threadIdx.x;
     if (c >= n) return;
     Cell q = cell_of(P, c);
     T s = mstencil<T>(P, q, c, n, M4, [&](uint32_t t) { return (T)b[t] * invd[t]; });
     r[c] = (T)b[c] - s;
 }
 
-// V-cycle, fine level, prolongation and post-smoothing in one pass:
-// xt = D^{-1} b + P xc (recomputed for the neighbours), x = xt + D^{-1}(b - M xt).
+// V-cycle, fine level, prolongation: xt = D^{-1} b + P xc (the pre-smoothed
+// iterate plus the coarse correction), one streaming pass.
+template <class TB, class T>
+__global__ void k_st_prolong(uint32_t n, const T *__restrict__ invd, const TB *__restrict__ b,
+                             const T *__restrict__ xc, const int32_t *__restrict__ agg, T *__restrict__ xt) {
+    uint32_t c = xcd_block() * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    xt[c] = (T)b[c] * invd[c] + xc[agg[c]];
+}
+
+// V-cycle, fine level, post-smoothing: x = xt + D^{-1}(b - M xt).
 template <class TB, class T>
 __global__ void k_st_post(Phys P, uint32_t n, const T *__restrict__ M4, const T *__restrict__ invd,
-                          const TB *__restrict__ b, const T *__restrict__ xc, const int32_t *__restrict__ agg,
-                          T *__restrict__ x) {
-    uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+                          const TB *__restrict__ b, const T *__restrict__ xt, T *__restrict__ x) {
+    uint32_t c = xcd_block() * blockDim.x + threadIdx.x;
     if (c >= n) return;
     Cell q = cell_of(P, c);
-    auto xt = [&](uint32_t t) { return (T)b[t] * invd[t] + xc[agg[t]]; };
-    T s = mstencil<T>(P, q, c, n, M4, xt);
-    T xc0 = xt(c);
-    x[c] = xc0 + invd[c] * ((T)b[c] - s);
+    T s = mstencil<T>(P, q, c, n, M4, [&](uint32_t t) { return xt[t]; });
+    x[c] = xt[c] + invd[c] * ((T)b[c] - s);
 }
 
 // Plain l1-Jacobi sweep x_out = x_in + D^{-1}(b - M x_in) (used when the
@@ -288,7 +294,7 @@ __global__ void k_st_post(Phys P, uint32_t n, const T *__restrict__ M4, const T 
 template <class TB, class T>
 __global__ void k_st_sweep(Phys P, uint32_t n, const T *__restrict__ M4, const T *__restrict__ invd,
                            const TB *__restrict__ b, const T *__restrict__ xin, T *__restrict__ xout, int zero) {
-    uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t c = xcd_block() * blockDim.x + threadIdx.x;
     if (c >= n) return;
     if (zero) {
         xout[c] = (T)b[c] * invd[c];
@@ -300,7 +306,7 @@ __global__ void k_st_sweep(Phys P, uint32_t n, const T *__restrict__ M4, const T
 }
 
 __global__ void k_stencil_rowcounts(Phys P, uint32_t n, int64_t *__restrict__ cnt) {
-    uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t c = xcd_block() * blockDim.x + threadIdx.x;
     if (c >= n) return;
     Cell q = cell_of(P, c);
     cnt[c] = 1 + (q.i > 0) + (q.i < P.nx - 1) + (q.j > 0) + (q.j < P.ny - 1) + (q.k > 0) + (q.k < P.nz - 1);
@@ -309,7 +315,7 @@ __global__ void k_stencil_rowcounts(Phys P, uint32_t n, int64_t *__restrict__ cn
 // Stencil -> CSR with ascending columns (-z,-y,-x,c,+x,+y,+z).
 __global__ void k_M_to_csr(Phys P, uint32_t n, const double *__restrict__ M4, const int64_t *__restrict__ rowptr,
                            int32_t *__restrict__ col, double *__restrict__ val) {
-    uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t c = xcd_block() * blockDim.x + threadIdx.x;
     if (c >= n) return;
     Cell q = cell_of(P, c);
     uint32_t nx = P.nx, nxy = (uint32_t)P.nx * (uint32_t)P.ny;
@@ -325,7 +331,7 @@ __global__ void k_M_to_csr(Phys P, uint32_t n, const double *__restrict__ M4, co
 
 __global__ void k_J_to_csr(Phys P, uint32_t n, const double *__restrict__ J7, const int64_t *__restrict__ rowptr,
                            int32_t *__restrict__ col, double *__restrict__ val) {
-    uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t c = xcd_block() * blockDim.x + threadIdx.x;
     if (c >= n) return;
     Cell q = cell_of(P, c);
     uint32_t nx = P.nx, nxy = (uint32_t)P.nx * (uint32_t)P.ny;
@@ -369,7 +375,7 @@ rich_status launch_assemble(const Phys &P, const double *Ks, const double *p, do
 template <class TX>
 rich_status launch_spmv_J(const Phys &P, const double *J7, const TX *x, double *y, hipStream_t s) {
     uint32_t n = ncells(P);
-    k_spmv_J<TX><<<nblocks(n), TPB, 0, s>>>(P, n, J7, x, y);
+    k_spmv_J<TX><<<(n + TPB - 1) / TPB, TPB, 0, s>>>(P, n, J7, x, y);
     LAUNCH_CHECK();
     return RICH_OK;
 }
@@ -393,9 +399,11 @@ rich_status launch_st_pre(const Phys &P, const T *M4, const T *invd, const TB *b
 
 template <class TB, class T>
 rich_status launch_st_post(const Phys &P, const T *M4, const T *invd, const TB *b, const T *xc,
-                           const int32_t *agg, T *x, hipStream_t s) {
+                           const int32_t *agg, T *x, T *xt, hipStream_t s) {
     uint32_t n = ncells(P);
-    k_st_post<TB, T><<<nblocks(n), TPB, 0, s>>>(P, n, M4, invd, b, xc, agg, x);
+    k_st_prolong<TB, T><<<nblocks(n), TPB, 0, s>>>(n, invd, b, xc, agg, xt);
+    LAUNCH_CHECK();
+    k_st_post<TB, T><<<nblocks(n), TPB, 0, s>>>(P, n, M4, invd, b, xt, x);
     LAUNCH_CHECK();
     return RICH_OK;
 }
@@ -420,7 +428,7 @@ rich_status launch_st_sweeps(const Phys &P, const T *M4, const T *invd, const TB
 #define INST_ST(TB, T)                                                                                    \
     template rich_status launch_st_pre<TB, T>(const Phys &, const T *, const T *, const TB *, T *, hipStream_t); \
     template rich_status launch_st_post<TB, T>(const Phys &, const T *, const T *, const TB *, const T *,      \
-                                               const int32_t *, T *, hipStream_t);                              \
+                                               const int32_t *, T *, T *, hipStream_t);                         \
     template rich_status launch_st_sweeps<TB, T>(const Phys &, const T *, const T *, const TB *, T *, T *, int, \
                                                  hipStream_t);
 INST_ST(double, double)

@@ -380,14 +380,14 @@ rich_status vcycle(rich_ctx *h, const double *b, T *z) {
     // up
     for (int l = H.nlev - 2; l >= 1; l--) {
         Level &Lv = H.L[l];
-        double bytes = (double)Lv.nnz * (4 + t) + (double)Lv.n * (12 + 4 * t) + (double)H.L[l + 1].n * t;
+        double bytes = (double)Lv.nnz * (4 + t) + (double)Lv.n * (12 + 7 * t) + (double)H.L[l + 1].n * t;
         RICH_TRY(timed(h, l == 1 ? RICH_K_VC1_POST : RICH_K_COUNT, bytes, [&] {
             return launch_csr_post<T, T>(Lv, lvval<T>(Lv), lvinvd<T>(Lv), (const T *)Lv.b,
                                          (const T *)H.L[l + 1].x, (T *)Lv.x, s);
         }));
     }
-    return timed(h, RICH_K_VC0_POST, n0 * (12 + 6 * t) + n1 * t, [&] {
-        return launch_st_post<double, T>(h->P, M4, invd0, b, (const T *)H.L[1].x, H.L[0].agg, z, s);
+    return timed(h, RICH_K_VC0_POST, n0 * (20 + 9 * t) + n1 * t, [&] {
+        return launch_st_post<double, T>(h->P, M4, invd0, b, (const T *)H.L[1].x, H.L[0].agg, z, (T *)H.L[0].r, s);
     });
 }
 
