@@ -102,6 +102,83 @@ def cpu_baseline(n_sample=64):
                       f"{st['status']}), rate scaled by the cell ratio {n_sample}^3/256^3"}
 
 
+def algorithmic_bytes(name, n, mixed=True):
+    """Algorithmic HBM bytes of one launch of the fine-grid kernels at n unknowns
+    (the per-row figures of the design doc, section 7); None when not tracked."""
+    import re
+    t = 4 if mixed else 8
+    m = re.search(r"k_(multidot|update_norm)<(\d+)>", name)
+    if m:
+        k = int(m.group(2))
+        return (8 * n * (k + 1), 0) if m.group(1) == "multidot" else (8 * n * (k + 1), 8 * n)
+    if "k_spmv_J<float>" in name:
+        return (60 * n, 8 * n)
+    if "k_st_pre<double, float>" in name:
+        return (8 * n + 5 * t * n, t * n)
+    if "k_residual" in name:
+        return (24 * n, 8 * n)
+    return None
+
+
+def pmc_summary(fetch_csv, write_csv, n):
+    """Per-kernel HBM traffic from rocprofv3 FETCH_SIZE / WRITE_SIZE counter runs,
+    calibrated by the 1 GiB device copy of --calibrate-copy."""
+    import collections
+    import csv
+    vals = {}
+    for path, cname in ((fetch_csv, "FETCH_SIZE"), (write_csv, "WRITE_SIZE")):
+        d = collections.defaultdict(list)
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] == cname:
+                d[r["Kernel_Name"]].append(float(r["Counter_Value"]) * 1024.0)  # KiB -> bytes
+        vals[cname] = d
+    gib = float(1 << 30)
+    cal = {}
+    for cname in vals:
+        copies = [v for k, lst in vals[cname].items() if "copyBuffer" in k for v in lst]
+        cal[cname] = gib / max(copies) if copies else 1.0
+    lines = [f"calibration (1 GiB copy): FETCH_SIZE x{cal['FETCH_SIZE']:.4f}, WRITE_SIZE x{cal['WRITE_SIZE']:.4f}",
+             f"{'kernel':58s} {'launches':>8s} {'fetch MB':>10s} {'write MB':>10s} {'alg MB':>10s} {'traffic/alg':>11s}"]
+    rows = []
+    for k, lst in vals["FETCH_SIZE"].items():
+        w = vals["WRITE_SIZE"].get(k, [0.0])
+        f_b = cal["FETCH_SIZE"] * sum(lst) / len(lst)
+        w_b = cal["WRITE_SIZE"] * sum(w) / len(w)
+        alg = algorithmic_bytes(k, n)
+        rows.append((k, len(lst), f_b, w_b, alg))
+    rows.sort(key=lambda r: -(r[2] + r[3]) * r[1])
+    for k, cnt, f_b, w_b, alg in rows[:40]:
+        short = k.replace("rich::(anonymous namespace)::", "").replace("void ", "")[:58]
+        a = (alg[0] + alg[1]) if alg else None
+        lines.append(f"{short:58s} {cnt:8d} {f_b / 1e6:10.2f} {w_b / 1e6:10.2f} "
+                     f"{(a / 1e6 if a else float('nan')):10.2f} {((f_b + w_b) / a if a else float('nan')):11.3f}")
+    return "\n".join(lines)
+
+
+def stats_summary(stats_csv):
+    """Kernel time by kernel family from a rocprofv3 --stats kernel_stats.csv."""
+    import collections
+    import csv
+    import re
+    fam = collections.defaultdict(lambda: [0, 0.0])
+    rows = list(csv.DictReader(open(stats_csv)))
+    for r in rows:
+        name = r["Name"].replace("void ", "").replace("rich::(anonymous namespace)::", "")
+        key = re.sub(r"<.*", "", name.split("(")[0])
+        fam[key][0] += int(r["Calls"])
+        fam[key][1] += float(r["TotalDurationNs"])
+    tot = sum(v[1] for v in fam.values())
+    lines = [f"total kernel time {tot / 1e9:.3f} s", f"{'kernel family':28s} {'calls':>8s} {'total ms':>10s} {'avg us':>9s} {'share':>6s}"]
+    for k, (c, t) in sorted(fam.items(), key=lambda kv: -kv[1][1])[:25]:
+        lines.append(f"{k:28s} {c:8d} {t / 1e6:10.1f} {t / c / 1e3:9.1f} {100 * t / tot:5.1f}%")
+    lines.append("")
+    lines.append(f"{'kernel (instance)':70s} {'calls':>8s} {'avg us':>9s}")
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"]))[:20]:
+        name = r["Name"].replace("void ", "").replace("rich::(anonymous namespace)::", "")[:70]
+        lines.append(f"{name:70s} {int(r['Calls']):8d} {float(r['AverageNs']) / 1e3:9.1f}")
+    return "\n".join(lines)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -111,9 +188,23 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the all-FP64 comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-profile", action="store_true", help="no per-kernel event timing")
+    ap.add_argument("--full-newton", action="store_true",
+                    help="also time the same steps with a fresh Jacobian every Newton iteration (msbset=1)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one 1 GiB device copy first (reference for HBM traffic counters)")
     ap.add_argument("--set", action="append", default=[], metavar="OPT=VALUE",
                     help="override a solver option (experiments; the headline uses the defaults)")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="print the calibrated per-kernel traffic table of two rocprofv3 --pmc runs and exit")
+    ap.add_argument("--stats-summary", metavar="KERNEL_STATS_CSV",
+                    help="print kernel time by family from a rocprofv3 --stats run and exit")
     args = ap.parse_args()
+    if args.stats_summary:
+        print(stats_summary(args.stats_summary))
+        return
+    if args.pmc_summary:
+        print(pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.n ** 3))
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               f"(the multi-GPU decomposition is described in DESIGN.md, not implemented)", file=sys.stderr)
@@ -139,6 +230,14 @@ def main():
     ks_dev = torch.from_numpy(ks).cuda()
     p0_dev = torch.from_numpy(p0).cuda()
     torch.cuda.synchronize()
+    if args.calibrate_copy:
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log("[bench] calibration copy: 1 GiB read + 1 GiB written")
+        del a, b
 
     mixed = run_gpu(rec, rich.PREC_MIXED, args.warmup, args.steps, ks_dev, p0_dev, not args.no_profile)
     mixed["solver"].close()
@@ -146,6 +245,23 @@ def main():
     if not args.no_fp64:
         fp64 = run_gpu(rec, rich.PREC_FP64, args.warmup, args.steps, ks_dev, p0_dev, False)
         fp64["solver"].close()
+
+    full = None
+    if args.full_newton:
+        import copy
+        rec_full = copy.deepcopy(rec)
+        rec_full.options.msbset = 1
+        full = {}
+        for name, prec in (("mixed", rich.PREC_MIXED), ("fp64", rich.PREC_FP64)):
+            r = run_gpu(rec_full, prec, args.warmup, args.steps, ks_dev, p0_dev, False)
+            r["solver"].close()
+            full[name] = {"value": args.steps / r["t_timed"], "ms_per_step": 1e3 * r["t_timed"] / max(args.steps, 1),
+                          "p50_step_ms": 1e3 * percentile(r["per_step"], 50),
+                          "p99_step_ms": 1e3 * percentile(r["per_step"], 99),
+                          "newton_its": sum(x["newton_its"] for x in r["stats"]),
+                          "gmres_its": sum(x["gmres_its"] for x in r["stats"]),
+                          "jac_builds": sum(x["jac_builds"] for x in r["stats"])}
+        full["mixed_over_fp64"] = full["mixed"]["value"] / full["fp64"]["value"]
 
     steps = args.steps
     value = steps / mixed["t_timed"] if steps else 0.0
@@ -190,6 +306,9 @@ def main():
         out["mixed_over_fp64"] = out["value"] / out["fp64"]["value"]
         a, b = mixed["p_final"].cpu().numpy(), fp64["p_final"].cpu().numpy()
         out["mixed_vs_fp64_rel_l2"] = float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+    if full is not None:
+        out["full_newton_msbset1"] = full
 
     # Property that holds at any size: the oracle's residual at the GPU's final
     # state (with the GPU's previous state as theta_old) is below the tolerance.

@@ -196,15 +196,41 @@ __global__ void k_sym_write(int64_t nc, const int64_t *__restrict__ segptr, cons
 
 // Numeric product on a fixed pattern: members ascending, each fine row in
 // column order, every term added to its coarse entry in that order (the
-// oracle's order), starting from zero.
-__global__ void k_gal_numeric(int64_t nc, const int64_t *__restrict__ mptr, const int32_t *__restrict__ mem,
-                              const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
-                              const double *__restrict__ val, const int32_t *__restrict__ agg,
-                              const int64_t *__restrict__ crow, const int32_t *__restrict__ ccol,
-                              double *__restrict__ cval) {
+// oracle's order), starting from zero.  Rows of up to GAL_REG entries are
+// accumulated in registers; longer rows directly in the output.
+constexpr int GAL_REG = 48;
+__global__ void __launch_bounds__(64) k_gal_numeric(int64_t nc, const int64_t *__restrict__ mptr,
+                                                    const int32_t *__restrict__ mem, const int64_t *__restrict__ rowptr,
+                                                    const int32_t *__restrict__ col, const double *__restrict__ val,
+                                                    const int32_t *__restrict__ agg, const int64_t *__restrict__ crow,
+                                                    const int32_t *__restrict__ ccol, double *__restrict__ cval) {
     int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (I >= nc) return;
     int64_t a = crow[I], b = crow[I + 1];
+    int len = (int)(b - a);
+    if (len <= GAL_REG) {
+        int32_t cj[GAL_REG];
+        double acc[GAL_REG];
+        for (int e = 0; e < len; e++) {
+            cj[e] = ccol[a + e];
+            acc[e] = 0.0;
+        }
+        for (int64_t t = mptr[I]; t < mptr[I + 1]; t++) {
+            int32_t i = mem[t];
+            for (int64_t e = rowptr[i]; e < rowptr[i + 1]; e++) {
+                int32_t J = agg[col[e]];
+                int lo = 0, hi = len - 1;
+                while (lo < hi) {
+                    int mid = (lo + hi) >> 1;
+                    if (cj[mid] < J) lo = mid + 1;
+                    else hi = mid;
+                }
+                acc[lo] += val[e];
+            }
+        }
+        for (int e = 0; e < len; e++) cval[a + e] = acc[e];
+        return;
+    }
     for (int64_t e = a; e < b; e++) cval[e] = 0.0;
     for (int64_t t = mptr[I]; t < mptr[I + 1]; t++) {
         int32_t i = mem[t];
@@ -360,7 +386,7 @@ __global__ void k_csr_to_dense(int64_t n, const int64_t *__restrict__ rowptr, co
 constexpr int GJB = 64;  // pivot block
 
 // P^{-1} by scalar Gauss-Jordan in LDS (one workgroup, b <= 64).
-__global__ void __launch_bounds__(256) k_bgj_pivot(const double *__restrict__ D, int64_t n, int64_t k0, int b,
+__global__ void __launch_bounds__(1024) k_bgj_pivot(const double *__restrict__ D, int64_t n, int64_t k0, int b,
                                                     double *__restrict__ Pinv, int *__restrict__ bad) {
     __shared__ double A[GJB][GJB + 1];
     __shared__ double rowk[GJB], colk[GJB];
@@ -396,23 +422,29 @@ __global__ void __launch_bounds__(256) k_bgj_pivot(const double *__restrict__ D,
     }
 }
 
-// R (b x n) and S (n x b, old column block).
-__global__ void k_bgj_panels(const double *__restrict__ D, int64_t n, int64_t k0, int b,
-                             const double *__restrict__ Pinv, double *__restrict__ R, double *__restrict__ S) {
+// R (b x n): one thread per entry, blockIdx.y = row r of the pivot block.
+__global__ void k_bgj_panel_R(const double *__restrict__ D, int64_t n, int64_t k0, int b,
+                              const double *__restrict__ Pinv, double *__restrict__ R) {
     int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n) return;
-    bool inK = j >= k0 && j < k0 + b;
-    for (int r = 0; r < b; r++) {
-        double v;
-        if (inK) {
-            v = Pinv[r * GJB + (j - k0)];
-        } else {
-            v = 0.0;
-            for (int t = 0; t < b; t++) v += Pinv[r * GJB + t] * D[(k0 + t) * n + j];
-        }
-        R[(int64_t)r * n + j] = v;
+    int r = blockIdx.y;
+    if (j >= n || r >= b) return;
+    double v;
+    if (j >= k0 && j < k0 + b) {
+        v = Pinv[r * GJB + (j - k0)];
+    } else {
+        v = 0.0;
+        for (int t = 0; t < b; t++) v += Pinv[r * GJB + t] * D[(k0 + t) * n + j];
     }
-    for (int t = 0; t < b; t++) S[j * GJB + t] = D[j * n + k0 + t];
+    R[(int64_t)r * n + j] = v;
+}
+
+// S (n x GJB): the old column block, one thread per entry.
+__global__ void k_bgj_panel_S(const double *__restrict__ D, int64_t n, int64_t k0, int b, double *__restrict__ S) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * GJB) return;
+    int64_t j = t / GJB;
+    int c = (int)(t - j * GJB);
+    if (c < b) S[t] = D[j * n + k0 + c];
 }
 
 // Rank-b update on 64x64 tiles, 4x4 outputs per thread, operands in LDS.
@@ -638,8 +670,9 @@ rich_status dense_inverse(const CsrDev &A, double *D, hipStream_t s) {
     unsigned tiles = (unsigned)((n + GJB - 1) / GJB);
     for (int64_t k0 = 0; k0 < n; k0 += GJB) {
         int b = (int)std::min<int64_t>(GJB, n - k0);
-        k_bgj_pivot<<<1, 256, 0, s>>>(D, n, k0, b, Pinv, bad);
-        k_bgj_panels<<<nblocks(n), TPB, 0, s>>>(D, n, k0, b, Pinv, R, S);
+        k_bgj_pivot<<<1, 1024, 0, s>>>(D, n, k0, b, Pinv, bad);
+        k_bgj_panel_R<<<dim3(nblocks(n), b), TPB, 0, s>>>(D, n, k0, b, Pinv, R);
+        k_bgj_panel_S<<<nblocks(n * GJB), TPB, 0, s>>>(D, n, k0, b, S);
         k_bgj_update<<<dim3(tiles, tiles), 256, 0, s>>>(D, n, k0, b, R, S);
     }
     LAUNCH_CHECK();
