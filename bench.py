@@ -179,6 +179,60 @@ def stats_summary(stats_csv):
     return "\n".join(lines)
 
 
+def run_serving(args):
+    """Ensemble serving: the seeded Poisson request stream (cubic grids of
+    32..96 cells, their own log-normal K_s, random interface mean, mixed
+    precision) submitted at its arrival times to a rich_server; reports
+    aggregate steps/s, p50/p99 per-step latency and admission waits."""
+    import numpy as np
+
+    import paper_2112_05051_amd as rich
+    import synth
+    reqs = synth.serving_stream(count=args.serve_count, rate=args.serve_rate, nsteps=args.serve_steps)
+    log(f"[serve] generating {len(reqs)} request fields")
+    inputs = [(t, rec, rec.ks(), rec.p0()) for t, rec in reqs]
+    srv = rich.Server(int(args.serve_budget_gb * (1 << 30)), args.serve_active)
+    ids = []
+    t0 = time.perf_counter()
+    for t_arr, rec, ks, p0 in inputs:
+        now = time.perf_counter() - t0
+        if t_arr > now:
+            time.sleep(t_arr - now)
+        ids.append(srv.submit(rec.problem, rec.options, ks, p0, rec.nsteps))
+    log(f"[serve] all {len(ids)} submitted after {time.perf_counter() - t0:.1f}s")
+    done = {}
+    while len(done) < len(ids):
+        for i in ids:
+            if i not in done:
+                r = srv.poll(i)
+                if r is not None:
+                    done[i] = r
+                    log(f"[serve] request {i} done: status {r['status']} steps {len(r['step_ms'])} "
+                        f"wait {r['wait_s']:.2f}s run {r['run_s']:.2f}s ({len(done)}/{len(ids)})")
+        time.sleep(0.05)
+    makespan = time.perf_counter() - t0
+    srv.close()
+    step_ms = np.concatenate([d["step_ms"] for d in done.values()])
+    waits = np.array([d["wait_s"] for d in done.values()])
+    total_steps = int(sum(len(d["step_ms"]) for d in done.values()))
+    by_mean = {}
+    for (t_arr, rec, _, _), i in zip(inputs, ids):
+        m = ["arith", "upstream", "harmonic"][rec.problem.mean]
+        by_mean.setdefault(m, []).append(done[i]["status"])
+    return {
+        "metric": "ensemble serving: aggregate time-steps/s, p50/p99 per-step ms",
+        "value": total_steps / makespan, "unit": "time-steps/s", "n_gpus": 1,
+        "requests": len(ids), "steps_per_request": args.serve_steps, "arrival_rate_per_s": args.serve_rate,
+        "max_active": args.serve_active, "budget_gb": args.serve_budget_gb, "makespan_s": makespan,
+        "total_steps": total_steps, "p50_step_ms": float(np.percentile(step_ms, 50)),
+        "p99_step_ms": float(np.percentile(step_ms, 99)), "admission_wait_p50_s": float(np.percentile(waits, 50)),
+        "admission_wait_p99_s": float(np.percentile(waits, 99)),
+        "status_by_mean": {k: {str(s): v.count(s) for s in sorted(set(v))} for k, v in by_mean.items()},
+        "dtype": "f64 (Newton, GMRES) + f32 (AMG V-cycle)", "data": "synthetic",
+        "config": {"workload": "c4_ensemble_poisson", "sizes": [32, 48, 64, 80, 96]},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -196,6 +250,12 @@ def main():
                     help="override a solver option (experiments; the headline uses the defaults)")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="print the calibrated per-kernel traffic table of two rocprofv3 --pmc runs and exit")
+    ap.add_argument("--serving", action="store_true", help="run the ensemble serving benchmark instead")
+    ap.add_argument("--serve-count", type=int, default=64)
+    ap.add_argument("--serve-steps", type=int, default=20)
+    ap.add_argument("--serve-rate", type=float, default=4.0)
+    ap.add_argument("--serve-active", type=int, default=4)
+    ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     ap.add_argument("--stats-summary", metavar="KERNEL_STATS_CSV",
                     help="print kernel time by family from a rocprofv3 --stats run and exit")
     args = ap.parse_args()
@@ -219,6 +279,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     rich.load()
+    if args.serving:
+        print(json.dumps(run_serving(args)), flush=True)
+        return
     rec = synth.recipe("c3", n=args.n)
     for kv in args.set:
         k, v = kv.split("=")

@@ -98,6 +98,9 @@ typedef struct rich_solver_opts {
     int precision;       /* RICH_PREC_* */
     double gmres_reorth; /* second Gram-Schmidt pass when ||w_after|| < gmres_reorth ||w_before||
                             (0 = never, 0.7071 = always-safe DGKS rule) */
+    int aux_dflux;       /* 1: the auxiliary matrix's diagonal also takes the flux-derivative
+                            terms -(p_n-p_c)/h^2 dK^AV/dp_c of the diffusion Jacobian (off-diagonal
+                            ones dropped: M stays symmetric); 0: frozen conductivity only */
     int amg_refresh;     /* on every rebuild after the first: 0 = refresh the fine level and its
                             smoother only (coarse matrices frozen, Section 6); 1 = also recompute
                             every coarse matrix from the new fine one, aggregates kept */
@@ -208,6 +211,37 @@ rich_status rich_profile(rich_handle_t h, int enable);
  * one kernel since profiling was enabled (waits for the stream). */
 rich_status rich_profile_read(rich_handle_t h, int kernel, int64_t *launches_host, double *ms_host,
                               double *bytes_host);
+
+/* ------------------------------------------------------------- serving -- */
+/* Ensemble serving (an addition to the paper's method): independent
+ * simulations, each with its own grid, K_s field, interface mean and step
+ * count, submitted at any time.  Requests wait in a FIFO queue and are
+ * admitted when one of `max_active` workers is free and their device-memory
+ * plan (rich_query_bytes plus K_s/p staging) fits the remaining budget; an
+ * admitted simulation stays resident on the GPU for all its steps and runs
+ * on its own HIP stream, so concurrent simulations overlap on the device.
+ * A simulation's result equals that of a lone rich_create/rich_step run.
+ * The server uses the device that is current when it is created. */
+typedef struct rich_server *rich_server_t;
+#define RICH_REQ_QUEUED 0
+#define RICH_REQ_RUNNING 1
+#define RICH_REQ_DONE 2
+rich_status rich_server_create(size_t hbm_budget_bytes, int max_active, rich_server_t *out);
+/* Ks_host, p0_host: N host values each, copied.  RICH_EBUDGET if the request
+ * alone exceeds the budget.  *req_id receives the request's id. */
+rich_status rich_server_submit(rich_server_t s, const rich_problem_t *prob, const rich_solver_opts_t *opts,
+                               const double *Ks_host, const double *p0_host, int nsteps, int64_t *req_id);
+/* *state: RICH_REQ_*.  Once done: *result is the simulation's status, p_host
+ * (N values) its final state, stats_host / step_ms_host (nsteps entries) the
+ * per-step counters and wall milliseconds, times_host (3 values) the
+ * admission wait [s], the resident time [s] and the number of steps run.
+ * Every output pointer may be NULL. */
+rich_status rich_server_poll(rich_server_t s, int64_t req_id, int *state, rich_status *result, double *p_host,
+                             rich_step_stats_t *stats_host, double *step_ms_host, double *times_host);
+/* Block until no request is queued or running. */
+rich_status rich_server_wait_idle(rich_server_t s);
+/* Let running simulations finish, drop queued ones, release the server. */
+rich_status rich_server_destroy(rich_server_t s);
 
 #ifdef __cplusplus
 }

@@ -185,7 +185,10 @@ int64_t orc_pattern_nnz(const orc_problem *P)
 static const int ORDER_LO[3] = {4, 2, 0}; /* -z, -y, -x */
 static const int ORDER_HI[3] = {1, 3, 5}; /* +x, +y, +z */
 
-/* which = 0: Jacobian of the residual; which = 1: auxiliary matrix. */
+/* which = 0: Jacobian of the residual; which = 1: auxiliary matrix; which =  */
+/* 2: auxiliary matrix whose diagonal also takes the flux-derivative terms   */
+/* -(p_n - p_c)/h^2 dK^AV/dp_c of the diffusion operator's Jacobian (the     */
+/* off-diagonal ones are left out so the matrix stays symmetric).           */
 static void assemble(const orc_problem *P, const double *Ks, const double *p, int which,
                      int64_t *rowptr, int32_t *col, double *val)
 {
@@ -224,6 +227,7 @@ static void assemble(const orc_problem *P, const double *Ks, const double *p, in
                         /* Section 4 / 5.2: Jacobian of the diffusion-only operator with the
                          * conductivity frozen (q_prec = -K grad p), plus the time term. */
                         diag += Kf / h2;
+                        if (which == 2) diag += -dp / h2 * dc;
                         if (fc.interior) {
                             off[f] = -Kf / h2;
                             nb[f] = fc.n;
@@ -257,6 +261,12 @@ void orc_auxiliary(const orc_problem *P, const double *Ks, const double *p, int6
                    int32_t *col, double *val)
 {
     assemble(P, Ks, p, 1, rowptr, col, val);
+}
+
+void orc_auxiliary_dflux(const orc_problem *P, const double *Ks, const double *p, int64_t *rowptr,
+                         int32_t *col, double *val)
+{
+    assemble(P, Ks, p, 2, rowptr, col, val);
 }
 
 void orc_csr_matvec(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
@@ -891,7 +901,8 @@ void orc_solver_destroy(orc_solver *S)
 static int rebuild(orc_solver *S, const double *u, orc_stats *st)
 {
     orc_jacobian(&S->P, S->Ks, u, S->J.rowptr, S->J.col, S->J.val);
-    orc_auxiliary(&S->P, S->Ks, u, S->M.rowptr, S->M.col, S->M.val);
+    if (S->O.aux_dflux) orc_auxiliary_dflux(&S->P, S->Ks, u, S->M.rowptr, S->M.col, S->M.val);
+    else orc_auxiliary(&S->P, S->Ks, u, S->M.rowptr, S->M.col, S->M.val);
     int rc = ORC_OK;
     if (!S->H) {
         rc = orc_amg_build(&S->O, S->N, S->M.rowptr, S->M.col, S->M.val, &S->H);

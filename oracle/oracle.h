@@ -59,6 +59,7 @@ typedef struct {
     int64_t coarse_dense_max;
     int coarse_l1_sweeps;
     int amg_refresh; /* 0: later rebuilds refresh the smoother only; 1: also the coarse matrices */
+    int aux_dflux;   /* 1: the auxiliary matrix's diagonal also takes the flux-derivative terms */
 } orc_opts;
 
 typedef struct {
@@ -89,6 +90,8 @@ void orc_jacobian(const orc_problem *P, const double *Ks, const double *p, int64
                   int32_t *col, double *val);
 void orc_auxiliary(const orc_problem *P, const double *Ks, const double *p, int64_t *rowptr,
                    int32_t *col, double *val);
+void orc_auxiliary_dflux(const orc_problem *P, const double *Ks, const double *p, int64_t *rowptr,
+                         int32_t *col, double *val);
 void orc_csr_matvec(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
                     const double *x, double *y);
 

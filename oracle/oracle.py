@@ -46,7 +46,8 @@ class COpts(C.Structure):
                 ("gmres_restart", C.c_int), ("eta", C.c_double), ("gmres_maxit", C.c_int),
                 ("amg_max_levels", C.c_int), ("amg_coarse_size", C.c_int64),
                 ("amg_sweeps", C.c_int), ("coarse_dense_max", C.c_int64),
-                ("coarse_l1_sweeps", C.c_int), ("amg_refresh", C.c_int)]
+                ("coarse_l1_sweeps", C.c_int), ("amg_refresh", C.c_int),
+                ("aux_dflux", C.c_int)]
 
 
 class CStats(C.Structure):
@@ -74,6 +75,7 @@ def lib():
         L.orc_pattern_nnz.restype = C.c_int64
         L.orc_jacobian.argtypes = [P(CProblem), d, d, i64, i32, d]
         L.orc_auxiliary.argtypes = [P(CProblem), d, d, i64, i32, d]
+        L.orc_auxiliary_dflux.argtypes = [P(CProblem), d, d, i64, i32, d]
         L.orc_csr_matvec.argtypes = [C.c_int64, i64, i32, d, d, d]
         L.orc_match_sweep.argtypes = [C.c_int64, i64, i32, d, i32]
         L.orc_match_sweep.restype = C.c_int64
@@ -176,9 +178,10 @@ def jacobian(P, Ks, p):
     return _assemble(lib().orc_jacobian, P, Ks, p)
 
 
-def auxiliary(P, Ks, p):
-    """Diffusion-only preconditioner matrix (symmetric M-matrix) as scipy CSR."""
-    return _assemble(lib().orc_auxiliary, P, Ks, p)
+def auxiliary(P, Ks, p, dflux=False):
+    """Diffusion-only preconditioner matrix (symmetric M-matrix) as scipy CSR;
+    dflux adds the flux-derivative terms of the diffusion Jacobian to its diagonal."""
+    return _assemble(lib().orc_auxiliary_dflux if dflux else lib().orc_auxiliary, P, Ks, p)
 
 
 def _csr_parts(A):

@@ -46,7 +46,7 @@ class Opts(C.Structure):
                 ("amg_max_levels", C.c_int), ("amg_coarse_size", C.c_int64),
                 ("amg_sweeps", C.c_int), ("coarse_dense_max", C.c_int64),
                 ("coarse_l1_sweeps", C.c_int), ("precision", C.c_int), ("gmres_reorth", C.c_double),
-                ("amg_refresh", C.c_int)]
+                ("aux_dflux", C.c_int), ("amg_refresh", C.c_int)]
 
 
 class StepStats(C.Structure):
@@ -63,7 +63,9 @@ EXPORTS = ["rich_query_bytes", "rich_create", "rich_destroy", "rich_set_state", 
            "rich_step", "rich_status_string", "rich_eval_theta", "rich_eval_residual",
            "rich_assemble", "rich_setup_hierarchy", "rich_apply_jacobian", "rich_apply_aux",
            "rich_apply_prec", "rich_gmres", "rich_levels", "rich_level_size", "rich_export_csr",
-           "rich_export_aggregates", "rich_match_sweep", "rich_profile", "rich_profile_read"]
+           "rich_export_aggregates", "rich_match_sweep", "rich_profile", "rich_profile_read",
+           "rich_server_create", "rich_server_submit", "rich_server_poll", "rich_server_wait_idle",
+           "rich_server_destroy"]
 
 KERNELS = ["spmv_J", "vc0_pre", "vc0_post", "vc0_restrict", "vc1_pre", "vc1_post", "multidot", "update",
            "residual"]
@@ -105,6 +107,11 @@ def load(path: str = LIB_PATH):
     L.rich_match_sweep.argtypes = [C.c_int64, vp, vp, vp, vp, i64p, vp]
     L.rich_profile.argtypes = [vp, C.c_int]
     L.rich_profile_read.argtypes = [vp, C.c_int, i64p, dp, dp]
+    L.rich_server_create.argtypes = [C.c_size_t, C.c_int, P(vp)]
+    L.rich_server_submit.argtypes = [vp, P(Problem), P(Opts), dp, dp, C.c_int, i64p]
+    L.rich_server_poll.argtypes = [vp, C.c_int64, P(C.c_int), P(C.c_int), dp, P(StepStats), dp, dp]
+    L.rich_server_wait_idle.argtypes = [vp]
+    L.rich_server_destroy.argtypes = [vp]
     for name in EXPORTS:
         getattr(L, name).restype = C.c_int if name != "rich_status_string" else C.c_char_p
     _lib = L
@@ -313,3 +320,62 @@ def match_sweep(rowptr, col, val, stream=None):
     _check(L.rich_match_sweep(n, _ptr(rowptr, torch.int64), _ptr(col, torch.int32), _ptr(val, torch.float64),
                               _ptr(agg), C.byref(nc), C.c_void_p(s.cuda_stream)), "rich_match_sweep")
     return agg[:n], nc.value
+
+
+REQ_QUEUED, REQ_RUNNING, REQ_DONE = 0, 1, 2
+
+
+class Server:
+    """Ensemble server (rich_server_t): FIFO admission by device-memory budget,
+    resident simulations on concurrent streams.  Inputs/outputs are host arrays."""
+
+    def __init__(self, hbm_budget_bytes: int, max_active: int = 4):
+        L = load()
+        self._L = L
+        self._s = C.c_void_p()
+        self._n = {}
+        self._steps = {}
+        _check(L.rich_server_create(hbm_budget_bytes, max_active, C.byref(self._s)), "rich_server_create")
+
+    def submit(self, problem, options, ks, p0, nsteps: int) -> int:
+        ks = np.ascontiguousarray(ks, dtype=np.float64)
+        p0 = np.ascontiguousarray(p0, dtype=np.float64)
+        rid = C.c_int64()
+        cp, co = make_problem(problem), make_opts(options)
+        _check(self._L.rich_server_submit(self._s, C.byref(cp), C.byref(co), ks.ctypes.data_as(C.POINTER(C.c_double)),
+                                          p0.ctypes.data_as(C.POINTER(C.c_double)), nsteps, C.byref(rid)),
+               "rich_server_submit")
+        self._n[rid.value] = p0.size
+        self._steps[rid.value] = nsteps
+        return rid.value
+
+    def poll(self, rid: int):
+        """None while queued/running; else a dict with the result."""
+        st, res = C.c_int(), C.c_int()
+        n, k = self._n[rid], max(1, self._steps[rid])
+        p = np.empty(n)
+        stats = (StepStats * k)()
+        ms = np.empty(k)
+        times = np.empty(3)
+        _check(self._L.rich_server_poll(self._s, rid, C.byref(st), C.byref(res), p.ctypes.data_as(C.POINTER(C.c_double)),
+                                        stats, ms.ctypes.data_as(C.POINTER(C.c_double)),
+                                        times.ctypes.data_as(C.POINTER(C.c_double))), "rich_server_poll")
+        if st.value != REQ_DONE:
+            return None
+        nrun = int(times[2])
+        return {"status": res.value, "p": p, "stats": [stats_dict(stats[i]) for i in range(nrun)],
+                "step_ms": ms[:nrun].copy(), "wait_s": float(times[0]), "run_s": float(times[1])}
+
+    def wait_idle(self):
+        _check(self._L.rich_server_wait_idle(self._s), "rich_server_wait_idle")
+
+    def close(self):
+        if getattr(self, "_s", None) is not None and self._s.value:
+            self._L.rich_server_destroy(self._s)
+            self._s = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

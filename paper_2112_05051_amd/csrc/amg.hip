@@ -652,17 +652,15 @@ rich_status compose_agg(int32_t *comp, const int32_t *a, int64_t n, hipStream_t 
     return RICH_OK;
 }
 
-// Inverse of an SPD CSR matrix into a dense row-major n x n buffer.
-rich_status dense_inverse(const CsrDev &A, double *D, hipStream_t s) {
+// Inverse of an SPD CSR matrix into a dense row-major n x n buffer, using
+// the workspace of dense_inverse_ws (no allocation: it runs on every refresh).
+int64_t dense_inverse_ws(int64_t n) { return (int64_t)GJB * GJB + 2 * (int64_t)GJB * n + 1; }
+
+rich_status dense_inverse(const CsrDev &A, double *D, double *ws, hipStream_t s) {
     int64_t n = A.n;
     if (n == 0) return RICH_OK;
-    DevAlloc tmp;
-    double *Pinv, *R, *S;
-    int *bad;
-    RICH_TRY(tmp.get(&Pinv, GJB * GJB));
-    RICH_TRY(tmp.get(&R, GJB * n));
-    RICH_TRY(tmp.get(&S, n * GJB));
-    RICH_TRY(tmp.get(&bad, 1));
+    double *Pinv = ws, *R = ws + GJB * GJB, *S = R + (int64_t)GJB * n;
+    int *bad = reinterpret_cast<int *>(S + (int64_t)GJB * n);
     HIP_TRY(hipMemsetAsync(bad, 0, sizeof(int), s));
     HIP_TRY(hipMemsetAsync(D, 0, (size_t)n * n * sizeof(double), s));
     k_csr_to_dense<<<nblocks(n), TPB, 0, s>>>(n, A.rowptr, A.col, A.val, D);

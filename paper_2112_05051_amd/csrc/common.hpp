@@ -100,7 +100,7 @@ rich_status launch_residual(const Phys &P, const double *Ks, const double *p, co
 // Assemble J (7N) and M (4N, FP64) plus M's FP32 copy (may be null) and the
 // l1 inverse diagonal of M in FP64 and FP32 (either may be null).
 rich_status launch_assemble(const Phys &P, const double *Ks, const double *p, double *J7, double *M4,
-                            float *M4f, double *invd, float *invdf, hipStream_t s);
+                            float *M4f, double *invd, float *invdf, int dflux, hipStream_t s);
 template <class TX>
 rich_status launch_spmv_J(const Phys &P, const double *J7, const TX *x, double *y, hipStream_t s);
 rich_status launch_spmv_M(const Phys &P, const double *M4, const double *x, double *y, hipStream_t s);
@@ -187,6 +187,7 @@ struct Hierarchy {
     bool dense = false;          // coarsest solved by dense inverse
     double *cinv = nullptr;      // n_c x n_c inverse (row-major), FP64
     float *cinvf = nullptr;
+    double *cws = nullptr;       // workspace of the inverse (kept: refreshes must not allocate)
     int64_t nnz_total = 0;
     DevAlloc mem;
 };
@@ -211,8 +212,10 @@ rich_status galerkin_numeric(const CsrDev &A, const int32_t *agg, const int64_t 
 rich_status members(const int32_t *agg, int64_t n, int64_t nc, int64_t *mptr, int32_t *mem,
                     hipStream_t s);
 rich_status csr_invd(const CsrDev &A, double *invd, float *invdf, hipStream_t s);
-// dense row-major inverse of an SPD CSR matrix (Gauss-Jordan; RICH_NOT_SPD on a non-positive pivot)
-rich_status dense_inverse(const CsrDev &A, double *D, hipStream_t s);
+// dense row-major inverse of an SPD CSR matrix (blocked Gauss-Jordan; RICH_NOT_SPD on a
+// non-positive pivot); ws holds dense_inverse_ws(n) doubles
+int64_t dense_inverse_ws(int64_t n);
+rich_status dense_inverse(const CsrDev &A, double *D, double *ws, hipStream_t s);
 rich_status compose_agg(int32_t *comp, const int32_t *a, int64_t n, hipStream_t s);
 
 template <class TB, class T>

@@ -157,10 +157,12 @@ __global__ void k_residual(Phys P, uint32_t n, const double *__restrict__ Ks, co
 // Jacobian rows (analytic derivatives of the residual above) and the
 // auxiliary matrix of Section 4's closing construction: the Jacobian of the
 // diffusion-only flux q = -K grad p with the conductivity frozen, plus the
-// time term.  Also the l1 row sums of M (diag + sum |off|) as inverses.
+// time term; with dflux its diagonal also takes the flux-derivative terms
+// -(p_n - p_c)/h^2 dK^AV/dp_c (off-diagonal ones dropped, M stays
+// symmetric).  Also the l1 row sums of M (diag + sum |off|) as inverses.
 __global__ void k_assemble(Phys P, uint32_t n, const double *__restrict__ Ks, const double *__restrict__ p,
                            double *__restrict__ J7, double *__restrict__ M4, float *__restrict__ M4f,
-                           double *__restrict__ invd, float *__restrict__ invdf) {
+                           double *__restrict__ invd, float *__restrict__ invdf, int dflux) {
     uint32_t c = xcd_block() * blockDim.x + threadIdx.x;
     if (c >= n) return;
     Cell q = cell_of(P, c);
@@ -184,6 +186,7 @@ __global__ void k_assemble(Phys P, uint32_t n, const double *__restrict__ Ks, co
         jd += Kf / h2 - dp / h2 * dc;
         if (zf) jd += -dir * Lc.dK / (2.0 * P.hz);
         md += Kf / h2;
+        if (dflux) md += -dp / h2 * dc;
         if (fc.kind == 1) {
             double v = -Kf / h2 - dp / h2 * dn;
             if (zf) v += -dir * Ln.dK / (2.0 * P.hz);
@@ -365,9 +368,9 @@ rich_status launch_residual(const Phys &P, const double *Ks, const double *p, co
 }
 
 rich_status launch_assemble(const Phys &P, const double *Ks, const double *p, double *J7, double *M4,
-                            float *M4f, double *invd, float *invdf, hipStream_t s) {
+                            float *M4f, double *invd, float *invdf, int dflux, hipStream_t s) {
     uint32_t n = ncells(P);
-    k_assemble<<<nblocks(n), TPB, 0, s>>>(P, n, Ks, p, J7, M4, M4f, invd, invdf);
+    k_assemble<<<nblocks(n), TPB, 0, s>>>(P, n, Ks, p, J7, M4, M4f, invd, invdf, dflux);
     LAUNCH_CHECK();
     return RICH_OK;
 }

@@ -286,8 +286,9 @@ rich_status build_hierarchy(rich_ctx *h) {
     H.dense = Lc.n <= h->O.coarse_dense_max;
     if (H.dense) {
         RICH_TRY(H.mem.get(&H.cinv, Lc.n * Lc.n));
+        RICH_TRY(H.mem.get(&H.cws, dense_inverse_ws(Lc.n)));
         CsrDev A{Lc.n, Lc.nnz, Lc.rowptr, Lc.col, Lc.val};
-        RICH_TRY(dense_inverse(A, H.cinv, s));
+        RICH_TRY(dense_inverse(A, H.cinv, H.cws, s));
         if (h->mixed) {
             RICH_TRY(H.mem.get(&H.cinvf, Lc.n * Lc.n));
             RICH_TRY(launch_cast(H.cinv, H.cinvf, Lc.n * Lc.n, s));
@@ -321,7 +322,7 @@ rich_status refresh_hierarchy(rich_ctx *h) {
     if (H.dense) {
         Level &Lc = H.L[H.nlev - 1];
         CsrDev A{Lc.n, Lc.nnz, Lc.rowptr, Lc.col, Lc.val};
-        RICH_TRY(dense_inverse(A, H.cinv, s));
+        RICH_TRY(dense_inverse(A, H.cinv, H.cws, s));
         if (h->mixed) RICH_TRY(launch_cast(H.cinv, H.cinvf, Lc.n * Lc.n, s));
     }
     return sync(h);
@@ -540,7 +541,7 @@ rich_status feval(rich_ctx *h, const double *u, double *F) {
 rich_status rebuild(rich_ctx *h, const double *u) {
     double t0 = now_s();
     RICH_TRY(launch_assemble(h->P, h->Ks, u, h->J7, h->M4, h->mixed ? h->M4f : nullptr, h->invd0,
-                             h->mixed ? h->invd0f : nullptr, h->s));
+                             h->mixed ? h->invd0f : nullptr, h->O.aux_dflux, h->s));
     RICH_TRY(sync(h));
     double t1 = now_s();
     if (h->cur) {
@@ -799,6 +800,7 @@ rich_status validate(const rich_problem_t *P, const rich_solver_opts_t *O) {
     if (O->coarse_dense_max < 0 || O->coarse_dense_max > 8192 || O->coarse_l1_sweeps < 1) return RICH_EINVAL;
     if (O->precision != RICH_PREC_FP64 && O->precision != RICH_PREC_MIXED) return RICH_EINVAL;
     if (O->amg_refresh != 0 && O->amg_refresh != 1) return RICH_EINVAL;
+    if (O->aux_dflux != 0 && O->aux_dflux != 1) return RICH_EINVAL;
     if (!(O->gmres_reorth >= 0.0 && O->gmres_reorth < 1.0)) return RICH_EINVAL;
     if (!(O->eta > 0) || !(O->fnormtol > 0) || O->max_newton < 1 || O->msbset < 1) return RICH_EINVAL;
     return RICH_OK;

@@ -73,6 +73,7 @@ class Options:
     amg_refresh: int = 1               # 1: every rebuild recomputes the coarse matrices (aggregates kept)
     precision: int = FP64
     gmres_reorth: float = 0.01          # second Gram-Schmidt pass only on severe cancellation
+    aux_dflux: int = 0                  # 1: preconditioner diagonal takes the flux-derivative terms
 
 
 @dataclass

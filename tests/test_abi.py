@@ -56,3 +56,16 @@ def test_argument_validation_without_gpu():
     assert lib.rich_query_bytes(C.byref(_lib.make_problem(P)), C.byref(_lib.make_opts(O2)), C.byref(b)) == -1
     h = C.c_void_p()
     assert lib.rich_create(C.byref(_lib.make_problem(P)), C.byref(_lib.make_opts(O)), None, None, C.byref(h)) == -1
+
+
+def test_server_rejects_over_budget_without_gpu():
+    import numpy as np
+
+    import paper_2112_05051_amd as rich
+    import synth
+    srv = rich.Server(1 << 20, 2)  # 1 MiB
+    rec = synth.recipe("c1", n=8)
+    with pytest.raises(rich.RichError) as e:
+        srv.submit(rec.problem, rec.options, rec.ks(), rec.p0(), 1)
+    assert e.value.status == -3
+    srv.close()

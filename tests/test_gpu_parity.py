@@ -236,3 +236,15 @@ def test_mixed_vcycle_close_to_fp64(rich, torch, orc):
         out[prec] = s.apply_prec(dev(torch, b)).cpu().numpy()
     err = np.linalg.norm(out[synth.MIXED] - out[synth.FP64]) / np.linalg.norm(out[synth.FP64])
     assert err <= 1e-5
+
+
+def test_aux_dflux_matches_oracle(rich, torch, orc):
+    """The optional flux-derivative diagonal of the auxiliary matrix (aux_dflux = 1)."""
+    P = box_problem(13, 11, 9, mean=synth.HARMONIC, dt=3.0)
+    ks = random_ks(P, 24)
+    p = random_heads(P.n, 25, -60, -30)
+    opts = synth.Options(aux_dflux=1, amg_max_levels=1, coarse_dense_max=0)
+    s = make_solver(rich, torch, P, ks, opts)
+    s.assemble(dev(torch, p))
+    rp, col, val = s.export_csr(rich.WHICH_A, 0)
+    csr_close(rp, col, val, orc.auxiliary(P, ks, p, dflux=True), 1e-12)

@@ -1,0 +1,56 @@
+"""Ensemble server: every request's result in the mix equals its result alone."""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def small_requests(count=6, steps=3, seed=7, sizes=(10, 12, 14, 16, 18)):
+    out = [rec for t, rec in synth.serving_stream(count=count, seed=seed, sizes=sizes, nsteps=steps)]
+    for rec in out:
+        rec.options.max_newton = 40  # bounds the cost of a request that does not converge
+    return out
+
+
+def run_alone(rich, torch, rec):
+    s = rich.Solver(rec.problem, rec.options, torch.from_numpy(rec.ks()).cuda())
+    s.set_state(torch.from_numpy(rec.p0()).cuda())
+    stats = s.step(rec.nsteps, raise_on_error=False)
+    return s.get_state().cpu().numpy(), stats
+
+
+def test_alone_equals_mix():
+    import torch
+
+    import paper_2112_05051_amd as rich
+    reqs = small_requests()
+    srv = rich.Server(8 << 30, 3)
+    ids = [srv.submit(rec.problem, rec.options, rec.ks(), rec.p0(), rec.nsteps) for rec in reqs]
+    srv.wait_idle()
+    for rec, i in zip(reqs, ids):
+        r = srv.poll(i)
+        assert r is not None
+        p_alone, st_alone = run_alone(rich, torch, rec)
+        # same statuses, same iteration history, same final state bit for bit
+        assert [s["status"] for s in r["stats"]] == [s["status"] for s in st_alone[:len(r["stats"])]]
+        assert np.array_equal(r["p"], p_alone), np.abs(r["p"] - p_alone).max()
+        assert [s["newton_its"] for s in r["stats"]] == [s["newton_its"] for s in st_alone[:len(r["stats"])]]
+        assert [s["gmres_its"] for s in r["stats"]] == [s["gmres_its"] for s in st_alone[:len(r["stats"])]]
+    srv.close()
+
+
+def test_budget_serialises_but_completes():
+    import paper_2112_05051_amd as rich
+    reqs = small_requests(count=4, steps=2, seed=8, sizes=(14,))
+    need = max(rich.query_bytes(rec.problem, rec.options) + 16 * rec.problem.n for rec in reqs)
+    srv = rich.Server(need + 1024, 4)  # room for one simulation at a time
+    ids = [srv.submit(rec.problem, rec.options, rec.ks(), rec.p0(), rec.nsteps) for rec in reqs]
+    srv.wait_idle()
+    res = [srv.poll(i) for i in ids]
+    assert all(r is not None and r["status"] == 0 for r in res)
+    # one at a time: total resident time is the sum of the parts, so the last
+    # request waited at least as long as all earlier ones ran
+    assert res[-1]["wait_s"] >= 0.9 * sum(r["run_s"] for r in res[:-1])
+    srv.close()

@@ -286,3 +286,21 @@ def test_auxiliary_symmetric_m_matrix_spd(orc, mean):
     p2 = np.full(P2.n, -30.0)
     Dm = (orc.jacobian(P2, ks2, p2) - orc.auxiliary(P2, ks2, p2)).toarray()
     assert np.allclose(Dm, -Dm.T, atol=1e-15 * np.abs(Dm).max())
+
+
+@pytest.mark.parametrize("mean", MEANS)
+def test_auxiliary_dflux_diagonal_is_the_diffusion_jacobian_diagonal(orc, mean):
+    """With every face held (Dirichlet box) the two gravity derivative terms of a
+    row cancel, so the diagonal of the flux-derivative auxiliary matrix must equal
+    the Jacobian's; its off-diagonals are the frozen-coefficient ones."""
+    P = box_problem(6, 5, 4, mean=mean, dt=3.0, bc=all_dirichlet())
+    ks = random_ks(P, 18)
+    p = random_heads(P.n, 19)
+    J = orc.jacobian(P, ks, p)
+    M = orc.auxiliary(P, ks, p)
+    Md = orc.auxiliary(P, ks, p, dflux=True)
+    assert np.allclose(Md.diagonal(), J.diagonal(), rtol=1e-13, atol=0)
+    off = lambda A: (A - sp.diags(A.diagonal())).toarray()
+    assert np.array_equal(off(Md), off(M))
+    D = Md.toarray()
+    assert np.array_equal(D, D.T)
