@@ -111,11 +111,13 @@ rich_status launch_J_to_csr(const Phys &P, const double *J7, const int64_t *rowp
 rich_status launch_stencil_rowcounts(const Phys &P, int64_t *rowptr_plus1, hipStream_t s);
 
 // fine-level V-cycle pieces (TB: type of the right-hand side, T: arithmetic)
+// the right-hand side is bs[0] * b (bs: a device scalar)
 template <class TB, class T>
-rich_status launch_st_pre(const Phys &P, const T *M4, const T *invd, const TB *b, T *r, hipStream_t s);
+rich_status launch_st_pre(const Phys &P, const T *M4, const T *invd, const TB *b, const double *bs, T *r,
+                          hipStream_t s);
 // xt (scratch, N) receives the prolongated iterate before post-smoothing
 template <class TB, class T>
-rich_status launch_st_post(const Phys &P, const T *M4, const T *invd, const TB *b, const T *xc,
+rich_status launch_st_post(const Phys &P, const T *M4, const T *invd, const TB *b, const double *bs, const T *xc,
                            const int32_t *agg, T *x, T *xt, hipStream_t s);
 template <class TB, class T>
 rich_status launch_st_sweeps(const Phys &P, const T *M4, const T *invd, const TB *b, T *x, T *tmp,
@@ -125,12 +127,15 @@ rich_status launch_st_sweeps(const Phys &P, const T *M4, const T *invd, const TB
 constexpr int RED_BLOCKS = 1024;   // fixed block count of every reduction (deterministic order)
 constexpr int RED_THREADS = 256;
 
-// partial[blk*(k+1) + i] for i < k: V_i . w ; slot k: w . w.  Then reduced in fixed order.
-rich_status launch_multidot(const double *V, int64_t ldv, int k, const double *w, int64_t n,
+// Basis vectors are stored unnormalised: the true V_i is vs[i] * stored V_i.
+// out[i] = V_i . w (i < k), out[k] = w . w; reduced in fixed order.
+rich_status launch_multidot(const double *V, int64_t ldv, int k, const double *vs, const double *w, int64_t n,
                             double *partial, double *out, hipStream_t s);
-// w -= sum_i h_i V_i (i < k, h on device); out[0] = ||w||^2 (after update)
-rich_status launch_update_norm(const double *V, int64_t ldv, int k, const double *h, double *w,
+// w -= sum_i h_i V_i (i < k, h and vs on device); out[0] = ||w||^2 (after update)
+rich_status launch_update_norm(const double *V, int64_t ldv, int k, const double *h, const double *vs, double *w,
                                int64_t n, double *partial, double *out, hipStream_t s);
+// vs[0] = 1 / sqrt(ww[0]) on the device
+rich_status launch_set_scale(double *vs, const double *ww, hipStream_t s);
 // out[0] = x.y (deterministic)
 rich_status launch_dot(const double *x, const double *y, int64_t n, double *partial, double *out,
                        hipStream_t s);
@@ -148,11 +153,13 @@ rich_status launch_xpay_to(const double *x, double a, const double *y, double *z
                            hipStream_t s);
 template <class TX>
 rich_status launch_add_to(double *y, const TX *x, int64_t n, hipStream_t s);
-// y = sum_i c_i V_i, c on device (k entries)
-rich_status launch_lincomb(const double *V, int64_t ldv, int k, const double *c, double *y, int64_t n,
-                           hipStream_t s);
+// y = sum_i c_i V_i, c and vs on device (k entries)
+rich_status launch_lincomb(const double *V, int64_t ldv, int k, const double *c, const double *vs, double *y,
+                           int64_t n, hipStream_t s);
 // y = b - y
 rich_status launch_b_minus(const double *b, double *y, int64_t n, hipStream_t s);
+// y = sp[0] * x (sp a device scalar)
+rich_status launch_scale_copy(const double *x, const double *sp, double *y, int64_t n, hipStream_t s);
 rich_status launch_negate_to(const double *x, double *y, int64_t n, hipStream_t s);
 template <class TA, class TB>
 rich_status launch_cast(const TA *a, TB *b, int64_t n, hipStream_t s);

@@ -263,33 +263,36 @@ __global__ void k_spmv_M(Phys P, uint32_t n, const double *__restrict__ M4, cons
 // x0 = D^{-1} b (never stored), r = b - M x0.
 template <class TB, class T>
 __global__ void k_st_pre(Phys P, uint32_t n, const T *__restrict__ M4, const T *__restrict__ invd,
-                         const TB *__restrict__ b, T *__restrict__ r) {
+                         const TB *__restrict__ b, const double *__restrict__ bsp, T *__restrict__ r) {
     uint32_t c = xcd_block() * blockDim.x + threadIdx.x;
     if (c >= n) return;
+    const TB bs = (TB)bsp[0];
     Cell q = cell_of(P, c);
-    T s = mstencil<T>(P, q, c, n, M4, [&](uint32_t t) { return (T)b[t] * invd[t]; });
-    r[c] = (T)b[c] - s;
+    T s = mstencil<T>(P, q, c, n, M4, [&](uint32_t t) { return (T)(b[t] * bs) * invd[t]; });
+    r[c] = (T)(b[c] * bs) - s;
 }
 
 // V-cycle, fine level, prolongation: xt = D^{-1} b + P xc (the pre-smoothed
 // iterate plus the coarse correction), one streaming pass.
 template <class TB, class T>
 __global__ void k_st_prolong(uint32_t n, const T *__restrict__ invd, const TB *__restrict__ b,
-                             const T *__restrict__ xc, const int32_t *__restrict__ agg, T *__restrict__ xt) {
+                             const double *__restrict__ bsp, const T *__restrict__ xc, const int32_t *__restrict__ agg,
+                             T *__restrict__ xt) {
     uint32_t c = xcd_block() * blockDim.x + threadIdx.x;
     if (c >= n) return;
-    xt[c] = (T)b[c] * invd[c] + xc[agg[c]];
+    xt[c] = (T)(b[c] * (TB)bsp[0]) * invd[c] + xc[agg[c]];
 }
 
 // V-cycle, fine level, post-smoothing: x = xt + D^{-1}(b - M xt).
 template <class TB, class T>
 __global__ void k_st_post(Phys P, uint32_t n, const T *__restrict__ M4, const T *__restrict__ invd,
-                          const TB *__restrict__ b, const T *__restrict__ xt, T *__restrict__ x) {
+                          const TB *__restrict__ b, const double *__restrict__ bsp, const T *__restrict__ xt,
+                          T *__restrict__ x) {
     uint32_t c = xcd_block() * blockDim.x + threadIdx.x;
     if (c >= n) return;
     Cell q = cell_of(P, c);
     T s = mstencil<T>(P, q, c, n, M4, [&](uint32_t t) { return xt[t]; });
-    x[c] = xt[c] + invd[c] * ((T)b[c] - s);
+    x[c] = xt[c] + invd[c] * ((T)(b[c] * (TB)bsp[0]) - s);
 }
 
 // Plain l1-Jacobi sweep x_out = x_in + D^{-1}(b - M x_in) (used when the
@@ -393,20 +396,21 @@ rich_status launch_spmv_M(const Phys &P, const double *M4, const double *x, doub
 }
 
 template <class TB, class T>
-rich_status launch_st_pre(const Phys &P, const T *M4, const T *invd, const TB *b, T *r, hipStream_t s) {
+rich_status launch_st_pre(const Phys &P, const T *M4, const T *invd, const TB *b, const double *bs, T *r,
+                          hipStream_t s) {
     uint32_t n = ncells(P);
-    k_st_pre<TB, T><<<nblocks(n), TPB, 0, s>>>(P, n, M4, invd, b, r);
+    k_st_pre<TB, T><<<nblocks(n), TPB, 0, s>>>(P, n, M4, invd, b, bs, r);
     LAUNCH_CHECK();
     return RICH_OK;
 }
 
 template <class TB, class T>
-rich_status launch_st_post(const Phys &P, const T *M4, const T *invd, const TB *b, const T *xc,
+rich_status launch_st_post(const Phys &P, const T *M4, const T *invd, const TB *b, const double *bs, const T *xc,
                            const int32_t *agg, T *x, T *xt, hipStream_t s) {
     uint32_t n = ncells(P);
-    k_st_prolong<TB, T><<<nblocks(n), TPB, 0, s>>>(n, invd, b, xc, agg, xt);
+    k_st_prolong<TB, T><<<nblocks(n), TPB, 0, s>>>(n, invd, b, bs, xc, agg, xt);
     LAUNCH_CHECK();
-    k_st_post<TB, T><<<nblocks(n), TPB, 0, s>>>(P, n, M4, invd, b, xt, x);
+    k_st_post<TB, T><<<nblocks(n), TPB, 0, s>>>(P, n, M4, invd, b, bs, xt, x);
     LAUNCH_CHECK();
     return RICH_OK;
 }
@@ -429,9 +433,10 @@ rich_status launch_st_sweeps(const Phys &P, const T *M4, const T *invd, const TB
 }
 
 #define INST_ST(TB, T)                                                                                    \
-    template rich_status launch_st_pre<TB, T>(const Phys &, const T *, const T *, const TB *, T *, hipStream_t); \
-    template rich_status launch_st_post<TB, T>(const Phys &, const T *, const T *, const TB *, const T *,      \
-                                               const int32_t *, T *, T *, hipStream_t);                         \
+    template rich_status launch_st_pre<TB, T>(const Phys &, const T *, const T *, const TB *, const double *, T *, \
+                                              hipStream_t);                                                     \
+    template rich_status launch_st_post<TB, T>(const Phys &, const T *, const T *, const TB *, const double *,   \
+                                               const T *, const int32_t *, T *, T *, hipStream_t);              \
     template rich_status launch_st_sweeps<TB, T>(const Phys &, const T *, const T *, const TB *, T *, T *, int, \
                                                  hipStream_t);
 INST_ST(double, double)

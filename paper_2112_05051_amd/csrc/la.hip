@@ -91,14 +91,21 @@ __global__ void __launch_bounds__(RED_THREADS) k_multidot(const double *__restri
     }
 }
 
-// out[i] = sum_b partial[b*(m) + i], b ascending (one block per output).
-__global__ void k_reduce_partials(const double *__restrict__ partial, int m, int nb, double *__restrict__ out) {
+// out[i] = sum_b partial[b*(m) + i], b ascending (one block per output),
+// times scale[i] for i < nscale (basis vectors stored with a scale factor).
+__global__ void k_reduce_partials(const double *__restrict__ partial, int m, int nb, double *__restrict__ out,
+                                  const double *__restrict__ scale = nullptr, int nscale = 0) {
     __shared__ double sh[RED_THREADS / WAVE];
     int i = blockIdx.x;
     double a = 0.0;
     for (int b = threadIdx.x; b < nb; b += blockDim.x) a += partial[(size_t)b * m + i];
     double r = block_sum(a, sh);
-    if (threadIdx.x == 0) out[i] = r;
+    if (threadIdx.x == 0) out[i] = (i < nscale) ? r * scale[i] : r;
+}
+
+// vs[0] = 1/sqrt(ww[0]) (0 for a zero vector): the scale of a new basis vector.
+__global__ void k_set_scale(double *__restrict__ vs, const double *__restrict__ ww) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) vs[0] = ww[0] > 0.0 ? 1.0 / sqrt(ww[0]) : 0.0;
 }
 
 __global__ void k_reduce_max(const double *__restrict__ partial, int m, int nb, double *__restrict__ out) {
@@ -112,15 +119,16 @@ __global__ void k_reduce_max(const double *__restrict__ partial, int m, int nb, 
     if (threadIdx.x == 0) out[0] = r;
 }
 
-// w -= sum_i h_i V_i and the partial sums of ||w||^2, K compile-time, row pairs.
+// w -= sum_i h_i (vs_i V_i) and the partial sums of ||w||^2, K compile-time, row pairs.
 template <int K>
 __global__ void __launch_bounds__(RED_THREADS) k_update_norm(const double *__restrict__ V, int64_t ldv,
-                                                             const double *__restrict__ h, double *__restrict__ w,
+                                                             const double *__restrict__ h,
+                                                             const double *__restrict__ vs, double *__restrict__ w,
                                                              int64_t n, double *__restrict__ partial) {
     __shared__ double sh[RED_THREADS / WAVE];
     double hr[K];
 #pragma unroll
-    for (int i = 0; i < K; i++) hr[i] = h[i];
+    for (int i = 0; i < K; i++) hr[i] = h[i] * vs[i];
     double acc = 0.0;
     const int64_t n2 = n >> 1;
     double2 *__restrict__ w2 = reinterpret_cast<double2 *>(w);
@@ -220,15 +228,21 @@ __global__ void k_add_to(double *__restrict__ y, const TX *__restrict__ x, int64
 }
 
 __global__ void k_lincomb(const double *__restrict__ V, int64_t ldv, int k, const double *__restrict__ cf,
-                          double *__restrict__ y, int64_t n) {
+                          const double *__restrict__ vs, double *__restrict__ y, int64_t n) {
     __shared__ double cs[KMAX];
-    for (int i = threadIdx.x; i < k; i += blockDim.x) cs[i] = cf[i];
+    for (int i = threadIdx.x; i < k; i += blockDim.x) cs[i] = cf[i] * vs[i];
     __syncthreads();
     int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n) return;
     double s = 0.0;
     for (int i = 0; i < k; i++) s += cs[i] * V[(size_t)i * ldv + c];
     y[c] = s;
+}
+
+__global__ void k_scale_copy(const double *__restrict__ x, const double *__restrict__ sp, double *__restrict__ y,
+                             int64_t n) {
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < n) y[c] = x[c] * sp[0];
 }
 
 __global__ void k_b_minus(const double *__restrict__ b, double *__restrict__ y, int64_t n) {
@@ -332,8 +346,8 @@ __global__ void k_scan_final(const int64_t *__restrict__ in, int64_t n, const in
     X(37) X(38) X(39) X(40) X(41) X(42) X(43) X(44) X(45) X(46) X(47) X(48) X(49) X(50) X(51) X(52) X(53)   \
     X(54) X(55) X(56) X(57) X(58) X(59) X(60) X(61) X(62) X(63) X(64)
 
-rich_status launch_multidot(const double *V, int64_t ldv, int k, const double *w, int64_t n, double *partial,
-                            double *out, hipStream_t s) {
+rich_status launch_multidot(const double *V, int64_t ldv, int k, const double *vs, const double *w, int64_t n,
+                            double *partial, double *out, hipStream_t s) {
     if (k < 1 || k > 64 || (ldv & 1)) return RICH_EINVAL;
     switch (k) {
 #define X(K)                                                                         \
@@ -344,18 +358,18 @@ rich_status launch_multidot(const double *V, int64_t ldv, int k, const double *w
 #undef X
     }
     LAUNCH_CHECK();
-    k_reduce_partials<<<k + 1, RED_THREADS, 0, s>>>(partial, k + 1, RED_BLOCKS, out);
+    k_reduce_partials<<<k + 1, RED_THREADS, 0, s>>>(partial, k + 1, RED_BLOCKS, out, vs, k);
     LAUNCH_CHECK();
     return RICH_OK;
 }
 
-rich_status launch_update_norm(const double *V, int64_t ldv, int k, const double *h, double *w, int64_t n,
-                               double *partial, double *out, hipStream_t s) {
+rich_status launch_update_norm(const double *V, int64_t ldv, int k, const double *h, const double *vs, double *w,
+                               int64_t n, double *partial, double *out, hipStream_t s) {
     if (k < 1 || k > 64 || (ldv & 1)) return RICH_EINVAL;
     switch (k) {
 #define X(K)                                                                            \
     case K:                                                                             \
-        k_update_norm<K><<<RED_BLOCKS, RED_THREADS, 0, s>>>(V, ldv, h, w, n, partial);  \
+        k_update_norm<K><<<RED_BLOCKS, RED_THREADS, 0, s>>>(V, ldv, h, vs, w, n, partial); \
         break;
         RICH_CASES_1_64(X)
 #undef X
@@ -426,9 +440,15 @@ rich_status launch_add_to(double *y, const TX *x, int64_t n, hipStream_t s) {
 template rich_status launch_add_to<double>(double *, const double *, int64_t, hipStream_t);
 template rich_status launch_add_to<float>(double *, const float *, int64_t, hipStream_t);
 
-rich_status launch_lincomb(const double *V, int64_t ldv, int k, const double *c, double *y, int64_t n,
-                           hipStream_t s) {
-    k_lincomb<<<nblocks(n), TPB, 0, s>>>(V, ldv, k, c, y, n);
+rich_status launch_lincomb(const double *V, int64_t ldv, int k, const double *c, const double *vs, double *y,
+                           int64_t n, hipStream_t s) {
+    k_lincomb<<<nblocks(n), TPB, 0, s>>>(V, ldv, k, c, vs, y, n);
+    LAUNCH_CHECK();
+    return RICH_OK;
+}
+
+rich_status launch_scale_copy(const double *x, const double *sp, double *y, int64_t n, hipStream_t s) {
+    k_scale_copy<<<nblocks(n), TPB, 0, s>>>(x, sp, y, n);
     LAUNCH_CHECK();
     return RICH_OK;
 }
@@ -466,6 +486,12 @@ rich_status launch_fill_i32(int32_t *x, int32_t v, int64_t n, hipStream_t s) {
 rich_status launch_fill_f64(double *x, double v, int64_t n, hipStream_t s) {
     if (n == 0) return RICH_OK;
     k_fill_f64<<<nblocks(n), TPB, 0, s>>>(x, v, n);
+    LAUNCH_CHECK();
+    return RICH_OK;
+}
+
+rich_status launch_set_scale(double *vs, const double *ww, hipStream_t s) {
+    k_set_scale<<<1, 64, 0, s>>>(vs, ww);
     LAUNCH_CHECK();
     return RICH_OK;
 }

@@ -53,6 +53,12 @@ struct rich_ctx {
     double *dres = nullptr;    // device scalars (m + 8)
     double *dres2 = nullptr;
     double *hres = nullptr;    // pinned host mirror (2 * (m + 8))
+    double *vs = nullptr;      // device scale of every stored basis vector (m + 1)
+    double *one = nullptr;     // device constant 1.0
+    double *hbuf = nullptr;    // device Arnoldi results, one row of (m + 4) per iteration
+    double *hall = nullptr;    // pinned host mirror of hbuf
+    double *bsc = nullptr;     // N: scaled right-hand side for a one-level hierarchy
+    std::vector<hipEvent_t> iter_ev;  // one per Arnoldi iteration
     // AMG
     Hierarchy *H = nullptr;
     bool have_J = false;
@@ -71,6 +77,8 @@ struct rich_ctx {
     ~rich_ctx() {
         delete H;
         if (hres) (void)hipHostFree(hres);
+        if (hall) (void)hipHostFree(hall);
+        for (auto e : iter_ev) (void)hipEventDestroy(e);
         for (auto &k : prof)
             for (auto &e : k.pending) {
                 (void)hipEventDestroy(e.first);
@@ -344,21 +352,24 @@ const float *lvinvd<float>(const Level &L) { return L.invdf; }
 
 // z = V-cycle(b): one l1-Jacobi sweep before and after each coarse
 // correction, the pre-sweep from zero (Section 5.2, symmetric V-cycle).
+// The right-hand side is bs[0] * b (bs a device scalar: the basis vectors are
+// stored unnormalised).
 template <class T>
-rich_status vcycle(rich_ctx *h, const double *b, T *z) {
+rich_status vcycle(rich_ctx *h, const double *b, const double *bs, T *z) {
     Hierarchy &H = *h->H;
     hipStream_t s = h->s;
     const T *M4 = h->mixed ? (const T *)(const void *)h->M4f : (const T *)(const void *)h->M4;
     const T *invd0 = h->mixed ? (const T *)(const void *)h->invd0f : (const T *)(const void *)h->invd0;
     const T *cinv = h->mixed ? (const T *)(const void *)H.cinvf : (const T *)(const void *)H.cinv;
     if (H.nlev == 1) {
-        if (H.dense) return launch_dense_gemv<double, T>(cinv, b, z, h->N, s);
-        return launch_st_sweeps<double, T>(h->P, M4, invd0, b, z, (T *)h->ztmp, h->O.coarse_l1_sweeps, s);
+        RICH_TRY(launch_scale_copy(b, bs, h->bsc, h->N, s));
+        if (H.dense) return launch_dense_gemv<double, T>(cinv, h->bsc, z, h->N, s);
+        return launch_st_sweeps<double, T>(h->P, M4, invd0, h->bsc, z, (T *)h->ztmp, h->O.coarse_l1_sweeps, s);
     }
     const double t = sizeof(T), n0 = (double)h->N, n1 = (double)H.L[1].n;
     // down
     RICH_TRY(timed(h, RICH_K_VC0_PRE, n0 * (8 + 6 * t),
-                   [&] { return launch_st_pre<double, T>(h->P, M4, invd0, b, (T *)H.L[0].r, s); }));
+                   [&] { return launch_st_pre<double, T>(h->P, M4, invd0, b, bs, (T *)H.L[0].r, s); }));
     RICH_TRY(timed(h, RICH_K_VC0_RESTRICT, n0 * (t + 4) + n1 * (8 + t), [&] {
         return launch_restrict<T>(H.L[0], (const T *)H.L[0].r, (T *)H.L[1].b, H.L[1].n, s);
     }));
@@ -388,13 +399,14 @@ rich_status vcycle(rich_ctx *h, const double *b, T *z) {
         }));
     }
     return timed(h, RICH_K_VC0_POST, n0 * (20 + 9 * t) + n1 * t, [&] {
-        return launch_st_post<double, T>(h->P, M4, invd0, b, (const T *)H.L[1].x, H.L[0].agg, z, (T *)H.L[0].r, s);
+        return launch_st_post<double, T>(h->P, M4, invd0, b, bs, (const T *)H.L[1].x, H.L[0].agg, z, (T *)H.L[0].r,
+                                         s);
     });
 }
 
-rich_status apply_prec(rich_ctx *h, const double *b) {
-    if (h->mixed) return vcycle<float>(h, b, (float *)h->z);
-    return vcycle<double>(h, b, (double *)h->z);
+rich_status apply_prec(rich_ctx *h, const double *b, const double *bs) {
+    if (h->mixed) return vcycle<float>(h, b, bs, (float *)h->z);
+    return vcycle<double>(h, b, bs, (double *)h->z);
 }
 
 rich_status spmv_J_z(rich_ctx *h, double *y) {
@@ -412,13 +424,18 @@ rich_status add_z(rich_ctx *h, double *x) {
 
 // ------------------------------------------------------------------ GMRES
 // Right-preconditioned restarted GMRES(m) on J M^{-1}: classical Gram-Schmidt
-// with a second pass when the norm drops below 0.7 of its value (Daniel-
-// Gragg-Kaufman-Stewart criterion), Givens rotations on the host,
-// x += M^{-1} V y at the end of each cycle, true residual at every restart.
-// Stops at ||b - J x||_2 <= eta ||b||_2 or after maxit Arnoldi steps.
+// (one fused dot block and one fused update per iteration; a second pass
+// when the norm drops below gmres_reorth of its value), Givens rotations on
+// the host, x += M^{-1} V y at the end of each cycle, true residual at every
+// restart.  Stops at ||b - J x||_2 <= eta ||b||_2 or after maxit Arnoldi steps.
+// Basis vectors are stored unnormalised with their scale on the device, so an
+// Arnoldi step needs no host value: the host enqueues iteration j+1 before it
+// reads iteration j's Hessenberg column, and only a (rare) second
+// Gram-Schmidt pass makes it wait and redo the speculative step.
 rich_status gmres(rich_ctx *h, const double *b, double *x, int *its_out, double *relres_out, bool *conv_out) {
-    int64_t N = h->N;
+    int64_t N = h->N, ld = h->ldv;
     int m = h->m;
+    const int W = m + 4;
     hipStream_t s = h->s;
     double eta = h->O.eta;
     std::vector<double> Hm((m + 1) * m), cs(m), sn(m), g(m + 1), y(m), hv(m + 8);
@@ -436,9 +453,25 @@ rich_status gmres(rich_ctx *h, const double *b, double *x, int *its_out, double 
         return RICH_OK;
     }
     if (!std::isfinite(bnorm)) return RICH_NONFINITE;
+    auto enqueue = [&](int j) -> rich_status {
+        double *vj = h->V + (size_t)j * ld;
+        double *w = h->V + (size_t)(j + 1) * ld;
+        double *hb = h->hbuf + (size_t)j * W;
+        RICH_TRY(apply_prec(h, vj, h->vs + j));
+        RICH_TRY(spmv_J_z(h, w));
+        RICH_TRY(timed(h, RICH_K_MULTIDOT, (double)N * 8 * (j + 2),
+                       [&] { return launch_multidot(h->V, ld, j + 1, h->vs, w, N, h->partial, hb, s); }));
+        RICH_TRY(timed(h, RICH_K_UPDATE, (double)N * 8 * (j + 3), [&] {
+            return launch_update_norm(h->V, ld, j + 1, hb, h->vs, w, N, h->partial, hb + j + 2, s);
+        }));
+        RICH_TRY(launch_set_scale(h->vs + j + 1, hb + j + 2, s));
+        HIP_TRY(hipMemcpyAsync(h->hall + (size_t)j * W, hb, (j + 3) * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipEventRecord(h->iter_ev[j], s));
+        return RICH_OK;
+    };
     bool first = true;
     for (;;) {
-        // true residual into V_0
+        // true residual into V_0 (stored unnormalised, scale 1/beta on the device)
         if (first) {
             HIP_TRY(hipMemcpyAsync(h->V, b, N * sizeof(double), hipMemcpyDeviceToDevice, s));
         } else {
@@ -456,41 +489,42 @@ rich_status gmres(rich_ctx *h, const double *b, double *x, int *its_out, double 
             break;
         }
         if (total >= h->O.gmres_maxit) break;
-        RICH_TRY(launch_scale(h->V, 1.0 / beta, N, s));
+        RICH_TRY(launch_set_scale(h->vs, h->dres + 2, s));  // dres[2] = ||V_0||^2 from norms()
         std::fill(g.begin(), g.end(), 0.0);
         g[0] = beta;
-        int k = 0;
+        int k = 0, queued = -1;
         for (int j = 0; j < m && total < h->O.gmres_maxit; j++) {
-            double *vj = h->V + (size_t)j * h->ldv;
-            double *w = h->V + (size_t)(j + 1) * h->ldv;
-            RICH_TRY(apply_prec(h, vj));
-            RICH_TRY(spmv_J_z(h, w));
-            RICH_TRY(timed(h, RICH_K_MULTIDOT, (double)N * 8 * (j + 2),
-                           [&] { return launch_multidot(h->V, h->ldv, j + 1, w, N, h->partial, h->dres, s); }));
-            RICH_TRY(timed(h, RICH_K_UPDATE, (double)N * 8 * (j + 3), [&] {
-                return launch_update_norm(h->V, h->ldv, j + 1, h->dres, w, N, h->partial, h->dres2, s);
-            }));
-            HIP_TRY(hipMemcpyAsync(h->hres, h->dres, (j + 2) * sizeof(double), hipMemcpyDeviceToHost, s));
-            HIP_TRY(hipMemcpyAsync(h->hres + (m + 8), h->dres2, sizeof(double), hipMemcpyDeviceToHost, s));
-            RICH_TRY(sync(h));
-            for (int i = 0; i <= j; i++) hv[i] = h->hres[i];
-            double ww0 = h->hres[j + 1];
-            double ww1 = h->hres[m + 8];
+            if (queued < j) {
+                RICH_TRY(enqueue(j));
+                queued = j;
+            }
+            if (j + 1 < m && total + 1 < h->O.gmres_maxit && queued < j + 1) {
+                RICH_TRY(enqueue(j + 1));  // speculative: needs nothing from the host
+                queued = j + 1;
+            }
+            HIP_TRY(hipEventSynchronize(h->iter_ev[j]));
+            const double *hr = h->hall + (size_t)j * W;
+            for (int i = 0; i <= j; i++) hv[i] = hr[i];
+            double ww0 = hr[j + 1], ww1 = hr[j + 2];
             if (std::sqrt(ww1) < h->O.gmres_reorth * std::sqrt(ww0)) {
-                // second Gram-Schmidt pass
-                RICH_TRY(launch_multidot(h->V, h->ldv, j + 1, w, N, h->partial, h->dres, s));
-                RICH_TRY(launch_update_norm(h->V, h->ldv, j + 1, h->dres, w, N, h->partial, h->dres2, s));
+                // second Gram-Schmidt pass on V_{j+1}; the speculative step j+1 used
+                // the once-orthogonalised vector and is redone
+                double *w = h->V + (size_t)(j + 1) * ld;
+                RICH_TRY(sync(h));
+                RICH_TRY(launch_multidot(h->V, ld, j + 1, h->vs, w, N, h->partial, h->dres, s));
+                RICH_TRY(launch_update_norm(h->V, ld, j + 1, h->dres, h->vs, w, N, h->partial, h->dres2, s));
+                RICH_TRY(launch_set_scale(h->vs + j + 1, h->dres2, s));
                 HIP_TRY(hipMemcpyAsync(h->hres, h->dres, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
                 HIP_TRY(hipMemcpyAsync(h->hres + (m + 8), h->dres2, sizeof(double), hipMemcpyDeviceToHost, s));
                 RICH_TRY(sync(h));
                 for (int i = 0; i <= j; i++) hv[i] += h->hres[i];
                 ww1 = h->hres[m + 8];
+                queued = j;
             }
             double hn = std::sqrt(ww1);
             if (!std::isfinite(hn)) return RICH_NONFINITE;
             for (int i = 0; i <= j; i++) Hm[i * m + j] = hv[i];
             Hm[(j + 1) * m + j] = hn;
-            if (hn > 0.0) RICH_TRY(launch_scale(w, 1.0 / hn, N, s));
             for (int i = 0; i < j; i++) {
                 double a = Hm[i * m + j], c = Hm[(i + 1) * m + j];
                 Hm[i * m + j] = cs[i] * a + sn[i] * c;
@@ -515,8 +549,8 @@ rich_status gmres(rich_ctx *h, const double *b, double *x, int *its_out, double 
         }
         memcpy(h->hres, y.data(), k * sizeof(double));
         HIP_TRY(hipMemcpyAsync(h->dres, h->hres, k * sizeof(double), hipMemcpyHostToDevice, s));
-        RICH_TRY(launch_lincomb(h->V, h->ldv, k, h->dres, h->work, N, s));
-        RICH_TRY(apply_prec(h, h->work));
+        RICH_TRY(launch_lincomb(h->V, ld, k, h->dres, h->vs, h->work, N, s));
+        RICH_TRY(apply_prec(h, h->work, h->one));
         RICH_TRY(add_z(h, x));
         RICH_TRY(sync(h));  // hres is reused before the next read
     }
@@ -920,8 +954,22 @@ rich_status rich_create(const rich_problem_t *prob, const rich_solver_opts_t *op
     G(&h->partial, (size_t)RED_BLOCKS * (h->m + 2) * 3);
     G(&h->dres, h->m + 8);
     G(&h->dres2, 8);
+    G(&h->vs, h->m + 2);
+    G(&h->one, 1);
+    G(&h->hbuf, (size_t)(h->m + 1) * (h->m + 4));
+    G(&h->bsc, N);
     if (st == RICH_OK && hipHostMalloc((void **)&h->hres, 2 * (h->m + 8) * sizeof(double)) != hipSuccess)
         st = RICH_ENOMEM;
+    if (st == RICH_OK &&
+        hipHostMalloc((void **)&h->hall, (size_t)(h->m + 1) * (h->m + 4) * sizeof(double)) != hipSuccess)
+        st = RICH_ENOMEM;
+    for (int j = 0; st == RICH_OK && j <= h->m; j++) {
+        hipEvent_t e;
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) st = RICH_EHIP;
+        else h->iter_ev.push_back(e);
+    }
+    if (st == RICH_OK) st = launch_fill_f64(h->one, 1.0, 1, h->s);
+    if (st == RICH_OK) st = launch_fill_f64(h->vs, 1.0, h->m + 2, h->s);
     if (st == RICH_OK && hipMemcpyAsync(h->Ks, Ks_dev, N * sizeof(double), hipMemcpyDeviceToDevice, h->s) != hipSuccess)
         st = RICH_EHIP;
     if (st == RICH_OK) st = launch_fill_f64(h->p, 0.0, N, h->s);
@@ -1004,7 +1052,7 @@ rich_status rich_apply_aux(rich_handle_t h, const double *x_dev, double *y_dev) 
 rich_status rich_apply_prec(rich_handle_t h, const double *b_dev, double *x_dev) {
     if (!h || !b_dev || !x_dev) return RICH_EINVAL;
     if (!h->H) return RICH_ESTATE;
-    RICH_TRY(apply_prec(h, b_dev));
+    RICH_TRY(apply_prec(h, b_dev, h->one));
     if (h->mixed) RICH_TRY(launch_cast<float, double>((const float *)h->z, x_dev, h->N, h->s));
     else HIP_TRY(hipMemcpyAsync(x_dev, h->z, h->N * sizeof(double), hipMemcpyDeviceToDevice, h->s));
     return sync(h);
