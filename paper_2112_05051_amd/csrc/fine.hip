@@ -295,6 +295,112 @@ __global__ void k_st_post(Phys P, uint32_t n, const T *__restrict__ M4, const T 
     x[c] = xt[c] + invd[c] * ((T)(b[c] * (TB)bsp[0]) - s);
 }
 
+// 2.5-D versions of the two fine-level V-cycle stencils for large grids.  A
+// block of 64 x 8 threads owns a 64 x 8 column tile and walks a chunk of kz
+// planes upward: the stencil input u of the planes below and above stays in
+// registers, the current plane (with a one-cell halo) and its +x / +y
+// couplings (with the lower neighbours' ones) are staged in LDS, so every
+// cell's data is loaded from memory once (halos aside).  The sums keep the
+// order of mstencil (diag, -x, +x, -y, +y, -z, +z).  Chunks are kz planes
+// deep, kz chosen so that the grid still has enough blocks to fill the chip.
+//   PRE : u = D^{-1} bs b (pre-smoothing from zero),  out = bs b - M u
+//   POST: u = D^{-1} bs b + P xc (prolongation fused), out = u + D^{-1}(bs b - M u)
+constexpr int T25X = 64, T25Y = 8;
+#ifndef ST25_MIN_BLOCKS
+#define ST25_MIN_BLOCKS 2048
+#endif
+template <class TB, class T, bool POST>
+__global__ void __launch_bounds__(T25X * T25Y) k_st25(Phys P, const T *__restrict__ M4, const T *__restrict__ invd,
+                                                     const TB *__restrict__ b, const double *__restrict__ bsp,
+                                                     const T *__restrict__ xc, const int32_t *__restrict__ agg,
+                                                     T *__restrict__ out, int kz) {
+    __shared__ T us[T25Y + 2][T25X + 2];
+    __shared__ T xps[T25Y][T25X + 1];
+    __shared__ T yps[T25Y + 1][T25X];
+    const int nx = P.nx, ny = P.ny, nz = P.nz;
+    const uint32_t n = (uint32_t)nx * (uint32_t)ny * (uint32_t)nz;
+    const uint32_t nxy = (uint32_t)nx * (uint32_t)ny;
+    const int tx = threadIdx.x, ty = threadIdx.y;
+    const int i = blockIdx.x * T25X + tx, j = blockIdx.y * T25Y + ty;
+    const int k0 = blockIdx.z * kz, k1 = min(k0 + kz, nz);
+    const bool inside = i < nx && j < ny;
+    const TB bs = (TB)bsp[0];
+    auto U = [&](uint32_t c) -> T {
+        T u = (T)(b[c] * bs) * invd[c];
+        if (POST) u += xc[agg[c]];
+        return u;
+    };
+    // column values of the current and the next plane: bs b, D^{-1}, u
+    T b_cur = 0, d_cur = 0, u_cur = 0, b_nxt = 0, d_nxt = 0, u_nxt = 0, u_prev = 0, zp_prev = 0;
+    uint32_t c = (uint32_t)i + (uint32_t)nx * ((uint32_t)j + (uint32_t)ny * (uint32_t)k0);
+    if (inside) {
+        b_cur = (T)(b[c] * bs);
+        d_cur = invd[c];
+        u_cur = b_cur * d_cur;
+        if (POST) u_cur += xc[agg[c]];
+        if (k0 > 0) {
+            u_prev = U(c - nxy);
+            zp_prev = M4[(size_t)M_ZP * n + c - nxy];
+        }
+    }
+    for (int k = k0; k < k1; k++, c += nxy) {
+        if (inside && k + 1 < nz) {
+            b_nxt = (T)(b[c + nxy] * bs);
+            d_nxt = invd[c + nxy];
+            u_nxt = b_nxt * d_nxt;
+            if (POST) u_nxt += xc[agg[c + nxy]];
+        } else {
+            u_nxt = 0;
+        }
+        us[ty + 1][tx + 1] = u_cur;
+        xps[ty][tx + 1] = inside ? M4[(size_t)M_XP * n + c] : (T)0;
+        yps[ty + 1][tx] = inside ? M4[(size_t)M_YP * n + c] : (T)0;
+        if (tx == 0) {
+            bool ok = i > 0 && j < ny;
+            us[ty + 1][0] = ok ? U(c - 1) : (T)0;
+            xps[ty][0] = ok ? M4[(size_t)M_XP * n + c - 1] : (T)0;
+        }
+        if (tx == T25X - 1) us[ty + 1][T25X + 1] = (i + 1 < nx && j < ny) ? U(c + 1) : (T)0;
+        if (ty == 0) {
+            bool ok = j > 0 && i < nx;
+            us[0][tx + 1] = ok ? U(c - nx) : (T)0;
+            yps[0][tx] = ok ? M4[(size_t)M_YP * n + c - nx] : (T)0;
+        }
+        if (ty == T25Y - 1) us[T25Y + 1][tx + 1] = (j + 1 < ny && i < nx) ? U(c + nx) : (T)0;
+        __syncthreads();
+        if (inside) {
+            T s = M4[(size_t)M_D * n + c] * u_cur;
+            if (i > 0) s += xps[ty][tx] * us[ty + 1][tx];
+            if (i < nx - 1) s += xps[ty][tx + 1] * us[ty + 1][tx + 2];
+            if (j > 0) s += yps[ty][tx] * us[ty][tx + 1];
+            if (j < ny - 1) s += yps[ty + 1][tx] * us[ty + 2][tx + 1];
+            if (k > 0) s += zp_prev * u_prev;
+            T zpc = M4[(size_t)M_ZP * n + c];
+            if (k < nz - 1) s += zpc * u_nxt;
+            out[c] = POST ? u_cur + d_cur * (b_cur - s) : b_cur - s;
+            zp_prev = zpc;
+        }
+        __syncthreads();
+        u_prev = u_cur;
+        u_cur = u_nxt;
+        b_cur = b_nxt;
+        d_cur = d_nxt;
+    }
+}
+
+// The 64-wide tile needs rows of at least about that length to keep its lanes busy.
+inline bool use25(const Phys &P) { return P.nx >= 48 && P.ny >= T25Y && P.nz >= 4; }
+inline int kz25(const Phys &P) {
+    int64_t tiles = (int64_t)((P.nx + T25X - 1) / T25X) * ((P.ny + T25Y - 1) / T25Y);
+    int kz = 16;
+    while (kz > 1 && tiles * ((P.nz + kz - 1) / kz) < ST25_MIN_BLOCKS) kz /= 2;
+    return kz;
+}
+inline dim3 grid25(const Phys &P, int kz) {
+    return dim3((unsigned)((P.nx + T25X - 1) / T25X), (unsigned)((P.ny + T25Y - 1) / T25Y),
+                (unsigned)((P.nz + kz - 1) / kz));
+}
+
 // Plain l1-Jacobi sweep x_out = x_in + D^{-1}(b - M x_in) (used when the
 // fine level is also the coarsest and too large for a direct solve).
 template <class TB, class T>
@@ -399,7 +505,12 @@ template <class TB, class T>
 rich_status launch_st_pre(const Phys &P, const T *M4, const T *invd, const TB *b, const double *bs, T *r,
                           hipStream_t s) {
     uint32_t n = ncells(P);
-    k_st_pre<TB, T><<<nblocks(n), TPB, 0, s>>>(P, n, M4, invd, b, bs, r);
+    if (use25(P)) {
+        int kz = kz25(P);
+        k_st25<TB, T, false><<<grid25(P, kz), dim3(T25X, T25Y), 0, s>>>(P, M4, invd, b, bs, nullptr, nullptr, r, kz);
+    } else {
+        k_st_pre<TB, T><<<nblocks(n), TPB, 0, s>>>(P, n, M4, invd, b, bs, r);
+    }
     LAUNCH_CHECK();
     return RICH_OK;
 }
@@ -408,9 +519,14 @@ template <class TB, class T>
 rich_status launch_st_post(const Phys &P, const T *M4, const T *invd, const TB *b, const double *bs, const T *xc,
                            const int32_t *agg, T *x, T *xt, hipStream_t s) {
     uint32_t n = ncells(P);
-    k_st_prolong<TB, T><<<nblocks(n), TPB, 0, s>>>(n, invd, b, bs, xc, agg, xt);
-    LAUNCH_CHECK();
-    k_st_post<TB, T><<<nblocks(n), TPB, 0, s>>>(P, n, M4, invd, b, bs, xt, x);
+    if (use25(P)) {
+        int kz = kz25(P);
+        k_st25<TB, T, true><<<grid25(P, kz), dim3(T25X, T25Y), 0, s>>>(P, M4, invd, b, bs, xc, agg, x, kz);
+    } else {
+        k_st_prolong<TB, T><<<nblocks(n), TPB, 0, s>>>(n, invd, b, bs, xc, agg, xt);
+        LAUNCH_CHECK();
+        k_st_post<TB, T><<<nblocks(n), TPB, 0, s>>>(P, n, M4, invd, b, bs, xt, x);
+    }
     LAUNCH_CHECK();
     return RICH_OK;
 }

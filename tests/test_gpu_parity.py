@@ -248,3 +248,29 @@ def test_aux_dflux_matches_oracle(rich, torch, orc):
     s.assemble(dev(torch, p))
     rp, col, val = s.export_csr(rich.WHICH_A, 0)
     csr_close(rp, col, val, orc.auxiliary(P, ks, p, dflux=True), 1e-12)
+
+
+@pytest.mark.parametrize("mean", [synth.ARITH, synth.UPSTREAM])
+def test_vcycle_tiled_stencil(rich, torch, orc, mean):
+    """Rows of 48+ cells take the tiled fine-level smoother: a ragged grid
+    (x: 64 + 36, y: 2 x 8 + 5, z: several chunks + tail) against the oracle's
+    V-cycle on the same hierarchy (FP64), and the FP32 V-cycle against it."""
+    P = box_problem(100, 21, 19, mean=mean, dt=10.0)
+    n = P.n
+    ks = random_ks(P, 51)
+    p = random_heads(n, 52, -70, -30)
+    opts = synth.Options(precision=synth.FP64)
+    s = make_solver(rich, torch, P, ks, opts)
+    s.assemble(dev(torch, p))
+    rp, col, val = s.export_csr(rich.WHICH_A, 0)
+    amg = orc.AMG(opts, sp.csr_matrix((val, col, rp), shape=(n, n)))
+    assert s.levels() == amg.levels >= 2
+    b = np.random.default_rng(53).standard_normal(n)
+    xo = amg.apply(b)
+    xg = s.apply_prec(dev(torch, b)).cpu().numpy()
+    assert np.linalg.norm(xg - xo) <= 1e-10 * np.linalg.norm(xo)
+    opts.precision = synth.MIXED
+    s = make_solver(rich, torch, P, ks, opts)
+    s.assemble(dev(torch, p))
+    xm = s.apply_prec(dev(torch, b)).cpu().numpy()
+    assert np.linalg.norm(xm - xo) <= 1e-5 * np.linalg.norm(xo)
