@@ -102,9 +102,22 @@ def cpu_baseline(n_sample=64):
                       f"{st['status']}), rate scaled by the cell ratio {n_sample}^3/256^3"}
 
 
+# Kernel families of the per-kernel table: the library's timer name, the
+# rocprofv3 kernel-name prefix and the source file that defines the kernel.
+FAMILIES = {
+    "update": ("k_update_norm<", "la.hip"),
+    "multidot": ("k_multidot<", "la.hip"),
+    "spmv_J": ("k_spmv_J<float>", "fine.hip"),
+    "vc0_pre": ("k_st25<double, float, false>", "fine.hip"),
+    "residual": ("k_residual", "fine.hip"),
+}
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "traffic_c3_256cube_mixed.md")
+
+
 def algorithmic_bytes(name, n, mixed=True):
-    """Algorithmic HBM bytes of one launch of the fine-grid kernels at n unknowns
-    (the per-row figures of the design doc, section 7); None when not tracked."""
+    """Algorithmic HBM bytes (read, written) of one launch of a fine-grid
+    kernel at n unknowns (the per-cell figures of the kernel table of the
+    design notes); None when the launch size is not fixed by n alone."""
     import re
     t = 4 if mixed else 8
     m = re.search(r"k_(multidot|update_norm)<(\d+)>", name)
@@ -113,16 +126,31 @@ def algorithmic_bytes(name, n, mixed=True):
         return (8 * n * (k + 1), 0) if m.group(1) == "multidot" else (8 * n * (k + 1), 8 * n)
     if "k_spmv_J<float>" in name:
         return (60 * n, 8 * n)
-    if "k_st_pre<double, float>" in name:
+    if "k_st25<double, float, false>" in name or "k_st_pre<double, float>" in name:
         return (8 * n + 5 * t * n, t * n)
     if "k_residual" in name:
         return (24 * n, 8 * n)
     return None
 
 
-def pmc_summary(fetch_csv, write_csv, n):
+def source_digest(fname):
+    import hashlib
+    path = os.path.join(ROOT, "paper_2112_05051_amd", "csrc", fname)
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def source_digests():
+    return {f: source_digest(f) for f in sorted({src for _, src in FAMILIES.values()})}
+
+
+def pmc_summary(fetch_csv, write_csv, n, digests=None):
     """Per-kernel HBM traffic from rocprofv3 FETCH_SIZE / WRITE_SIZE counter runs,
-    calibrated by the 1 GiB device copy of --calibrate-copy."""
+    calibrated by the 1 GiB device copy of --calibrate-copy.  The trailing
+    'family' lines (measured bytes over algorithmic bytes, summed over the
+    family's launches, with the digest of the kernel's source file) are what
+    the benchmark reads back to report measured traffic.  `digests` are the
+    source digests the profiled run printed (its "source_digests")."""
+    digests = digests or source_digests()
     import collections
     import csv
     vals = {}
@@ -138,6 +166,7 @@ def pmc_summary(fetch_csv, write_csv, n):
         copies = [v for k, lst in vals[cname].items() if "copyBuffer" in k for v in lst]
         cal[cname] = gib / max(copies) if copies else 1.0
     lines = [f"calibration (1 GiB copy): FETCH_SIZE x{cal['FETCH_SIZE']:.4f}, WRITE_SIZE x{cal['WRITE_SIZE']:.4f}",
+             "",
              f"{'kernel':58s} {'launches':>8s} {'fetch MB':>10s} {'write MB':>10s} {'alg MB':>10s} {'traffic/alg':>11s}"]
     rows = []
     for k, lst in vals["FETCH_SIZE"].items():
@@ -152,7 +181,30 @@ def pmc_summary(fetch_csv, write_csv, n):
         a = (alg[0] + alg[1]) if alg else None
         lines.append(f"{short:58s} {cnt:8d} {f_b / 1e6:10.2f} {w_b / 1e6:10.2f} "
                      f"{(a / 1e6 if a else float('nan')):10.2f} {((f_b + w_b) / a if a else float('nan')):11.3f}")
+    lines += ["", "family      launches  traffic/alg  source digest"]
+    for fam, (prefix, src) in FAMILIES.items():
+        sel = [r for r in rows if prefix in r[0] and r[4]]
+        if not sel:
+            continue
+        meas = sum((r[2] + r[3]) * r[1] for r in sel)
+        alg = sum((r[4][0] + r[4][1]) * r[1] for r in sel)
+        lines.append(f"family {fam} {sum(r[1] for r in sel)} {meas / alg:.4f} {src} {digests[src]}")
     return "\n".join(lines)
+
+
+def traffic_ratio(family):
+    """Measured/algorithmic HBM bytes of a kernel family from the committed
+    counter summary, or None if there is none or the kernel's source has
+    changed since the counters were taken."""
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    for line in text.splitlines():
+        f = line.split()
+        if len(f) == 6 and f[0] == "family" and f[1] == family:
+            return float(f[3]) if f[5] == source_digest(f[4]) else None
+    return None
 
 
 def stats_summary(stats_csv):
@@ -248,8 +300,9 @@ def main():
                     help="run one 1 GiB device copy first (reference for HBM traffic counters)")
     ap.add_argument("--set", action="append", default=[], metavar="OPT=VALUE",
                     help="override a solver option (experiments; the headline uses the defaults)")
-    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
-                    help="print the calibrated per-kernel traffic table of two rocprofv3 --pmc runs and exit")
+    ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "BENCH_JSON"),
+                    help="print the calibrated per-kernel traffic table of two rocprofv3 --pmc runs "
+                         "(BENCH_JSON: the JSON line the profiled run printed) and exit")
     ap.add_argument("--serving", action="store_true", help="run the ensemble serving benchmark instead")
     ap.add_argument("--serve-count", type=int, default=64)
     ap.add_argument("--serve-steps", type=int, default=20)
@@ -263,7 +316,8 @@ def main():
         print(stats_summary(args.stats_summary))
         return
     if args.pmc_summary:
-        print(pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.n ** 3))
+        digests = json.load(open(args.pmc_summary[2]))["source_digests"]
+        print(pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.n ** 3, digests))
         return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -359,6 +413,7 @@ def main():
         "ls_backtracks": sum(s["ls_backtracks"] for s in mixed["stats"]),
         "hierarchy_n_nnz": mixed["levels"],
         "options": {k: getattr(rec.options, k) for k in vars(rec.options)},
+        "source_digests": source_digests(),
     }
     if fp64 is not None:
         out["fp64"] = {"value": steps / fp64["t_timed"], "ms_per_step": 1e3 * fp64["t_timed"] / max(steps, 1),
@@ -392,8 +447,11 @@ def main():
         out["kernels"] = kern
         dom = max(kern, key=lambda k: kern[k]["total_ms"])
         d = kern[dom]
+        ratio = traffic_ratio(dom) if args.n == 256 else None
         out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": d["gbs"], "peak": HBM_PEAK_GBS,
-                           "unit": "GB/s", "frac": d["gbs"] / HBM_PEAK_GBS, "traffic": None,
+                           "unit": "GB/s", "frac": d["gbs"] / HBM_PEAK_GBS,
+                           "traffic": ratio * d["bytes_per_launch"] if ratio is not None else None,
+                           "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                            "avg_us": d["avg_us"], "bytes_per_launch": d["bytes_per_launch"]}
         if "spmv_J" in kern:
             out["spmv_hbm_gbs"] = kern["spmv_J"]["gbs"]

@@ -320,9 +320,15 @@ __global__ void __launch_bounds__(T25X * T25Y) k_st25(Phys P, const T *__restric
     const int nx = P.nx, ny = P.ny, nz = P.nz;
     const uint32_t n = (uint32_t)nx * (uint32_t)ny * (uint32_t)nz;
     const uint32_t nxy = (uint32_t)nx * (uint32_t)ny;
+    // XCD-aware tile order: the blocks one XCD runs are consecutive tiles
+    // (x fastest), so the halos a tile shares with its neighbours are mostly
+    // fetched once into that XCD's L2.
+    const unsigned ntx = (unsigned)(nx + T25X - 1) / T25X, nty = (unsigned)(ny + T25Y - 1) / T25Y;
+    const unsigned L = xcd_block();
+    if (L >= ntx * nty * (unsigned)((nz + kz - 1) / kz)) return;
     const int tx = threadIdx.x, ty = threadIdx.y;
-    const int i = blockIdx.x * T25X + tx, j = blockIdx.y * T25Y + ty;
-    const int k0 = blockIdx.z * kz, k1 = min(k0 + kz, nz);
+    const int i = (int)(L % ntx) * T25X + tx, j = (int)((L / ntx) % nty) * T25Y + ty;
+    const int k0 = (int)(L / (ntx * nty)) * kz, k1 = min(k0 + kz, nz);
     const bool inside = i < nx && j < ny;
     const TB bs = (TB)bsp[0];
     auto U = [&](uint32_t c) -> T {
@@ -396,9 +402,9 @@ inline int kz25(const Phys &P) {
     while (kz > 1 && tiles * ((P.nz + kz - 1) / kz) < ST25_MIN_BLOCKS) kz /= 2;
     return kz;
 }
-inline dim3 grid25(const Phys &P, int kz) {
-    return dim3((unsigned)((P.nx + T25X - 1) / T25X), (unsigned)((P.ny + T25Y - 1) / T25Y),
-                (unsigned)((P.nz + kz - 1) / kz));
+inline unsigned grid25(const Phys &P, int kz) {
+    int64_t tiles = (int64_t)((P.nx + T25X - 1) / T25X) * ((P.ny + T25Y - 1) / T25Y) * ((P.nz + kz - 1) / kz);
+    return xcd_grid(tiles, 1);
 }
 
 // Plain l1-Jacobi sweep x_out = x_in + D^{-1}(b - M x_in) (used when the

@@ -398,7 +398,7 @@ rich_status vcycle(rich_ctx *h, const double *b, const double *bs, T *z) {
                                          (const T *)H.L[l + 1].x, (T *)Lv.x, s);
         }));
     }
-    return timed(h, RICH_K_VC0_POST, n0 * (20 + 9 * t) + n1 * t, [&] {
+    return timed(h, RICH_K_VC0_POST, n0 * (12 + 6 * t) + n1 * t, [&] {
         return launch_st_post<double, T>(h->P, M4, invd0, b, bs, (const T *)H.L[1].x, H.L[0].agg, z, (T *)H.L[0].r,
                                          s);
     });
