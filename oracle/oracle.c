@@ -439,6 +439,231 @@ void orc_galerkin(int64_t n, const int64_t *rowptr, const int32_t *col, const do
 }
 
 /* ------------------------------------------------------------------------ */
+/* Smoothed aggregation (Section 5.2: the paper's two coarsening schemes,    */
+/* DSVMB and SMATCH, both smooth the piecewise-constant prolongator of the   */
+/* aggregates).  One damped-Jacobi step is applied to the tentative          */
+/* prolongator P_t (P_t(i, agg(i)) = 1):                                     */
+/*     P = (I - omega D^{-1} A) P_t,   D = diag(A),                          */
+/*     omega = 4 / (3 rho),   rho = max_i sum_j |a_ij| / a_ii                */
+/* (rho is the Gershgorin bound on the spectral radius of D^{-1} A; the     */
+/* paper leaves the smoothing parameters to its cited methods).  Row i of P  */
+/* has an entry for every aggregate J that row i of A touches:              */
+/*     P_iJ = [agg(i) = J] - w_i t_iJ,   w_i = omega / a_ii,                 */
+/*     t_iJ = sum of a_ik over the k of row i with agg(k) = J.               */
+/* The coarse matrix is C = P^T (A P) (eq. (Vcycle)'s M_{l+1} = P^T M_l P),  */
+/* formed as Q = A P and then C = P^T Q.  Every sum runs in a fixed order:  */
+/* t_iJ and Q_iJ over k in row i's column order, C_IJ over i ascending, so   */
+/* that the result is reproducible bit for bit.  Patterns are structural:    */
+/* an entry whose terms cancel is kept with the value zero.                  */
+/* ------------------------------------------------------------------------ */
+static int64_t csr_find_diag(const int64_t *rowptr, const int32_t *col, int64_t i)
+{
+    for (int64_t e = rowptr[i]; e < rowptr[i + 1]; e++)
+        if (col[e] == i) return e;
+    return -1;
+}
+
+int64_t orc_smoothed_prolongator_nnz(int64_t n, const int64_t *rowptr, const int32_t *col,
+                                     const int32_t *agg, int64_t nc)
+{
+    int64_t *mark = (int64_t *)malloc((size_t)(nc > 0 ? nc : 1) * sizeof(int64_t));
+    for (int64_t J = 0; J < nc; J++) mark[J] = -1;
+    int64_t nnz = 0;
+    for (int64_t i = 0; i < n; i++)
+        for (int64_t e = rowptr[i]; e < rowptr[i + 1]; e++) {
+            int32_t J = agg[col[e]];
+            if (mark[J] != i) {
+                mark[J] = i;
+                nnz++;
+            }
+        }
+    free(mark);
+    return nnz;
+}
+
+double orc_smoothed_prolongator(int64_t n, const int64_t *rowptr, const int32_t *col,
+                                const double *val, const int32_t *agg, int64_t nc, int64_t *prow,
+                                int32_t *pcol, double *pval)
+{
+    double rho = 0.0;
+    for (int64_t i = 0; i < n; i++) {
+        double s = 0.0;
+        for (int64_t e = rowptr[i]; e < rowptr[i + 1]; e++) s += fabs(val[e]);
+        double r = s / val[csr_find_diag(rowptr, col, i)];
+        if (r > rho) rho = r;
+    }
+    double omega = 4.0 / (3.0 * rho);
+    int64_t *mark = (int64_t *)malloc((size_t)(nc > 0 ? nc : 1) * sizeof(int64_t));
+    double *t = (double *)malloc((size_t)(nc > 0 ? nc : 1) * sizeof(double));
+    int32_t *list = (int32_t *)malloc((size_t)(nc > 0 ? nc : 1) * sizeof(int32_t));
+    for (int64_t J = 0; J < nc; J++) mark[J] = -1;
+    int64_t o = 0;
+    prow[0] = 0;
+    for (int64_t i = 0; i < n; i++) {
+        double w = omega / val[csr_find_diag(rowptr, col, i)];
+        int64_t len = 0;
+        for (int64_t e = rowptr[i]; e < rowptr[i + 1]; e++) {
+            int32_t J = agg[col[e]];
+            if (mark[J] != i) {
+                mark[J] = i;
+                t[J] = 0.0;
+                list[len++] = J;
+            }
+            t[J] += val[e];
+        }
+        qsort(list, (size_t)len, sizeof(int32_t), cmp_i32);
+        for (int64_t a = 0; a < len; a++) {
+            int32_t J = list[a];
+            pcol[o] = J;
+            pval[o++] = (J == agg[i] ? 1.0 : 0.0) - w * t[J];
+        }
+        prow[i + 1] = o;
+    }
+    free(list);
+    free(t);
+    free(mark);
+    return omega;
+}
+
+/* Q = A P (n x nc) in CSR with sorted columns; values when qval != NULL. */
+static int64_t spgemm_rows(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
+                           int64_t nc, const int64_t *prow, const int32_t *pcol, const double *pval,
+                           int64_t *qrow, int32_t *qcol, double *qval)
+{
+    int64_t *mark = (int64_t *)malloc((size_t)(nc > 0 ? nc : 1) * sizeof(int64_t));
+    double *acc = (double *)malloc((size_t)(nc > 0 ? nc : 1) * sizeof(double));
+    int32_t *list = (int32_t *)malloc((size_t)(nc > 0 ? nc : 1) * sizeof(int32_t));
+    for (int64_t J = 0; J < nc; J++) mark[J] = -1;
+    int64_t o = 0;
+    if (qrow) qrow[0] = 0;
+    for (int64_t i = 0; i < n; i++) {
+        int64_t len = 0;
+        for (int64_t e = rowptr[i]; e < rowptr[i + 1]; e++) {
+            int64_t k = col[e];
+            for (int64_t f = prow[k]; f < prow[k + 1]; f++) {
+                int32_t J = pcol[f];
+                if (mark[J] != i) {
+                    mark[J] = i;
+                    acc[J] = 0.0;
+                    list[len++] = J;
+                }
+                if (qval) acc[J] += val[e] * pval[f];
+            }
+        }
+        if (qrow) {
+            qsort(list, (size_t)len, sizeof(int32_t), cmp_i32);
+            for (int64_t a = 0; a < len; a++) {
+                qcol[o + a] = list[a];
+                if (qval) qval[o + a] = acc[list[a]];
+            }
+            qrow[i + 1] = o + len;
+        }
+        o += len;
+    }
+    free(list);
+    free(acc);
+    free(mark);
+    return o;
+}
+
+/* P^T in CSR: row I lists the i with P_iI present, ascending. */
+static void transpose_csr(int64_t n, int64_t nc, const int64_t *prow, const int32_t *pcol,
+                          const double *pval, int64_t *trow, int64_t *tcol, double *tval)
+{
+    for (int64_t I = 0; I <= nc; I++) trow[I] = 0;
+    for (int64_t f = 0; f < prow[n]; f++) trow[pcol[f] + 1]++;
+    for (int64_t I = 0; I < nc; I++) trow[I + 1] += trow[I];
+    int64_t *fill = (int64_t *)malloc((size_t)(nc > 0 ? nc : 1) * sizeof(int64_t));
+    for (int64_t I = 0; I < nc; I++) fill[I] = trow[I];
+    for (int64_t i = 0; i < n; i++)
+        for (int64_t f = prow[i]; f < prow[i + 1]; f++) {
+            int64_t o = fill[pcol[f]]++;
+            tcol[o] = i;
+            tval[o] = pval[f];
+        }
+    free(fill);
+}
+
+/* C = P^T Q: C_IJ = sum over i ascending of P_iI Q_iJ. */
+static int64_t pt_times_q(int64_t n, int64_t nc, const int64_t *trow, const int64_t *tcol,
+                          const double *tval, const int64_t *qrow, const int32_t *qcol,
+                          const double *qval, int64_t *crow, int32_t *ccol, double *cval)
+{
+    int64_t *mark = (int64_t *)malloc((size_t)(nc > 0 ? nc : 1) * sizeof(int64_t));
+    double *acc = (double *)malloc((size_t)(nc > 0 ? nc : 1) * sizeof(double));
+    int32_t *list = (int32_t *)malloc((size_t)(nc > 0 ? nc : 1) * sizeof(int32_t));
+    for (int64_t J = 0; J < nc; J++) mark[J] = -1;
+    int64_t o = 0;
+    if (crow) crow[0] = 0;
+    for (int64_t I = 0; I < nc; I++) {
+        int64_t len = 0;
+        for (int64_t t = trow[I]; t < trow[I + 1]; t++) {
+            int64_t i = tcol[t];
+            for (int64_t f = qrow[i]; f < qrow[i + 1]; f++) {
+                int32_t J = qcol[f];
+                if (mark[J] != I) {
+                    mark[J] = I;
+                    acc[J] = 0.0;
+                    list[len++] = J;
+                }
+                if (cval) acc[J] += tval[t] * qval[f];
+            }
+        }
+        if (crow) {
+            qsort(list, (size_t)len, sizeof(int32_t), cmp_i32);
+            for (int64_t a = 0; a < len; a++) {
+                ccol[o + a] = list[a];
+                if (cval) cval[o + a] = acc[list[a]];
+            }
+            crow[I + 1] = o + len;
+        }
+        o += len;
+    }
+    free(list);
+    free(acc);
+    free(mark);
+    return o;
+}
+
+/* Shared driver of orc_rap_nnz / orc_rap: returns nnz(C); fills C when crow. */
+static int64_t rap(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
+                   int64_t nc, const int64_t *prow, const int32_t *pcol, const double *pval,
+                   int64_t *crow, int32_t *ccol, double *cval)
+{
+    int64_t qnnz = spgemm_rows(n, rowptr, col, NULL, nc, prow, pcol, NULL, NULL, NULL, NULL);
+    int64_t *qrow = (int64_t *)malloc((size_t)(n + 1) * sizeof(int64_t));
+    int32_t *qcol = (int32_t *)malloc((size_t)(qnnz > 0 ? qnnz : 1) * sizeof(int32_t));
+    double *qval = pval ? (double *)malloc((size_t)(qnnz > 0 ? qnnz : 1) * sizeof(double)) : NULL;
+    spgemm_rows(n, rowptr, col, val, nc, prow, pcol, pval, qrow, qcol, qval);
+    int64_t pnnz = prow[n];
+    int64_t *trow = (int64_t *)malloc((size_t)(nc + 1) * sizeof(int64_t));
+    int64_t *tcol = (int64_t *)malloc((size_t)(pnnz > 0 ? pnnz : 1) * sizeof(int64_t));
+    double *tval = (double *)calloc((size_t)(pnnz > 0 ? pnnz : 1), sizeof(double));
+    transpose_csr(n, nc, prow, pcol, pval ? pval : tval, trow, tcol, tval);
+    int64_t cnnz = pt_times_q(n, nc, trow, tcol, tval, qrow, qcol, qval, crow, ccol, cval);
+    free(tval);
+    free(tcol);
+    free(trow);
+    free(qval);
+    free(qcol);
+    free(qrow);
+    return cnnz;
+}
+
+int64_t orc_rap_nnz(int64_t n, const int64_t *rowptr, const int32_t *col, int64_t nc,
+                    const int64_t *prow, const int32_t *pcol)
+{
+    return rap(n, rowptr, col, NULL, nc, prow, pcol, NULL, NULL, NULL, NULL);
+}
+
+void orc_rap(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val, int64_t nc,
+             const int64_t *prow, const int32_t *pcol, const double *pval, int64_t *crow,
+             int32_t *ccol, double *cval)
+{
+    rap(n, rowptr, col, val, nc, prow, pcol, pval, crow, ccol, cval);
+}
+
+/* ------------------------------------------------------------------------ */
 /* AMG hierarchy (Section 5.2).  The aggregates of level l come from        */
 /* `amg_sweeps` pairwise matching sweeps, each sweep matching the Galerkin  */
 /* product of the previous one, so aggregates hold at most 2^sweeps         */
@@ -452,6 +677,10 @@ void orc_galerkin(int64_t n, const int64_t *rowptr, const int32_t *col, const do
 /* rebuilds refresh the fine matrix and its smoother and, when amg_refresh  */
 /* is set (the reading used by default, see DESIGN), recompute every coarse */
 /* matrix from the new fine one with the same aggregates.                   */
+/* With amg_smoothed the prolongator of each level is the smoothed one of  */
+/* orc_smoothed_prolongator and the coarse matrix P^T A P by orc_rap; the   */
+/* aggregates still come from the matching sweeps on piecewise-constant     */
+/* products, and a refresh recomputes P (with its omega) and P^T A P.      */
 /* Smoother: l1-Jacobi, D_ii = sum_j |a_ij| (reading of the paper's "l1-     */
 /* Jacobi").  Coarsest: dense Cholesky when n <= coarse_dense_max, else      */
 /* coarse_l1_sweeps l1-Jacobi sweeps from zero (both keep M^{-1} linear).    */
@@ -462,6 +691,8 @@ struct orc_amg {
     int refresh;
     orc_csr A[ORC_MAXLEV];
     int32_t *agg[ORC_MAXLEV];
+    orc_csr P[ORC_MAXLEV]; /* smoothed prolongator of level l (n_l rows), or empty */
+    int smoothed;
     double *l1[ORC_MAXLEV];
     int dense;
     double *chol; /* n_c x n_c, row-major lower factor */
@@ -576,7 +807,27 @@ int orc_amg_build(const orc_opts *O, int64_t n, const int64_t *rowptr, const int
             break;
         }
         H->agg[l] = comp;
-        galerkin_alloc(&H->A[l], comp, ncomp, &H->A[l + 1]);
+        if (O->amg_smoothed) {
+            const orc_csr *A = &H->A[l];
+            orc_csr *Pl = &H->P[l];
+            int64_t pnnz = orc_smoothed_prolongator_nnz(A->n, A->rowptr, A->col, comp, ncomp);
+            Pl->n = A->n;
+            Pl->rowptr = (int64_t *)malloc((size_t)(A->n + 1) * sizeof(int64_t));
+            Pl->col = (int32_t *)malloc((size_t)(pnnz > 0 ? pnnz : 1) * sizeof(int32_t));
+            Pl->val = (double *)malloc((size_t)(pnnz > 0 ? pnnz : 1) * sizeof(double));
+            orc_smoothed_prolongator(A->n, A->rowptr, A->col, A->val, comp, ncomp, Pl->rowptr, Pl->col,
+                                     Pl->val);
+            int64_t cnnz = orc_rap_nnz(A->n, A->rowptr, A->col, ncomp, Pl->rowptr, Pl->col);
+            orc_csr *C = &H->A[l + 1];
+            C->n = ncomp;
+            C->rowptr = (int64_t *)malloc((size_t)(ncomp + 1) * sizeof(int64_t));
+            C->col = (int32_t *)malloc((size_t)(cnnz > 0 ? cnnz : 1) * sizeof(int32_t));
+            C->val = (double *)malloc((size_t)(cnnz > 0 ? cnnz : 1) * sizeof(double));
+            orc_rap(A->n, A->rowptr, A->col, A->val, ncomp, Pl->rowptr, Pl->col, Pl->val, C->rowptr,
+                    C->col, C->val);
+        } else {
+            galerkin_alloc(&H->A[l], comp, ncomp, &H->A[l + 1]);
+        }
         l++;
     }
     H->nlev = l + 1;
@@ -586,6 +837,7 @@ int orc_amg_build(const orc_opts *O, int64_t n, const int64_t *rowptr, const int
     }
     H->coarse_sweeps = O->coarse_l1_sweeps;
     H->refresh = O->amg_refresh;
+    H->smoothed = O->amg_smoothed;
     H->dense = H->A[H->nlev - 1].n <= O->coarse_dense_max;
     if (H->dense) {
         int st = dense_cholesky(&H->A[H->nlev - 1], &H->chol);
@@ -607,8 +859,17 @@ int orc_amg_update_fine(orc_amg *H, const double *val)
         for (int l = 0; l + 1 < H->nlev; l++) {
             const orc_csr *A = &H->A[l];
             orc_csr *C = &H->A[l + 1];
-            /* same aggregates, so the same pattern: recompute the values */
-            orc_galerkin(A->n, A->rowptr, A->col, A->val, H->agg[l], C->n, C->rowptr, C->col, C->val);
+            /* same aggregates, so the same patterns: recompute the values */
+            if (H->smoothed) {
+                orc_csr *Pl = &H->P[l];
+                orc_smoothed_prolongator(A->n, A->rowptr, A->col, A->val, H->agg[l], C->n, Pl->rowptr,
+                                         Pl->col, Pl->val);
+                orc_rap(A->n, A->rowptr, A->col, A->val, C->n, Pl->rowptr, Pl->col, Pl->val, C->rowptr,
+                        C->col, C->val);
+            } else {
+                orc_galerkin(A->n, A->rowptr, A->col, A->val, H->agg[l], C->n, C->rowptr, C->col,
+                             C->val);
+            }
             l1_diag(C, H->l1[l + 1]);
         }
         last = H->nlev - 1;
@@ -641,11 +902,27 @@ void orc_amg_level_export(const orc_amg *H, int l, int64_t *rowptr, int32_t *col
 
 int orc_amg_coarse_is_dense(const orc_amg *H) { return H->dense; }
 
+int64_t orc_amg_prolongator_nnz(const orc_amg *H, int l)
+{
+    if (!H->smoothed || l >= H->nlev - 1) return 0;
+    return H->P[l].rowptr[H->P[l].n];
+}
+
+void orc_amg_prolongator_export(const orc_amg *H, int l, int64_t *prow, int32_t *pcol,
+                                double *pval)
+{
+    const orc_csr *Pl = &H->P[l];
+    memcpy(prow, Pl->rowptr, (size_t)(Pl->n + 1) * sizeof(int64_t));
+    memcpy(pcol, Pl->col, (size_t)Pl->rowptr[Pl->n] * sizeof(int32_t));
+    memcpy(pval, Pl->val, (size_t)Pl->rowptr[Pl->n] * sizeof(double));
+}
+
 void orc_amg_destroy(orc_amg *H)
 {
     if (!H) return;
     for (int l = 0; l < H->nlev; l++) {
         csr_free(&H->A[l]);
+        csr_free(&H->P[l]);
         free(H->agg[l]);
         free(H->l1[l]);
     }
@@ -699,9 +976,21 @@ static void vcycle(const orc_amg *H, int l, const double *b, double *x)
     for (int64_t i = 0; i < n; i++) x[i] = b[i] / d[i];
     orc_csr_matvec(n, A->rowptr, A->col, A->val, x, r);
     for (int64_t i = 0; i < n; i++) r[i] = b[i] - r[i];
-    for (int64_t i = 0; i < n; i++) bc[agg[i]] += r[i];
-    vcycle(H, l + 1, bc, xc);
-    for (int64_t i = 0; i < n; i++) x[i] += xc[agg[i]];
+    if (H->smoothed) { /* b_c = P^T r, then x += P x_c */
+        const orc_csr *Pl = &H->P[l];
+        for (int64_t i = 0; i < n; i++)
+            for (int64_t f = Pl->rowptr[i]; f < Pl->rowptr[i + 1]; f++) bc[Pl->col[f]] += Pl->val[f] * r[i];
+        vcycle(H, l + 1, bc, xc);
+        for (int64_t i = 0; i < n; i++) {
+            double t = 0.0;
+            for (int64_t f = Pl->rowptr[i]; f < Pl->rowptr[i + 1]; f++) t += Pl->val[f] * xc[Pl->col[f]];
+            x[i] += t;
+        }
+    } else {
+        for (int64_t i = 0; i < n; i++) bc[agg[i]] += r[i];
+        vcycle(H, l + 1, bc, xc);
+        for (int64_t i = 0; i < n; i++) x[i] += xc[agg[i]];
+    }
     orc_csr_matvec(n, A->rowptr, A->col, A->val, x, r);
     for (int64_t i = 0; i < n; i++) x[i] += (b[i] - r[i]) / d[i];
     free(r);

@@ -60,6 +60,7 @@ typedef struct {
     int coarse_l1_sweeps;
     int amg_refresh; /* 0: later rebuilds refresh the smoother only; 1: also the coarse matrices */
     int aux_dflux;   /* 1: the auxiliary matrix's diagonal also takes the flux-derivative terms */
+    int amg_smoothed; /* 1: smoothed-aggregation prolongators; 0: piecewise constant */
 } orc_opts;
 
 typedef struct {
@@ -103,6 +104,18 @@ int64_t orc_galerkin_nnz(int64_t n, const int64_t *rowptr, const int32_t *col, c
 void orc_galerkin(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
                   const int32_t *agg, int64_t nc, int64_t *crow, int32_t *ccol, double *cval);
 
+/* ---- smoothed aggregation: P = (I - omega D^{-1} A) P_t, C = P^T (A P) ---- */
+int64_t orc_smoothed_prolongator_nnz(int64_t n, const int64_t *rowptr, const int32_t *col,
+                                     const int32_t *agg, int64_t nc);
+double orc_smoothed_prolongator(int64_t n, const int64_t *rowptr, const int32_t *col,
+                                const double *val, const int32_t *agg, int64_t nc, int64_t *prow,
+                                int32_t *pcol, double *pval); /* returns omega */
+int64_t orc_rap_nnz(int64_t n, const int64_t *rowptr, const int32_t *col, int64_t nc,
+                    const int64_t *prow, const int32_t *pcol);
+void orc_rap(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val, int64_t nc,
+             const int64_t *prow, const int32_t *pcol, const double *pval, int64_t *crow,
+             int32_t *ccol, double *cval);
+
 /* ---- AMG hierarchy (opaque) ---- */
 typedef struct orc_amg orc_amg;
 int orc_amg_build(const orc_opts *O, int64_t n, const int64_t *rowptr, const int32_t *col,
@@ -113,6 +126,9 @@ void orc_amg_level_info(const orc_amg *H, int l, int64_t *n, int64_t *nnz);
 void orc_amg_level_export(const orc_amg *H, int l, int64_t *rowptr, int32_t *col, double *val,
                           int32_t *agg /* nullable; only for l < levels-1 */);
 int orc_amg_coarse_is_dense(const orc_amg *H);
+int64_t orc_amg_prolongator_nnz(const orc_amg *H, int l); /* 0 unless smoothed and l < levels-1 */
+void orc_amg_prolongator_export(const orc_amg *H, int l, int64_t *prow, int32_t *pcol,
+                                double *pval);
 void orc_amg_apply(const orc_amg *H, const double *b, double *x);
 void orc_amg_destroy(orc_amg *H);
 

@@ -47,7 +47,7 @@ class COpts(C.Structure):
                 ("amg_max_levels", C.c_int), ("amg_coarse_size", C.c_int64),
                 ("amg_sweeps", C.c_int), ("coarse_dense_max", C.c_int64),
                 ("coarse_l1_sweeps", C.c_int), ("amg_refresh", C.c_int),
-                ("aux_dflux", C.c_int)]
+                ("aux_dflux", C.c_int), ("amg_smoothed", C.c_int)]
 
 
 class CStats(C.Structure):
@@ -82,6 +82,16 @@ def lib():
         L.orc_galerkin_nnz.argtypes = [C.c_int64, i64, i32, i32, C.c_int64]
         L.orc_galerkin_nnz.restype = C.c_int64
         L.orc_galerkin.argtypes = [C.c_int64, i64, i32, d, i32, C.c_int64, i64, i32, d]
+        L.orc_smoothed_prolongator_nnz.argtypes = [C.c_int64, i64, i32, i32, C.c_int64]
+        L.orc_smoothed_prolongator_nnz.restype = C.c_int64
+        L.orc_smoothed_prolongator.argtypes = [C.c_int64, i64, i32, d, i32, C.c_int64, i64, i32, d]
+        L.orc_smoothed_prolongator.restype = C.c_double
+        L.orc_rap_nnz.argtypes = [C.c_int64, i64, i32, C.c_int64, i64, i32]
+        L.orc_rap_nnz.restype = C.c_int64
+        L.orc_rap.argtypes = [C.c_int64, i64, i32, d, C.c_int64, i64, i32, d, i64, i32, d]
+        L.orc_amg_prolongator_nnz.argtypes = [vp, C.c_int]
+        L.orc_amg_prolongator_nnz.restype = C.c_int64
+        L.orc_amg_prolongator_export.argtypes = [vp, C.c_int, i64, i32, d]
         L.orc_amg_build.argtypes = [P(COpts), C.c_int64, i64, i32, d, P(vp)]
         L.orc_amg_update_fine.argtypes = [vp, d]
         L.orc_amg_levels.argtypes = [vp]
@@ -209,6 +219,35 @@ def galerkin(A, agg, nc):
     return sp.csr_matrix((cval, ccol, crp), shape=(nc, nc))
 
 
+def smoothed_prolongator(A, agg, nc):
+    """P = (I - omega D^{-1} A) P_t for the aggregates agg; returns (P, omega)."""
+    rp, col, val = _csr_parts(A)
+    agg = np.ascontiguousarray(agg, np.int32)
+    n = A.shape[0]
+    nnz = lib().orc_smoothed_prolongator_nnz(n, _i64(rp), _i32(col), _i32(agg), nc)
+    prow = np.empty(n + 1, np.int64)
+    pcol = np.empty(nnz, np.int32)
+    pval = np.empty(nnz)
+    omega = lib().orc_smoothed_prolongator(n, _i64(rp), _i32(col), _d(val), _i32(agg), nc, _i64(prow),
+                                           _i32(pcol), _d(pval))
+    return sp.csr_matrix((pval, pcol, prow), shape=(n, nc)), float(omega)
+
+
+def rap(A, P):
+    """C = P^T (A P) with the oracle's summation order."""
+    rp, col, val = _csr_parts(A)
+    P = sp.csr_matrix(P)
+    prow, pcol, pval = _csr_parts(P)
+    n, nc = P.shape
+    nnz = lib().orc_rap_nnz(n, _i64(rp), _i32(col), nc, _i64(prow), _i32(pcol))
+    crow = np.empty(nc + 1, np.int64)
+    ccol = np.empty(nnz, np.int32)
+    cval = np.empty(nnz)
+    lib().orc_rap(n, _i64(rp), _i32(col), _d(val), nc, _i64(prow), _i32(pcol), _d(pval), _i64(crow),
+                  _i32(ccol), _d(cval))
+    return sp.csr_matrix((cval, ccol, crow), shape=(nc, nc))
+
+
 class AMG:
     """Oracle AMG hierarchy built from a fine matrix (keeps its own copies)."""
 
@@ -246,6 +285,19 @@ class AMG:
         lib().orc_amg_level_export(self._h, l, _i64(rp), _i32(col), _d(val),
                                    _i32(agg) if agg is not None else None)
         return sp.csr_matrix((val, col, rp), shape=(n.value, n.value)), agg
+
+    def prolongator(self, l):
+        """The smoothed prolongator of level l (None for piecewise-constant hierarchies)."""
+        nnz = lib().orc_amg_prolongator_nnz(self._h, l)
+        if nnz == 0:
+            return None
+        n = self.level(l)[0].shape[0]
+        nc = self.level(l + 1)[0].shape[0]
+        prow = np.empty(n + 1, np.int64)
+        pcol = np.empty(nnz, np.int32)
+        pval = np.empty(nnz)
+        lib().orc_amg_prolongator_export(self._h, l, _i64(prow), _i32(pcol), _d(pval))
+        return sp.csr_matrix((pval, pcol, prow), shape=(n, nc))
 
     def apply(self, b):
         b = _f64(b)
