@@ -46,11 +46,14 @@ def run_gpu(rec, precision, warmup, steps, ks_dev, p0_dev, profile):
     s = rich.Solver(rec.problem, opts, ks_dev)
     s.set_state(p0_dev)
     torch.cuda.synchronize()
+    log(f"[bench] warm-up ({warmup} steps, includes the AMG set-up)")
     t0 = time.perf_counter()
     warm = s.step(warmup) if warmup > 0 else []
     torch.cuda.synchronize()
     t_warm = time.perf_counter() - t0
-    log(f"[bench] precision={'mixed' if precision else 'fp64'} warmup {warmup} steps {t_warm:.2f}s")
+    log(f"[bench] precision={'mixed' if precision else 'fp64'} warmup {warmup} steps {t_warm:.2f}s "
+        f"(AMG set-up and refreshes {sum(w['t_setup'] for w in warm):.2f}s, "
+        f"GMRES {sum(w['gmres_its'] for w in warm)} its)")
     if profile:
         s.profile(True)
     p_prev = None

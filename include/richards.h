@@ -104,6 +104,11 @@ typedef struct rich_solver_opts {
     int amg_refresh;     /* on every rebuild after the first: 0 = refresh the fine level and its
                             smoother only (coarse matrices frozen, Section 6); 1 = also recompute
                             every coarse matrix from the new fine one, aggregates kept */
+    int amg_smoothed;    /* number of levels, from the finest, whose prolongator is smoothed
+                            (Section 5.2), 0..16: P = (I - omega D^{-1} A) P_t with D = diag(A),
+                            omega = 4 / (3 max_i sum_j |a_ij| / a_ii), and coarse matrix P^T A P;
+                            the other levels keep the piecewise-constant P_t.  Smoothing costs
+                            set-up work and denser coarse levels and saves GMRES iterations */
 } rich_solver_opts_t;
 
 /* Per-time-step counters and timings (host wall seconds of each phase). */
@@ -172,6 +177,8 @@ rich_status rich_levels(rich_handle_t h, int *nlev_host);
 rich_status rich_level_size(rich_handle_t h, int level, int64_t *n_host, int64_t *nnz_host);
 #define RICH_WHICH_J 0  /* the Jacobian (level ignored) */
 #define RICH_WHICH_A 1  /* the level-l AMG matrix, FP64 (level 0 = auxiliary M) */
+#define RICH_WHICH_P 2  /* the smoothed prolongator of level l -> l+1 (n_l rows, n_{l+1}
+                           columns); RICH_EINVAL for piecewise-constant hierarchies */
 /* Copy a matrix to host CSR (columns ascending).  *nnz_inout: capacity in,
  * entries written out; RICH_EINVAL if the capacity is too small. */
 rich_status rich_export_csr(rich_handle_t h, int which, int level, int64_t *rowptr_host,

@@ -677,10 +677,11 @@ void orc_rap(int64_t n, const int64_t *rowptr, const int32_t *col, const double 
 /* rebuilds refresh the fine matrix and its smoother and, when amg_refresh  */
 /* is set (the reading used by default, see DESIGN), recompute every coarse */
 /* matrix from the new fine one with the same aggregates.                   */
-/* With amg_smoothed the prolongator of each level is the smoothed one of  */
-/* orc_smoothed_prolongator and the coarse matrix P^T A P by orc_rap; the   */
-/* aggregates still come from the matching sweeps on piecewise-constant     */
-/* products, and a refresh recomputes P (with its omega) and P^T A P.      */
+/* The first amg_smoothed levels (from the finest) take the smoothed       */
+/* prolongator of orc_smoothed_prolongator and the coarse matrix P^T A P   */
+/* of orc_rap; the aggregates still come from the matching sweeps on       */
+/* piecewise-constant products, and a refresh recomputes P (with its       */
+/* omega) and P^T A P.                                                      */
 /* Smoother: l1-Jacobi, D_ii = sum_j |a_ij| (reading of the paper's "l1-     */
 /* Jacobi").  Coarsest: dense Cholesky when n <= coarse_dense_max, else      */
 /* coarse_l1_sweeps l1-Jacobi sweeps from zero (both keep M^{-1} linear).    */
@@ -692,7 +693,6 @@ struct orc_amg {
     orc_csr A[ORC_MAXLEV];
     int32_t *agg[ORC_MAXLEV];
     orc_csr P[ORC_MAXLEV]; /* smoothed prolongator of level l (n_l rows), or empty */
-    int smoothed;
     double *l1[ORC_MAXLEV];
     int dense;
     double *chol; /* n_c x n_c, row-major lower factor */
@@ -807,7 +807,7 @@ int orc_amg_build(const orc_opts *O, int64_t n, const int64_t *rowptr, const int
             break;
         }
         H->agg[l] = comp;
-        if (O->amg_smoothed) {
+        if (l < O->amg_smoothed) {
             const orc_csr *A = &H->A[l];
             orc_csr *Pl = &H->P[l];
             int64_t pnnz = orc_smoothed_prolongator_nnz(A->n, A->rowptr, A->col, comp, ncomp);
@@ -837,7 +837,6 @@ int orc_amg_build(const orc_opts *O, int64_t n, const int64_t *rowptr, const int
     }
     H->coarse_sweeps = O->coarse_l1_sweeps;
     H->refresh = O->amg_refresh;
-    H->smoothed = O->amg_smoothed;
     H->dense = H->A[H->nlev - 1].n <= O->coarse_dense_max;
     if (H->dense) {
         int st = dense_cholesky(&H->A[H->nlev - 1], &H->chol);
@@ -860,7 +859,7 @@ int orc_amg_update_fine(orc_amg *H, const double *val)
             const orc_csr *A = &H->A[l];
             orc_csr *C = &H->A[l + 1];
             /* same aggregates, so the same patterns: recompute the values */
-            if (H->smoothed) {
+            if (H->P[l].rowptr) {
                 orc_csr *Pl = &H->P[l];
                 orc_smoothed_prolongator(A->n, A->rowptr, A->col, A->val, H->agg[l], C->n, Pl->rowptr,
                                          Pl->col, Pl->val);
@@ -904,7 +903,7 @@ int orc_amg_coarse_is_dense(const orc_amg *H) { return H->dense; }
 
 int64_t orc_amg_prolongator_nnz(const orc_amg *H, int l)
 {
-    if (!H->smoothed || l >= H->nlev - 1) return 0;
+    if (l >= H->nlev - 1 || !H->P[l].rowptr) return 0;
     return H->P[l].rowptr[H->P[l].n];
 }
 
@@ -976,7 +975,7 @@ static void vcycle(const orc_amg *H, int l, const double *b, double *x)
     for (int64_t i = 0; i < n; i++) x[i] = b[i] / d[i];
     orc_csr_matvec(n, A->rowptr, A->col, A->val, x, r);
     for (int64_t i = 0; i < n; i++) r[i] = b[i] - r[i];
-    if (H->smoothed) { /* b_c = P^T r, then x += P x_c */
+    if (H->P[l].rowptr) { /* b_c = P^T r, then x += P x_c */
         const orc_csr *Pl = &H->P[l];
         for (int64_t i = 0; i < n; i++)
             for (int64_t f = Pl->rowptr[i]; f < Pl->rowptr[i + 1]; f++) bc[Pl->col[f]] += Pl->val[f] * r[i];

@@ -60,7 +60,7 @@ typedef struct {
     int coarse_l1_sweeps;
     int amg_refresh; /* 0: later rebuilds refresh the smoother only; 1: also the coarse matrices */
     int aux_dflux;   /* 1: the auxiliary matrix's diagonal also takes the flux-derivative terms */
-    int amg_smoothed; /* 1: smoothed-aggregation prolongators; 0: piecewise constant */
+    int amg_smoothed; /* levels (from the finest) with smoothed prolongators; 0: none */
 } orc_opts;
 
 typedef struct {

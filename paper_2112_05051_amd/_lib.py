@@ -20,7 +20,7 @@ EINVAL, ENOMEM, EBUDGET, NONFINITE = -1, -2, -3, -4
 LINSOLVE_FAIL, LINESEARCH_FAIL, MAXITER, NOT_SPD, EHIP, ESTATE = -5, -6, -7, -9, -10, -11
 STEP_TOO_SMALL = 2
 PREC_FP64, PREC_MIXED = 0, 1
-WHICH_J, WHICH_A = 0, 1
+WHICH_J, WHICH_A, WHICH_P = 0, 1, 2
 
 
 class RichError(RuntimeError):
@@ -46,7 +46,7 @@ class Opts(C.Structure):
                 ("amg_max_levels", C.c_int), ("amg_coarse_size", C.c_int64),
                 ("amg_sweeps", C.c_int), ("coarse_dense_max", C.c_int64),
                 ("coarse_l1_sweeps", C.c_int), ("precision", C.c_int), ("gmres_reorth", C.c_double),
-                ("aux_dflux", C.c_int), ("amg_refresh", C.c_int)]
+                ("aux_dflux", C.c_int), ("amg_refresh", C.c_int), ("amg_smoothed", C.c_int)]
 
 
 class StepStats(C.Structure):
@@ -274,7 +274,17 @@ class Solver:
 
     def export_csr(self, which: int, level: int = 0):
         """(indptr int64, indices int32, data float64) numpy arrays."""
-        if which == WHICH_J or level == 0:
+        if which == WHICH_P:
+            n, cap = self.level_size(level)[0], 0
+            nnz = C.c_int64(0)
+            dummy = np.empty(1, np.int64)
+            st = self._L.rich_export_csr(self._h, which, level, dummy.ctypes.data_as(C.POINTER(C.c_int64)),
+                                         dummy.ctypes.data_as(C.POINTER(C.c_int32)),
+                                         dummy.ctypes.data_as(C.POINTER(C.c_double)), C.byref(nnz))
+            if nnz.value == 0:
+                _check(st, "rich_export_csr")
+            cap = nnz.value
+        elif which == WHICH_J or level == 0:
             n, cap = self.n, 7 * self.n
         else:
             n, cap = self.level_size(level)

@@ -271,36 +271,29 @@ __global__ void k_iota(int64_t n, int32_t *__restrict__ x) {
 // Rows are processed by groups of G lanes (4 or 8, by the level's mean row
 // length) that stride over the row's entries; the group sum is formed with
 // shuffles in a fixed lane order.
-template <int G, class T>
-__device__ inline T group_sum(T v) {
-#pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) v += __shfl_down(v, o, G);
-    return v;
-}
 
+// pre-smoothing from zero and residual: x0 = D^{-1} b (stored by the
+// restriction that produced b), r = b - A x0
 template <int G, class TB, class T>
 __global__ void k_csr_pre(int64_t n, const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
-                          const T *__restrict__ val, const T *__restrict__ invd, const TB *__restrict__ b,
+                          const T *__restrict__ val, const T *__restrict__ x0, const TB *__restrict__ b,
                           T *__restrict__ r) {
     int64_t row = ((int64_t)xcd_block() * blockDim.x + threadIdx.x) / G;
     int lane = threadIdx.x % G;
     if (row >= n) return;
     T s = 0;
-    for (int64_t e = rowptr[row] + lane; e < rowptr[row + 1]; e += G) {
-        int32_t j = col[e];
-        s += val[e] * ((T)b[j] * invd[j]);
-    }
+    for (int64_t e = rowptr[row] + lane; e < rowptr[row + 1]; e += G) s += val[e] * x0[col[e]];
     s = group_sum<G>(s);
     if (lane == 0) r[row] = (T)b[row] - s;
 }
 
-// prolongation: xt = D^{-1} b + P xc
-template <class TB, class T>
-__global__ void k_csr_prolong(int64_t n, const T *__restrict__ invd, const TB *__restrict__ b,
-                              const T *__restrict__ xc, const int32_t *__restrict__ agg, T *__restrict__ xt) {
+// prolongation: xt = x0 + P xc
+template <class T>
+__global__ void k_csr_prolong(int64_t n, const T *__restrict__ x0, const T *__restrict__ xc,
+                              const int32_t *__restrict__ agg, T *__restrict__ xt) {
     int64_t row = (int64_t)xcd_block() * blockDim.x + threadIdx.x;
     if (row >= n) return;
-    xt[row] = (T)b[row] * invd[row] + xc[agg[row]];
+    xt[row] = x0[row] + xc[agg[row]];
 }
 
 // post-smoothing: x = xt + D^{-1}(b - A xt)
@@ -334,15 +327,77 @@ __global__ void k_csr_sweep(int64_t n, const int64_t *__restrict__ rowptr, const
     if (lane == 0) xout[row] = xin[row] + invd[row] * ((T)b[row] - s);
 }
 
+// ------------------------------------------------ CSR-stream levels
+// A block takes a run of whole rows holding at most STREAM_CHUNK +
+// STREAM_MAXROW - 1 entries: its threads first form the products of all the
+// run's entries in entry order (coalesced loads, neighbouring gathers) into
+// LDS, then one thread per row adds its row's products in order.
+constexpr int STREAM_LDS = STREAM_CHUNK + STREAM_MAXROW;
+// PRE: v = x0, out = b - A x0;  POST: v = xt, out = xt + D^{-1}(b - A xt).
+// G lanes add up a row.
+template <int G, class TB, class T, bool POST>
+__global__ void __launch_bounds__(256) k_csr_stream(const int64_t *__restrict__ rb, const int64_t *__restrict__ rowptr,
+                                                    const int32_t *__restrict__ col, const T *__restrict__ val,
+                                                    const T *__restrict__ invd, const TB *__restrict__ b,
+                                                    const T *__restrict__ v, T *__restrict__ out) {
+    __shared__ T prod[STREAM_LDS];
+    int64_t blk = xcd_block();
+    int64_t r0 = rb[blk], r1 = rb[blk + 1];
+    if (r0 >= r1) return;
+    int64_t e0 = rowptr[r0], e1 = rowptr[r1];
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) prod[e - e0] = val[e] * v[col[e]];
+    __syncthreads();
+    const int lane = threadIdx.x % G;
+    // every lane of a group runs the same number of row iterations (shuffles)
+    for (int64_t rbase = r0; rbase < r1; rbase += blockDim.x / G) {
+        int64_t row = rbase + threadIdx.x / G;
+        T s = 0;
+        if (row < r1)
+            for (int64_t e = rowptr[row] + lane; e < rowptr[row + 1]; e += G) s += prod[e - e0];
+        s = group_sum<G>(s);
+        if (lane == 0 && row < r1) {
+            if (POST) out[row] = v[row] + invd[row] * ((T)b[row] - s);
+            else out[row] = (T)b[row] - s;
+        }
+    }
+}
+
+// rb[b] = first row whose first entry is at or past b * STREAM_CHUNK; the
+// blocks past the last chunk (grid padding) are empty
+__global__ void k_stream_rb(int64_t n, int64_t nrb, int64_t ngrid, const int64_t *__restrict__ rowptr,
+                            int64_t *__restrict__ rb) {
+    int64_t blk = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (blk > ngrid) return;
+    if (blk >= nrb) {
+        rb[blk] = n;
+        return;
+    }
+    int64_t target = blk * (int64_t)STREAM_CHUNK, lo = 0, hi = n;
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (rowptr[mid] < target) lo = mid + 1;
+        else hi = mid;
+    }
+    rb[blk] = lo;
+}
+
+__global__ void k_max_rowlen(int64_t n, const int64_t *__restrict__ rowptr, int *__restrict__ too_long) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && rowptr[i + 1] - rowptr[i] > STREAM_MAXROW) too_long[0] = 1;
+}
+
 // bc[I] = sum over the members of I (ascending) of r
+// (and x0c[I] = D_c^{-1} bc[I], the coarse pre-smoothed iterate, when x0c is set)
 template <class T>
 __global__ void k_restrict(int64_t nc, const int64_t *__restrict__ mptr, const int32_t *__restrict__ mem,
-                           const T *__restrict__ r, T *__restrict__ bc) {
+                           const T *__restrict__ r, T *__restrict__ bc, const T *__restrict__ invdc,
+                           T *__restrict__ x0c) {
     int64_t I = (int64_t)xcd_block() * blockDim.x + threadIdx.x;
     if (I >= nc) return;
     T s = 0;
     for (int64_t t = mptr[I]; t < mptr[I + 1]; t++) s += r[mem[t]];
     bc[I] = s;
+    if (x0c) x0c[I] = s * invdc[I];
 }
 
 // x = Ainv b, one wavefront per row (row-major Ainv)
@@ -634,6 +689,32 @@ rich_status galerkin(const CsrDev &A, const int32_t *agg, int64_t nc, CsrDev *C,
     return RICH_OK;
 }
 
+rich_status stream_blocks(Level &Lv, DevAlloc &mem, hipStream_t s) {
+    if (Lv.n == 0) return RICH_OK;
+    DevAlloc tmp;
+    int *flag;
+    RICH_TRY(tmp.get(&flag, 1));
+    HIP_TRY(hipMemsetAsync(flag, 0, sizeof(int), s));
+    k_max_rowlen<<<nblocks(Lv.n), TPB, 0, s>>>(Lv.n, Lv.rowptr, flag);
+    LAUNCH_CHECK();
+    int too_long = 0;
+    HIP_TRY(hipMemcpyAsync(&too_long, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (too_long) return RICH_OK;
+    int64_t nrb = (Lv.nnz + STREAM_CHUNK - 1) / STREAM_CHUNK;
+    // lanes per row in the reduction phase, by the mean row length
+    int64_t mean = Lv.nnz / Lv.n;
+    Lv.sg = mean < 8 ? 1 : mean < 16 ? 2 : mean < 32 ? 4 : 8;
+    // the launch grid is rounded up to a multiple of the XCD count: pad with empty blocks
+    int64_t ngrid = xcd_grid(nrb, 1);
+    RICH_TRY(mem.get(&Lv.rb, ngrid + 1));
+    k_stream_rb<<<nblocks(ngrid + 1), TPB, 0, s>>>(Lv.n, nrb, ngrid, Lv.rowptr, Lv.rb);
+    LAUNCH_CHECK();
+    Lv.nrb = ngrid;
+    HIP_TRY(hipStreamSynchronize(s));  // tmp is freed on return
+    return RICH_OK;
+}
+
 rich_status csr_invd(const CsrDev &A, double *invd, float *invdf, hipStream_t s) {
     if (A.n == 0) return RICH_OK;
     k_csr_invd<<<nblocks(A.n), TPB, 0, s>>>(A.n, A.rowptr, A.val, invd, invdf);
@@ -683,25 +764,47 @@ rich_status dense_inverse(const CsrDev &A, double *D, double *ws, hipStream_t s)
 // lanes per row: 4 for short rows, 8 otherwise
 static inline bool short_rows(const Level &Lv) { return Lv.nnz < 16 * Lv.n; }
 
+template <class TB, class T, bool POST>
+void launch_stream(const Level &Lv, const T *val, const T *invd, const TB *b, const T *v, T *out, hipStream_t s) {
+    unsigned g = (unsigned)Lv.nrb;
+    switch (Lv.sg) {
+    case 1: k_csr_stream<1, TB, T, POST><<<g, 256, 0, s>>>(Lv.rb, Lv.rowptr, Lv.col, val, invd, b, v, out); break;
+    case 2: k_csr_stream<2, TB, T, POST><<<g, 256, 0, s>>>(Lv.rb, Lv.rowptr, Lv.col, val, invd, b, v, out); break;
+    case 4: k_csr_stream<4, TB, T, POST><<<g, 256, 0, s>>>(Lv.rb, Lv.rowptr, Lv.col, val, invd, b, v, out); break;
+    default: k_csr_stream<8, TB, T, POST><<<g, 256, 0, s>>>(Lv.rb, Lv.rowptr, Lv.col, val, invd, b, v, out); break;
+    }
+}
+
 template <class TB, class T>
-rich_status launch_csr_pre(const Level &Lv, const T *val, const T *invd, const TB *b, T *r, hipStream_t s) {
+rich_status launch_csr_pre(const Level &Lv, const T *val, const T *x0, const TB *b, T *r, hipStream_t s) {
     if (Lv.n == 0) return RICH_OK;
+    if (Lv.rb) {
+        launch_stream<TB, T, false>(Lv, val, nullptr, b, x0, r, s);
+        LAUNCH_CHECK();
+        return RICH_OK;
+    }
     if (short_rows(Lv))
-        k_csr_pre<4, TB, T><<<xcd_grid(Lv.n * 4, TPB), TPB, 0, s>>>(Lv.n, Lv.rowptr, Lv.col, val, invd, b, r);
+        k_csr_pre<4, TB, T><<<xcd_grid(Lv.n * 4, TPB), TPB, 0, s>>>(Lv.n, Lv.rowptr, Lv.col, val, x0, b, r);
     else
-        k_csr_pre<8, TB, T><<<xcd_grid(Lv.n * 8, TPB), TPB, 0, s>>>(Lv.n, Lv.rowptr, Lv.col, val, invd, b, r);
+        k_csr_pre<8, TB, T><<<xcd_grid(Lv.n * 8, TPB), TPB, 0, s>>>(Lv.n, Lv.rowptr, Lv.col, val, x0, b, r);
     LAUNCH_CHECK();
     return RICH_OK;
 }
 
 template <class TB, class T>
-rich_status launch_csr_post(const Level &Lv, const T *val, const T *invd, const TB *b, const T *xc, T *x,
-                            hipStream_t s) {
+rich_status launch_csr_post(const Level &Lv, const T *val, const T *invd, const TB *b, const T *x0, const T *xc,
+                            T *x, hipStream_t s) {
     if (Lv.n == 0) return RICH_OK;
     T *xt = (T *)Lv.r;  // the residual of this level is dead by now
-    k_csr_prolong<TB, T><<<xcd_grid(Lv.n, TPB), TPB, 0, s>>>(Lv.n, invd, b, xc, Lv.agg, xt);
-    LAUNCH_CHECK();
-    if (short_rows(Lv))
+    if (Lv.prow) {
+        RICH_TRY(launch_sa_prolong<TB, T>(Lv, invd, b, nullptr, x0, xc, xt, s));
+    } else {
+        k_csr_prolong<T><<<xcd_grid(Lv.n, TPB), TPB, 0, s>>>(Lv.n, x0, xc, Lv.agg, xt);
+        LAUNCH_CHECK();
+    }
+    if (Lv.rb)
+        launch_stream<TB, T, true>(Lv, val, invd, b, xt, x, s);
+    else if (short_rows(Lv))
         k_csr_post<4, TB, T><<<xcd_grid(Lv.n * 4, TPB), TPB, 0, s>>>(Lv.n, Lv.rowptr, Lv.col, val, invd, b, xt, x);
     else
         k_csr_post<8, TB, T><<<xcd_grid(Lv.n * 8, TPB), TPB, 0, s>>>(Lv.n, Lv.rowptr, Lv.col, val, invd, b, xt, x);
@@ -710,9 +813,10 @@ rich_status launch_csr_post(const Level &Lv, const T *val, const T *invd, const 
 }
 
 template <class T>
-rich_status launch_restrict(const Level &Lv, const T *r, T *bc, int64_t nc, hipStream_t s) {
+rich_status launch_restrict(const Level &Lv, const T *r, T *bc, int64_t nc, const T *invdc, T *x0c, hipStream_t s) {
     if (nc == 0) return RICH_OK;
-    k_restrict<T><<<xcd_grid(nc, TPB), TPB, 0, s>>>(nc, Lv.mptr, Lv.mem, r, bc);
+    if (Lv.prow) return launch_sa_restrict<T>(Lv, r, bc, nc, invdc, x0c, s);
+    k_restrict<T><<<xcd_grid(nc, TPB), TPB, 0, s>>>(nc, Lv.mptr, Lv.mem, r, bc, invdc, x0c);
     LAUNCH_CHECK();
     return RICH_OK;
 }
@@ -751,15 +855,17 @@ rich_status launch_csr_spmv(const CsrDev &A, const double *x, double *y, hipStre
 
 #define INST_CSR(TB, T)                                                                                         \
     template rich_status launch_csr_pre<TB, T>(const Level &, const T *, const T *, const TB *, T *, hipStream_t); \
-    template rich_status launch_csr_post<TB, T>(const Level &, const T *, const T *, const TB *, const T *, T *,   \
-                                                hipStream_t);                                                     \
+    template rich_status launch_csr_post<TB, T>(const Level &, const T *, const T *, const TB *, const T *,        \
+                                                const T *, T *, hipStream_t);                                     \
     template rich_status launch_dense_gemv<TB, T>(const T *, const TB *, T *, int64_t, hipStream_t);               \
     template rich_status launch_csr_sweeps<TB, T>(const Level &, const T *, const T *, const TB *, T *, T *, int,  \
                                                   hipStream_t);
 INST_CSR(double, double)
 INST_CSR(double, float)
 INST_CSR(float, float)
-template rich_status launch_restrict<double>(const Level &, const double *, double *, int64_t, hipStream_t);
-template rich_status launch_restrict<float>(const Level &, const float *, float *, int64_t, hipStream_t);
+template rich_status launch_restrict<double>(const Level &, const double *, double *, int64_t, const double *,
+                                             double *, hipStream_t);
+template rich_status launch_restrict<float>(const Level &, const float *, float *, int64_t, const float *, float *,
+                                            hipStream_t);
 
 }  // namespace rich

@@ -186,7 +186,22 @@ struct Level {
     int32_t *mem = nullptr;     // (n)
     // V-cycle work vectors, in the cycle's precision
     void *b = nullptr, *x = nullptr, *r = nullptr;
+    // smoothed aggregation (to level+1): prolongator P (n rows), its transpose
+    // PT (n_{l+1} rows), Q = A P (kept for the numeric refreshes) and the bits
+    // of rho = max_i sum_j |a_ij| / a_ii; prow == nullptr for piecewise-constant P
+    int64_t pnnz = 0, qnnz = 0;
+    int64_t *prow = nullptr, *trow = nullptr, *qrow = nullptr;
+    int32_t *pcol = nullptr, *tcol = nullptr, *qcol = nullptr;
+    double *pval = nullptr, *tval = nullptr, *qval = nullptr;
+    float *pvalf = nullptr, *tvalf = nullptr;
+    unsigned long long *rho = nullptr;
+    // row blocks of the CSR-stream kernels (levels >= 1): block b holds the
+    // rows whose first entry lies in [b STREAM_CHUNK, (b+1) STREAM_CHUNK)
+    int64_t nrb = 0;
+    int64_t *rb = nullptr;  // nrb + 1 row boundaries; nullptr: rows too long, plain CSR kernels
+    int sg = 1;             // lanes per row in the kernels' reduction phase
 };
+constexpr int STREAM_CHUNK = 1536, STREAM_MAXROW = 512;
 
 struct Hierarchy {
     int nlev = 0;
@@ -225,19 +240,55 @@ int64_t dense_inverse_ws(int64_t n);
 rich_status dense_inverse(const CsrDev &A, double *D, double *ws, hipStream_t s);
 rich_status compose_agg(int32_t *comp, const int32_t *a, int64_t n, hipStream_t s);
 
+// r = b - A x0 (x0 = D^{-1} b, the pre-smoothed iterate from zero, stored by the restriction)
 template <class TB, class T>
-rich_status launch_csr_pre(const Level &Lv, const T *val, const T *invd, const TB *b, T *r, hipStream_t s);
-// x = post-smooth(prolong(xc)); the level's r buffer holds the prolongated iterate
+rich_status launch_csr_pre(const Level &Lv, const T *val, const T *x0, const TB *b, T *r, hipStream_t s);
+// x = post-smooth(x0 + P xc); the level's r buffer holds the prolongated iterate
 template <class TB, class T>
-rich_status launch_csr_post(const Level &Lv, const T *val, const T *invd, const TB *b, const T *xc,
-                            T *x, hipStream_t s);
+rich_status launch_csr_post(const Level &Lv, const T *val, const T *invd, const TB *b, const T *x0,
+                            const T *xc, T *x, hipStream_t s);
+// bc = P^T r, and x0c = invdc * bc when x0c is set
 template <class T>
-rich_status launch_restrict(const Level &Lv, const T *r, T *bc, int64_t nc, hipStream_t s);
+rich_status launch_restrict(const Level &Lv, const T *r, T *bc, int64_t nc, const T *invdc, T *x0c,
+                            hipStream_t s);
 template <class TB, class T>
 rich_status launch_dense_gemv(const T *Ainv, const TB *b, T *x, int64_t n, hipStream_t s);
 template <class TB, class T>
 rich_status launch_csr_sweeps(const Level &Lv, const T *val, const T *invd, const TB *b, T *x, T *tmp,
                               int sweeps, hipStream_t s);
 rich_status launch_csr_spmv(const CsrDev &A, const double *x, double *y, hipStream_t s);
+
+// Row blocks of a CSR level for the CSR-stream V-cycle kernels (left unset
+// when a row is longer than STREAM_MAXROW).
+rich_status stream_blocks(Level &Lv, DevAlloc &mem, hipStream_t s);
+
+// Smoothed aggregation.  Patterns of P, PT, Q = A P and C = P^T Q for the
+// aggregates agg (members mptr/mem) of the fine level A; the arrays go to mem_out.
+rich_status sa_symbolic(const CsrDev &A, const int32_t *agg, int64_t nc, const int64_t *mptr,
+                        const int32_t *mem, Level &Lf, CsrDev *C, bool mixed, DevAlloc &mem_out,
+                        hipStream_t s);
+// Values of P, PT, Q and C (and the FP32 copies of P and PT when mixed), in
+// the oracle's summation order.
+rich_status sa_numeric(const CsrDev &A, const int32_t *agg, Level &Lf, const CsrDev &C, bool mixed,
+                       hipStream_t s);
+// bc = P^T r (and x0c = invdc * bc when x0c is set)
+template <class T>
+rich_status launch_sa_restrict(const Level &Lv, const T *r, T *bc, int64_t nc, const T *invdc, T *x0c,
+                               hipStream_t s);
+// xt = x0 + P xc, x0 given or D^{-1} (bs b) (bs: device scalar, or nullptr for 1)
+template <class TB, class T>
+rich_status launch_sa_prolong(const Level &Lv, const T *invd, const TB *b, const double *bs, const T *x0,
+                              const T *xc, T *xt, hipStream_t s);
+// fine level, post-smoothing from a stored prolongated iterate xt
+template <class TB, class T>
+rich_status launch_st_post_from(const Phys &P, const T *M4, const T *invd, const TB *b, const double *bs,
+                                const T *xt, T *x, hipStream_t s);
+
+template <int G, class T>
+__device__ inline T group_sum(T v) {
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) v += __shfl_down(v, o, G);
+    return v;
+}
 
 }  // namespace rich

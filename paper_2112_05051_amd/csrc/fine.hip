@@ -303,17 +303,21 @@ __global__ void k_st_post(Phys P, uint32_t n, const T *__restrict__ M4, const T 
 // cell's data is loaded from memory once (halos aside).  The sums keep the
 // order of mstencil (diag, -x, +x, -y, +y, -z, +z).  Chunks are kz planes
 // deep, kz chosen so that the grid still has enough blocks to fill the chip.
-//   PRE : u = D^{-1} bs b (pre-smoothing from zero),  out = bs b - M u
-//   POST: u = D^{-1} bs b + P xc (prolongation fused), out = u + D^{-1}(bs b - M u)
+//   ST25_PRE  : u = D^{-1} bs b (pre-smoothing from zero),  out = bs b - M u
+//   ST25_POST : u = D^{-1} bs b + P xc (piecewise-constant prolongation
+//               fused),                                     out = u + D^{-1}(bs b - M u)
+//   ST25_XT   : u = xt (a stored prolongated iterate),      out as ST25_POST
 constexpr int T25X = 64, T25Y = 8;
 #ifndef ST25_MIN_BLOCKS
 #define ST25_MIN_BLOCKS 2048
 #endif
-template <class TB, class T, bool POST>
+enum { ST25_PRE = 0, ST25_POST = 1, ST25_XT = 2 };
+template <class TB, class T, int MODE>
 __global__ void __launch_bounds__(T25X * T25Y) k_st25(Phys P, const T *__restrict__ M4, const T *__restrict__ invd,
                                                      const TB *__restrict__ b, const double *__restrict__ bsp,
                                                      const T *__restrict__ xc, const int32_t *__restrict__ agg,
                                                      T *__restrict__ out, int kz) {
+    constexpr bool POST = MODE != ST25_PRE;
     __shared__ T us[T25Y + 2][T25X + 2];
     __shared__ T xps[T25Y][T25X + 1];
     __shared__ T yps[T25Y + 1][T25X];
@@ -331,9 +335,11 @@ __global__ void __launch_bounds__(T25X * T25Y) k_st25(Phys P, const T *__restric
     const int k0 = (int)(L / (ntx * nty)) * kz, k1 = min(k0 + kz, nz);
     const bool inside = i < nx && j < ny;
     const TB bs = (TB)bsp[0];
+    // xc holds xt in ST25_XT mode
     auto U = [&](uint32_t c) -> T {
+        if (MODE == ST25_XT) return xc[c];
         T u = (T)(b[c] * bs) * invd[c];
-        if (POST) u += xc[agg[c]];
+        if (MODE == ST25_POST) u += xc[agg[c]];
         return u;
     };
     // column values of the current and the next plane: bs b, D^{-1}, u
@@ -342,8 +348,8 @@ __global__ void __launch_bounds__(T25X * T25Y) k_st25(Phys P, const T *__restric
     if (inside) {
         b_cur = (T)(b[c] * bs);
         d_cur = invd[c];
-        u_cur = b_cur * d_cur;
-        if (POST) u_cur += xc[agg[c]];
+        u_cur = MODE == ST25_XT ? xc[c] : b_cur * d_cur;
+        if (MODE == ST25_POST) u_cur += xc[agg[c]];
         if (k0 > 0) {
             u_prev = U(c - nxy);
             zp_prev = M4[(size_t)M_ZP * n + c - nxy];
@@ -353,8 +359,8 @@ __global__ void __launch_bounds__(T25X * T25Y) k_st25(Phys P, const T *__restric
         if (inside && k + 1 < nz) {
             b_nxt = (T)(b[c + nxy] * bs);
             d_nxt = invd[c + nxy];
-            u_nxt = b_nxt * d_nxt;
-            if (POST) u_nxt += xc[agg[c + nxy]];
+            u_nxt = MODE == ST25_XT ? xc[c + nxy] : b_nxt * d_nxt;
+            if (MODE == ST25_POST) u_nxt += xc[agg[c + nxy]];
         } else {
             u_nxt = 0;
         }
@@ -513,7 +519,7 @@ rich_status launch_st_pre(const Phys &P, const T *M4, const T *invd, const TB *b
     uint32_t n = ncells(P);
     if (use25(P)) {
         int kz = kz25(P);
-        k_st25<TB, T, false><<<grid25(P, kz), dim3(T25X, T25Y), 0, s>>>(P, M4, invd, b, bs, nullptr, nullptr, r, kz);
+        k_st25<TB, T, ST25_PRE><<<grid25(P, kz), dim3(T25X, T25Y), 0, s>>>(P, M4, invd, b, bs, nullptr, nullptr, r, kz);
     } else {
         k_st_pre<TB, T><<<nblocks(n), TPB, 0, s>>>(P, n, M4, invd, b, bs, r);
     }
@@ -527,10 +533,24 @@ rich_status launch_st_post(const Phys &P, const T *M4, const T *invd, const TB *
     uint32_t n = ncells(P);
     if (use25(P)) {
         int kz = kz25(P);
-        k_st25<TB, T, true><<<grid25(P, kz), dim3(T25X, T25Y), 0, s>>>(P, M4, invd, b, bs, xc, agg, x, kz);
+        k_st25<TB, T, ST25_POST><<<grid25(P, kz), dim3(T25X, T25Y), 0, s>>>(P, M4, invd, b, bs, xc, agg, x, kz);
     } else {
         k_st_prolong<TB, T><<<nblocks(n), TPB, 0, s>>>(n, invd, b, bs, xc, agg, xt);
         LAUNCH_CHECK();
+        k_st_post<TB, T><<<nblocks(n), TPB, 0, s>>>(P, n, M4, invd, b, bs, xt, x);
+    }
+    LAUNCH_CHECK();
+    return RICH_OK;
+}
+
+template <class TB, class T>
+rich_status launch_st_post_from(const Phys &P, const T *M4, const T *invd, const TB *b, const double *bs,
+                                const T *xt, T *x, hipStream_t s) {
+    uint32_t n = ncells(P);
+    if (use25(P)) {
+        int kz = kz25(P);
+        k_st25<TB, T, ST25_XT><<<grid25(P, kz), dim3(T25X, T25Y), 0, s>>>(P, M4, invd, b, bs, xt, nullptr, x, kz);
+    } else {
         k_st_post<TB, T><<<nblocks(n), TPB, 0, s>>>(P, n, M4, invd, b, bs, xt, x);
     }
     LAUNCH_CHECK();
@@ -559,6 +579,8 @@ rich_status launch_st_sweeps(const Phys &P, const T *M4, const T *invd, const TB
                                               hipStream_t);                                                     \
     template rich_status launch_st_post<TB, T>(const Phys &, const T *, const T *, const TB *, const double *,   \
                                                const T *, const int32_t *, T *, T *, hipStream_t);              \
+    template rich_status launch_st_post_from<TB, T>(const Phys &, const T *, const T *, const TB *,              \
+                                                    const double *, const T *, T *, hipStream_t);               \
     template rich_status launch_st_sweeps<TB, T>(const Phys &, const T *, const T *, const TB *, T *, T *, int, \
                                                  hipStream_t);
 INST_ST(double, double)

@@ -247,10 +247,16 @@ rich_status build_hierarchy(rich_ctx *h) {
         RICH_TRY(H.mem.get(&Lf.mptr, nc + 1));
         RICH_TRY(H.mem.get(&Lf.mem, levA.n));
         RICH_TRY(members(comp, levA.n, nc, Lf.mptr, Lf.mem, s));
-        // the coarse matrix: Galerkin product with the composed aggregates
+        // the coarse matrix: Galerkin product with the composed aggregates,
+        // through the piecewise-constant or the smoothed prolongator
         CsrDev C;
-        RICH_TRY(galerkin_symbolic(levA, comp, nc, Lf.mptr, Lf.mem, &C, H.mem, s));
-        RICH_TRY(galerkin_numeric(levA, comp, Lf.mptr, Lf.mem, C, s));
+        if (l < h->O.amg_smoothed) {
+            RICH_TRY(sa_symbolic(levA, comp, nc, Lf.mptr, Lf.mem, Lf, &C, h->mixed, H.mem, s));
+            RICH_TRY(sa_numeric(levA, comp, Lf, C, h->mixed, s));
+        } else {
+            RICH_TRY(galerkin_symbolic(levA, comp, nc, Lf.mptr, Lf.mem, &C, H.mem, s));
+            RICH_TRY(galerkin_numeric(levA, comp, Lf.mptr, Lf.mem, C, s));
+        }
         RICH_TRY(sync(h));
         Level &Lc = H.L[l + 1];
         Lc.n = C.n;
@@ -280,6 +286,8 @@ rich_status build_hierarchy(rich_ctx *h) {
                 RICH_TRY(launch_cast(Lv.val, Lv.valf, Lv.nnz, s));
             }
             RICH_TRY(csr_invd(A, Lv.invd, Lv.invdf, s));
+            // levels smoothed inside the cycle get their CSR-stream row blocks
+            if (t < H.nlev - 1) RICH_TRY(stream_blocks(Lv, H.mem, s));
         }
         char *b, *x, *r;
         RICH_TRY(H.mem.get(&b, Lv.n * esz));
@@ -322,7 +330,8 @@ rich_status refresh_hierarchy(rich_ctx *h) {
             Level &Lf = H.L[l], &Lc = H.L[l + 1];
             CsrDev A{Lf.n, Lf.nnz, Lf.rowptr, Lf.col, Lf.val};
             CsrDev C{Lc.n, Lc.nnz, Lc.rowptr, Lc.col, Lc.val};
-            RICH_TRY(galerkin_numeric(A, Lf.agg, Lf.mptr, Lf.mem, C, s));
+            if (Lf.prow) RICH_TRY(sa_numeric(A, Lf.agg, Lf, C, h->mixed, s));
+            else RICH_TRY(galerkin_numeric(A, Lf.agg, Lf.mptr, Lf.mem, C, s));
             RICH_TRY(csr_invd(C, Lc.invd, Lc.invdf, s));
             if (h->mixed) RICH_TRY(launch_cast(Lc.val, Lc.valf, Lc.nnz, s));
         }
@@ -370,16 +379,23 @@ rich_status vcycle(rich_ctx *h, const double *b, const double *bs, T *z) {
     // down
     RICH_TRY(timed(h, RICH_K_VC0_PRE, n0 * (8 + 6 * t),
                    [&] { return launch_st_pre<double, T>(h->P, M4, invd0, b, bs, (T *)H.L[0].r, s); }));
-    RICH_TRY(timed(h, RICH_K_VC0_RESTRICT, n0 * (t + 4) + n1 * (8 + t), [&] {
-        return launch_restrict<T>(H.L[0], (const T *)H.L[0].r, (T *)H.L[1].b, H.L[1].n, s);
+    const Level &L0 = H.L[0];
+    double rbytes = L0.prow ? (double)L0.pnnz * (4 + 2 * t) + n1 * (8 + t) : n0 * (t + 4) + n1 * (8 + t);
+    // each restriction also stores the next level's pre-smoothed iterate
+    // x0 = D^{-1} b in its x buffer, except for the coarsest level
+    auto x0_of = [&](int l) { return l < H.nlev - 1 ? (T *)H.L[l].x : nullptr; };
+    RICH_TRY(timed(h, RICH_K_VC0_RESTRICT, rbytes, [&] {
+        return launch_restrict<T>(H.L[0], (const T *)H.L[0].r, (T *)H.L[1].b, H.L[1].n, lvinvd<T>(H.L[1]), x0_of(1),
+                                  s);
     }));
     for (int l = 1; l < H.nlev - 1; l++) {
         Level &Lv = H.L[l];
         double bytes = (double)Lv.nnz * (4 + t) + (double)Lv.n * (8 + 3 * t);
         RICH_TRY(timed(h, l == 1 ? RICH_K_VC1_PRE : RICH_K_COUNT, bytes, [&] {
-            return launch_csr_pre<T, T>(Lv, lvval<T>(Lv), lvinvd<T>(Lv), (const T *)Lv.b, (T *)Lv.r, s);
+            return launch_csr_pre<T, T>(Lv, lvval<T>(Lv), (const T *)Lv.x, (const T *)Lv.b, (T *)Lv.r, s);
         }));
-        RICH_TRY(launch_restrict<T>(Lv, (const T *)Lv.r, (T *)H.L[l + 1].b, H.L[l + 1].n, s));
+        RICH_TRY(launch_restrict<T>(Lv, (const T *)Lv.r, (T *)H.L[l + 1].b, H.L[l + 1].n, lvinvd<T>(H.L[l + 1]),
+                                    x0_of(l + 1), s));
     }
     // coarsest
     Level &Lc = H.L[H.nlev - 1];
@@ -394,9 +410,18 @@ rich_status vcycle(rich_ctx *h, const double *b, const double *bs, T *z) {
         Level &Lv = H.L[l];
         double bytes = (double)Lv.nnz * (4 + t) + (double)Lv.n * (12 + 7 * t) + (double)H.L[l + 1].n * t;
         RICH_TRY(timed(h, l == 1 ? RICH_K_VC1_POST : RICH_K_COUNT, bytes, [&] {
-            return launch_csr_post<T, T>(Lv, lvval<T>(Lv), lvinvd<T>(Lv), (const T *)Lv.b,
+            return launch_csr_post<T, T>(Lv, lvval<T>(Lv), lvinvd<T>(Lv), (const T *)Lv.b, (const T *)Lv.x,
                                          (const T *)H.L[l + 1].x, (T *)Lv.x, s);
         }));
+    }
+    if (L0.prow) {
+        // smoothed prolongation into the level's r buffer, then post-smoothing
+        double pbytes = n0 * (12 + 6 * t) + n1 * t + (double)L0.pnnz * (4 + t) + n0 * (8 + 2 * t);
+        return timed(h, RICH_K_VC0_POST, pbytes, [&] {
+            T *xt = (T *)H.L[0].r;
+            RICH_TRY(launch_sa_prolong<double, T>(L0, invd0, b, bs, nullptr, (const T *)H.L[1].x, xt, s));
+            return launch_st_post_from<double, T>(h->P, M4, invd0, b, bs, xt, z, s);
+        });
     }
     return timed(h, RICH_K_VC0_POST, n0 * (12 + 6 * t) + n1 * t, [&] {
         return launch_st_post<double, T>(h->P, M4, invd0, b, bs, (const T *)H.L[1].x, H.L[0].agg, z, (T *)H.L[0].r,
@@ -835,6 +860,7 @@ rich_status validate(const rich_problem_t *P, const rich_solver_opts_t *O) {
     if (O->precision != RICH_PREC_FP64 && O->precision != RICH_PREC_MIXED) return RICH_EINVAL;
     if (O->amg_refresh != 0 && O->amg_refresh != 1) return RICH_EINVAL;
     if (O->aux_dflux != 0 && O->aux_dflux != 1) return RICH_EINVAL;
+    if (O->amg_smoothed < 0 || O->amg_smoothed > 16) return RICH_EINVAL;
     if (!(O->gmres_reorth >= 0.0 && O->gmres_reorth < 1.0)) return RICH_EINVAL;
     if (!(O->eta > 0) || !(O->fnormtol > 0) || O->max_newton < 1 || O->msbset < 1) return RICH_EINVAL;
     return RICH_OK;
@@ -902,6 +928,15 @@ rich_status rich_query_bytes(const rich_problem_t *prob, const rich_solver_opts_
     // hierarchy bound: operator complexity <= 3, 12-byte CSR entries plus value copies
     size_t nnz0 = 7 * N;
     b += 2 * nnz0 * (12 + esz) + N * (8 + esz + 3 * esz + 8) * 2;
+    if (opts->amg_smoothed) {
+        // level 0 dominates: P and PT (~4.2 entries per fine row), Q = A P
+        // (~12 per row), coarse levels about twice as dense, and the scratch
+        // of the symbolic products during set-up
+        b += 2 * (5 * N) * (12 + 8 + esz);
+        b += 14 * N * 12;
+        b += nnz0 * (12 + esz);
+        b += 200 * N;
+    }
     size_t nc = (size_t)(opts->coarse_dense_max);
     b += nc * nc * (8 + esz);
     *bytes = b;
@@ -1115,6 +1150,20 @@ rich_status rich_export_csr(rich_handle_t h, int which, int level, int64_t *rowp
         HIP_TRY(hipMemcpyAsync(val_host, val, nnz * sizeof(double), hipMemcpyDeviceToHost, h->s));
         RICH_TRY(sync(h));
         *nnz_inout = nnz;
+        return RICH_OK;
+    }
+    if (which == RICH_WHICH_P) {
+        if (!h->H || level < 0 || level >= h->H->nlev - 1 || !h->H->L[level].prow) return RICH_EINVAL;
+        const Level &Lp = h->H->L[level];
+        if (*nnz_inout < Lp.pnnz) {
+            *nnz_inout = Lp.pnnz;
+            return RICH_EINVAL;
+        }
+        HIP_TRY(hipMemcpyAsync(rowptr_host, Lp.prow, (Lp.n + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, h->s));
+        HIP_TRY(hipMemcpyAsync(col_host, Lp.pcol, Lp.pnnz * sizeof(int32_t), hipMemcpyDeviceToHost, h->s));
+        HIP_TRY(hipMemcpyAsync(val_host, Lp.pval, Lp.pnnz * sizeof(double), hipMemcpyDeviceToHost, h->s));
+        RICH_TRY(sync(h));
+        *nnz_inout = Lp.pnnz;
         return RICH_OK;
     }
     if (which != RICH_WHICH_A || !h->H || level < 0 || level >= h->H->nlev) return RICH_EINVAL;

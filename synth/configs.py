@@ -74,7 +74,7 @@ class Options:
     precision: int = FP64
     gmres_reorth: float = 0.01          # second Gram-Schmidt pass only on severe cancellation
     aux_dflux: int = 0                  # 1: preconditioner diagonal takes the flux-derivative terms
-    amg_smoothed: int = 0               # 1: smoothed-aggregation prolongators (damped Jacobi on P_t)
+    amg_smoothed: int = 0               # levels (from the finest) whose prolongator is smoothed (damped Jacobi on P_t)
 
 
 @dataclass

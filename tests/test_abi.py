@@ -54,6 +54,13 @@ def test_argument_validation_without_gpu():
         assert lib.rich_query_bytes(C.byref(_lib.make_problem(Q)), C.byref(_lib.make_opts(O)), C.byref(b)) == -1
     O2 = synth.Options(gmres_restart=65)
     assert lib.rich_query_bytes(C.byref(_lib.make_problem(P)), C.byref(_lib.make_opts(O2)), C.byref(b)) == -1
+    O3 = synth.Options(amg_smoothed=17)
+    assert lib.rich_query_bytes(C.byref(_lib.make_problem(P)), C.byref(_lib.make_opts(O3)), C.byref(b)) == -1
+    # the smoothed hierarchy plans for its prolongators and denser coarse levels
+    b_sa = C.c_size_t()
+    O4 = synth.Options(amg_smoothed=1)
+    assert lib.rich_query_bytes(C.byref(_lib.make_problem(P)), C.byref(_lib.make_opts(O4)), C.byref(b_sa)) == 0
+    assert b_sa.value > b.value
     h = C.c_void_p()
     assert lib.rich_create(C.byref(_lib.make_problem(P)), C.byref(_lib.make_opts(O)), None, None, C.byref(h)) == -1
 

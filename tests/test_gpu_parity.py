@@ -104,14 +104,16 @@ def test_match_sweep_empty(rich, torch):
     assert nc == 0 and agg.numel() == 0
 
 
+@pytest.mark.parametrize("smoothed", [0, 1, 16])
 @pytest.mark.parametrize("mean", MEANS)
-def test_hierarchy_bitexact(rich, torch, orc, mean):
-    """The GPU's set-up on its own M == the oracle's set-up on that same M."""
+def test_hierarchy_bitexact(rich, torch, orc, mean, smoothed):
+    """The GPU's set-up on its own M == the oracle's set-up on that same M
+    (smoothed: prolongators and coarse matrices equal bit for bit)."""
     P = box_problem(37, 29, 23, mean=mean, dt=10.0)
     n = P.n
     ks = random_ks(P, 31)
     p = random_heads(n, 32, -70, -30)
-    opts = synth.Options(amg_coarse_size=200, coarse_dense_max=600)
+    opts = synth.Options(amg_coarse_size=200, coarse_dense_max=600, amg_smoothed=smoothed)
     s = make_solver(rich, torch, P, ks, opts)
     s.assemble(dev(torch, p))
     rp, col, val = s.export_csr(rich.WHICH_A, 0)
@@ -122,10 +124,17 @@ def test_hierarchy_bitexact(rich, torch, orc, mean):
         Ao, aggo = amg.level(l)
         rp, col, val = s.export_csr(rich.WHICH_A, l)
         csr_close(rp, col, val, Ao, 1e-12)
+        if smoothed:
+            assert np.array_equal(val, Ao.data)
         if l < amg.levels - 1:
             agg_g, nc = s.export_aggregates(l)
             assert np.array_equal(agg_g, aggo)
             assert np.bincount(agg_g).max() <= 8
+            if l < smoothed:
+                prp, pcol, pval = s.export_csr(rich.WHICH_P, l)
+                Po = amg.prolongator(l)
+                assert np.array_equal(prp, Po.indptr) and np.array_equal(pcol, Po.indices)
+                assert np.array_equal(pval, Po.data)
     # one V-cycle (FP64) vs the oracle's on the same hierarchy
     b = np.random.default_rng(33).standard_normal(n)
     xg = s.apply_prec(dev(torch, b)).cpu().numpy()
@@ -176,8 +185,10 @@ def test_full_steps_fp64(rich, torch, orc, name, n, mean):
         assert err <= 1e-8, (step, err, sg, so)
 
 
-def test_full_steps_mixed(rich, torch, orc):
+@pytest.mark.parametrize("smoothed", [0, 1])
+def test_full_steps_mixed(rich, torch, orc, smoothed):
     r = smooth_recipe("c3", 24)
+    r.options.amg_smoothed = smoothed
     assert r.options.precision == synth.MIXED
     P = r.problem
     ks, p = r.ks(), r.p0()
@@ -194,14 +205,14 @@ def test_full_steps_mixed(rich, torch, orc):
         assert err <= 1e-6, (step, err, sg, so)
 
 
-@pytest.mark.parametrize("refresh", [0, 1])
-def test_hierarchy_refresh(rich, torch, orc, refresh):
+@pytest.mark.parametrize("refresh,smoothed", [(0, 0), (1, 0), (1, 16)])
+def test_hierarchy_refresh(rich, torch, orc, refresh, smoothed):
     """After a second assembly the GPU's refreshed hierarchy equals the oracle's
     (aggregates kept; coarse matrices recomputed when refresh = 1)."""
     P = box_problem(33, 27, 21, mean=synth.UPSTREAM, dt=10.0)
     n = P.n
     ks = random_ks(P, 41)
-    opts = synth.Options(amg_coarse_size=150, coarse_dense_max=400, amg_refresh=refresh)
+    opts = synth.Options(amg_coarse_size=150, coarse_dense_max=400, amg_refresh=refresh, amg_smoothed=smoothed)
     s = make_solver(rich, torch, P, ks, opts)
     s.assemble(dev(torch, random_heads(n, 42, -70, -30)))
     rp, col, val = s.export_csr(rich.WHICH_A, 0)
@@ -250,8 +261,8 @@ def test_aux_dflux_matches_oracle(rich, torch, orc):
     csr_close(rp, col, val, orc.auxiliary(P, ks, p, dflux=True), 1e-12)
 
 
-@pytest.mark.parametrize("mean", [synth.ARITH, synth.UPSTREAM])
-def test_vcycle_tiled_stencil(rich, torch, orc, mean):
+@pytest.mark.parametrize("mean,smoothed", [(synth.ARITH, 0), (synth.UPSTREAM, 0), (synth.UPSTREAM, 1)])
+def test_vcycle_tiled_stencil(rich, torch, orc, mean, smoothed):
     """Rows of 48+ cells take the tiled fine-level smoother: a ragged grid
     (x: 64 + 36, y: 2 x 8 + 5, z: several chunks + tail) against the oracle's
     V-cycle on the same hierarchy (FP64), and the FP32 V-cycle against it."""
@@ -259,7 +270,7 @@ def test_vcycle_tiled_stencil(rich, torch, orc, mean):
     n = P.n
     ks = random_ks(P, 51)
     p = random_heads(n, 52, -70, -30)
-    opts = synth.Options(precision=synth.FP64)
+    opts = synth.Options(precision=synth.FP64, amg_smoothed=smoothed)
     s = make_solver(rich, torch, P, ks, opts)
     s.assemble(dev(torch, p))
     rp, col, val = s.export_csr(rich.WHICH_A, 0)

@@ -91,10 +91,12 @@ def test_rap_is_the_bilinear_form(orc):
     assert np.linalg.eigvalsh(Cd).min() > 0
 
 
-def test_smoothed_vcycle_equals_section_5_2_recursion(orc):
+@pytest.mark.parametrize("smoothed", [1, 16])
+def test_smoothed_vcycle_equals_section_5_2_recursion(orc, smoothed):
+    """smoothed = 1: only the finest prolongator is smoothed; 16: all of them."""
     P = box_problem(9, 8, 7)
     M = orc.auxiliary(P, random_ks(P, 6), random_heads(P.n, 7, -70, -30))
-    opts = synth.Options(amg_coarse_size=20, coarse_dense_max=200, amg_smoothed=1)
+    opts = synth.Options(amg_coarse_size=20, coarse_dense_max=200, amg_smoothed=smoothed)
     amg = orc.AMG(opts, M)
     L = amg.levels
     assert L >= 3 and amg.coarse_dense
@@ -104,7 +106,13 @@ def test_smoothed_vcycle_equals_section_5_2_recursion(orc):
         Ml = mats[l].toarray()
         n = Ml.shape[0]
         Sinv = np.diag(1.0 / np.abs(Ml).sum(axis=1))
-        Pl = amg.prolongator(l).toarray()
+        Ps = amg.prolongator(l)
+        assert (Ps is not None) == (l < smoothed)
+        if Ps is None:
+            Pl = np.zeros((n, mats[l + 1].shape[0]))
+            Pl[np.arange(n), amg.level(l)[1]] = 1.0
+        else:
+            Pl = Ps.toarray()
         assert Pl.shape == (n, mats[l + 1].shape[0])
         I = np.eye(n)
         Mbar = Sinv.T + Sinv - Sinv.T @ Ml @ Sinv + (I - Sinv.T @ Ml) @ Pl @ Mbar @ Pl.T @ (I - Ml @ Sinv)
@@ -122,7 +130,7 @@ def test_refresh_recomputes_prolongator_and_product(orc):
     ks = random_ks(P, 11)
     M1 = orc.auxiliary(P, ks, random_heads(P.n, 12, -70, -30)).tocsr()
     M2 = orc.auxiliary(P, ks, random_heads(P.n, 13, -60, -10)).tocsr()
-    opts = synth.Options(amg_coarse_size=20, coarse_dense_max=200, amg_smoothed=1)
+    opts = synth.Options(amg_coarse_size=20, coarse_dense_max=200, amg_smoothed=16)
     amg = orc.AMG(opts, M1)
     amg.update_fine(M2)
     _, agg = amg.level(0)
@@ -142,9 +150,9 @@ def test_smoothing_reduces_gmres_iterations(orc):
     J = orc.jacobian(P, ks, p)
     M = orc.auxiliary(P, ks, p)
     its = {}
-    for sm in (0, 1):
+    for sm in (0, 1, 16):
         r.options.amg_smoothed = sm
         amg = orc.AMG(r.options, M)
         x, conv, its[sm], _ = orc.gmres(J, -F, amg, 30, 1e-8, 300)
         assert conv
-    assert its[1] < its[0]
+    assert its[1] < its[0] and its[16] < its[0]
