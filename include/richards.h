@@ -109,6 +109,8 @@ typedef struct rich_solver_opts {
                             omega = 4 / (3 max_i sum_j |a_ij| / a_ii), and coarse matrix P^T A P;
                             the other levels keep the piecewise-constant P_t.  Smoothing costs
                             set-up work and denser coarse levels and saves GMRES iterations */
+    int tile_kz;         /* planes per thread block in the tiled fine-level smoother kernels
+                            (0 = automatic; a tuning knob, results do not depend on it) */
 } rich_solver_opts_t;
 
 /* Per-time-step counters and timings (host wall seconds of each phase). */

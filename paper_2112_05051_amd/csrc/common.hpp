@@ -54,6 +54,7 @@ struct Phys {
     int bc_type[6];
     double bc_value[6];
     double dt;
+    int tile_kz;  // planes per block of the tiled fine-level smoother (0: automatic)
 };
 
 // Device buffer owned by a context (raw hipMalloc, freed in the context's destructor).

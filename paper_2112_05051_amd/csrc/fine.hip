@@ -295,32 +295,44 @@ __global__ void k_st_post(Phys P, uint32_t n, const T *__restrict__ M4, const T 
     x[c] = xt[c] + invd[c] * ((T)(b[c] * (TB)bsp[0]) - s);
 }
 
-// 2.5-D versions of the two fine-level V-cycle stencils for large grids.  A
-// block of 64 x 8 threads owns a 64 x 8 column tile and walks a chunk of kz
-// planes upward: the stencil input u of the planes below and above stays in
-// registers, the current plane (with a one-cell halo) and its +x / +y
-// couplings (with the lower neighbours' ones) are staged in LDS, so every
-// cell's data is loaded from memory once (halos aside).  The sums keep the
-// order of mstencil (diag, -x, +x, -y, +y, -z, +z).  Chunks are kz planes
-// deep, kz chosen so that the grid still has enough blocks to fill the chip.
+// 2.5-D versions of the fine-level V-cycle stencils.  A block of 64 x 8
+// threads owns a 64 x 8 column tile and walks a chunk of kz planes upward:
+// the stencil input u of the planes below and above stays in registers, the
+// current plane (with a one-cell halo) and its +x / +y couplings (with the
+// lower neighbours' ones) go through LDS, so every cell's data is loaded from
+// memory once (halos aside).  Loads run ahead of the arithmetic: while plane
+// k is computed, the coefficients and halo inputs of plane k+1 and the
+// column inputs of plane k+2 are already in flight; LDS is double-buffered
+// by plane parity, so one barrier per plane suffices.  The sums keep the
+// order of mstencil (diag, -x, +x, -y, +y, -z, +z).
 //   ST25_PRE  : u = D^{-1} bs b (pre-smoothing from zero),  out = bs b - M u
 //   ST25_POST : u = D^{-1} bs b + P xc (piecewise-constant prolongation
 //               fused),                                     out = u + D^{-1}(bs b - M u)
 //   ST25_XT   : u = xt (a stored prolongated iterate),      out as ST25_POST
-constexpr int T25X = 64, T25Y = 8;
+#ifndef ST25_TY
+#define ST25_TY 8
+#endif
+constexpr int T25X = 64, T25Y = ST25_TY;
 #ifndef ST25_MIN_BLOCKS
 #define ST25_MIN_BLOCKS 2048
 #endif
 enum { ST25_PRE = 0, ST25_POST = 1, ST25_XT = 2 };
+
+// The inputs of u at one cell as loaded (u is formed when it is used).
+template <class T>
+struct St25In {
+    T b = 0, d = 0, x = 0;  // bs b, D^{-1}, xc[agg] or xt
+};
+
 template <class TB, class T, int MODE>
 __global__ void __launch_bounds__(T25X * T25Y) k_st25(Phys P, const T *__restrict__ M4, const T *__restrict__ invd,
                                                      const TB *__restrict__ b, const double *__restrict__ bsp,
                                                      const T *__restrict__ xc, const int32_t *__restrict__ agg,
                                                      T *__restrict__ out, int kz) {
     constexpr bool POST = MODE != ST25_PRE;
-    __shared__ T us[T25Y + 2][T25X + 2];
-    __shared__ T xps[T25Y][T25X + 1];
-    __shared__ T yps[T25Y + 1][T25X];
+    __shared__ T us[2][T25Y + 2][T25X + 2];
+    __shared__ T xps[2][T25Y][T25X + 1];
+    __shared__ T yps[2][T25Y + 1][T25X];
     const int nx = P.nx, ny = P.ny, nz = P.nz;
     const uint32_t n = (uint32_t)nx * (uint32_t)ny * (uint32_t)nz;
     const uint32_t nxy = (uint32_t)nx * (uint32_t)ny;
@@ -335,74 +347,117 @@ __global__ void __launch_bounds__(T25X * T25Y) k_st25(Phys P, const T *__restric
     const int k0 = (int)(L / (ntx * nty)) * kz, k1 = min(k0 + kz, nz);
     const bool inside = i < nx && j < ny;
     const TB bs = (TB)bsp[0];
-    // xc holds xt in ST25_XT mode
-    auto U = [&](uint32_t c) -> T {
-        if (MODE == ST25_XT) return xc[c];
-        T u = (T)(b[c] * bs) * invd[c];
-        if (MODE == ST25_POST) u += xc[agg[c]];
+    // which halo cell this thread also loads (at most one in x and one in y)
+    const bool hxl = tx == 0 && i > 0 && j < ny, hxr = tx == T25X - 1 && i + 1 < nx && j < ny;
+    const bool hyl = ty == 0 && j > 0 && i < nx, hyr = ty == T25Y - 1 && j + 1 < ny && i < nx;
+    const int hxo = hxl ? -1 : 1;
+    const int hyo = hyl ? -nx : nx;
+    const bool hx = hxl || hxr, hy = hyl || hyr;
+
+    auto load_in = [&](uint32_t c) {
+        St25In<T> r;
+        if (MODE != ST25_XT) r.b = (T)(b[c] * bs);
+        if (MODE != ST25_XT) r.d = invd[c];
+        if (MODE == ST25_POST) r.x = xc[agg[c]];
+        if (MODE == ST25_XT) r.x = xc[c];
+        return r;
+    };
+    auto u_of = [&](const St25In<T> &r) -> T {
+        if (MODE == ST25_XT) return r.x;
+        T u = r.b * r.d;
+        if (MODE == ST25_POST) u += r.x;
         return u;
     };
-    // column values of the current and the next plane: bs b, D^{-1}, u
-    T b_cur = 0, d_cur = 0, u_cur = 0, b_nxt = 0, d_nxt = 0, u_nxt = 0, u_prev = 0, zp_prev = 0;
+    auto b_of = [&](uint32_t c) -> T { return (T)(b[c] * bs); };
+
+    // plane state: coefficients of plane k (own, and the lower-neighbour
+    // halo couplings), halo inputs of plane k, column inputs of k, k+1, k+2
+    T m_d = 0, m_xp = 0, m_yp = 0, m_zp = 0, h_xp = 0, h_yp = 0;
+    St25In<T> c0, c1, c2, hxin, hyin;
+    T u_prev = 0, zp_prev = 0;
     uint32_t c = (uint32_t)i + (uint32_t)nx * ((uint32_t)j + (uint32_t)ny * (uint32_t)k0);
+    auto load_plane = [&](uint32_t cc, T &md, T &mxp, T &myp, T &mzp, T &hxp, T &hyp, St25In<T> &hxi,
+                          St25In<T> &hyi) {
+        if (inside) {
+            md = M4[(size_t)M_D * n + cc];
+            mxp = M4[(size_t)M_XP * n + cc];
+            myp = M4[(size_t)M_YP * n + cc];
+            mzp = M4[(size_t)M_ZP * n + cc];
+        }
+        if (hx) {
+            hxi = load_in(cc + hxo);
+            if (hxl) hxp = M4[(size_t)M_XP * n + cc - 1];
+        }
+        if (hy) {
+            hyi = load_in(cc + hyo);
+            if (hyl) hyp = M4[(size_t)M_YP * n + cc - nx];
+        }
+    };
     if (inside) {
-        b_cur = (T)(b[c] * bs);
-        d_cur = invd[c];
-        u_cur = MODE == ST25_XT ? xc[c] : b_cur * d_cur;
-        if (MODE == ST25_POST) u_cur += xc[agg[c]];
+        c0 = load_in(c);
+        if (k0 + 1 < nz) c1 = load_in(c + nxy);
         if (k0 > 0) {
-            u_prev = U(c - nxy);
+            u_prev = u_of(load_in(c - nxy));
             zp_prev = M4[(size_t)M_ZP * n + c - nxy];
         }
     }
+    load_plane(c, m_d, m_xp, m_yp, m_zp, h_xp, h_yp, hxin, hyin);
     for (int k = k0; k < k1; k++, c += nxy) {
-        if (inside && k + 1 < nz) {
-            b_nxt = (T)(b[c + nxy] * bs);
-            d_nxt = invd[c + nxy];
-            u_nxt = MODE == ST25_XT ? xc[c + nxy] : b_nxt * d_nxt;
-            if (MODE == ST25_POST) u_nxt += xc[agg[c + nxy]];
-        } else {
-            u_nxt = 0;
-        }
-        us[ty + 1][tx + 1] = u_cur;
-        xps[ty][tx + 1] = inside ? M4[(size_t)M_XP * n + c] : (T)0;
-        yps[ty + 1][tx] = inside ? M4[(size_t)M_YP * n + c] : (T)0;
+        const int q = (k - k0) & 1;
+        // loads for the next iteration
+        T n_d = 0, n_xp = 0, n_yp = 0, n_zp = 0, nh_xp = 0, nh_yp = 0;
+        St25In<T> nhx, nhy;
+        if (k + 1 < k1) load_plane(c + nxy, n_d, n_xp, n_yp, n_zp, nh_xp, nh_yp, nhx, nhy);
+        if (inside && k + 2 < nz && k + 1 < k1) c2 = load_in(c + 2 * nxy);
+        // this plane through LDS
+        const T u_cur = u_of(c0);
+        const T u_nxt = (inside && k + 1 < nz) ? u_of(c1) : (T)0;
+        us[q][ty + 1][tx + 1] = inside ? u_cur : (T)0;
+        xps[q][ty][tx + 1] = m_xp;
+        yps[q][ty + 1][tx] = m_yp;
         if (tx == 0) {
-            bool ok = i > 0 && j < ny;
-            us[ty + 1][0] = ok ? U(c - 1) : (T)0;
-            xps[ty][0] = ok ? M4[(size_t)M_XP * n + c - 1] : (T)0;
+            us[q][ty + 1][0] = hxl ? u_of(hxin) : (T)0;
+            xps[q][ty][0] = h_xp;
         }
-        if (tx == T25X - 1) us[ty + 1][T25X + 1] = (i + 1 < nx && j < ny) ? U(c + 1) : (T)0;
+        if (tx == T25X - 1) us[q][ty + 1][T25X + 1] = hxr ? u_of(hxin) : (T)0;
         if (ty == 0) {
-            bool ok = j > 0 && i < nx;
-            us[0][tx + 1] = ok ? U(c - nx) : (T)0;
-            yps[0][tx] = ok ? M4[(size_t)M_YP * n + c - nx] : (T)0;
+            us[q][0][tx + 1] = hyl ? u_of(hyin) : (T)0;
+            yps[q][0][tx] = h_yp;
         }
-        if (ty == T25Y - 1) us[T25Y + 1][tx + 1] = (j + 1 < ny && i < nx) ? U(c + nx) : (T)0;
+        if (ty == T25Y - 1) us[q][T25Y + 1][tx + 1] = hyr ? u_of(hyin) : (T)0;
         __syncthreads();
         if (inside) {
-            T s = M4[(size_t)M_D * n + c] * u_cur;
-            if (i > 0) s += xps[ty][tx] * us[ty + 1][tx];
-            if (i < nx - 1) s += xps[ty][tx + 1] * us[ty + 1][tx + 2];
-            if (j > 0) s += yps[ty][tx] * us[ty][tx + 1];
-            if (j < ny - 1) s += yps[ty + 1][tx] * us[ty + 2][tx + 1];
+            T s = m_d * u_cur;
+            if (i > 0) s += xps[q][ty][tx] * us[q][ty + 1][tx];
+            if (i < nx - 1) s += xps[q][ty][tx + 1] * us[q][ty + 1][tx + 2];
+            if (j > 0) s += yps[q][ty][tx] * us[q][ty][tx + 1];
+            if (j < ny - 1) s += yps[q][ty + 1][tx] * us[q][ty + 2][tx + 1];
             if (k > 0) s += zp_prev * u_prev;
-            T zpc = M4[(size_t)M_ZP * n + c];
-            if (k < nz - 1) s += zpc * u_nxt;
-            out[c] = POST ? u_cur + d_cur * (b_cur - s) : b_cur - s;
-            zp_prev = zpc;
+            if (k < nz - 1) s += m_zp * u_nxt;
+            const T bc = MODE == ST25_XT ? b_of(c) : c0.b;
+            const T dc = MODE == ST25_XT ? invd[c] : c0.d;
+            out[c] = POST ? u_cur + dc * (bc - s) : bc - s;
         }
-        __syncthreads();
+        // rotate (the other LDS buffer is written next: no second barrier)
         u_prev = u_cur;
-        u_cur = u_nxt;
-        b_cur = b_nxt;
-        d_cur = d_nxt;
+        zp_prev = m_zp;
+        c0 = c1;
+        c1 = c2;
+        m_d = n_d;
+        m_xp = n_xp;
+        m_yp = n_yp;
+        m_zp = n_zp;
+        h_xp = nh_xp;
+        h_yp = nh_yp;
+        hxin = nhx;
+        hyin = nhy;
     }
 }
 
 // The 64-wide tile needs rows of at least about that length to keep its lanes busy.
 inline bool use25(const Phys &P) { return P.nx >= 48 && P.ny >= T25Y && P.nz >= 4; }
 inline int kz25(const Phys &P) {
+    if (P.tile_kz > 0) return P.tile_kz < P.nz ? P.tile_kz : P.nz;
     int64_t tiles = (int64_t)((P.nx + T25X - 1) / T25X) * ((P.ny + T25Y - 1) / T25Y);
     int kz = 16;
     while (kz > 1 && tiles * ((P.nz + kz - 1) / kz) < ST25_MIN_BLOCKS) kz /= 2;

@@ -861,6 +861,7 @@ rich_status validate(const rich_problem_t *P, const rich_solver_opts_t *O) {
     if (O->amg_refresh != 0 && O->amg_refresh != 1) return RICH_EINVAL;
     if (O->aux_dflux != 0 && O->aux_dflux != 1) return RICH_EINVAL;
     if (O->amg_smoothed < 0 || O->amg_smoothed > 16) return RICH_EINVAL;
+    if (O->tile_kz < 0 || O->tile_kz > 4096) return RICH_EINVAL;
     if (!(O->gmres_reorth >= 0.0 && O->gmres_reorth < 1.0)) return RICH_EINVAL;
     if (!(O->eta > 0) || !(O->fnormtol > 0) || O->max_newton < 1 || O->msbset < 1) return RICH_EINVAL;
     return RICH_OK;
@@ -886,6 +887,7 @@ Phys to_phys(const rich_problem_t *P) {
         q.bc_value[f] = P->bc_value[f];
     }
     q.dt = P->dt;
+    q.tile_kz = 0;
     return q;
 }
 
@@ -949,6 +951,7 @@ rich_status rich_create(const rich_problem_t *prob, const rich_solver_opts_t *op
     if (!Ks_dev || !out) return RICH_EINVAL;
     rich_ctx *h = new rich_ctx();
     h->P = to_phys(prob);
+    h->P.tile_kz = opts->tile_kz;
     h->O = *opts;
     h->N = (int64_t)prob->nx * prob->ny * prob->nz;
     h->s = (hipStream_t)hip_stream;

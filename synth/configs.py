@@ -75,6 +75,7 @@ class Options:
     gmres_reorth: float = 0.01          # second Gram-Schmidt pass only on severe cancellation
     aux_dflux: int = 0                  # 1: preconditioner diagonal takes the flux-derivative terms
     amg_smoothed: int = 0               # levels (from the finest) whose prolongator is smoothed (damped Jacobi on P_t)
+    tile_kz: int = 0                    # planes per block of the tiled fine-level smoother (0: automatic)
 
 
 @dataclass

@@ -264,24 +264,32 @@ def test_aux_dflux_matches_oracle(rich, torch, orc):
 @pytest.mark.parametrize("mean,smoothed", [(synth.ARITH, 0), (synth.UPSTREAM, 0), (synth.UPSTREAM, 1)])
 def test_vcycle_tiled_stencil(rich, torch, orc, mean, smoothed):
     """Rows of 48+ cells take the tiled fine-level smoother: a ragged grid
-    (x: 64 + 36, y: 2 x 8 + 5, z: several chunks + tail) against the oracle's
-    V-cycle on the same hierarchy (FP64), and the FP32 V-cycle against it."""
+    (x: 64 + 36, y: 2 x 8 + 5, z: chunks of 1, 4 (4 x 4 + 3) and 19 planes)
+    against the oracle's V-cycle on the same hierarchy (FP64), bit for bit the
+    same for every chunk depth, and the FP32 V-cycle against it."""
     P = box_problem(100, 21, 19, mean=mean, dt=10.0)
     n = P.n
     ks = random_ks(P, 51)
     p = random_heads(n, 52, -70, -30)
-    opts = synth.Options(precision=synth.FP64, amg_smoothed=smoothed)
-    s = make_solver(rich, torch, P, ks, opts)
-    s.assemble(dev(torch, p))
-    rp, col, val = s.export_csr(rich.WHICH_A, 0)
-    amg = orc.AMG(opts, sp.csr_matrix((val, col, rp), shape=(n, n)))
-    assert s.levels() == amg.levels >= 2
     b = np.random.default_rng(53).standard_normal(n)
+    xs = {}
+    for kz in (1, 4, 0):
+        opts = synth.Options(precision=synth.FP64, amg_smoothed=smoothed, tile_kz=kz)
+        s = make_solver(rich, torch, P, ks, opts)
+        s.assemble(dev(torch, p))
+        xs[kz] = s.apply_prec(dev(torch, b)).cpu().numpy()
+        if kz == 0:
+            rp, col, val = s.export_csr(rich.WHICH_A, 0)
+            amg = orc.AMG(opts, sp.csr_matrix((val, col, rp), shape=(n, n)))
+            assert s.levels() == amg.levels >= 2
+        s.close()
+    assert np.array_equal(xs[1], xs[4]) and np.array_equal(xs[1], xs[0])
     xo = amg.apply(b)
-    xg = s.apply_prec(dev(torch, b)).cpu().numpy()
-    assert np.linalg.norm(xg - xo) <= 1e-10 * np.linalg.norm(xo)
-    opts.precision = synth.MIXED
-    s = make_solver(rich, torch, P, ks, opts)
-    s.assemble(dev(torch, p))
-    xm = s.apply_prec(dev(torch, b)).cpu().numpy()
-    assert np.linalg.norm(xm - xo) <= 1e-5 * np.linalg.norm(xo)
+    assert np.linalg.norm(xs[0] - xo) <= 1e-10 * np.linalg.norm(xo)
+    for kz in (4, 0):
+        opts = synth.Options(precision=synth.MIXED, amg_smoothed=smoothed, tile_kz=kz)
+        s = make_solver(rich, torch, P, ks, opts)
+        s.assemble(dev(torch, p))
+        xm = s.apply_prec(dev(torch, b)).cpu().numpy()
+        s.close()
+        assert np.linalg.norm(xm - xo) <= 1e-5 * np.linalg.norm(xo)
