@@ -53,10 +53,14 @@ typedef int rich_status;
 #define RICH_ESTATE (-11)         /* call not valid in the handle's current state */
 #define RICH_STEP_TOO_SMALL 2     /* warning: Newton stalled with a fresh J; state kept */
 
-/* interface means of K (Section 2.1; harmonic: named in the abstract) */
+/* interface means of K (Section 2.1; harmonic: named in the abstract).  The
+ * integral mean averages K_s k_r(psi) over the heads between the two cells
+ * (K_s: the two cells' arithmetic mean) with a 16-point Gauss-Legendre rule. */
 #define RICH_MEAN_ARITH 0
 #define RICH_MEAN_UPSTREAM 1
 #define RICH_MEAN_HARMONIC 2
+#define RICH_MEAN_GEOMETRIC 3
+#define RICH_MEAN_INTEGRAL 4
 /* boundary face types */
 #define RICH_BC_NOFLUX 0
 #define RICH_BC_DIRICHLET 1

@@ -111,14 +111,54 @@ static int face_info(const orc_problem *P, int i, int j, int k, int f, const dou
     return 0;
 }
 
-/* Interface means (Section 2.1): arithmetic, upstream eq. (upstream_mean)   */
-/* with L the lower-index side, U = L + e_d and ties (p_U - p_L = 0) taking  */
-/* K_U; harmonic 2 K_L K_U / (K_L + K_U) (named in the abstract).  Returns   */
-/* the mean and its partial derivatives w.r.t. the cell's and neighbour's    */
-/* heads (the upstream derivative does not differentiate the switch).       */
-static void face_mean(int mean, int dir, double pc, double Kc, double dKc, double pn, double Kn,
-                      double dKn, double *Kf, double *dc, double *dn)
+/* Gauss-Legendre rule with ORC_GL nodes on [0, 1]: the nodes are the roots */
+/* of the Legendre polynomial P_n found by Newton's method from the usual    */
+/* cosine estimates, w_i = 2 / ((1 - x_i^2) P_n'(x_i)^2) (halved for [0,1]). */
+#define ORC_GL 16
+static double gl_t[ORC_GL], gl_w[ORC_GL];
+static int gl_ready = 0;
+
+static void gl_init(void)
 {
+    if (gl_ready) return;
+    const int n = ORC_GL;
+    const double pi = 3.14159265358979323846;
+    for (int i = 0; i < n; i++) {
+        double x = cos(pi * (i + 0.75) / (n + 0.5)), dp = 1.0;
+        for (int it = 0; it < 100; it++) {
+            double p0 = 1.0, p1 = x;
+            for (int k = 2; k <= n; k++) {
+                double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (x * p1 - p0) / (x * x - 1.0);
+            double dx = p1 / dp;
+            x -= dx;
+            if (fabs(dx) < 1e-16) break;
+        }
+        gl_t[i] = 0.5 * (1.0 - x);
+        gl_w[i] = 1.0 / ((1.0 - x * x) * dp * dp);
+    }
+    gl_ready = 1;
+}
+
+/* Interface means (Section 2.1): arithmetic; upstream eq. (upstream_mean)  */
+/* with L the lower-index side, U = L + e_d and ties (p_U - p_L = 0) taking  */
+/* K_U; harmonic 2 K_L K_U / (K_L + K_U) (named in the abstract); geometric  */
+/* sqrt(K_L K_U); integral mean: the average of K over the heads between    */
+/* p_L and p_U, with K_s the arithmetic mean of the two cells' K_s (and     */
+/* K(p_U) when the heads are equal, where the paper's printed "p_U" and the */
+/* sign of its 1/(p_L - p_U) are typos), evaluated by the ORC_GL-point Gauss-*/
+/* Legendre rule on [p_L, p_U] (no closed form for this K(p)); its          */
+/* derivatives are those of the rule.  Returns the mean and its partial     */
+/* derivatives w.r.t. the cell's and the neighbour's heads (the upstream    */
+/* derivative does not differentiate the switch).                           */
+static void face_mean(const orc_problem *P, int dir, double pc, double Ksc, const double Lc[4],
+                      double pn, double Ksn, const double Ln[4], double *Kf, double *dc, double *dn)
+{
+    int mean = P->mean;
+    double Kc = Lc[2], dKc = Lc[3], Kn = Ln[2], dKn = Ln[3];
     if (mean == ORC_ARITH) {
         *Kf = 0.5 * (Kc + Kn);
         *dc = 0.5 * dKc;
@@ -128,6 +168,25 @@ static void face_mean(int mean, int dir, double pc, double Kc, double dKc, doubl
         *Kf = 2.0 * Kc * Kn / s;
         *dc = 2.0 * Kn * Kn * dKc / (s * s);
         *dn = 2.0 * Kc * Kc * dKn / (s * s);
+    } else if (mean == ORC_GEOMETRIC) {
+        double g = sqrt(Kc * Kn);
+        *Kf = g;
+        *dc = 0.5 * Kn * dKc / g;
+        *dn = 0.5 * Kc * dKn / g;
+    } else if (mean == ORC_INTEGRAL) {
+        gl_init();
+        double pL = dir > 0 ? pc : pn, pU = dir > 0 ? pn : pc;
+        double Ks = 0.5 * (dir > 0 ? Ksc + Ksn : Ksn + Ksc);
+        double q = 0.0, qL = 0.0, qU = 0.0, L[4];
+        for (int t = 0; t < ORC_GL; t++) {
+            orc_laws(P, pL + (pU - pL) * gl_t[t], Ks, L);
+            q += gl_w[t] * L[2];
+            qL += gl_w[t] * (1.0 - gl_t[t]) * L[3];
+            qU += gl_w[t] * gl_t[t] * L[3];
+        }
+        *Kf = q;
+        *dc = dir > 0 ? qL : qU;
+        *dn = dir > 0 ? qU : qL;
     } else { /* upstream */
         double pU, pL;
         if (dir > 0) { pU = pn; pL = pc; }
@@ -137,6 +196,15 @@ static void face_mean(int mean, int dir, double pc, double Kc, double dKc, doubl
         if (take_n) { *Kf = Kn; *dc = 0.0; *dn = dKn; }
         else { *Kf = Kc; *dc = dKc; *dn = 0.0; }
     }
+}
+
+void orc_face_mean(const orc_problem *P, int dir, double pc, double Ksc, double pn, double Ksn,
+                   double out[3])
+{
+    double Lc[4], Ln[4];
+    orc_laws(P, pc, Ksc, Lc);
+    orc_laws(P, pn, Ksn, Ln);
+    face_mean(P, dir, pc, Ksc, Lc, pn, Ksn, Ln, &out[0], &out[1], &out[2]);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -161,7 +229,7 @@ void orc_residual(const orc_problem *P, const double *Ks, const double *p, const
                     if (!face_info(P, i, j, k, f, p, Ks, &fc)) continue;
                     orc_laws(P, fc.pn, fc.Ksn, Ln);
                     double Kf, dc, dn;
-                    face_mean(P->mean, fc.dir, p[c], Lc[2], Lc[3], fc.pn, Ln[2], Ln[3], &Kf, &dc, &dn);
+                    face_mean(P, fc.dir, p[c], Ks[c], Lc, fc.pn, fc.Ksn, Ln, &Kf, &dc, &dn);
                     acc += -Kf * (fc.pn - p[c]) / (fc.h * fc.h);
                     if (fc.axis == 2) acc += fc.dir * (-(Lc[2] + Ln[2]) / (2.0 * P->hz));
                 }
@@ -209,7 +277,7 @@ static void assemble(const orc_problem *P, const double *Ks, const double *p, in
                     if (!face_info(P, i, j, k, f, p, Ks, &fc)) continue;
                     orc_laws(P, fc.pn, fc.Ksn, Ln);
                     double Kf, dc, dn;
-                    face_mean(P->mean, fc.dir, p[c], Lc[2], Lc[3], fc.pn, Ln[2], Ln[3], &Kf, &dc, &dn);
+                    face_mean(P, fc.dir, p[c], Ks[c], Lc, fc.pn, fc.Ksn, Ln, &Kf, &dc, &dn);
                     double h2 = fc.h * fc.h;
                     double dp = fc.pn - p[c];
                     if (which == 0) {

@@ -21,6 +21,8 @@
 #define ORC_ARITH 0
 #define ORC_UPSTREAM 1
 #define ORC_HARMONIC 2
+#define ORC_GEOMETRIC 3
+#define ORC_INTEGRAL 4
 
 #define ORC_NOFLUX 0
 #define ORC_DIRICHLET 1
@@ -81,6 +83,9 @@ typedef struct {
 
 /* ---- constitutive laws, residual, Jacobian, auxiliary matrix ---- */
 void orc_laws(const orc_problem *P, double p, double Ks, double out[4]); /* theta, theta', K, K' */
+/* interface mean of a face between heads pc and pn (dir = +1: pn on the higher-index side) */
+void orc_face_mean(const orc_problem *P, int dir, double pc, double Ksc, double pn, double Ksn,
+                   double out[3]); /* K_f, dK_f/dp_c, dK_f/dp_n */
 void orc_laws_array(const orc_problem *P, int64_t n, const double *p, const double *Ks,
                     double *out /* n x 4 */);
 void orc_theta(const orc_problem *P, const double *p, double *theta);

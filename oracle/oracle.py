@@ -70,6 +70,7 @@ def lib():
         vp = C.c_void_p
         L.orc_laws_array.argtypes = [P(CProblem), C.c_int64, d, d, d]
         L.orc_theta.argtypes = [P(CProblem), d, d]
+        L.orc_face_mean.argtypes = [P(CProblem), C.c_int, C.c_double, C.c_double, C.c_double, C.c_double, d]
         L.orc_residual.argtypes = [P(CProblem), d, d, d, d]
         L.orc_pattern_nnz.argtypes = [P(CProblem)]
         L.orc_pattern_nnz.restype = C.c_int64
@@ -153,6 +154,14 @@ def laws(P, p, Ks):
     cp = cproblem(P)
     lib().orc_laws_array(C.byref(cp), p.size, _d(p), _d(Ks), _d(out))
     return out[:, 0], out[:, 1], out[:, 2], out[:, 3]
+
+
+def face_mean(P, direction, pc, Ksc, pn, Ksn):
+    """(K_f, dK_f/dp_c, dK_f/dp_n) of one face (direction +1: pn on the higher-index side)."""
+    out = np.empty(3)
+    cp = cproblem(P)
+    lib().orc_face_mean(C.byref(cp), int(direction), float(pc), float(Ksc), float(pn), float(Ksn), _d(out))
+    return out[0], out[1], out[2]
 
 
 def theta(P, p):

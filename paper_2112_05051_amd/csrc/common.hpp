@@ -46,6 +46,7 @@ inline unsigned xcd_grid(int64_t n, int tpb) {
 }
 
 // Problem parameters passed by value to the stencil kernels.
+constexpr int RICH_GL = 16;
 struct Phys {
     int nx, ny, nz;
     double hx, hy, hz;
@@ -55,6 +56,7 @@ struct Phys {
     double bc_value[6];
     double dt;
     int tile_kz;  // planes per block of the tiled fine-level smoother (0: automatic)
+    double gl_t[RICH_GL], gl_w[RICH_GL];  // Gauss-Legendre rule on [0, 1] of the integral mean
 };
 
 // Device buffer owned by a context (raw hipMalloc, freed in the context's destructor).

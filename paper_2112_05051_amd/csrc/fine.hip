@@ -95,10 +95,14 @@ __device__ inline Face face(const Phys &P, const Cell &q, uint32_t c, int f, con
 }
 
 // Interface mean of K and its partial derivatives (Section 2.1).  dir > 0:
-// the neighbour is the higher-index side U; upstream takes K_U when
-// p_U - p_L >= 0, else K_L.
-__device__ inline void mean_of(int mean, int dir, double pc, const Law &Lc, double pn, const Law &Ln,
-                               double &Kf, double &dc, double &dn) {
+// the neighbour is the higher-index side U.  Upstream takes K_U when
+// p_U - p_L >= 0, else K_L; harmonic 2 K_L K_U / (K_L + K_U); geometric
+// sqrt(K_L K_U); integral: the average of K_s k_r over the heads between p_L
+// and p_U (K_s the mean of the two sides), by the Gauss-Legendre rule held in
+// Phys, always evaluated from the L side so both cells of a face agree bitwise.
+__device__ inline void mean_of(const Phys &P, int dir, double pc, const Law &Lc, double Ksc, double pn,
+                               const Law &Ln, double Ksn, double &Kf, double &dc, double &dn) {
+    int mean = P.mean;
     if (mean == RICH_MEAN_ARITH) {
         Kf = 0.5 * (Lc.K + Ln.K);
         dc = 0.5 * Lc.dK;
@@ -108,6 +112,24 @@ __device__ inline void mean_of(int mean, int dir, double pc, const Law &Lc, doub
         Kf = 2.0 * Lc.K * Ln.K / s;
         dc = 2.0 * Ln.K * Ln.K * Lc.dK / (s * s);
         dn = 2.0 * Lc.K * Lc.K * Ln.dK / (s * s);
+    } else if (mean == RICH_MEAN_GEOMETRIC) {
+        double g = sqrt(Lc.K * Ln.K);
+        Kf = g;
+        dc = 0.5 * Ln.K * Lc.dK / g;
+        dn = 0.5 * Lc.K * Ln.dK / g;
+    } else if (mean == RICH_MEAN_INTEGRAL) {
+        double pL = dir > 0 ? pc : pn, pU = dir > 0 ? pn : pc;
+        double Ks = 0.5 * (dir > 0 ? Ksc + Ksn : Ksn + Ksc);
+        double q = 0.0, qL = 0.0, qU = 0.0;
+        for (int t = 0; t < RICH_GL; t++) {
+            Law L = laws(P, pL + (pU - pL) * P.gl_t[t], Ks);
+            q += P.gl_w[t] * L.K;
+            qL += P.gl_w[t] * (1.0 - P.gl_t[t]) * L.dK;
+            qU += P.gl_w[t] * P.gl_t[t] * L.dK;
+        }
+        Kf = q;
+        dc = dir > 0 ? qL : qU;
+        dn = dir > 0 ? qU : qL;
     } else {
         bool take_n = dir > 0 ? (pn - pc >= 0.0) : !(pc - pn >= 0.0);
         if (take_n) {
@@ -147,7 +169,7 @@ __global__ void k_residual(Phys P, uint32_t n, const double *__restrict__ Ks, co
         Law Ln = laws(P, fc.pn, fc.Ksn);
         double Kf, dc, dn;
         int dir = (f & 1) ? 1 : -1;
-        mean_of(P.mean, dir, pc, Lc, fc.pn, Ln, Kf, dc, dn);
+        mean_of(P, dir, pc, Lc, Ks[c], fc.pn, Ln, fc.Ksn, Kf, dc, dn);
         acc += -Kf * (fc.pn - pc) / (fc.h * fc.h);
         if ((f >> 1) == 2) acc += dir * (-(Lc.K + Ln.K) / (2.0 * P.hz));
     }
@@ -179,7 +201,7 @@ __global__ void k_assemble(Phys P, uint32_t n, const double *__restrict__ Ks, co
         Law Ln = laws(P, fc.pn, fc.Ksn);
         double Kf, dc, dn;
         int dir = (f & 1) ? 1 : -1;
-        mean_of(P.mean, dir, pc, Lc, fc.pn, Ln, Kf, dc, dn);
+        mean_of(P, dir, pc, Lc, Ks[c], fc.pn, Ln, fc.Ksn, Kf, dc, dn);
         double h2 = fc.h * fc.h;
         double dp = fc.pn - pc;
         bool zf = (f >> 1) == 2;

@@ -850,7 +850,7 @@ rich_status validate(const rich_problem_t *P, const rich_solver_opts_t *O) {
     int64_t n = (int64_t)P->nx * P->ny * P->nz;
     if (n >= (int64_t)1 << 31) return RICH_EINVAL;
     if (!(P->hx > 0) || !(P->hy > 0) || !(P->hz > 0) || !(P->dt > 0)) return RICH_EINVAL;
-    if (P->mean < 0 || P->mean > 2) return RICH_EINVAL;
+    if (P->mean < 0 || P->mean > 4) return RICH_EINVAL;
     for (int f = 0; f < 6; f++)
         if (P->bc_type[f] != RICH_BC_NOFLUX && P->bc_type[f] != RICH_BC_DIRICHLET) return RICH_EINVAL;
     if (!(P->alpha > 0) || !(P->A > 0) || !(P->beta > 1) || !(P->gamma > 1)) return RICH_EINVAL;
@@ -865,6 +865,30 @@ rich_status validate(const rich_problem_t *P, const rich_solver_opts_t *O) {
     if (!(O->gmres_reorth >= 0.0 && O->gmres_reorth < 1.0)) return RICH_EINVAL;
     if (!(O->eta > 0) || !(O->fnormtol > 0) || O->max_newton < 1 || O->msbset < 1) return RICH_EINVAL;
     return RICH_OK;
+}
+
+// Gauss-Legendre nodes and weights on [0, 1]: roots of the Legendre
+// polynomial P_n by Newton's method (three-term recurrence, cosine starting
+// values), weights 2 / ((1 - x^2) P_n'(x)^2), both mapped from [-1, 1].
+void gauss_legendre01(double *t, double *w, int n) {
+    const double pi = 3.14159265358979323846;
+    for (int i = 0; i < n; i++) {
+        double x = std::cos(pi * (i + 0.75) / (n + 0.5)), d = 1.0;
+        for (int it = 0; it < 100; it++) {
+            double a = 1.0, b = x;
+            for (int k = 2; k <= n; k++) {
+                double c = ((2.0 * k - 1.0) * x * b - (k - 1.0) * a) / k;
+                a = b;
+                b = c;
+            }
+            d = n * (x * b - a) / (x * x - 1.0);
+            double step = b / d;
+            x -= step;
+            if (std::fabs(step) < 1e-16) break;
+        }
+        t[i] = 0.5 * (1.0 - x);
+        w[i] = 1.0 / ((1.0 - x * x) * d * d);
+    }
 }
 
 Phys to_phys(const rich_problem_t *P) {
@@ -888,6 +912,7 @@ Phys to_phys(const rich_problem_t *P) {
     }
     q.dt = P->dt;
     q.tile_kz = 0;
+    gauss_legendre01(q.gl_t, q.gl_w, RICH_GL);
     return q;
 }
 

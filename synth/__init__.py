@@ -8,5 +8,5 @@ HIP path receive the arrays produced here as plain inputs.
 """
 from .fields import splitmix64, uniform01, std_normal, gaussian_field, lognormal_ks
 from .configs import (Problem, Options, Recipe, recipe, RECIPES, serving_stream, cube_problem,
-                      ARITH, UPSTREAM, HARMONIC, NOFLUX, DIRICHLET, FP64, MIXED,
+                      ARITH, UPSTREAM, HARMONIC, GEOMETRIC, INTEGRAL, NOFLUX, DIRICHLET, FP64, MIXED,
                       KS0, P_INIT, P_TOP, L_CUBE)

@@ -17,8 +17,9 @@ import numpy as np
 
 from .fields import lognormal_ks, uniform01
 
-ARITH, UPSTREAM, HARMONIC = 0, 1, 2
-MEAN_NAMES = {"arith": ARITH, "upstream": UPSTREAM, "harmonic": HARMONIC}
+ARITH, UPSTREAM, HARMONIC, GEOMETRIC, INTEGRAL = 0, 1, 2, 3, 4
+MEAN_NAMES = {"arith": ARITH, "upstream": UPSTREAM, "harmonic": HARMONIC, "geometric": GEOMETRIC,
+              "integral": INTEGRAL}
 NOFLUX, DIRICHLET = 0, 1
 FP64, MIXED = 0, 1
 

@@ -15,7 +15,7 @@ from tests.helpers import (all_dirichlet, box_problem, csr_close, random_heads, 
 
 pytestmark = pytest.mark.gpu
 
-MEANS = [synth.ARITH, synth.UPSTREAM, synth.HARMONIC]
+MEANS = [synth.ARITH, synth.UPSTREAM, synth.HARMONIC, synth.GEOMETRIC, synth.INTEGRAL]
 
 
 @pytest.fixture(scope="module")
@@ -165,9 +165,12 @@ def test_gmres_parity(rich, torch, orc):
     assert np.linalg.norm(x - xo) <= 10 * r.options.eta * np.linalg.norm(xo)
 
 
-@pytest.mark.parametrize("name,n,mean", [("c1", 12, None), ("c1", 16, None), ("c2", 20, None)])
+@pytest.mark.parametrize("name,n,mean", [("c1", 12, None), ("c1", 16, None), ("c2", 20, None),
+                                         ("c1", 16, synth.GEOMETRIC), ("c2", 16, synth.INTEGRAL)])
 def test_full_steps_fp64(rich, torch, orc, name, n, mean):
     r = smooth_recipe(name, n)
+    if mean is not None:
+        r.problem.mean = mean
     r.options.fnormtol = 1e-12
     r.options.precision = synth.FP64
     P = r.problem

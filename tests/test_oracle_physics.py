@@ -16,7 +16,7 @@ import scipy.sparse as sp
 import synth
 from tests.helpers import all_dirichlet, box_problem, random_heads, random_ks
 
-MEANS = [synth.ARITH, synth.UPSTREAM, synth.HARMONIC]
+MEANS = [synth.ARITH, synth.UPSTREAM, synth.HARMONIC, synth.GEOMETRIC, synth.INTEGRAL]
 
 
 def _P():
@@ -73,13 +73,23 @@ def paper_interior_residual(orc, P, ks, p, th_old, mean):
     nx, ny, nz = P.nx, P.ny, P.nz
     th, _, K, _ = orc.laws(P, p, ks)
     p3, K3 = p.reshape(nz, ny, nx), K.reshape(nz, ny, nx)
+    ks3 = np.broadcast_to(ks, p.shape).reshape(nz, ny, nx)
     th3, tho3 = th.reshape(nz, ny, nx), th_old.reshape(nz, ny, nx)
+    gt, gw = np.polynomial.legendre.leggauss(16)
+    gt, gw = 0.5 * (gt + 1.0), 0.5 * gw
 
-    def kav(KL, KU, pL, pU):
+    def kav(KL, KU, pL, pU, ksL, ksU):
         if mean == synth.ARITH:
             return 0.5 * (KL + KU)
         if mean == synth.HARMONIC:
             return 2 * KL * KU / (KL + KU)
+        if mean == synth.GEOMETRIC:
+            return np.sqrt(KL * KU)
+        if mean == synth.INTEGRAL:  # average of K over [pL, pU] with the mean K_s
+            kf = 0.5 * (ksL + ksU)
+            psi = pL[None] + (pU - pL)[None] * gt[:, None, None, None]
+            Kq = orc.laws(P, psi.ravel(), np.broadcast_to(kf[None], psi.shape).ravel())[2].reshape(psi.shape)
+            return np.tensordot(gw, Kq, axes=1)
         return np.where(pU - pL >= 0, KU, KL)
 
     out = np.zeros((nz - 2, ny - 2, nx - 2))
@@ -90,8 +100,8 @@ def paper_interior_residual(orc, P, ks, p, th_old, mean):
         up[ax] = slice(2, None)
         dn[ax] = slice(0, -2)
         up, dn = tuple(up), tuple(dn)
-        q_plus = -kav(K3[c], K3[up], p3[c], p3[up]) * (p3[up] - p3[c]) / h**2
-        q_minus = -kav(K3[dn], K3[c], p3[dn], p3[c]) * (p3[c] - p3[dn]) / h**2
+        q_plus = -kav(K3[c], K3[up], p3[c], p3[up], ks3[c], ks3[up]) * (p3[up] - p3[c]) / h**2
+        q_minus = -kav(K3[dn], K3[c], p3[dn], p3[c], ks3[dn], ks3[c]) * (p3[c] - p3[dn]) / h**2
         if ax == 0:
             q_plus = q_plus - K3[up] / (2 * h)
             q_minus = q_minus - K3[dn] / (2 * h)
@@ -304,3 +314,50 @@ def test_auxiliary_dflux_diagonal_is_the_diffusion_jacobian_diagonal(orc, mean):
     assert np.array_equal(off(Md), off(M))
     D = Md.toarray()
     assert np.array_equal(D, D.T)
+
+
+# ------------------------------------------------------- interface means
+def test_geometric_mean_between_harmonic_and_arithmetic(orc):
+    """Section 2.1: K^G = sqrt(K_L K_U); the classical HM <= GM <= AM ordering."""
+    rng = np.random.default_rng(21)
+    for _ in range(20):
+        pL, pU = rng.uniform(-80, -1, 2)
+        kL, kU = synth.KS0 * np.exp(rng.normal(0, 2, 2))
+        vals = {}
+        for m in (synth.ARITH, synth.HARMONIC, synth.GEOMETRIC):
+            P = _P()
+            P.mean = m
+            vals[m] = orc.face_mean(P, +1, pL, kL, pU, kU)[0]
+        KL = orc.laws(_P(), np.array([pL]), kL)[2][0]
+        KU = orc.laws(_P(), np.array([pU]), kU)[2][0]
+        assert vals[synth.GEOMETRIC] ** 2 == pytest.approx(KL * KU, rel=1e-14)
+        assert vals[synth.HARMONIC] <= vals[synth.GEOMETRIC] * (1 + 1e-15)
+        assert vals[synth.GEOMETRIC] <= vals[synth.ARITH] * (1 + 1e-15)
+
+
+def test_integral_mean_against_adaptive_quadrature(orc):
+    """The integral mean of Section 2.1, (1/(p_U - p_L)) * integral of K over
+    [p_L, p_U], against scipy's adaptive quadrature (the oracle's 16-point
+    Gauss-Legendre rule is accurate to ~1e-6 across the saturation kink), its
+    derivatives against central differences, the mean-value bounds, the
+    equal-head limit K(p) and the symmetry in the two sides."""
+    from scipy.integrate import quad
+    P = _P()
+    P.mean = synth.INTEGRAL
+    ks = synth.KS0
+    K = lambda x: orc.laws(P, np.array([x]), ks)[2][0]
+    for pL, pU in ((-61.5, -20.7), (-40.0, 5.0), (-61.5, -1.0), (-30.0, -20.7), (-5.0, -70.0), (2.0, 4.0)):
+        Kf, dL, dU = orc.face_mean(P, +1, pL, ks, pU, ks)
+        ref = quad(K, pL, pU, epsabs=0, epsrel=1e-12, limit=200)[0] / (pU - pL)
+        assert Kf == pytest.approx(ref, rel=2e-6)
+        assert min(K(pL), K(pU)) * (1 - 1e-12) <= Kf <= max(K(pL), K(pU)) * (1 + 1e-12)
+        h = 1e-5 * max(1.0, abs(pL))
+        fdL = (orc.face_mean(P, +1, pL + h, ks, pU, ks)[0] - orc.face_mean(P, +1, pL - h, ks, pU, ks)[0]) / (2 * h)
+        fdU = (orc.face_mean(P, +1, pL, ks, pU + h, ks)[0] - orc.face_mean(P, +1, pL, ks, pU - h, ks)[0]) / (2 * h)
+        assert dL == pytest.approx(fdL, rel=1e-5, abs=1e-12 * Kf)
+        assert dU == pytest.approx(fdU, rel=1e-5, abs=1e-12 * Kf)
+        # seen from the other cell (direction -1) the same face gives the same mean
+        Kr, dcr, dnr = orc.face_mean(P, -1, pU, ks, pL, ks)
+        assert Kr == Kf and dcr == dU and dnr == dL
+    Kf = orc.face_mean(P, +1, -33.0, ks, -33.0, ks)[0]
+    assert Kf == pytest.approx(K(-33.0), rel=1e-14)
