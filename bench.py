@@ -294,6 +294,9 @@ def main():
     ap.add_argument("--steps", type=int, default=9)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=256, help="cube size (256 = the benchmark workload)")
+    ap.add_argument("--workload", choices=["c3", "paper3d"], default="c3",
+                    help="c3: the 256^3 benchmark; paper3d: the paper's own 3-D infiltration test "
+                         "(798 x 798 x 38 unknowns; run it with --warmup 0 --steps 9 for the whole simulation)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the all-FP64 comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-profile", action="store_true", help="no per-kernel event timing")
@@ -339,7 +342,7 @@ def main():
     if args.serving:
         print(json.dumps(run_serving(args)), flush=True)
         return
-    rec = synth.recipe("c3", n=args.n)
+    rec = synth.recipe("c3", n=args.n) if args.workload == "c3" else synth.recipe("paper3d")
     for kv in args.set:
         k, v = kv.split("=")
         setattr(rec.options, k, type(getattr(rec.options, k))(float(v)))
@@ -398,8 +401,10 @@ def main():
         "vs_baseline": None,
         "dtype": "f64 (Newton, GMRES) + f32 (AMG V-cycle)",
         "data": "synthetic",
-        "config": {"workload": rec.name, "cells": rec.problem.n, "grid": [rec.problem.nx] * 3,
-                   "mean": "upstream", "dt_s": rec.problem.dt, "ks_sigma_ln": rec.ks_sigma,
+        "config": {"workload": rec.name, "cells": rec.problem.n,
+                   "grid": [rec.problem.nx, rec.problem.ny, rec.problem.nz],
+                   "mean": ["arith", "upstream", "harmonic", "geometric", "integral"][rec.problem.mean],
+                   "dt_s": rec.problem.dt, "ks_sigma_ln": rec.ks_sigma,
                    "ks_corr_cells": list(rec.ks_ell), "newton_tol": rec.options.fnormtol,
                    "gmres": f"GMRES({rec.options.gmres_restart}) eta {rec.options.eta}",
                    "amg": "matching aggregation (<=8), V(1,1) l1-Jacobi, dense coarsest"},
@@ -450,7 +455,7 @@ def main():
         out["kernels"] = kern
         dom = max(kern, key=lambda k: kern[k]["total_ms"])
         d = kern[dom]
-        ratio = traffic_ratio(dom) if args.n == 256 else None
+        ratio = traffic_ratio(dom) if (args.n == 256 and args.workload == "c3") else None
         out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": d["gbs"], "peak": HBM_PEAK_GBS,
                            "unit": "GB/s", "frac": d["gbs"] / HBM_PEAK_GBS,
                            "traffic": ratio * d["bytes_per_launch"] if ratio is not None else None,

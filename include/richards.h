@@ -79,6 +79,14 @@ typedef struct rich_problem {
     int bc_type[6];      /* RICH_BC_* per face -x,+x,-y,+y,-z,+z */
     double bc_value[6];  /* Dirichlet head [cm] per face */
     double dt;           /* time step [s] (> 0) */
+    /* optional Dirichlet patch (Section 6's 3-D test: zero head on a square of the top face):
+       boundary nodes of face patch_face (-1: none; the face must be Dirichlet) whose two
+       tangential coordinates lie in [patch_lo, patch_hi] (cm; node (i,j) of a face sits at
+       ((i+1) h, (j+1) h) along the face's axes in x, y, z order) take patch_value instead of
+       bc_value[patch_face] */
+    int patch_face;
+    double patch_lo[2], patch_hi[2];
+    double patch_value;
 } rich_problem_t;
 
 /* Solver controls (Sections 3 and 6). */

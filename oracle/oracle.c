@@ -72,8 +72,10 @@ void orc_theta(const orc_problem *P, const double *p, double *theta)
 /* ------------------------------------------------------------------------ */
 /* Grid faces.  Face f = 0..5 is -x,+x,-y,+y,-z,+z.  A face either joins two */
 /* unknowns (interior), or touches a Dirichlet boundary node whose head is    */
-/* the face's value and whose K_s is the adjacent cell's (the paper treats K_s */
-/* as a constant), or is a no-flux face, which carries no flux at all.        */
+/* the face's value (or the patch value where the optional Dirichlet patch  */
+/* covers the node: the square of zero head on the top face of Section 6's  */
+/* 3-D test) and whose K_s is the adjacent cell's (the paper treats K_s as a */
+/* constant), or is a no-flux face, which carries no flux at all.            */
 /* ------------------------------------------------------------------------ */
 typedef struct {
     int interior;
@@ -105,6 +107,13 @@ static int face_info(const orc_problem *P, int i, int j, int k, int f, const dou
         F->interior = 0;
         F->n = -1;
         F->pn = P->bc_value[f];
+        if (f == P->patch_face) {
+            /* the boundary node's coordinates along the face's two axes */
+            double u = axis == 0 ? (j + 1) * P->hy : (i + 1) * P->hx;
+            double v = axis == 2 ? (j + 1) * P->hy : (k + 1) * P->hz;
+            if (u >= P->patch_lo[0] && u <= P->patch_hi[0] && v >= P->patch_lo[1] && v <= P->patch_hi[1])
+                F->pn = P->patch_value;
+        }
         F->Ksn = Ks[c];
         return 1;
     }

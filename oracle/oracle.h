@@ -46,6 +46,9 @@ typedef struct {
     int bc_type[6];
     double bc_value[6];
     double dt;
+    int patch_face;                 /* Dirichlet patch on one face (-1: none) */
+    double patch_lo[2], patch_hi[2];
+    double patch_value;
 } orc_problem;
 
 typedef struct {

@@ -35,7 +35,8 @@ class Problem(C.Structure):
                 ("alpha", C.c_double), ("beta", C.c_double), ("theta_s", C.c_double),
                 ("theta_r", C.c_double), ("A", C.c_double), ("gamma", C.c_double),
                 ("mean", C.c_int), ("bc_type", C.c_int * 6), ("bc_value", C.c_double * 6),
-                ("dt", C.c_double)]
+                ("dt", C.c_double), ("patch_face", C.c_int), ("patch_lo", C.c_double * 2),
+                ("patch_hi", C.c_double * 2), ("patch_value", C.c_double)]
 
 
 class Opts(C.Structure):
@@ -142,6 +143,11 @@ def make_problem(p) -> Problem:
     for t in range(6):
         c.bc_type[t] = int(p.bc_type[t])
         c.bc_value[t] = float(p.bc_value[t])
+    c.patch_face = int(getattr(p, "patch_face", -1))
+    for t in range(2):
+        c.patch_lo[t] = float(getattr(p, "patch_lo", (0.0, 0.0))[t])
+        c.patch_hi[t] = float(getattr(p, "patch_hi", (0.0, 0.0))[t])
+    c.patch_value = float(getattr(p, "patch_value", 0.0))
     return c
 
 

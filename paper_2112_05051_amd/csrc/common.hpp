@@ -55,6 +55,8 @@ struct Phys {
     int bc_type[6];
     double bc_value[6];
     double dt;
+    int patch_face;  // Dirichlet patch on one face (-1: none)
+    double patch_lo[2], patch_hi[2], patch_value;
     int tile_kz;  // planes per block of the tiled fine-level smoother (0: automatic)
     double gl_t[RICH_GL], gl_w[RICH_GL];  // Gauss-Legendre rule on [0, 1] of the integral mean
 };

@@ -57,7 +57,8 @@ __device__ inline Law laws(const Phys &P, double p, double Ks) {
 }
 
 // One face of cell c.  kind: 0 = none (no-flux face), 1 = interior neighbour,
-// 2 = Dirichlet boundary node (head = face value, K_s = the cell's).
+// 2 = Dirichlet boundary node (head = face value, or the patch value where the
+// optional Dirichlet patch covers the node; K_s = the cell's).
 struct Face {
     int kind;
     uint32_t n;
@@ -84,6 +85,13 @@ __device__ inline Face face(const Phys &P, const Cell &q, uint32_t c, int f, con
         F.kind = 2;
         F.n = c;
         F.pn = P.bc_value[f];
+        if (f == P.patch_face) {
+            // the boundary node's coordinates along the face's two axes
+            double u = axis == 0 ? (q.j + 1) * P.hy : (q.i + 1) * P.hx;
+            double v = axis == 2 ? (q.j + 1) * P.hy : (q.k + 1) * P.hz;
+            if (u >= P.patch_lo[0] && u <= P.patch_hi[0] && v >= P.patch_lo[1] && v <= P.patch_hi[1])
+                F.pn = P.patch_value;
+        }
         F.Ksn = Ks[c];
     } else {
         F.kind = 0;

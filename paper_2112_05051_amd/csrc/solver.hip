@@ -851,6 +851,9 @@ rich_status validate(const rich_problem_t *P, const rich_solver_opts_t *O) {
     if (n >= (int64_t)1 << 31) return RICH_EINVAL;
     if (!(P->hx > 0) || !(P->hy > 0) || !(P->hz > 0) || !(P->dt > 0)) return RICH_EINVAL;
     if (P->mean < 0 || P->mean > 4) return RICH_EINVAL;
+    if (P->patch_face < -1 || P->patch_face > 5) return RICH_EINVAL;
+    if (P->patch_face >= 0 && (P->bc_type[P->patch_face] != RICH_BC_DIRICHLET || !std::isfinite(P->patch_value)))
+        return RICH_EINVAL;
     for (int f = 0; f < 6; f++)
         if (P->bc_type[f] != RICH_BC_NOFLUX && P->bc_type[f] != RICH_BC_DIRICHLET) return RICH_EINVAL;
     if (!(P->alpha > 0) || !(P->A > 0) || !(P->beta > 1) || !(P->gamma > 1)) return RICH_EINVAL;
@@ -911,6 +914,12 @@ Phys to_phys(const rich_problem_t *P) {
         q.bc_value[f] = P->bc_value[f];
     }
     q.dt = P->dt;
+    q.patch_face = P->patch_face;
+    for (int t = 0; t < 2; t++) {
+        q.patch_lo[t] = P->patch_lo[t];
+        q.patch_hi[t] = P->patch_hi[t];
+    }
+    q.patch_value = P->patch_value;
     q.tile_kz = 0;
     gauss_legendre01(q.gl_t, q.gl_w, RICH_GL);
     return q;

@@ -48,6 +48,12 @@ class Problem:
     bc_type: tuple = (NOFLUX, NOFLUX, NOFLUX, NOFLUX, NOFLUX, DIRICHLET)
     bc_value: tuple = (0.0, 0.0, 0.0, 0.0, 0.0, P_TOP)
     dt: float = 1.0
+    # optional Dirichlet patch: boundary nodes of face patch_face whose two
+    # tangential coordinates [cm] lie in [patch_lo, patch_hi] hold patch_value
+    patch_face: int = -1
+    patch_lo: tuple = (0.0, 0.0)
+    patch_hi: tuple = (0.0, 0.0)
+    patch_value: float = 0.0
 
     @property
     def n(self) -> int:
@@ -93,6 +99,8 @@ class Recipe:
 
     def ks(self) -> np.ndarray:
         p = self.problem
+        if self.ks_sigma == 0.0:
+            return np.full(p.n, KS0, dtype=np.float64)
         return lognormal_ks((p.nx, p.ny, p.nz), KS0, self.ks_sigma, self.ks_ell, self.ks_seed)
 
     def p0(self) -> np.ndarray:
@@ -130,7 +138,25 @@ def _c5(n: int = 512) -> Recipe:
                   "512^3 lognormal K_s (sigma 3, l=32/32/4), harmonic mean, dt=30 s, 5 steps")
 
 
-RECIPES = {"c1": _c1, "c2": _c2, "c3": _c3, "c5": _c5}
+def _paper3d(n: int = 798, nz: int | None = None, precision: int = MIXED) -> Recipe:
+    """The 3-D infiltration test of the paper's experiments (Section 6): the
+    box [0,64] x [0,64] x [0,1] cm with 800 x 800 x 40 mesh points (798 x 798
+    x 38 unknowns), upstream mean, head h_r on every face except a square of
+    zero head in the middle of the top face (a/4 <= x, y <= 3a/4), initial
+    head h_r, t in [0, 2] s with 10 time levels (9 steps of 2/9 s), GMRES(10)
+    with eta = 1e-7.  The paper leaves h_r and the constitutive parameters of
+    this test unstated: h_r = -61.5 cm and the Haverkamp parameters of its
+    Fig. 1 with a homogeneous K_s are used."""
+    nz = nz if nz is not None else 38
+    P = Problem(nx=n, ny=n, nz=nz, hx=64.0 / (n + 1), hy=64.0 / (n + 1), hz=1.0 / (nz + 1), mean=UPSTREAM,
+                bc_type=(DIRICHLET,) * 6, bc_value=(P_INIT,) * 6, dt=2.0 / 9.0,
+                patch_face=5, patch_lo=(16.0, 16.0), patch_hi=(48.0, 48.0), patch_value=0.0)
+    o = Options(precision=precision, gmres_restart=10, eta=1e-7)
+    return Recipe(f"paper3d_{n + 2}x{n + 2}x{nz + 2}", P, o, 9, 0.0, (1, 1, 1), 0,
+                  "the paper's 3-D infiltration test: upstream mean, zero-head square on the top face")
+
+
+RECIPES = {"c1": _c1, "c2": _c2, "c3": _c3, "c5": _c5, "paper3d": _paper3d}
 
 
 def recipe(name: str, n: int | None = None, **kw) -> Recipe:

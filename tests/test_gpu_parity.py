@@ -296,3 +296,29 @@ def test_vcycle_tiled_stencil(rich, torch, orc, mean, smoothed):
         xm = s.apply_prec(dev(torch, b)).cpu().numpy()
         s.close()
         assert np.linalg.norm(xm - xo) <= 1e-5 * np.linalg.norm(xo)
+
+
+@pytest.mark.parametrize("precision,tol", [(synth.FP64, 1e-8), (synth.MIXED, 1e-6)])
+def test_paper_3d_case_steps(rich, torch, orc, precision, tol):
+    """Section 6's 3-D test (zero-head square on the top face, GMRES(10),
+    eta 1e-7) on a reduced 30 x 30 x 6 grid: two steps against the oracle."""
+    r = synth.recipe("paper3d", n=30, nz=6, precision=precision)
+    if precision == synth.FP64:
+        r.options.fnormtol = 1e-12
+    P = r.problem
+    ks, p = r.ks(), r.p0()
+    s = make_solver(rich, torch, P, ks, r.options)
+    s.set_state(dev(torch, p))
+    th = orc.theta(P, p)
+    F_g = s.residual(dev(torch, p), dev(torch, th)).cpu().numpy()
+    F_o = orc.residual(P, ks, p, th)
+    assert np.max(np.abs(F_g - F_o)) <= 1e-12 * np.max(np.abs(F_o))
+    o = orc.Solver(P, r.options, ks)
+    po = p.copy()
+    for step in range(2):
+        sg = s.step(1)[0]
+        so = o.step(po)
+        assert sg["status"] == 0 and so["status"] == 0
+        pg = s.get_state().cpu().numpy()
+        err = np.linalg.norm(pg - po) / np.linalg.norm(po)
+        assert err <= tol, (step, err, sg, so)

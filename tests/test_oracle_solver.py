@@ -260,3 +260,33 @@ def test_failure_paths(orc):
     st = S.step(q)
     assert st["status"] in (orc.MAXITER, orc.STEP_TOO_SMALL, orc.LINESEARCH_FAIL)
     assert np.array_equal(q, p) or st["status"] == orc.STEP_TOO_SMALL
+
+
+def test_paper_3d_case_patch_and_symmetry(orc):
+    """Section 6's 3-D test: a zero-head square on the top face.  Phi changes
+    only in the top-layer cells under the square (counted independently from
+    the node coordinates), and the solution keeps the square's symmetries
+    (x <-> y and both mirrors) after two steps."""
+    r = synth.recipe("paper3d", n=20, nz=5)
+    r.options.precision = synth.FP64
+    P = r.problem
+    ks, p = r.ks(), r.p0()
+    th = orc.theta(P, p)
+    F1 = orc.residual(P, ks, p, th)
+    P0 = synth.recipe("paper3d", n=20, nz=5).problem
+    P0.patch_face = -1
+    F0 = orc.residual(P0, ks, p, th)
+    changed = np.abs(F1 - F0).reshape(P.nz, P.ny, P.nx) > 0
+    x = (np.arange(P.nx) + 1) * P.hx
+    y = (np.arange(P.ny) + 1) * P.hy
+    inside = ((x >= 16) & (x <= 48))[None, :] & ((y >= 16) & (y <= 48))[:, None]
+    assert inside.sum() > 0 and np.array_equal(changed[-1], inside) and not changed[:-1].any()
+    S = orc.Solver(P, r.options, ks)
+    for _ in range(2):
+        st = S.step(p)
+        assert st["status"] == 0
+    p3 = p.reshape(P.nz, P.ny, P.nx)
+    scale = np.abs(p3).max()
+    for q in (p3.transpose(0, 2, 1), p3[:, :, ::-1], p3[:, ::-1, :]):
+        assert np.abs(p3 - q).max() <= 1e-10 * scale
+    assert p3[-1][inside].max() > P.bc_value[0] + 1.0  # water entered under the square
