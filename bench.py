@@ -111,7 +111,7 @@ FAMILIES = {
     "update": ("k_update_norm<", "la.hip"),
     "multidot": ("k_multidot<", "la.hip"),
     "spmv_J": ("k_spmv_J<float>", "fine.hip"),
-    "vc0_pre": ("k_st25<double, float, false>", "fine.hip"),
+    "vc0_pre": ("k_st25<double, float, 0>", "fine.hip"),
     "residual": ("k_residual", "fine.hip"),
 }
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "traffic_c3_256cube_mixed.md")
@@ -129,7 +129,7 @@ def algorithmic_bytes(name, n, mixed=True):
         return (8 * n * (k + 1), 0) if m.group(1) == "multidot" else (8 * n * (k + 1), 8 * n)
     if "k_spmv_J<float>" in name:
         return (60 * n, 8 * n)
-    if "k_st25<double, float, false>" in name or "k_st_pre<double, float>" in name:
+    if "k_st25<double, float, 0>" in name or "k_st_pre<double, float>" in name:
         return (8 * n + 5 * t * n, t * n)
     if "k_residual" in name:
         return (24 * n, 8 * n)
