@@ -196,44 +196,47 @@ __global__ void k_sym_write(int64_t nc, const int64_t *__restrict__ segptr, cons
 
 // Numeric product on a fixed pattern: members ascending, each fine row in
 // column order, every term added to its coarse entry in that order (the
-// oracle's order), starting from zero.  Rows of up to GAL_REG entries are
-// accumulated in registers; longer rows directly in the output.
-constexpr int GAL_REG = 48;
+// oracle's order), starting from zero.  One thread per coarse row; rows of up
+// to GAL_REG entries accumulate in LDS (column-major over the block's 64
+// threads, so dynamic indexing never spills to scratch memory), longer rows
+// directly in the output.
+constexpr int GAL_REG = 32;
 __global__ void __launch_bounds__(64) k_gal_numeric(int64_t nc, const int64_t *__restrict__ mptr,
                                                     const int32_t *__restrict__ mem, const int64_t *__restrict__ rowptr,
                                                     const int32_t *__restrict__ col, const double *__restrict__ val,
                                                     const int32_t *__restrict__ agg, const int64_t *__restrict__ crow,
                                                     const int32_t *__restrict__ ccol, double *__restrict__ cval) {
+    __shared__ double acc_s[GAL_REG * 64];
+    __shared__ int32_t cj_s[GAL_REG * 64];
     int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (I >= nc) return;
+    const int t = threadIdx.x;
     int64_t a = crow[I], b = crow[I + 1];
     int len = (int)(b - a);
     if (len <= GAL_REG) {
-        int32_t cj[GAL_REG];
-        double acc[GAL_REG];
         for (int e = 0; e < len; e++) {
-            cj[e] = ccol[a + e];
-            acc[e] = 0.0;
+            cj_s[e * 64 + t] = ccol[a + e];
+            acc_s[e * 64 + t] = 0.0;
         }
-        for (int64_t t = mptr[I]; t < mptr[I + 1]; t++) {
-            int32_t i = mem[t];
+        for (int64_t q = mptr[I]; q < mptr[I + 1]; q++) {
+            int32_t i = mem[q];
             for (int64_t e = rowptr[i]; e < rowptr[i + 1]; e++) {
                 int32_t J = agg[col[e]];
                 int lo = 0, hi = len - 1;
                 while (lo < hi) {
                     int mid = (lo + hi) >> 1;
-                    if (cj[mid] < J) lo = mid + 1;
+                    if (cj_s[mid * 64 + t] < J) lo = mid + 1;
                     else hi = mid;
                 }
-                acc[lo] += val[e];
+                acc_s[lo * 64 + t] += val[e];
             }
         }
-        for (int e = 0; e < len; e++) cval[a + e] = acc[e];
+        for (int e = 0; e < len; e++) cval[a + e] = acc_s[e * 64 + t];
         return;
     }
     for (int64_t e = a; e < b; e++) cval[e] = 0.0;
-    for (int64_t t = mptr[I]; t < mptr[I + 1]; t++) {
-        int32_t i = mem[t];
+    for (int64_t q = mptr[I]; q < mptr[I + 1]; q++) {
+        int32_t i = mem[q];
         for (int64_t e = rowptr[i]; e < rowptr[i + 1]; e++) {
             int32_t J = agg[col[e]];
             int64_t lo = a, hi = b - 1;
