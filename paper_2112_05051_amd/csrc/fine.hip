@@ -256,13 +256,16 @@ __global__ void k_spmv_J(Phys P, uint32_t n, const double *__restrict__ J7, cons
     if (c >= n) return;
     Cell q = cell_of(P, c);
     uint32_t nx = P.nx, nxy = (uint32_t)P.nx * (uint32_t)P.ny;
-    double s = J7[(size_t)J_D * n + c] * (double)x[c];
-    if (q.i > 0) s += J7[(size_t)J_XM * n + c] * (double)x[c - 1];
-    if (q.i < P.nx - 1) s += J7[(size_t)J_XP * n + c] * (double)x[c + 1];
-    if (q.j > 0) s += J7[(size_t)J_YM * n + c] * (double)x[c - nx];
-    if (q.j < P.ny - 1) s += J7[(size_t)J_YP * n + c] * (double)x[c + nx];
-    if (q.k > 0) s += J7[(size_t)J_ZM * n + c] * (double)x[c - nxy];
-    if (q.k < P.nz - 1) s += J7[(size_t)J_ZP * n + c] * (double)x[c + nxy];
+    // J is streamed (non-temporal): its 7 arrays are far larger than the caches
+#define JL(t) __builtin_nontemporal_load(J7 + (size_t)(t) * n + c)
+    double s = JL(J_D) * (double)x[c];
+    if (q.i > 0) s += JL(J_XM) * (double)x[c - 1];
+    if (q.i < P.nx - 1) s += JL(J_XP) * (double)x[c + 1];
+    if (q.j > 0) s += JL(J_YM) * (double)x[c - nx];
+    if (q.j < P.ny - 1) s += JL(J_YP) * (double)x[c + nx];
+    if (q.k > 0) s += JL(J_ZM) * (double)x[c - nxy];
+    if (q.k < P.nz - 1) s += JL(J_ZP) * (double)x[c + nxy];
+#undef JL
     y[c] = s;
 }
 

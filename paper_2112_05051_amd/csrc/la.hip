@@ -72,8 +72,13 @@ __global__ void __launch_bounds__(RED_THREADS) k_multidot(const double *__restri
     for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n2; c += (int64_t)gridDim.x * blockDim.x) {
         double2 wc = w2[c];
         double2 v[K];
+        // the basis is streamed (non-temporal): it is far larger than the caches
+        typedef double d2v __attribute__((ext_vector_type(2)));
 #pragma unroll
-        for (int i = 0; i < K; i++) v[i] = reinterpret_cast<const double2 *>(V + (size_t)i * ldv)[c];
+        for (int i = 0; i < K; i++) {
+            d2v t = __builtin_nontemporal_load(reinterpret_cast<const d2v *>(V + (size_t)i * ldv) + c);
+            v[i] = make_double2(t.x, t.y);
+        }
 #pragma unroll
         for (int i = 0; i < K; i++) acc[i] += v[i].x * wc.x + v[i].y * wc.y;
         acc[K] += wc.x * wc.x + wc.y * wc.y;
@@ -131,20 +136,23 @@ __global__ void __launch_bounds__(RED_THREADS) k_update_norm(const double *__res
     for (int i = 0; i < K; i++) hr[i] = h[i] * vs[i];
     double acc = 0.0;
     const int64_t n2 = n >> 1;
-    double2 *__restrict__ w2 = reinterpret_cast<double2 *>(w);
+    // streaming loads and stores: nothing here is re-read before it leaves the caches
+    typedef double d2v __attribute__((ext_vector_type(2)));
+    d2v *__restrict__ w2 = reinterpret_cast<d2v *>(w);
     for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n2; c += (int64_t)gridDim.x * blockDim.x) {
-        double2 wc = w2[c];
-        double2 v[K];
+        d2v wc = __builtin_nontemporal_load(w2 + c);
+        d2v v[K];
 #pragma unroll
-        for (int i = 0; i < K; i++) v[i] = reinterpret_cast<const double2 *>(V + (size_t)i * ldv)[c];
+        for (int i = 0; i < K; i++) v[i] = __builtin_nontemporal_load(reinterpret_cast<const d2v *>(V + (size_t)i * ldv) + c);
 #pragma unroll
         for (int i = 0; i < K; i++) {
             wc.x -= hr[i] * v[i].x;
             wc.y -= hr[i] * v[i].y;
         }
-        w2[c] = wc;
+        __builtin_nontemporal_store(wc, w2 + c);
         acc += wc.x * wc.x + wc.y * wc.y;
     }
+
     if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
         double wc = w[n - 1];
 #pragma unroll
