@@ -75,7 +75,7 @@ typedef struct rich_problem {
     /* eq. (s(p)): theta = alpha (theta_s - theta_r) / (alpha + |p|^beta) + theta_r
        eq. (K(p)): K = K_s A / (A + |p|^gamma); p >= 0 is saturated */
     double alpha, beta, theta_s, theta_r, A, gamma;
-    int mean;            /* RICH_MEAN_* */
+    int mean;            /* RICH_MEAN_* on every face, or on the x and y faces when mean_vertical >= 0 */
     int bc_type[6];      /* RICH_BC_* per face -x,+x,-y,+y,-z,+z */
     double bc_value[6];  /* Dirichlet head [cm] per face */
     double dt;           /* time step [s] (> 0) */
@@ -87,6 +87,8 @@ typedef struct rich_problem {
     int patch_face;
     double patch_lo[2], patch_hi[2];
     double patch_value;
+    int mean_vertical;   /* RICH_MEAN_* on the z faces (Section 2.1: one mean for the horizontal and
+                            another for the vertical direction); -1 = the same as mean */
 } rich_problem_t;
 
 /* Solver controls (Sections 3 and 6). */

@@ -162,11 +162,12 @@ static void gl_init(void)
 /* Legendre rule on [p_L, p_U] (no closed form for this K(p)); its          */
 /* derivatives are those of the rule.  Returns the mean and its partial     */
 /* derivatives w.r.t. the cell's and the neighbour's heads (the upstream    */
-/* derivative does not differentiate the switch).                           */
-static void face_mean(const orc_problem *P, int dir, double pc, double Ksc, const double Lc[4],
+/* derivative does not differentiate the switch).  With mean_vertical >= 0 */
+/* the z faces take that mean instead (Section 2.1's per-direction option). */
+static void face_mean(const orc_problem *P, int axis, int dir, double pc, double Ksc, const double Lc[4],
                       double pn, double Ksn, const double Ln[4], double *Kf, double *dc, double *dn)
 {
-    int mean = P->mean;
+    int mean = (axis == 2 && P->mean_vertical >= 0) ? P->mean_vertical : P->mean;
     double Kc = Lc[2], dKc = Lc[3], Kn = Ln[2], dKn = Ln[3];
     if (mean == ORC_ARITH) {
         *Kf = 0.5 * (Kc + Kn);
@@ -207,13 +208,13 @@ static void face_mean(const orc_problem *P, int dir, double pc, double Ksc, cons
     }
 }
 
-void orc_face_mean(const orc_problem *P, int dir, double pc, double Ksc, double pn, double Ksn,
-                   double out[3])
+void orc_face_mean(const orc_problem *P, int axis, int dir, double pc, double Ksc, double pn,
+                   double Ksn, double out[3])
 {
     double Lc[4], Ln[4];
     orc_laws(P, pc, Ksc, Lc);
     orc_laws(P, pn, Ksn, Ln);
-    face_mean(P, dir, pc, Ksc, Lc, pn, Ksn, Ln, &out[0], &out[1], &out[2]);
+    face_mean(P, axis, dir, pc, Ksc, Lc, pn, Ksn, Ln, &out[0], &out[1], &out[2]);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -238,7 +239,7 @@ void orc_residual(const orc_problem *P, const double *Ks, const double *p, const
                     if (!face_info(P, i, j, k, f, p, Ks, &fc)) continue;
                     orc_laws(P, fc.pn, fc.Ksn, Ln);
                     double Kf, dc, dn;
-                    face_mean(P, fc.dir, p[c], Ks[c], Lc, fc.pn, fc.Ksn, Ln, &Kf, &dc, &dn);
+                    face_mean(P, fc.axis, fc.dir, p[c], Ks[c], Lc, fc.pn, fc.Ksn, Ln, &Kf, &dc, &dn);
                     acc += -Kf * (fc.pn - p[c]) / (fc.h * fc.h);
                     if (fc.axis == 2) acc += fc.dir * (-(Lc[2] + Ln[2]) / (2.0 * P->hz));
                 }
@@ -286,7 +287,7 @@ static void assemble(const orc_problem *P, const double *Ks, const double *p, in
                     if (!face_info(P, i, j, k, f, p, Ks, &fc)) continue;
                     orc_laws(P, fc.pn, fc.Ksn, Ln);
                     double Kf, dc, dn;
-                    face_mean(P, fc.dir, p[c], Ks[c], Lc, fc.pn, fc.Ksn, Ln, &Kf, &dc, &dn);
+                    face_mean(P, fc.axis, fc.dir, p[c], Ks[c], Lc, fc.pn, fc.Ksn, Ln, &Kf, &dc, &dn);
                     double h2 = fc.h * fc.h;
                     double dp = fc.pn - p[c];
                     if (which == 0) {

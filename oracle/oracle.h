@@ -49,6 +49,7 @@ typedef struct {
     int patch_face;                 /* Dirichlet patch on one face (-1: none) */
     double patch_lo[2], patch_hi[2];
     double patch_value;
+    int mean_vertical;              /* mean on z faces (-1: the same as mean) */
 } orc_problem;
 
 typedef struct {
@@ -87,8 +88,8 @@ typedef struct {
 /* ---- constitutive laws, residual, Jacobian, auxiliary matrix ---- */
 void orc_laws(const orc_problem *P, double p, double Ks, double out[4]); /* theta, theta', K, K' */
 /* interface mean of a face between heads pc and pn (dir = +1: pn on the higher-index side) */
-void orc_face_mean(const orc_problem *P, int dir, double pc, double Ksc, double pn, double Ksn,
-                   double out[3]); /* K_f, dK_f/dp_c, dK_f/dp_n */
+void orc_face_mean(const orc_problem *P, int axis, int dir, double pc, double Ksc, double pn,
+                   double Ksn, double out[3]); /* K_f, dK_f/dp_c, dK_f/dp_n */
 void orc_laws_array(const orc_problem *P, int64_t n, const double *p, const double *Ks,
                     double *out /* n x 4 */);
 void orc_theta(const orc_problem *P, const double *p, double *theta);

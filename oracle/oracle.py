@@ -37,7 +37,7 @@ class CProblem(C.Structure):
                 ("theta_r", C.c_double), ("A", C.c_double), ("gamma", C.c_double),
                 ("mean", C.c_int), ("bc_type", C.c_int * 6), ("bc_value", C.c_double * 6),
                 ("dt", C.c_double), ("patch_face", C.c_int), ("patch_lo", C.c_double * 2),
-                ("patch_hi", C.c_double * 2), ("patch_value", C.c_double)]
+                ("patch_hi", C.c_double * 2), ("patch_value", C.c_double), ("mean_vertical", C.c_int)]
 
 
 class COpts(C.Structure):
@@ -71,7 +71,7 @@ def lib():
         vp = C.c_void_p
         L.orc_laws_array.argtypes = [P(CProblem), C.c_int64, d, d, d]
         L.orc_theta.argtypes = [P(CProblem), d, d]
-        L.orc_face_mean.argtypes = [P(CProblem), C.c_int, C.c_double, C.c_double, C.c_double, C.c_double, d]
+        L.orc_face_mean.argtypes = [P(CProblem), C.c_int, C.c_int, C.c_double, C.c_double, C.c_double, C.c_double, d]
         L.orc_residual.argtypes = [P(CProblem), d, d, d, d]
         L.orc_pattern_nnz.argtypes = [P(CProblem)]
         L.orc_pattern_nnz.restype = C.c_int64
@@ -138,6 +138,7 @@ def cproblem(P) -> CProblem:
         c.patch_lo[t] = float(getattr(P, "patch_lo", (0.0, 0.0))[t])
         c.patch_hi[t] = float(getattr(P, "patch_hi", (0.0, 0.0))[t])
     c.patch_value = float(getattr(P, "patch_value", 0.0))
+    c.mean_vertical = int(getattr(P, "mean_vertical", -1))
     return c
 
 
@@ -162,11 +163,13 @@ def laws(P, p, Ks):
     return out[:, 0], out[:, 1], out[:, 2], out[:, 3]
 
 
-def face_mean(P, direction, pc, Ksc, pn, Ksn):
-    """(K_f, dK_f/dp_c, dK_f/dp_n) of one face (direction +1: pn on the higher-index side)."""
+def face_mean(P, direction, pc, Ksc, pn, Ksn, axis=0):
+    """(K_f, dK_f/dp_c, dK_f/dp_n) of one face on the given axis (direction +1: pn on
+    the higher-index side)."""
     out = np.empty(3)
     cp = cproblem(P)
-    lib().orc_face_mean(C.byref(cp), int(direction), float(pc), float(Ksc), float(pn), float(Ksn), _d(out))
+    lib().orc_face_mean(C.byref(cp), int(axis), int(direction), float(pc), float(Ksc), float(pn), float(Ksn),
+                        _d(out))
     return out[0], out[1], out[2]
 
 

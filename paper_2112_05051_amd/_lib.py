@@ -36,7 +36,7 @@ class Problem(C.Structure):
                 ("theta_r", C.c_double), ("A", C.c_double), ("gamma", C.c_double),
                 ("mean", C.c_int), ("bc_type", C.c_int * 6), ("bc_value", C.c_double * 6),
                 ("dt", C.c_double), ("patch_face", C.c_int), ("patch_lo", C.c_double * 2),
-                ("patch_hi", C.c_double * 2), ("patch_value", C.c_double)]
+                ("patch_hi", C.c_double * 2), ("patch_value", C.c_double), ("mean_vertical", C.c_int)]
 
 
 class Opts(C.Structure):
@@ -148,6 +148,7 @@ def make_problem(p) -> Problem:
         c.patch_lo[t] = float(getattr(p, "patch_lo", (0.0, 0.0))[t])
         c.patch_hi[t] = float(getattr(p, "patch_hi", (0.0, 0.0))[t])
     c.patch_value = float(getattr(p, "patch_value", 0.0))
+    c.mean_vertical = int(getattr(p, "mean_vertical", -1))
     return c
 
 

@@ -51,7 +51,7 @@ struct Phys {
     int nx, ny, nz;
     double hx, hy, hz;
     double alpha, beta, theta_s, theta_r, A, gamma;
-    int mean;
+    int mean, mean_vertical;  // mean_vertical: mean of the z faces (-1: mean)
     int bc_type[6];
     double bc_value[6];
     double dt;

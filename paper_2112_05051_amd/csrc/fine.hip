@@ -108,9 +108,11 @@ __device__ inline Face face(const Phys &P, const Cell &q, uint32_t c, int f, con
 // sqrt(K_L K_U); integral: the average of K_s k_r over the heads between p_L
 // and p_U (K_s the mean of the two sides), by the Gauss-Legendre rule held in
 // Phys, always evaluated from the L side so both cells of a face agree bitwise.
-__device__ inline void mean_of(const Phys &P, int dir, double pc, const Law &Lc, double Ksc, double pn,
+// With mean_vertical >= 0 the z faces take that mean (one mean for the
+// horizontal and another for the vertical direction).
+__device__ inline void mean_of(const Phys &P, int axis, int dir, double pc, const Law &Lc, double Ksc, double pn,
                                const Law &Ln, double Ksn, double &Kf, double &dc, double &dn) {
-    int mean = P.mean;
+    int mean = (axis == 2 && P.mean_vertical >= 0) ? P.mean_vertical : P.mean;
     if (mean == RICH_MEAN_ARITH) {
         Kf = 0.5 * (Lc.K + Ln.K);
         dc = 0.5 * Lc.dK;
@@ -177,7 +179,7 @@ __global__ void k_residual(Phys P, uint32_t n, const double *__restrict__ Ks, co
         Law Ln = laws(P, fc.pn, fc.Ksn);
         double Kf, dc, dn;
         int dir = (f & 1) ? 1 : -1;
-        mean_of(P, dir, pc, Lc, Ks[c], fc.pn, Ln, fc.Ksn, Kf, dc, dn);
+        mean_of(P, f >> 1, dir, pc, Lc, Ks[c], fc.pn, Ln, fc.Ksn, Kf, dc, dn);
         acc += -Kf * (fc.pn - pc) / (fc.h * fc.h);
         if ((f >> 1) == 2) acc += dir * (-(Lc.K + Ln.K) / (2.0 * P.hz));
     }
@@ -209,7 +211,7 @@ __global__ void k_assemble(Phys P, uint32_t n, const double *__restrict__ Ks, co
         Law Ln = laws(P, fc.pn, fc.Ksn);
         double Kf, dc, dn;
         int dir = (f & 1) ? 1 : -1;
-        mean_of(P, dir, pc, Lc, Ks[c], fc.pn, Ln, fc.Ksn, Kf, dc, dn);
+        mean_of(P, f >> 1, dir, pc, Lc, Ks[c], fc.pn, Ln, fc.Ksn, Kf, dc, dn);
         double h2 = fc.h * fc.h;
         double dp = fc.pn - pc;
         bool zf = (f >> 1) == 2;

@@ -851,6 +851,7 @@ rich_status validate(const rich_problem_t *P, const rich_solver_opts_t *O) {
     if (n >= (int64_t)1 << 31) return RICH_EINVAL;
     if (!(P->hx > 0) || !(P->hy > 0) || !(P->hz > 0) || !(P->dt > 0)) return RICH_EINVAL;
     if (P->mean < 0 || P->mean > 4) return RICH_EINVAL;
+    if (P->mean_vertical < -1 || P->mean_vertical > 4) return RICH_EINVAL;
     if (P->patch_face < -1 || P->patch_face > 5) return RICH_EINVAL;
     if (P->patch_face >= 0 && (P->bc_type[P->patch_face] != RICH_BC_DIRICHLET || !std::isfinite(P->patch_value)))
         return RICH_EINVAL;
@@ -909,6 +910,7 @@ Phys to_phys(const rich_problem_t *P) {
     q.A = P->A;
     q.gamma = P->gamma;
     q.mean = P->mean;
+    q.mean_vertical = P->mean_vertical;
     for (int f = 0; f < 6; f++) {
         q.bc_type[f] = P->bc_type[f];
         q.bc_value[f] = P->bc_value[f];

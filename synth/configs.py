@@ -54,6 +54,7 @@ class Problem:
     patch_lo: tuple = (0.0, 0.0)
     patch_hi: tuple = (0.0, 0.0)
     patch_value: float = 0.0
+    mean_vertical: int = -1             # mean on the z faces (-1: the same as mean)
 
     @property
     def n(self) -> int:

@@ -322,3 +322,22 @@ def test_paper_3d_case_steps(rich, torch, orc, precision, tol):
         pg = s.get_state().cpu().numpy()
         err = np.linalg.norm(pg - po) / np.linalg.norm(po)
         assert err <= tol, (step, err, sg, so)
+
+
+@pytest.mark.parametrize("mean,mean_z", [(synth.ARITH, synth.UPSTREAM), (synth.HARMONIC, synth.INTEGRAL)])
+def test_per_direction_means(rich, torch, orc, mean, mean_z):
+    """One mean on the x and y faces, another on the z faces: Phi, J and M."""
+    P = box_problem(13, 11, 9, mean=mean, dt=3.0)
+    P.mean_vertical = mean_z
+    ks = random_ks(P, 61)
+    p = random_heads(P.n, 62)
+    th = orc.theta(P, random_heads(P.n, 63))
+    s = make_solver(rich, torch, P, ks)
+    F_g = s.residual(dev(torch, p), dev(torch, th)).cpu().numpy()
+    F_o = orc.residual(P, ks, p, th)
+    assert np.max(np.abs(F_g - F_o)) <= 1e-12 * np.max(np.abs(F_o))
+    s.assemble(dev(torch, p))
+    rp, col, val = s.export_csr(rich.WHICH_J, 0)
+    csr_close(rp, col, val, orc.jacobian(P, ks, p), 1e-12)
+    rp, col, val = s.export_csr(rich.WHICH_A, 0)
+    csr_close(rp, col, val, orc.auxiliary(P, ks, p), 1e-12)

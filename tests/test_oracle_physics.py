@@ -66,7 +66,7 @@ def test_laws_continuity_at_zero(orc):
 
 
 # -------------------------------------------------------------- residual
-def paper_interior_residual(orc, P, ks, p, th_old, mean):
+def paper_interior_residual(orc, P, ks, p, th_old, mean, mean_z=None):
     """Section 2.1 eq. (dynamic_of_the_problem), f = 0, written literally on the
     interior cells with the q's as printed (gravity: -K(p_{k+1})/(2 h_z) in
     q_{k+1/2} and -K(p_{k-1})/(2 h_z) in q_{k-1/2})."""
@@ -78,14 +78,14 @@ def paper_interior_residual(orc, P, ks, p, th_old, mean):
     gt, gw = np.polynomial.legendre.leggauss(16)
     gt, gw = 0.5 * (gt + 1.0), 0.5 * gw
 
-    def kav(KL, KU, pL, pU, ksL, ksU):
-        if mean == synth.ARITH:
+    def kav(KL, KU, pL, pU, ksL, ksU, m=mean):
+        if m == synth.ARITH:
             return 0.5 * (KL + KU)
-        if mean == synth.HARMONIC:
+        if m == synth.HARMONIC:
             return 2 * KL * KU / (KL + KU)
-        if mean == synth.GEOMETRIC:
+        if m == synth.GEOMETRIC:
             return np.sqrt(KL * KU)
-        if mean == synth.INTEGRAL:  # average of K over [pL, pU] with the mean K_s
+        if m == synth.INTEGRAL:  # average of K over [pL, pU] with the mean K_s
             kf = 0.5 * (ksL + ksU)
             psi = pL[None] + (pU - pL)[None] * gt[:, None, None, None]
             Kq = orc.laws(P, psi.ravel(), np.broadcast_to(kf[None], psi.shape).ravel())[2].reshape(psi.shape)
@@ -100,8 +100,9 @@ def paper_interior_residual(orc, P, ks, p, th_old, mean):
         up[ax] = slice(2, None)
         dn[ax] = slice(0, -2)
         up, dn = tuple(up), tuple(dn)
-        q_plus = -kav(K3[c], K3[up], p3[c], p3[up], ks3[c], ks3[up]) * (p3[up] - p3[c]) / h**2
-        q_minus = -kav(K3[dn], K3[c], p3[dn], p3[c], ks3[dn], ks3[c]) * (p3[c] - p3[dn]) / h**2
+        m = mean_z if (ax == 0 and mean_z is not None) else mean
+        q_plus = -kav(K3[c], K3[up], p3[c], p3[up], ks3[c], ks3[up], m) * (p3[up] - p3[c]) / h**2
+        q_minus = -kav(K3[dn], K3[c], p3[dn], p3[c], ks3[dn], ks3[c], m) * (p3[c] - p3[dn]) / h**2
         if ax == 0:
             q_plus = q_plus - K3[up] / (2 * h)
             q_minus = q_minus - K3[dn] / (2 * h)
@@ -361,3 +362,32 @@ def test_integral_mean_against_adaptive_quadrature(orc):
         assert Kr == Kf and dcr == dU and dnr == dL
     Kf = orc.face_mean(P, +1, -33.0, ks, -33.0, ks)[0]
     assert Kf == pytest.approx(K(-33.0), rel=1e-14)
+
+
+@pytest.mark.parametrize("mean,mean_z", [(synth.ARITH, synth.UPSTREAM), (synth.HARMONIC, synth.ARITH),
+                                         (synth.UPSTREAM, synth.INTEGRAL)])
+def test_per_direction_means(orc, mean, mean_z):
+    """Section 2.1's combination of two means, one for the horizontal and one
+    for the vertical direction: Phi equals the literal interior form with the
+    per-axis means, and J matches central differences."""
+    P = box_problem(6, 5, 7, mean=mean, dt=4.0)
+    P.mean_vertical = mean_z
+    ks = random_ks(P, 31)
+    p = random_heads(P.n, 32)
+    th_old = orc.theta(P, random_heads(P.n, 33))
+    F = orc.residual(P, ks, p, th_old).reshape(P.nz, P.ny, P.nx)[1:-1, 1:-1, 1:-1]
+    ref = paper_interior_residual(orc, P, ks, p, th_old, mean, mean_z)
+    assert np.max(np.abs(F - ref)) <= 1e-12 * np.max(np.abs(ref))
+    P2 = box_problem(4, 3, 5, mean=mean, dt=2.0, bc=all_dirichlet())
+    P2.mean_vertical = mean_z
+    rng = np.random.default_rng(34)
+    ks2 = random_ks(P2, 35)
+    p2 = -70 + 60 * rng.permutation(P2.n) / P2.n
+    th2 = orc.theta(P2, random_heads(P2.n, 36))
+    J = orc.jacobian(P2, ks2, p2).toarray()
+    for j in range(P2.n):
+        h = 1e-6 * abs(p2[j])
+        e = np.zeros(P2.n)
+        e[j] = h
+        col = (orc.residual(P2, ks2, p2 + e, th2) - orc.residual(P2, ks2, p2 - e, th2)) / (2 * h)
+        assert np.allclose(J[:, j], col, rtol=1e-5, atol=1e-7 * np.abs(J).max())
