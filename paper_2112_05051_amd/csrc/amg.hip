@@ -443,40 +443,43 @@ __global__ void k_csr_to_dense(int64_t n, const int64_t *__restrict__ rowptr, co
 //   D_ij <- [j not in K] D_ij - sum_t S_it R_tj          otherwise.
 constexpr int GJB = 64;  // pivot block
 
-// P^{-1} by scalar Gauss-Jordan in LDS (one workgroup, b <= 64).
+// P^{-1} by scalar Gauss-Jordan in LDS (one workgroup, b <= 64).  The block
+// is padded to 64 x 64 with the identity (its inverse is then diag(P^{-1}, I)),
+// each of the 1024 threads owns four fixed entries, and the block is
+// double-buffered so that one barrier per pivot suffices.
 __global__ void __launch_bounds__(1024) k_bgj_pivot(const double *__restrict__ D, int64_t n, int64_t k0, int b,
                                                     double *__restrict__ Pinv, int *__restrict__ bad) {
-    __shared__ double A[GJB][GJB + 1];
-    __shared__ double rowk[GJB], colk[GJB];
-    for (int t = threadIdx.x; t < b * b; t += blockDim.x) {
-        int r = t / b, c = t - r * b;
-        A[r][c] = D[(k0 + r) * n + k0 + c];
+    __shared__ double A[2][GJB][GJB + 1];
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        int t = tid + 1024 * q, i = t >> 6, j = t & 63;
+        A[0][i][j] = (i < b && j < b) ? D[(k0 + i) * n + k0 + j] : (i == j ? 1.0 : 0.0);
     }
     __syncthreads();
-    for (int k = 0; k < b; k++) {
-        for (int t = threadIdx.x; t < b; t += blockDim.x) {
-            rowk[t] = A[k][t];
-            colk[t] = A[t][k];
-        }
-        __syncthreads();
-        double p = rowk[k];
+    int cur = 0;
+    for (int k = 0; k < b; k++, cur ^= 1) {
+        double p = A[cur][k][k];
         if (!(p > 0.0)) {
-            if (threadIdx.x == 0) *bad = 1;
+            if (tid == 0) *bad = 1;
             p = 1.0;  // keep going; the caller reports the failure
         }
-        for (int t = threadIdx.x; t < b * b; t += blockDim.x) {
-            int i = t / b, j = t - i * b;
+        const double ip = 1.0 / p;
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            int t = tid + 1024 * q, i = t >> 6, j = t & 63;
             double v;
-            if (i == k) v = (j == k) ? 1.0 / p : rowk[j] / p;
-            else if (j == k) v = -colk[i] / p;
-            else v = A[i][j] - colk[i] * rowk[j] / p;
-            A[i][j] = v;
+            if (i == k) v = (j == k) ? ip : A[cur][k][j] * ip;
+            else if (j == k) v = -A[cur][i][k] * ip;
+            else v = A[cur][i][j] - A[cur][i][k] * ip * A[cur][k][j];
+            A[cur ^ 1][i][j] = v;
         }
         __syncthreads();
     }
-    for (int t = threadIdx.x; t < b * b; t += blockDim.x) {
-        int r = t / b, c = t - r * b;
-        Pinv[r * GJB + c] = A[r][c];
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        int t = tid + 1024 * q, i = t >> 6, j = t & 63;
+        if (i < b && j < b) Pinv[i * GJB + j] = A[cur][i][j];
     }
 }
 
@@ -505,7 +508,12 @@ __global__ void k_bgj_panel_S(const double *__restrict__ D, int64_t n, int64_t k
     if (c < b) S[t] = D[j * n + k0 + c];
 }
 
-// Rank-b update on 64x64 tiles, 4x4 outputs per thread, operands in LDS.
+// Rank-b update on 64x64 tiles with FP64 matrix cores: the four wavefronts of
+// a block each own 16 rows of the tile and accumulate four 16x16 blocks with
+// v_mfma_f64_16x16x4f64 over the (zero-padded) 64-long inner dimension.
+// Operand layout of that instruction: lane l supplies A[l%16][l/16] and
+// B[l/16][l%16]; result register v of lane l is D[l/16 + 4v][l%16].
+typedef double rich_d4 __attribute__((ext_vector_type(4)));
 __global__ void __launch_bounds__(256) k_bgj_update(double *__restrict__ D, int64_t n, int64_t k0, int b,
                                                      const double *__restrict__ R, const double *__restrict__ S) {
     __shared__ double Ss[GJB][GJB + 1];  // [row in tile][t]
@@ -518,33 +526,29 @@ __global__ void __launch_bounds__(256) k_bgj_update(double *__restrict__ D, int6
         Rs[r][c] = (r < b && gj < n) ? R[(int64_t)r * n + gj] : 0.0;
     }
     __syncthreads();
-    int tr = (threadIdx.x / 16) * 4, tc = (threadIdx.x % 16) * 4;
-    double acc[4][4] = {};
-    for (int t = 0; t < b; t++) {
-        double a[4], r4[4];
+    const int w = threadIdx.x / 64, l = threadIdx.x % 64;
+    const int li = l % 16, lk = l / 16;
+    rich_d4 acc[4];
 #pragma unroll
-        for (int u = 0; u < 4; u++) {
-            a[u] = Ss[tr + u][t];
-            r4[u] = Rs[t][tc + u];
-        }
+    for (int c = 0; c < 4; c++) acc[c] = (rich_d4){0.0, 0.0, 0.0, 0.0};
+    for (int t = 0; t < GJB; t += 4) {
+        double a = Ss[16 * w + li][t + lk];
 #pragma unroll
-        for (int u = 0; u < 4; u++)
-#pragma unroll
-            for (int v = 0; v < 4; v++) acc[u][v] += a[u] * r4[v];
+        for (int c = 0; c < 4; c++) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Rs[t + lk][16 * c + li], acc[c], 0, 0, 0);
     }
 #pragma unroll
-    for (int u = 0; u < 4; u++) {
-        int64_t gi = i0 + tr + u;
-        if (gi >= n) continue;
-        bool rowK = gi >= k0 && gi < k0 + b;
+    for (int c = 0; c < 4; c++) {
+        int64_t gj = j0 + 16 * c + li;
+        if (gj >= n) continue;
+        bool colK = gj >= k0 && gj < k0 + b;
 #pragma unroll
         for (int v = 0; v < 4; v++) {
-            int64_t gj = j0 + tc + v;
-            if (gj >= n) continue;
-            bool colK = gj >= k0 && gj < k0 + b;
+            int64_t gi = i0 + 16 * w + lk + 4 * v;
+            if (gi >= n) continue;
+            bool rowK = gi >= k0 && gi < k0 + b;
             double out;
             if (rowK) out = R[(gi - k0) * n + gj];
-            else out = (colK ? 0.0 : D[gi * n + gj]) - acc[u][v];
+            else out = (colK ? 0.0 : D[gi * n + gj]) - acc[c][v];
             D[gi * n + gj] = out;
         }
     }
