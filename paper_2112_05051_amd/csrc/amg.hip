@@ -343,20 +343,44 @@ __global__ void __launch_bounds__(256) k_csr_stream(const int64_t *__restrict__ 
                                                     const int32_t *__restrict__ col, const T *__restrict__ val,
                                                     const T *__restrict__ invd, const TB *__restrict__ b,
                                                     const T *__restrict__ v, T *__restrict__ out) {
+    constexpr int PER = STREAM_LDS / 256;  // entries per thread in the product phase
     __shared__ T prod[STREAM_LDS];
     int64_t blk = xcd_block();
     int64_t r0 = rb[blk], r1 = rb[blk + 1];
     if (r0 >= r1) return;
     int64_t e0 = rowptr[r0], e1 = rowptr[r1];
-    for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) prod[e - e0] = val[e] * v[col[e]];
-    __syncthreads();
+    // the reduction phase's first row pointers are loaded ahead of the products
     const int lane = threadIdx.x % G;
+    int64_t row0 = r0 + threadIdx.x / G;
+    int64_t ra = row0 < r1 ? rowptr[row0] : 0, rbe = row0 < r1 ? rowptr[row0 + 1] : 0;
+    // every load of the product phase is issued before the first use
+    int32_t cj[PER];
+    T vv[PER];
+#pragma unroll
+    for (int q = 0; q < PER; q++) {
+        int64_t e = e0 + threadIdx.x + 256 * q;
+        cj[q] = e < e1 ? col[e] : 0;
+        vv[q] = e < e1 ? val[e] : (T)0;
+    }
+    T xs[PER];
+#pragma unroll
+    for (int q = 0; q < PER; q++) xs[q] = v[cj[q]];
+#pragma unroll
+    for (int q = 0; q < PER; q++) {
+        int64_t e = e0 + threadIdx.x + 256 * q;
+        if (e < e1) prod[e - e0] = vv[q] * xs[q];
+    }
+    __syncthreads();
     // every lane of a group runs the same number of row iterations (shuffles)
     for (int64_t rbase = r0; rbase < r1; rbase += blockDim.x / G) {
         int64_t row = rbase + threadIdx.x / G;
+        if (rbase != r0) {
+            ra = row < r1 ? rowptr[row] : 0;
+            rbe = row < r1 ? rowptr[row + 1] : 0;
+        }
         T s = 0;
         if (row < r1)
-            for (int64_t e = rowptr[row] + lane; e < rowptr[row + 1]; e += G) s += prod[e - e0];
+            for (int64_t e = ra + lane; e < rbe; e += G) s += prod[e - e0];
         s = group_sum<G>(s);
         if (lane == 0 && row < r1) {
             if (POST) out[row] = v[row] + invd[row] * ((T)b[row] - s);
