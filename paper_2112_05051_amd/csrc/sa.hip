@@ -157,8 +157,10 @@ __global__ void k_sa_tval(int64_t nc, const int64_t *__restrict__ trow, const in
     }
 }
 
-// Q_iJ = sum over row i of A (column order) of a_ik P_kJ.  Rows of up to
-// SA_REG entries accumulate in registers, longer ones in the output.
+// Q_iJ = sum over row i of A (column order) of a_ik P_kJ.  One thread per
+// row; rows of up to SA_REG entries accumulate in LDS (column-major over the
+// block's 64 threads, so the dynamic indexing never spills to scratch
+// memory), longer ones in the output.
 constexpr int SA_REG = 32;
 __global__ void __launch_bounds__(64) k_sa_qnum(int64_t n, const int64_t *__restrict__ rowptr,
                                                 const int32_t *__restrict__ col, const double *__restrict__ val,
@@ -166,16 +168,17 @@ __global__ void __launch_bounds__(64) k_sa_qnum(int64_t n, const int64_t *__rest
                                                 const double *__restrict__ pval, const int64_t *__restrict__ qrow,
                                                 const int32_t *__restrict__ qcol, double *__restrict__ qval) {
 #pragma clang fp contract(off)
+    __shared__ double acc_s[SA_REG * 64];
+    __shared__ int32_t cj_s[SA_REG * 64];
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    const int t = threadIdx.x;
     int64_t q0 = qrow[i], q1 = qrow[i + 1];
     int len = (int)(q1 - q0);
     if (len <= SA_REG) {
-        int32_t cj[SA_REG];
-        double acc[SA_REG];
         for (int e = 0; e < len; e++) {
-            cj[e] = qcol[q0 + e];
-            acc[e] = 0.0;
+            cj_s[e * 64 + t] = qcol[q0 + e];
+            acc_s[e * 64 + t] = 0.0;
         }
         for (int64_t e = rowptr[i]; e < rowptr[i + 1]; e++) {
             int32_t k = col[e];
@@ -185,14 +188,14 @@ __global__ void __launch_bounds__(64) k_sa_qnum(int64_t n, const int64_t *__rest
                 int lo = 0, hi = len - 1;
                 while (lo < hi) {
                     int mid = (lo + hi) >> 1;
-                    if (cj[mid] < J) lo = mid + 1;
+                    if (cj_s[mid * 64 + t] < J) lo = mid + 1;
                     else hi = mid;
                 }
                 double prod = a * pval[f];
-                acc[lo] = acc[lo] + prod;
+                acc_s[lo * 64 + t] = acc_s[lo * 64 + t] + prod;
             }
         }
-        for (int e = 0; e < len; e++) qval[q0 + e] = acc[e];
+        for (int e = 0; e < len; e++) qval[q0 + e] = acc_s[e * 64 + t];
         return;
     }
     for (int64_t f = q0; f < q1; f++) qval[f] = 0.0;
@@ -207,7 +210,8 @@ __global__ void __launch_bounds__(64) k_sa_qnum(int64_t n, const int64_t *__rest
     }
 }
 
-// C_IJ = sum over the rows i of PT row I (ascending) of PT_Ii Q_iJ
+// C_IJ = sum over the rows i of PT row I (ascending) of PT_Ii Q_iJ, with LDS
+// accumulators as in k_sa_qnum.
 constexpr int SA_CREG = 64;
 __global__ void __launch_bounds__(64) k_sa_cnum(int64_t nc, const int64_t *__restrict__ trow,
                                                 const int32_t *__restrict__ tcol, const double *__restrict__ tval,
@@ -215,39 +219,40 @@ __global__ void __launch_bounds__(64) k_sa_cnum(int64_t nc, const int64_t *__res
                                                 const double *__restrict__ qval, const int64_t *__restrict__ crow,
                                                 const int32_t *__restrict__ ccol, double *__restrict__ cval) {
 #pragma clang fp contract(off)
+    __shared__ double acc_s[SA_CREG * 64];
+    __shared__ int32_t cj_s[SA_CREG * 64];
     int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (I >= nc) return;
+    const int t = threadIdx.x;
     int64_t c0 = crow[I], c1 = crow[I + 1];
     int len = (int)(c1 - c0);
     if (len <= SA_CREG) {
-        int32_t cj[SA_CREG];
-        double acc[SA_CREG];
         for (int e = 0; e < len; e++) {
-            cj[e] = ccol[c0 + e];
-            acc[e] = 0.0;
+            cj_s[e * 64 + t] = ccol[c0 + e];
+            acc_s[e * 64 + t] = 0.0;
         }
-        for (int64_t t = trow[I]; t < trow[I + 1]; t++) {
-            int32_t i = tcol[t];
-            double p = tval[t];
+        for (int64_t q = trow[I]; q < trow[I + 1]; q++) {
+            int32_t i = tcol[q];
+            double p = tval[q];
             for (int64_t f = qrow[i]; f < qrow[i + 1]; f++) {
                 int32_t J = qcol[f];
                 int lo = 0, hi = len - 1;
                 while (lo < hi) {
                     int mid = (lo + hi) >> 1;
-                    if (cj[mid] < J) lo = mid + 1;
+                    if (cj_s[mid * 64 + t] < J) lo = mid + 1;
                     else hi = mid;
                 }
                 double prod = p * qval[f];
-                acc[lo] = acc[lo] + prod;
+                acc_s[lo * 64 + t] = acc_s[lo * 64 + t] + prod;
             }
         }
-        for (int e = 0; e < len; e++) cval[c0 + e] = acc[e];
+        for (int e = 0; e < len; e++) cval[c0 + e] = acc_s[e * 64 + t];
         return;
     }
     for (int64_t f = c0; f < c1; f++) cval[f] = 0.0;
-    for (int64_t t = trow[I]; t < trow[I + 1]; t++) {
-        int32_t i = tcol[t];
-        double p = tval[t];
+    for (int64_t q = trow[I]; q < trow[I + 1]; q++) {
+        int32_t i = tcol[q];
+        double p = tval[q];
         for (int64_t f = qrow[i]; f < qrow[i + 1]; f++) {
             int64_t o = find_col(ccol, c0, c1, qcol[f]);
             double prod = p * qval[f];
