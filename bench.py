@@ -246,10 +246,14 @@ def run_serving(args):
 
     import paper_2112_05051_amd as rich
     import synth
-    reqs = synth.serving_stream(count=args.serve_count, rate=args.serve_rate, nsteps=args.serve_steps)
+    sizes = tuple(int(v) for v in args.serve_sizes.split(","))
+    reqs = synth.serving_stream(count=args.serve_count, rate=args.serve_rate, nsteps=args.serve_steps, sizes=sizes)
+    if args.serve_mean:
+        for _, rec in reqs:
+            rec.problem.mean = synth.MEAN_NAMES[args.serve_mean]
     log(f"[serve] generating {len(reqs)} request fields")
     inputs = [(t, rec, rec.ks(), rec.p0()) for t, rec in reqs]
-    srv = rich.Server(int(args.serve_budget_gb * (1 << 30)), args.serve_active)
+    srv = rich.Server(int(args.serve_budget_gb * (1 << 30)), args.serve_active, fused=args.serve_fused)
     ids = []
     t0 = time.perf_counter()
     for t_arr, rec, ks, p0 in inputs:
@@ -269,6 +273,7 @@ def run_serving(args):
                         f"wait {r['wait_s']:.2f}s run {r['run_s']:.2f}s ({len(done)}/{len(ids)})")
         time.sleep(0.05)
     makespan = time.perf_counter() - t0
+    flushes, products = srv.batch_stats()
     srv.close()
     step_ms = np.concatenate([d["step_ms"] for d in done.values()])
     waits = np.array([d["wait_s"] for d in done.values()])
@@ -282,12 +287,14 @@ def run_serving(args):
         "value": total_steps / makespan, "unit": "time-steps/s", "n_gpus": 1,
         "requests": len(ids), "steps_per_request": args.serve_steps, "arrival_rate_per_s": args.serve_rate,
         "max_active": args.serve_active, "budget_gb": args.serve_budget_gb, "makespan_s": makespan,
+        "fused": args.serve_fused, "batched_flushes": flushes,
+        "batched_products": products, "mean_batch": products / flushes if flushes else None,
         "total_steps": total_steps, "p50_step_ms": float(np.percentile(step_ms, 50)),
         "p99_step_ms": float(np.percentile(step_ms, 99)), "admission_wait_p50_s": float(np.percentile(waits, 50)),
         "admission_wait_p99_s": float(np.percentile(waits, 99)),
         "status_by_mean": {k: {str(s): v.count(s) for s in sorted(set(v))} for k, v in by_mean.items()},
         "dtype": "f64 (Newton, GMRES) + f32 (AMG V-cycle)", "data": "synthetic",
-        "config": {"workload": "c4_ensemble_poisson", "sizes": [32, 48, 64, 80, 96]},
+        "config": {"workload": "c4_ensemble_poisson", "sizes": list(sizes), "mean": args.serve_mean or "random"},
     }
 
 
@@ -321,6 +328,11 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=4.0)
     ap.add_argument("--serve-active", type=int, default=4)
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
+    ap.add_argument("--serve-fused", action="store_true",
+                    help="fuse the preconditioned products of same-size simulations into batched launches")
+    ap.add_argument("--serve-sizes", default="32,48,64,80,96", help="cube sizes the requests draw from")
+    ap.add_argument("--serve-mean", choices=["arith", "upstream", "harmonic"],
+                    help="one interface mean for every request (default: drawn per request)")
     ap.add_argument("--stats-summary", metavar="KERNEL_STATS_CSV",
                     help="print kernel time by family from a rocprofv3 --stats run and exit")
     args = ap.parse_args()

@@ -243,7 +243,18 @@ rich_status rich_profile_read(rich_handle_t h, int kernel, int64_t *launches_hos
  * plan (rich_query_bytes plus K_s/p staging) fits the remaining budget; an
  * admitted simulation stays resident on the GPU for all its steps and runs
  * on its own HIP stream, so concurrent simulations overlap on the device.
- * A simulation's result equals that of a lone rich_create/rich_step run.
+ * With fused batching (off by default), the resident simulations inside
+ * a GMRES solve post each preconditioned product J M^{-1} v to a batcher
+ * shared by the simulations of the same grid size and precision; the
+ * batcher's thread issues every product posted so far as one batch on its
+ * own stream, then the products posted meanwhile, and so on.  A batch runs
+ * as one launch per kernel (fine smoother, restriction, each coarse level's
+ * smoother, coarsest product, prolongations, J SpMV) over a work list of
+ * (simulation, block range).  Simulations whose hierarchy the batched kernels
+ * do not cover (smoothed prolongators, one level, no dense coarsest solve)
+ * launch on their own stream.
+ * A simulation's result equals that of a lone rich_create/rich_step run
+ * (bit for bit: every block runs the lone kernel's code on its data).
  * The server uses the device that is current when it is created. */
 typedef struct rich_server *rich_server_t;
 #define RICH_REQ_QUEUED 0
@@ -261,6 +272,13 @@ rich_status rich_server_submit(rich_server_t s, const rich_problem_t *prob, cons
  * Every output pointer may be NULL. */
 rich_status rich_server_poll(rich_server_t s, int64_t req_id, int *state, rich_status *result, double *p_host,
                              rich_step_stats_t *stats_host, double *step_ms_host, double *times_host);
+/* Fused batching on (fused != 0) or off (the default: every simulation
+ * launches on its own stream, which measures faster on the ensembles tried).
+ * Only before the first submission: RICH_ESTATE afterwards. */
+rich_status rich_server_set_batching(rich_server_t s, int fused);
+/* Batched flushes so far and the products they carried (their ratio is the
+ * mean number of simulations per fused launch). */
+rich_status rich_server_batch_stats(rich_server_t s, int64_t *flushes, int64_t *products);
 /* Block until no request is queued or running. */
 rich_status rich_server_wait_idle(rich_server_t s);
 /* Let running simulations finish, drop queued ones, release the server. */

@@ -67,7 +67,7 @@ EXPORTS = ["rich_query_bytes", "rich_create", "rich_destroy", "rich_set_state", 
            "rich_apply_prec", "rich_gmres", "rich_levels", "rich_level_size", "rich_export_csr",
            "rich_export_aggregates", "rich_match_sweep", "rich_profile", "rich_profile_read",
            "rich_server_create", "rich_server_submit", "rich_server_poll", "rich_server_wait_idle",
-           "rich_server_destroy"]
+           "rich_server_destroy", "rich_server_set_batching", "rich_server_batch_stats"]
 
 KERNELS = ["spmv_J", "vc0_pre", "vc0_post", "vc0_restrict", "vc1_pre", "vc1_post", "multidot", "update",
            "residual"]
@@ -114,6 +114,8 @@ def load(path: str = LIB_PATH):
     L.rich_server_poll.argtypes = [vp, C.c_int64, P(C.c_int), P(C.c_int), dp, P(StepStats), dp, dp]
     L.rich_server_wait_idle.argtypes = [vp]
     L.rich_server_destroy.argtypes = [vp]
+    L.rich_server_set_batching.argtypes = [vp, C.c_int]
+    L.rich_server_batch_stats.argtypes = [vp, i64p, i64p]
     for name in EXPORTS:
         getattr(L, name).restype = C.c_int if name != "rich_status_string" else C.c_char_p
     _lib = L
@@ -345,15 +347,24 @@ REQ_QUEUED, REQ_RUNNING, REQ_DONE = 0, 1, 2
 
 class Server:
     """Ensemble server (rich_server_t): FIFO admission by device-memory budget,
-    resident simulations on concurrent streams.  Inputs/outputs are host arrays."""
+    resident simulations on concurrent streams, their preconditioned products
+    fused into batched launches when ``fused`` is true.  Inputs/outputs are
+    host arrays."""
 
-    def __init__(self, hbm_budget_bytes: int, max_active: int = 4):
+    def __init__(self, hbm_budget_bytes: int, max_active: int = 4, fused: bool = False):
         L = load()
         self._L = L
         self._s = C.c_void_p()
         self._n = {}
         self._steps = {}
         _check(L.rich_server_create(hbm_budget_bytes, max_active, C.byref(self._s)), "rich_server_create")
+        _check(L.rich_server_set_batching(self._s, 1 if fused else 0), "rich_server_set_batching")
+
+    def batch_stats(self):
+        """(flushes, products): batched flushes so far and the products they carried."""
+        f, p = C.c_int64(), C.c_int64()
+        _check(self._L.rich_server_batch_stats(self._s, C.byref(f), C.byref(p)), "rich_server_batch_stats")
+        return f.value, p.value
 
     def submit(self, problem, options, ks, p0, nsteps: int) -> int:
         ks = np.ascontiguousarray(ks, dtype=np.float64)

@@ -4,6 +4,7 @@
 #include "common.hpp"
 
 #include <algorithm>
+#include <cstring>
 
 namespace rich {
 
@@ -292,11 +293,16 @@ __global__ void k_csr_pre(int64_t n, const int64_t *__restrict__ rowptr, const i
 
 // prolongation: xt = x0 + P xc
 template <class T>
-__global__ void k_csr_prolong(int64_t n, const T *__restrict__ x0, const T *__restrict__ xc,
-                              const int32_t *__restrict__ agg, T *__restrict__ xt) {
-    int64_t row = (int64_t)xcd_block() * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void csr_prolong_at(int64_t n, const T *__restrict__ x0, const T *__restrict__ xc,
+                                               const int32_t *__restrict__ agg, T *__restrict__ xt, int64_t row) {
     if (row >= n) return;
     xt[row] = x0[row] + xc[agg[row]];
+}
+
+template <class T>
+__global__ void k_csr_prolong(int64_t n, const T *__restrict__ x0, const T *__restrict__ xc,
+                              const int32_t *__restrict__ agg, T *__restrict__ xt) {
+    csr_prolong_at(n, x0, xc, agg, xt, (int64_t)xcd_block() * blockDim.x + threadIdx.x);
 }
 
 // post-smoothing: x = xt + D^{-1}(b - A xt)
@@ -339,13 +345,12 @@ constexpr int STREAM_LDS = STREAM_CHUNK + STREAM_MAXROW;
 // PRE: v = x0, out = b - A x0;  POST: v = xt, out = xt + D^{-1}(b - A xt).
 // G lanes add up a row.
 template <int G, class TB, class T, bool POST>
-__global__ void __launch_bounds__(256) k_csr_stream(const int64_t *__restrict__ rb, const int64_t *__restrict__ rowptr,
-                                                    const int32_t *__restrict__ col, const T *__restrict__ val,
-                                                    const T *__restrict__ invd, const TB *__restrict__ b,
-                                                    const T *__restrict__ v, T *__restrict__ out) {
+__device__ __forceinline__ void csr_stream_body(const int64_t *__restrict__ rb, const int64_t *__restrict__ rowptr,
+                                                const int32_t *__restrict__ col, const T *__restrict__ val,
+                                                const T *__restrict__ invd, const TB *__restrict__ b,
+                                                const T *__restrict__ v, T *__restrict__ out, int64_t blk) {
     constexpr int PER = STREAM_LDS / 256;  // entries per thread in the product phase
     __shared__ T prod[STREAM_LDS];
-    int64_t blk = xcd_block();
     int64_t r0 = rb[blk], r1 = rb[blk + 1];
     if (r0 >= r1) return;
     int64_t e0 = rowptr[r0], e1 = rowptr[r1];
@@ -389,6 +394,14 @@ __global__ void __launch_bounds__(256) k_csr_stream(const int64_t *__restrict__ 
     }
 }
 
+template <int G, class TB, class T, bool POST>
+__global__ void __launch_bounds__(256) k_csr_stream(const int64_t *__restrict__ rb, const int64_t *__restrict__ rowptr,
+                                                    const int32_t *__restrict__ col, const T *__restrict__ val,
+                                                    const T *__restrict__ invd, const TB *__restrict__ b,
+                                                    const T *__restrict__ v, T *__restrict__ out) {
+    csr_stream_body<G, TB, T, POST>(rb, rowptr, col, val, invd, b, v, out, xcd_block());
+}
+
 // rb[b] = first row whose first entry is at or past b * STREAM_CHUNK; the
 // blocks past the last chunk (grid padding) are empty
 __global__ void k_stream_rb(int64_t n, int64_t nrb, int64_t ngrid, const int64_t *__restrict__ rowptr,
@@ -416,10 +429,10 @@ __global__ void k_max_rowlen(int64_t n, const int64_t *__restrict__ rowptr, int 
 // bc[I] = sum over the members of I (ascending) of r
 // (and x0c[I] = D_c^{-1} bc[I], the coarse pre-smoothed iterate, when x0c is set)
 template <class T>
-__global__ void k_restrict(int64_t nc, const int64_t *__restrict__ mptr, const int32_t *__restrict__ mem,
-                           const T *__restrict__ r, T *__restrict__ bc, const T *__restrict__ invdc,
-                           T *__restrict__ x0c) {
-    int64_t I = (int64_t)xcd_block() * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void restrict_at(int64_t nc, const int64_t *__restrict__ mptr,
+                                            const int32_t *__restrict__ mem, const T *__restrict__ r,
+                                            T *__restrict__ bc, const T *__restrict__ invdc, T *__restrict__ x0c,
+                                            int64_t I) {
     if (I >= nc) return;
     T s = 0;
     for (int64_t t = mptr[I]; t < mptr[I + 1]; t++) s += r[mem[t]];
@@ -427,10 +440,18 @@ __global__ void k_restrict(int64_t nc, const int64_t *__restrict__ mptr, const i
     if (x0c) x0c[I] = s * invdc[I];
 }
 
+template <class T>
+__global__ void k_restrict(int64_t nc, const int64_t *__restrict__ mptr, const int32_t *__restrict__ mem,
+                           const T *__restrict__ r, T *__restrict__ bc, const T *__restrict__ invdc,
+                           T *__restrict__ x0c) {
+    restrict_at(nc, mptr, mem, r, bc, invdc, x0c, (int64_t)xcd_block() * blockDim.x + threadIdx.x);
+}
+
 // x = Ainv b, one wavefront per row (row-major Ainv)
 template <class TB, class T>
-__global__ void k_dense_gemv(const T *__restrict__ Ainv, const TB *__restrict__ b, T *__restrict__ x, int64_t n) {
-    int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
+__device__ __forceinline__ void dense_gemv_at(const T *__restrict__ Ainv, const TB *__restrict__ b,
+                                              T *__restrict__ x, int64_t n, int64_t blk) {
+    int64_t row = (blk * blockDim.x + threadIdx.x) / 64;
     int lane = threadIdx.x % 64;
     if (row >= n) return;
     T s = 0;
@@ -438,6 +459,51 @@ __global__ void k_dense_gemv(const T *__restrict__ Ainv, const TB *__restrict__ 
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
     if (lane == 0) x[row] = s;
+}
+
+template <class TB, class T>
+__global__ void k_dense_gemv(const T *__restrict__ Ainv, const TB *__restrict__ b, T *__restrict__ x, int64_t n) {
+    dense_gemv_at(Ainv, b, x, n, blockIdx.x);
+}
+
+// ---------------------------------------- batched coarse-level launches
+// The coarse-level V-cycle kernels over several simulations at once (same
+// per-block code as the lone launches above).
+template <class T>
+struct CoarseArgs {
+    int64_t n;
+    const int64_t *rb, *rowptr;
+    const int32_t *col;
+    const T *val, *invd, *b, *v;
+    T *out;
+    const int32_t *agg;  // prolongation / restriction maps
+    const int64_t *mptr;
+    const int32_t *mem;
+    T *x0c;
+};
+
+// MODE 0: restriction (b = r, out = bc, invd = invdc), 1: prolongation
+// xt = x0 + P xc (b = x0, v = xc, out = xt), 2: dense coarsest product
+// (val = Ainv, b = bc, out = x)
+template <class T, int MODE>
+__global__ void k_coarse_batch(Batch<CoarseArgs<T>> B) {
+    const unsigned L = MODE == 2 ? blockIdx.x : xcd_block();
+    if (L >= B.begin[B.n]) return;
+    const int e = batch_entry(B, L);
+    const CoarseArgs<T> &a = B.a[e];
+    const int64_t blk = (int64_t)(L - B.begin[e]);
+    if (MODE == 0) restrict_at(a.n, a.mptr, a.mem, a.b, a.out, a.invd, a.x0c, blk * blockDim.x + threadIdx.x);
+    if (MODE == 1) csr_prolong_at(a.n, a.b, a.v, a.agg, a.out, blk * blockDim.x + threadIdx.x);
+    if (MODE == 2) dense_gemv_at(a.val, a.b, a.out, a.n, blk);
+}
+
+template <int G, class T, bool POST>
+__global__ void __launch_bounds__(256) k_csr_stream_batch(Batch<CoarseArgs<T>> B) {
+    const unsigned L = xcd_block();
+    if (L >= B.begin[B.n]) return;
+    const int e = batch_entry(B, L);
+    const CoarseArgs<T> &a = B.a[e];
+    csr_stream_body<G, T, T, POST>(a.rb, a.rowptr, a.col, a.val, a.invd, a.b, a.v, a.out, L - B.begin[e]);
 }
 
 __global__ void k_csr_spmv(int64_t n, const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
@@ -883,6 +949,121 @@ rich_status launch_csr_spmv(const CsrDev &A, const double *x, double *y, hipStre
     LAUNCH_CHECK();
     return RICH_OK;
 }
+
+// ---------------------------------------- batched coarse-level launchers
+template <class T>
+static CoarseArgs<T> coarse_args() {
+    CoarseArgs<T> a;
+    memset(&a, 0, sizeof(a));
+    return a;
+}
+
+template <class T, bool POST>
+static rich_status stream_batch(const std::vector<CsrItem<T>> &v, hipStream_t s) {
+    for (int G : {1, 2, 4, 8}) {
+        std::vector<CoarseArgs<T>> a;
+        std::vector<unsigned> nb;
+        for (const auto &it : v) {
+            const Level &Lv = *it.Lv;
+            int g = Lv.sg == 1 || Lv.sg == 2 || Lv.sg == 4 ? Lv.sg : 8;
+            if (g != G || Lv.n == 0) continue;
+            CoarseArgs<T> c = coarse_args<T>();
+            c.n = Lv.n;
+            c.rb = Lv.rb;
+            c.rowptr = Lv.rowptr;
+            c.col = Lv.col;
+            c.val = it.val;
+            c.invd = it.invd;
+            c.b = it.b;
+            c.v = POST ? (const T *)Lv.r : it.x0;
+            c.out = it.out;
+            a.push_back(c);
+            nb.push_back((unsigned)Lv.nrb);
+        }
+        using B = Batch<CoarseArgs<T>>;
+        switch (G) {
+        case 1: RICH_TRY(launch_batches(a, nb, [&](const B &bt, unsigned g) { k_csr_stream_batch<1, T, POST><<<g, 256, 0, s>>>(bt); })); break;
+        case 2: RICH_TRY(launch_batches(a, nb, [&](const B &bt, unsigned g) { k_csr_stream_batch<2, T, POST><<<g, 256, 0, s>>>(bt); })); break;
+        case 4: RICH_TRY(launch_batches(a, nb, [&](const B &bt, unsigned g) { k_csr_stream_batch<4, T, POST><<<g, 256, 0, s>>>(bt); })); break;
+        default: RICH_TRY(launch_batches(a, nb, [&](const B &bt, unsigned g) { k_csr_stream_batch<8, T, POST><<<g, 256, 0, s>>>(bt); })); break;
+        }
+    }
+    return RICH_OK;
+}
+
+template <class T>
+rich_status launch_csr_pre_batch(const std::vector<CsrItem<T>> &v, hipStream_t s) {
+    return stream_batch<T, false>(v, s);
+}
+
+template <class T>
+rich_status launch_csr_post_batch(const std::vector<CsrItem<T>> &v, hipStream_t s) {
+    // xt = x0 + P xc into each level's r buffer, then post-smoothing from xt
+    std::vector<CoarseArgs<T>> a;
+    std::vector<unsigned> nb;
+    for (const auto &it : v) {
+        const Level &Lv = *it.Lv;
+        CoarseArgs<T> c = coarse_args<T>();
+        c.n = Lv.n;
+        c.b = it.x0;
+        c.v = it.xc;
+        c.agg = Lv.agg;
+        c.out = (T *)Lv.r;
+        a.push_back(c);
+        nb.push_back((unsigned)((Lv.n + TPB - 1) / TPB));
+    }
+    RICH_TRY(launch_batches(a, nb, [&](const Batch<CoarseArgs<T>> &bt, unsigned g) {
+        k_coarse_batch<T, 1><<<g, TPB, 0, s>>>(bt);
+    }));
+    return stream_batch<T, true>(v, s);
+}
+
+template <class T>
+rich_status launch_restrict_batch(const std::vector<RestrictItem<T>> &v, hipStream_t s) {
+    std::vector<CoarseArgs<T>> a;
+    std::vector<unsigned> nb;
+    for (const auto &it : v) {
+        CoarseArgs<T> c = coarse_args<T>();
+        c.n = it.nc;
+        c.mptr = it.Lv->mptr;
+        c.mem = it.Lv->mem;
+        c.b = it.r;
+        c.out = it.bc;
+        c.invd = it.invdc;
+        c.x0c = it.x0c;
+        a.push_back(c);
+        nb.push_back((unsigned)((it.nc + TPB - 1) / TPB));
+    }
+    return launch_batches(a, nb, [&](const Batch<CoarseArgs<T>> &bt, unsigned g) {
+        k_coarse_batch<T, 0><<<g, TPB, 0, s>>>(bt);
+    });
+}
+
+template <class T>
+rich_status launch_dense_gemv_batch(const std::vector<GemvItem<T>> &v, hipStream_t s) {
+    std::vector<CoarseArgs<T>> a;
+    std::vector<unsigned> nb;
+    for (const auto &it : v) {
+        CoarseArgs<T> c = coarse_args<T>();
+        c.n = it.n;
+        c.val = it.Ainv;
+        c.b = it.b;
+        c.out = it.x;
+        a.push_back(c);
+        nb.push_back((unsigned)((it.n * 64 + TPB - 1) / TPB));
+    }
+    return launch_batches(a, nb, [&](const Batch<CoarseArgs<T>> &bt, unsigned g) {
+        k_coarse_batch<T, 2><<<g, TPB, 0, s>>>(bt);
+    });
+}
+
+#define INST_BATCH(T)                                                                              \
+    template rich_status launch_csr_pre_batch<T>(const std::vector<CsrItem<T>> &, hipStream_t);      \
+    template rich_status launch_csr_post_batch<T>(const std::vector<CsrItem<T>> &, hipStream_t);     \
+    template rich_status launch_restrict_batch<T>(const std::vector<RestrictItem<T>> &, hipStream_t); \
+    template rich_status launch_dense_gemv_batch<T>(const std::vector<GemvItem<T>> &, hipStream_t);
+INST_BATCH(double)
+INST_BATCH(float)
 
 #define INST_CSR(TB, T)                                                                                         \
     template rich_status launch_csr_pre<TB, T>(const Level &, const T *, const T *, const TB *, T *, hipStream_t); \

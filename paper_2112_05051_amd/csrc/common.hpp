@@ -9,6 +9,8 @@
 
 #include "../../include/richards.h"
 
+struct rich_batcher;
+
 namespace rich {
 
 void set_error(const char *what, const char *file, int line, hipError_t e);
@@ -43,6 +45,49 @@ __device__ inline unsigned xcd_block() {
 inline unsigned xcd_grid(int64_t n, int tpb) {
     int64_t b = (n + tpb - 1) / tpb;
     return (unsigned)((b + NXCD - 1) / NXCD * NXCD);
+}
+
+// ------------------------------------------------------- batched launches
+// One launch covers the same kernel for several resident simulations: entry
+// e owns the virtual blocks [begin[e], begin[e+1]) (in XCD-aware order) and
+// has its own arguments; each block runs exactly the code of the lone
+// launch on its entry's data, so results do not depend on the batch.
+constexpr int RICH_BATCH_MAX = 8;
+struct Grid3 {
+    int nx, ny, nz;
+};
+template <class A>
+struct Batch {
+    int n = 0;
+    unsigned begin[RICH_BATCH_MAX + 1] = {};
+    A a[RICH_BATCH_MAX];
+};
+template <class A>
+__device__ inline int batch_entry(const Batch<A> &B, unsigned L) {
+    int e = 0;
+    for (int t = 1; t < B.n; t++) e += L >= B.begin[t] ? 1 : 0;
+    return e;
+}
+// Host side: group items into batches of at most RICH_BATCH_MAX and call
+// launch(batch, grid) for each (grid = total blocks rounded up to the XCDs).
+template <class A, class F>
+rich_status launch_batches(const std::vector<A> &items, const std::vector<unsigned> &blocks, F launch) {
+    for (size_t i0 = 0; i0 < items.size(); i0 += RICH_BATCH_MAX) {
+        Batch<A> B;
+        size_t i1 = items.size() < i0 + RICH_BATCH_MAX ? items.size() : i0 + RICH_BATCH_MAX;
+        B.n = (int)(i1 - i0);
+        unsigned tot = 0;
+        for (size_t i = i0; i < i1; i++) {
+            B.begin[i - i0] = tot;
+            B.a[i - i0] = items[i];
+            tot += blocks[i];
+        }
+        B.begin[B.n] = tot;
+        if (tot == 0) continue;
+        launch(B, (tot + NXCD - 1) / NXCD * NXCD);
+        LAUNCH_CHECK();
+    }
+    return RICH_OK;
 }
 
 // Problem parameters passed by value to the stencil kernels.
@@ -124,6 +169,32 @@ rich_status launch_st_pre(const Phys &P, const T *M4, const T *invd, const TB *b
 template <class TB, class T>
 rich_status launch_st_post(const Phys &P, const T *M4, const T *invd, const TB *b, const double *bs, const T *xc,
                            const int32_t *agg, T *x, T *xt, hipStream_t s);
+// One simulation's part of a batched fine-level V-cycle step (same meaning as
+// the arguments of launch_st_pre / launch_st_post; xt: N scratch).
+template <class TB, class T>
+struct FineItem {
+    const Phys *P;
+    const T *M4, *invd;
+    const TB *b;
+    const double *bs;
+    const T *xc;
+    const int32_t *agg;
+    T *xt;
+    T *out;
+};
+template <class TB, class T>
+rich_status launch_st_pre_batch(const std::vector<FineItem<TB, T>> &items, hipStream_t s);
+template <class TB, class T>
+rich_status launch_st_post_batch(const std::vector<FineItem<TB, T>> &items, hipStream_t s);
+template <class TX>
+struct SpmvItem {
+    const Phys *P;
+    const double *J7;
+    const TX *x;
+    double *y;
+};
+template <class TX>
+rich_status launch_spmv_J_batch(const std::vector<SpmvItem<TX>> &items, hipStream_t s);
 template <class TB, class T>
 rich_status launch_st_sweeps(const Phys &P, const T *M4, const T *invd, const TB *b, T *x, T *tmp,
                              int sweeps, hipStream_t s);
@@ -236,6 +307,15 @@ rich_status galerkin_symbolic(const CsrDev &A, const int32_t *agg, int64_t nc, c
                               const int32_t *mem, CsrDev *C, DevAlloc &mem_out, hipStream_t s);
 rich_status galerkin_numeric(const CsrDev &A, const int32_t *agg, const int64_t *mptr, const int32_t *mem,
                              const CsrDev &C, hipStream_t s);
+// Fused serving launches (solver.hip): a batcher gathers the preconditioned
+// products of the GMRES solves of the simulations attached to it and its
+// thread issues them as batched launches on its own stream (on the device
+// current at creation).
+rich_batcher *batcher_create();
+void batcher_destroy(rich_batcher *B);
+rich_status batcher_attach(rich_handle_t h, rich_batcher *B);
+void batcher_stats(rich_batcher *B, int64_t *flushes, int64_t *items);
+
 rich_status members(const int32_t *agg, int64_t n, int64_t nc, int64_t *mptr, int32_t *mem,
                     hipStream_t s);
 rich_status csr_invd(const CsrDev &A, double *invd, float *invdf, hipStream_t s);
@@ -248,6 +328,39 @@ rich_status compose_agg(int32_t *comp, const int32_t *a, int64_t n, hipStream_t 
 // r = b - A x0 (x0 = D^{-1} b, the pre-smoothed iterate from zero, stored by the restriction)
 template <class TB, class T>
 rich_status launch_csr_pre(const Level &Lv, const T *val, const T *x0, const TB *b, T *r, hipStream_t s);
+// Batched coarse-level V-cycle steps over several simulations (levels with
+// CSR-stream row blocks and a piecewise-constant prolongator only).
+// CsrItem: pre: out = r = b - A x0;  post: out = x = post-smooth(x0 + P xc)
+// (the level's r buffer holds x0 + P xc).
+template <class T>
+struct CsrItem {
+    const Level *Lv;
+    const T *val, *invd, *b, *x0, *xc;
+    T *out;
+};
+template <class T>
+struct RestrictItem {
+    const Level *Lv;  // the finer level (its members lists)
+    const T *r;
+    T *bc;
+    int64_t nc;
+    const T *invdc;
+    T *x0c;
+};
+template <class T>
+struct GemvItem {
+    const T *Ainv, *b;
+    T *x;
+    int64_t n;
+};
+template <class T>
+rich_status launch_csr_pre_batch(const std::vector<CsrItem<T>> &items, hipStream_t s);
+template <class T>
+rich_status launch_csr_post_batch(const std::vector<CsrItem<T>> &items, hipStream_t s);
+template <class T>
+rich_status launch_restrict_batch(const std::vector<RestrictItem<T>> &items, hipStream_t s);
+template <class T>
+rich_status launch_dense_gemv_batch(const std::vector<GemvItem<T>> &items, hipStream_t s);
 // x = post-smooth(x0 + P xc); the level's r buffer holds the prolongated iterate
 template <class TB, class T>
 rich_status launch_csr_post(const Level &Lv, const T *val, const T *invd, const TB *b, const T *x0,

@@ -16,7 +16,8 @@ struct Cell {
     int i, j, k;
 };
 
-__device__ inline Cell cell_of(const Phys &P, uint32_t c) {
+template <class G>
+__device__ inline Cell cell_of(const G &P, uint32_t c) {
     uint32_t nxy = (uint32_t)P.nx * (uint32_t)P.ny;
     uint32_t k = c / nxy;
     uint32_t rem = c - k * nxy;
@@ -251,10 +252,9 @@ __global__ void k_assemble(Phys P, uint32_t n, const double *__restrict__ Ks, co
 }
 
 // y = J x, J in the 7-array stencil form; x may be FP32 (mixed path).
-template <class TX>
-__global__ void k_spmv_J(Phys P, uint32_t n, const double *__restrict__ J7, const TX *__restrict__ x,
-                         double *__restrict__ y) {
-    uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+template <class TX, class G>
+__device__ __forceinline__ void spmv_J_at(const G &P, uint32_t n, const double *__restrict__ J7,
+                                          const TX *__restrict__ x, double *__restrict__ y, uint32_t c) {
     if (c >= n) return;
     Cell q = cell_of(P, c);
     uint32_t nx = P.nx, nxy = (uint32_t)P.nx * (uint32_t)P.ny;
@@ -271,10 +271,15 @@ __global__ void k_spmv_J(Phys P, uint32_t n, const double *__restrict__ J7, cons
     y[c] = s;
 }
 
+template <class TX>
+__global__ void k_spmv_J(Phys P, uint32_t n, const double *__restrict__ J7, const TX *__restrict__ x,
+                         double *__restrict__ y) {
+    spmv_J_at(P, n, J7, x, y, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
 // Symmetric stencil M: sum_j m_cj * v_j with the -d couplings read at the lower neighbour.
-template <class T, class F>
-__device__ inline T mstencil(const Phys &P, const Cell &q, uint32_t c, uint32_t n, const T *__restrict__ M4,
-                             F v) {
+template <class T, class G, class F>
+__device__ inline T mstencil(const G &P, const Cell &q, uint32_t c, uint32_t n, const T *__restrict__ M4, F v) {
     uint32_t nx = P.nx, nxy = (uint32_t)P.nx * (uint32_t)P.ny;
     T s = M4[(size_t)M_D * n + c] * v(c);
     if (q.i > 0) s += M4[(size_t)M_XP * n + c - 1] * v(c - 1);
@@ -296,10 +301,10 @@ __global__ void k_spmv_M(Phys P, uint32_t n, const double *__restrict__ M4, cons
 
 // V-cycle, fine level, pre-smoothing from x = 0 and residual in one pass:
 // x0 = D^{-1} b (never stored), r = b - M x0.
-template <class TB, class T>
-__global__ void k_st_pre(Phys P, uint32_t n, const T *__restrict__ M4, const T *__restrict__ invd,
-                         const TB *__restrict__ b, const double *__restrict__ bsp, T *__restrict__ r) {
-    uint32_t c = xcd_block() * blockDim.x + threadIdx.x;
+template <class TB, class T, class G>
+__device__ __forceinline__ void st_pre_at(const G &P, uint32_t n, const T *__restrict__ M4,
+                                          const T *__restrict__ invd, const TB *__restrict__ b,
+                                          const double *__restrict__ bsp, T *__restrict__ r, uint32_t c) {
     if (c >= n) return;
     const TB bs = (TB)bsp[0];
     Cell q = cell_of(P, c);
@@ -307,27 +312,46 @@ __global__ void k_st_pre(Phys P, uint32_t n, const T *__restrict__ M4, const T *
     r[c] = (T)(b[c] * bs) - s;
 }
 
+template <class TB, class T>
+__global__ void k_st_pre(Phys P, uint32_t n, const T *__restrict__ M4, const T *__restrict__ invd,
+                         const TB *__restrict__ b, const double *__restrict__ bsp, T *__restrict__ r) {
+    st_pre_at(P, n, M4, invd, b, bsp, r, xcd_block() * blockDim.x + threadIdx.x);
+}
+
 // V-cycle, fine level, prolongation: xt = D^{-1} b + P xc (the pre-smoothed
 // iterate plus the coarse correction), one streaming pass.
 template <class TB, class T>
-__global__ void k_st_prolong(uint32_t n, const T *__restrict__ invd, const TB *__restrict__ b,
-                             const double *__restrict__ bsp, const T *__restrict__ xc, const int32_t *__restrict__ agg,
-                             T *__restrict__ xt) {
-    uint32_t c = xcd_block() * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void st_prolong_at(uint32_t n, const T *__restrict__ invd, const TB *__restrict__ b,
+                                              const double *__restrict__ bsp, const T *__restrict__ xc,
+                                              const int32_t *__restrict__ agg, T *__restrict__ xt, uint32_t c) {
     if (c >= n) return;
     xt[c] = (T)(b[c] * (TB)bsp[0]) * invd[c] + xc[agg[c]];
 }
 
-// V-cycle, fine level, post-smoothing: x = xt + D^{-1}(b - M xt).
 template <class TB, class T>
-__global__ void k_st_post(Phys P, uint32_t n, const T *__restrict__ M4, const T *__restrict__ invd,
-                          const TB *__restrict__ b, const double *__restrict__ bsp, const T *__restrict__ xt,
-                          T *__restrict__ x) {
-    uint32_t c = xcd_block() * blockDim.x + threadIdx.x;
+__global__ void k_st_prolong(uint32_t n, const T *__restrict__ invd, const TB *__restrict__ b,
+                             const double *__restrict__ bsp, const T *__restrict__ xc, const int32_t *__restrict__ agg,
+                             T *__restrict__ xt) {
+    st_prolong_at(n, invd, b, bsp, xc, agg, xt, xcd_block() * blockDim.x + threadIdx.x);
+}
+
+// V-cycle, fine level, post-smoothing: x = xt + D^{-1}(b - M xt).
+template <class TB, class T, class G>
+__device__ __forceinline__ void st_post_at(const G &P, uint32_t n, const T *__restrict__ M4,
+                                           const T *__restrict__ invd, const TB *__restrict__ b,
+                                           const double *__restrict__ bsp, const T *__restrict__ xt,
+                                           T *__restrict__ x, uint32_t c) {
     if (c >= n) return;
     Cell q = cell_of(P, c);
     T s = mstencil<T>(P, q, c, n, M4, [&](uint32_t t) { return xt[t]; });
     x[c] = xt[c] + invd[c] * ((T)(b[c] * (TB)bsp[0]) - s);
+}
+
+template <class TB, class T>
+__global__ void k_st_post(Phys P, uint32_t n, const T *__restrict__ M4, const T *__restrict__ invd,
+                          const TB *__restrict__ b, const double *__restrict__ bsp, const T *__restrict__ xt,
+                          T *__restrict__ x) {
+    st_post_at(P, n, M4, invd, b, bsp, xt, x, xcd_block() * blockDim.x + threadIdx.x);
 }
 
 // 2.5-D versions of the fine-level V-cycle stencils.  A block of 64 x 8
@@ -359,11 +383,12 @@ struct St25In {
     T b = 0, d = 0, x = 0;  // bs b, D^{-1}, xc[agg] or xt
 };
 
-template <class TB, class T, int MODE>
-__global__ void __launch_bounds__(T25X * T25Y) k_st25(Phys P, const T *__restrict__ M4, const T *__restrict__ invd,
-                                                     const TB *__restrict__ b, const double *__restrict__ bsp,
-                                                     const T *__restrict__ xc, const int32_t *__restrict__ agg,
-                                                     T *__restrict__ out, int kz) {
+// L: the tile (virtual block) this block computes.
+template <class TB, class T, int MODE, class G>
+__device__ __forceinline__ void st25_body(const G &P, const T *__restrict__ M4, const T *__restrict__ invd,
+                                          const TB *__restrict__ b, const double *__restrict__ bsp,
+                                          const T *__restrict__ xc, const int32_t *__restrict__ agg,
+                                          T *__restrict__ out, int kz, unsigned L) {
     constexpr bool POST = MODE != ST25_PRE;
     __shared__ T us[2][T25Y + 2][T25X + 2];
     __shared__ T xps[2][T25Y][T25X + 1];
@@ -375,7 +400,6 @@ __global__ void __launch_bounds__(T25X * T25Y) k_st25(Phys P, const T *__restric
     // (x fastest), so the halos a tile shares with its neighbours are mostly
     // fetched once into that XCD's L2.
     const unsigned ntx = (unsigned)(nx + T25X - 1) / T25X, nty = (unsigned)(ny + T25Y - 1) / T25Y;
-    const unsigned L = xcd_block();
     if (L >= ntx * nty * (unsigned)((nz + kz - 1) / kz)) return;
     const int tx = threadIdx.x, ty = threadIdx.y;
     const int i = (int)(L % ntx) * T25X + tx, j = (int)((L / ntx) % nty) * T25Y + ty;
@@ -489,6 +513,68 @@ __global__ void __launch_bounds__(T25X * T25Y) k_st25(Phys P, const T *__restric
     }
 }
 
+template <class TB, class T, int MODE>
+__global__ void __launch_bounds__(T25X * T25Y) k_st25(Phys P, const T *__restrict__ M4, const T *__restrict__ invd,
+                                                     const TB *__restrict__ b, const double *__restrict__ bsp,
+                                                     const T *__restrict__ xc, const int32_t *__restrict__ agg,
+                                                     T *__restrict__ out, int kz) {
+    st25_body<TB, T, MODE>(P, M4, invd, b, bsp, xc, agg, out, kz, xcd_block());
+}
+
+// Batched forms: one launch over the fine levels of several simulations.
+template <class TB, class T>
+struct StArgs {
+    Grid3 g;
+    uint32_t n;
+    int kz;
+    const T *M4, *invd;
+    const TB *b;
+    const double *bs;
+    const T *xc;
+    const int32_t *agg;
+    T *xt, *out;
+};
+
+template <class TB, class T, int MODE>
+__global__ void __launch_bounds__(T25X * T25Y) k_st25_batch(Batch<StArgs<TB, T>> B) {
+    const unsigned L = xcd_block();
+    if (L >= B.begin[B.n]) return;
+    const int e = batch_entry(B, L);
+    const StArgs<TB, T> &a = B.a[e];
+    st25_body<TB, T, MODE>(a.g, a.M4, a.invd, a.b, a.bs, a.xc, a.agg, a.out, a.kz, L - B.begin[e]);
+}
+
+// MODE 0: pre-smoothing + residual, 1: prolongation into xt, 2: post-smoothing from xt
+template <class TB, class T, int MODE>
+__global__ void k_st1_batch(Batch<StArgs<TB, T>> B) {
+    const unsigned L = xcd_block();
+    if (L >= B.begin[B.n]) return;
+    const int e = batch_entry(B, L);
+    const StArgs<TB, T> &a = B.a[e];
+    const uint32_t c = (L - B.begin[e]) * blockDim.x + threadIdx.x;
+    if (MODE == 0) st_pre_at(a.g, a.n, a.M4, a.invd, a.b, a.bs, a.out, c);
+    if (MODE == 1) st_prolong_at(a.n, a.invd, a.b, a.bs, a.xc, a.agg, a.xt, c);
+    if (MODE == 2) st_post_at(a.g, a.n, a.M4, a.invd, a.b, a.bs, a.xt, a.out, c);
+}
+
+template <class TX>
+struct SpmvArgs {
+    Grid3 g;
+    uint32_t n;
+    const double *J7;
+    const TX *x;
+    double *y;
+};
+
+template <class TX>
+__global__ void k_spmv_J_batch(Batch<SpmvArgs<TX>> B) {
+    const unsigned L = xcd_block();
+    if (L >= B.begin[B.n]) return;
+    const int e = batch_entry(B, L);
+    const SpmvArgs<TX> &a = B.a[e];
+    spmv_J_at(a.g, a.n, a.J7, a.x, a.y, (L - B.begin[e]) * blockDim.x + threadIdx.x);
+}
+
 // The 64-wide tile needs rows of at least about that length to keep its lanes busy.
 inline bool use25(const Phys &P) { return P.nx >= 48 && P.ny >= T25Y && P.nz >= 4; }
 inline int kz25(const Phys &P) {
@@ -498,10 +584,10 @@ inline int kz25(const Phys &P) {
     while (kz > 1 && tiles * ((P.nz + kz - 1) / kz) < ST25_MIN_BLOCKS) kz /= 2;
     return kz;
 }
-inline unsigned grid25(const Phys &P, int kz) {
-    int64_t tiles = (int64_t)((P.nx + T25X - 1) / T25X) * ((P.ny + T25Y - 1) / T25Y) * ((P.nz + kz - 1) / kz);
-    return xcd_grid(tiles, 1);
+inline int64_t tiles25(const Phys &P, int kz) {
+    return (int64_t)((P.nx + T25X - 1) / T25X) * ((P.ny + T25Y - 1) / T25Y) * ((P.nz + kz - 1) / kz);
 }
+inline unsigned grid25(const Phys &P, int kz) { return xcd_grid(tiles25(P, kz), 1); }
 
 // Plain l1-Jacobi sweep x_out = x_in + D^{-1}(b - M x_in) (used when the
 // fine level is also the coarsest and too large for a direct solve).
@@ -664,6 +750,82 @@ rich_status launch_st_sweeps(const Phys &P, const T *M4, const T *invd, const TB
     return RICH_OK;
 }
 
+template <class TB, class T>
+static StArgs<TB, T> st_args(const FineItem<TB, T> &it, int kz) {
+    const Phys &P = *it.P;
+    StArgs<TB, T> a;
+    a.g = Grid3{P.nx, P.ny, P.nz};
+    a.n = ncells(P);
+    a.kz = kz;
+    a.M4 = it.M4;
+    a.invd = it.invd;
+    a.b = it.b;
+    a.bs = it.bs;
+    a.xc = it.xc;
+    a.agg = it.agg;
+    a.xt = it.xt;
+    a.out = it.out;
+    return a;
+}
+
+// Split the items into those on the tiled kernel and those on the plain one.
+template <class TB, class T>
+static void st_split(const std::vector<FineItem<TB, T>> &v, std::vector<StArgs<TB, T>> &a25,
+                     std::vector<unsigned> &b25, std::vector<StArgs<TB, T>> &a1, std::vector<unsigned> &b1) {
+    for (const auto &it : v) {
+        const Phys &P = *it.P;
+        if (use25(P)) {
+            int kz = kz25(P);
+            a25.push_back(st_args(it, kz));
+            b25.push_back((unsigned)tiles25(P, kz));
+        } else {
+            a1.push_back(st_args(it, 0));
+            b1.push_back((ncells(P) + TPB - 1) / TPB);
+        }
+    }
+}
+
+template <class TB, class T>
+rich_status launch_st_pre_batch(const std::vector<FineItem<TB, T>> &v, hipStream_t s) {
+    std::vector<StArgs<TB, T>> a25, a1;
+    std::vector<unsigned> b25, b1;
+    st_split(v, a25, b25, a1, b1);
+    using B = Batch<StArgs<TB, T>>;
+    RICH_TRY(launch_batches(a25, b25, [&](const B &bt, unsigned g) {
+        k_st25_batch<TB, T, ST25_PRE><<<g, dim3(T25X, T25Y), 0, s>>>(bt);
+    }));
+    return launch_batches(a1, b1, [&](const B &bt, unsigned g) { k_st1_batch<TB, T, 0><<<g, TPB, 0, s>>>(bt); });
+}
+
+template <class TB, class T>
+rich_status launch_st_post_batch(const std::vector<FineItem<TB, T>> &v, hipStream_t s) {
+    std::vector<StArgs<TB, T>> a25, a1;
+    std::vector<unsigned> b25, b1;
+    st_split(v, a25, b25, a1, b1);
+    using B = Batch<StArgs<TB, T>>;
+    RICH_TRY(launch_batches(a25, b25, [&](const B &bt, unsigned g) {
+        k_st25_batch<TB, T, ST25_POST><<<g, dim3(T25X, T25Y), 0, s>>>(bt);
+    }));
+    RICH_TRY(launch_batches(a1, b1, [&](const B &bt, unsigned g) { k_st1_batch<TB, T, 1><<<g, TPB, 0, s>>>(bt); }));
+    return launch_batches(a1, b1, [&](const B &bt, unsigned g) { k_st1_batch<TB, T, 2><<<g, TPB, 0, s>>>(bt); });
+}
+
+template <class TX>
+rich_status launch_spmv_J_batch(const std::vector<SpmvItem<TX>> &v, hipStream_t s) {
+    std::vector<SpmvArgs<TX>> a;
+    std::vector<unsigned> nb;
+    for (const auto &it : v) {
+        const Phys &P = *it.P;
+        a.push_back(SpmvArgs<TX>{Grid3{P.nx, P.ny, P.nz}, ncells(P), it.J7, it.x, it.y});
+        nb.push_back((ncells(P) + TPB - 1) / TPB);
+    }
+    return launch_batches(a, nb, [&](const Batch<SpmvArgs<TX>> &bt, unsigned g) {
+        k_spmv_J_batch<TX><<<g, TPB, 0, s>>>(bt);
+    });
+}
+template rich_status launch_spmv_J_batch<double>(const std::vector<SpmvItem<double>> &, hipStream_t);
+template rich_status launch_spmv_J_batch<float>(const std::vector<SpmvItem<float>> &, hipStream_t);
+
 #define INST_ST(TB, T)                                                                                    \
     template rich_status launch_st_pre<TB, T>(const Phys &, const T *, const T *, const TB *, const double *, T *, \
                                               hipStream_t);                                                     \
@@ -672,7 +834,9 @@ rich_status launch_st_sweeps(const Phys &P, const T *M4, const T *invd, const TB
     template rich_status launch_st_post_from<TB, T>(const Phys &, const T *, const T *, const TB *,              \
                                                     const double *, const T *, T *, hipStream_t);               \
     template rich_status launch_st_sweeps<TB, T>(const Phys &, const T *, const T *, const TB *, T *, T *, int, \
-                                                 hipStream_t);
+                                                 hipStream_t);                                                  \
+    template rich_status launch_st_pre_batch<TB, T>(const std::vector<FineItem<TB, T>> &, hipStream_t);         \
+    template rich_status launch_st_post_batch<TB, T>(const std::vector<FineItem<TB, T>> &, hipStream_t);
 INST_ST(double, double)
 INST_ST(double, float)
 INST_ST(float, float)

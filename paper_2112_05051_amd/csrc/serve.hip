@@ -3,10 +3,17 @@
 // is free and their device-memory plan (rich_query_bytes) fits what the
 // budget has left; every admitted simulation stays resident on the GPU for
 // all of its steps, driven by its own worker thread on its own HIP stream,
-// so the kernels of concurrent simulations overlap on the device.  Each
-// simulation runs exactly the kernels of a lone rich_step call on its own
-// stream with deterministic reductions, so its result does not depend on
-// what else is running.
+// so the kernels of concurrent simulations overlap on the device.  With fused
+// batching the preconditioned products of the simulations' GMRES solves go
+// through a batcher, which issues them as batched launches over all posted
+// simulations (the batcher itself lives with the solver).  Simulations share
+// a batcher only when they have the same grid and precision: the blocks of a
+// batched launch finish together, so a batch is only as fast as its largest
+// member, while simulations of different classes keep overlapping on separate
+// batcher streams.  Every block of a batched launch runs the lone kernel's
+// code on its own simulation's data and all reductions are deterministic, so
+// a simulation's result does not depend on what else is running.
+#include <array>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
@@ -54,12 +61,19 @@ struct rich_server {
     int64_t next_id = 1;
     int running = 0;
     bool stop = false;
+    bool fused = false;               // fused batching of the preconditioned products
+    // one batcher per class of (grid, precision), created with its first admission
+    std::map<std::array<int, 4>, rich_batcher *> batchers;
 };
 
 namespace {
 
+std::array<int, 4> batch_class(const Request &R) {
+    return {R.prob.nx, R.prob.ny, R.prob.nz, R.opts.precision};
+}
+
 // Run one admitted request to completion on the worker's stream.
-void run_request(rich_server *S, hipStream_t stream, Request &R) {
+void run_request(rich_server *S, hipStream_t stream, Request &R, rich_batcher *batcher) {
     int64_t N = (int64_t)R.prob.nx * R.prob.ny * R.prob.nz;
     double *dks = nullptr, *dp = nullptr;
     rich_handle_t h = nullptr;
@@ -72,6 +86,7 @@ void run_request(rich_server *S, hipStream_t stream, Request &R) {
          hipStreamSynchronize(stream) != hipSuccess))
         st = RICH_EHIP;
     if (st == RICH_OK) st = rich_create(&R.prob, &R.opts, dks, stream, &h);
+    if (st == RICH_OK && S->fused) st = batcher ? rich::batcher_attach(h, batcher) : RICH_EHIP;
     if (st == RICH_OK) st = rich_set_state(h, dp);
     for (int t = 0; t < R.nsteps && st >= 0; t++) {
         double t0 = wall_s();
@@ -97,6 +112,7 @@ void worker_main(rich_server *S) {
     if (hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess) return;
     for (;;) {
         std::shared_ptr<Request> R;
+        rich_batcher *batcher = nullptr;
         {
             std::unique_lock<std::mutex> lk(S->mu);
             // FIFO: the head of the queue is admitted once its plan fits the budget
@@ -106,10 +122,15 @@ void worker_main(rich_server *S) {
             S->queue.pop_front();
             S->in_use += R->bytes;
             S->running++;
+            if (S->fused) {
+                rich_batcher *&b = S->batchers[batch_class(*R)];
+                if (!b) b = rich::batcher_create();
+                batcher = b;
+            }
             R->state = RICH_REQ_RUNNING;
             R->t_start = wall_s();
         }
-        run_request(S, stream, *R);
+        run_request(S, stream, *R, batcher);
         {
             std::lock_guard<std::mutex> lk(S->mu);
             R->t_end = wall_s();
@@ -193,6 +214,29 @@ rich_status rich_server_poll(rich_server_t S, int64_t req_id, int *state, rich_s
     return RICH_OK;
 }
 
+rich_status rich_server_set_batching(rich_server_t S, int fused) {
+    if (!S) return RICH_EINVAL;
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (S->next_id != 1) return RICH_ESTATE;
+    S->fused = fused != 0;
+    return RICH_OK;
+}
+
+rich_status rich_server_batch_stats(rich_server_t S, int64_t *flushes, int64_t *products) {
+    if (!S) return RICH_EINVAL;
+    int64_t f = 0, p = 0;
+    std::lock_guard<std::mutex> lk(S->mu);
+    for (auto &kv : S->batchers) {
+        int64_t f1 = 0, p1 = 0;
+        if (kv.second) rich::batcher_stats(kv.second, &f1, &p1);
+        f += f1;
+        p += p1;
+    }
+    if (flushes) *flushes = f;
+    if (products) *products = p;
+    return RICH_OK;
+}
+
 rich_status rich_server_wait_idle(rich_server_t S) {
     if (!S) return RICH_EINVAL;
     std::unique_lock<std::mutex> lk(S->mu);
@@ -214,6 +258,7 @@ rich_status rich_server_destroy(rich_server_t S) {
     }
     S->cv.notify_all();
     for (auto &t : S->workers) t.join();
+    for (auto &kv : S->batchers) rich::batcher_destroy(kv.second);
     delete S;
     return RICH_OK;
 }

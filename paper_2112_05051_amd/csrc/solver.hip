@@ -4,10 +4,13 @@
 // V-cycle driver and hierarchy set-up (Section 5.2).  Every vector operation
 // runs on the GPU; the host only reads back the few scalars each decision
 // needs.
+#include <algorithm>
 #include <chrono>
+#include <condition_variable>
 #include <cmath>
 #include <cstring>
 #include <mutex>
+#include <thread>
 
 #include "common.hpp"
 
@@ -59,6 +62,11 @@ struct rich_ctx {
     double *hall = nullptr;    // pinned host mirror of hbuf
     double *bsc = nullptr;     // N: scaled right-hand side for a one-level hierarchy
     std::vector<hipEvent_t> iter_ev;  // one per Arnoldi iteration
+    // fused serving launches: the batcher this simulation posts its
+    // preconditioned products to (null: launched on its own stream)
+    rich_batcher *batcher = nullptr;
+    hipEvent_t bev = nullptr;          // inputs of the posted product are ready
+    bool in_batch = false;             // inside a GMRES solve that posts to the batcher
     // AMG
     Hierarchy *H = nullptr;
     bool have_J = false;
@@ -79,6 +87,7 @@ struct rich_ctx {
         if (hres) (void)hipHostFree(hres);
         if (hall) (void)hipHostFree(hall);
         for (auto e : iter_ev) (void)hipEventDestroy(e);
+        if (bev) (void)hipEventDestroy(bev);
         for (auto &k : prof)
             for (auto &e : k.pending) {
                 (void)hipEventDestroy(e.first);
@@ -442,6 +451,187 @@ rich_status spmv_J_z(rich_ctx *h, double *y) {
     });
 }
 
+// ------------------------------------------------- fused serving launches
+// Resident simulations of a server post each preconditioned product
+// w = J M^{-1} (bs b) (or M^{-1} b alone, w null) of their GMRES solves to a
+// shared batcher.  The batcher's own thread takes every product posted so far
+// and issues them as one batch on the batcher's stream, then takes whatever
+// was posted meanwhile (continuous batching: batches grow with the load, and
+// nothing waits for a simulation that is not ready).  A batch is one launch
+// per kernel and V-cycle level: the fine smoother, restriction, coarse
+// smoothers, coarsest product, prolongations and the J SpMV each cover every
+// simulation in it.  Each simulation's stream waits for its inputs before and
+// for the batch after.  Every block runs the code of the lone launch on its
+// own simulation's data, so a simulation's results are the same alone and in
+// a batch.
+struct BatchReq {
+    rich_ctx *h;
+    const double *b, *bs;
+    double *w;
+    uint64_t ticket;
+};
+
+}  // namespace
+
+struct rich_batcher {
+    std::mutex mu;
+    std::condition_variable cv;     // posts, and finished issues
+    hipStream_t s = nullptr;
+    hipEvent_t done = nullptr;      // recorded after each batch
+    std::thread thread;             // issues the batches
+    bool stop = false;
+    std::vector<BatchReq> pend;     // posted products
+    uint64_t posted = 0;            // tickets handed out
+    uint64_t issued = 0;            // products with ticket < issued are issued
+    rich_status last = RICH_OK;     // first error of an issue, sticky
+    int64_t flushes = 0, items = 0;
+};
+
+namespace {
+
+template <class T>
+const T *m4_of(const rich_ctx *h) {
+    return h->mixed ? (const T *)(const void *)h->M4f : (const T *)(const void *)h->M4;
+}
+template <class T>
+const T *invd0_of(const rich_ctx *h) {
+    return h->mixed ? (const T *)(const void *)h->invd0f : (const T *)(const void *)h->invd0;
+}
+
+// A simulation can join a batch when its V-cycle has the shape the batched
+// kernels cover: a piecewise-constant hierarchy of two or more levels with a
+// dense coarsest solve and CSR-stream row blocks on every smoothed coarse level.
+bool batchable(const rich_ctx *h) {
+    const Hierarchy *H = h->H;
+    if (!H || H->nlev < 2 || !H->dense) return false;
+    for (int l = 0; l < H->nlev - 1; l++) {
+        if (H->L[l].prow) return false;
+        if (l >= 1 && !H->L[l].rb) return false;
+    }
+    return true;
+}
+
+template <class T>
+rich_status apply_batch(const std::vector<BatchReq> &rq, hipStream_t s) {
+    if (rq.empty()) return RICH_OK;
+    auto x0_of = [](const Hierarchy &H, int l) { return l < H.nlev - 1 ? (T *)H.L[l].x : nullptr; };
+    int maxlev = 0;
+    for (const auto &q : rq) maxlev = std::max(maxlev, q.h->H->nlev);
+    std::vector<FineItem<double, T>> f;
+    std::vector<RestrictItem<T>> ri;
+    std::vector<CsrItem<T>> ci;
+    std::vector<GemvItem<T>> gi;
+    // down: fine pre-smoothing + residual, restriction
+    for (const auto &q : rq) {
+        Hierarchy &H = *q.h->H;
+        f.push_back({&q.h->P, m4_of<T>(q.h), invd0_of<T>(q.h), q.b, q.bs, nullptr, nullptr, nullptr, (T *)H.L[0].r});
+        ri.push_back({&H.L[0], (const T *)H.L[0].r, (T *)H.L[1].b, H.L[1].n, lvinvd<T>(H.L[1]), x0_of(H, 1)});
+    }
+    RICH_TRY(launch_st_pre_batch<double, T>(f, s));
+    RICH_TRY(launch_restrict_batch<T>(ri, s));
+    for (int l = 1; l < maxlev - 1; l++) {
+        ci.clear();
+        ri.clear();
+        for (const auto &q : rq) {
+            Hierarchy &H = *q.h->H;
+            if (l >= H.nlev - 1) continue;
+            Level &Lv = H.L[l];
+            ci.push_back({&Lv, lvval<T>(Lv), nullptr, (const T *)Lv.b, (const T *)Lv.x, nullptr, (T *)Lv.r});
+            ri.push_back({&Lv, (const T *)Lv.r, (T *)H.L[l + 1].b, H.L[l + 1].n, lvinvd<T>(H.L[l + 1]),
+                          x0_of(H, l + 1)});
+        }
+        RICH_TRY(launch_csr_pre_batch<T>(ci, s));
+        RICH_TRY(launch_restrict_batch<T>(ri, s));
+    }
+    // coarsest
+    for (const auto &q : rq) {
+        Hierarchy &H = *q.h->H;
+        Level &Lc = H.L[H.nlev - 1];
+        const T *cinv = q.h->mixed ? (const T *)(const void *)H.cinvf : (const T *)(const void *)H.cinv;
+        gi.push_back({cinv, (const T *)Lc.b, (T *)Lc.x, Lc.n});
+    }
+    RICH_TRY(launch_dense_gemv_batch<T>(gi, s));
+    // up: prolongation + post-smoothing
+    for (int l = maxlev - 2; l >= 1; l--) {
+        ci.clear();
+        for (const auto &q : rq) {
+            Hierarchy &H = *q.h->H;
+            if (l >= H.nlev - 1) continue;
+            Level &Lv = H.L[l];
+            ci.push_back({&Lv, lvval<T>(Lv), lvinvd<T>(Lv), (const T *)Lv.b, (const T *)Lv.x,
+                          (const T *)H.L[l + 1].x, (T *)Lv.x});
+        }
+        RICH_TRY(launch_csr_post_batch<T>(ci, s));
+    }
+    f.clear();
+    std::vector<SpmvItem<T>> sp;
+    for (const auto &q : rq) {
+        Hierarchy &H = *q.h->H;
+        f.push_back({&q.h->P, m4_of<T>(q.h), invd0_of<T>(q.h), q.b, q.bs, (const T *)H.L[1].x, H.L[0].agg,
+                     (T *)H.L[0].r, (T *)q.h->z});
+        if (q.w) sp.push_back({&q.h->P, q.h->J7, (const T *)q.h->z, q.w});
+    }
+    RICH_TRY(launch_st_post_batch<double, T>(f, s));
+    return launch_spmv_J_batch<T>(sp, s);
+}
+
+// Issue one batch on the batcher's stream (batcher thread, lock not held).
+rich_status issue_batch(rich_batcher *B, const std::vector<BatchReq> &rq) {
+    std::vector<BatchReq> mixed, fp64;
+    for (const auto &q : rq) {
+        HIP_TRY(hipStreamWaitEvent(B->s, q.h->bev, 0));
+        (q.h->mixed ? mixed : fp64).push_back(q);
+    }
+    RICH_TRY(apply_batch<float>(mixed, B->s));
+    RICH_TRY(apply_batch<double>(fp64, B->s));
+    HIP_TRY(hipEventRecord(B->done, B->s));
+    for (const auto &q : rq) HIP_TRY(hipStreamWaitEvent(q.h->s, B->done, 0));
+    return RICH_OK;
+}
+
+void batcher_main(rich_batcher *B, int device) {
+    (void)hipSetDevice(device);
+    std::unique_lock<std::mutex> lk(B->mu);
+    for (;;) {
+        B->cv.wait(lk, [&] { return B->stop || !B->pend.empty(); });
+        if (B->pend.empty()) return;  // stopping, nothing left
+        std::vector<BatchReq> rq;
+        rq.swap(B->pend);
+        lk.unlock();
+        rich_status st = issue_batch(B, rq);
+        lk.lock();
+        if (st != RICH_OK && B->last == RICH_OK) B->last = st;
+        B->issued = rq.back().ticket + 1;
+        B->flushes++;
+        B->items += (int64_t)rq.size();
+        B->cv.notify_all();
+    }
+}
+
+// w = J M^{-1} (bs b) (w null: z = M^{-1} (bs b) only), through the batcher
+// when the simulation is in a batched solve, else on its own stream.
+rich_status prec_product(rich_ctx *h, const double *b, const double *bs, double *w) {
+    if (!h->in_batch) {
+        RICH_TRY(apply_prec(h, b, bs));
+        return w ? spmv_J_z(h, w) : RICH_OK;
+    }
+    rich_batcher *B = h->batcher;
+    HIP_TRY(hipEventRecord(h->bev, h->s));
+    std::unique_lock<std::mutex> lk(B->mu);
+    const uint64_t t = B->posted++;
+    B->pend.push_back({h, b, bs, w, t});
+    B->cv.notify_all();
+    B->cv.wait(lk, [&] { return B->issued > t; });
+    return B->last;
+}
+
+// Membership of a GMRES solve in the batch (RAII).
+struct BatchScope {
+    rich_ctx *h;
+    explicit BatchScope(rich_ctx *hh) : h(hh) { h->in_batch = h->batcher && batchable(h); }
+    ~BatchScope() { h->in_batch = false; }
+};
+
 rich_status add_z(rich_ctx *h, double *x) {
     if (h->mixed) return launch_add_to<float>(x, (const float *)h->z, h->N, h->s);
     return launch_add_to<double>(x, (const double *)h->z, h->N, h->s);
@@ -478,12 +668,12 @@ rich_status gmres(rich_ctx *h, const double *b, double *x, int *its_out, double 
         return RICH_OK;
     }
     if (!std::isfinite(bnorm)) return RICH_NONFINITE;
+    BatchScope batch_scope(h);
     auto enqueue = [&](int j) -> rich_status {
         double *vj = h->V + (size_t)j * ld;
         double *w = h->V + (size_t)(j + 1) * ld;
         double *hb = h->hbuf + (size_t)j * W;
-        RICH_TRY(apply_prec(h, vj, h->vs + j));
-        RICH_TRY(spmv_J_z(h, w));
+        RICH_TRY(prec_product(h, vj, h->vs + j, w));
         RICH_TRY(timed(h, RICH_K_MULTIDOT, (double)N * 8 * (j + 2),
                        [&] { return launch_multidot(h->V, ld, j + 1, h->vs, w, N, h->partial, hb, s); }));
         RICH_TRY(timed(h, RICH_K_UPDATE, (double)N * 8 * (j + 3), [&] {
@@ -575,7 +765,7 @@ rich_status gmres(rich_ctx *h, const double *b, double *x, int *its_out, double 
         memcpy(h->hres, y.data(), k * sizeof(double));
         HIP_TRY(hipMemcpyAsync(h->dres, h->hres, k * sizeof(double), hipMemcpyHostToDevice, s));
         RICH_TRY(launch_lincomb(h->V, ld, k, h->dres, h->vs, h->work, N, s));
-        RICH_TRY(apply_prec(h, h->work, h->one));
+        RICH_TRY(prec_product(h, h->work, h->one, nullptr));
         RICH_TRY(add_z(h, x));
         RICH_TRY(sync(h));  // hres is reused before the next read
     }
@@ -1261,3 +1451,53 @@ rich_status rich_match_sweep(int64_t n, const int64_t *rowptr_dev, const int32_t
 }
 
 }  // extern "C"
+
+// ------------------------------------------------- batcher (server side)
+namespace rich {
+
+rich_batcher *batcher_create() {
+    rich_batcher *B = new rich_batcher();
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess || hipStreamCreateWithFlags(&B->s, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&B->done, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        batcher_destroy(B);
+        return nullptr;
+    }
+    B->thread = std::thread(batcher_main, B, device);
+    return B;
+}
+
+// Every attached simulation has finished before the batcher is destroyed.
+void batcher_destroy(rich_batcher *B) {
+    if (!B) return;
+    if (B->thread.joinable()) {
+        {
+            std::lock_guard<std::mutex> lk(B->mu);
+            B->stop = true;
+        }
+        B->cv.notify_all();
+        B->thread.join();
+    }
+    if (B->s) {
+        (void)hipStreamSynchronize(B->s);
+        (void)hipStreamDestroy(B->s);
+    }
+    if (B->done) (void)hipEventDestroy(B->done);
+    delete B;
+}
+
+rich_status batcher_attach(rich_handle_t h, rich_batcher *B) {
+    if (!h) return RICH_EINVAL;
+    if (B && !h->bev) HIP_TRY(hipEventCreateWithFlags(&h->bev, hipEventDisableTiming));
+    h->batcher = B;
+    return RICH_OK;
+}
+
+void batcher_stats(rich_batcher *B, int64_t *flushes, int64_t *items) {
+    std::lock_guard<std::mutex> lk(B->mu);
+    if (flushes) *flushes = B->flushes;
+    if (items) *items = B->items;
+}
+
+}  // namespace rich

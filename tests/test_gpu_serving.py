@@ -1,4 +1,6 @@
-"""Ensemble server: every request's result in the mix equals its result alone."""
+"""Ensemble server: every request's result in the mix equals its result alone,
+with the preconditioned products of the resident simulations fused into
+batched launches and without."""
 import numpy as np
 import pytest
 
@@ -21,14 +23,7 @@ def run_alone(rich, torch, rec):
     return s.get_state().cpu().numpy(), stats
 
 
-def test_alone_equals_mix():
-    import torch
-
-    import paper_2112_05051_amd as rich
-    reqs = small_requests()
-    srv = rich.Server(8 << 30, 3)
-    ids = [srv.submit(rec.problem, rec.options, rec.ks(), rec.p0(), rec.nsteps) for rec in reqs]
-    srv.wait_idle()
+def check_alone_equals_mix(rich, torch, srv, reqs, ids):
     for rec, i in zip(reqs, ids):
         r = srv.poll(i)
         assert r is not None
@@ -38,6 +33,48 @@ def test_alone_equals_mix():
         assert np.array_equal(r["p"], p_alone), np.abs(r["p"] - p_alone).max()
         assert [s["newton_its"] for s in r["stats"]] == [s["newton_its"] for s in st_alone[:len(r["stats"])]]
         assert [s["gmres_its"] for s in r["stats"]] == [s["gmres_its"] for s in st_alone[:len(r["stats"])]]
+
+
+@pytest.mark.parametrize("fused", [True, False])
+def test_alone_equals_mix(fused):
+    import torch
+
+    import paper_2112_05051_amd as rich
+    reqs = small_requests()
+    srv = rich.Server(8 << 30, 3, fused=fused)
+    ids = [srv.submit(rec.problem, rec.options, rec.ks(), rec.p0(), rec.nsteps) for rec in reqs]
+    srv.wait_idle()
+    check_alone_equals_mix(rich, torch, srv, reqs, ids)
+    flushes, products = srv.batch_stats()
+    if fused:
+        assert flushes > 0 and products >= flushes  # the products went through the batchers
+    else:
+        assert flushes == 0 and products == 0
+    srv.close()
+
+
+def test_fused_kernels_all_paths():
+    """48^3 grids run the tiled fine smoother and have a CSR-stream coarse
+    level, 16^3 grids the plain fine kernels; simulations of one size share
+    batched launches, and every result equals the lone run bit for bit."""
+    import torch
+
+    import paper_2112_05051_amd as rich
+    reqs = []
+    for seed, n in ((11, 48), (12, 48), (13, 16), (14, 16)):
+        rec = synth.serving_stream(count=1, seed=seed, sizes=(n,), nsteps=2)[0][1]
+        rec.problem.mean = synth.UPSTREAM  # converges on these fields
+        rec.options.max_newton = 40
+        reqs.append(rec)
+    srv = rich.Server(16 << 30, 4, fused=True)
+    ids = [srv.submit(rec.problem, rec.options, rec.ks(), rec.p0(), rec.nsteps) for rec in reqs]
+    srv.wait_idle()
+    flushes, products = srv.batch_stats()
+    assert flushes > 0 and products > flushes, (flushes, products)
+    check_alone_equals_mix(rich, torch, srv, reqs, ids)
+    # the tiled-size simulations ran Newton steps (and so fused GMRES products)
+    for i in ids[:2]:
+        assert sum(s["gmres_its"] for s in srv.poll(i)["stats"]) > 0
     srv.close()
 
 
