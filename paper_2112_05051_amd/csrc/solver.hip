@@ -454,16 +454,19 @@ rich_status spmv_J_z(rich_ctx *h, double *y) {
 // ------------------------------------------------- fused serving launches
 // Resident simulations of a server post each preconditioned product
 // w = J M^{-1} (bs b) (or M^{-1} b alone, w null) of their GMRES solves to a
-// shared batcher.  The batcher's own thread takes every product posted so far
-// and issues them as one batch on the batcher's stream, then takes whatever
-// was posted meanwhile (continuous batching: batches grow with the load, and
-// nothing waits for a simulation that is not ready).  A batch is one launch
+// shared batcher.  The batcher's own thread issues the posted products as one
+// batch on the batcher's stream once every attached simulation that is inside
+// a GMRES solve has posted, or once the oldest post has waited BATCH_WINDOW_S
+// (a simulation busy elsewhere holds no one up for longer), then gathers the
+// next batch.  A batch is one launch
 // per kernel and V-cycle level: the fine smoother, restriction, coarse
 // smoothers, coarsest product, prolongations and the J SpMV each cover every
 // simulation in it.  Each simulation's stream waits for its inputs before and
 // for the batch after.  Every block runs the code of the lone launch on its
 // own simulation's data, so a simulation's results are the same alone and in
 // a batch.
+constexpr double BATCH_WINDOW_S = 100e-6;
+
 struct BatchReq {
     rich_ctx *h;
     const double *b, *bs;
@@ -480,6 +483,8 @@ struct rich_batcher {
     hipEvent_t done = nullptr;      // recorded after each batch
     std::thread thread;             // issues the batches
     bool stop = false;
+    int in_solve = 0;               // attached simulations inside a GMRES solve
+    std::chrono::steady_clock::time_point first;  // time of the oldest pending post
     std::vector<BatchReq> pend;     // posted products
     uint64_t posted = 0;            // tickets handed out
     uint64_t issued = 0;            // products with ticket < issued are issued
@@ -595,6 +600,9 @@ void batcher_main(rich_batcher *B, int device) {
     for (;;) {
         B->cv.wait(lk, [&] { return B->stop || !B->pend.empty(); });
         if (B->pend.empty()) return;  // stopping, nothing left
+        const auto deadline = B->first + std::chrono::duration_cast<std::chrono::steady_clock::duration>(
+                                              std::chrono::duration<double>(BATCH_WINDOW_S));
+        B->cv.wait_until(lk, deadline, [&] { return B->stop || (int)B->pend.size() >= B->in_solve; });
         std::vector<BatchReq> rq;
         rq.swap(B->pend);
         lk.unlock();
@@ -619,6 +627,7 @@ rich_status prec_product(rich_ctx *h, const double *b, const double *bs, double 
     HIP_TRY(hipEventRecord(h->bev, h->s));
     std::unique_lock<std::mutex> lk(B->mu);
     const uint64_t t = B->posted++;
+    if (B->pend.empty()) B->first = std::chrono::steady_clock::now();
     B->pend.push_back({h, b, bs, w, t});
     B->cv.notify_all();
     B->cv.wait(lk, [&] { return B->issued > t; });
@@ -628,8 +637,20 @@ rich_status prec_product(rich_ctx *h, const double *b, const double *bs, double 
 // Membership of a GMRES solve in the batch (RAII).
 struct BatchScope {
     rich_ctx *h;
-    explicit BatchScope(rich_ctx *hh) : h(hh) { h->in_batch = h->batcher && batchable(h); }
-    ~BatchScope() { h->in_batch = false; }
+    explicit BatchScope(rich_ctx *hh) : h(hh) {
+        if (!h->batcher || !batchable(h)) return;
+        std::lock_guard<std::mutex> lk(h->batcher->mu);
+        h->batcher->in_solve++;
+        h->in_batch = true;
+    }
+    ~BatchScope() {
+        if (!h->in_batch) return;
+        rich_batcher *B = h->batcher;
+        std::lock_guard<std::mutex> lk(B->mu);
+        h->in_batch = false;
+        B->in_solve--;
+        B->cv.notify_all();  // the pending batch may be complete now
+    }
 };
 
 rich_status add_z(rich_ctx *h, double *x) {
