@@ -78,6 +78,28 @@ def test_fused_kernels_all_paths():
     srv.close()
 
 
+def test_fused_fp64():
+    """The all-FP64 batched V-cycle: two same-size FP64 simulations share
+    batches and each equals its lone run bit for bit."""
+    import torch
+
+    import paper_2112_05051_amd as rich
+    reqs = []
+    for seed in (21, 22):
+        rec = synth.serving_stream(count=1, seed=seed, sizes=(24,), nsteps=2)[0][1]
+        rec.problem.mean = synth.ARITH
+        rec.options.precision = synth.FP64
+        rec.options.max_newton = 40
+        reqs.append(rec)
+    srv = rich.Server(8 << 30, 2, fused=True)
+    ids = [srv.submit(rec.problem, rec.options, rec.ks(), rec.p0(), rec.nsteps) for rec in reqs]
+    srv.wait_idle()
+    flushes, products = srv.batch_stats()
+    assert flushes > 0 and products > flushes, (flushes, products)
+    check_alone_equals_mix(rich, torch, srv, reqs, ids)
+    srv.close()
+
+
 def test_budget_serialises_but_completes():
     import paper_2112_05051_amd as rich
     reqs = small_requests(count=4, steps=2, seed=8, sizes=(14,))
