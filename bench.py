@@ -345,7 +345,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              f"(the multi-GPU decomposition is described in DESIGN.md, not implemented)", file=sys.stderr)
+              f"(how the path would shard is a design note, not an implementation)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

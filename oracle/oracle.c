@@ -5,7 +5,7 @@
  * CPU-baseline leg of the benchmark; never by the product library, with which
  * it shares no code.  Every function is a direct, unblocked transcription of
  * the definition it cites; where the paper is silent the reading used is
- * stated in the comment (the same readings are listed in the design doc).
+ * stated in the comment.
  *
  * Pinning: the laws, residual, Jacobian and auxiliary matrix are pinned by the
  * paper's printed Jacobian entries, central finite differences, mass balance,
@@ -753,7 +753,7 @@ void orc_rap(int64_t n, const int64_t *rowptr, const int32_t *col, const double 
 /* half of the rows while the current one fits the dense coarsest solver.   */
 /* Re-use (Section 6): the aggregates are kept for the whole run; later     */
 /* rebuilds refresh the fine matrix and its smoother and, when amg_refresh  */
-/* is set (the reading used by default, see DESIGN), recompute every coarse */
+/* is set (the reading used by default), recompute every coarse           */
 /* matrix from the new fine one with the same aggregates.                   */
 /* The first amg_smoothed levels (from the finest) take the smoothed       */
 /* prolongator of orc_smoothed_prolongator and the coarse matrix P^T A P   */
@@ -761,7 +761,11 @@ void orc_rap(int64_t n, const int64_t *rowptr, const int32_t *col, const double 
 /* piecewise-constant products, and a refresh recomputes P (with its       */
 /* omega) and P^T A P.                                                      */
 /* Smoother: l1-Jacobi, D_ii = sum_j |a_ij| (reading of the paper's "l1-     */
-/* Jacobi").  Coarsest: dense Cholesky when n <= coarse_dense_max, else      */
+/* Jacobi"); with smoother = 1 the finest level takes one multicolour        */
+/* Gauss-Seidel sweep instead (orc_mcgs_sweep: backward before, forward      */
+/* after the coarse correction, as the paper's experiments of Section 6 use  */
+/* backward/forward Gauss-Seidel), the coarser levels keep l1-Jacobi.        */
+/* Coarsest: dense Cholesky when n <= coarse_dense_max, else                 */
 /* coarse_l1_sweeps l1-Jacobi sweeps from zero (both keep M^{-1} linear).    */
 /* ------------------------------------------------------------------------ */
 #define ORC_MAXLEV 32
@@ -772,6 +776,9 @@ struct orc_amg {
     int32_t *agg[ORC_MAXLEV];
     orc_csr P[ORC_MAXLEV]; /* smoothed prolongator of level l (n_l rows), or empty */
     double *l1[ORC_MAXLEV];
+    int smoother;   /* 1: multicolour Gauss-Seidel on level 0 */
+    int32_t *color; /* level-0 colours (smoother 1) */
+    int ncolor;
     int dense;
     double *chol; /* n_c x n_c, row-major lower factor */
     int coarse_sweeps;
@@ -785,6 +792,56 @@ static void csr_free(orc_csr *A)
     A->rowptr = NULL;
     A->col = NULL;
     A->val = NULL;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Multicolour Gauss-Seidel (the GPU form of the paper's hybrid Gauss-Seidel */
+/* smoother of Section 5.2 / Section 6).  Colouring: greedy in index order,  */
+/* colour(i) = the smallest colour no neighbour j < i has; on the 7-point    */
+/* grid graph in x-fastest order this is the red-black parity (i+j+k) mod 2. */
+/* A sweep visits the colours in ascending (forward, dir = +1) or descending */
+/* (backward, dir = -1) order, rows of one colour in index order or its      */
+/* reverse, and sets x_i = (b_i - sum_{j != i} a_ij x_j) / a_ii in place: a  */
+/* Gauss-Seidel sweep in the colour-sorted ordering.                          */
+/* ------------------------------------------------------------------------ */
+int orc_greedy_colors(int64_t n, const int64_t *rowptr, const int32_t *col, int32_t *color)
+{
+    int ncolor = 0;
+    int64_t maxdeg = 1;
+    for (int64_t i = 0; i < n; i++)
+        if (rowptr[i + 1] - rowptr[i] + 1 > maxdeg) maxdeg = rowptr[i + 1] - rowptr[i] + 1;
+    char *used = (char *)calloc((size_t)maxdeg + 1, 1);
+    for (int64_t i = 0; i < n; i++) {
+        memset(used, 0, (size_t)maxdeg + 1);
+        for (int64_t e = rowptr[i]; e < rowptr[i + 1]; e++) {
+            int64_t j = col[e];
+            if (j < i && color[j] <= maxdeg) used[color[j]] = 1;
+        }
+        int c = 0;
+        while (used[c]) c++;
+        color[i] = c;
+        if (c + 1 > ncolor) ncolor = c + 1;
+    }
+    free(used);
+    return ncolor;
+}
+
+void orc_mcgs_sweep(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
+                    const int32_t *color, int ncolor, int dir, const double *b, double *x)
+{
+    for (int k = 0; k < ncolor; k++) {
+        int c = dir > 0 ? k : ncolor - 1 - k;
+        for (int64_t t = 0; t < n; t++) {
+            int64_t i = dir > 0 ? t : n - 1 - t;
+            if (color[i] != c) continue;
+            double s = b[i], d = 0.0;
+            for (int64_t e = rowptr[i]; e < rowptr[i + 1]; e++) {
+                if (col[e] == i) d = val[e];
+                else s -= val[e] * x[col[e]];
+            }
+            x[i] = s / d;
+        }
+    }
 }
 
 static void l1_diag(const orc_csr *A, double *d)
@@ -915,6 +972,11 @@ int orc_amg_build(const orc_opts *O, int64_t n, const int64_t *rowptr, const int
     }
     H->coarse_sweeps = O->coarse_l1_sweeps;
     H->refresh = O->amg_refresh;
+    H->smoother = O->smoother;
+    if (H->smoother == 1 && H->nlev > 1) {
+        H->color = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+        H->ncolor = orc_greedy_colors(n, H->A[0].rowptr, H->A[0].col, H->color);
+    }
     H->dense = H->A[H->nlev - 1].n <= O->coarse_dense_max;
     if (H->dense) {
         int st = dense_cholesky(&H->A[H->nlev - 1], &H->chol);
@@ -1004,6 +1066,7 @@ void orc_amg_destroy(orc_amg *H)
         free(H->l1[l]);
     }
     free(H->chol);
+    free(H->color);
     free(H);
 }
 
@@ -1035,8 +1098,9 @@ static void coarse_solve(const orc_amg *H, const double *b, double *x)
     free(r);
 }
 
-/* Symmetric V-cycle of Section 5.2 with one l1-Jacobi sweep before and after */
-/* the coarse correction; the pre-sweep starts from x = 0.                    */
+/* Symmetric V-cycle of Section 5.2 with one l1-Jacobi sweep (one backward / */
+/* forward multicolour Gauss-Seidel sweep on level 0 with smoother 1) before  */
+/* and after the coarse correction; the pre-sweep starts from x = 0.          */
 static void vcycle(const orc_amg *H, int l, const double *b, double *x)
 {
     if (l == H->nlev - 1) {
@@ -1050,7 +1114,13 @@ static void vcycle(const orc_amg *H, int l, const double *b, double *x)
     double *r = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
     double *bc = (double *)calloc((size_t)(nc > 0 ? nc : 1), sizeof(double));
     double *xc = (double *)malloc((size_t)(nc > 0 ? nc : 1) * sizeof(double));
-    for (int64_t i = 0; i < n; i++) x[i] = b[i] / d[i];
+    const int gs = l == 0 && H->smoother == 1;
+    if (gs) { /* backward Gauss-Seidel sweep from x = 0 */
+        for (int64_t i = 0; i < n; i++) x[i] = 0.0;
+        orc_mcgs_sweep(n, A->rowptr, A->col, A->val, H->color, H->ncolor, -1, b, x);
+    } else {
+        for (int64_t i = 0; i < n; i++) x[i] = b[i] / d[i];
+    }
     orc_csr_matvec(n, A->rowptr, A->col, A->val, x, r);
     for (int64_t i = 0; i < n; i++) r[i] = b[i] - r[i];
     if (H->P[l].rowptr) { /* b_c = P^T r, then x += P x_c */
@@ -1068,8 +1138,12 @@ static void vcycle(const orc_amg *H, int l, const double *b, double *x)
         vcycle(H, l + 1, bc, xc);
         for (int64_t i = 0; i < n; i++) x[i] += xc[agg[i]];
     }
-    orc_csr_matvec(n, A->rowptr, A->col, A->val, x, r);
-    for (int64_t i = 0; i < n; i++) x[i] += (b[i] - r[i]) / d[i];
+    if (gs) { /* forward Gauss-Seidel sweep */
+        orc_mcgs_sweep(n, A->rowptr, A->col, A->val, H->color, H->ncolor, +1, b, x);
+    } else {
+        orc_csr_matvec(n, A->rowptr, A->col, A->val, x, r);
+        for (int64_t i = 0; i < n; i++) x[i] += (b[i] - r[i]) / d[i];
+    }
     free(r);
     free(bc);
     free(xc);

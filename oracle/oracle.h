@@ -67,6 +67,8 @@ typedef struct {
     int amg_refresh; /* 0: later rebuilds refresh the smoother only; 1: also the coarse matrices */
     int aux_dflux;   /* 1: the auxiliary matrix's diagonal also takes the flux-derivative terms */
     int amg_smoothed; /* levels (from the finest) with smoothed prolongators; 0: none */
+    int smoother;     /* 0: l1-Jacobi on every level; 1: multicolour Gauss-Seidel on the finest
+                         level (backward before, forward after the coarse correction) */
 } orc_opts;
 
 typedef struct {
@@ -124,6 +126,11 @@ int64_t orc_rap_nnz(int64_t n, const int64_t *rowptr, const int32_t *col, int64_
 void orc_rap(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val, int64_t nc,
              const int64_t *prow, const int32_t *pcol, const double *pval, int64_t *crow,
              int32_t *ccol, double *cval);
+
+/* ---- multicolour Gauss-Seidel ---- */
+int orc_greedy_colors(int64_t n, const int64_t *rowptr, const int32_t *col, int32_t *color);
+void orc_mcgs_sweep(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
+                    const int32_t *color, int ncolor, int dir, const double *b, double *x);
 
 /* ---- AMG hierarchy (opaque) ---- */
 typedef struct orc_amg orc_amg;

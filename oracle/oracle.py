@@ -48,7 +48,7 @@ class COpts(C.Structure):
                 ("amg_max_levels", C.c_int), ("amg_coarse_size", C.c_int64),
                 ("amg_sweeps", C.c_int), ("coarse_dense_max", C.c_int64),
                 ("coarse_l1_sweeps", C.c_int), ("amg_refresh", C.c_int),
-                ("aux_dflux", C.c_int), ("amg_smoothed", C.c_int)]
+                ("aux_dflux", C.c_int), ("amg_smoothed", C.c_int), ("smoother", C.c_int)]
 
 
 class CStats(C.Structure):
@@ -91,6 +91,8 @@ def lib():
         L.orc_rap_nnz.argtypes = [C.c_int64, i64, i32, C.c_int64, i64, i32]
         L.orc_rap_nnz.restype = C.c_int64
         L.orc_rap.argtypes = [C.c_int64, i64, i32, d, C.c_int64, i64, i32, d, i64, i32, d]
+        L.orc_greedy_colors.argtypes = [C.c_int64, i64, i32, i32]
+        L.orc_mcgs_sweep.argtypes = [C.c_int64, i64, i32, d, i32, C.c_int, C.c_int, d, d]
         L.orc_amg_prolongator_nnz.argtypes = [vp, C.c_int]
         L.orc_amg_prolongator_nnz.restype = C.c_int64
         L.orc_amg_prolongator_export.argtypes = [vp, C.c_int, i64, i32, d]
@@ -145,7 +147,7 @@ def cproblem(P) -> CProblem:
 def copts(O) -> COpts:
     c = COpts()
     for f, t in COpts._fields_:
-        v = getattr(O, f)
+        v = getattr(O, f, 0)
         setattr(c, f, float(v) if t is C.c_double else int(v))
     return c
 
@@ -249,6 +251,24 @@ def smoothed_prolongator(A, agg, nc):
     omega = lib().orc_smoothed_prolongator(n, _i64(rp), _i32(col), _d(val), _i32(agg), nc, _i64(prow),
                                            _i32(pcol), _d(pval))
     return sp.csr_matrix((pval, pcol, prow), shape=(n, nc)), float(omega)
+
+
+def greedy_colors(A):
+    """Greedy colouring of A's graph in index order; returns (colour array, number of colours)."""
+    rp, col, _ = _csr_parts(A)
+    color = np.empty(A.shape[0], np.int32)
+    nc = lib().orc_greedy_colors(A.shape[0], _i64(rp), _i32(col), _i32(color))
+    return color, int(nc)
+
+
+def mcgs_sweep(A, color, ncolor, direction, b, x):
+    """One multicolour Gauss-Seidel sweep on A x = b from x (forward: direction +1,
+    colours ascending; backward: -1); returns the new x."""
+    rp, col, val = _csr_parts(A)
+    x = np.array(x, dtype=np.float64)
+    lib().orc_mcgs_sweep(A.shape[0], _i64(rp), _i32(col), _d(val), _i32(np.asarray(color, np.int32)),
+                         int(ncolor), int(direction), _d(_f64(b)), _d(x))
+    return x
 
 
 def rap(A, P):

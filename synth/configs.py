@@ -2,9 +2,9 @@
 
 The constitutive parameters are the ones the paper lists for its 1-D study and
 Figure 1 (Haverkamp-type laws, Section 2).  Geometry, boundary data and the
-K_s statistics of the larger workloads are this project's choices, written
-down in the design doc: a 64 cm cube, initial head -61.5 cm, top face held at
--20.7 cm (Dirichlet), the five other faces no-flux.  The grid spacing is
+K_s statistics of the larger workloads are this project's choices: a 64 cm
+cube, initial head -61.5 cm, top face held at -20.7 cm (Dirichlet), the five
+other faces no-flux.  The grid spacing is
 h = L / (n + 1): the n unknowns per axis are the interior nodes of an
 (n + 2)-node grid whose outermost nodes lie on the boundary (Section 2.1).
 """
@@ -84,6 +84,7 @@ class Options:
     aux_dflux: int = 0                  # 1: preconditioner diagonal takes the flux-derivative terms
     amg_smoothed: int = 0               # levels (from the finest) whose prolongator is smoothed (damped Jacobi on P_t)
     tile_kz: int = 0                    # planes per block of the tiled fine-level smoother (0: automatic)
+    smoother: int = 0                   # 0: l1-Jacobi; 1: multicolour Gauss-Seidel on the finest level
 
 
 @dataclass
