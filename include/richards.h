@@ -125,7 +125,16 @@ typedef struct rich_solver_opts {
                             set-up work and denser coarse levels and saves GMRES iterations */
     int tile_kz;         /* planes per thread block in the tiled fine-level smoother kernels
                             (0 = automatic; a tuning knob, results do not depend on it) */
+    int smoother;        /* fine-level smoother of a multi-level hierarchy: RICH_SMOOTH_L1
+                            (l1-Jacobi, the default) or RICH_SMOOTH_MCGS (multicolour
+                            Gauss-Seidel, colour (i+j+k) mod 2, diagonal m_cc: one backward
+                            sweep from zero before and one forward sweep after the coarse
+                            correction, the GPU form of the hybrid backward/forward
+                            Gauss-Seidel of the paper's experiments, Section 6); coarser
+                            levels always take l1-Jacobi */
 } rich_solver_opts_t;
+#define RICH_SMOOTH_L1 0
+#define RICH_SMOOTH_MCGS 1
 
 /* Per-time-step counters and timings (host wall seconds of each phase). */
 typedef struct rich_step_stats {

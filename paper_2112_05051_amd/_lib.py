@@ -48,7 +48,7 @@ class Opts(C.Structure):
                 ("amg_sweeps", C.c_int), ("coarse_dense_max", C.c_int64),
                 ("coarse_l1_sweeps", C.c_int), ("precision", C.c_int), ("gmres_reorth", C.c_double),
                 ("aux_dflux", C.c_int), ("amg_refresh", C.c_int), ("amg_smoothed", C.c_int),
-                ("tile_kz", C.c_int)]
+                ("tile_kz", C.c_int), ("smoother", C.c_int)]
 
 
 class StepStats(C.Structure):

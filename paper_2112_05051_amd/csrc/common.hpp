@@ -169,6 +169,16 @@ rich_status launch_st_pre(const Phys &P, const T *M4, const T *invd, const TB *b
 template <class TB, class T>
 rich_status launch_st_post(const Phys &P, const T *M4, const T *invd, const TB *b, const double *bs, const T *xc,
                            const int32_t *agg, T *x, T *xt, hipStream_t s);
+// Multicolour Gauss-Seidel fine level: x0 = one backward sweep from zero on
+// M x = bs b, r = bs b - M x0; post: xt = x0 + P xc (when agg is set; else xt
+// already holds the prolongated iterate), one forward sweep from xt into x
+// (xt is overwritten).
+template <class TB, class T>
+rich_status launch_gs_pre(const Phys &P, const T *M4, const TB *b, const double *bs, T *x0, T *r, hipStream_t s);
+template <class TB, class T>
+rich_status launch_gs_post(const Phys &P, const T *M4, const TB *b, const double *bs, const T *x0, const T *xc,
+                           const int32_t *agg, T *xt, T *x, hipStream_t s);
+
 // One simulation's part of a batched fine-level V-cycle step (same meaning as
 // the arguments of launch_st_pre / launch_st_post; xt: N scratch).
 template <class TB, class T>

@@ -589,6 +589,78 @@ inline int64_t tiles25(const Phys &P, int kz) {
 }
 inline unsigned grid25(const Phys &P, int kz) { return xcd_grid(tiles25(P, kz), 1); }
 
+// Multicolour Gauss-Seidel on the fine level (the GPU form of the hybrid
+// backward/forward Gauss-Seidel smoother of the paper's experiments, Section
+// 6): colour (i + j + k) mod 2, so cells of one colour couple only to cells of
+// the other; x_c = (b_c - sum_n m_cn x_n) / m_cc, the terms subtracted in
+// ascending column order (-z, -y, -x, +x, +y, +z).
+template <class T, class G, class F>
+__device__ inline T gs_row(const G &P, const Cell &q, uint32_t c, uint32_t n, const T *__restrict__ M4, T bc, F v) {
+    uint32_t nx = P.nx, nxy = (uint32_t)P.nx * (uint32_t)P.ny;
+    T s = bc;
+    if (q.k > 0) s -= M4[(size_t)M_ZP * n + c - nxy] * v(c - nxy);
+    if (q.j > 0) s -= M4[(size_t)M_YP * n + c - nx] * v(c - nx);
+    if (q.i > 0) s -= M4[(size_t)M_XP * n + c - 1] * v(c - 1);
+    if (q.i < P.nx - 1) s -= M4[(size_t)M_XP * n + c] * v(c + 1);
+    if (q.j < P.ny - 1) s -= M4[(size_t)M_YP * n + c] * v(c + nx);
+    if (q.k < P.nz - 1) s -= M4[(size_t)M_ZP * n + c] * v(c + nxy);
+    return s / M4[(size_t)M_D * n + c];
+}
+
+// Pre-smoothing, one backward sweep from x = 0: colour 1 takes b / m_cc, then
+// colour 0 takes its row with those values (formed on the fly): one pass.
+template <class TB, class T>
+__global__ void k_gs_pre(Phys P, uint32_t n, const T *__restrict__ M4, const TB *__restrict__ b,
+                         const double *__restrict__ bsp, T *__restrict__ x0) {
+    uint32_t c = xcd_block() * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    const TB bs = (TB)bsp[0];
+    Cell q = cell_of(P, c);
+    const T bc = (T)(b[c] * bs);
+    if ((q.i + q.j + q.k) & 1) {
+        x0[c] = bc / M4[(size_t)M_D * n + c];
+        return;
+    }
+    x0[c] = gs_row<T>(P, q, c, n, M4, bc, [&](uint32_t t) { return (T)(b[t] * bs) / M4[(size_t)M_D * n + t]; });
+}
+
+// r = bs b - M x
+template <class TB, class T>
+__global__ void k_gs_res(Phys P, uint32_t n, const T *__restrict__ M4, const TB *__restrict__ b,
+                         const double *__restrict__ bsp, const T *__restrict__ x, T *__restrict__ r) {
+    uint32_t c = xcd_block() * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    Cell q = cell_of(P, c);
+    T s = mstencil<T>(P, q, c, n, M4, [&](uint32_t t) { return x[t]; });
+    r[c] = (T)(b[c] * (TB)bsp[0]) - s;
+}
+
+// xt = x0 + P xc (piecewise-constant prolongation)
+template <class T>
+__global__ void k_gs_prolong(uint32_t n, const T *__restrict__ x0, const T *__restrict__ xc,
+                             const int32_t *__restrict__ agg, T *__restrict__ xt) {
+    uint32_t c = xcd_block() * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    xt[c] = x0[c] + xc[agg[c]];
+}
+
+// One colour of a sweep: cells of `color` take their row on x_in; the other
+// cells copy x_in when x_out is another vector (in place they keep theirs:
+// a cell of `color` reads only cells of the other colour, so it is race free).
+template <class TB, class T>
+__global__ void k_gs_color(Phys P, uint32_t n, const T *__restrict__ M4, const TB *__restrict__ b,
+                           const double *__restrict__ bsp, int color, const T *x_in, T *x_out) {
+    uint32_t c = xcd_block() * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    Cell q = cell_of(P, c);
+    if (((q.i + q.j + q.k) & 1) != color) {
+        if (x_out != x_in) x_out[c] = x_in[c];
+        return;
+    }
+    const T bc = (T)(b[c] * (TB)bsp[0]);
+    x_out[c] = gs_row<T>(P, q, c, n, M4, bc, [&](uint32_t t) { return x_in[t]; });
+}
+
 // Plain l1-Jacobi sweep x_out = x_in + D^{-1}(b - M x_in) (used when the
 // fine level is also the coarsest and too large for a direct solve).
 template <class TB, class T>
@@ -751,6 +823,32 @@ rich_status launch_st_sweeps(const Phys &P, const T *M4, const T *invd, const TB
 }
 
 template <class TB, class T>
+rich_status launch_gs_pre(const Phys &P, const T *M4, const TB *b, const double *bs, T *x0, T *r, hipStream_t s) {
+    uint32_t n = ncells(P);
+    k_gs_pre<TB, T><<<nblocks(n), TPB, 0, s>>>(P, n, M4, b, bs, x0);
+    LAUNCH_CHECK();
+    k_gs_res<TB, T><<<nblocks(n), TPB, 0, s>>>(P, n, M4, b, bs, x0, r);
+    LAUNCH_CHECK();
+    return RICH_OK;
+}
+
+template <class TB, class T>
+rich_status launch_gs_post(const Phys &P, const T *M4, const TB *b, const double *bs, const T *x0, const T *xc,
+                           const int32_t *agg, T *xt, T *x, hipStream_t s) {
+    uint32_t n = ncells(P);
+    if (agg) {
+        k_gs_prolong<T><<<nblocks(n), TPB, 0, s>>>(n, x0, xc, agg, xt);
+        LAUNCH_CHECK();
+    }
+    // forward sweep: colour 0 in place, then colour 1 into x
+    k_gs_color<TB, T><<<nblocks(n), TPB, 0, s>>>(P, n, M4, b, bs, 0, xt, xt);
+    LAUNCH_CHECK();
+    k_gs_color<TB, T><<<nblocks(n), TPB, 0, s>>>(P, n, M4, b, bs, 1, xt, x);
+    LAUNCH_CHECK();
+    return RICH_OK;
+}
+
+template <class TB, class T>
 static StArgs<TB, T> st_args(const FineItem<TB, T> &it, int kz) {
     const Phys &P = *it.P;
     StArgs<TB, T> a;
@@ -836,6 +934,10 @@ template rich_status launch_spmv_J_batch<float>(const std::vector<SpmvItem<float
     template rich_status launch_st_sweeps<TB, T>(const Phys &, const T *, const T *, const TB *, T *, T *, int, \
                                                  hipStream_t);                                                  \
     template rich_status launch_st_pre_batch<TB, T>(const std::vector<FineItem<TB, T>> &, hipStream_t);         \
+    template rich_status launch_gs_pre<TB, T>(const Phys &, const T *, const TB *, const double *, T *, T *,      \
+                                              hipStream_t);                                                    \
+    template rich_status launch_gs_post<TB, T>(const Phys &, const T *, const TB *, const double *, const T *,   \
+                                               const T *, const int32_t *, T *, T *, hipStream_t);             \
     template rich_status launch_st_post_batch<TB, T>(const std::vector<FineItem<TB, T>> &, hipStream_t);
 INST_ST(double, double)
 INST_ST(double, float)

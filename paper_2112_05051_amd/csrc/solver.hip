@@ -385,9 +385,12 @@ rich_status vcycle(rich_ctx *h, const double *b, const double *bs, T *z) {
         return launch_st_sweeps<double, T>(h->P, M4, invd0, h->bsc, z, (T *)h->ztmp, h->O.coarse_l1_sweeps, s);
     }
     const double t = sizeof(T), n0 = (double)h->N, n1 = (double)H.L[1].n;
+    const bool gs = h->O.smoother == RICH_SMOOTH_MCGS;
     // down
-    RICH_TRY(timed(h, RICH_K_VC0_PRE, n0 * (8 + 6 * t),
-                   [&] { return launch_st_pre<double, T>(h->P, M4, invd0, b, bs, (T *)H.L[0].r, s); }));
+    RICH_TRY(timed(h, RICH_K_VC0_PRE, gs ? n0 * (16 + 12 * t) : n0 * (8 + 6 * t), [&] {
+        if (gs) return launch_gs_pre<double, T>(h->P, M4, b, bs, (T *)H.L[0].x, (T *)H.L[0].r, s);
+        return launch_st_pre<double, T>(h->P, M4, invd0, b, bs, (T *)H.L[0].r, s);
+    }));
     const Level &L0 = H.L[0];
     double rbytes = L0.prow ? (double)L0.pnnz * (4 + 2 * t) + n1 * (8 + t) : n0 * (t + 4) + n1 * (8 + t);
     // each restriction also stores the next level's pre-smoothed iterate
@@ -422,6 +425,15 @@ rich_status vcycle(rich_ctx *h, const double *b, const double *bs, T *z) {
             return launch_csr_post<T, T>(Lv, lvval<T>(Lv), lvinvd<T>(Lv), (const T *)Lv.b, (const T *)Lv.x,
                                          (const T *)H.L[l + 1].x, (T *)Lv.x, s);
         }));
+    }
+    if (gs) {
+        // x0 + P xc into the level's r buffer, then the forward Gauss-Seidel sweep
+        return timed(h, RICH_K_VC0_POST, n0 * (20 + 12 * t) + n1 * t, [&] {
+            T *xt = (T *)H.L[0].r;
+            const T *x0 = (const T *)H.L[0].x, *xc = (const T *)H.L[1].x;
+            if (L0.prow) RICH_TRY(launch_sa_prolong<double, T>(L0, invd0, b, bs, x0, xc, xt, s));
+            return launch_gs_post<double, T>(h->P, M4, b, bs, x0, xc, L0.prow ? nullptr : L0.agg, xt, z, s);
+        });
     }
     if (L0.prow) {
         // smoothed prolongation into the level's r buffer, then post-smoothing
@@ -508,7 +520,7 @@ const T *invd0_of(const rich_ctx *h) {
 // dense coarsest solve and CSR-stream row blocks on every smoothed coarse level.
 bool batchable(const rich_ctx *h) {
     const Hierarchy *H = h->H;
-    if (!H || H->nlev < 2 || !H->dense) return false;
+    if (!H || H->nlev < 2 || !H->dense || h->O.smoother != RICH_SMOOTH_L1) return false;
     for (int l = 0; l < H->nlev - 1; l++) {
         if (H->L[l].prow) return false;
         if (l >= 1 && !H->L[l].rb) return false;
@@ -1077,6 +1089,7 @@ rich_status validate(const rich_problem_t *P, const rich_solver_opts_t *O) {
     if (O->aux_dflux != 0 && O->aux_dflux != 1) return RICH_EINVAL;
     if (O->amg_smoothed < 0 || O->amg_smoothed > 16) return RICH_EINVAL;
     if (O->tile_kz < 0 || O->tile_kz > 4096) return RICH_EINVAL;
+    if (O->smoother != RICH_SMOOTH_L1 && O->smoother != RICH_SMOOTH_MCGS) return RICH_EINVAL;
     if (!(O->gmres_reorth >= 0.0 && O->gmres_reorth < 1.0)) return RICH_EINVAL;
     if (!(O->eta > 0) || !(O->fnormtol > 0) || O->max_newton < 1 || O->msbset < 1) return RICH_EINVAL;
     return RICH_OK;
