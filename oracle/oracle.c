@@ -795,6 +795,76 @@ static void csr_free(orc_csr *A)
 }
 
 /* ------------------------------------------------------------------------ */
+/* Decoupled greedy aggregation: the DSVMB coarsening of Section 5.2 (the    */
+/* smoothed aggregation of Vanek, Mandel and Brezina, each process          */
+/* aggregating its own rows and ignoring couplings to other processes).     */
+/* Reading: the "processes" are consecutive blocks of `block` rows; j is     */
+/* strongly coupled to i when |a_ij| >= theta sqrt(a_ii a_jj) (j != i, same  */
+/* block).  Within a block, rows in index order:                            */
+/*  phase 1: a row whose strong neighbours are all unaggregated (and itself  */
+/*           too) starts an aggregate holding it and those neighbours;      */
+/*  phase 2: every row still free joins the phase-1 aggregate of its         */
+/*           strongest strong neighbour that phase 1 aggregated (ties: the   */
+/*           lowest index);                                                 */
+/*  phase 3: every row still free starts an aggregate holding it and its    */
+/*           strong neighbours that are still free.                         */
+/* Aggregates are numbered block by block in order of creation.  Returns    */
+/* the number of aggregates.                                                 */
+/* ------------------------------------------------------------------------ */
+int64_t orc_vmb_aggregate(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
+                          double theta, int64_t block, int32_t *agg)
+{
+    double *diag = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    int32_t *p1 = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    for (int64_t i = 0; i < n; i++) {
+        diag[i] = 0.0;
+        for (int64_t e = rowptr[i]; e < rowptr[i + 1]; e++)
+            if (col[e] == i) diag[i] = val[e];
+        agg[i] = -1;
+    }
+    int64_t nc = 0;
+    for (int64_t b0 = 0; b0 < n; b0 += block) {
+        int64_t b1 = b0 + block < n ? b0 + block : n;
+#define STRONG(i, e) (col[e] != (i) && col[e] >= b0 && col[e] < b1 && \
+                      fabs(val[e]) >= theta * sqrt(fabs(diag[i] * diag[col[e]])))
+        for (int64_t i = b0; i < b1; i++) { /* phase 1 */
+            int ok = agg[i] < 0;
+            for (int64_t e = rowptr[i]; ok && e < rowptr[i + 1]; e++)
+                if (STRONG(i, e) && agg[col[e]] >= 0) ok = 0;
+            if (!ok) continue;
+            agg[i] = (int32_t)nc;
+            for (int64_t e = rowptr[i]; e < rowptr[i + 1]; e++)
+                if (STRONG(i, e)) agg[col[e]] = (int32_t)nc;
+            nc++;
+        }
+        for (int64_t i = b0; i < b1; i++) p1[i] = agg[i];
+        for (int64_t i = b0; i < b1; i++) { /* phase 2 */
+            if (agg[i] >= 0) continue;
+            double best = -1.0;
+            for (int64_t e = rowptr[i]; e < rowptr[i + 1]; e++) {
+                if (!STRONG(i, e) || p1[col[e]] < 0) continue;
+                double s = fabs(val[e]) / sqrt(fabs(diag[i] * diag[col[e]]));
+                if (s > best) {
+                    best = s;
+                    agg[i] = p1[col[e]];
+                }
+            }
+        }
+        for (int64_t i = b0; i < b1; i++) { /* phase 3 */
+            if (agg[i] >= 0) continue;
+            agg[i] = (int32_t)nc;
+            for (int64_t e = rowptr[i]; e < rowptr[i + 1]; e++)
+                if (STRONG(i, e) && agg[col[e]] < 0) agg[col[e]] = (int32_t)nc;
+            nc++;
+        }
+#undef STRONG
+    }
+    free(diag);
+    free(p1);
+    return nc;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Multicolour Gauss-Seidel (the GPU form of the paper's hybrid Gauss-Seidel */
 /* smoother of Section 5.2 / Section 6).  Colouring: greedy in index order,  */
 /* colour(i) = the smallest colour no neighbour j < i has; on the 7-point    */
@@ -914,7 +984,20 @@ int orc_amg_build(const orc_opts *O, int64_t n, const int64_t *rowptr, const int
         int own = 0; /* whether cur is a temporary */
         int32_t *comp = (int32_t *)malloc((size_t)(H->A[l].n > 0 ? H->A[l].n : 1) * sizeof(int32_t));
         for (int64_t i = 0; i < H->A[l].n; i++) comp[i] = (int32_t)i;
-        for (int s = 0; s < O->amg_sweeps; s++) {
+        if (O->amg_aggregation == 1) {
+            const orc_csr *A = &H->A[l];
+            int64_t nc = orc_vmb_aggregate(A->n, A->rowptr, A->col, A->val, O->amg_theta, O->amg_block, comp);
+            if (nc == A->n) {
+                free(comp);
+                break;
+            }
+            cur.n = nc; /* only the size is used below */
+            cur.rowptr = NULL;
+            cur.col = NULL;
+            cur.val = NULL;
+            own = 1;
+        }
+        for (int s = 0; s < O->amg_sweeps && O->amg_aggregation != 1; s++) {
             int32_t *a = (int32_t *)malloc((size_t)(cur.n > 0 ? cur.n : 1) * sizeof(int32_t));
             int64_t nc = orc_match_sweep(cur.n, cur.rowptr, cur.col, cur.val, a);
             if (nc == cur.n) {

@@ -69,6 +69,9 @@ typedef struct {
     int amg_smoothed; /* levels (from the finest) with smoothed prolongators; 0: none */
     int smoother;     /* 0: l1-Jacobi on every level; 1: multicolour Gauss-Seidel on the finest
                          level (backward before, forward after the coarse correction) */
+    int amg_aggregation; /* 0: pairwise matching sweeps; 1: decoupled greedy (VMB) aggregation */
+    double amg_theta;    /* strength threshold of the greedy aggregation */
+    int64_t amg_block;   /* rows per decoupled block of the greedy aggregation */
 } orc_opts;
 
 typedef struct {
@@ -126,6 +129,10 @@ int64_t orc_rap_nnz(int64_t n, const int64_t *rowptr, const int32_t *col, int64_
 void orc_rap(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val, int64_t nc,
              const int64_t *prow, const int32_t *pcol, const double *pval, int64_t *crow,
              int32_t *ccol, double *cval);
+
+/* ---- decoupled greedy aggregation (Vanek-Mandel-Brezina) ---- */
+int64_t orc_vmb_aggregate(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
+                          double theta, int64_t block, int32_t *agg);
 
 /* ---- multicolour Gauss-Seidel ---- */
 int orc_greedy_colors(int64_t n, const int64_t *rowptr, const int32_t *col, int32_t *color);

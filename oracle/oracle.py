@@ -48,7 +48,8 @@ class COpts(C.Structure):
                 ("amg_max_levels", C.c_int), ("amg_coarse_size", C.c_int64),
                 ("amg_sweeps", C.c_int), ("coarse_dense_max", C.c_int64),
                 ("coarse_l1_sweeps", C.c_int), ("amg_refresh", C.c_int),
-                ("aux_dflux", C.c_int), ("amg_smoothed", C.c_int), ("smoother", C.c_int)]
+                ("aux_dflux", C.c_int), ("amg_smoothed", C.c_int), ("smoother", C.c_int),
+                ("amg_aggregation", C.c_int), ("amg_theta", C.c_double), ("amg_block", C.c_int64)]
 
 
 class CStats(C.Structure):
@@ -91,6 +92,8 @@ def lib():
         L.orc_rap_nnz.argtypes = [C.c_int64, i64, i32, C.c_int64, i64, i32]
         L.orc_rap_nnz.restype = C.c_int64
         L.orc_rap.argtypes = [C.c_int64, i64, i32, d, C.c_int64, i64, i32, d, i64, i32, d]
+        L.orc_vmb_aggregate.argtypes = [C.c_int64, i64, i32, d, C.c_double, C.c_int64, i32]
+        L.orc_vmb_aggregate.restype = C.c_int64
         L.orc_greedy_colors.argtypes = [C.c_int64, i64, i32, i32]
         L.orc_mcgs_sweep.argtypes = [C.c_int64, i64, i32, d, i32, C.c_int, C.c_int, d, d]
         L.orc_amg_prolongator_nnz.argtypes = [vp, C.c_int]
@@ -251,6 +254,14 @@ def smoothed_prolongator(A, agg, nc):
     omega = lib().orc_smoothed_prolongator(n, _i64(rp), _i32(col), _d(val), _i32(agg), nc, _i64(prow),
                                            _i32(pcol), _d(pval))
     return sp.csr_matrix((pval, pcol, prow), shape=(n, nc)), float(omega)
+
+
+def vmb_aggregate(A, theta, block):
+    """Decoupled greedy aggregation of A (blocks of `block` rows); returns (agg, number of aggregates)."""
+    rp, col, val = _csr_parts(A)
+    agg = np.empty(A.shape[0], np.int32)
+    nc = lib().orc_vmb_aggregate(A.shape[0], _i64(rp), _i32(col), _d(val), float(theta), int(block), _i32(agg))
+    return agg, int(nc)
 
 
 def greedy_colors(A):
