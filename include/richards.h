@@ -132,9 +132,25 @@ typedef struct rich_solver_opts {
                             correction, the GPU form of the hybrid backward/forward
                             Gauss-Seidel of the paper's experiments, Section 6); coarser
                             levels always take l1-Jacobi */
+    int amg_aggregation; /* RICH_AGG_MATCHING (pairwise matching sweeps, the default) or
+                            RICH_AGG_VMB: the DSVMB coarsening of Section 5.2, decoupled greedy
+                            aggregation (Vanek-Mandel-Brezina) in which every block of amg_block
+                            consecutive rows aggregates its own rows and ignores couplings that
+                            leave it; j is strongly coupled to i when |a_ij| >= amg_theta
+                            sqrt(|a_ii a_jj|); phase 1 roots (rows whose strong neighbours are
+                            all free) take their strong neighbourhood, phase 2 attaches each
+                            remaining row to its strongest phase-1 neighbour's aggregate,
+                            phase 3 groups what is left.  Combine with amg_smoothed for the
+                            smoothed prolongator. */
+    double amg_theta;    /* strength threshold of RICH_AGG_VMB, 0..1 (0: every coupling is strong;
+                            larger values stall the coarsening where the storage term theta'/dt
+                            dominates the diagonal) */
+    int64_t amg_block;   /* rows per decoupled block of RICH_AGG_VMB, >= 1 (4096) */
 } rich_solver_opts_t;
 #define RICH_SMOOTH_L1 0
 #define RICH_SMOOTH_MCGS 1
+#define RICH_AGG_MATCHING 0
+#define RICH_AGG_VMB 1
 
 /* Per-time-step counters and timings (host wall seconds of each phase). */
 typedef struct rich_step_stats {

@@ -48,7 +48,8 @@ class Opts(C.Structure):
                 ("amg_sweeps", C.c_int), ("coarse_dense_max", C.c_int64),
                 ("coarse_l1_sweeps", C.c_int), ("precision", C.c_int), ("gmres_reorth", C.c_double),
                 ("aux_dflux", C.c_int), ("amg_refresh", C.c_int), ("amg_smoothed", C.c_int),
-                ("tile_kz", C.c_int), ("smoother", C.c_int)]
+                ("tile_kz", C.c_int), ("smoother", C.c_int), ("amg_aggregation", C.c_int),
+                ("amg_theta", C.c_double), ("amg_block", C.c_int64)]
 
 
 class StepStats(C.Structure):

@@ -118,6 +118,80 @@ __global__ void k_number(int64_t n, const int32_t *__restrict__ mate, const int6
     agg[i] = (int32_t)((m < 0 || i < m) ? id[i] : id[m]);
 }
 
+// ------------------------------------- decoupled greedy (VMB) aggregation
+// DSVMB coarsening (Section 5.2): each block of `block` consecutive rows (a
+// "process") aggregates its own rows, ignoring couplings that leave the block,
+// so the blocks are independent: one thread per block runs the three greedy
+// phases over its rows in index order.  j is strongly coupled to i when
+// |a_ij| >= theta sqrt(|a_ii a_jj|).  Phase 1: a free row whose strong
+// neighbours are all free starts an aggregate with them; phase 2: a free row
+// joins the phase-1 aggregate of its strongest strong neighbour aggregated in
+// phase 1 (first in column order on ties); phase 3: a free row starts an
+// aggregate with its free strong neighbours.  Ids are block-local here and
+// offset by the aggregates of the earlier blocks afterwards.
+__global__ void k_row_diag(int64_t n, const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+                           const double *__restrict__ val, double *__restrict__ diag) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double d = 0.0;
+    for (int64_t e = rowptr[i]; e < rowptr[i + 1]; e++)
+        if (col[e] == i) d = val[e];
+    diag[i] = d;
+}
+
+__global__ void k_vmb_block(int64_t n, int64_t block, int64_t nblk, const int64_t *__restrict__ rowptr,
+                            const int32_t *__restrict__ col, const double *__restrict__ val,
+                            const double *__restrict__ diag, double theta, int32_t *__restrict__ agg,
+                            int32_t *__restrict__ p1, int64_t *__restrict__ count) {
+#pragma clang fp contract(off)
+    int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nblk) return;
+    const int64_t b0 = b * block, b1 = b0 + block < n ? b0 + block : n;
+    auto strong = [&](int64_t i, int64_t e) {
+        int64_t j = col[e];
+        return j != i && j >= b0 && j < b1 && fabs(val[e]) >= theta * sqrt(fabs(diag[i] * diag[j]));
+    };
+    int32_t nc = 0;
+    for (int64_t i = b0; i < b1; i++) agg[i] = -1;
+    for (int64_t i = b0; i < b1; i++) {  // phase 1
+        bool ok = agg[i] < 0;
+        for (int64_t e = rowptr[i]; ok && e < rowptr[i + 1]; e++)
+            if (strong(i, e) && agg[col[e]] >= 0) ok = false;
+        if (!ok) continue;
+        agg[i] = nc;
+        for (int64_t e = rowptr[i]; e < rowptr[i + 1]; e++)
+            if (strong(i, e)) agg[col[e]] = nc;
+        nc++;
+    }
+    for (int64_t i = b0; i < b1; i++) p1[i] = agg[i];
+    for (int64_t i = b0; i < b1; i++) {  // phase 2
+        if (agg[i] >= 0) continue;
+        double best = -1.0;
+        for (int64_t e = rowptr[i]; e < rowptr[i + 1]; e++) {
+            if (!strong(i, e) || p1[col[e]] < 0) continue;
+            double sv = fabs(val[e]) / sqrt(fabs(diag[i] * diag[col[e]]));
+            if (sv > best) {
+                best = sv;
+                agg[i] = p1[col[e]];
+            }
+        }
+    }
+    for (int64_t i = b0; i < b1; i++) {  // phase 3
+        if (agg[i] >= 0) continue;
+        agg[i] = nc;
+        for (int64_t e = rowptr[i]; e < rowptr[i + 1]; e++)
+            if (strong(i, e) && agg[col[e]] < 0) agg[col[e]] = nc;
+        nc++;
+    }
+    count[b] = nc;
+}
+
+__global__ void k_vmb_offset(int64_t n, int64_t block, const int64_t *__restrict__ off, int32_t *__restrict__ agg) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    agg[i] += (int32_t)off[i / block];
+}
+
 // ---------------------------------------------------------------- Galerkin
 __global__ void k_count_members(int64_t n, const int32_t *__restrict__ agg, int64_t *__restrict__ cnt) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -698,6 +772,34 @@ rich_status match_sweep(int64_t n, const int64_t *rowptr, const int32_t *col, co
     HIP_TRY(hipMemcpyAsync(&nc, id + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     *nc_out = nc;
+    return RICH_OK;
+}
+
+rich_status vmb_aggregate(const CsrDev &A, double theta, int64_t block, int32_t *agg, int64_t *nc_out,
+                          hipStream_t s) {
+    *nc_out = 0;
+    if (A.n == 0) return RICH_OK;
+    const int64_t nblk = (A.n + block - 1) / block;
+    DevAlloc tmp;
+    double *diag;
+    int32_t *p1;
+    int64_t *cnt, *off, *stmp;
+    RICH_TRY(tmp.get(&diag, A.n));
+    RICH_TRY(tmp.get(&p1, A.n));
+    RICH_TRY(tmp.get(&cnt, nblk + 1));
+    RICH_TRY(tmp.get(&off, nblk + 1));
+    RICH_TRY(tmp.get(&stmp, scan_tmp_size(nblk + 1)));
+    k_row_diag<<<nblocks(A.n), TPB, 0, s>>>(A.n, A.rowptr, A.col, A.val, diag);
+    LAUNCH_CHECK();
+    HIP_TRY(hipMemsetAsync(cnt, 0, (nblk + 1) * sizeof(int64_t), s));
+    k_vmb_block<<<(unsigned)((nblk + 63) / 64), 64, 0, s>>>(A.n, block, nblk, A.rowptr, A.col, A.val, diag, theta,
+                                                             agg, p1, cnt);
+    LAUNCH_CHECK();
+    RICH_TRY(scan_exclusive_i64(cnt, off, nblk + 1, stmp, s));  // off[nblk] = total
+    k_vmb_offset<<<nblocks(A.n), TPB, 0, s>>>(A.n, block, off, agg);
+    LAUNCH_CHECK();
+    HIP_TRY(hipMemcpyAsync(nc_out, off + nblk, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));  // tmp is freed on return
     return RICH_OK;
 }
 

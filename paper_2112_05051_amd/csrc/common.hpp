@@ -334,6 +334,9 @@ rich_status csr_invd(const CsrDev &A, double *invd, float *invdf, hipStream_t s)
 int64_t dense_inverse_ws(int64_t n);
 rich_status dense_inverse(const CsrDev &A, double *D, double *ws, hipStream_t s);
 rich_status compose_agg(int32_t *comp, const int32_t *a, int64_t n, hipStream_t s);
+// Decoupled greedy aggregation of A over blocks of `block` rows (strength
+// threshold theta); agg (n) receives aggregate ids, *nc their number.
+rich_status vmb_aggregate(const CsrDev &A, double theta, int64_t block, int32_t *agg, int64_t *nc, hipStream_t s);
 
 // r = b - A x0 (x0 = D^{-1} b, the pre-smoothed iterate from zero, stored by the restriction)
 template <class TB, class T>

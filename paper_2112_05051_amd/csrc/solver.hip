@@ -208,7 +208,12 @@ rich_status build_hierarchy(rich_ctx *h) {
         int32_t *comp;
         RICH_TRY(H.mem.get(&comp, levA.n));
         RICH_TRY(compose_agg(comp, nullptr, levA.n, s));
-        for (int sw = 0; sw < h->O.amg_sweeps; sw++) {
+        int64_t nc_vmb = levA.n;
+        if (h->O.amg_aggregation == RICH_AGG_VMB) {
+            RICH_TRY(vmb_aggregate(levA, h->O.amg_theta, h->O.amg_block, comp, &nc_vmb, s));
+            own = nc_vmb < levA.n;
+        }
+        for (int sw = 0; sw < h->O.amg_sweeps && h->O.amg_aggregation == RICH_AGG_MATCHING; sw++) {
             DevAlloc *am = new DevAlloc();
             int32_t *a;
             rich_status st = am->get(&a, cur.n);
@@ -243,7 +248,7 @@ rich_status build_hierarchy(rich_ctx *h) {
             H.mem.release(comp);
             break;
         }
-        int64_t nc = cur.n;
+        int64_t nc = h->O.amg_aggregation == RICH_AGG_VMB ? nc_vmb : cur.n;
         delete cur_mem;  // the pairwise products served the matching only
         // a level that keeps more than half of the rows is not worth its cost
         // once the current level fits the dense coarsest solver: stop here
@@ -1090,6 +1095,9 @@ rich_status validate(const rich_problem_t *P, const rich_solver_opts_t *O) {
     if (O->amg_smoothed < 0 || O->amg_smoothed > 16) return RICH_EINVAL;
     if (O->tile_kz < 0 || O->tile_kz > 4096) return RICH_EINVAL;
     if (O->smoother != RICH_SMOOTH_L1 && O->smoother != RICH_SMOOTH_MCGS) return RICH_EINVAL;
+    if (O->amg_aggregation != RICH_AGG_MATCHING && O->amg_aggregation != RICH_AGG_VMB) return RICH_EINVAL;
+    if (O->amg_aggregation == RICH_AGG_VMB && (!(O->amg_theta >= 0.0 && O->amg_theta <= 1.0) || O->amg_block < 1))
+        return RICH_EINVAL;
     if (!(O->gmres_reorth >= 0.0 && O->gmres_reorth < 1.0)) return RICH_EINVAL;
     if (!(O->eta > 0) || !(O->fnormtol > 0) || O->max_newton < 1 || O->msbset < 1) return RICH_EINVAL;
     return RICH_OK;

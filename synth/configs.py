@@ -86,7 +86,7 @@ class Options:
     tile_kz: int = 0                    # planes per block of the tiled fine-level smoother (0: automatic)
     smoother: int = 0                   # 0: l1-Jacobi; 1: multicolour Gauss-Seidel on the finest level
     amg_aggregation: int = 0            # 0: pairwise matching sweeps; 1: decoupled greedy (VMB) aggregation
-    amg_theta: float = 0.01             # strength threshold of the greedy aggregation
+    amg_theta: float = 0.0              # strength threshold of the greedy aggregation (0: every coupling)
     amg_block: int = 4096               # rows per decoupled block of the greedy aggregation
 
 

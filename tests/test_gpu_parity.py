@@ -396,3 +396,62 @@ def test_full_steps_gauss_seidel(rich, torch, orc, precision, tol):
         pg = s.get_state().cpu().numpy()
         err = np.linalg.norm(pg - po) / np.linalg.norm(po)
         assert err <= tol, (step, err, sg, so)
+
+
+@pytest.mark.parametrize("block,smoothed", [(4096, 0), (997, 0), (4096, 16)])
+@pytest.mark.parametrize("mean", [synth.ARITH, synth.UPSTREAM])
+def test_vmb_hierarchy_bitexact(rich, torch, orc, mean, block, smoothed):
+    """Decoupled greedy aggregation (amg_aggregation = 1): the GPU's aggregates
+    on every level equal the oracle's bit for bit (a ragged last block when the
+    block size does not divide the rows), coarse matrices and smoothed
+    prolongators as for matching, and one V-cycle agrees."""
+    P = box_problem(37, 29, 23, mean=mean, dt=10.0)
+    n = P.n
+    ks = random_ks(P, 81)
+    p = random_heads(n, 82, -70, -30)
+    opts = synth.Options(amg_aggregation=1, amg_block=block, amg_smoothed=smoothed, amg_coarse_size=200,
+                         coarse_dense_max=600)
+    s = make_solver(rich, torch, P, ks, opts)
+    s.assemble(dev(torch, p))
+    rp, col, val = s.export_csr(rich.WHICH_A, 0)
+    amg = orc.AMG(opts, sp.csr_matrix((val, col, rp), shape=(n, n)))
+    assert s.levels() == amg.levels >= 3
+    for l in range(amg.levels):
+        Ao, aggo = amg.level(l)
+        rp, col, val = s.export_csr(rich.WHICH_A, l)
+        csr_close(rp, col, val, Ao, 1e-12)
+        if l < amg.levels - 1:
+            agg_g, nc = s.export_aggregates(l)
+            assert np.array_equal(agg_g, aggo)
+            assert nc == int(aggo.max()) + 1
+            if l < smoothed:
+                prp, pcol, pval = s.export_csr(rich.WHICH_P, l)
+                Po = amg.prolongator(l)
+                assert np.array_equal(prp, Po.indptr) and np.array_equal(pcol, Po.indices)
+    b = np.random.default_rng(83).standard_normal(n)
+    xg = s.apply_prec(dev(torch, b)).cpu().numpy()
+    xo = amg.apply(b)
+    assert np.linalg.norm(xg - xo) <= 1e-10 * np.linalg.norm(xo)
+
+
+@pytest.mark.parametrize("precision,tol", [(synth.FP64, 1e-8), (synth.MIXED, 1e-6)])
+def test_full_steps_vmb(rich, torch, orc, precision, tol):
+    r = smooth_recipe("c3", 24)
+    r.options.amg_aggregation = 1
+    r.options.amg_smoothed = 16
+    r.options.precision = precision
+    if precision == synth.FP64:
+        r.options.fnormtol = 1e-12
+    P = r.problem
+    ks, p = r.ks(), r.p0()
+    s = make_solver(rich, torch, P, ks, r.options)
+    s.set_state(dev(torch, p))
+    o = orc.Solver(P, r.options, ks)
+    po = p.copy()
+    for step in range(2):
+        sg = s.step(1)[0]
+        so = o.step(po)
+        assert sg["status"] == 0 and so["status"] == 0
+        pg = s.get_state().cpu().numpy()
+        err = np.linalg.norm(pg - po) / np.linalg.norm(po)
+        assert err <= tol, (step, err, sg, so)
