@@ -438,8 +438,9 @@ __device__ __forceinline__ void csr_stream_body(const int64_t *__restrict__ rb, 
 #pragma unroll
     for (int q = 0; q < PER; q++) {
         int64_t e = e0 + threadIdx.x + 256 * q;
-        cj[q] = e < e1 ? col[e] : 0;
-        vv[q] = e < e1 ? val[e] : (T)0;
+        // the matrix entries are read once per sweep: streamed past the caches
+        cj[q] = e < e1 ? __builtin_nontemporal_load(col + e) : 0;
+        vv[q] = e < e1 ? __builtin_nontemporal_load(val + e) : (T)0;
     }
     T xs[PER];
 #pragma unroll

@@ -438,10 +438,12 @@ __device__ __forceinline__ void st25_body(const G &P, const T *__restrict__ M4, 
     auto load_plane = [&](uint32_t cc, T &md, T &mxp, T &myp, T &mzp, T &hxp, T &hyp, St25In<T> &hxi,
                           St25In<T> &hyi) {
         if (inside) {
-            md = M4[(size_t)M_D * n + cc];
-            mxp = M4[(size_t)M_XP * n + cc];
-            myp = M4[(size_t)M_YP * n + cc];
-            mzp = M4[(size_t)M_ZP * n + cc];
+            // a cell's own coefficients are read once: streamed past the caches
+            // (the halo couplings below are shared with the neighbouring tiles)
+            md = __builtin_nontemporal_load(M4 + (size_t)M_D * n + cc);
+            mxp = __builtin_nontemporal_load(M4 + (size_t)M_XP * n + cc);
+            myp = __builtin_nontemporal_load(M4 + (size_t)M_YP * n + cc);
+            mzp = __builtin_nontemporal_load(M4 + (size_t)M_ZP * n + cc);
         }
         if (hx) {
             hxi = load_in(cc + hxo);
