@@ -503,23 +503,46 @@ __global__ void k_max_rowlen(int64_t n, const int64_t *__restrict__ rowptr, int 
 
 // bc[I] = sum over the members of I (ascending) of r
 // (and x0c[I] = D_c^{-1} bc[I], the coarse pre-smoothed iterate, when x0c is set)
+// A block of RESTRICT_TPB threads takes RESTRICT_TPB consecutive coarse rows:
+// their member lists are one contiguous stretch of mem, which the block reads
+// with coalesced loads, gathering the r values into LDS in member order; each
+// thread then adds its row's values in that order (the same sums as a thread
+// walking its list alone).  A stretch longer than the LDS falls back to the
+// per-thread walk.
+constexpr int RESTRICT_TPB = 256, RESTRICT_LDS = 2048;
 template <class T>
-__device__ __forceinline__ void restrict_at(int64_t nc, const int64_t *__restrict__ mptr,
-                                            const int32_t *__restrict__ mem, const T *__restrict__ r,
-                                            T *__restrict__ bc, const T *__restrict__ invdc, T *__restrict__ x0c,
-                                            int64_t I) {
+__device__ __forceinline__ void restrict_block(int64_t nc, const int64_t *__restrict__ mptr,
+                                               const int32_t *__restrict__ mem, const T *__restrict__ r,
+                                               T *__restrict__ bc, const T *__restrict__ invdc,
+                                               T *__restrict__ x0c, int64_t blk) {
+    __shared__ T rv[RESTRICT_LDS];
+    const int64_t I0 = blk * RESTRICT_TPB;
+    if (I0 >= nc) return;
+    const int64_t I1 = I0 + RESTRICT_TPB < nc ? I0 + RESTRICT_TPB : nc;
+    const int64_t I = I0 + threadIdx.x;
+    const int64_t t0 = mptr[I0], t1 = mptr[I1];
+    const bool staged = t1 - t0 <= RESTRICT_LDS;
+    if (staged) {
+        for (int64_t t = t0 + threadIdx.x; t < t1; t += RESTRICT_TPB) rv[t - t0] = r[mem[t]];
+        __syncthreads();
+    }
     if (I >= nc) return;
+    const int64_t a = mptr[I], e = mptr[I + 1];
     T s = 0;
-    for (int64_t t = mptr[I]; t < mptr[I + 1]; t++) s += r[mem[t]];
+    if (staged)
+        for (int64_t t = a; t < e; t++) s += rv[t - t0];
+    else
+        for (int64_t t = a; t < e; t++) s += r[mem[t]];
     bc[I] = s;
     if (x0c) x0c[I] = s * invdc[I];
 }
 
 template <class T>
-__global__ void k_restrict(int64_t nc, const int64_t *__restrict__ mptr, const int32_t *__restrict__ mem,
-                           const T *__restrict__ r, T *__restrict__ bc, const T *__restrict__ invdc,
-                           T *__restrict__ x0c) {
-    restrict_at(nc, mptr, mem, r, bc, invdc, x0c, (int64_t)xcd_block() * blockDim.x + threadIdx.x);
+__global__ void __launch_bounds__(RESTRICT_TPB) k_restrict(int64_t nc, const int64_t *__restrict__ mptr,
+                                                           const int32_t *__restrict__ mem, const T *__restrict__ r,
+                                                           T *__restrict__ bc, const T *__restrict__ invdc,
+                                                           T *__restrict__ x0c) {
+    restrict_block(nc, mptr, mem, r, bc, invdc, x0c, xcd_block());
 }
 
 // x = Ainv b, one wavefront per row (row-major Ainv)
@@ -567,7 +590,7 @@ __global__ void k_coarse_batch(Batch<CoarseArgs<T>> B) {
     const int e = batch_entry(B, L);
     const CoarseArgs<T> &a = B.a[e];
     const int64_t blk = (int64_t)(L - B.begin[e]);
-    if (MODE == 0) restrict_at(a.n, a.mptr, a.mem, a.b, a.out, a.invd, a.x0c, blk * blockDim.x + threadIdx.x);
+    if (MODE == 0) restrict_block(a.n, a.mptr, a.mem, a.b, a.out, a.invd, a.x0c, blk);
     if (MODE == 1) csr_prolong_at(a.n, a.b, a.v, a.agg, a.out, blk * blockDim.x + threadIdx.x);
     if (MODE == 2) dense_gemv_at(a.val, a.b, a.out, a.n, blk);
 }
@@ -1016,7 +1039,7 @@ template <class T>
 rich_status launch_restrict(const Level &Lv, const T *r, T *bc, int64_t nc, const T *invdc, T *x0c, hipStream_t s) {
     if (nc == 0) return RICH_OK;
     if (Lv.prow) return launch_sa_restrict<T>(Lv, r, bc, nc, invdc, x0c, s);
-    k_restrict<T><<<xcd_grid(nc, TPB), TPB, 0, s>>>(nc, Lv.mptr, Lv.mem, r, bc, invdc, x0c);
+    k_restrict<T><<<xcd_grid(nc, RESTRICT_TPB), RESTRICT_TPB, 0, s>>>(nc, Lv.mptr, Lv.mem, r, bc, invdc, x0c);
     LAUNCH_CHECK();
     return RICH_OK;
 }
