@@ -100,6 +100,31 @@ def test_fused_fp64():
     srv.close()
 
 
+def test_fused_mixed_hierarchies():
+    """Same-size simulations whose hierarchies differ share a batcher: a
+    smoothed-prolongator one (not batchable: it launches on its own stream), a
+    greedy-aggregation one (large aggregates: the restriction's unstaged path)
+    and plain ones; every result equals its lone run bit for bit."""
+    import torch
+
+    import paper_2112_05051_amd as rich
+    reqs = []
+    for seed, tweak in ((31, {}), (32, {"amg_smoothed": 1}), (33, {"amg_aggregation": 1}), (34, {})):
+        rec = synth.serving_stream(count=1, seed=seed, sizes=(20,), nsteps=2)[0][1]
+        rec.problem.mean = synth.UPSTREAM
+        rec.options.max_newton = 40
+        for k, v in tweak.items():
+            setattr(rec.options, k, v)
+        reqs.append(rec)
+    srv = rich.Server(8 << 30, 4, fused=True)
+    ids = [srv.submit(rec.problem, rec.options, rec.ks(), rec.p0(), rec.nsteps) for rec in reqs]
+    srv.wait_idle()
+    flushes, products = srv.batch_stats()
+    assert flushes > 0
+    check_alone_equals_mix(rich, torch, srv, reqs, ids)
+    srv.close()
+
+
 def test_budget_serialises_but_completes():
     import paper_2112_05051_amd as rich
     reqs = small_requests(count=4, steps=2, seed=8, sizes=(14,))
