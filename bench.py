@@ -344,7 +344,7 @@ def main():
         print(pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.n ** 3, digests))
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: the solver runs on one GPU; --gpus {args.gpus} is not supported "
               f"(how the path would shard is a design note, not an implementation)", file=sys.stderr)
         sys.exit(2)
 
