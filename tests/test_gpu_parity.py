@@ -455,3 +455,27 @@ def test_full_steps_vmb(rich, torch, orc, precision, tol):
         pg = s.get_state().cpu().numpy()
         err = np.linalg.norm(pg - po) / np.linalg.norm(po)
         assert err <= tol, (step, err, sg, so)
+
+
+@pytest.mark.parametrize("shape,dense_max", [((1, 1, 1), 4096), ((1, 1, 40), 4096), ((1, 1, 40), 0),
+                                             ((3, 2, 1), 4096)])
+def test_degenerate_grids_steps(rich, torch, orc, shape, dense_max):
+    """A single cell, a vertical column and a flat slab: one-level hierarchies
+    (dense direct solve, or l1 sweeps when the dense solve is off) through two
+    backward-Euler steps, against the oracle."""
+    P = box_problem(*shape, mean=synth.UPSTREAM, dt=5.0)
+    opts = synth.Options(precision=synth.FP64, fnormtol=1e-12, coarse_dense_max=dense_max, coarse_l1_sweeps=8,
+                         gmres_maxit=400)
+    ks = random_ks(P, 91) if P.n > 1 else np.full(1, synth.KS0)
+    p = np.full(P.n, synth.P_INIT)
+    s = make_solver(rich, torch, P, ks, opts)
+    s.set_state(dev(torch, p))
+    o = orc.Solver(P, opts, ks)
+    po = p.copy()
+    for step in range(2):
+        sg = s.step(1)[0]
+        so = o.step(po)
+        assert sg["status"] == 0 and so["status"] == 0, (sg, so)
+        pg = s.get_state().cpu().numpy()
+        assert np.linalg.norm(pg - po) <= 1e-8 * np.linalg.norm(po), (step, pg[:4], po[:4])
+    assert s.levels() == 1
