@@ -2,6 +2,8 @@
 // matrix assembly, 7-point stencil products and the fine-level pieces of the
 // AMG V-cycle.  One thread per cell, x-fastest cell order, SoA coefficient
 // arrays (every load and store of a wavefront is one contiguous run).
+#include <algorithm>
+
 #include "common.hpp"
 
 namespace rich {
@@ -579,12 +581,15 @@ __global__ void k_spmv_J_batch(Batch<SpmvArgs<TX>> B) {
 
 // The 64-wide tile needs rows of at least about that length to keep its lanes busy.
 inline bool use25(const Phys &P) { return P.nx >= 48 && P.ny >= T25Y && P.nz >= 4; }
+// Planes per block: the fewest chunks of at most 16 planes that give at least
+// ST25_MIN_BLOCKS blocks, with the planes spread evenly over the chunks (a
+// short last chunk leaves its blocks' share of the sweep idle).
 inline int kz25(const Phys &P) {
     if (P.tile_kz > 0) return P.tile_kz < P.nz ? P.tile_kz : P.nz;
     int64_t tiles = (int64_t)((P.nx + T25X - 1) / T25X) * ((P.ny + T25Y - 1) / T25Y);
-    int kz = 16;
-    while (kz > 1 && tiles * ((P.nz + kz - 1) / kz) < ST25_MIN_BLOCKS) kz /= 2;
-    return kz;
+    int64_t chunks = std::max<int64_t>((ST25_MIN_BLOCKS + tiles - 1) / tiles, (P.nz + 15) / 16);
+    chunks = std::min<int64_t>(chunks, P.nz);
+    return (int)((P.nz + chunks - 1) / chunks);
 }
 inline int64_t tiles25(const Phys &P, int kz) {
     return (int64_t)((P.nx + T25X - 1) / T25X) * ((P.ny + T25Y - 1) / T25Y) * ((P.nz + kz - 1) / kz);
