@@ -685,6 +685,9 @@ rich_status add_z(rich_ctx *h, double *x) {
 // Arnoldi step needs no host value: the host enqueues iteration j+1 before it
 // reads iteration j's Hessenberg column, and only a (rare) second
 // Gram-Schmidt pass makes it wait and redo the speculative step.
+constexpr double GMRES_SPEC_MARGIN = 4.0;
+constexpr int64_t GMRES_SPEC_MIN_ROWS = (int64_t)1 << 21;
+
 rich_status gmres(rich_ctx *h, const double *b, double *x, int *its_out, double *relres_out, bool *conv_out) {
     int64_t N = h->N, ld = h->ldv;
     int m = h->m;
@@ -751,8 +754,19 @@ rich_status gmres(rich_ctx *h, const double *b, double *x, int *its_out, double 
                 RICH_TRY(enqueue(j));
                 queued = j;
             }
-            if (j + 1 < m && total + 1 < h->O.gmres_maxit && queued < j + 1) {
-                RICH_TRY(enqueue(j + 1));  // speculative: needs nothing from the host
+            // Step j + 1 is queued before step j is read back (it needs nothing
+            // from the host), unless, on a grid large enough that an iteration
+            // costs far more than a host round trip, the residual estimate
+            // extrapolated with the last reduction factor says step j is about
+            // to meet the tolerance: a speculative step past convergence is a
+            // whole wasted iteration, a missed one only a round trip.
+            bool speculate = true;
+            if (N >= GMRES_SPEC_MIN_ROWS && j >= 1 && g[j - 1] != 0.0) {
+                const double pred = std::fabs(g[j]) * (std::fabs(g[j]) / std::fabs(g[j - 1]));
+                speculate = pred > GMRES_SPEC_MARGIN * eta * bnorm;
+            }
+            if (speculate && j + 1 < m && total + 1 < h->O.gmres_maxit && queued < j + 1) {
+                RICH_TRY(enqueue(j + 1));
                 queued = j + 1;
             }
             HIP_TRY(hipEventSynchronize(h->iter_ev[j]));
