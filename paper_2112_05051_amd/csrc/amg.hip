@@ -552,8 +552,18 @@ __device__ __forceinline__ void dense_gemv_at(const T *__restrict__ Ainv, const 
     int64_t row = (blk * blockDim.x + threadIdx.x) / 64;
     int lane = threadIdx.x % 64;
     if (row >= n) return;
-    T s = 0;
-    for (int64_t j = lane; j < n; j += 64) s += Ainv[row * n + j] * (T)b[j];
+    // four independent partial sums per lane keep four row segments in flight
+    const T *__restrict__ a = Ainv + row * n;
+    T s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+    int64_t j = lane;
+    for (; j + 192 < n; j += 256) {
+        s0 += a[j] * (T)b[j];
+        s1 += a[j + 64] * (T)b[j + 64];
+        s2 += a[j + 128] * (T)b[j + 128];
+        s3 += a[j + 192] * (T)b[j + 192];
+    }
+    for (; j < n; j += 64) s0 += a[j] * (T)b[j];
+    T s = (s0 + s1) + (s2 + s3);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
     if (lane == 0) x[row] = s;
