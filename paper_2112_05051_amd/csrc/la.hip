@@ -136,11 +136,12 @@ __global__ void __launch_bounds__(RED_THREADS) k_update_norm(const double *__res
     for (int i = 0; i < K; i++) hr[i] = h[i] * vs[i];
     double acc = 0.0;
     const int64_t n2 = n >> 1;
-    // streaming loads and stores: nothing here is re-read before it leaves the caches
+    // the basis is streamed past the caches; w, the next basis vector, is
+    // kept cacheable (the V-cycle reads it next)
     typedef double d2v __attribute__((ext_vector_type(2)));
     d2v *__restrict__ w2 = reinterpret_cast<d2v *>(w);
     for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n2; c += (int64_t)gridDim.x * blockDim.x) {
-        d2v wc = __builtin_nontemporal_load(w2 + c);
+        d2v wc = w2[c];
         d2v v[K];
 #pragma unroll
         for (int i = 0; i < K; i++) v[i] = __builtin_nontemporal_load(reinterpret_cast<const d2v *>(V + (size_t)i * ldv) + c);
@@ -149,7 +150,7 @@ __global__ void __launch_bounds__(RED_THREADS) k_update_norm(const double *__res
             wc.x -= hr[i] * v[i].x;
             wc.y -= hr[i] * v[i].y;
         }
-        __builtin_nontemporal_store(wc, w2 + c);
+        w2[c] = wc;  // the next basis vector: read again at once by the V-cycle
         acc += wc.x * wc.x + wc.y * wc.y;
     }
 
