@@ -523,7 +523,8 @@ __device__ __forceinline__ void restrict_block(int64_t nc, const int64_t *__rest
     const int64_t t0 = mptr[I0], t1 = mptr[I1];
     const bool staged = t1 - t0 <= RESTRICT_LDS;
     if (staged) {
-        for (int64_t t = t0 + threadIdx.x; t < t1; t += RESTRICT_TPB) rv[t - t0] = r[mem[t]];
+        // the member lists are read once per cycle: streamed past the caches
+        for (int64_t t = t0 + threadIdx.x; t < t1; t += RESTRICT_TPB) rv[t - t0] = r[__builtin_nontemporal_load(mem + t)];
         __syncthreads();
     }
     if (I >= nc) return;
