@@ -475,13 +475,13 @@ rich_status spmv_J_z(rich_ctx *h, double *y) {
 // batch on the batcher's stream once every attached simulation that is inside
 // a GMRES solve has posted, or once the oldest post has waited BATCH_WINDOW_S
 // (a simulation busy elsewhere holds no one up for longer), then gathers the
-// next batch.  A batch is one launch
-// per kernel and V-cycle level: the fine smoother, restriction, coarse
-// smoothers, coarsest product, prolongations and the J SpMV each cover every
-// simulation in it.  Each simulation's stream waits for its inputs before and
-// for the batch after.  Every block runs the code of the lone launch on its
-// own simulation's data, so a simulation's results are the same alone and in
-// a batch.
+// next batch.  A batch is one launch per kernel and V-cycle level: the fine
+// smoother, restriction, coarse smoothers, coarsest product, prolongations and
+// the J SpMV each cover every simulation in it.  Each simulation's stream
+// waits for its inputs before and for the batch after.  Every block runs the
+// code of the lone launch on its own simulation's data, so a simulation's
+// results are the same alone and in a batch.  An error while issuing a batch
+// is returned to every product posted from then on.
 constexpr double BATCH_WINDOW_S = 100e-6;
 
 struct BatchReq {
