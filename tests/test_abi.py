@@ -76,3 +76,35 @@ def test_server_rejects_over_budget_without_gpu():
         srv.submit(rec.problem, rec.options, rec.ks(), rec.p0(), 1)
     assert e.value.status == -3
     srv.close()
+
+
+def test_option_domains_without_gpu():
+    """The smoother, aggregation and strength options are checked on the host."""
+    import ctypes as C
+
+    import paper_2112_05051_amd as rich
+    from paper_2112_05051_amd import _lib
+    import synth
+    lib = rich.load()
+    P = synth.cube_problem(8, synth.ARITH, 1.0)
+    b = C.c_size_t()
+    for kw, ok in (({"smoother": 1}, True), ({"smoother": 2}, False), ({"amg_aggregation": 1}, True),
+                   ({"amg_aggregation": 2}, False), ({"amg_aggregation": 1, "amg_theta": 1.5}, False),
+                   ({"amg_aggregation": 1, "amg_block": 0}, False), ({"amg_aggregation": 1, "amg_theta": 0.25}, True)):
+        O = synth.Options(**kw)
+        rc = lib.rich_query_bytes(C.byref(_lib.make_problem(P)), C.byref(_lib.make_opts(O)), C.byref(b))
+        assert (rc == 0) == ok, (kw, rc)
+
+
+def test_server_batching_set_only_before_submissions():
+    import numpy as np
+
+    import paper_2112_05051_amd as rich
+    import synth
+    lib = rich.load()
+    srv = rich.Server(1 << 30, 1, fused=True)
+    rec = synth.recipe("c1", n=6)
+    srv.submit(rec.problem, rec.options, rec.ks(), rec.p0(), 1)
+    assert lib.rich_server_set_batching(srv._s, 0) == -11  # RICH_ESTATE
+    assert srv.batch_stats() == (0, 0)
+    srv.close()
