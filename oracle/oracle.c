@@ -12,7 +12,10 @@
  * the hydrostatic steady state and closed-form spectra (tests/test_oracle_*).
  * Matching is pinned by brute force on tiny graphs, the V-cycle by the
  * recursion of Section 5.2 written as dense matrices, GMRES by finite
- * termination.  The Newton / line-search control flow (orc_solver_step) is
+ * termination; the smoothed prolongator by the 1-D hat functions; the
+ * multicolour Gauss-Seidel sweeps by triangular solves in the colour-sorted
+ * ordering; the greedy aggregation by hand-worked 1-D and 2-D cases and its
+ * invariants.  The Newton / line-search control flow (orc_solver_step) is
  * pinned only through invariants (Armijo inequality at every accepted step,
  * convergence to the residual tolerance, mass balance): its iteration counts
  * are "parity unpinned" against the paper, whose workload differs.
