@@ -1,5 +1,6 @@
-"""The two benchmark-size workloads on the GPU, through the C-ABI, in the
-launch configuration the benchmark uses (the recipes' own grids and options).
+"""The benchmark-size workloads on the GPU, through the C-ABI, in the launch
+configuration the benchmark uses (the recipes' own grids and options): the
+128^3 and 256^3 cubes and the paper's 3-D test at its full 798 x 798 x 38.
 
 At these sizes the oracle cannot run the solver in seconds, so the tests check
 what it can compute directly: theta and Phi element by element on the full
@@ -85,4 +86,28 @@ def test_full_size_hierarchy_c2(rich, torch, orc):
     A1 = orc.galerkin(M, agg_o.astype(np.int32), nc_o)
     rp1, col1, val1 = s.export_csr(rich.WHICH_A, 1)
     csr_close(rp1, col1, val1, A1, 1e-12)
+    s.close()
+
+
+def test_paper_3d_full_size_step(rich, torch, orc):
+    """The paper's 3-D infiltration test at its real size (24.2 M unknowns,
+    the zero-head patch on the top face): theta and Phi on the full fields, and
+    the oracle's residual at the GPU's state after the first step."""
+    rec = synth.recipe("paper3d")
+    P = rec.problem
+    assert (P.nx, P.ny, P.nz) == (798, 798, 38)
+    ks, p0 = rec.ks(), rec.p0()
+    s = rich.Solver(P, rec.options, torch.from_numpy(ks).cuda())
+    p0_d = torch.from_numpy(p0).cuda()
+    th_o = orc.theta(P, p0)
+    assert np.max(np.abs(s.theta(p0_d).cpu().numpy() - th_o)) <= 1e-13 * np.max(np.abs(th_o))
+    s.set_state(p0_d)
+    st = s.step(1)[0]
+    assert st["status"] == 0, st
+    pg = s.get_state().cpu().numpy()
+    F = orc.residual(P, ks, pg, th_o)
+    assert np.max(np.abs(F)) <= rec.options.fnormtol * (1 + 1e-6), (np.max(np.abs(F)), st)
+    # the patch is wetting the top layer: heads there rose from h_r
+    top = pg.reshape(P.nz, P.ny, P.nx)[-1]
+    assert top.max() > p0.max() + 1.0
     s.close()
