@@ -262,14 +262,25 @@ __device__ __forceinline__ void spmv_J_at(const G &P, uint32_t n, const double *
     uint32_t nx = P.nx, nxy = (uint32_t)P.nx * (uint32_t)P.ny;
     // J is streamed (non-temporal): its 7 arrays are far larger than the caches
 #define JL(t) __builtin_nontemporal_load(J7 + (size_t)(t) * n + c)
-    double s = JL(J_D) * (double)x[c];
-    if (q.i > 0) s += JL(J_XM) * (double)x[c - 1];
-    if (q.i < P.nx - 1) s += JL(J_XP) * (double)x[c + 1];
-    if (q.j > 0) s += JL(J_YM) * (double)x[c - nx];
-    if (q.j < P.ny - 1) s += JL(J_YP) * (double)x[c + nx];
-    if (q.k > 0) s += JL(J_ZM) * (double)x[c - nxy];
-    if (q.k < P.nz - 1) s += JL(J_ZP) * (double)x[c + nxy];
+    // An absent neighbour's index is clamped to the cell itself, so every load
+    // is in bounds and all of them are issued before the first product (a
+    // load inside each boundary test would wait for its value before the next
+    // one is sent).  The sum keeps the order diag, -x, +x, -y, +y, -z, +z.
+    const uint32_t cxm = q.i > 0 ? c - 1 : c, cxp = q.i < P.nx - 1 ? c + 1 : c;
+    const uint32_t cym = q.j > 0 ? c - nx : c, cyp = q.j < P.ny - 1 ? c + nx : c;
+    const uint32_t czm = q.k > 0 ? c - nxy : c, czp = q.k < P.nz - 1 ? c + nxy : c;
+    const double a0 = JL(J_D), a1 = JL(J_XM), a2 = JL(J_XP), a3 = JL(J_YM), a4 = JL(J_YP), a5 = JL(J_ZM),
+                 a6 = JL(J_ZP);
 #undef JL
+    const double x0 = (double)x[c], x1 = (double)x[cxm], x2 = (double)x[cxp], x3 = (double)x[cym],
+                 x4 = (double)x[cyp], x5 = (double)x[czm], x6 = (double)x[czp];
+    double s = a0 * x0;
+    if (q.i > 0) s += a1 * x1;
+    if (q.i < P.nx - 1) s += a2 * x2;
+    if (q.j > 0) s += a3 * x3;
+    if (q.j < P.ny - 1) s += a4 * x4;
+    if (q.k > 0) s += a5 * x5;
+    if (q.k < P.nz - 1) s += a6 * x6;
     y[c] = s;
 }
 
@@ -283,13 +294,22 @@ __global__ void k_spmv_J(Phys P, uint32_t n, const double *__restrict__ J7, cons
 template <class T, class G, class F>
 __device__ inline T mstencil(const G &P, const Cell &q, uint32_t c, uint32_t n, const T *__restrict__ M4, F v) {
     uint32_t nx = P.nx, nxy = (uint32_t)P.nx * (uint32_t)P.ny;
-    T s = M4[(size_t)M_D * n + c] * v(c);
-    if (q.i > 0) s += M4[(size_t)M_XP * n + c - 1] * v(c - 1);
-    if (q.i < P.nx - 1) s += M4[(size_t)M_XP * n + c] * v(c + 1);
-    if (q.j > 0) s += M4[(size_t)M_YP * n + c - nx] * v(c - nx);
-    if (q.j < P.ny - 1) s += M4[(size_t)M_YP * n + c] * v(c + nx);
-    if (q.k > 0) s += M4[(size_t)M_ZP * n + c - nxy] * v(c - nxy);
-    if (q.k < P.nz - 1) s += M4[(size_t)M_ZP * n + c] * v(c + nxy);
+    // absent neighbours clamped to the cell itself: every load is in bounds and
+    // all are issued before the first product, as in the J product above
+    const uint32_t cxm = q.i > 0 ? c - 1 : c, cxp = q.i < P.nx - 1 ? c + 1 : c;
+    const uint32_t cym = q.j > 0 ? c - nx : c, cyp = q.j < P.ny - 1 ? c + nx : c;
+    const uint32_t czm = q.k > 0 ? c - nxy : c, czp = q.k < P.nz - 1 ? c + nxy : c;
+    const T m0 = M4[(size_t)M_D * n + c], m1 = M4[(size_t)M_XP * n + cxm], m2 = M4[(size_t)M_XP * n + c],
+            m3 = M4[(size_t)M_YP * n + cym], m4 = M4[(size_t)M_YP * n + c], m5 = M4[(size_t)M_ZP * n + czm],
+            m6 = M4[(size_t)M_ZP * n + c];
+    const T v0 = v(c), v1 = v(cxm), v2 = v(cxp), v3 = v(cym), v4 = v(cyp), v5 = v(czm), v6 = v(czp);
+    T s = m0 * v0;
+    if (q.i > 0) s += m1 * v1;
+    if (q.i < P.nx - 1) s += m2 * v2;
+    if (q.j > 0) s += m3 * v3;
+    if (q.j < P.ny - 1) s += m4 * v4;
+    if (q.k > 0) s += m5 * v5;
+    if (q.k < P.nz - 1) s += m6 * v6;
     return s;
 }
 
