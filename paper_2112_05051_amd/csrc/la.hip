@@ -59,8 +59,15 @@ __device__ inline double block_max(double v, double *sh) {
 // use; rows are taken in pairs with 16-byte loads (the basis stride ldv is a
 // multiple of 2 and the vectors are 16-byte aligned).  The odd last row of
 // an odd n is added by the first thread of block 0.
+// Register budget of the basis kernels.  Their launch (RED_BLOCKS blocks of
+// RED_THREADS) holds 4 waves per SIMD, yet scheduled for the default occupancy
+// the compiler loads one or two basis vectors at a time, each product waiting
+// for its own load.  Allowing 256 VGPRs (two waves per SIMD) lets it issue the
+// loads of all K vectors of a row pair up front.  Kernels under 128 VGPRs
+// (K <= 18) still run four waves per SIMD.
+#define RED_WPE_ATTR __attribute__((amdgpu_waves_per_eu(2, 2)))
 template <int K>
-__global__ void __launch_bounds__(RED_THREADS) k_multidot(const double *__restrict__ V, int64_t ldv,
+__global__ void __launch_bounds__(RED_THREADS) RED_WPE_ATTR k_multidot(const double *__restrict__ V, int64_t ldv,
                                                           const double *__restrict__ w, int64_t n,
                                                           double *__restrict__ partial) {
     __shared__ double sh[RED_THREADS / WAVE];
@@ -126,7 +133,7 @@ __global__ void k_reduce_max(const double *__restrict__ partial, int m, int nb, 
 
 // w -= sum_i h_i (vs_i V_i) and the partial sums of ||w||^2, K compile-time, row pairs.
 template <int K>
-__global__ void __launch_bounds__(RED_THREADS) k_update_norm(const double *__restrict__ V, int64_t ldv,
+__global__ void __launch_bounds__(RED_THREADS) RED_WPE_ATTR k_update_norm(const double *__restrict__ V, int64_t ldv,
                                                              const double *__restrict__ h,
                                                              const double *__restrict__ vs, double *__restrict__ w,
                                                              int64_t n, double *__restrict__ partial) {
@@ -243,8 +250,18 @@ __global__ void k_lincomb(const double *__restrict__ V, int64_t ldv, int k, cons
     __syncthreads();
     int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n) return;
+    // eight basis values are loaded before their products (the sum keeps the
+    // order i = 0, 1, ...); the basis is streamed past the caches
     double s = 0.0;
-    for (int i = 0; i < k; i++) s += cs[i] * V[(size_t)i * ldv + c];
+    int i = 0;
+    for (; i + 8 <= k; i += 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++) v[u] = __builtin_nontemporal_load(V + (size_t)(i + u) * ldv + c);
+#pragma unroll
+        for (int u = 0; u < 8; u++) s += cs[i + u] * v[u];
+    }
+    for (; i < k; i++) s += cs[i] * __builtin_nontemporal_load(V + (size_t)i * ldv + c);
     y[c] = s;
 }
 
