@@ -432,6 +432,19 @@ __device__ __forceinline__ void csr_stream_body(const int64_t *__restrict__ rb, 
     const int lane = threadIdx.x % G;
     int64_t row0 = r0 + threadIdx.x / G;
     int64_t ra = row0 < r1 ? rowptr[row0] : 0, rbe = row0 < r1 ? rowptr[row0 + 1] : 0;
+    // the row's b, D^{-1} and v of the final update, loaded with its row
+    // pointers so that the write after the group sum does not wait for them
+    T pb = 0, pd = 0, pv = 0;
+    auto row_in = [&](int64_t row) {
+        if (row < r1) {
+            pb = (T)b[row];
+            if (POST) {
+                pd = invd[row];
+                pv = v[row];
+            }
+        }
+    };
+    row_in(row0);
     // every load of the product phase is issued before the first use
     int32_t cj[PER];
     T vv[PER];
@@ -457,14 +470,15 @@ __device__ __forceinline__ void csr_stream_body(const int64_t *__restrict__ rb, 
         if (rbase != r0) {
             ra = row < r1 ? rowptr[row] : 0;
             rbe = row < r1 ? rowptr[row + 1] : 0;
+            row_in(row);
         }
         T s = 0;
         if (row < r1)
             for (int64_t e = ra + lane; e < rbe; e += G) s += prod[e - e0];
         s = group_sum<G>(s);
         if (lane == 0 && row < r1) {
-            if (POST) out[row] = v[row] + invd[row] * ((T)b[row] - s);
-            else out[row] = (T)b[row] - s;
+            if (POST) out[row] = pv + pd * (pb - s);
+            else out[row] = pb - s;
         }
     }
 }
