@@ -400,9 +400,10 @@ constexpr int T25X = 64, T25Y = ST25_TY;
 enum { ST25_PRE = 0, ST25_POST = 1, ST25_XT = 2 };
 
 // The inputs of u at one cell as loaded (u is formed when it is used).
-template <class T>
+template <class T, class TB>
 struct St25In {
-    T b = 0, d = 0, x = 0;  // bs b, D^{-1}, xc[agg] or xt
+    TB b = 0;  // b as loaded: scaled and rounded where it is used
+    T d = 0, x = 0;  // D^{-1}, xc[agg] or xt
 };
 
 // L: the tile (virtual block) this block computes.
@@ -435,17 +436,20 @@ __device__ __forceinline__ void st25_body(const G &P, const T *__restrict__ M4, 
     const int hyo = hyl ? -nx : nx;
     const bool hx = hxl || hxr, hy = hyl || hyr;
 
+    // a prefetched b is only scaled when it is used: converting it at once
+    // would wait for its load, and with it for every load issued before it
+    auto bval = [&](const St25In<T, TB> &r) -> T { return (T)(r.b * bs); };
     auto load_in = [&](uint32_t c) {
-        St25In<T> r;
-        if (MODE != ST25_XT) r.b = (T)(b[c] * bs);
+        St25In<T, TB> r;
+        if (MODE != ST25_XT) r.b = b[c];
         if (MODE != ST25_XT) r.d = invd[c];
         if (MODE == ST25_POST) r.x = xc[agg[c]];
         if (MODE == ST25_XT) r.x = xc[c];
         return r;
     };
-    auto u_of = [&](const St25In<T> &r) -> T {
+    auto u_of = [&](const St25In<T, TB> &r) -> T {
         if (MODE == ST25_XT) return r.x;
-        T u = r.b * r.d;
+        T u = bval(r) * r.d;
         if (MODE == ST25_POST) u += r.x;
         return u;
     };
@@ -454,11 +458,11 @@ __device__ __forceinline__ void st25_body(const G &P, const T *__restrict__ M4, 
     // plane state: coefficients of plane k (own, and the lower-neighbour
     // halo couplings), halo inputs of plane k, column inputs of k, k+1, k+2
     T m_d = 0, m_xp = 0, m_yp = 0, m_zp = 0, h_xp = 0, h_yp = 0;
-    St25In<T> c0, c1, c2, hxin, hyin;
+    St25In<T, TB> c0, c1, c2, hxin, hyin;
     T u_prev = 0, zp_prev = 0;
     uint32_t c = (uint32_t)i + (uint32_t)nx * ((uint32_t)j + (uint32_t)ny * (uint32_t)k0);
-    auto load_plane = [&](uint32_t cc, T &md, T &mxp, T &myp, T &mzp, T &hxp, T &hyp, St25In<T> &hxi,
-                          St25In<T> &hyi) {
+    auto load_plane = [&](uint32_t cc, T &md, T &mxp, T &myp, T &mzp, T &hxp, T &hyp, St25In<T, TB> &hxi,
+                          St25In<T, TB> &hyi) {
         if (inside) {
             // a cell's own coefficients are read once: streamed past the caches
             // (the halo couplings below are shared with the neighbouring tiles)
@@ -489,7 +493,7 @@ __device__ __forceinline__ void st25_body(const G &P, const T *__restrict__ M4, 
         const int q = (k - k0) & 1;
         // loads for the next iteration
         T n_d = 0, n_xp = 0, n_yp = 0, n_zp = 0, nh_xp = 0, nh_yp = 0;
-        St25In<T> nhx, nhy;
+        St25In<T, TB> nhx, nhy;
         if (k + 1 < k1) load_plane(c + nxy, n_d, n_xp, n_yp, n_zp, nh_xp, nh_yp, nhx, nhy);
         if (inside && k + 2 < nz && k + 1 < k1) c2 = load_in(c + 2 * nxy);
         // this plane through LDS
@@ -517,7 +521,7 @@ __device__ __forceinline__ void st25_body(const G &P, const T *__restrict__ M4, 
             if (j < ny - 1) s += yps[q][ty + 1][tx] * us[q][ty + 2][tx + 1];
             if (k > 0) s += zp_prev * u_prev;
             if (k < nz - 1) s += m_zp * u_nxt;
-            const T bc = MODE == ST25_XT ? b_of(c) : c0.b;
+            const T bc = MODE == ST25_XT ? b_of(c) : bval(c0);
             const T dc = MODE == ST25_XT ? invd[c] : c0.d;
             out[c] = POST ? u_cur + dc * (bc - s) : bc - s;
         }
