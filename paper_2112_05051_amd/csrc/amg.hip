@@ -536,13 +536,31 @@ __device__ __forceinline__ void restrict_block(int64_t nc, const int64_t *__rest
     const int64_t I = I0 + threadIdx.x;
     const int64_t t0 = mptr[I0], t1 = mptr[I1];
     const bool staged = t1 - t0 <= RESTRICT_LDS;
-    if (staged) {
-        // the member lists are read once per cycle: streamed past the caches
-        for (int64_t t = t0 + threadIdx.x; t < t1; t += RESTRICT_TPB) rv[t - t0] = r[__builtin_nontemporal_load(mem + t)];
+    // the thread's own row bounds are loaded before the staging, which issues
+    // all its member-index loads, then all its gathers (a gather waiting for
+    // its index one at a time would serialise eight round trips to memory);
+    // a slot past the stretch reads member t0 and is not stored
+    const int64_t a = I < nc ? mptr[I] : 0, e = I < nc ? mptr[I + 1] : 0;
+    if (staged && t1 > t0) {
+        constexpr int PER = RESTRICT_LDS / RESTRICT_TPB;
+        int32_t m[PER];
+#pragma unroll
+        for (int q = 0; q < PER; q++) {
+            const int64_t t = t0 + threadIdx.x + (int64_t)q * RESTRICT_TPB;
+            // the member lists are read once per cycle: streamed past the caches
+            m[q] = __builtin_nontemporal_load(mem + (t < t1 ? t : t0));
+        }
+        T x[PER];
+#pragma unroll
+        for (int q = 0; q < PER; q++) x[q] = r[m[q]];
+#pragma unroll
+        for (int q = 0; q < PER; q++) {
+            const int64_t t = t0 + threadIdx.x + (int64_t)q * RESTRICT_TPB;
+            if (t < t1) rv[t - t0] = x[q];
+        }
         __syncthreads();
     }
     if (I >= nc) return;
-    const int64_t a = mptr[I], e = mptr[I + 1];
     T s = 0;
     if (staged)
         for (int64_t t = a; t < e; t++) s += rv[t - t0];
