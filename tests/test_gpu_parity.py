@@ -61,8 +61,11 @@ def test_theta_residual(rich, torch, orc, mean, shape):
 
 
 @pytest.mark.parametrize("mean", MEANS)
-def test_jacobian_aux_spmv(rich, torch, orc, mean):
-    P = box_problem(13, 11, 9, mean=mean, dt=3.0)
+@pytest.mark.parametrize("shape", [(13, 11, 9), (1, 1, 7), (1, 6, 1), (5, 1, 3)])
+def test_jacobian_aux_spmv(rich, torch, orc, mean, shape):
+    """J and M (CSR and their stencil products) against the oracle; the thin
+    shapes have cells with both neighbours absent along a direction."""
+    P = box_problem(*shape, mean=mean, dt=3.0)
     n = P.n
     ks = random_ks(P, 21)
     p = random_heads(n, 22, saturated_fraction=0.03)
