@@ -59,17 +59,19 @@ __device__ inline double block_max(double v, double *sh) {
 // use; rows are taken in pairs with 16-byte loads (the basis stride ldv is a
 // multiple of 2 and the vectors are 16-byte aligned).  The odd last row of
 // an odd n is added by the first thread of block 0.
-// Register budget of the basis kernels.  Their launch (RED_BLOCKS blocks of
-// RED_THREADS) holds 4 waves per SIMD, yet scheduled for the default occupancy
-// the compiler loads one or two basis vectors at a time, each product waiting
-// for its own load.  Allowing 256 VGPRs (two waves per SIMD) lets it issue the
-// loads of all K vectors of a row pair up front.  Kernels under 128 VGPRs
-// (K <= 18) still run four waves per SIMD.
+// Register budget of the basis kernels on large vectors.  Their launch
+// (RED_BLOCKS blocks of RED_THREADS) holds 4 waves per SIMD, yet scheduled for
+// the default occupancy the compiler loads one or two basis vectors at a time,
+// each product waiting for its own load.  Allowing 256 VGPRs (two waves per
+// SIMD) lets it issue the loads of all K vectors of a row pair up front.  On
+// short vectors the kernels are latency-bound and the second round of blocks
+// that two waves per SIMD imply costs more than it saves: there the default
+// schedule (the _small kernels) runs.  Both compute the same sums.
 #define RED_WPE_ATTR __attribute__((amdgpu_waves_per_eu(2, 2)))
+constexpr int64_t RED_WIDE_MIN = int64_t(1) << 21;
 template <int K>
-__global__ void __launch_bounds__(RED_THREADS) RED_WPE_ATTR k_multidot(const double *__restrict__ V, int64_t ldv,
-                                                          const double *__restrict__ w, int64_t n,
-                                                          double *__restrict__ partial) {
+__device__ __forceinline__ void multidot_body(const double *__restrict__ V, int64_t ldv, const double *__restrict__ w,
+                                              int64_t n, double *__restrict__ partial) {
     __shared__ double sh[RED_THREADS / WAVE];
     double acc[K + 1];
 #pragma unroll
@@ -103,6 +105,20 @@ __global__ void __launch_bounds__(RED_THREADS) RED_WPE_ATTR k_multidot(const dou
     }
 }
 
+template <int K>
+__global__ void __launch_bounds__(RED_THREADS) RED_WPE_ATTR k_multidot(const double *__restrict__ V, int64_t ldv,
+                                                                     const double *__restrict__ w, int64_t n,
+                                                                     double *__restrict__ partial) {
+    multidot_body<K>(V, ldv, w, n, partial);
+}
+
+template <int K>
+__global__ void __launch_bounds__(RED_THREADS) k_multidot_small(const double *__restrict__ V, int64_t ldv,
+                                                                const double *__restrict__ w, int64_t n,
+                                                                double *__restrict__ partial) {
+    multidot_body<K>(V, ldv, w, n, partial);
+}
+
 // out[i] = sum_b partial[b*(m) + i], b ascending (one block per output),
 // times scale[i] for i < nscale (basis vectors stored with a scale factor).
 __global__ void k_reduce_partials(const double *__restrict__ partial, int m, int nb, double *__restrict__ out,
@@ -133,10 +149,9 @@ __global__ void k_reduce_max(const double *__restrict__ partial, int m, int nb, 
 
 // w -= sum_i h_i (vs_i V_i) and the partial sums of ||w||^2, K compile-time, row pairs.
 template <int K>
-__global__ void __launch_bounds__(RED_THREADS) RED_WPE_ATTR k_update_norm(const double *__restrict__ V, int64_t ldv,
-                                                             const double *__restrict__ h,
-                                                             const double *__restrict__ vs, double *__restrict__ w,
-                                                             int64_t n, double *__restrict__ partial) {
+__device__ __forceinline__ void update_norm_body(const double *__restrict__ V, int64_t ldv,
+                                                 const double *__restrict__ h, const double *__restrict__ vs,
+                                                 double *__restrict__ w, int64_t n, double *__restrict__ partial) {
     __shared__ double sh[RED_THREADS / WAVE];
     double hr[K];
 #pragma unroll
@@ -170,6 +185,24 @@ __global__ void __launch_bounds__(RED_THREADS) RED_WPE_ATTR k_update_norm(const 
     }
     double r = block_sum(acc, sh);
     if (threadIdx.x == 0) partial[blockIdx.x] = r;
+}
+
+template <int K>
+__global__ void __launch_bounds__(RED_THREADS) RED_WPE_ATTR k_update_norm(const double *__restrict__ V, int64_t ldv,
+                                                                        const double *__restrict__ h,
+                                                                        const double *__restrict__ vs,
+                                                                        double *__restrict__ w, int64_t n,
+                                                                        double *__restrict__ partial) {
+    update_norm_body<K>(V, ldv, h, vs, w, n, partial);
+}
+
+template <int K>
+__global__ void __launch_bounds__(RED_THREADS) k_update_norm_small(const double *__restrict__ V, int64_t ldv,
+                                                                   const double *__restrict__ h,
+                                                                   const double *__restrict__ vs,
+                                                                   double *__restrict__ w, int64_t n,
+                                                                   double *__restrict__ partial) {
+    update_norm_body<K>(V, ldv, h, vs, w, n, partial);
 }
 
 __global__ void k_dot(const double *__restrict__ x, const double *__restrict__ y, int64_t n,
@@ -378,7 +411,10 @@ rich_status launch_multidot(const double *V, int64_t ldv, int k, const double *v
     switch (k) {
 #define X(K)                                                                         \
     case K:                                                                          \
-        k_multidot<K><<<RED_BLOCKS, RED_THREADS, 0, s>>>(V, ldv, w, n, partial);     \
+        if (n >= RED_WIDE_MIN)                                                       \
+            k_multidot<K><<<RED_BLOCKS, RED_THREADS, 0, s>>>(V, ldv, w, n, partial); \
+        else                                                                         \
+            k_multidot_small<K><<<RED_BLOCKS, RED_THREADS, 0, s>>>(V, ldv, w, n, partial); \
         break;
         RICH_CASES_1_64(X)
 #undef X
@@ -395,7 +431,10 @@ rich_status launch_update_norm(const double *V, int64_t ldv, int k, const double
     switch (k) {
 #define X(K)                                                                            \
     case K:                                                                             \
-        k_update_norm<K><<<RED_BLOCKS, RED_THREADS, 0, s>>>(V, ldv, h, vs, w, n, partial); \
+        if (n >= RED_WIDE_MIN)                                                          \
+            k_update_norm<K><<<RED_BLOCKS, RED_THREADS, 0, s>>>(V, ldv, h, vs, w, n, partial); \
+        else                                                                            \
+            k_update_norm_small<K><<<RED_BLOCKS, RED_THREADS, 0, s>>>(V, ldv, h, vs, w, n, partial); \
         break;
         RICH_CASES_1_64(X)
 #undef X
