@@ -425,9 +425,11 @@ __device__ __forceinline__ void csr_stream_body(const int64_t *__restrict__ rb, 
                                                 const T *__restrict__ v, T *__restrict__ out, int64_t blk) {
     constexpr int PER = STREAM_LDS / 256;  // entries per thread in the product phase
     __shared__ T prod[STREAM_LDS];
-    int64_t r0 = rb[blk], r1 = rb[blk + 1];
+    // the block's first and end rows and their first entries, read together,
+    // so that the entry loads below need not wait for the row pointers
+    int64_t r0 = rb[2 * blk], r1 = rb[2 * blk + 2];
     if (r0 >= r1) return;
-    int64_t e0 = rowptr[r0], e1 = rowptr[r1];
+    int64_t e0 = rb[2 * blk + 1], e1 = rb[2 * blk + 3];
     // the reduction phase's first row pointers are loaded ahead of the products
     const int lane = threadIdx.x % G;
     int64_t row0 = r0 + threadIdx.x / G;
@@ -491,23 +493,25 @@ __global__ void __launch_bounds__(256) k_csr_stream(const int64_t *__restrict__ 
     csr_stream_body<G, TB, T, POST>(rb, rowptr, col, val, invd, b, v, out, xcd_block());
 }
 
-// rb[b] = first row whose first entry is at or past b * STREAM_CHUNK; the
-// blocks past the last chunk (grid padding) are empty
+// rb[2b] = first row whose first entry is at or past b * STREAM_CHUNK and
+// rb[2b + 1] = that row's first entry; the blocks past the last chunk (grid
+// padding) are empty
 __global__ void k_stream_rb(int64_t n, int64_t nrb, int64_t ngrid, const int64_t *__restrict__ rowptr,
                             int64_t *__restrict__ rb) {
     int64_t blk = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (blk > ngrid) return;
-    if (blk >= nrb) {
-        rb[blk] = n;
-        return;
+    int64_t lo = n;
+    if (blk < nrb) {
+        int64_t target = blk * (int64_t)STREAM_CHUNK, hi = n;
+        lo = 0;
+        while (lo < hi) {
+            int64_t mid = (lo + hi) >> 1;
+            if (rowptr[mid] < target) lo = mid + 1;
+            else hi = mid;
+        }
     }
-    int64_t target = blk * (int64_t)STREAM_CHUNK, lo = 0, hi = n;
-    while (lo < hi) {
-        int64_t mid = (lo + hi) >> 1;
-        if (rowptr[mid] < target) lo = mid + 1;
-        else hi = mid;
-    }
-    rb[blk] = lo;
+    rb[2 * blk] = lo;
+    rb[2 * blk + 1] = rowptr[lo];
 }
 
 __global__ void k_max_rowlen(int64_t n, const int64_t *__restrict__ rowptr, int *__restrict__ too_long) {
@@ -973,7 +977,7 @@ rich_status stream_blocks(Level &Lv, DevAlloc &mem, hipStream_t s) {
     Lv.sg = mean < 8 ? 1 : mean < 16 ? 2 : mean < 32 ? 4 : 8;
     // the launch grid is rounded up to a multiple of the XCD count: pad with empty blocks
     int64_t ngrid = xcd_grid(nrb, 1);
-    RICH_TRY(mem.get(&Lv.rb, ngrid + 1));
+    RICH_TRY(mem.get(&Lv.rb, 2 * (ngrid + 1)));
     k_stream_rb<<<nblocks(ngrid + 1), TPB, 0, s>>>(Lv.n, nrb, ngrid, Lv.rowptr, Lv.rb);
     LAUNCH_CHECK();
     Lv.nrb = ngrid;

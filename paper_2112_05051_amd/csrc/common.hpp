@@ -284,7 +284,7 @@ struct Level {
     // row blocks of the CSR-stream kernels (levels >= 1): block b holds the
     // rows whose first entry lies in [b STREAM_CHUNK, (b+1) STREAM_CHUNK)
     int64_t nrb = 0;
-    int64_t *rb = nullptr;  // nrb + 1 row boundaries; nullptr: rows too long, plain CSR kernels
+    int64_t *rb = nullptr;  // nrb + 1 (first row, its first entry) pairs; nullptr: rows too long, plain CSR kernels
     int sg = 1;             // lanes per row in the kernels' reduction phase
 };
 constexpr int STREAM_CHUNK = 1536, STREAM_MAXROW = 512;
