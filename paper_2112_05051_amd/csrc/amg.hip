@@ -50,9 +50,34 @@ __global__ void k_diag(int64_t n, const int64_t *__restrict__ rowptr, const int3
     diag[i] = d;
 }
 
+// The edge weights of a sweep, once: w[e] = 1 - 2 a_lo,hi / (d_lo + d_hi) for
+// the entry e = (i, j), the coupling a read in the lower-numbered row; NaN
+// where the entry can never be a candidate (the diagonal, a coupling missing
+// from the lower row, a zero coupling).  k_candidates skips every entry
+// whose weight is not finite.
+__global__ void k_match_weights(int64_t n, const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+                                const double *__restrict__ val, const double *__restrict__ diag,
+                                double *__restrict__ w) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int64_t e = rowptr[i]; e < rowptr[i + 1]; e++) {
+        int32_t j = col[e];
+        double we = __builtin_nan("");
+        if (j != i) {
+            int64_t lo = j < i ? j : i, hi = j < i ? i : j;
+            bool found = true;
+            double a = lo == i ? val[e] : find_entry(rowptr, col, val, lo, (int32_t)hi, &found);
+            if (found && a != 0.0) we = 1.0 - (2.0 * a) / (diag[lo] + diag[hi]);
+        }
+        w[e] = we;
+    }
+}
+
+// One matching round: every free row proposes its free neighbour of largest
+// weight (ties to the smaller (lo, hi) pair); -1 when there is none.
 __global__ void k_candidates(int64_t n, const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
-                             const double *__restrict__ val, const double *__restrict__ diag,
-                             const int32_t *__restrict__ mate, int32_t *__restrict__ cand) {
+                             const double *__restrict__ w, const int32_t *__restrict__ mate,
+                             int32_t *__restrict__ cand) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     if (mate[i] != -1) {
@@ -65,22 +90,13 @@ __global__ void k_candidates(int64_t n, const int64_t *__restrict__ rowptr, cons
     for (int64_t e = rowptr[i]; e < rowptr[i + 1]; e++) {
         int32_t j = col[e];
         if (j == i || mate[j] != -1) continue;
+        double we = w[e];
+        if (!isfinite(we)) continue;
         int64_t lo = j < i ? j : i, hi = j < i ? i : j;
-        double a;
-        if (lo == i) {
-            a = val[e];
-        } else {
-            bool found;
-            a = find_entry(rowptr, col, val, lo, (int32_t)hi, &found);
-            if (!found) continue;
-        }
-        if (a == 0.0) continue;
-        double w = 1.0 - (2.0 * a) / (diag[lo] + diag[hi]);
-        if (!isfinite(w)) continue;
-        bool better = best < 0 || w > bw || (w == bw && (lo < blo || (lo == blo && hi < bhi)));
+        bool better = best < 0 || we > bw || (we == bw && (lo < blo || (lo == blo && hi < bhi)));
         if (better) {
             best = j;
-            bw = w;
+            bw = we;
             blo = lo;
             bhi = hi;
         }
@@ -812,6 +828,14 @@ rich_status match_sweep(int64_t n, const int64_t *rowptr, const int32_t *col, co
     }
     k_diag<<<nblocks(n), TPB, 0, s>>>(n, rowptr, col, val, diag);
     LAUNCH_CHECK();
+    // the weights do not change between rounds: computed once
+    int64_t nnz = 0;
+    HIP_TRY(hipMemcpyAsync(&nnz, rowptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    double *wts;
+    RICH_TRY(tmp.get(&wts, nnz > 0 ? nnz : 1));
+    k_match_weights<<<nblocks(n), TPB, 0, s>>>(n, rowptr, col, val, diag, wts);
+    LAUNCH_CHECK();
     RICH_TRY(launch_fill_i32(mate, -1, n, s));
     int *h_still = nullptr;
     HIP_TRY(hipHostMalloc((void **)&h_still, sizeof(int)));
@@ -820,7 +844,7 @@ rich_status match_sweep(int64_t n, const int64_t *rowptr, const int32_t *col, co
         HIP_TRY(hipMemsetAsync(still, 0, sizeof(int), s));
         // a few rounds per host check; extra rounds after completion are no-ops
         for (int t = 0; t < 4; t++) {
-            k_candidates<<<nblocks(n), TPB, 0, s>>>(n, rowptr, col, val, diag, mate, cand);
+            k_candidates<<<nblocks(n), TPB, 0, s>>>(n, rowptr, col, wts, mate, cand);
             k_commit<<<nblocks(n), TPB, 0, s>>>(n, cand, mate, still);
         }
         LAUNCH_CHECK();
