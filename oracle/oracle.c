@@ -15,10 +15,16 @@
  * termination; the smoothed prolongator by the 1-D hat functions; the
  * multicolour Gauss-Seidel sweeps by triangular solves in the colour-sorted
  * ordering; the greedy aggregation by hand-worked 1-D and 2-D cases and its
- * invariants.  The Newton / line-search control flow (orc_solver_step) is
- * pinned only through invariants (Armijo inequality at every accepted step,
- * convergence to the residual tolerance, mass balance): its iteration counts
- * are "parity unpinned" against the paper, whose workload differs.
+ * invariants.  The Newton / line-search control flow (orc_solver_step)
+ * records every attempt (orc_solver_trace); the tests recompute from that
+ * record, independently, the Armijo condition at every accepted step (with
+ * f re-evaluated at the returned states), each backtracking step as the
+ * minimiser of the quadratic or cubic model (numpy solves and polynomial
+ * roots), the beta lengthening, the rebuild schedule of
+ * eq. (jacobian_update_condition) and the outcome of every attempt.  The
+ * coarsest-level l1 sweeps are pinned by the dense sum of the sweep
+ * operators.  Iteration counts are "parity unpinned" against the paper,
+ * whose workload differs.
  */
 #include "oracle.h"
 
@@ -1363,7 +1369,35 @@ struct orc_solver {
     int have_J;
     int since_build;
     double *theta_old, *u, *F, *ut, *Ft, *d, *Jd, *ub, *Fb;
+    int nstep;                  /* time steps taken */
+    orc_newton_event *trace;    /* armed record of the controller (may be NULL) */
+    int trace_cap, trace_len;
 };
+
+void orc_solver_trace(orc_solver *S, orc_newton_event *buf, int cap)
+{
+    S->trace = buf;
+    S->trace_cap = buf ? cap : 0;
+    S->trace_len = 0;
+}
+
+int orc_solver_trace_len(const orc_solver *S) { return S->trace_len; }
+
+static void trace_push(orc_solver *S, const orc_newton_event *ev)
+{
+    if (!S->trace) return;
+    if (S->trace_len < S->trace_cap) S->trace[S->trace_len] = *ev;
+    S->trace_len++;
+}
+
+static void trace_trial(orc_newton_event *ev, double lam, double f)
+{
+    if (ev->ntrial < ORC_TRACE_TRIALS) {
+        ev->trial_lam[ev->ntrial] = lam;
+        ev->trial_f[ev->ntrial] = f;
+    }
+    ev->ntrial++;
+}
 
 static double norm_inf(int64_t n, const double *v)
 {
@@ -1470,7 +1504,7 @@ static double rel_length(int64_t n, const double *s, double lam, const double *u
  * On success u+lam d is in S->ut and its residual in S->Ft.
  */
 static int line_search(orc_solver *S, double slope, double mxstep, int truncated, double *lam_out,
-                       int *nback)
+                       int *nback, orc_newton_event *ev)
 {
     int64_t N = S->N;
     const double alpha = S->O.ls_alpha, beta = 0.9;
@@ -1478,21 +1512,25 @@ static int line_search(orc_solver *S, double slope, double mxstep, int truncated
     double rl = rel_length(N, S->d, 1.0, S->u);
     double lam_min = rl > 0.0 ? S->O.scsteptol / rl : 0.0;
     double lam = 1.0, lam_prev = 0.0, f_prev = 0.0;
-    int first = 1;
+    int have_model = 0; /* a finite trial has been seen: the next model is cubic */
     *nback = 0;
+    ev->rel_d = rl;
     for (;;) {
         for (int64_t i = 0; i < N; i++) S->ut[i] = S->u[i] + lam * S->d[i];
         orc_residual(&S->P, S->Ks, S->ut, S->theta_old, S->Ft);
         double ft = half_sq(N, S->Ft);
+        trace_trial(ev, lam, ft);
         if (isfinite(ft) && ft <= f0 + alpha * lam * slope) break;
         if (lam < lam_min) return ORC_LINESEARCH_FAIL;
         double lt;
         if (!isfinite(ft)) {
             lt = 0.1 * lam;
-        } else if (first) {
-            lt = -slope / (2.0 * (ft - f0 - slope));
-            first = 0;
+        } else if (!have_model) {
+            /* minimiser of the quadratic q with q(0) = f0, q'(0) = slope, q(lam) = ft */
+            lt = -slope * lam * lam / (2.0 * (ft - f0 - slope * lam));
         } else {
+            /* minimiser of the cubic c with c(0) = f0, c'(0) = slope through the
+               last two finite trials (lam_prev, f_prev) and (lam, ft) */
             double t1 = ft - f0 - lam * slope;
             double t2 = f_prev - f0 - lam_prev * slope;
             double a = (t1 / (lam * lam) - t2 / (lam_prev * lam_prev)) / (lam - lam_prev);
@@ -1508,6 +1546,7 @@ static int line_search(orc_solver *S, double slope, double mxstep, int truncated
         if (isfinite(ft)) {
             lam_prev = lam;
             f_prev = ft;
+            have_model = 1;
         }
         if (!(lt <= 0.5 * lam)) lt = 0.5 * lam;
         if (!(lt >= 0.1 * lam)) lt = 0.1 * lam;
@@ -1524,6 +1563,7 @@ static int line_search(orc_solver *S, double slope, double mxstep, int truncated
             for (int64_t i = 0; i < N; i++) S->ub[i] = S->u[i] + lt * S->d[i];
             orc_residual(&S->P, S->Ks, S->ub, S->theta_old, S->Fb);
             double fb = half_sq(N, S->Fb);
+            trace_trial(ev, lt, fb);
             if (!(isfinite(fb) && fb <= f0 + alpha * lt * slope)) break;
             lam = lt;
             ft = fb;
@@ -1556,6 +1596,7 @@ int orc_solver_step(orc_solver *S, double *p, orc_stats *st)
     int64_t N = S->N;
     memset(st, 0, sizeof(*st));
     st->min_lambda = 1.0;
+    int step_index = S->nstep++;
     if (!all_finite(N, p)) return st->status = ORC_NONFINITE;
     orc_theta(&S->P, p, S->theta_old);
     memcpy(S->u, p, (size_t)N * sizeof(double));
@@ -1569,16 +1610,27 @@ int orc_solver_step(orc_solver *S, double *p, orc_stats *st)
     }
     double prev_step = 0.0;
     int retry = 0, status = ORC_OK;
+    orc_newton_event ev;
     while (fnorm > S->O.fnormtol) {
         if (st->newton_its >= S->O.max_newton) {
             status = ORC_MAXITER;
             break;
         }
+        memset(&ev, 0, sizeof(ev));
+        ev.step = step_index;
+        ev.newton_it = st->newton_its;
+        ev.since_build = S->since_build;
+        ev.mxstep = mxstep;
+        ev.f0 = half_sq(N, S->F);
+        ev.reason = (!S->have_J ? ORC_RB_NOJ : 0) | (S->have_J && S->since_build >= S->O.msbset ? ORC_RB_MSBSET : 0) |
+                    (prev_step > 1.5 ? ORC_RB_BIGSTEP : 0) | (retry ? ORC_RB_RETRY : 0);
         int fresh = 0;
-        if (!S->have_J || S->since_build >= S->O.msbset || prev_step > 1.5 || retry) {
+        if (ev.reason) {
             int rc = rebuild(S, S->u, st);
             if (rc != ORC_OK) {
                 status = rc;
+                ev.outcome = ORC_EV_FAIL_OTHER;
+                trace_push(S, &ev);
                 break;
             }
             fresh = 1;
@@ -1590,10 +1642,14 @@ int orc_solver_step(orc_solver *S, double *p, orc_stats *st)
         int conv = orc_gmres(N, S->J.rowptr, S->J.col, S->J.val, S->H, S->Ft, S->d,
                              S->O.gmres_restart, S->O.eta, S->O.gmres_maxit, &its, &relres);
         st->gmres_its += its;
+        ev.gmres_its = its;
+        ev.gmres_conv = conv;
         if (!conv) {
             st->linsolve_fails++;
             if (!fresh) {
                 retry = 1;
+                ev.outcome = ORC_EV_RETRY_GMRES;
+                trace_push(S, &ev);
                 continue;
             }
         }
@@ -1603,26 +1659,39 @@ int orc_solver_step(orc_solver *S, double *p, orc_stats *st)
             for (int64_t i = 0; i < N; i++) S->d[i] *= mxstep / dn;
             truncated = 1;
         }
+        ev.truncated = truncated;
+        ev.dnorm2 = sqrt(dot(N, S->d, S->d));
+        ev.dnorminf = norm_inf(N, S->d);
         orc_csr_matvec(N, S->J.rowptr, S->J.col, S->J.val, S->d, S->Jd);
         double slope = dot(N, S->F, S->Jd);
+        ev.slope = slope;
         if (!(slope < 0.0)) {
             if (!fresh) {
                 retry = 1;
+                ev.outcome = ORC_EV_RETRY_SLOPE;
+                trace_push(S, &ev);
                 continue;
             }
             status = ORC_LINSOLVE_FAIL;
+            ev.outcome = ORC_EV_FAIL_SLOPE;
+            trace_push(S, &ev);
             break;
         }
         double lam;
         int nb;
-        int rc = line_search(S, slope, mxstep, truncated, &lam, &nb);
+        int rc = line_search(S, slope, mxstep, truncated, &lam, &nb, &ev);
         st->ls_backtracks += nb;
+        ev.nback = nb;
         if (rc != ORC_OK) {
             if (!fresh) {
                 retry = 1;
+                ev.outcome = ORC_EV_RETRY_LS;
+                trace_push(S, &ev);
                 continue;
             }
             status = rc;
+            ev.outcome = ORC_EV_FAIL_LS;
+            trace_push(S, &ev);
             break;
         }
         if (lam < st->min_lambda) st->min_lambda = lam;
@@ -1633,19 +1702,34 @@ int orc_solver_step(orc_solver *S, double *p, orc_stats *st)
         st->newton_its++;
         S->since_build++;
         fnorm = norm_inf(N, S->F);
+        ev.lam = lam;
+        ev.f_acc = half_sq(N, S->F);
+        ev.step_inf = step_inf;
+        ev.step_rel = step_rel;
+        ev.fnorm_inf = fnorm;
+        ev.outcome = ORC_EV_ACCEPT;
         if (!isfinite(fnorm)) {
             status = ORC_NONFINITE;
+            ev.outcome = ORC_EV_FAIL_OTHER;
+            trace_push(S, &ev);
             break;
         }
-        if (fnorm <= S->O.fnormtol) break;
+        if (fnorm <= S->O.fnormtol) {
+            trace_push(S, &ev);
+            break;
+        }
         if (step_rel < S->O.scsteptol) {
             if (!fresh) {
                 retry = 1;
+                ev.outcome = ORC_EV_ACCEPT_SHORT;
             } else {
                 status = ORC_STEP_TOO_SMALL;
+                ev.outcome = ORC_EV_STALL;
+                trace_push(S, &ev);
                 break;
             }
         }
+        trace_push(S, &ev);
         prev_step = step_inf;
     }
     st->fnorm_inf = fnorm;

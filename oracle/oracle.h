@@ -167,4 +167,45 @@ int orc_solver_create(const orc_problem *P, const orc_opts *O, const double *Ks,
 int orc_solver_step(orc_solver *S, double *p, orc_stats *st);
 void orc_solver_destroy(orc_solver *S);
 
+/* ---- record of the Newton controller (Section 3), one entry per attempt ---- */
+/* An attempt is one pass of the rebuild test, the linear solve and the line    */
+/* search; an attempt that ends with a retry request is followed by another    */
+/* attempt at the same Newton iterate.                                          */
+#define ORC_TRACE_TRIALS 48
+#define ORC_EV_ACCEPT 0        /* step accepted */
+#define ORC_EV_ACCEPT_SHORT 1  /* step accepted, shorter than scsteptol, stale J: rebuild next */
+#define ORC_EV_RETRY_GMRES 2   /* GMRES failed with a stale J */
+#define ORC_EV_RETRY_SLOPE 3   /* d no descent direction, stale J */
+#define ORC_EV_RETRY_LS 4      /* line search failed, stale J */
+#define ORC_EV_FAIL_SLOPE 5    /* d no descent direction, fresh J: LINSOLVE_FAIL */
+#define ORC_EV_FAIL_LS 6       /* line search failed, fresh J: LINESEARCH_FAIL */
+#define ORC_EV_STALL 7         /* step shorter than scsteptol with a fresh J: STEP_TOO_SMALL */
+#define ORC_EV_FAIL_OTHER 8    /* set-up error or non-finite residual */
+#define ORC_RB_NOJ 1           /* rebuild reasons (bits) */
+#define ORC_RB_MSBSET 2
+#define ORC_RB_BIGSTEP 4
+#define ORC_RB_RETRY 8
+typedef struct {
+    int step;         /* time step, counted from 0 since the solver was created */
+    int newton_it;    /* accepted Newton iterations of this step before the attempt */
+    int since_build;  /* iterations since the last rebuild, before the rebuild test */
+    int reason;       /* ORC_RB_* bits that held at the rebuild test (0: J re-used) */
+    int gmres_its, gmres_conv, truncated, outcome;
+    int ntrial;       /* line-search trials u + lam d in order, the full step lam = 1 first */
+    int nback;        /* of which backtracking trials (the rest lengthen a full step) */
+    double f0;        /* 0.5 ||Phi(u)||_2^2 at the attempt's iterate */
+    double slope;     /* Phi(u)^T J d */
+    double dnorm2, dnorminf;  /* of the (possibly truncated) correction d */
+    double rel_d;     /* max_i |d_i| / max(|u_i|, 1) */
+    double mxstep;    /* maximum step length */
+    double lam, f_acc;        /* accepted step and 0.5 ||Phi||^2 there (lam 0 if none) */
+    double step_inf, step_rel, fnorm_inf;  /* ||lam d||_inf, its relative length, ||Phi||_inf after */
+    double trial_lam[ORC_TRACE_TRIALS], trial_f[ORC_TRACE_TRIALS];  /* f = 0.5 ||Phi||^2 */
+} orc_newton_event;
+/* Record the attempts of the following orc_solver_step calls into buf (cap  */
+/* entries; NULL stops recording).  Returns the number recorded since armed,  */
+/* which may exceed cap (the excess is dropped).                              */
+void orc_solver_trace(orc_solver *S, orc_newton_event *buf, int cap);
+int orc_solver_trace_len(const orc_solver *S);
+
 #endif

@@ -59,6 +59,30 @@ class CStats(C.Structure):
                 ("mass_residual", C.c_double), ("min_lambda", C.c_double)]
 
 
+TRACE_TRIALS = 48
+EV_ACCEPT, EV_ACCEPT_SHORT, EV_RETRY_GMRES, EV_RETRY_SLOPE, EV_RETRY_LS = 0, 1, 2, 3, 4
+EV_FAIL_SLOPE, EV_FAIL_LS, EV_STALL, EV_FAIL_OTHER = 5, 6, 7, 8
+RB_NOJ, RB_MSBSET, RB_BIGSTEP, RB_RETRY = 1, 2, 4, 8
+
+
+class CEvent(C.Structure):
+    _fields_ = [("step", C.c_int), ("newton_it", C.c_int), ("since_build", C.c_int), ("reason", C.c_int),
+                ("gmres_its", C.c_int), ("gmres_conv", C.c_int), ("truncated", C.c_int), ("outcome", C.c_int),
+                ("ntrial", C.c_int), ("nback", C.c_int),
+                ("f0", C.c_double), ("slope", C.c_double), ("dnorm2", C.c_double), ("dnorminf", C.c_double),
+                ("rel_d", C.c_double), ("mxstep", C.c_double), ("lam", C.c_double), ("f_acc", C.c_double),
+                ("step_inf", C.c_double), ("step_rel", C.c_double), ("fnorm_inf", C.c_double),
+                ("trial_lam", C.c_double * TRACE_TRIALS), ("trial_f", C.c_double * TRACE_TRIALS)]
+
+
+def event_dict(e) -> dict:
+    d = {f: getattr(e, f) for f, _ in e._fields_ if not f.startswith("trial_")}
+    k = min(e.ntrial, TRACE_TRIALS)
+    d["trial_lam"] = [e.trial_lam[i] for i in range(k)]
+    d["trial_f"] = [e.trial_f[i] for i in range(k)]
+    return d
+
+
 _lib = None
 
 
@@ -112,6 +136,8 @@ def lib():
         L.orc_solver_create.argtypes = [P(CProblem), P(COpts), d, P(vp)]
         L.orc_solver_step.argtypes = [vp, d, P(CStats)]
         L.orc_solver_destroy.argtypes = [vp]
+        L.orc_solver_trace.argtypes = [vp, P(CEvent), C.c_int]
+        L.orc_solver_trace_len.argtypes = [vp]
         _lib = L
     return _lib
 
@@ -392,6 +418,16 @@ class Solver:
         st = CStats()
         lib().orc_solver_step(self._h, _d(p), C.byref(st))
         return stats_dict(st)
+
+    def trace(self, capacity: int = 4096):
+        """Record the Newton attempts of the following steps (read with events())."""
+        self._ev = (CEvent * capacity)()
+        lib().orc_solver_trace(self._h, self._ev, capacity)
+
+    def events(self) -> list:
+        n = lib().orc_solver_trace_len(self._h)
+        assert n <= len(self._ev), "trace capacity exceeded"
+        return [event_dict(self._ev[i]) for i in range(n)]
 
     def __del__(self):
         if getattr(self, "_h", None) and self._h.value and _lib is not None:

@@ -124,6 +124,37 @@ def test_vcycle_equals_section_5_2_recursion(orc):
     assert np.linalg.eigvalsh(0.5 * (Mbar + Mbar.T)).min() > 0
 
 
+@pytest.mark.parametrize("sweeps", [1, 2, 4])
+def test_vcycle_with_l1_sweeps_at_the_coarsest(orc, sweeps):
+    """When the coarsest level is too large for the direct solve, it takes k
+    l1-Jacobi sweeps from zero: M-bar_c = sum_{i<k} (I - D^-1 A_c)^i D^-1 with D the
+    l1 diagonal, and the rest of the recursion of Section 5.2 is unchanged."""
+    P = box_problem(9, 8, 7)
+    M = orc.auxiliary(P, random_ks(P, 6), random_heads(P.n, 7, -70, -30))
+    opts = synth.Options(amg_coarse_size=20, coarse_dense_max=0, coarse_l1_sweeps=sweeps)
+    amg = orc.AMG(opts, M)
+    L = amg.levels
+    assert L >= 3 and not amg.coarse_dense
+    mats, aggs = zip(*[amg.level(l) for l in range(L)])
+    Ac = mats[-1].toarray()
+    Dinv = np.diag(1.0 / np.abs(Ac).sum(axis=1))
+    E = np.eye(Ac.shape[0]) - Dinv @ Ac
+    Mbar = sum(np.linalg.matrix_power(E, i) for i in range(sweeps)) @ Dinv
+    for l in range(L - 2, -1, -1):
+        Ml = mats[l].toarray()
+        n = Ml.shape[0]
+        Sinv = np.diag(1.0 / np.abs(Ml).sum(axis=1))
+        Pl = np.zeros((n, mats[l + 1].shape[0]))
+        Pl[np.arange(n), aggs[l]] = 1.0
+        I = np.eye(n)
+        Mbar = Sinv.T + Sinv - Sinv.T @ Ml @ Sinv + (I - Sinv.T @ Ml) @ Pl @ Mbar @ Pl.T @ (I - Ml @ Sinv)
+    b = np.random.default_rng(8).standard_normal(P.n)
+    x = amg.apply(b)
+    ref = Mbar @ b
+    assert np.linalg.norm(x - ref) <= 1e-11 * np.linalg.norm(ref)
+    assert np.allclose(Mbar, Mbar.T, atol=1e-12 * np.abs(Mbar).max())
+
+
 def test_gmres_finite_termination(orc):
     rng = np.random.default_rng(9)
     n = 25
