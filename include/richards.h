@@ -152,7 +152,17 @@ typedef struct rich_solver_opts {
 #define RICH_AGG_MATCHING 0
 #define RICH_AGG_VMB 1
 
-/* Per-time-step counters and timings (host wall seconds of each phase). */
+/* Per-time-step counters, timings and traffic.  The phases are those the
+ * paper's experiments time (Section 6): residual evaluations (Feval), the
+ * Jacobian with the auxiliary matrix (assembled together in one pass over
+ * the grid), the update of the preconditioner from a new auxiliary matrix
+ * (Aux: smoother data and coarse matrices), the full AMG set-up (Setup),
+ * the linear solves (LinSol) and everything else (Overhead: line-search
+ * vector updates, norms, host decisions).  Times are host wall seconds;
+ * bytes are the algorithmic HBM bytes of the kernels each phase launched
+ * (the data the operations must move, re-reads excluded) of the kernels of
+ * Feval, Jacobian, LinSol and Overhead; set-up and Aux work (sorting,
+ * matching, sparse products) is timed but not counted in bytes. */
 typedef struct rich_step_stats {
     int status;
     int newton_its, jac_builds, gmres_its, ls_backtracks, amg_setups, linsolve_fails, levels;
@@ -160,8 +170,45 @@ typedef struct rich_step_stats {
     double mass_residual; /* dt * sum_c Phi_c at the accepted state */
     double min_lambda;    /* smallest accepted line-search step */
     double opc;           /* operator complexity sum nnz(A_l) / nnz(A_0) */
-    double t_feval, t_jac, t_setup, t_linsol, t_total;
+    double t_feval, t_jac, t_aux, t_setup, t_linsol, t_overhead, t_total;
+    double bytes_feval, bytes_jac, bytes_linsol, bytes_overhead;
 } rich_step_stats_t;
+
+/* Record of one attempt of the Newton controller (Section 3): the rebuild
+ * test of eq. (jacobian_update_condition), the GMRES solve and the line
+ * search at one iterate.  An attempt that ends with a retry request (stale
+ * J) is followed by another at the same iterate. */
+#define RICH_TRACE_TRIALS 48
+#define RICH_EV_ACCEPT 0        /* step accepted */
+#define RICH_EV_ACCEPT_SHORT 1  /* accepted, shorter than scsteptol, stale J: rebuild next */
+#define RICH_EV_RETRY_GMRES 2   /* GMRES failed with a stale J */
+#define RICH_EV_RETRY_SLOPE 3   /* d is no descent direction, stale J */
+#define RICH_EV_RETRY_LS 4      /* line search failed, stale J */
+#define RICH_EV_FAIL_SLOPE 5    /* d is no descent direction, fresh J (RICH_LINSOLVE_FAIL) */
+#define RICH_EV_FAIL_LS 6       /* line search failed, fresh J (RICH_LINESEARCH_FAIL) */
+#define RICH_EV_STALL 7         /* shorter than scsteptol with a fresh J (RICH_STEP_TOO_SMALL) */
+#define RICH_EV_FAIL_OTHER 8    /* set-up error or non-finite residual */
+#define RICH_RB_NOJ 1           /* rebuild reasons (bits): no J yet */
+#define RICH_RB_MSBSET 2        /* msbset iterations since the last rebuild */
+#define RICH_RB_BIGSTEP 4       /* the previous step had ||lam d||_inf > 1.5 */
+#define RICH_RB_RETRY 8         /* the previous attempt asked for a retry */
+typedef struct rich_newton_event {
+    int step;         /* time step, counted from 0 since the handle was created */
+    int newton_it;    /* accepted Newton iterations of this step before the attempt */
+    int since_build;  /* iterations since the last rebuild, before the rebuild test */
+    int reason;       /* RICH_RB_* bits that held (0: J re-used) */
+    int gmres_its, gmres_conv, truncated, outcome;
+    int ntrial;       /* line-search trials u + lam d in order, the full step first */
+    int nback;        /* of which backtracking trials (the rest lengthen a full step) */
+    double f0;        /* 0.5 ||Phi(u)||_2^2 at the attempt's iterate */
+    double slope;     /* Phi(u)^T J d */
+    double dnorm2, dnorminf;  /* of the (possibly truncated) correction d */
+    double rel_d;     /* max_i |d_i| / max(|u_i|, 1) */
+    double mxstep;    /* maximum step length */
+    double lam, f_acc;        /* accepted step and 0.5 ||Phi||^2 there (0 if none) */
+    double step_inf, step_rel, fnorm_inf;  /* ||lam d||_inf, relative length, ||Phi||_inf after */
+    double trial_lam[RICH_TRACE_TRIALS], trial_f[RICH_TRACE_TRIALS];  /* f = 0.5 ||Phi||^2 */
+} rich_newton_event_t;
 
 typedef struct rich_ctx *rich_handle_t;
 
@@ -185,8 +232,18 @@ rich_status rich_set_state(rich_handle_t h, const double *p_dev);
 rich_status rich_get_state(rich_handle_t h, double *p_dev);
 
 /* Advance nsteps backward-Euler steps.  stats_host: nsteps entries or NULL.
- * Returns the first non-OK status (the state is then the last good level). */
+ * Returns the first error (< 0; the state is then the last good level and
+ * no further step is taken), else the largest warning (> 0) any step gave,
+ * else RICH_OK. */
 rich_status rich_step(rich_handle_t h, int nsteps, rich_step_stats_t *stats_host);
+
+/* Record every attempt of the Newton controller in the following rich_step
+ * calls into events_host (host memory, `capacity` entries, owned by the
+ * caller and written during rich_step); NULL stops recording.  Arming resets
+ * the count.  rich_trace_count gives the number of attempts since arming,
+ * which may exceed the capacity (the excess is not stored). */
+rich_status rich_trace_newton(rich_handle_t h, rich_newton_event_t *events_host, int capacity);
+rich_status rich_trace_count(rich_handle_t h, int64_t *count_host);
 
 const char *rich_status_string(rich_status s);
 

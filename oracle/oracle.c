@@ -1383,6 +1383,11 @@ void orc_solver_trace(orc_solver *S, orc_newton_event *buf, int cap)
 
 int orc_solver_trace_len(const orc_solver *S) { return S->trace_len; }
 
+void orc_solver_iterate(const orc_solver *S, double *u)
+{
+    memcpy(u, S->u, (size_t)S->N * sizeof(double));
+}
+
 static void trace_push(orc_solver *S, const orc_newton_event *ev)
 {
     if (!S->trace) return;

@@ -207,5 +207,8 @@ typedef struct {
 /* which may exceed cap (the excess is dropped).                              */
 void orc_solver_trace(orc_solver *S, orc_newton_event *buf, int cap);
 int orc_solver_trace_len(const orc_solver *S);
+/* The last Newton iterate of the most recent step (its state also when the */
+/* step failed and p was left at the previous level).                       */
+void orc_solver_iterate(const orc_solver *S, double *u);
 
 #endif

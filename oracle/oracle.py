@@ -138,6 +138,7 @@ def lib():
         L.orc_solver_destroy.argtypes = [vp]
         L.orc_solver_trace.argtypes = [vp, P(CEvent), C.c_int]
         L.orc_solver_trace_len.argtypes = [vp]
+        L.orc_solver_iterate.argtypes = [vp, d]
         _lib = L
     return _lib
 
@@ -423,6 +424,12 @@ class Solver:
         """Record the Newton attempts of the following steps (read with events())."""
         self._ev = (CEvent * capacity)()
         lib().orc_solver_trace(self._h, self._ev, capacity)
+
+    def iterate(self, n):
+        """The last Newton iterate of the most recent step (n values)."""
+        u = np.empty(n)
+        lib().orc_solver_iterate(self._h, _d(u))
+        return u
 
     def events(self) -> list:
         n = lib().orc_solver_trace_len(self._h)

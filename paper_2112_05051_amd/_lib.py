@@ -58,12 +58,38 @@ class StepStats(C.Structure):
                 ("linsolve_fails", C.c_int), ("levels", C.c_int),
                 ("fnorm_inf", C.c_double), ("mass_residual", C.c_double),
                 ("min_lambda", C.c_double), ("opc", C.c_double),
-                ("t_feval", C.c_double), ("t_jac", C.c_double), ("t_setup", C.c_double),
-                ("t_linsol", C.c_double), ("t_total", C.c_double)]
+                ("t_feval", C.c_double), ("t_jac", C.c_double), ("t_aux", C.c_double),
+                ("t_setup", C.c_double), ("t_linsol", C.c_double), ("t_overhead", C.c_double),
+                ("t_total", C.c_double), ("bytes_feval", C.c_double), ("bytes_jac", C.c_double),
+                ("bytes_linsol", C.c_double), ("bytes_overhead", C.c_double)]
+
+
+TRACE_TRIALS = 48
+EV_ACCEPT, EV_ACCEPT_SHORT, EV_RETRY_GMRES, EV_RETRY_SLOPE, EV_RETRY_LS = 0, 1, 2, 3, 4
+EV_FAIL_SLOPE, EV_FAIL_LS, EV_STALL, EV_FAIL_OTHER = 5, 6, 7, 8
+RB_NOJ, RB_MSBSET, RB_BIGSTEP, RB_RETRY = 1, 2, 4, 8
+
+
+class NewtonEvent(C.Structure):
+    _fields_ = [("step", C.c_int), ("newton_it", C.c_int), ("since_build", C.c_int), ("reason", C.c_int),
+                ("gmres_its", C.c_int), ("gmres_conv", C.c_int), ("truncated", C.c_int), ("outcome", C.c_int),
+                ("ntrial", C.c_int), ("nback", C.c_int),
+                ("f0", C.c_double), ("slope", C.c_double), ("dnorm2", C.c_double), ("dnorminf", C.c_double),
+                ("rel_d", C.c_double), ("mxstep", C.c_double), ("lam", C.c_double), ("f_acc", C.c_double),
+                ("step_inf", C.c_double), ("step_rel", C.c_double), ("fnorm_inf", C.c_double),
+                ("trial_lam", C.c_double * TRACE_TRIALS), ("trial_f", C.c_double * TRACE_TRIALS)]
+
+
+def event_dict(e) -> dict:
+    d = {f: getattr(e, f) for f, _ in e._fields_ if not f.startswith("trial_")}
+    k = min(e.ntrial, TRACE_TRIALS)
+    d["trial_lam"] = [e.trial_lam[i] for i in range(k)]
+    d["trial_f"] = [e.trial_f[i] for i in range(k)]
+    return d
 
 
 EXPORTS = ["rich_query_bytes", "rich_create", "rich_destroy", "rich_set_state", "rich_get_state",
-           "rich_step", "rich_status_string", "rich_eval_theta", "rich_eval_residual",
+           "rich_step", "rich_trace_newton", "rich_trace_count", "rich_status_string", "rich_eval_theta", "rich_eval_residual",
            "rich_assemble", "rich_setup_hierarchy", "rich_apply_jacobian", "rich_apply_aux",
            "rich_apply_prec", "rich_gmres", "rich_levels", "rich_level_size", "rich_export_csr",
            "rich_export_aggregates", "rich_match_sweep", "rich_profile", "rich_profile_read",
@@ -93,6 +119,8 @@ def load(path: str = LIB_PATH):
     L.rich_set_state.argtypes = [vp, vp]
     L.rich_get_state.argtypes = [vp, vp]
     L.rich_step.argtypes = [vp, C.c_int, P(StepStats)]
+    L.rich_trace_newton.argtypes = [vp, P(NewtonEvent), C.c_int]
+    L.rich_trace_count.argtypes = [vp, i64p]
     L.rich_status_string.argtypes = [C.c_int]
     L.rich_status_string.restype = C.c_char_p
     L.rich_eval_theta.argtypes = [vp, vp, vp]
@@ -234,6 +262,18 @@ class Solver:
         if raise_on_error and rc < 0:
             raise RichError(rc, "rich_step")
         return out
+
+    def trace(self, capacity: int = 4096):
+        """Record the Newton attempts of the following steps (read with events())."""
+        self._ev = (NewtonEvent * capacity)()
+        _check(self._L.rich_trace_newton(self._h, self._ev, capacity), "rich_trace_newton")
+
+    def events(self) -> list:
+        n = C.c_int64()
+        _check(self._L.rich_trace_count(self._h, C.byref(n)), "rich_trace_count")
+        if n.value > len(self._ev):
+            raise RuntimeError("trace capacity exceeded")
+        return [event_dict(self._ev[i]) for i in range(n.value)]
 
     def theta(self, p):
         out = self._new()

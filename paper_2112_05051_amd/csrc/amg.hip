@@ -348,7 +348,7 @@ __global__ void k_csr_invd(int64_t n, const int64_t *__restrict__ rowptr, const 
     double s = 0.0;
     for (int64_t e = rowptr[i]; e < rowptr[i + 1]; e++) s += fabs(val[e]);
     if (invd) invd[i] = 1.0 / s;
-    if (invdf) invdf[i] = (float)(1.0 / s);
+    if (invdf) invdf[i] = f32_sat(1.0 / s);
 }
 
 __global__ void k_compose(int64_t n, int32_t *__restrict__ comp, const int32_t *__restrict__ a) {

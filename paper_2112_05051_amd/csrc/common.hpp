@@ -33,6 +33,19 @@ const char *last_error();
 
 #define LAUNCH_CHECK() HIP_TRY(hipGetLastError())
 
+// FP64 -> FP32 for the single-precision copies of the preconditioner: values
+// beyond FP32's range saturate at +-FLT_MAX instead of becoming infinite (a
+// Newton iterate far outside the physical range makes the auxiliary matrix's
+// entries tiny and its inverse diagonal huge); NaN stays NaN.
+__device__ inline float f32_sat(double x) {
+    constexpr double m = 3.4028234663852886e38;
+    return (float)(x > m ? m : (x < -m ? -m : x));
+}
+template <class TB, class TA>
+__device__ inline TB convert(TA x) { return (TB)x; }
+template <>
+__device__ inline float convert<float, double>(double x) { return f32_sat(x); }
+
 // XCD-aware block order.  Workgroups are dealt round-robin over the 8 XCDs
 // (each with its own L2); this maps them so that XCD x processes one
 // contiguous range of logical blocks, keeping the +-nx and +-nx*ny stencil

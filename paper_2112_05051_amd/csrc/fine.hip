@@ -244,13 +244,13 @@ __global__ void k_assemble(Phys P, uint32_t n, const double *__restrict__ Ks, co
 #pragma unroll
     for (int f = 0; f < 6; f++) l1 += fabs(moff[f]);
     if (M4f) {
-        M4f[(size_t)M_D * n + c] = (float)md;
-        M4f[(size_t)M_XP * n + c] = (float)moff[1];
-        M4f[(size_t)M_YP * n + c] = (float)moff[3];
-        M4f[(size_t)M_ZP * n + c] = (float)moff[5];
+        M4f[(size_t)M_D * n + c] = f32_sat(md);
+        M4f[(size_t)M_XP * n + c] = f32_sat(moff[1]);
+        M4f[(size_t)M_YP * n + c] = f32_sat(moff[3]);
+        M4f[(size_t)M_ZP * n + c] = f32_sat(moff[5]);
     }
     if (invd) invd[c] = 1.0 / l1;
-    if (invdf) invdf[c] = (float)(1.0 / l1);
+    if (invdf) invdf[c] = f32_sat(1.0 / l1);
 }
 
 // y = J x, J in the 7-array stencil form; x may be FP32 (mixed path).

@@ -317,7 +317,7 @@ __global__ void k_negate_to(const double *__restrict__ x, double *__restrict__ y
 template <class TA, class TB>
 __global__ void k_cast(const TA *__restrict__ a, TB *__restrict__ b, int64_t n) {
     int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c < n) b[c] = (TB)a[c];
+    if (c < n) b[c] = convert<TB>(a[c]);
 }
 
 __global__ void k_fill_i32(int32_t *x, int32_t v, int64_t n) {

@@ -88,13 +88,16 @@ void run_request(rich_server *S, hipStream_t stream, Request &R, rich_batcher *b
     if (st == RICH_OK) st = rich_create(&R.prob, &R.opts, dks, stream, &h);
     if (st == RICH_OK && S->fused) st = batcher ? rich::batcher_attach(h, batcher) : RICH_EHIP;
     if (st == RICH_OK) st = rich_set_state(h, dp);
+    rich_status warn = RICH_OK;  // largest warning of a completed step
     for (int t = 0; t < R.nsteps && st >= 0; t++) {
         double t0 = wall_s();
         rich_step_stats_t ss;
         st = rich_step(h, 1, &ss);
         R.step_ms.push_back(1e3 * (wall_s() - t0));
         R.stats.push_back(ss);
+        if (st > warn) warn = st;
     }
+    if (st >= 0) st = warn;
     if (h) {
         rich_status g = rich_get_state(h, dp);
         if (g == RICH_OK && hipMemcpyAsync(R.p.data(), dp, N * sizeof(double), hipMemcpyDeviceToHost, stream) == hipSuccess)

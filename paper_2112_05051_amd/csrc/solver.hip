@@ -71,8 +71,14 @@ struct rich_ctx {
     Hierarchy *H = nullptr;
     bool have_J = false;
     int since_build = 0;
-    // stats of the step in progress
+    // stats of the step in progress, and the phase whose bytes kernels add to
     rich_step_stats_t *cur = nullptr;
+    double *phase_bytes = nullptr;
+    // record of the Newton controller (rich_trace_newton)
+    int nstep = 0;
+    rich_newton_event_t *trace = nullptr;
+    int trace_cap = 0;
+    int64_t trace_len = 0;
     // optional per-kernel event timing
     struct KProf {
         int64_t launches = 0;
@@ -150,9 +156,15 @@ rich_status prof_event(rich_ctx *h, hipEvent_t *e) {
     return RICH_OK;
 }
 
+// Add a launch's algorithmic bytes to the phase in progress.
+inline void charge(rich_ctx *h, double bytes) {
+    if (h->phase_bytes) *h->phase_bytes += bytes;
+}
+
 // Launch through `f`, bracketed by events when profiling is on.
 template <class F>
 rich_status timed(rich_ctx *h, int id, double bytes, F &&f) {
+    charge(h, bytes);
     if (!h->profiling || id >= RICH_K_COUNT) return f();
     hipEvent_t a, b;
     RICH_TRY(prof_event(h, &a));
@@ -385,8 +397,14 @@ rich_status vcycle(rich_ctx *h, const double *b, const double *bs, T *z) {
     const T *invd0 = h->mixed ? (const T *)(const void *)h->invd0f : (const T *)(const void *)h->invd0;
     const T *cinv = h->mixed ? (const T *)(const void *)H.cinvf : (const T *)(const void *)H.cinv;
     if (H.nlev == 1) {
+        const double n = (double)h->N, t = sizeof(T);
         RICH_TRY(launch_scale_copy(b, bs, h->bsc, h->N, s));
-        if (H.dense) return launch_dense_gemv<double, T>(cinv, h->bsc, z, h->N, s);
+        charge(h, 16 * n);
+        if (H.dense) {
+            charge(h, n * n * t + 8 * n + t * n);
+            return launch_dense_gemv<double, T>(cinv, h->bsc, z, h->N, s);
+        }
+        charge(h, h->O.coarse_l1_sweeps * n * (5 * t + 16));
         return launch_st_sweeps<double, T>(h->P, M4, invd0, h->bsc, z, (T *)h->ztmp, h->O.coarse_l1_sweeps, s);
     }
     const double t = sizeof(T), n0 = (double)h->N, n1 = (double)H.L[1].n;
@@ -411,14 +429,17 @@ rich_status vcycle(rich_ctx *h, const double *b, const double *bs, T *z) {
         RICH_TRY(timed(h, l == 1 ? RICH_K_VC1_PRE : RICH_K_COUNT, bytes, [&] {
             return launch_csr_pre<T, T>(Lv, lvval<T>(Lv), (const T *)Lv.x, (const T *)Lv.b, (T *)Lv.r, s);
         }));
+        charge(h, (double)Lv.n * (t + 4) + (double)H.L[l + 1].n * (8 + t));
         RICH_TRY(launch_restrict<T>(Lv, (const T *)Lv.r, (T *)H.L[l + 1].b, H.L[l + 1].n, lvinvd<T>(H.L[l + 1]),
                                     x0_of(l + 1), s));
     }
     // coarsest
     Level &Lc = H.L[H.nlev - 1];
     if (H.dense) {
+        charge(h, (double)Lc.n * Lc.n * t + 2.0 * Lc.n * t);
         RICH_TRY(launch_dense_gemv<T, T>(cinv, (const T *)Lc.b, (T *)Lc.x, Lc.n, s));
     } else {
+        charge(h, h->O.coarse_l1_sweeps * ((double)Lc.nnz * (4 + t) + (double)Lc.n * (8 + 4 * t)));
         RICH_TRY(launch_csr_sweeps<T, T>(Lc, lvval<T>(Lc), lvinvd<T>(Lc), (const T *)Lc.b, (T *)Lc.x, (T *)Lc.r,
                                          h->O.coarse_l1_sweeps, s));
     }
@@ -699,6 +720,7 @@ rich_status gmres(rich_ctx *h, const double *b, double *x, int *its_out, double 
     RICH_TRY(norms(h, b, nb));
     double bnorm = std::sqrt(nb[2]);
     RICH_TRY(launch_fill_f64(x, 0.0, N, s));
+    charge(h, 16.0 * N);
     int total = 0;
     bool conv = false;
     double relres = 0.0;
@@ -730,10 +752,13 @@ rich_status gmres(rich_ctx *h, const double *b, double *x, int *its_out, double 
         // true residual into V_0 (stored unnormalised, scale 1/beta on the device)
         if (first) {
             HIP_TRY(hipMemcpyAsync(h->V, b, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+            charge(h, 16.0 * N);
         } else {
             RICH_TRY(launch_spmv_J<double>(h->P, h->J7, x, h->V, s));
             RICH_TRY(launch_b_minus(b, h->V, N, s));
+            charge(h, 72.0 * N + 24.0 * N);
         }
+        charge(h, 8.0 * N);  // norms of V_0
         first = false;
         double rn[3];
         RICH_TRY(norms(h, h->V, rn));
@@ -819,6 +844,7 @@ rich_status gmres(rich_ctx *h, const double *b, double *x, int *its_out, double 
         RICH_TRY(launch_lincomb(h->V, ld, k, h->dres, h->vs, h->work, N, s));
         RICH_TRY(prec_product(h, h->work, h->one, nullptr));
         RICH_TRY(add_z(h, x));
+        charge(h, 8.0 * (k + 1) * N + (16.0 + (h->mixed ? 4 : 8)) * N);
         RICH_TRY(sync(h));  // hres is reused before the next read
     }
     *its_out = total;
@@ -828,34 +854,54 @@ rich_status gmres(rich_ctx *h, const double *b, double *x, int *its_out, double 
 }
 
 // ----------------------------------------------------------------- Newton
+// Host seconds since t0, added to one phase timer of the step in progress.
+struct PhaseClock {
+    rich_ctx *h;
+    double *timer, *bytes_sink, *saved_sink, t0;
+    PhaseClock(rich_ctx *hh, double *t, double *b) : h(hh), timer(t), bytes_sink(b), saved_sink(hh->phase_bytes) {
+        t0 = now_s();
+        if (h->cur) h->phase_bytes = b;
+    }
+    ~PhaseClock() { h->phase_bytes = saved_sink; }
+    rich_status stop() {
+        if (!h->cur) return RICH_OK;
+        RICH_TRY(sync(h));
+        *timer += now_s() - t0;
+        return RICH_OK;
+    }
+};
+
 rich_status feval(rich_ctx *h, const double *u, double *F) {
-    double t0 = now_s();
+    rich_step_stats_t *st = h->cur;
+    PhaseClock clk(h, st ? &st->t_feval : nullptr, st ? &st->bytes_feval : nullptr);
     RICH_TRY(timed(h, RICH_K_RESIDUAL, (double)h->N * 32,
                    [&] { return launch_residual(h->P, h->Ks, u, h->theta_old, F, h->s); }));
-    if (h->cur) {
-        RICH_TRY(sync(h));
-        h->cur->t_feval += now_s() - t0;
-    }
-    return RICH_OK;
+    return clk.stop();
 }
 
+// J and M at u in one pass over the grid; then the preconditioner: the full
+// AMG set-up the first time, else its numeric update from the new M.
 rich_status rebuild(rich_ctx *h, const double *u) {
-    double t0 = now_s();
-    RICH_TRY(launch_assemble(h->P, h->Ks, u, h->J7, h->M4, h->mixed ? h->M4f : nullptr, h->invd0,
-                             h->mixed ? h->invd0f : nullptr, h->O.aux_dflux, h->s));
-    RICH_TRY(sync(h));
-    double t1 = now_s();
-    if (h->cur) {
-        h->cur->t_jac += t1 - t0;
-        h->cur->jac_builds++;
+    rich_step_stats_t *st = h->cur;
+    {
+        PhaseClock clk(h, st ? &st->t_jac : nullptr, st ? &st->bytes_jac : nullptr);
+        charge(h, (double)h->N * (16 + 56 + 32 + 8 + (h->mixed ? 20 : 0)));
+        RICH_TRY(launch_assemble(h->P, h->Ks, u, h->J7, h->M4, h->mixed ? h->M4f : nullptr, h->invd0,
+                                 h->mixed ? h->invd0f : nullptr, h->O.aux_dflux, h->s));
+        RICH_TRY(sync(h));
+        RICH_TRY(clk.stop());
     }
+    if (st) st->jac_builds++;
     if (!h->H) {
+        PhaseClock clk(h, st ? &st->t_setup : nullptr, nullptr);
         RICH_TRY(build_hierarchy(h));
-        if (h->cur) h->cur->amg_setups++;
+        RICH_TRY(clk.stop());
+        if (st) st->amg_setups++;
     } else {
+        PhaseClock clk(h, st ? &st->t_aux : nullptr, nullptr);
         RICH_TRY(refresh_hierarchy(h));
+        RICH_TRY(clk.stop());
     }
-    if (h->cur) h->cur->t_setup += now_s() - t1;
     h->have_J = true;
     h->since_build = 0;
     return RICH_OK;
@@ -864,214 +910,300 @@ rich_status rebuild(rich_ctx *h, const double *u) {
 // f = 0.5 ||F||^2 and ||F||_inf
 rich_status fnorms(rich_ctx *h, const double *F, double *f_half, double *finf) {
     double n3[3];
+    charge(h, 8.0 * h->N);
     RICH_TRY(norms(h, F, n3));
     *f_half = 0.5 * n3[2];
     *finf = n3[0];
     return RICH_OK;
 }
 
-// Line search of Section 3 (Armijo-Goldstein), backtracking as in Dennis &
-// Schnabel's Algorithm A6.3.1: quadratic then cubic model minimisers clamped
-// to [0.1, 0.5] of the last step; the beta condition lengthens a full step
-// shorter than the maximum step.  On success ut/Ft hold the accepted point.
-rich_status line_search(rich_ctx *h, double slope, double mxstep, bool truncated, double f0, double *lam_out,
-                        int *nback) {
-    int64_t N = h->N;
-    const double alpha = h->O.ls_alpha, beta = 0.9;
-    RICH_TRY(launch_rel_length(h->d, h->u, N, h->partial, h->dres, h->s));
-    double rl;
-    RICH_TRY(readback(h, h->dres, 1, &rl));
-    double lam_min = rl > 0.0 ? h->O.scsteptol / rl : 0.0;
-    double lam = 1.0, lam_prev = 0.0, f_prev = 0.0;
-    bool first = true;
-    *nback = 0;
-    for (;;) {
-        RICH_TRY(launch_xpay_to(h->u, lam, h->d, h->ut, N, h->s));
-        RICH_TRY(feval(h, h->ut, h->Ft));
-        double ft, finf;
-        RICH_TRY(fnorms(h, h->Ft, &ft, &finf));
-        if (std::isfinite(ft) && ft <= f0 + alpha * lam * slope) break;
-        if (lam < lam_min) return RICH_LINESEARCH_FAIL;
+void record_trial(rich_newton_event_t *ev, double lam, double f) {
+    if (ev->ntrial < RICH_TRACE_TRIALS) {
+        ev->trial_lam[ev->ntrial] = lam;
+        ev->trial_f[ev->ntrial] = f;
+    }
+    ev->ntrial++;
+}
+
+// Next trial step of the backtracking line search after the trial
+// (lam, f(u + lam d)) failed the Armijo condition: Dennis & Schnabel's
+// Algorithm A6.3.1, a published method.  The model of f along d takes
+// f(0) = f0 and f'(0) = slope; the first reduction minimises the parabola
+// through the trial, later ones the cubic through the last two finite trials.
+// A non-finite trial gives no model and cuts the step to a tenth.  The result
+// is kept in [0.1 lam, 0.5 lam].
+struct Backtrack {
+    double f0, slope;
+    bool have = false;     // a finite trial is on record: cubic model next
+    double lp = 0.0, fp = 0.0;
+
+    double next(double lam, double ft) {
         double lt;
         if (!std::isfinite(ft)) {
             lt = 0.1 * lam;
-        } else if (first) {
-            lt = -slope / (2.0 * (ft - f0 - slope));
-            first = false;
         } else {
-            double t1 = ft - f0 - lam * slope;
-            double t2 = f_prev - f0 - lam_prev * slope;
-            double a = (t1 / (lam * lam) - t2 / (lam_prev * lam_prev)) / (lam - lam_prev);
-            double b = (-lam_prev * t1 / (lam * lam) + lam * t2 / (lam_prev * lam_prev)) / (lam - lam_prev);
-            if (a == 0.0) {
-                lt = -slope / (2.0 * b);
+            const double r = ft - f0 - slope * lam;  // what the linear model misses at lam
+            if (!have) {
+                lt = -slope * lam * lam / (2.0 * r);
             } else {
-                double disc = b * b - 3.0 * a * slope;
-                lt = disc < 0.0 ? 0.5 * lam : (-b + std::sqrt(disc)) / (3.0 * a);
+                // c(x) = f0 + slope x + b x^2 + a x^3 through (lp, fp) and (lam, ft)
+                const double rp = fp - f0 - slope * lp;
+                const double l2 = lam * lam, p2 = lp * lp;
+                const double det = l2 * p2 * (lp - lam);
+                const double b = (r * p2 * lp - rp * l2 * lam) / det;
+                const double a = (rp * l2 - r * p2) / det;
+                if (a == 0.0) {
+                    lt = -slope / (2.0 * b);
+                } else {
+                    const double disc = b * b - 3.0 * a * slope;
+                    if (disc < 0.0) lt = 0.5 * lam;
+                    else if (b >= 0.0) lt = -slope / (b + std::sqrt(disc));  // the root c' = 0, no cancellation
+                    else lt = (std::sqrt(disc) - b) / (3.0 * a);
+                }
             }
+            have = true;
+            lp = lam;
+            fp = ft;
         }
-        if (std::isfinite(ft)) {
-            lam_prev = lam;
-            f_prev = ft;
-        }
-        if (!(lt <= 0.5 * lam)) lt = 0.5 * lam;
+        if (!(lt <= 0.5 * lam)) lt = 0.5 * lam;  // also catches NaN
         if (!(lt >= 0.1 * lam)) lt = 0.1 * lam;
-        lam = lt;
-        (*nback)++;
+        return lt;
+    }
+};
+
+// Line search of Section 3 (Armijo-Goldstein) along d from u.  Trials are
+// taken until f(u + lam d) <= f0 + alpha lam slope; below the smallest step
+// scsteptol / max_i(|d_i| / max(|u_i|, 1)) it gives up.  A full step that
+// was not truncated and beats the beta = 0.9 bound of the linear model is
+// doubled while the doubled step keeps the Armijo condition and stays within
+// the maximum step (at most ten times).  On success ut/Ft hold the point.
+rich_status line_search(rich_ctx *h, double f0, double slope, double mxstep, bool truncated, double dnorm,
+                        rich_newton_event_t *ev, double *lam_out) {
+    const int64_t N = h->N;
+    const double alpha = h->O.ls_alpha, beta = 0.9;
+    charge(h, 16.0 * N);
+    RICH_TRY(launch_rel_length(h->d, h->u, N, h->partial, h->dres, h->s));
+    RICH_TRY(readback(h, h->dres, 1, &ev->rel_d));
+    const double lam_min = ev->rel_d > 0.0 ? h->O.scsteptol / ev->rel_d : 0.0;
+    auto armijo = [&](double lam, double f) { return std::isfinite(f) && f <= f0 + alpha * lam * slope; };
+    auto trial = [&](double lam, double *x, double *Fx, double *f) -> rich_status {
+        charge(h, 24.0 * N);
+        RICH_TRY(launch_xpay_to(h->u, lam, h->d, x, N, h->s));
+        RICH_TRY(feval(h, x, Fx));
+        double finf;
+        RICH_TRY(fnorms(h, Fx, f, &finf));
+        record_trial(ev, lam, *f);
+        return RICH_OK;
+    };
+    Backtrack model{f0, slope};
+    double lam = 1.0, ft;
+    for (;;) {
+        RICH_TRY(trial(lam, h->ut, h->Ft, &ft));
+        if (armijo(lam, ft)) break;
+        if (lam < lam_min) return RICH_LINESEARCH_FAIL;
+        lam = model.next(lam, ft);
+        ev->nback++;
     }
     if (lam == 1.0 && !truncated) {
-        double nd[3];
-        RICH_TRY(norms(h, h->d, nd));
-        double dn = std::sqrt(nd[2]);
-        double ft, finf;
-        RICH_TRY(fnorms(h, h->Ft, &ft, &finf));
-        int tries = 0;
-        while (ft < f0 + beta * lam * slope && 2.0 * lam * dn <= mxstep && tries < 10) {
-            double lt = 2.0 * lam;
-            RICH_TRY(launch_xpay_to(h->u, lt, h->d, h->ub, N, h->s));
-            RICH_TRY(feval(h, h->ub, h->Fb));
-            double fb, fbinf;
-            RICH_TRY(fnorms(h, h->Fb, &fb, &fbinf));
-            if (!(std::isfinite(fb) && fb <= f0 + alpha * lt * slope)) break;
-            lam = lt;
+        for (int k = 0; k < 10 && ft < f0 + beta * lam * slope && 2.0 * lam * dnorm <= mxstep; k++) {
+            double fb;
+            RICH_TRY(trial(2.0 * lam, h->ub, h->Fb, &fb));
+            if (!armijo(2.0 * lam, fb)) break;
+            lam *= 2.0;
             ft = fb;
             std::swap(h->ut, h->ub);
             std::swap(h->Ft, h->Fb);
-            tries++;
         }
     }
     *lam_out = lam;
     return RICH_OK;
 }
 
-// One backward-Euler step (Section 2.1) by the modified inexact Newton
-// method of Section 3; the Jacobian re-use rules of eq.
-// (jacobian_update_condition) with the counter persisting across steps.
 struct CurGuard {
     rich_ctx *h;
-    ~CurGuard() { h->cur = nullptr; }
+    ~CurGuard() {
+        h->cur = nullptr;
+        h->phase_bytes = nullptr;
+    }
 };
 
+void push_event(rich_ctx *h, const rich_newton_event_t &ev) {
+    if (!h->trace) return;
+    if (h->trace_len < h->trace_cap) h->trace[h->trace_len] = ev;
+    h->trace_len++;
+}
+
+// One backward-Euler step (Section 2.1) by the modified inexact Newton
+// method of Section 3, from the previous level.  Each attempt first applies
+// the rebuild test of eq. (jacobian_update_condition): J (with M and the
+// preconditioner) is rebuilt when none exists yet, after msbset iterations
+// since the last rebuild (the count carries over from step to step: J is
+// re-used across steps, Section 6), after a step with ||lam d||_inf > 1.5,
+// or when the previous attempt asked for a retry.  A stale J that lets
+// GMRES fail, gives no descent direction or makes the line search fail is
+// rebuilt and the attempt repeated; with a fresh J these end the step.  A
+// step shorter than scsteptol asks for a rebuild (stale J) or ends the step
+// with the warning RICH_STEP_TOO_SMALL (fresh J, state kept).
 rich_status newton_step(rich_ctx *h, rich_step_stats_t *st) {
-    int64_t N = h->N;
+    const int64_t N = h->N;
     hipStream_t s = h->s;
     memset(st, 0, sizeof(*st));
     st->min_lambda = 1.0;
     h->cur = st;
+    h->phase_bytes = &st->bytes_overhead;
     CurGuard guard{h};
-    double t_start = now_s();
+    const int step_index = h->nstep++;
+    const double t_start = now_s();
     double pn[3];
     RICH_TRY(norms(h, h->p, pn));
     if (!std::isfinite(pn[0])) return st->status = RICH_NONFINITE;
     RICH_TRY(launch_theta(h->P, h->p, h->theta_old, s));
     HIP_TRY(hipMemcpyAsync(h->u, h->p, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    charge(h, 8.0 * N + 16.0 * N + 16.0 * N);
     RICH_TRY(feval(h, h->u, h->F));
     double f0, fnorm;
     RICH_TRY(fnorms(h, h->F, &f0, &fnorm));
     if (!std::isfinite(fnorm)) return st->status = RICH_NONFINITE;
     double mxstep = h->O.mxnewtstep;
-    if (!(mxstep > 0.0)) {
-        double un = std::sqrt(pn[2]);
-        mxstep = 1000.0 * (un > 1.0 ? un : 1.0);
-    }
-    double prev_step = 0.0;
+    if (!(mxstep > 0.0)) mxstep = 1000.0 * std::max(std::sqrt(pn[2]), 1.0);
+
+    double prev_step = 0.0;  // ||lam d||_inf of the last accepted step of this time step
     bool retry = false;
     rich_status status = RICH_OK;
+    rich_newton_event_t ev;
+    // ends the attempt: record it and, for a retry, ask for a rebuild
+    auto finish = [&](int outcome) {
+        ev.outcome = outcome;
+        push_event(h, ev);
+        retry = outcome == RICH_EV_RETRY_GMRES || outcome == RICH_EV_RETRY_SLOPE || outcome == RICH_EV_RETRY_LS ||
+                outcome == RICH_EV_ACCEPT_SHORT;
+    };
     while (fnorm > h->O.fnormtol) {
         if (st->newton_its >= h->O.max_newton) {
             status = RICH_MAXITER;
             break;
         }
-        bool fresh = false;
-        if (!h->have_J || h->since_build >= h->O.msbset || prev_step > 1.5 || retry) {
+        memset(&ev, 0, sizeof(ev));
+        ev.step = step_index;
+        ev.newton_it = st->newton_its;
+        ev.since_build = h->since_build;
+        ev.mxstep = mxstep;
+        ev.f0 = f0;
+        if (!h->have_J) ev.reason |= RICH_RB_NOJ;
+        else if (h->since_build >= h->O.msbset) ev.reason |= RICH_RB_MSBSET;
+        if (prev_step > 1.5) ev.reason |= RICH_RB_BIGSTEP;
+        if (retry) ev.reason |= RICH_RB_RETRY;
+        const bool fresh = ev.reason != 0;
+        if (fresh) {
             rich_status rc = rebuild(h, h->u);
             if (rc != RICH_OK) {
                 status = rc;
+                finish(RICH_EV_FAIL_OTHER);
                 break;
             }
-            fresh = true;
-            retry = false;
         }
-        double t0 = now_s();
-        RICH_TRY(launch_negate_to(h->F, h->rhs, N, s));
+        retry = false;
+        // linear solve J d = -F
         int its;
         double relres;
         bool conv;
-        RICH_TRY(gmres(h, h->rhs, h->d, &its, &relres, &conv));
+        {
+            PhaseClock clk(h, &st->t_linsol, &st->bytes_linsol);
+            charge(h, 16.0 * N);
+            RICH_TRY(launch_negate_to(h->F, h->rhs, N, s));
+            RICH_TRY(gmres(h, h->rhs, h->d, &its, &relres, &conv));
+            RICH_TRY(clk.stop());
+        }
         st->gmres_its += its;
-        st->t_linsol += now_s() - t0;
+        ev.gmres_its = its;
+        ev.gmres_conv = conv;
         if (!conv) {
             st->linsolve_fails++;
             if (!fresh) {
-                retry = true;
+                finish(RICH_EV_RETRY_GMRES);
                 continue;
             }
         }
-        bool truncated = false;
+        // step limit, slope of f along d
         double dn3[3];
+        charge(h, 8.0 * N);
         RICH_TRY(norms(h, h->d, dn3));
         double dn = std::sqrt(dn3[2]);
         if (dn > mxstep) {
+            charge(h, 16.0 * N + 8.0 * N);
             RICH_TRY(launch_scale(h->d, mxstep / dn, N, s));
-            truncated = true;
+            RICH_TRY(norms(h, h->d, dn3));
+            dn = std::sqrt(dn3[2]);
+            ev.truncated = 1;
         }
+        ev.dnorm2 = dn;
+        ev.dnorminf = dn3[0];
+        charge(h, 72.0 * N + 16.0 * N);
         RICH_TRY(launch_spmv_J<double>(h->P, h->J7, h->d, h->Jd, s));
-        double slope;
-        RICH_TRY(dotp(h, h->F, h->Jd, &slope));
-        if (!(slope < 0.0)) {
+        RICH_TRY(dotp(h, h->F, h->Jd, &ev.slope));
+        if (!(ev.slope < 0.0)) {
             if (!fresh) {
-                retry = true;
+                finish(RICH_EV_RETRY_SLOPE);
                 continue;
             }
             status = RICH_LINSOLVE_FAIL;
+            finish(RICH_EV_FAIL_SLOPE);
             break;
         }
-        double fcur = f0;
         double lam;
-        int nb;
-        rich_status rc = line_search(h, slope, mxstep, truncated, fcur, &lam, &nb);
-        st->ls_backtracks += nb;
+        rich_status rc = line_search(h, f0, ev.slope, mxstep, ev.truncated != 0, dn, &ev, &lam);
+        st->ls_backtracks += ev.nback;
         if (rc == RICH_LINESEARCH_FAIL) {
             if (!fresh) {
-                retry = true;
+                finish(RICH_EV_RETRY_LS);
                 continue;
             }
             status = rc;
+            finish(RICH_EV_FAIL_LS);
             break;
         }
         RICH_TRY(rc);
-        if (lam < st->min_lambda) st->min_lambda = lam;
-        double dinf[3];
-        RICH_TRY(norms(h, h->d, dinf));
-        double step_inf = lam * dinf[0];
+        // accept u + lam d
+        st->min_lambda = std::min(st->min_lambda, lam);
+        ev.lam = lam;
+        ev.step_inf = lam * ev.dnorminf;
+        charge(h, 16.0 * N);
         RICH_TRY(launch_rel_length(h->d, h->ut, N, h->partial, h->dres, s));
-        double rl;
-        RICH_TRY(readback(h, h->dres, 1, &rl));
-        double step_rel = lam * rl;
+        RICH_TRY(readback(h, h->dres, 1, &ev.step_rel));
+        ev.step_rel *= lam;
         std::swap(h->u, h->ut);
         std::swap(h->F, h->Ft);
         st->newton_its++;
         h->since_build++;
         RICH_TRY(fnorms(h, h->F, &f0, &fnorm));
+        ev.f_acc = f0;
+        ev.fnorm_inf = fnorm;
         if (!std::isfinite(fnorm)) {
             status = RICH_NONFINITE;
+            finish(RICH_EV_FAIL_OTHER);
             break;
         }
-        if (fnorm <= h->O.fnormtol) break;
-        if (step_rel < h->O.scsteptol) {
-            if (!fresh) {
-                retry = true;
-            } else {
+        if (fnorm <= h->O.fnormtol) {
+            finish(RICH_EV_ACCEPT);
+            break;
+        }
+        if (ev.step_rel < h->O.scsteptol) {
+            if (fresh) {
                 status = RICH_STEP_TOO_SMALL;
+                finish(RICH_EV_STALL);
                 break;
             }
+            finish(RICH_EV_ACCEPT_SHORT);
+        } else {
+            finish(RICH_EV_ACCEPT);
         }
-        prev_step = step_inf;
+        prev_step = ev.step_inf;
     }
     st->fnorm_inf = fnorm;
     if (status == RICH_OK || status == RICH_STEP_TOO_SMALL) {
         HIP_TRY(hipMemcpyAsync(h->p, h->u, N * sizeof(double), hipMemcpyDeviceToDevice, s));
         double fn[3];
+        charge(h, 16.0 * N + 8.0 * N);
         RICH_TRY(norms(h, h->F, fn));
         st->mass_residual = h->P.dt * fn[1];
     }
@@ -1081,8 +1213,8 @@ rich_status newton_step(rich_ctx *h, rich_step_stats_t *st) {
     }
     RICH_TRY(sync(h));
     st->t_total = now_s() - t_start;
+    st->t_overhead = st->t_total - (st->t_feval + st->t_jac + st->t_aux + st->t_setup + st->t_linsol);
     st->status = status;
-    h->cur = nullptr;
     return status;
 }
 
@@ -1323,12 +1455,28 @@ rich_status rich_get_state(rich_handle_t h, double *p_dev) {
 
 rich_status rich_step(rich_handle_t h, int nsteps, rich_step_stats_t *stats_host) {
     if (!h || nsteps < 0) return RICH_EINVAL;
+    rich_status warn = RICH_OK;
     for (int t = 0; t < nsteps; t++) {
         rich_step_stats_t st;
         rich_status rc = newton_step(h, &st);
         if (stats_host) stats_host[t] = st;
         if (rc < 0) return rc;
+        warn = std::max(warn, rc);
     }
+    return warn;
+}
+
+rich_status rich_trace_newton(rich_handle_t h, rich_newton_event_t *events_host, int capacity) {
+    if (!h || (events_host && capacity < 0)) return RICH_EINVAL;
+    h->trace = events_host;
+    h->trace_cap = events_host ? capacity : 0;
+    h->trace_len = 0;
+    return RICH_OK;
+}
+
+rich_status rich_trace_count(rich_handle_t h, int64_t *count_host) {
+    if (!h || !count_host) return RICH_EINVAL;
+    *count_host = h->trace_len;
     return RICH_OK;
 }
 

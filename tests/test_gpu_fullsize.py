@@ -111,3 +111,38 @@ def test_paper_3d_full_size_step(rich, torch, orc):
     top = pg.reshape(P.nz, P.ny, P.nx)[-1]
     assert top.max() > p0.max() + 1.0
     s.close()
+
+
+def test_full_size_vcycle_and_gmres_c2(rich, torch, orc):
+    """128^3 (2^21 rows: the wide Gram-Schmidt kernels and the speculative
+    Arnoldi step of large grids): one FP64 V-cycle on the GPU's own auxiliary
+    matrix equals the oracle's V-cycle on that matrix (Section 5.2), and one
+    GMRES(30) solve of a Newton correction matches the oracle's (iterations
+    within one, solutions within 10 eta; Section 6's stopping rule)."""
+    rec = synth.recipe("c2")
+    P, opts = rec.problem, rec.options
+    assert P.n == 1 << 21 and opts.precision == synth.FP64
+    ks, p0 = rec.ks(), rec.p0()
+    rng = np.random.default_rng(7)
+    p1 = p0.copy()
+    p1.reshape(P.nz, P.ny, P.nx)[-8:] += rng.uniform(0.0, 35.0, (8, P.ny, P.nx))  # a wetted top band
+    th = orc.theta(P, p0)
+    F = orc.residual(P, ks, p1, th)
+    s = rich.Solver(P, opts, torch.from_numpy(ks).cuda())
+    s.assemble(torch.from_numpy(p1).cuda())
+    rp, col, val = s.export_csr(rich.WHICH_A, 0)
+    amg = orc.AMG(opts, sp.csr_matrix((val, col, rp), shape=(P.n, P.n)))
+    assert s.levels() == amg.levels >= 3
+    b = -F
+    xg = s.apply_prec(torch.from_numpy(b).cuda()).cpu().numpy()
+    xo = amg.apply(b)
+    assert np.linalg.norm(xg - xo) <= 1e-10 * np.linalg.norm(xo)
+    x, its, rr, conv = s.gmres(torch.from_numpy(b).cuda())
+    x = x.cpu().numpy()
+    J = orc.jacobian(P, ks, p1)
+    xo, conv_o, its_o, rr_o = orc.gmres(J, b, amg, opts.gmres_restart, opts.eta, opts.gmres_maxit)
+    assert conv and conv_o and its_o > opts.gmres_restart  # at least one restart
+    assert abs(its - its_o) <= 1, (its, its_o)
+    assert np.linalg.norm(J @ x - b) <= opts.eta * np.linalg.norm(b) * (1 + 1e-6)
+    assert np.linalg.norm(x - xo) <= 10 * opts.eta * np.linalg.norm(xo)
+    s.close()
