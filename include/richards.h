@@ -295,6 +295,22 @@ rich_status rich_match_sweep(int64_t n, const int64_t *rowptr_dev, const int32_t
                              const double *val_dev, int32_t *agg_dev, int64_t *n_coarse_host,
                              void *hip_stream);
 
+/* For callers that cannot allocate memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): rich_match_sweep
+ * with the same arguments and results, whose device work arrays live in a
+ * fixed array of RICH_NOALLOC_SCRATCH_BYTES per GPU (reserved for the life
+ * of the process on every GPU the library runs on) and which calls no
+ * allocator.  The work arrays need about 32 n + 8 nnz bytes (nnz =
+ * rowptr[n]); larger inputs return RICH_EBUDGET before any kernel runs.
+ * Every call on one GPU uses that GPU's one array, so calls that overlap on
+ * a GPU (other host threads, other streams) race and must be serialised by
+ * the caller; each call initialises what it reads before using it.  Runs
+ * on hip_stream and returns when done. */
+#define RICH_NOALLOC_SCRATCH_BYTES (64u << 20)
+rich_status rich_match_sweep_noalloc(int64_t n, const int64_t *rowptr_dev, const int32_t *col_dev,
+                                     const double *val_dev, int32_t *agg_dev, int64_t *n_coarse_host,
+                                     void *hip_stream);
+
 /* ----------------------------------------------------------- profiling -- */
 /* Hot kernels whose launches can be timed with HIP events on the handle's
  * stream while profiling is on.  Each launch also adds its algorithmic HBM

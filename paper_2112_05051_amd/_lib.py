@@ -92,7 +92,7 @@ EXPORTS = ["rich_query_bytes", "rich_create", "rich_destroy", "rich_set_state", 
            "rich_step", "rich_trace_newton", "rich_trace_count", "rich_status_string", "rich_eval_theta", "rich_eval_residual",
            "rich_assemble", "rich_setup_hierarchy", "rich_apply_jacobian", "rich_apply_aux",
            "rich_apply_prec", "rich_gmres", "rich_levels", "rich_level_size", "rich_export_csr",
-           "rich_export_aggregates", "rich_match_sweep", "rich_profile", "rich_profile_read",
+           "rich_export_aggregates", "rich_match_sweep", "rich_match_sweep_noalloc", "rich_profile", "rich_profile_read",
            "rich_server_create", "rich_server_submit", "rich_server_poll", "rich_server_wait_idle",
            "rich_server_destroy", "rich_server_set_batching", "rich_server_batch_stats"]
 
@@ -136,6 +136,7 @@ def load(path: str = LIB_PATH):
     L.rich_export_csr.argtypes = [vp, C.c_int, C.c_int, i64p, i32p, dp, i64p]
     L.rich_export_aggregates.argtypes = [vp, C.c_int, i32p, i64p]
     L.rich_match_sweep.argtypes = [C.c_int64, vp, vp, vp, vp, i64p, vp]
+    L.rich_match_sweep_noalloc.argtypes = [C.c_int64, vp, vp, vp, vp, i64p, vp]
     L.rich_profile.argtypes = [vp, C.c_int]
     L.rich_profile_read.argtypes = [vp, C.c_int, i64p, dp, dp]
     L.rich_server_create.argtypes = [C.c_size_t, C.c_int, P(vp)]
@@ -370,16 +371,24 @@ class Solver:
         return agg, nc.value
 
 
-def match_sweep(rowptr, col, val, stream=None):
-    """One pairwise matching sweep on a device CSR matrix -> (agg int32 tensor, n_coarse)."""
+def match_sweep(rowptr, col, val, stream=None, agg=None, noalloc=False):
+    """One pairwise matching sweep on a device CSR matrix -> (agg int32 tensor, n_coarse).
+
+    noalloc: call rich_match_sweep_noalloc (no allocation inside the library;
+    agg, when given, is the caller's int32 output tensor of at least n entries)."""
     import torch
     L = load()
     n = rowptr.numel() - 1
-    agg = torch.empty(max(n, 1), dtype=torch.int32, device="cuda")
+    if agg is None:
+        agg = torch.empty(max(n, 1), dtype=torch.int32, device="cuda")
+    if agg.numel() < n or agg.dtype != torch.int32:
+        raise ValueError("agg must be an int32 tensor of at least n entries")
     nc = C.c_int64()
     s = stream if stream is not None else torch.cuda.current_stream()
-    _check(L.rich_match_sweep(n, _ptr(rowptr, torch.int64), _ptr(col, torch.int32), _ptr(val, torch.float64),
-                              _ptr(agg), C.byref(nc), C.c_void_p(s.cuda_stream)), "rich_match_sweep")
+    fn, name = (L.rich_match_sweep_noalloc, "rich_match_sweep_noalloc") if noalloc else (L.rich_match_sweep,
+                                                                                        "rich_match_sweep")
+    _check(fn(n, _ptr(rowptr, torch.int64), _ptr(col, torch.int32), _ptr(val, torch.float64), _ptr(agg),
+              C.byref(nc), C.c_void_p(s.cuda_stream)), name)
     return agg[:n], nc.value
 
 

@@ -808,66 +808,90 @@ __global__ void __launch_bounds__(256) k_bgj_update(double *__restrict__ D, int6
 }  // namespace
 
 // ------------------------------------------------------------------ host
-rich_status match_sweep(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val, int32_t *agg,
-                        int64_t *nc_out, hipStream_t s) {
-    DevAlloc tmp;
-    double *diag;
-    int32_t *mate, *cand;
-    int64_t *flag, *id, *stmp;
-    int *still;
-    RICH_TRY(tmp.get(&diag, n));
-    RICH_TRY(tmp.get(&mate, n));
-    RICH_TRY(tmp.get(&cand, n));
-    RICH_TRY(tmp.get(&flag, n));
-    RICH_TRY(tmp.get(&id, n + 1));
-    RICH_TRY(tmp.get(&stmp, scan_tmp_size(n)));
-    RICH_TRY(tmp.get(&still, 1));
+namespace {
+size_t ws_round(size_t b) { return (b + 255) & ~(size_t)255; }
+}  // namespace
+
+size_t match_ws_bytes(int64_t n, int64_t nnz) {
+    const size_t un = (size_t)(n > 0 ? n : 1);
+    return ws_round(un * 8) + ws_round((size_t)(nnz > 0 ? nnz : 1) * 8) + 2 * ws_round(un * 4) +
+           ws_round(un * 8) + ws_round((un + 1) * 8) + ws_round((size_t)scan_tmp_size(n) * 8) + ws_round(4);
+}
+
+MatchWs match_ws_carve(void *base, int64_t n, int64_t nnz) {
+    const size_t un = (size_t)(n > 0 ? n : 1);
+    char *p = static_cast<char *>(base);
+    MatchWs w;
+    auto take = [&](size_t b) {
+        char *q = p;
+        p += ws_round(b);
+        return q;
+    };
+    w.diag = (double *)take(un * 8);
+    w.wts = (double *)take((size_t)(nnz > 0 ? nnz : 1) * 8);
+    w.mate = (int32_t *)take(un * 4);
+    w.cand = (int32_t *)take(un * 4);
+    w.flag = (int64_t *)take(un * 8);
+    w.id = (int64_t *)take((un + 1) * 8);
+    w.stmp = (int64_t *)take((size_t)scan_tmp_size(n) * 8);
+    w.still = (int32_t *)take(4);
+    return w;
+}
+
+rich_status match_sweep_ws(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val, int32_t *agg,
+                           int64_t *nc_out, const MatchWs &w, int *h_still, hipStream_t s) {
     if (n == 0) {
         *nc_out = 0;
         return RICH_OK;
     }
-    k_diag<<<nblocks(n), TPB, 0, s>>>(n, rowptr, col, val, diag);
+    k_diag<<<nblocks(n), TPB, 0, s>>>(n, rowptr, col, val, w.diag);
     LAUNCH_CHECK();
     // the weights do not change between rounds: computed once
-    int64_t nnz = 0;
-    HIP_TRY(hipMemcpyAsync(&nnz, rowptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    double *wts;
-    RICH_TRY(tmp.get(&wts, nnz > 0 ? nnz : 1));
-    k_match_weights<<<nblocks(n), TPB, 0, s>>>(n, rowptr, col, val, diag, wts);
+    k_match_weights<<<nblocks(n), TPB, 0, s>>>(n, rowptr, col, val, w.diag, w.wts);
     LAUNCH_CHECK();
-    RICH_TRY(launch_fill_i32(mate, -1, n, s));
-    int *h_still = nullptr;
-    HIP_TRY(hipHostMalloc((void **)&h_still, sizeof(int)));
-    rich_status st = RICH_OK;
+    RICH_TRY(launch_fill_i32(w.mate, -1, n, s));
     for (int64_t round = 0;; round++) {
-        HIP_TRY(hipMemsetAsync(still, 0, sizeof(int), s));
+        RICH_TRY(launch_fill_i32(w.still, 0, 1, s));
         // a few rounds per host check; extra rounds after completion are no-ops
         for (int t = 0; t < 4; t++) {
-            k_candidates<<<nblocks(n), TPB, 0, s>>>(n, rowptr, col, wts, mate, cand);
-            k_commit<<<nblocks(n), TPB, 0, s>>>(n, cand, mate, still);
+            k_candidates<<<nblocks(n), TPB, 0, s>>>(n, rowptr, col, w.wts, w.mate, w.cand);
+            k_commit<<<nblocks(n), TPB, 0, s>>>(n, w.cand, w.mate, w.still);
         }
         LAUNCH_CHECK();
-        HIP_TRY(hipMemcpyAsync(h_still, still, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(h_still, w.still, sizeof(int), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         if (!*h_still) break;
-        if (round > 4 * n + 16) {  // every round matches or retires at least one vertex
-            st = RICH_EHIP;
-            break;
-        }
+        if (round > 4 * n + 16) return RICH_EHIP;  // every round matches or retires at least one vertex
     }
-    (void)hipHostFree(h_still);
-    RICH_TRY(st);
-    k_leaders<<<nblocks(n), TPB, 0, s>>>(n, mate, flag);
+    k_leaders<<<nblocks(n), TPB, 0, s>>>(n, w.mate, w.flag);
     LAUNCH_CHECK();
-    RICH_TRY(scan_exclusive_i64(flag, id, n, stmp, s));
-    k_number<<<nblocks(n), TPB, 0, s>>>(n, mate, id, agg);
+    RICH_TRY(scan_exclusive_i64(w.flag, w.id, n, w.stmp, s));
+    k_number<<<nblocks(n), TPB, 0, s>>>(n, w.mate, w.id, agg);
     LAUNCH_CHECK();
     int64_t nc = 0;
-    HIP_TRY(hipMemcpyAsync(&nc, id + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&nc, w.id + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     *nc_out = nc;
     return RICH_OK;
+}
+
+rich_status match_sweep(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val, int32_t *agg,
+                        int64_t *nc_out, hipStream_t s) {
+    if (n == 0) {
+        *nc_out = 0;
+        return RICH_OK;
+    }
+    int64_t nnz = 0;
+    HIP_TRY(hipMemcpyAsync(&nnz, rowptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    DevAlloc tmp;
+    char *base;
+    RICH_TRY(tmp.get(&base, match_ws_bytes(n, nnz)));
+    int *h_still = nullptr;
+    HIP_TRY(hipHostMalloc((void **)&h_still, sizeof(int)));
+    rich_status st = match_sweep_ws(n, rowptr, col, val, agg, nc_out, match_ws_carve(base, n, nnz), h_still, s);
+    (void)hipHostFree(h_still);
+    return st;
 }
 
 rich_status vmb_aggregate(const CsrDev &A, double theta, int64_t block, int32_t *agg, int64_t *nc_out,

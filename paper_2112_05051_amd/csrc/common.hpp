@@ -316,6 +316,21 @@ struct Hierarchy {
 // one matching sweep on a device CSR (setup-time); returns n_coarse
 rich_status match_sweep(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
                         int32_t *agg, int64_t *nc_out, hipStream_t s);
+// The device work arrays of one matching sweep of n rows and nnz entries,
+// carved in this order from one buffer of match_ws_bytes(n, nnz) bytes
+// (each array 256-byte aligned).
+struct MatchWs {
+    double *diag = nullptr, *wts = nullptr;
+    int32_t *mate = nullptr, *cand = nullptr;
+    int64_t *flag = nullptr, *id = nullptr, *stmp = nullptr;
+    int32_t *still = nullptr;
+};
+size_t match_ws_bytes(int64_t n, int64_t nnz);
+MatchWs match_ws_carve(void *base, int64_t n, int64_t nnz);
+// the sweep on given work arrays; h_still: host int the round loop reads
+// the device's "still free" flag into (pinned or pageable)
+rich_status match_sweep_ws(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
+                           int32_t *agg, int64_t *nc_out, const MatchWs &w, int *h_still, hipStream_t s);
 // C = P^T A P for piecewise-constant P given by agg (canonical summation order)
 struct CsrDev {
     int64_t n = 0, nnz = 0;
