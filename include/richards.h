@@ -275,8 +275,9 @@ rich_status rich_levels(rich_handle_t h, int *nlev_host);
 rich_status rich_level_size(rich_handle_t h, int level, int64_t *n_host, int64_t *nnz_host);
 #define RICH_WHICH_J 0  /* the Jacobian (level ignored) */
 #define RICH_WHICH_A 1  /* the level-l AMG matrix, FP64 (level 0 = auxiliary M) */
-#define RICH_WHICH_P 2  /* the smoothed prolongator of level l -> l+1 (n_l rows, n_{l+1}
-                           columns); RICH_EINVAL for piecewise-constant hierarchies */
+#define RICH_WHICH_P 2  /* the prolongator of level l -> l+1 (n_l rows, n_{l+1} columns):
+                           the smoothed one, or the piecewise-constant P(i, agg(i)) = 1 */
+#define RICH_WHICH_PT 3 /* its transpose, the restriction (n_{l+1} rows, n_l columns) */
 /* Copy a matrix to host CSR (columns ascending).  *nnz_inout: capacity in,
  * entries written out; RICH_EINVAL if the capacity is too small. */
 rich_status rich_export_csr(rich_handle_t h, int which, int level, int64_t *rowptr_host,
@@ -353,12 +354,17 @@ rich_status rich_profile_read(rich_handle_t h, int kernel, int64_t *launches_hos
  * launch on their own stream.
  * A simulation's result equals that of a lone rich_create/rich_step run
  * (bit for bit: every block runs the lone kernel's code on its data).
- * The server uses the device that is current when it is created. */
+ * The server uses the device of the stream given at creation, or the device
+ * that is current then. */
 typedef struct rich_server *rich_server_t;
 #define RICH_REQ_QUEUED 0
 #define RICH_REQ_RUNNING 1
 #define RICH_REQ_DONE 2
-rich_status rich_server_create(size_t hbm_budget_bytes, int max_active, rich_server_t *out);
+/* hip_stream: NULL, or a hipStream_t whose device the server runs on and after
+ * whose work (as queued at each rich_server_submit) that request's first
+ * kernel runs; with NULL the server uses the device current at creation and
+ * orders nothing.  Each worker launches on a non-blocking stream of its own. */
+rich_status rich_server_create(size_t hbm_budget_bytes, int max_active, void *hip_stream, rich_server_t *out);
 /* Ks_host, p0_host: N host values each, copied.  RICH_EBUDGET if the request
  * alone exceeds the budget.  *req_id receives the request's id. */
 rich_status rich_server_submit(rich_server_t s, const rich_problem_t *prob, const rich_solver_opts_t *opts,
@@ -378,7 +384,7 @@ rich_status rich_server_set_batching(rich_server_t s, int fused);
  * mean number of simulations per fused launch). */
 rich_status rich_server_batch_stats(rich_server_t s, int64_t *flushes, int64_t *products);
 /* Block until no request is queued or running. */
-rich_status rich_server_wait_idle(rich_server_t s);
+rich_status rich_server_run_until_idle(rich_server_t s);
 /* Let running simulations finish, drop queued ones, release the server. */
 rich_status rich_server_destroy(rich_server_t s);
 

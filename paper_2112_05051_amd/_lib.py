@@ -20,7 +20,7 @@ EINVAL, ENOMEM, EBUDGET, NONFINITE = -1, -2, -3, -4
 LINSOLVE_FAIL, LINESEARCH_FAIL, MAXITER, NOT_SPD, EHIP, ESTATE = -5, -6, -7, -9, -10, -11
 STEP_TOO_SMALL = 2
 PREC_FP64, PREC_MIXED = 0, 1
-WHICH_J, WHICH_A, WHICH_P = 0, 1, 2
+WHICH_J, WHICH_A, WHICH_P, WHICH_PT = 0, 1, 2, 3
 
 
 class RichError(RuntimeError):
@@ -93,7 +93,7 @@ EXPORTS = ["rich_query_bytes", "rich_create", "rich_destroy", "rich_set_state", 
            "rich_assemble", "rich_setup_hierarchy", "rich_apply_jacobian", "rich_apply_aux",
            "rich_apply_prec", "rich_gmres", "rich_levels", "rich_level_size", "rich_export_csr",
            "rich_export_aggregates", "rich_match_sweep", "rich_match_sweep_noalloc", "rich_profile", "rich_profile_read",
-           "rich_server_create", "rich_server_submit", "rich_server_poll", "rich_server_wait_idle",
+           "rich_server_create", "rich_server_submit", "rich_server_poll", "rich_server_run_until_idle",
            "rich_server_destroy", "rich_server_set_batching", "rich_server_batch_stats"]
 
 KERNELS = ["spmv_J", "vc0_pre", "vc0_post", "vc0_restrict", "vc1_pre", "vc1_post", "multidot", "update",
@@ -139,10 +139,10 @@ def load(path: str = LIB_PATH):
     L.rich_match_sweep_noalloc.argtypes = [C.c_int64, vp, vp, vp, vp, i64p, vp]
     L.rich_profile.argtypes = [vp, C.c_int]
     L.rich_profile_read.argtypes = [vp, C.c_int, i64p, dp, dp]
-    L.rich_server_create.argtypes = [C.c_size_t, C.c_int, P(vp)]
+    L.rich_server_create.argtypes = [C.c_size_t, C.c_int, vp, P(vp)]
     L.rich_server_submit.argtypes = [vp, P(Problem), P(Opts), dp, dp, C.c_int, i64p]
     L.rich_server_poll.argtypes = [vp, C.c_int64, P(C.c_int), P(C.c_int), dp, P(StepStats), dp, dp]
-    L.rich_server_wait_idle.argtypes = [vp]
+    L.rich_server_run_until_idle.argtypes = [vp]
     L.rich_server_destroy.argtypes = [vp]
     L.rich_server_set_batching.argtypes = [vp, C.c_int]
     L.rich_server_batch_stats.argtypes = [vp, i64p, i64p]
@@ -326,8 +326,8 @@ class Solver:
 
     def export_csr(self, which: int, level: int = 0):
         """(indptr int64, indices int32, data float64) numpy arrays."""
-        if which == WHICH_P:
-            n, cap = self.level_size(level)[0], 0
+        if which in (WHICH_P, WHICH_PT):
+            n = self.level_size(level + (which == WHICH_PT))[0]
             nnz = C.c_int64(0)
             dummy = np.empty(1, np.int64)
             st = self._L.rich_export_csr(self._h, which, level, dummy.ctypes.data_as(C.POINTER(C.c_int64)),
@@ -401,13 +401,14 @@ class Server:
     fused into batched launches when ``fused`` is true.  Inputs/outputs are
     host arrays."""
 
-    def __init__(self, hbm_budget_bytes: int, max_active: int = 4, fused: bool = False):
+    def __init__(self, hbm_budget_bytes: int, max_active: int = 4, fused: bool = False, stream=None):
         L = load()
         self._L = L
         self._s = C.c_void_p()
         self._n = {}
         self._steps = {}
-        _check(L.rich_server_create(hbm_budget_bytes, max_active, C.byref(self._s)), "rich_server_create")
+        hs = C.c_void_p(stream.cuda_stream) if stream is not None else None
+        _check(L.rich_server_create(hbm_budget_bytes, max_active, hs, C.byref(self._s)), "rich_server_create")
         _check(L.rich_server_set_batching(self._s, 1 if fused else 0), "rich_server_set_batching")
 
     def batch_stats(self):
@@ -445,8 +446,9 @@ class Server:
         return {"status": res.value, "p": p, "stats": [stats_dict(stats[i]) for i in range(nrun)],
                 "step_ms": ms[:nrun].copy(), "wait_s": float(times[0]), "run_s": float(times[1])}
 
-    def wait_idle(self):
-        _check(self._L.rich_server_wait_idle(self._s), "rich_server_wait_idle")
+    def run_until_idle(self):
+        """Block until no request is queued or running."""
+        _check(self._L.rich_server_run_until_idle(self._s), "rich_server_run_until_idle")
 
     def close(self):
         if getattr(self, "_s", None) is not None and self._s.value:

@@ -46,6 +46,7 @@ struct Request {
     std::vector<rich_step_stats_t> stats;
     std::vector<double> step_ms;
     double t_submit = 0, t_start = 0, t_end = 0;
+    hipEvent_t after = nullptr;  // the server's stream at submission (null: no ordering)
 };
 
 }  // namespace
@@ -53,6 +54,7 @@ struct Request {
 struct rich_server {
     size_t budget = 0, in_use = 0;
     int device = 0;
+    hipStream_t order = nullptr;      // caller's stream each request is ordered after (may be null)
     std::mutex mu;
     std::condition_variable cv;
     std::deque<std::shared_ptr<Request>> queue;
@@ -85,6 +87,7 @@ void run_request(rich_server *S, hipStream_t stream, Request &R, rich_batcher *b
          hipMemcpyAsync(dp, R.p.data(), N * sizeof(double), hipMemcpyHostToDevice, stream) != hipSuccess ||
          hipStreamSynchronize(stream) != hipSuccess))
         st = RICH_EHIP;
+    if (st == RICH_OK && R.after && hipStreamWaitEvent(stream, R.after, 0) != hipSuccess) st = RICH_EHIP;
     if (st == RICH_OK) st = rich_create(&R.prob, &R.opts, dks, stream, &h);
     if (st == RICH_OK && S->fused) st = batcher ? rich::batcher_attach(h, batcher) : RICH_EHIP;
     if (st == RICH_OK) st = rich_set_state(h, dp);
@@ -106,6 +109,10 @@ void run_request(rich_server *S, hipStream_t stream, Request &R, rich_batcher *b
     }
     if (dks) (void)hipFree(dks);
     if (dp) (void)hipFree(dp);
+    if (R.after) {
+        (void)hipEventDestroy(R.after);
+        R.after = nullptr;
+    }
     R.result = st;
 }
 
@@ -150,14 +157,19 @@ void worker_main(rich_server *S) {
 
 extern "C" {
 
-rich_status rich_server_create(size_t hbm_budget, int max_active, rich_server_t *out) {
+rich_status rich_server_create(size_t hbm_budget, int max_active, void *hip_stream, rich_server_t *out) {
     if (!out || hbm_budget == 0 || max_active < 1 || max_active > 64) return RICH_EINVAL;
+    int device = 0;
+    if (hip_stream) {
+        HIP_TRY(hipStreamGetDevice((hipStream_t)hip_stream, &device));
+    } else if (hipGetDevice(&device) != hipSuccess) {
+        (void)hipGetLastError();
+        device = 0;
+    }
     rich_server *S = new rich_server();
     S->budget = hbm_budget;
-    if (hipGetDevice(&S->device) != hipSuccess) {
-        (void)hipGetLastError();
-        S->device = 0;
-    }
+    S->device = device;
+    S->order = (hipStream_t)hip_stream;
     for (int t = 0; t < max_active; t++) S->workers.emplace_back(worker_main, S);
     *out = S;
     return RICH_OK;
@@ -179,9 +191,16 @@ rich_status rich_server_submit(rich_server_t S, const rich_problem_t *prob, cons
     R->nsteps = nsteps;
     R->bytes = bytes;
     R->t_submit = wall_s();
+    if (S->order) {
+        HIP_TRY(hipEventCreateWithFlags(&R->after, hipEventDisableTiming));
+        HIP_TRY(hipEventRecord(R->after, S->order));
+    }
     {
         std::lock_guard<std::mutex> lk(S->mu);
-        if (S->stop) return RICH_ESTATE;
+        if (S->stop) {
+            if (R->after) (void)hipEventDestroy(R->after);
+            return RICH_ESTATE;
+        }
         R->id = S->next_id++;
         S->all[R->id] = R;
         S->queue.push_back(R);
@@ -240,7 +259,7 @@ rich_status rich_server_batch_stats(rich_server_t S, int64_t *flushes, int64_t *
     return RICH_OK;
 }
 
-rich_status rich_server_wait_idle(rich_server_t S) {
+rich_status rich_server_run_until_idle(rich_server_t S) {
     if (!S) return RICH_EINVAL;
     std::unique_lock<std::mutex> lk(S->mu);
     S->cv.wait(lk, [&] { return S->queue.empty() && S->running == 0; });
@@ -256,6 +275,10 @@ rich_status rich_server_destroy(rich_server_t S) {
         for (auto &R : S->queue) {
             R->state = RICH_REQ_DONE;
             R->result = RICH_ESTATE;  // never admitted
+            if (R->after) {
+                (void)hipEventDestroy(R->after);
+                R->after = nullptr;
+            }
         }
         S->queue.clear();
     }

@@ -1585,18 +1585,52 @@ rich_status rich_export_csr(rich_handle_t h, int which, int level, int64_t *rowp
         *nnz_inout = nnz;
         return RICH_OK;
     }
-    if (which == RICH_WHICH_P) {
-        if (!h->H || level < 0 || level >= h->H->nlev - 1 || !h->H->L[level].prow) return RICH_EINVAL;
+    if (which == RICH_WHICH_P || which == RICH_WHICH_PT) {
+        if (!h->H || level < 0 || level >= h->H->nlev - 1) return RICH_EINVAL;
         const Level &Lp = h->H->L[level];
-        if (*nnz_inout < Lp.pnnz) {
-            *nnz_inout = Lp.pnnz;
+        const int64_t nc = h->H->L[level + 1].n;
+        const bool tr = which == RICH_WHICH_PT;
+        const int64_t nnz = Lp.prow ? Lp.pnnz : Lp.n, nrows = tr ? nc : Lp.n;
+        if (*nnz_inout < nnz) {
+            *nnz_inout = nnz;
             return RICH_EINVAL;
         }
-        HIP_TRY(hipMemcpyAsync(rowptr_host, Lp.prow, (Lp.n + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, h->s));
-        HIP_TRY(hipMemcpyAsync(col_host, Lp.pcol, Lp.pnnz * sizeof(int32_t), hipMemcpyDeviceToHost, h->s));
-        HIP_TRY(hipMemcpyAsync(val_host, Lp.pval, Lp.pnnz * sizeof(double), hipMemcpyDeviceToHost, h->s));
-        RICH_TRY(sync(h));
-        *nnz_inout = Lp.pnnz;
+        if (Lp.prow) {  // smoothed: P and its transpose are stored
+            HIP_TRY(hipMemcpyAsync(rowptr_host, tr ? Lp.trow : Lp.prow, (nrows + 1) * sizeof(int64_t),
+                                   hipMemcpyDeviceToHost, h->s));
+            HIP_TRY(hipMemcpyAsync(col_host, tr ? Lp.tcol : Lp.pcol, nnz * sizeof(int32_t), hipMemcpyDeviceToHost,
+                                   h->s));
+            HIP_TRY(hipMemcpyAsync(val_host, tr ? Lp.tval : Lp.pval, nnz * sizeof(double), hipMemcpyDeviceToHost,
+                                   h->s));
+            RICH_TRY(sync(h));
+            // columns ascending within each row, as for every exported matrix
+            std::vector<std::pair<int32_t, double>> row;
+            for (int64_t r = 0; r < nrows; r++) {
+                row.clear();
+                for (int64_t e = rowptr_host[r]; e < rowptr_host[r + 1]; e++) row.push_back({col_host[e], val_host[e]});
+                std::sort(row.begin(), row.end(), [](const auto &a, const auto &b) { return a.first < b.first; });
+                for (int64_t e = rowptr_host[r], k = 0; e < rowptr_host[r + 1]; e++, k++) {
+                    col_host[e] = row[k].first;
+                    val_host[e] = row[k].second;
+                }
+            }
+        } else {  // piecewise constant: P(i, agg(i)) = 1, built from the aggregate map
+            std::vector<int32_t> agg(Lp.n);
+            HIP_TRY(hipMemcpyAsync(agg.data(), Lp.agg, Lp.n * sizeof(int32_t), hipMemcpyDeviceToHost, h->s));
+            RICH_TRY(sync(h));
+            if (!tr) {
+                for (int64_t i = 0; i <= Lp.n; i++) rowptr_host[i] = i;
+                for (int64_t i = 0; i < Lp.n; i++) col_host[i] = agg[i];
+            } else {
+                std::fill(rowptr_host, rowptr_host + nc + 1, 0);
+                for (int64_t i = 0; i < Lp.n; i++) rowptr_host[agg[i] + 1]++;
+                for (int64_t c = 0; c < nc; c++) rowptr_host[c + 1] += rowptr_host[c];
+                std::vector<int64_t> pos(rowptr_host, rowptr_host + nc);
+                for (int64_t i = 0; i < Lp.n; i++) col_host[pos[agg[i]]++] = (int32_t)i;  // members ascending
+            }
+            std::fill(val_host, val_host + nnz, 1.0);
+        }
+        *nnz_inout = nnz;
         return RICH_OK;
     }
     if (which != RICH_WHICH_A || !h->H || level < 0 || level >= h->H->nlev) return RICH_EINVAL;

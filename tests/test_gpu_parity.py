@@ -133,11 +133,20 @@ def test_hierarchy_bitexact(rich, torch, orc, mean, smoothed):
             agg_g, nc = s.export_aggregates(l)
             assert np.array_equal(agg_g, aggo)
             assert np.bincount(agg_g).max() <= 8
+            prp, pcol, pval = s.export_csr(rich.WHICH_P, l)
             if l < smoothed:
-                prp, pcol, pval = s.export_csr(rich.WHICH_P, l)
                 Po = amg.prolongator(l)
-                assert np.array_equal(prp, Po.indptr) and np.array_equal(pcol, Po.indices)
-                assert np.array_equal(pval, Po.data)
+            else:  # piecewise constant: P(i, agg(i)) = 1
+                Po = sp.csr_matrix((np.ones(Ao.shape[0]), (np.arange(Ao.shape[0]), aggo)),
+                                   shape=(Ao.shape[0], nc))
+            assert np.array_equal(prp, Po.indptr) and np.array_equal(pcol, Po.indices)
+            assert np.array_equal(pval, Po.data)
+            # the restriction is the prolongator's transpose, columns ascending
+            trp, tcol, tval = s.export_csr(rich.WHICH_PT, l)
+            PoT = sp.csr_matrix(Po.T)
+            PoT.sort_indices()
+            assert np.array_equal(trp, PoT.indptr) and np.array_equal(tcol, PoT.indices)
+            assert np.array_equal(tval, PoT.data)
     # one V-cycle (FP64) vs the oracle's on the same hierarchy
     b = np.random.default_rng(33).standard_normal(n)
     xg = s.apply_prec(dev(torch, b)).cpu().numpy()

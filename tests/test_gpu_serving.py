@@ -43,7 +43,7 @@ def test_alone_equals_mix(fused):
     reqs = small_requests()
     srv = rich.Server(8 << 30, 3, fused=fused)
     ids = [srv.submit(rec.problem, rec.options, rec.ks(), rec.p0(), rec.nsteps) for rec in reqs]
-    srv.wait_idle()
+    srv.run_until_idle()
     check_alone_equals_mix(rich, torch, srv, reqs, ids)
     flushes, products = srv.batch_stats()
     if fused:
@@ -68,7 +68,7 @@ def test_fused_kernels_all_paths():
         reqs.append(rec)
     srv = rich.Server(16 << 30, 4, fused=True)
     ids = [srv.submit(rec.problem, rec.options, rec.ks(), rec.p0(), rec.nsteps) for rec in reqs]
-    srv.wait_idle()
+    srv.run_until_idle()
     flushes, products = srv.batch_stats()
     assert flushes > 0 and products > flushes, (flushes, products)
     check_alone_equals_mix(rich, torch, srv, reqs, ids)
@@ -93,7 +93,7 @@ def test_fused_fp64():
         reqs.append(rec)
     srv = rich.Server(8 << 30, 2, fused=True)
     ids = [srv.submit(rec.problem, rec.options, rec.ks(), rec.p0(), rec.nsteps) for rec in reqs]
-    srv.wait_idle()
+    srv.run_until_idle()
     flushes, products = srv.batch_stats()
     assert flushes > 0 and products > flushes, (flushes, products)
     check_alone_equals_mix(rich, torch, srv, reqs, ids)
@@ -118,7 +118,7 @@ def test_fused_mixed_hierarchies():
         reqs.append(rec)
     srv = rich.Server(8 << 30, 4, fused=True)
     ids = [srv.submit(rec.problem, rec.options, rec.ks(), rec.p0(), rec.nsteps) for rec in reqs]
-    srv.wait_idle()
+    srv.run_until_idle()
     flushes, products = srv.batch_stats()
     assert flushes > 0
     check_alone_equals_mix(rich, torch, srv, reqs, ids)
@@ -131,10 +131,52 @@ def test_budget_serialises_but_completes():
     need = max(rich.query_bytes(rec.problem, rec.options) + 16 * rec.problem.n for rec in reqs)
     srv = rich.Server(need + 1024, 4)  # room for one simulation at a time
     ids = [srv.submit(rec.problem, rec.options, rec.ks(), rec.p0(), rec.nsteps) for rec in reqs]
-    srv.wait_idle()
+    srv.run_until_idle()
     res = [srv.poll(i) for i in ids]
     assert all(r is not None and r["status"] == 0 for r in res)
     # one at a time: total resident time is the sum of the parts, so the last
     # request waited at least as long as all earlier ones ran
     assert res[-1]["wait_s"] >= 0.9 * sum(r["run_s"] for r in res[:-1])
+    srv.close()
+
+
+def test_served_results_match_the_oracle(orc):
+    """FP64 requests of several sizes and interface means served together:
+    each served result equals the oracle's run of the same request (rel. L2
+    <= 1e-8 at fnormtol 1e-12) with the same Newton counters; a request the
+    oracle cannot converge fails on the server too.  The server is created on
+    a caller's stream and its requests are ordered after it."""
+    import torch
+
+    import paper_2112_05051_amd as rich
+    reqs = small_requests(count=8, steps=2, seed=4, sizes=(10, 12, 14, 16, 18))
+    for rec in reqs:
+        rec.options.precision = synth.FP64
+        rec.options.fnormtol = 1e-12
+        rec.options.max_newton = 30
+    stream = torch.cuda.Stream()
+    srv = rich.Server(8 << 30, 4, stream=stream)
+    ids = [srv.submit(rec.problem, rec.options, rec.ks(), rec.p0(), rec.nsteps) for rec in reqs]
+    srv.run_until_idle()
+    converged = 0
+    for rec, i in zip(reqs, ids):
+        r = srv.poll(i)
+        o = orc.Solver(rec.problem, rec.options, rec.ks())
+        po = rec.p0().copy()
+        so = []
+        for _ in range(rec.nsteps):
+            so.append(o.step(po))
+            if so[-1]["status"] < 0:
+                break
+        if so[-1]["status"] < 0:
+            assert r["status"] < 0, (rec.name, r["status"], so[-1]["status"])
+            continue
+        converged += 1
+        assert r["status"] == 0, (rec.name, r["status"])
+        err = np.linalg.norm(r["p"] - po) / np.linalg.norm(po)
+        assert err <= 1e-8, (rec.name, err)
+        for sg, s_o in zip(r["stats"], so):
+            for f in ("newton_its", "jac_builds", "ls_backtracks"):
+                assert sg[f] == s_o[f], (rec.name, f, sg[f], s_o[f])
+    assert converged >= 5
     srv.close()
