@@ -52,7 +52,7 @@ def run_gpu(rec, precision, warmup, steps, ks_dev, p0_dev, profile):
     torch.cuda.synchronize()
     t_warm = time.perf_counter() - t0
     log(f"[bench] precision={'mixed' if precision else 'fp64'} warmup {warmup} steps {t_warm:.2f}s "
-        f"(AMG set-up and refreshes {sum(w['t_setup'] for w in warm):.2f}s, "
+        f"(AMG set-up and refreshes {sum(w['t_setup'] + w['t_aux'] for w in warm):.2f}s, "
         f"GMRES {sum(w['gmres_its'] for w in warm)} its)")
     if profile:
         s.profile(True)
@@ -87,25 +87,67 @@ def percentile(xs, q):
     return float(np.percentile(np.asarray(xs), q)) if xs else float("nan")
 
 
-def cpu_baseline(n_sample=64, nsteps=2):
-    """The oracle, single-threaded, on the first nsteps steps of the same recipe
-    at n_sample^3 (field statistics in cells unchanged), the rate scaled by the
-    cell count to 256^3 (an optimistic figure for the CPU: iteration counts
-    grow with the grid)."""
-    import synth
+def host_cpu():
+    """Core count and model of this host (the oracle runs on one of its cores)."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "usable_cores": len(os.sched_getaffinity(0)), "model": model}
+
+
+def cpu_baseline(rec, ks, timed_stats, gmres_sample=5):
+    """The oracle (plain C, one thread) timed on a bounded sample of the
+    benchmark's own workload: on the recipe's initial state at its full grid,
+    one residual evaluation, one assembly of J and the auxiliary matrix, the
+    AMG set-up, one numeric refresh of the hierarchy and the first
+    `gmres_sample` iterations of a GMRES solve.  These per-unit times, weighted
+    by the counts of the GPU's timed steps (residual evaluations, rebuilds,
+    GMRES iterations; the GPU's counts equal the oracle's in the parity tests),
+    give the oracle's time per step.  Optimistic for the CPU: the sampled
+    GMRES iterations have the shortest Gram-Schmidt of a cycle, and set-up,
+    norms and line-search vector work are not counted."""
     from oracle import oracle as orc
-    rec = synth.recipe("c3", n=n_sample)
-    ks, p = rec.ks(), rec.p0()
-    S = orc.Solver(rec.problem, rec.options, ks)
+    P, N = rec.problem, rec.problem.n
+    p0 = rec.p0()
+    t = {}
     t0 = time.perf_counter()
-    sts = [S.step(p) for _ in range(nsteps)]
-    dt = time.perf_counter() - t0
-    scale = (n_sample ** 3) / (256 ** 3)
-    return {"value": nsteps * scale / dt, "unit": "time-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"the first {nsteps} backward-Euler steps of the 256^3 recipe's statistics on a {n_sample}^3 "
-                      f"grid ({dt:.1f} s, {sum(s['newton_its'] for s in sts)} Newton, "
-                      f"{sum(s['gmres_its'] for s in sts)} GMRES its, statuses {[s['status'] for s in sts]}), "
-                      f"rate scaled by the cell ratio {n_sample}^3/256^3"}
+    th = orc.theta(P, p0)
+    t1 = time.perf_counter()
+    F = orc.residual(P, ks, p0, th)
+    t["residual"] = time.perf_counter() - t1
+    t0 = time.perf_counter()
+    J = orc.jacobian(P, ks, p0)
+    M = orc.auxiliary(P, ks, p0)
+    t["assembly"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    amg = orc.AMG(rec.options, M)
+    t["amg_setup"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    amg.update_fine(M)
+    t["refresh"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    orc.gmres(J, -F, amg, rec.options.gmres_restart, rec.options.eta, gmres_sample)
+    t["gmres_iteration"] = (time.perf_counter() - t0) / gmres_sample
+    steps = max(len(timed_stats), 1)
+    n_res = sum(s["bytes_feval"] for s in timed_stats) / (32.0 * N)
+    n_build = sum(s["jac_builds"] for s in timed_stats)
+    n_gmres = sum(s["gmres_its"] for s in timed_stats)
+    per_step = (n_res * t["residual"] + n_build * (t["assembly"] + t["refresh"]) +
+                n_gmres * t["gmres_iteration"]) / steps
+    return {"value": 1.0 / per_step, "unit": "time-steps/s", "cores": 1, "kind": "oracle",
+            "host": host_cpu(),
+            "sample": (f"per-unit oracle times on the {P.nx}x{P.ny}x{P.nz} recipe at its initial state "
+                       f"(residual {t['residual']:.1f} s, J+M assembly {t['assembly']:.1f} s, AMG set-up "
+                       f"{t['amg_setup']:.1f} s (not counted: once per run), refresh {t['refresh']:.1f} s, "
+                       f"GMRES iteration {t['gmres_iteration']:.2f} s over the first {gmres_sample}) weighted by "
+                       f"the GPU's timed steps: {n_res / steps:.1f} residuals, {n_build / steps:.2f} rebuilds, "
+                       f"{n_gmres / steps:.0f} GMRES iterations per step"),
+            "unit_seconds": t, "per_step_s": per_step}
 
 
 # Kernel families of the per-kernel table: the library's timer name, the
@@ -115,27 +157,65 @@ FAMILIES = {
     "multidot": ("k_multidot<", "la.hip"),
     "spmv_J": ("k_spmv_J<float>", "fine.hip"),
     "vc0_pre": ("k_st25<double, float, 0>", "fine.hip"),
-    "residual": ("k_residual", "fine.hip"),
+    "vc0_post": ("k_st25<double, float, 1>", "fine.hip"),
+    "restrict": ("k_restrict<float>", "amg.hip"),
+    "csr_pre": ("k_csr_stream<2, float, float, false>", "amg.hip"),
+    "csr_post": ("k_csr_stream<2, float, float, true>", "amg.hip"),
+    "residual": ("k_faces_tiled<false", "fine.hip"),
+    "assembly": ("k_faces_tiled<true", "fine.hip"),
 }
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "traffic_c3_256cube_mixed.md")
 
 
-def algorithmic_bytes(name, n, mixed=True):
-    """Algorithmic HBM bytes (read, written) of one launch of a fine-grid
-    kernel at n unknowns (the per-cell figures of the kernel table of the
-    design notes); None when the launch size is not fixed by n alone."""
+def _ceil(a, b):
+    return (a + b - 1) // b
+
+
+def _xcd(blocks):
+    return _ceil(blocks, 8) * 8
+
+
+def algorithmic_bytes(name, n, blocks=None, levels=None, mixed=True):
+    """Algorithmic HBM bytes of one launch (the per-row figures of the kernel
+    table of the design notes): fine-grid kernels from n alone; the coarse
+    kernels of level l from that level's rows and entries, the level found by
+    the launch's block count (CSR-stream: one block per 1536 entries, the
+    restriction: one block per 256 coarse rows, both padded to a multiple of
+    8).  None when the launch cannot be placed."""
     import re
     t = 4 if mixed else 8
     m = re.search(r"k_(multidot|update_norm)<(\d+)>", name)
     if m:
         k = int(m.group(2))
-        return (8 * n * (k + 1), 0) if m.group(1) == "multidot" else (8 * n * (k + 1), 8 * n)
+        return 8 * n * (k + 1) + (8 * n if m.group(1) == "update_norm" else 0)
     if "k_spmv_J<float>" in name:
-        return (60 * n, 8 * n)
+        return 68 * n
     if "k_st25<double, float, 0>" in name or "k_st_pre<double, float>" in name:
-        return (8 * n + 5 * t * n, t * n)
-    if "k_residual" in name:
-        return (24 * n, 8 * n)
+        return 8 * n + 6 * t * n
+    if "k_faces_tiled<false" in name or "k_residual" in name:
+        return 32 * n
+    if "k_faces_tiled<true" in name:
+        return n * (16 + 56 + 32 + 8 + (20 if mixed else 0))
+    if not levels or blocks is None:
+        return None
+    if "k_st25<double, float, 1>" in name:
+        return 8 * n + 6 * t * n + 4 * n + t * levels[1][0]
+    if "k_restrict<" in name:
+        for l in range(len(levels) - 1):
+            nl, nc = levels[l][0], levels[l + 1][0]
+            if _xcd(_ceil(nc, 256)) == blocks:
+                x0 = l + 1 < len(levels) - 1  # the coarse pre-smoothed iterate is stored below the coarsest
+                return nl * (t + 4) + nc * (8 + t + (2 * t if x0 else 0))
+        return None
+    m = re.search(r"k_csr_stream<\d+, float, float, (true|false)>", name)
+    if m:
+        for l in range(1, len(levels) - 1):
+            nl, nnz = levels[l]
+            if _xcd(_ceil(nnz, 1536)) == blocks:
+                if m.group(1) == "false":
+                    return nnz * (4 + t) + nl * (8 + 3 * t)
+                return nnz * (4 + t) + nl * (12 + 7 * t) + levels[l + 1][0] * t
+        return None
     return None
 
 
@@ -149,13 +229,14 @@ def source_digests():
     return {f: source_digest(f) for f in sorted({src for _, src in FAMILIES.values()})}
 
 
-def pmc_summary(fetch_csv, write_csv, n, digests=None):
+def pmc_summary(fetch_csv, write_csv, n, digests=None, levels=None):
     """Per-kernel HBM traffic from rocprofv3 FETCH_SIZE / WRITE_SIZE counter runs,
-    calibrated by the 1 GiB device copy of --calibrate-copy.  The trailing
-    'family' lines (measured bytes over algorithmic bytes, summed over the
-    family's launches, with the digest of the kernel's source file) are what
-    the benchmark reads back to report measured traffic.  `digests` are the
-    source digests the profiled run printed (its "source_digests")."""
+    calibrated by the 1 GiB device copy of --calibrate-copy, per kernel and
+    launch size.  The trailing 'family' lines (measured bytes over algorithmic
+    bytes, summed over the family's launches, with the digest of the kernel's
+    source file) are what the benchmark reads back to report measured traffic.
+    `digests` are the source digests the profiled run printed, `levels` its
+    hierarchy ([rows, entries] per level)."""
     digests = digests or source_digests()
     import collections
     import csv
@@ -164,37 +245,39 @@ def pmc_summary(fetch_csv, write_csv, n, digests=None):
         d = collections.defaultdict(list)
         for r in csv.DictReader(open(path)):
             if r["Counter_Name"] == cname:
-                d[r["Kernel_Name"]].append(float(r["Counter_Value"]) * 1024.0)  # KiB -> bytes
+                grid = int(r["Grid_Size"]) if r.get("Grid_Size") else 0
+                d[(r["Kernel_Name"], grid)].append(float(r["Counter_Value"]) * 1024.0)  # KiB -> bytes
         vals[cname] = d
     gib = float(1 << 30)
     cal = {}
     for cname in vals:
-        copies = [v for k, lst in vals[cname].items() if "copyBuffer" in k for v in lst]
+        copies = [v for (k, _), lst in vals[cname].items() if "copyBuffer" in k for v in lst]
         cal[cname] = gib / max(copies) if copies else 1.0
     lines = [f"calibration (1 GiB copy): FETCH_SIZE x{cal['FETCH_SIZE']:.4f}, WRITE_SIZE x{cal['WRITE_SIZE']:.4f}",
              "",
-             f"{'kernel':58s} {'launches':>8s} {'fetch MB':>10s} {'write MB':>10s} {'alg MB':>10s} {'traffic/alg':>11s}"]
+             f"{'kernel':52s} {'blocks':>7s} {'launches':>8s} {'fetch MB':>9s} {'write MB':>9s} {'alg MB':>9s} "
+             f"{'traffic/alg':>11s}"]
     rows = []
-    for k, lst in vals["FETCH_SIZE"].items():
-        w = vals["WRITE_SIZE"].get(k, [0.0])
+    for (k, grid), lst in vals["FETCH_SIZE"].items():
+        w = vals["WRITE_SIZE"].get((k, grid), [0.0])
         f_b = cal["FETCH_SIZE"] * sum(lst) / len(lst)
         w_b = cal["WRITE_SIZE"] * sum(w) / len(w)
-        alg = algorithmic_bytes(k, n)
-        rows.append((k, len(lst), f_b, w_b, alg))
-    rows.sort(key=lambda r: -(r[2] + r[3]) * r[1])
-    for k, cnt, f_b, w_b, alg in rows[:40]:
-        short = k.replace("rich::(anonymous namespace)::", "").replace("void ", "")[:58]
-        a = (alg[0] + alg[1]) if alg else None
-        lines.append(f"{short:58s} {cnt:8d} {f_b / 1e6:10.2f} {w_b / 1e6:10.2f} "
-                     f"{(a / 1e6 if a else float('nan')):10.2f} {((f_b + w_b) / a if a else float('nan')):11.3f}")
+        blocks = grid // 256 if grid else None
+        alg = algorithmic_bytes(k, n, blocks, levels)
+        rows.append((k, blocks, len(lst), f_b, w_b, alg))
+    rows.sort(key=lambda r: -(r[3] + r[4]) * r[2])
+    for k, blocks, cnt, f_b, w_b, alg in rows[:45]:
+        short = k.replace("rich::(anonymous namespace)::", "").replace("void ", "")[:52]
+        lines.append(f"{short:52s} {blocks if blocks else 0:7d} {cnt:8d} {f_b / 1e6:9.2f} {w_b / 1e6:9.2f} "
+                     f"{(alg / 1e6 if alg else float('nan')):9.2f} {((f_b + w_b) / alg if alg else float('nan')):11.3f}")
     lines += ["", "family      launches  traffic/alg  source digest"]
     for fam, (prefix, src) in FAMILIES.items():
-        sel = [r for r in rows if prefix in r[0] and r[4]]
+        sel = [r for r in rows if prefix in r[0] and r[5]]
         if not sel:
             continue
-        meas = sum((r[2] + r[3]) * r[1] for r in sel)
-        alg = sum((r[4][0] + r[4][1]) * r[1] for r in sel)
-        lines.append(f"family {fam} {sum(r[1] for r in sel)} {meas / alg:.4f} {src} {digests[src]}")
+        meas = sum((r[3] + r[4]) * r[2] for r in sel)
+        alg = sum(r[5] * r[2] for r in sel)
+        lines.append(f"family {fam} {sum(r[2] for r in sel)} {meas / alg:.4f} {src} {digests[src]}")
     return "\n".join(lines)
 
 
@@ -317,6 +400,9 @@ def main():
                     help="run one 1 GiB device copy first (reference for HBM traffic counters)")
     ap.add_argument("--mean", choices=["arith", "upstream", "harmonic", "geometric", "integral"],
                     help="override the workload's interface mean (experiments)")
+    ap.add_argument("--max-newton", type=int,
+                    help="Newton iteration limit per step (default: the recipe's; c5 with its harmonic mean: 3, "
+                         "enough to show that its steps do not converge)")
     ap.add_argument("--set", action="append", default=[], metavar="OPT=VALUE",
                     help="override a solver option (experiments; the headline uses the defaults)")
     ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "BENCH_JSON"),
@@ -340,8 +426,9 @@ def main():
         print(stats_summary(args.stats_summary))
         return
     if args.pmc_summary:
-        digests = json.load(open(args.pmc_summary[2]))["source_digests"]
-        print(pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.n ** 3, digests))
+        info = json.loads(open(args.pmc_summary[2]).read().strip().splitlines()[-1])
+        print(pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.n ** 3, info["source_digests"],
+                          info.get("hierarchy_n_nnz")))
         return
     if args.gpus != 1:
         print(f"bench.py: the solver runs on one GPU; --gpus {args.gpus} is not supported "
@@ -367,6 +454,13 @@ def main():
     for kv in args.set:
         k, v = kv.split("=")
         setattr(rec.options, k, type(getattr(rec.options, k))(float(v)))
+    if args.max_newton:
+        rec.options.max_newton = args.max_newton
+    elif args.workload == "c5" and rec.problem.mean == synth.HARMONIC:
+        # With the harmonic mean at this spacing and dt the Jacobian is indefinite along the
+        # infiltration mode and Newton from the previous level cannot converge (the CPU tests
+        # show the mechanism); a few iterations show it without spending minutes per step.
+        rec.options.max_newton = 3
     t = time.perf_counter()
     ks = rec.ks()
     p0 = rec.p0()
@@ -408,7 +502,8 @@ def main():
         full["mixed_over_fp64"] = full["mixed"]["value"] / full["fp64"]["value"]
 
     steps = args.steps
-    value = steps / mixed["t_timed"] if steps else 0.0
+    converged = all(s["status"] >= 0 for s in mixed["stats"])
+    value = steps / mixed["t_timed"] if steps and converged else 0.0
     out = {
         "metric": METRIC,
         "value": value,
@@ -438,6 +533,8 @@ def main():
         "levels": mixed["stats"][-1]["levels"] if mixed["stats"] else None,
         "opc": mixed["stats"][-1]["opc"] if mixed["stats"] else None,
         "statuses": sorted({s["status"] for s in mixed["stats"]}),
+        "converged": converged,
+        "max_newton": rec.options.max_newton,
         "linsolve_fails": sum(s["linsolve_fails"] for s in mixed["stats"]),
         "ls_backtracks": sum(s["ls_backtracks"] for s in mixed["stats"]),
         "hierarchy_n_nnz": mixed["levels"],
@@ -484,9 +581,9 @@ def main():
                            "avg_us": d["avg_us"], "bytes_per_launch": d["bytes_per_launch"]}
         if "spmv_J" in kern:
             out["spmv_hbm_gbs"] = kern["spmv_J"]["gbs"]
-    if not args.no_cpu:
+    if not args.no_cpu and mixed["stats"]:
         log("[bench] oracle CPU baseline ...")
-        out["cpu_baseline"] = cpu_baseline()
+        out["cpu_baseline"] = cpu_baseline(rec, ks, mixed["stats"])
     print(json.dumps(out), flush=True)
 
 

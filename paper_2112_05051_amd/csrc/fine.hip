@@ -113,6 +113,9 @@ __device__ inline Face face(const Phys &P, const Cell &q, uint32_t c, int f, con
 // Phys, always evaluated from the L side so both cells of a face agree bitwise.
 // With mean_vertical >= 0 the z faces take that mean (one mean for the
 // horizontal and another for the vertical direction).
+// INTEG = false leaves the integral mean out (for kernels launched only when
+// no face takes it: its quadrature loop costs registers in every caller).
+template <bool INTEG = true>
 __device__ inline void mean_of(const Phys &P, int axis, int dir, double pc, const Law &Lc, double Ksc, double pn,
                                const Law &Ln, double Ksn, double &Kf, double &dc, double &dn) {
     int mean = (axis == 2 && P.mean_vertical >= 0) ? P.mean_vertical : P.mean;
@@ -130,7 +133,7 @@ __device__ inline void mean_of(const Phys &P, int axis, int dir, double pc, cons
         Kf = g;
         dc = 0.5 * Ln.K * Lc.dK / g;
         dn = 0.5 * Lc.K * Ln.dK / g;
-    } else if (mean == RICH_MEAN_INTEGRAL) {
+    } else if (INTEG && mean == RICH_MEAN_INTEGRAL) {
         double pL = dir > 0 ? pc : pn, pU = dir > 0 ? pn : pc;
         double Ks = 0.5 * (dir > 0 ? Ksc + Ksn : Ksn + Ksc);
         double q = 0.0, qL = 0.0, qU = 0.0;
@@ -251,6 +254,285 @@ __global__ void k_assemble(Phys P, uint32_t n, const double *__restrict__ Ks, co
     }
     if (invd) invd[c] = 1.0 / l1;
     if (invdf) invdf[c] = f32_sat(1.0 / l1);
+}
+
+// ------------------------------------ plane-tiled residual and assembly
+// A block owns an FT_X x FT_Y tile of (x, y) columns and a run of z planes.
+// For each plane it stages the tile and a one-cell ring around it in LDS
+// (heads, K_s and the laws of every cell, each evaluated once; the tile's own
+// cells carry their laws over from the plane below, where they were the upper
+// neighbours), then computes every face between two cells of the domain once
+// (its interface mean and, for the Jacobian, the mean's derivatives) and
+// hands it to both cells: the face's term enters the lower-index cell's row
+// as it is and the upper cell's with the roles swapped.  Faces on the domain
+// boundary are taken per cell as in the one-thread-per-cell kernels.  Each
+// cell adds its faces in the order -x, +x, -y, +y, -z, +z.
+constexpr int FT_X = 32, FT_Y = 8, FT_TPB = FT_X * FT_Y;
+constexpr int FT_RX = FT_X + 2, FT_RY = FT_Y + 2, FT_RING = FT_RX * FT_RY;
+constexpr int FT_NRING = FT_RING - FT_TPB;  // ring positions staged per plane (84)
+constexpr int FT_NFX = (FT_X + 1) * FT_Y, FT_NFY = FT_X * (FT_Y + 1);
+
+// a face's interface mean and its derivatives w.r.t. the lower and upper heads
+struct FaceMean {
+    double Kf, dL, dU;
+};
+
+// The tile's ring positions, in LDS order of a (FT_RY x FT_RX) array: the
+// rows above and below the tile, then the left and right columns.
+__device__ inline int ring_pos(int t) {
+    if (t < FT_RX) return t;                                  // row 0
+    if (t < 2 * FT_RX) return (FT_RY - 1) * FT_RX + (t - FT_RX);  // last row
+    t -= 2 * FT_RX;                                           // 0 .. 2 FT_Y - 1
+    int r = 1 + t / 2;
+    return r * FT_RX + ((t & 1) ? FT_RX - 1 : 0);
+}
+
+template <bool JAC, bool INTEG>
+__global__ void __launch_bounds__(FT_TPB) k_faces_tiled(Phys P, int kz, const double *__restrict__ Ks,
+                                                        const double *__restrict__ p,
+                                                        const double *__restrict__ th_old, double *__restrict__ F,
+                                                        double *__restrict__ J7, double *__restrict__ M4,
+                                                        float *__restrict__ M4f, double *__restrict__ invd,
+                                                        float *__restrict__ invdf, int dflux) {
+    __shared__ double sp[FT_RING], sks[FT_RING], sK[FT_RING], sdK[JAC ? FT_RING : 1];
+    __shared__ double fx[JAC ? 3 : 1][FT_NFX], fy[JAC ? 3 : 1][FT_NFY];
+    const int tx = threadIdx.x % FT_X, ty = threadIdx.x / FT_X;
+    const int i0 = blockIdx.x * FT_X, j0 = blockIdx.y * FT_Y;
+    const int k0 = blockIdx.z * kz, k1 = min(k0 + kz, P.nz);
+    const int i = i0 + tx, j = j0 + ty;
+    const bool own = i < P.nx && j < P.ny;
+    const uint32_t nxy = (uint32_t)P.nx * (uint32_t)P.ny, n = nxy * (uint32_t)P.nz;
+    const int me = (ty + 1) * FT_RX + (tx + 1);
+    const double hx2 = P.hx * P.hx, hy2 = P.hy * P.hy, hz2 = P.hz * P.hz;
+    // the own column: current plane (c), the one above (u) and the face below
+    double pc = 0.0, ksc = 0.0, pu = 0.0, ksu = 0.0;
+    Law Lc{}, Lu{};
+    // residual: diffusive flux and gravity term of the face below / above, as they
+    // enter the lower cell's row (the upper cell takes their negatives)
+    double q_dn = 0.0, g_dn = 0.0, q_up = 0.0, g_up = 0.0;
+    FaceMean m_dn{}, m_up{};                // Jacobian: means of those faces
+    double pd = 0.0, dKd = 0.0;             // Jacobian: head and K' of the cell below
+    const uint32_t col = own ? (uint32_t)i + (uint32_t)P.nx * (uint32_t)j : 0u;
+    if (own) {
+        const uint32_t c = col + nxy * (uint32_t)k0;
+        pc = p[c];
+        ksc = Ks[c];
+        Lc = laws(P, pc, ksc);
+        if (k0 > 0) {
+            const uint32_t cd = c - nxy;
+            pd = p[cd];
+            const double ksd = Ks[cd];
+            const Law Ld = laws(P, pd, ksd);
+            double Kf, dL, dU;
+            mean_of<INTEG>(P, 2, 1, pd, Ld, ksd, pc, Lc, ksc, Kf, dL, dU);
+            q_dn = -Kf * (pc - pd) / hz2;
+            g_dn = -(Ld.K + Lc.K) / (2.0 * P.hz);
+            m_dn = {Kf, dL, dU};
+            dKd = Ld.dK;
+        }
+    }
+    for (int k = k0; k < k1; k++) {
+        // stage plane k: the own cells from registers, the ring from memory
+        if (own) {
+            sp[me] = pc;
+            sks[me] = ksc;
+            sK[me] = Lc.K;
+            if constexpr (JAC) sdK[me] = Lc.dK;
+        }
+        if (threadIdx.x < FT_NRING) {
+            const int pos = ring_pos(threadIdx.x);
+            const int gi = i0 - 1 + pos % FT_RX, gj = j0 - 1 + pos / FT_RX;
+            if (gi >= 0 && gi < P.nx && gj >= 0 && gj < P.ny) {
+                const uint32_t cc = (uint32_t)gi + (uint32_t)P.nx * ((uint32_t)gj + (uint32_t)P.ny * (uint32_t)k);
+                const double pr = p[cc], kr = Ks[cc];
+                const Law L = laws(P, pr, kr);
+                sp[pos] = pr;
+                sks[pos] = kr;
+                sK[pos] = L.K;
+                if constexpr (JAC) sdK[pos] = L.dK;
+            }
+        }
+        // the own column's cell above and the face between
+        const bool up = own && k + 1 < P.nz;
+        if (up) {
+            const uint32_t cu = col + nxy * (uint32_t)(k + 1);
+            pu = p[cu];
+            ksu = Ks[cu];
+            Lu = laws(P, pu, ksu);
+            double Kf, dL, dU;
+            mean_of<INTEG>(P, 2, 1, pc, Lc, ksc, pu, Lu, ksu, Kf, dL, dU);
+            q_up = -Kf * (pu - pc) / hz2;
+            g_up = -(Lc.K + Lu.K) / (2.0 * P.hz);
+            m_up = {Kf, dL, dU};
+        }
+        __syncthreads();
+        // x faces: face f joins tile columns f - 1 (lower) and f of row r
+        for (int t = threadIdx.x; t < FT_NFX; t += FT_TPB) {
+            const int f = t % (FT_X + 1), r = t / (FT_X + 1);
+            const int iL = i0 + f - 1, jj = j0 + r;
+            if (iL >= 0 && iL + 1 < P.nx && jj < P.ny) {
+                const int a = (r + 1) * FT_RX + f, b = a + 1;
+                Law La{0.0, 0.0, sK[a], JAC ? sdK[a] : 0.0}, Lb{0.0, 0.0, sK[b], JAC ? sdK[b] : 0.0};
+                double Kf, dL, dU;
+                mean_of<INTEG>(P, 0, 1, sp[a], La, sks[a], sp[b], Lb, sks[b], Kf, dL, dU);
+                if constexpr (JAC) {
+                    fx[0][t] = Kf;
+                    fx[1][t] = dL;
+                    fx[2][t] = dU;
+                } else {
+                    fx[0][t] = -Kf * (sp[b] - sp[a]) / hx2;
+                }
+            }
+        }
+        // y faces: face g joins tile rows g - 1 (lower) and g of column c
+        for (int t = threadIdx.x; t < FT_NFY; t += FT_TPB) {
+            const int c = t % FT_X, g = t / FT_X;
+            const int jL = j0 + g - 1, ii = i0 + c;
+            if (jL >= 0 && jL + 1 < P.ny && ii < P.nx) {
+                const int a = g * FT_RX + c + 1, b = a + FT_RX;
+                Law La{0.0, 0.0, sK[a], JAC ? sdK[a] : 0.0}, Lb{0.0, 0.0, sK[b], JAC ? sdK[b] : 0.0};
+                double Kf, dL, dU;
+                mean_of<INTEG>(P, 1, 1, sp[a], La, sks[a], sp[b], Lb, sks[b], Kf, dL, dU);
+                if constexpr (JAC) {
+                    fy[0][t] = Kf;
+                    fy[1][t] = dL;
+                    fy[2][t] = dU;
+                } else {
+                    fy[0][t] = -Kf * (sp[b] - sp[a]) / hy2;
+                }
+            }
+        }
+        __syncthreads();
+        if (own) {
+            const uint32_t c = col + nxy * (uint32_t)k;
+            const Cell q{i, j, k};
+            // the face of direction f: interior (shared, from LDS or the column
+            // registers) unless it lies on the domain boundary
+            const int fxm = ty * (FT_X + 1) + tx, fym = ty * FT_X + tx;
+            // whether face f has a neighbour in the domain, and that neighbour's LDS slot (x, y faces)
+            auto inside = [&](int f) {
+                return f == 0 ? i > 0 : f == 1 ? i + 1 < P.nx : f == 2 ? j > 0 : f == 3 ? j + 1 < P.ny
+                     : f == 4 ? k > 0 : k + 1 < P.nz;
+            };
+            auto slot = [&](int f) { return f == 0 ? me - 1 : f == 1 ? me + 1 : f == 2 ? me - FT_RX : me + FT_RX; };
+            if constexpr (!JAC) {
+                double acc = (Lc.th - th_old[c]) / P.dt;
+#pragma unroll
+                for (int f = 0; f < 6; f++) {
+                    if (inside(f)) {
+                        // the cell is the lower one on its + faces
+                        const double v = f == 0 ? fx[0][fxm] : f == 1 ? fx[0][fxm + 1] : f == 2 ? fy[0][fym]
+                                       : f == 3 ? fy[0][fym + FT_X] : f == 4 ? q_dn : q_up;
+                        acc += (f & 1) ? v : -v;
+                        if (f == 4) acc += -g_dn;
+                        if (f == 5) acc += g_up;
+                        continue;
+                    }
+                    Face fc = face(P, q, c, f, p, Ks);
+                    if (fc.kind == 0) continue;
+                    Law Ln = laws(P, fc.pn, fc.Ksn);
+                    double Kf, dcc, dnn;
+                    int dir = (f & 1) ? 1 : -1;
+                    mean_of<INTEG>(P, f >> 1, dir, pc, Lc, ksc, fc.pn, Ln, fc.Ksn, Kf, dcc, dnn);
+                    acc += -Kf * (fc.pn - pc) / (fc.h * fc.h);
+                    if ((f >> 1) == 2) acc += dir * (-(Lc.K + Ln.K) / (2.0 * P.hz));
+                }
+                F[c] = acc;
+            } else {
+                double jd = Lc.dth / P.dt, md = Lc.dth / P.dt;
+                double joff[6] = {0, 0, 0, 0, 0, 0}, moff[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+                for (int f = 0; f < 6; f++) {
+                    const int axis = f >> 1, dir = (f & 1) ? 1 : -1;
+                    double Kf, dcc, dnn, pn, dKn, h2;
+                    bool interior;
+                    if (inside(f)) {
+                        interior = true;
+                        FaceMean m;
+                        if (f < 2) {
+                            const int t = fxm + f;
+                            m = {fx[0][t], fx[1][t], fx[2][t]};
+                        } else if (f < 4) {
+                            const int t = fym + (f - 2) * FT_X;
+                            m = {fy[0][t], fy[1][t], fy[2][t]};
+                        } else {
+                            m = f == 4 ? m_dn : m_up;
+                        }
+                        Kf = m.Kf;
+                        // the cell is the lower one on its + faces
+                        dcc = dir > 0 ? m.dL : m.dU;
+                        dnn = dir > 0 ? m.dU : m.dL;
+                        if (f < 4) {
+                            pn = sp[slot(f)];
+                            dKn = sdK[slot(f)];
+                        } else {
+                            pn = f == 4 ? pd : pu;
+                            dKn = f == 4 ? dKd : Lu.dK;
+                        }
+                        h2 = axis == 0 ? hx2 : axis == 1 ? hy2 : hz2;
+                    } else {
+                        Face fc = face(P, q, c, f, p, Ks);
+                        if (fc.kind == 0) continue;
+                        interior = false;
+                        Law Ln = laws(P, fc.pn, fc.Ksn);
+                        mean_of<INTEG>(P, axis, dir, pc, Lc, ksc, fc.pn, Ln, fc.Ksn, Kf, dcc, dnn);
+                        pn = fc.pn;
+                        dKn = Ln.dK;
+                        h2 = fc.h * fc.h;
+                    }
+                    const double dp = pn - pc;
+                    const bool zf = axis == 2;
+                    jd += Kf / h2 - dp / h2 * dcc;
+                    if (zf) jd += -dir * Lc.dK / (2.0 * P.hz);
+                    md += Kf / h2;
+                    if (dflux) md += -dp / h2 * dcc;
+                    if (interior) {
+                        double v = -Kf / h2 - dp / h2 * dnn;
+                        if (zf) v += -dir * dKn / (2.0 * P.hz);
+                        joff[f] = v;
+                        moff[f] = -Kf / h2;
+                    }
+                }
+                J7[(size_t)J_D * n + c] = jd;
+                J7[(size_t)J_XM * n + c] = joff[0];
+                J7[(size_t)J_XP * n + c] = joff[1];
+                J7[(size_t)J_YM * n + c] = joff[2];
+                J7[(size_t)J_YP * n + c] = joff[3];
+                J7[(size_t)J_ZM * n + c] = joff[4];
+                J7[(size_t)J_ZP * n + c] = joff[5];
+                M4[(size_t)M_D * n + c] = md;
+                M4[(size_t)M_XP * n + c] = moff[1];
+                M4[(size_t)M_YP * n + c] = moff[3];
+                M4[(size_t)M_ZP * n + c] = moff[5];
+                double l1 = md;
+#pragma unroll
+                for (int f = 0; f < 6; f++) l1 += fabs(moff[f]);
+                if (M4f) {
+                    M4f[(size_t)M_D * n + c] = f32_sat(md);
+                    M4f[(size_t)M_XP * n + c] = f32_sat(moff[1]);
+                    M4f[(size_t)M_YP * n + c] = f32_sat(moff[3]);
+                    M4f[(size_t)M_ZP * n + c] = f32_sat(moff[5]);
+                }
+                if (invd) invd[c] = 1.0 / l1;
+                if (invdf) invdf[c] = f32_sat(1.0 / l1);
+            }
+        }
+        // carry the column up one plane
+        if (up) {
+            if constexpr (JAC) {
+                pd = pc;
+                dKd = Lc.dK;
+                m_dn = m_up;
+            } else {
+                q_dn = q_up;
+                g_dn = g_up;
+            }
+            pc = pu;
+            ksc = ksu;
+            Lc = Lu;
+        }
+        __syncthreads();  // the staged plane and faces are overwritten next
+    }
 }
 
 // y = J x, J in the 7-array stencil form; x may be FP32 (mixed path).
@@ -759,10 +1041,41 @@ rich_status launch_theta(const Phys &P, const double *p, double *theta, hipStrea
     return RICH_OK;
 }
 
+// Grid of the plane-tiled kernels: FT_X x FT_Y columns per block and enough
+// planes per block that the launch has about 2048 blocks; false when the
+// (x, y) tiling does not fit the launch limits (the one-thread-per-cell
+// kernels take those grids).
+static bool has_integral(const Phys &P) {
+    return P.mean == RICH_MEAN_INTEGRAL || P.mean_vertical == RICH_MEAN_INTEGRAL;
+}
+
+static bool faces_grid(const Phys &P, dim3 *g, int *kz) {
+    const int64_t tx = (P.nx + FT_X - 1) / FT_X, ty = (P.ny + FT_Y - 1) / FT_Y;
+    if (tx > 0x7fffffff || ty > 65535) return false;
+    const int64_t want = std::max<int64_t>(1, 2048 / std::max<int64_t>(1, tx * ty));
+    int64_t z = (P.nz + want - 1) / want;
+    z = std::min<int64_t>(std::max<int64_t>(z, 1), 64);
+    const int64_t tz = (P.nz + z - 1) / z;
+    if (tz > 65535) return false;
+    *g = dim3((unsigned)tx, (unsigned)ty, (unsigned)tz);
+    *kz = (int)z;
+    return true;
+}
+
 rich_status launch_residual(const Phys &P, const double *Ks, const double *p, const double *theta_old,
                             double *F, hipStream_t s) {
     uint32_t n = ncells(P);
-    k_residual<<<nblocks(n), TPB, 0, s>>>(P, n, Ks, p, theta_old, F);
+    dim3 g;
+    int kz;
+    if (faces_grid(P, &g, &kz)) {
+        if (has_integral(P))
+            k_faces_tiled<false, true><<<g, FT_TPB, 0, s>>>(P, kz, Ks, p, theta_old, F, nullptr, nullptr, nullptr,
+                                                            nullptr, nullptr, 0);
+        else
+            k_faces_tiled<false, false><<<g, FT_TPB, 0, s>>>(P, kz, Ks, p, theta_old, F, nullptr, nullptr, nullptr,
+                                                             nullptr, nullptr, 0);
+    } else
+        k_residual<<<nblocks(n), TPB, 0, s>>>(P, n, Ks, p, theta_old, F);
     LAUNCH_CHECK();
     return RICH_OK;
 }
@@ -770,7 +1083,17 @@ rich_status launch_residual(const Phys &P, const double *Ks, const double *p, co
 rich_status launch_assemble(const Phys &P, const double *Ks, const double *p, double *J7, double *M4,
                             float *M4f, double *invd, float *invdf, int dflux, hipStream_t s) {
     uint32_t n = ncells(P);
-    k_assemble<<<nblocks(n), TPB, 0, s>>>(P, n, Ks, p, J7, M4, M4f, invd, invdf, dflux);
+    dim3 g;
+    int kz;
+    if (faces_grid(P, &g, &kz)) {
+        if (has_integral(P))
+            k_faces_tiled<true, true><<<g, FT_TPB, 0, s>>>(P, kz, Ks, p, nullptr, nullptr, J7, M4, M4f, invd, invdf,
+                                                           dflux);
+        else
+            k_faces_tiled<true, false><<<g, FT_TPB, 0, s>>>(P, kz, Ks, p, nullptr, nullptr, J7, M4, M4f, invd,
+                                                            invdf, dflux);
+    } else
+        k_assemble<<<nblocks(n), TPB, 0, s>>>(P, n, Ks, p, J7, M4, M4f, invd, invdf, dflux);
     LAUNCH_CHECK();
     return RICH_OK;
 }

@@ -415,7 +415,9 @@ rich_status vcycle(rich_ctx *h, const double *b, const double *bs, T *z) {
         return launch_st_pre<double, T>(h->P, M4, invd0, b, bs, (T *)H.L[0].r, s);
     }));
     const Level &L0 = H.L[0];
-    double rbytes = L0.prow ? (double)L0.pnnz * (4 + 2 * t) + n1 * (8 + t) : n0 * (t + 4) + n1 * (8 + t);
+    // (+ the coarse pre-smoothed iterate and the inverse diagonal it needs, below the coarsest level)
+    double rbytes = (L0.prow ? (double)L0.pnnz * (4 + 2 * t) + n1 * (8 + t) : n0 * (t + 4) + n1 * (8 + t)) +
+                    (H.nlev > 2 ? 2 * t * n1 : 0.0);
     // each restriction also stores the next level's pre-smoothed iterate
     // x0 = D^{-1} b in its x buffer, except for the coarsest level
     auto x0_of = [&](int l) { return l < H.nlev - 1 ? (T *)H.L[l].x : nullptr; };
@@ -429,7 +431,7 @@ rich_status vcycle(rich_ctx *h, const double *b, const double *bs, T *z) {
         RICH_TRY(timed(h, l == 1 ? RICH_K_VC1_PRE : RICH_K_COUNT, bytes, [&] {
             return launch_csr_pre<T, T>(Lv, lvval<T>(Lv), (const T *)Lv.x, (const T *)Lv.b, (T *)Lv.r, s);
         }));
-        charge(h, (double)Lv.n * (t + 4) + (double)H.L[l + 1].n * (8 + t));
+        charge(h, (double)Lv.n * (t + 4) + (double)H.L[l + 1].n * (8 + t + (l + 1 < H.nlev - 1 ? 2 * t : 0)));
         RICH_TRY(launch_restrict<T>(Lv, (const T *)Lv.r, (T *)H.L[l + 1].b, H.L[l + 1].n, lvinvd<T>(H.L[l + 1]),
                                     x0_of(l + 1), s));
     }
