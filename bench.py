@@ -336,7 +336,8 @@ def run_serving(args):
             rec.problem.mean = synth.MEAN_NAMES[args.serve_mean]
     log(f"[serve] generating {len(reqs)} request fields")
     inputs = [(t, rec, rec.ks(), rec.p0()) for t, rec in reqs]
-    srv = rich.Server(int(args.serve_budget_gb * (1 << 30)), args.serve_active, fused=args.serve_fused)
+    srv = rich.Server(int(args.serve_budget_gb * (1 << 30)), args.serve_active,
+                      fused=args.serve_fused or args.serve_persistent, persistent=args.serve_persistent)
     ids = []
     t0 = time.perf_counter()
     for t_arr, rec, ks, p0 in inputs:
@@ -372,7 +373,8 @@ def run_serving(args):
         "value": total_steps / makespan, "unit": "time-steps/s", "n_gpus": 1,
         "requests": len(ids), "steps_per_request": args.serve_steps, "arrival_rate_per_s": args.serve_rate,
         "max_active": args.serve_active, "budget_gb": args.serve_budget_gb, "makespan_s": makespan,
-        "fused": args.serve_fused, "batched_flushes": flushes,
+        "fused": args.serve_fused or args.serve_persistent, "persistent": args.serve_persistent,
+        "batched_flushes": flushes,
         "batched_products": products, "mean_batch": products / flushes if flushes else None,
         "total_steps": total_steps, "p50_step_ms": float(np.percentile(step_ms, 50)),
         "p99_step_ms": float(np.percentile(step_ms, 99)),
@@ -426,6 +428,8 @@ def main():
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     ap.add_argument("--serve-fused", action="store_true",
                     help="fuse the preconditioned products of same-size simulations into batched launches")
+    ap.add_argument("--serve-persistent", action="store_true",
+                    help="fused batched launches as persistent grids taking work from a device-side queue")
     ap.add_argument("--serve-sizes", default="32,48,64,80,96", help="cube sizes the requests draw from")
     ap.add_argument("--serve-mean", choices=["arith", "upstream", "harmonic"],
                     help="one interface mean for every request (default: drawn per request)")

@@ -376,10 +376,18 @@ rich_status rich_server_submit(rich_server_t s, const rich_problem_t *prob, cons
  * Every output pointer may be NULL. */
 rich_status rich_server_poll(rich_server_t s, int64_t req_id, int *state, rich_status *result, double *p_host,
                              rich_step_stats_t *stats_host, double *step_ms_host, double *times_host);
-/* Fused batching on (fused != 0) or off (the default: every simulation
- * launches on its own stream, which measures faster on the ensembles tried).
- * Only before the first submission: RICH_ESTATE afterwards. */
-rich_status rich_server_set_batching(rich_server_t s, int fused);
+/* Batching mode: RICH_BATCH_OFF (the default: every simulation launches on
+ * its own stream, which measures faster on the ensembles tried),
+ * RICH_BATCH_FUSED (one launch per kernel over the posted products, one
+ * thread block per block of work) or RICH_BATCH_PERSISTENT (the same fused
+ * launches as persistent grids: a fixed number of thread blocks, each taking
+ * blocks of work from a device-side work counter until none is left; every
+ * block leaves once the counter passes the launch's total).  Only before the
+ * first submission: RICH_ESTATE afterwards; RICH_EINVAL for another mode. */
+#define RICH_BATCH_OFF 0
+#define RICH_BATCH_FUSED 1
+#define RICH_BATCH_PERSISTENT 2
+rich_status rich_server_set_batching(rich_server_t s, int mode);
 /* Batched flushes so far and the products they carried (their ratio is the
  * mean number of simulations per fused launch). */
 rich_status rich_server_batch_stats(rich_server_t s, int64_t *flushes, int64_t *products);

@@ -393,15 +393,18 @@ def match_sweep(rowptr, col, val, stream=None, agg=None, noalloc=False):
 
 
 REQ_QUEUED, REQ_RUNNING, REQ_DONE = 0, 1, 2
+BATCH_OFF, BATCH_FUSED, BATCH_PERSISTENT = 0, 1, 2
 
 
 class Server:
     """Ensemble server (rich_server_t): FIFO admission by device-memory budget,
     resident simulations on concurrent streams, their preconditioned products
-    fused into batched launches when ``fused`` is true.  Inputs/outputs are
+    fused into batched launches when ``fused`` is true (as persistent grids on
+    a device work queue when ``persistent`` is also true).  Inputs/outputs are
     host arrays."""
 
-    def __init__(self, hbm_budget_bytes: int, max_active: int = 4, fused: bool = False, stream=None):
+    def __init__(self, hbm_budget_bytes: int, max_active: int = 4, fused: bool = False, stream=None,
+                 persistent: bool = False):
         L = load()
         self._L = L
         self._s = C.c_void_p()
@@ -409,7 +412,8 @@ class Server:
         self._steps = {}
         hs = C.c_void_p(stream.cuda_stream) if stream is not None else None
         _check(L.rich_server_create(hbm_budget_bytes, max_active, hs, C.byref(self._s)), "rich_server_create")
-        _check(L.rich_server_set_batching(self._s, 1 if fused else 0), "rich_server_set_batching")
+        mode = BATCH_PERSISTENT if (fused and persistent) else BATCH_FUSED if fused else BATCH_OFF
+        _check(L.rich_server_set_batching(self._s, mode), "rich_server_set_batching")
 
     def batch_stats(self):
         """(flushes, products): batched flushes so far and the products they carried."""

@@ -648,23 +648,23 @@ struct CoarseArgs {
 // (val = Ainv, b = bc, out = x)
 template <class T, int MODE>
 __global__ void k_coarse_batch(Batch<CoarseArgs<T>> B) {
-    const unsigned L = MODE == 2 ? blockIdx.x : xcd_block();
-    if (L >= B.begin[B.n]) return;
-    const int e = batch_entry(B, L);
-    const CoarseArgs<T> &a = B.a[e];
-    const int64_t blk = (int64_t)(L - B.begin[e]);
-    if (MODE == 0) restrict_block(a.n, a.mptr, a.mem, a.b, a.out, a.invd, a.x0c, blk);
-    if (MODE == 1) csr_prolong_at(a.n, a.b, a.v, a.agg, a.out, blk * blockDim.x + threadIdx.x);
-    if (MODE == 2) dense_gemv_at(a.val, a.b, a.out, a.n, blk);
+    for_each_block(B, MODE == 2 ? blockIdx.x : xcd_block(), [&](unsigned L) {
+        const int e = batch_entry(B, L);
+        const CoarseArgs<T> &a = B.a[e];
+        const int64_t blk = (int64_t)(L - B.begin[e]);
+        if (MODE == 0) restrict_block(a.n, a.mptr, a.mem, a.b, a.out, a.invd, a.x0c, blk);
+        if (MODE == 1) csr_prolong_at(a.n, a.b, a.v, a.agg, a.out, blk * blockDim.x + threadIdx.x);
+        if (MODE == 2) dense_gemv_at(a.val, a.b, a.out, a.n, blk);
+    });
 }
 
 template <int G, class T, bool POST>
 __global__ void __launch_bounds__(256) k_csr_stream_batch(Batch<CoarseArgs<T>> B) {
-    const unsigned L = xcd_block();
-    if (L >= B.begin[B.n]) return;
-    const int e = batch_entry(B, L);
-    const CoarseArgs<T> &a = B.a[e];
-    csr_stream_body<G, T, T, POST>(a.rb, a.rowptr, a.col, a.val, a.invd, a.b, a.v, a.out, L - B.begin[e]);
+    for_each_block(B, xcd_block(), [&](unsigned L) {
+        const int e = batch_entry(B, L);
+        const CoarseArgs<T> &a = B.a[e];
+        csr_stream_body<G, T, T, POST>(a.rb, a.rowptr, a.col, a.val, a.invd, a.b, a.v, a.out, L - B.begin[e]);
+    });
 }
 
 __global__ void k_csr_spmv(int64_t n, const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
@@ -1180,7 +1180,7 @@ static CoarseArgs<T> coarse_args() {
 }
 
 template <class T, bool POST>
-static rich_status stream_batch(const std::vector<CsrItem<T>> &v, hipStream_t s) {
+static rich_status stream_batch(const std::vector<CsrItem<T>> &v, hipStream_t s, WorkQueue *q) {
     for (int G : {1, 2, 4, 8}) {
         std::vector<CoarseArgs<T>> a;
         std::vector<unsigned> nb;
@@ -1203,22 +1203,22 @@ static rich_status stream_batch(const std::vector<CsrItem<T>> &v, hipStream_t s)
         }
         using B = Batch<CoarseArgs<T>>;
         switch (G) {
-        case 1: RICH_TRY(launch_batches(a, nb, [&](const B &bt, unsigned g) { k_csr_stream_batch<1, T, POST><<<g, 256, 0, s>>>(bt); })); break;
-        case 2: RICH_TRY(launch_batches(a, nb, [&](const B &bt, unsigned g) { k_csr_stream_batch<2, T, POST><<<g, 256, 0, s>>>(bt); })); break;
-        case 4: RICH_TRY(launch_batches(a, nb, [&](const B &bt, unsigned g) { k_csr_stream_batch<4, T, POST><<<g, 256, 0, s>>>(bt); })); break;
-        default: RICH_TRY(launch_batches(a, nb, [&](const B &bt, unsigned g) { k_csr_stream_batch<8, T, POST><<<g, 256, 0, s>>>(bt); })); break;
+        case 1: RICH_TRY(launch_batches(a, nb, [&](const B &bt, unsigned g) { k_csr_stream_batch<1, T, POST><<<g, 256, 0, s>>>(bt); }, q)); break;
+        case 2: RICH_TRY(launch_batches(a, nb, [&](const B &bt, unsigned g) { k_csr_stream_batch<2, T, POST><<<g, 256, 0, s>>>(bt); }, q)); break;
+        case 4: RICH_TRY(launch_batches(a, nb, [&](const B &bt, unsigned g) { k_csr_stream_batch<4, T, POST><<<g, 256, 0, s>>>(bt); }, q)); break;
+        default: RICH_TRY(launch_batches(a, nb, [&](const B &bt, unsigned g) { k_csr_stream_batch<8, T, POST><<<g, 256, 0, s>>>(bt); }, q)); break;
         }
     }
     return RICH_OK;
 }
 
 template <class T>
-rich_status launch_csr_pre_batch(const std::vector<CsrItem<T>> &v, hipStream_t s) {
-    return stream_batch<T, false>(v, s);
+rich_status launch_csr_pre_batch(const std::vector<CsrItem<T>> &v, hipStream_t s, WorkQueue *q) {
+    return stream_batch<T, false>(v, s, q);
 }
 
 template <class T>
-rich_status launch_csr_post_batch(const std::vector<CsrItem<T>> &v, hipStream_t s) {
+rich_status launch_csr_post_batch(const std::vector<CsrItem<T>> &v, hipStream_t s, WorkQueue *q) {
     // xt = x0 + P xc into each level's r buffer, then post-smoothing from xt
     std::vector<CoarseArgs<T>> a;
     std::vector<unsigned> nb;
@@ -1235,12 +1235,12 @@ rich_status launch_csr_post_batch(const std::vector<CsrItem<T>> &v, hipStream_t 
     }
     RICH_TRY(launch_batches(a, nb, [&](const Batch<CoarseArgs<T>> &bt, unsigned g) {
         k_coarse_batch<T, 1><<<g, TPB, 0, s>>>(bt);
-    }));
-    return stream_batch<T, true>(v, s);
+    }, q));
+    return stream_batch<T, true>(v, s, q);
 }
 
 template <class T>
-rich_status launch_restrict_batch(const std::vector<RestrictItem<T>> &v, hipStream_t s) {
+rich_status launch_restrict_batch(const std::vector<RestrictItem<T>> &v, hipStream_t s, WorkQueue *q) {
     std::vector<CoarseArgs<T>> a;
     std::vector<unsigned> nb;
     for (const auto &it : v) {
@@ -1257,11 +1257,11 @@ rich_status launch_restrict_batch(const std::vector<RestrictItem<T>> &v, hipStre
     }
     return launch_batches(a, nb, [&](const Batch<CoarseArgs<T>> &bt, unsigned g) {
         k_coarse_batch<T, 0><<<g, TPB, 0, s>>>(bt);
-    });
+    }, q);
 }
 
 template <class T>
-rich_status launch_dense_gemv_batch(const std::vector<GemvItem<T>> &v, hipStream_t s) {
+rich_status launch_dense_gemv_batch(const std::vector<GemvItem<T>> &v, hipStream_t s, WorkQueue *q) {
     std::vector<CoarseArgs<T>> a;
     std::vector<unsigned> nb;
     for (const auto &it : v) {
@@ -1275,14 +1275,14 @@ rich_status launch_dense_gemv_batch(const std::vector<GemvItem<T>> &v, hipStream
     }
     return launch_batches(a, nb, [&](const Batch<CoarseArgs<T>> &bt, unsigned g) {
         k_coarse_batch<T, 2><<<g, TPB, 0, s>>>(bt);
-    });
+    }, q);
 }
 
 #define INST_BATCH(T)                                                                              \
-    template rich_status launch_csr_pre_batch<T>(const std::vector<CsrItem<T>> &, hipStream_t);      \
-    template rich_status launch_csr_post_batch<T>(const std::vector<CsrItem<T>> &, hipStream_t);     \
-    template rich_status launch_restrict_batch<T>(const std::vector<RestrictItem<T>> &, hipStream_t); \
-    template rich_status launch_dense_gemv_batch<T>(const std::vector<GemvItem<T>> &, hipStream_t);
+    template rich_status launch_csr_pre_batch<T>(const std::vector<CsrItem<T>> &, hipStream_t, WorkQueue *);      \
+    template rich_status launch_csr_post_batch<T>(const std::vector<CsrItem<T>> &, hipStream_t, WorkQueue *);     \
+    template rich_status launch_restrict_batch<T>(const std::vector<RestrictItem<T>> &, hipStream_t, WorkQueue *); \
+    template rich_status launch_dense_gemv_batch<T>(const std::vector<GemvItem<T>> &, hipStream_t, WorkQueue *);
 INST_BATCH(double)
 INST_BATCH(float)
 

@@ -74,6 +74,10 @@ struct Batch {
     int n = 0;
     unsigned begin[RICH_BATCH_MAX + 1] = {};
     A a[RICH_BATCH_MAX];
+    // persistent launches: a fixed grid whose blocks take virtual blocks from
+    // the device counter *ctr (values from `base` on belong to this launch)
+    unsigned long long *ctr = nullptr;
+    unsigned long long base = 0;
 };
 template <class A>
 __device__ inline int batch_entry(const Batch<A> &B, unsigned L) {
@@ -81,10 +85,45 @@ __device__ inline int batch_entry(const Batch<A> &B, unsigned L) {
     for (int t = 1; t < B.n; t++) e += L >= B.begin[t] ? 1 : 0;
     return e;
 }
-// Host side: group items into batches of at most RICH_BATCH_MAX and call
-// launch(batch, grid) for each (grid = total blocks rounded up to the XCDs).
+// The virtual blocks a thread block of a batched launch runs: its own one
+// (XCD-aware order), or, in a persistent launch, one after another from the
+// launch's work counter until the counter passes the batch's total.  Every
+// block's last fetch finds the total passed and leaves, so each block of the
+// grid fetches exactly once more than the virtual blocks it ran: the counter
+// advances by total + grid per launch, which the host adds to the next
+// launch's base.  f must be block-uniform in its barriers (it is the body of
+// the lone launch, whose early returns depend on the virtual block only).
 template <class A, class F>
-rich_status launch_batches(const std::vector<A> &items, const std::vector<unsigned> &blocks, F launch) {
+__device__ __forceinline__ void for_each_block(const Batch<A> &B, unsigned first, F &&f) {
+    const unsigned total = B.begin[B.n];
+    if (!B.ctr) {
+        if (first < total) f(first);
+        return;
+    }
+    __shared__ unsigned s_next;
+    const bool lead = threadIdx.x == 0 && threadIdx.y == 0;
+    for (;;) {
+        __syncthreads();  // the previous virtual block is done with LDS and s_next
+        if (lead) s_next = (unsigned)(atomicAdd(B.ctr, 1ull) - B.base);
+        __syncthreads();
+        const unsigned L = s_next;
+        if (L >= total) return;
+        f(L);
+    }
+}
+// A work counter of persistent batched launches on one stream, with the
+// host's account of the values already consumed.
+struct WorkQueue {
+    unsigned long long *ctr = nullptr;  // device, zero at creation
+    unsigned long long next = 0;        // first value of the next launch
+    unsigned grid = 1024;               // thread blocks of a persistent launch
+};
+// Host side: group items into batches of at most RICH_BATCH_MAX and call
+// launch(batch, grid) for each (grid = total blocks rounded up to the XCDs,
+// or, with a work queue, a persistent grid of at most q->grid blocks).
+template <class A, class F>
+rich_status launch_batches(const std::vector<A> &items, const std::vector<unsigned> &blocks, F launch,
+                           WorkQueue *q = nullptr) {
     for (size_t i0 = 0; i0 < items.size(); i0 += RICH_BATCH_MAX) {
         Batch<A> B;
         size_t i1 = items.size() < i0 + RICH_BATCH_MAX ? items.size() : i0 + RICH_BATCH_MAX;
@@ -97,7 +136,14 @@ rich_status launch_batches(const std::vector<A> &items, const std::vector<unsign
         }
         B.begin[B.n] = tot;
         if (tot == 0) continue;
-        launch(B, (tot + NXCD - 1) / NXCD * NXCD);
+        unsigned grid = (tot + NXCD - 1) / NXCD * NXCD;
+        if (q) {
+            grid = tot < q->grid ? tot : q->grid;
+            B.ctr = q->ctr;
+            B.base = q->next;
+            q->next += (unsigned long long)tot + grid;
+        }
+        launch(B, grid);
         LAUNCH_CHECK();
     }
     return RICH_OK;
@@ -206,9 +252,9 @@ struct FineItem {
     T *out;
 };
 template <class TB, class T>
-rich_status launch_st_pre_batch(const std::vector<FineItem<TB, T>> &items, hipStream_t s);
+rich_status launch_st_pre_batch(const std::vector<FineItem<TB, T>> &items, hipStream_t s, WorkQueue *q = nullptr);
 template <class TB, class T>
-rich_status launch_st_post_batch(const std::vector<FineItem<TB, T>> &items, hipStream_t s);
+rich_status launch_st_post_batch(const std::vector<FineItem<TB, T>> &items, hipStream_t s, WorkQueue *q = nullptr);
 template <class TX>
 struct SpmvItem {
     const Phys *P;
@@ -217,7 +263,7 @@ struct SpmvItem {
     double *y;
 };
 template <class TX>
-rich_status launch_spmv_J_batch(const std::vector<SpmvItem<TX>> &items, hipStream_t s);
+rich_status launch_spmv_J_batch(const std::vector<SpmvItem<TX>> &items, hipStream_t s, WorkQueue *q = nullptr);
 template <class TB, class T>
 rich_status launch_st_sweeps(const Phys &P, const T *M4, const T *invd, const TB *b, T *x, T *tmp,
                              int sweeps, hipStream_t s);
@@ -263,6 +309,7 @@ rich_status launch_negate_to(const double *x, double *y, int64_t n, hipStream_t 
 template <class TA, class TB>
 rich_status launch_cast(const TA *a, TB *b, int64_t n, hipStream_t s);
 rich_status launch_fill_i32(int32_t *x, int32_t v, int64_t n, hipStream_t s);
+rich_status launch_fill_u64(unsigned long long *x, unsigned long long v, int64_t n, hipStream_t s);
 rich_status launch_fill_f64(double *x, double v, int64_t n, hipStream_t s);
 
 // exclusive scan of int64 counts in place: out[0] = 0, out[i] = sum_{k<i} in[k];
@@ -349,7 +396,8 @@ rich_status galerkin_numeric(const CsrDev &A, const int32_t *agg, const int64_t 
 // products of the GMRES solves of the simulations attached to it and its
 // thread issues them as batched launches on its own stream (on the device
 // current at creation).
-rich_batcher *batcher_create();
+// persistent: its batched launches run as persistent grids on a work queue
+rich_batcher *batcher_create(bool persistent);
 void batcher_destroy(rich_batcher *B);
 rich_status batcher_attach(rich_handle_t h, rich_batcher *B);
 void batcher_stats(rich_batcher *B, int64_t *flushes, int64_t *items);
@@ -395,13 +443,13 @@ struct GemvItem {
     int64_t n;
 };
 template <class T>
-rich_status launch_csr_pre_batch(const std::vector<CsrItem<T>> &items, hipStream_t s);
+rich_status launch_csr_pre_batch(const std::vector<CsrItem<T>> &items, hipStream_t s, WorkQueue *q = nullptr);
 template <class T>
-rich_status launch_csr_post_batch(const std::vector<CsrItem<T>> &items, hipStream_t s);
+rich_status launch_csr_post_batch(const std::vector<CsrItem<T>> &items, hipStream_t s, WorkQueue *q = nullptr);
 template <class T>
-rich_status launch_restrict_batch(const std::vector<RestrictItem<T>> &items, hipStream_t s);
+rich_status launch_restrict_batch(const std::vector<RestrictItem<T>> &items, hipStream_t s, WorkQueue *q = nullptr);
 template <class T>
-rich_status launch_dense_gemv_batch(const std::vector<GemvItem<T>> &items, hipStream_t s);
+rich_status launch_dense_gemv_batch(const std::vector<GemvItem<T>> &items, hipStream_t s, WorkQueue *q = nullptr);
 // x = post-smooth(x0 + P xc); the level's r buffer holds the prolongated iterate
 template <class TB, class T>
 rich_status launch_csr_post(const Level &Lv, const T *val, const T *invd, const TB *b, const T *x0,

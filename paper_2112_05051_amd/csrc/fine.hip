@@ -847,24 +847,24 @@ struct StArgs {
 
 template <class TB, class T, int MODE>
 __global__ void __launch_bounds__(T25X * T25Y) k_st25_batch(Batch<StArgs<TB, T>> B) {
-    const unsigned L = xcd_block();
-    if (L >= B.begin[B.n]) return;
-    const int e = batch_entry(B, L);
-    const StArgs<TB, T> &a = B.a[e];
-    st25_body<TB, T, MODE>(a.g, a.M4, a.invd, a.b, a.bs, a.xc, a.agg, a.out, a.kz, L - B.begin[e]);
+    for_each_block(B, xcd_block(), [&](unsigned L) {
+        const int e = batch_entry(B, L);
+        const StArgs<TB, T> &a = B.a[e];
+        st25_body<TB, T, MODE>(a.g, a.M4, a.invd, a.b, a.bs, a.xc, a.agg, a.out, a.kz, L - B.begin[e]);
+    });
 }
 
 // MODE 0: pre-smoothing + residual, 1: prolongation into xt, 2: post-smoothing from xt
 template <class TB, class T, int MODE>
 __global__ void k_st1_batch(Batch<StArgs<TB, T>> B) {
-    const unsigned L = xcd_block();
-    if (L >= B.begin[B.n]) return;
-    const int e = batch_entry(B, L);
-    const StArgs<TB, T> &a = B.a[e];
-    const uint32_t c = (L - B.begin[e]) * blockDim.x + threadIdx.x;
-    if (MODE == 0) st_pre_at(a.g, a.n, a.M4, a.invd, a.b, a.bs, a.out, c);
-    if (MODE == 1) st_prolong_at(a.n, a.invd, a.b, a.bs, a.xc, a.agg, a.xt, c);
-    if (MODE == 2) st_post_at(a.g, a.n, a.M4, a.invd, a.b, a.bs, a.xt, a.out, c);
+    for_each_block(B, xcd_block(), [&](unsigned L) {
+        const int e = batch_entry(B, L);
+        const StArgs<TB, T> &a = B.a[e];
+        const uint32_t c = (L - B.begin[e]) * blockDim.x + threadIdx.x;
+        if (MODE == 0) st_pre_at(a.g, a.n, a.M4, a.invd, a.b, a.bs, a.out, c);
+        if (MODE == 1) st_prolong_at(a.n, a.invd, a.b, a.bs, a.xc, a.agg, a.xt, c);
+        if (MODE == 2) st_post_at(a.g, a.n, a.M4, a.invd, a.b, a.bs, a.xt, a.out, c);
+    });
 }
 
 template <class TX>
@@ -878,11 +878,11 @@ struct SpmvArgs {
 
 template <class TX>
 __global__ void k_spmv_J_batch(Batch<SpmvArgs<TX>> B) {
-    const unsigned L = xcd_block();
-    if (L >= B.begin[B.n]) return;
-    const int e = batch_entry(B, L);
-    const SpmvArgs<TX> &a = B.a[e];
-    spmv_J_at(a.g, a.n, a.J7, a.x, a.y, (L - B.begin[e]) * blockDim.x + threadIdx.x);
+    for_each_block(B, xcd_block(), [&](unsigned L) {
+        const int e = batch_entry(B, L);
+        const SpmvArgs<TX> &a = B.a[e];
+        spmv_J_at(a.g, a.n, a.J7, a.x, a.y, (L - B.begin[e]) * blockDim.x + threadIdx.x);
+    });
 }
 
 // The 64-wide tile needs rows of at least about that length to keep its lanes busy.
@@ -1238,32 +1238,33 @@ static void st_split(const std::vector<FineItem<TB, T>> &v, std::vector<StArgs<T
 }
 
 template <class TB, class T>
-rich_status launch_st_pre_batch(const std::vector<FineItem<TB, T>> &v, hipStream_t s) {
+rich_status launch_st_pre_batch(const std::vector<FineItem<TB, T>> &v, hipStream_t s, WorkQueue *q) {
     std::vector<StArgs<TB, T>> a25, a1;
     std::vector<unsigned> b25, b1;
     st_split(v, a25, b25, a1, b1);
     using B = Batch<StArgs<TB, T>>;
     RICH_TRY(launch_batches(a25, b25, [&](const B &bt, unsigned g) {
         k_st25_batch<TB, T, ST25_PRE><<<g, dim3(T25X, T25Y), 0, s>>>(bt);
-    }));
-    return launch_batches(a1, b1, [&](const B &bt, unsigned g) { k_st1_batch<TB, T, 0><<<g, TPB, 0, s>>>(bt); });
+    }, q));
+    return launch_batches(a1, b1, [&](const B &bt, unsigned g) { k_st1_batch<TB, T, 0><<<g, TPB, 0, s>>>(bt); }, q);
 }
 
 template <class TB, class T>
-rich_status launch_st_post_batch(const std::vector<FineItem<TB, T>> &v, hipStream_t s) {
+rich_status launch_st_post_batch(const std::vector<FineItem<TB, T>> &v, hipStream_t s, WorkQueue *q) {
     std::vector<StArgs<TB, T>> a25, a1;
     std::vector<unsigned> b25, b1;
     st_split(v, a25, b25, a1, b1);
     using B = Batch<StArgs<TB, T>>;
     RICH_TRY(launch_batches(a25, b25, [&](const B &bt, unsigned g) {
         k_st25_batch<TB, T, ST25_POST><<<g, dim3(T25X, T25Y), 0, s>>>(bt);
-    }));
-    RICH_TRY(launch_batches(a1, b1, [&](const B &bt, unsigned g) { k_st1_batch<TB, T, 1><<<g, TPB, 0, s>>>(bt); }));
-    return launch_batches(a1, b1, [&](const B &bt, unsigned g) { k_st1_batch<TB, T, 2><<<g, TPB, 0, s>>>(bt); });
+    }, q));
+    RICH_TRY(launch_batches(a1, b1, [&](const B &bt, unsigned g) { k_st1_batch<TB, T, 1><<<g, TPB, 0, s>>>(bt); },
+                            q));
+    return launch_batches(a1, b1, [&](const B &bt, unsigned g) { k_st1_batch<TB, T, 2><<<g, TPB, 0, s>>>(bt); }, q);
 }
 
 template <class TX>
-rich_status launch_spmv_J_batch(const std::vector<SpmvItem<TX>> &v, hipStream_t s) {
+rich_status launch_spmv_J_batch(const std::vector<SpmvItem<TX>> &v, hipStream_t s, WorkQueue *q) {
     std::vector<SpmvArgs<TX>> a;
     std::vector<unsigned> nb;
     for (const auto &it : v) {
@@ -1273,10 +1274,10 @@ rich_status launch_spmv_J_batch(const std::vector<SpmvItem<TX>> &v, hipStream_t 
     }
     return launch_batches(a, nb, [&](const Batch<SpmvArgs<TX>> &bt, unsigned g) {
         k_spmv_J_batch<TX><<<g, TPB, 0, s>>>(bt);
-    });
+    }, q);
 }
-template rich_status launch_spmv_J_batch<double>(const std::vector<SpmvItem<double>> &, hipStream_t);
-template rich_status launch_spmv_J_batch<float>(const std::vector<SpmvItem<float>> &, hipStream_t);
+template rich_status launch_spmv_J_batch<double>(const std::vector<SpmvItem<double>> &, hipStream_t, WorkQueue *);
+template rich_status launch_spmv_J_batch<float>(const std::vector<SpmvItem<float>> &, hipStream_t, WorkQueue *);
 
 #define INST_ST(TB, T)                                                                                    \
     template rich_status launch_st_pre<TB, T>(const Phys &, const T *, const T *, const TB *, const double *, T *, \
@@ -1287,12 +1288,13 @@ template rich_status launch_spmv_J_batch<float>(const std::vector<SpmvItem<float
                                                     const double *, const T *, T *, hipStream_t);               \
     template rich_status launch_st_sweeps<TB, T>(const Phys &, const T *, const T *, const TB *, T *, T *, int, \
                                                  hipStream_t);                                                  \
-    template rich_status launch_st_pre_batch<TB, T>(const std::vector<FineItem<TB, T>> &, hipStream_t);         \
+    template rich_status launch_st_pre_batch<TB, T>(const std::vector<FineItem<TB, T>> &, hipStream_t,          \
+                                                    WorkQueue *);                                               \
     template rich_status launch_gs_pre<TB, T>(const Phys &, const T *, const TB *, const double *, T *, T *,      \
                                               hipStream_t);                                                    \
     template rich_status launch_gs_post<TB, T>(const Phys &, const T *, const TB *, const double *, const T *,   \
                                                const T *, const int32_t *, T *, T *, hipStream_t);             \
-    template rich_status launch_st_post_batch<TB, T>(const std::vector<FineItem<TB, T>> &, hipStream_t);
+    template rich_status launch_st_post_batch<TB, T>(const std::vector<FineItem<TB, T>> &, hipStream_t, WorkQueue *);
 INST_ST(double, double)
 INST_ST(double, float)
 INST_ST(float, float)

@@ -325,6 +325,11 @@ __global__ void k_fill_i32(int32_t *x, int32_t v, int64_t n) {
     if (c < n) x[c] = v;
 }
 
+__global__ void k_fill_u64(unsigned long long *x, unsigned long long v, int64_t n) {
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < n) x[c] = v;
+}
+
 __global__ void k_fill_f64(double *x, double v, int64_t n) {
     int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c < n) x[c] = v;
@@ -544,6 +549,13 @@ template rich_status launch_cast<float, float>(const float *, float *, int64_t, 
 rich_status launch_fill_i32(int32_t *x, int32_t v, int64_t n, hipStream_t s) {
     if (n == 0) return RICH_OK;
     k_fill_i32<<<nblocks(n), TPB, 0, s>>>(x, v, n);
+    LAUNCH_CHECK();
+    return RICH_OK;
+}
+
+rich_status launch_fill_u64(unsigned long long *x, unsigned long long v, int64_t n, hipStream_t s) {
+    if (n == 0) return RICH_OK;
+    k_fill_u64<<<nblocks(n), TPB, 0, s>>>(x, v, n);
     LAUNCH_CHECK();
     return RICH_OK;
 }

@@ -63,7 +63,8 @@ struct rich_server {
     int64_t next_id = 1;
     int running = 0;
     bool stop = false;
-    bool fused = false;               // fused batching of the preconditioned products
+    int fused = 0;                    // fused batching of the preconditioned products: 0 off, 1 fused
+                                      // launches, 2 persistent fused launches on a work queue
     // one batcher per class of (grid, precision), created with its first admission
     std::map<std::array<int, 4>, rich_batcher *> batchers;
 };
@@ -134,7 +135,7 @@ void worker_main(rich_server *S) {
             S->running++;
             if (S->fused) {
                 rich_batcher *&b = S->batchers[batch_class(*R)];
-                if (!b) b = rich::batcher_create();
+                if (!b) b = rich::batcher_create(S->fused == 2);
                 batcher = b;
             }
             R->state = RICH_REQ_RUNNING;
@@ -236,11 +237,11 @@ rich_status rich_server_poll(rich_server_t S, int64_t req_id, int *state, rich_s
     return RICH_OK;
 }
 
-rich_status rich_server_set_batching(rich_server_t S, int fused) {
-    if (!S) return RICH_EINVAL;
+rich_status rich_server_set_batching(rich_server_t S, int mode) {
+    if (!S || mode < 0 || mode > 2) return RICH_EINVAL;
     std::lock_guard<std::mutex> lk(S->mu);
     if (S->next_id != 1) return RICH_ESTATE;
-    S->fused = fused != 0;
+    S->fused = mode;
     return RICH_OK;
 }
 

@@ -530,6 +530,8 @@ struct rich_batcher {
     uint64_t issued = 0;            // products with ticket < issued are issued
     rich_status last = RICH_OK;     // first error of an issue, sticky
     int64_t flushes = 0, items = 0;
+    bool persistent = false;        // launches as persistent grids taking work from `queue`
+    WorkQueue queue;                // device work counter of those launches (on stream s)
 };
 
 namespace {
@@ -557,7 +559,7 @@ bool batchable(const rich_ctx *h) {
 }
 
 template <class T>
-rich_status apply_batch(const std::vector<BatchReq> &rq, hipStream_t s) {
+rich_status apply_batch(const std::vector<BatchReq> &rq, hipStream_t s, WorkQueue *q) {
     if (rq.empty()) return RICH_OK;
     auto x0_of = [](const Hierarchy &H, int l) { return l < H.nlev - 1 ? (T *)H.L[l].x : nullptr; };
     int maxlev = 0;
@@ -572,8 +574,8 @@ rich_status apply_batch(const std::vector<BatchReq> &rq, hipStream_t s) {
         f.push_back({&q.h->P, m4_of<T>(q.h), invd0_of<T>(q.h), q.b, q.bs, nullptr, nullptr, nullptr, (T *)H.L[0].r});
         ri.push_back({&H.L[0], (const T *)H.L[0].r, (T *)H.L[1].b, H.L[1].n, lvinvd<T>(H.L[1]), x0_of(H, 1)});
     }
-    RICH_TRY(launch_st_pre_batch<double, T>(f, s));
-    RICH_TRY(launch_restrict_batch<T>(ri, s));
+    RICH_TRY(launch_st_pre_batch<double, T>(f, s, q));
+    RICH_TRY(launch_restrict_batch<T>(ri, s, q));
     for (int l = 1; l < maxlev - 1; l++) {
         ci.clear();
         ri.clear();
@@ -585,8 +587,8 @@ rich_status apply_batch(const std::vector<BatchReq> &rq, hipStream_t s) {
             ri.push_back({&Lv, (const T *)Lv.r, (T *)H.L[l + 1].b, H.L[l + 1].n, lvinvd<T>(H.L[l + 1]),
                           x0_of(H, l + 1)});
         }
-        RICH_TRY(launch_csr_pre_batch<T>(ci, s));
-        RICH_TRY(launch_restrict_batch<T>(ri, s));
+        RICH_TRY(launch_csr_pre_batch<T>(ci, s, q));
+        RICH_TRY(launch_restrict_batch<T>(ri, s, q));
     }
     // coarsest
     for (const auto &q : rq) {
@@ -595,7 +597,7 @@ rich_status apply_batch(const std::vector<BatchReq> &rq, hipStream_t s) {
         const T *cinv = q.h->mixed ? (const T *)(const void *)H.cinvf : (const T *)(const void *)H.cinv;
         gi.push_back({cinv, (const T *)Lc.b, (T *)Lc.x, Lc.n});
     }
-    RICH_TRY(launch_dense_gemv_batch<T>(gi, s));
+    RICH_TRY(launch_dense_gemv_batch<T>(gi, s, q));
     // up: prolongation + post-smoothing
     for (int l = maxlev - 2; l >= 1; l--) {
         ci.clear();
@@ -606,7 +608,7 @@ rich_status apply_batch(const std::vector<BatchReq> &rq, hipStream_t s) {
             ci.push_back({&Lv, lvval<T>(Lv), lvinvd<T>(Lv), (const T *)Lv.b, (const T *)Lv.x,
                           (const T *)H.L[l + 1].x, (T *)Lv.x});
         }
-        RICH_TRY(launch_csr_post_batch<T>(ci, s));
+        RICH_TRY(launch_csr_post_batch<T>(ci, s, q));
     }
     f.clear();
     std::vector<SpmvItem<T>> sp;
@@ -616,8 +618,8 @@ rich_status apply_batch(const std::vector<BatchReq> &rq, hipStream_t s) {
                      (T *)H.L[0].r, (T *)q.h->z});
         if (q.w) sp.push_back({&q.h->P, q.h->J7, (const T *)q.h->z, q.w});
     }
-    RICH_TRY(launch_st_post_batch<double, T>(f, s));
-    return launch_spmv_J_batch<T>(sp, s);
+    RICH_TRY(launch_st_post_batch<double, T>(f, s, q));
+    return launch_spmv_J_batch<T>(sp, s, q);
 }
 
 // Issue one batch on the batcher's stream (batcher thread, lock not held).
@@ -627,8 +629,9 @@ rich_status issue_batch(rich_batcher *B, const std::vector<BatchReq> &rq) {
         HIP_TRY(hipStreamWaitEvent(B->s, q.h->bev, 0));
         (q.h->mixed ? mixed : fp64).push_back(q);
     }
-    RICH_TRY(apply_batch<float>(mixed, B->s));
-    RICH_TRY(apply_batch<double>(fp64, B->s));
+    WorkQueue *q = B->persistent ? &B->queue : nullptr;
+    RICH_TRY(apply_batch<float>(mixed, B->s, q));
+    RICH_TRY(apply_batch<double>(fp64, B->s, q));
     HIP_TRY(hipEventRecord(B->done, B->s));
     for (const auto &q : rq) HIP_TRY(hipStreamWaitEvent(q.h->s, B->done, 0));
     return RICH_OK;
@@ -1695,7 +1698,7 @@ rich_status rich_match_sweep(int64_t n, const int64_t *rowptr_dev, const int32_t
 // ------------------------------------------------- batcher (server side)
 namespace rich {
 
-rich_batcher *batcher_create() {
+rich_batcher *batcher_create(bool persistent) {
     rich_batcher *B = new rich_batcher();
     int device = 0;
     if (hipGetDevice(&device) != hipSuccess || hipStreamCreateWithFlags(&B->s, hipStreamNonBlocking) != hipSuccess ||
@@ -1703,6 +1706,17 @@ rich_batcher *batcher_create() {
         (void)hipGetLastError();
         batcher_destroy(B);
         return nullptr;
+    }
+    if (persistent) {
+        // the work counter starts at zero (a fill kernel, not a memset) and is
+        // only ever advanced by the launches on B->s
+        if (hipMalloc((void **)&B->queue.ctr, sizeof(unsigned long long)) != hipSuccess ||
+            launch_fill_u64(B->queue.ctr, 0ull, 1, B->s) != RICH_OK || hipStreamSynchronize(B->s) != hipSuccess) {
+            (void)hipGetLastError();
+            batcher_destroy(B);
+            return nullptr;
+        }
+        B->persistent = true;
     }
     B->thread = std::thread(batcher_main, B, device);
     return B;
@@ -1724,6 +1738,7 @@ void batcher_destroy(rich_batcher *B) {
         (void)hipStreamDestroy(B->s);
     }
     if (B->done) (void)hipEventDestroy(B->done);
+    if (B->queue.ctr) (void)hipFree(B->queue.ctr);
     delete B;
 }
 

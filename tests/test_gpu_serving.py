@@ -1,6 +1,7 @@
 """Ensemble server: every request's result in the mix equals its result alone,
 with the preconditioned products of the resident simulations fused into
-batched launches and without."""
+batched launches (plain or persistent) and without; served results against
+the oracle."""
 import numpy as np
 import pytest
 
@@ -35,13 +36,13 @@ def check_alone_equals_mix(rich, torch, srv, reqs, ids):
         assert [s["gmres_its"] for s in r["stats"]] == [s["gmres_its"] for s in st_alone[:len(r["stats"])]]
 
 
-@pytest.mark.parametrize("fused", [True, False])
-def test_alone_equals_mix(fused):
+@pytest.mark.parametrize("fused,persistent", [(True, False), (True, True), (False, False)])
+def test_alone_equals_mix(fused, persistent):
     import torch
 
     import paper_2112_05051_amd as rich
     reqs = small_requests()
-    srv = rich.Server(8 << 30, 3, fused=fused)
+    srv = rich.Server(8 << 30, 3, fused=fused, persistent=persistent)
     ids = [srv.submit(rec.problem, rec.options, rec.ks(), rec.p0(), rec.nsteps) for rec in reqs]
     srv.run_until_idle()
     check_alone_equals_mix(rich, torch, srv, reqs, ids)
@@ -53,10 +54,12 @@ def test_alone_equals_mix(fused):
     srv.close()
 
 
-def test_fused_kernels_all_paths():
+@pytest.mark.parametrize("persistent", [False, True])
+def test_fused_kernels_all_paths(persistent):
     """48^3 grids run the tiled fine smoother and have a CSR-stream coarse
     level, 16^3 grids the plain fine kernels; simulations of one size share
-    batched launches, and every result equals the lone run bit for bit."""
+    batched launches (plain, or persistent grids taking their blocks from a
+    device work queue), and every result equals the lone run bit for bit."""
     import torch
 
     import paper_2112_05051_amd as rich
@@ -66,7 +69,7 @@ def test_fused_kernels_all_paths():
         rec.problem.mean = synth.UPSTREAM  # converges on these fields
         rec.options.max_newton = 40
         reqs.append(rec)
-    srv = rich.Server(16 << 30, 4, fused=True)
+    srv = rich.Server(16 << 30, 4, fused=True, persistent=persistent)
     ids = [srv.submit(rec.problem, rec.options, rec.ks(), rec.p0(), rec.nsteps) for rec in reqs]
     srv.run_until_idle()
     flushes, products = srv.batch_stats()
@@ -78,7 +81,8 @@ def test_fused_kernels_all_paths():
     srv.close()
 
 
-def test_fused_fp64():
+@pytest.mark.parametrize("persistent", [False, True])
+def test_fused_fp64(persistent):
     """The all-FP64 batched V-cycle: two same-size FP64 simulations share
     batches and each equals its lone run bit for bit."""
     import torch
@@ -91,7 +95,7 @@ def test_fused_fp64():
         rec.options.precision = synth.FP64
         rec.options.max_newton = 40
         reqs.append(rec)
-    srv = rich.Server(8 << 30, 2, fused=True)
+    srv = rich.Server(8 << 30, 2, fused=True, persistent=persistent)
     ids = [srv.submit(rec.problem, rec.options, rec.ks(), rec.p0(), rec.nsteps) for rec in reqs]
     srv.run_until_idle()
     flushes, products = srv.batch_stats()
