@@ -603,12 +603,17 @@ def main():
         log("[bench] C4 serving stream ...")
         del ks_dev, p0_dev
         torch.cuda.empty_cache()
-        sv = run_serving(args)
+        try:
+            sv = run_serving(args)
+        except Exception as e:  # the headline above stands on its own
+            sv = None
+            out["serving_c4"] = {"error": repr(e)}
         keep = ("value", "unit", "requests", "steps_per_request", "arrival_rate_per_s", "max_active", "makespan_s",
                 "total_steps", "p50_step_ms", "p99_step_ms", "converged_requests", "converged_steps_per_s",
                 "p50_step_ms_converged", "p99_step_ms_converged", "admission_wait_p50_s", "admission_wait_p99_s",
                 "status_by_mean")
-        out["serving_c4"] = {k: sv[k] for k in keep}
+        if sv is not None:
+            out["serving_c4"] = {k: sv[k] for k in keep}
     print(json.dumps(out), flush=True)
 
 
