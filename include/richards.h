@@ -146,6 +146,24 @@ typedef struct rich_solver_opts {
                             larger values stall the coarsening where the storage term theta'/dt
                             dominates the diagonal) */
     int64_t amg_block;   /* rows per decoupled block of RICH_AGG_VMB, >= 1 (4096) */
+    int gmres_block;     /* Arnoldi vectors generated per Gram-Schmidt round of GMRES, 1..6.
+                            1: one vector per round (classical Gram-Schmidt, the second pass
+                            governed by gmres_reorth).  s >= 2: s-step GMRES (Section 6's
+                            right-preconditioned GMRES(m), the same Krylov space and minimal
+                            residual): s vectors of the shifted power basis
+                            q_{t+1} = (J M^{-1} - gmres_shift I) q_t are generated, then
+                            orthogonalised against the basis and each other in one
+                            block round (dots and Gram matrix in one pass, a Cholesky factor
+                            of the Gram matrix's Pythagorean complement, one update pass), so
+                            the basis is read twice per s vectors instead of twice per vector.
+                            A round whose Cholesky factor loses more than gmres_reorth of a
+                            vector's norm is redone vector by vector with two classical
+                            passes.  The Hessenberg matrix follows from the basis change;
+                            convergence is tested after every column (the iteration count is
+                            that of one-vector rounds), the next round's size is cut to the
+                            steps the residual's decay predicts. */
+    double gmres_shift;  /* shift of the s-step power basis (> 0 keeps it well conditioned:
+                            the preconditioned spectrum lies near (0, 1]); 0.7 */
 } rich_solver_opts_t;
 #define RICH_SMOOTH_L1 0
 #define RICH_SMOOTH_MCGS 1
@@ -326,7 +344,9 @@ rich_status rich_match_sweep_noalloc(int64_t n, const int64_t *rowptr_dev, const
 #define RICH_K_MULTIDOT 6     /* Gram-Schmidt dot block V^T w (first pass) */
 #define RICH_K_UPDATE 7       /* w -= V h with ||w||^2 (first pass) */
 #define RICH_K_RESIDUAL 8     /* Phi(p) */
-#define RICH_K_COUNT 9
+#define RICH_K_BLOCK_DOT 9    /* s-step GMRES: block dots V^T Q and Gram matrix Q^T Q */
+#define RICH_K_BLOCK_UPDATE 10 /* s-step GMRES: Q <- (Q - V C) R^{-1} */
+#define RICH_K_COUNT 11
 /* enable != 0: clear the counters and start timing; 0: stop. */
 rich_status rich_profile(rich_handle_t h, int enable);
 /* Launch count, summed kernel milliseconds and summed algorithmic bytes of

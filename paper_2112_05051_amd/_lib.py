@@ -49,7 +49,8 @@ class Opts(C.Structure):
                 ("coarse_l1_sweeps", C.c_int), ("precision", C.c_int), ("gmres_reorth", C.c_double),
                 ("aux_dflux", C.c_int), ("amg_refresh", C.c_int), ("amg_smoothed", C.c_int),
                 ("tile_kz", C.c_int), ("smoother", C.c_int), ("amg_aggregation", C.c_int),
-                ("amg_theta", C.c_double), ("amg_block", C.c_int64)]
+                ("amg_theta", C.c_double), ("amg_block", C.c_int64),
+                ("gmres_block", C.c_int), ("gmres_shift", C.c_double)]
 
 
 class StepStats(C.Structure):
@@ -97,7 +98,7 @@ EXPORTS = ["rich_query_bytes", "rich_create", "rich_destroy", "rich_set_state", 
            "rich_server_destroy", "rich_server_set_batching", "rich_server_batch_stats"]
 
 KERNELS = ["spmv_J", "vc0_pre", "vc0_post", "vc0_restrict", "vc1_pre", "vc1_post", "multidot", "update",
-           "residual"]
+           "residual", "block_dot", "block_update"]
 
 _lib = None
 

@@ -211,7 +211,8 @@ rich_status launch_residual(const Phys &P, const double *Ks, const double *p, co
 rich_status launch_assemble(const Phys &P, const double *Ks, const double *p, double *J7, double *M4,
                             float *M4f, double *invd, float *invdf, int dflux, hipStream_t s);
 template <class TX>
-rich_status launch_spmv_J(const Phys &P, const double *J7, const TX *x, double *y, hipStream_t s);
+rich_status launch_spmv_J(const Phys &P, const double *J7, const TX *x, double *y, hipStream_t s,
+                          const double *sb = nullptr, const double *sbs = nullptr, double sig = 0.0);
 rich_status launch_spmv_M(const Phys &P, const double *M4, const double *x, double *y, hipStream_t s);
 rich_status launch_stencil_to_csr(const Phys &P, const double *M4, const int64_t *rowptr,
                                   int32_t *col, double *val, hipStream_t s);
@@ -261,6 +262,8 @@ struct SpmvItem {
     const double *J7;
     const TX *x;
     double *y;
+    const double *sb = nullptr, *sbs = nullptr;  // optional shift: y = J x - sig (sbs[0] sb)
+    double sig = 0.0;
 };
 template <class TX>
 rich_status launch_spmv_J_batch(const std::vector<SpmvItem<TX>> &items, hipStream_t s, WorkQueue *q = nullptr);
@@ -271,6 +274,8 @@ rich_status launch_st_sweeps(const Phys &P, const T *M4, const T *invd, const TB
 // ------------------------------------------------------------ vector kernels
 constexpr int RED_BLOCKS = 1024;   // fixed block count of every reduction (deterministic order)
 constexpr int RED_THREADS = 256;
+constexpr int GMRES_BLOCK_MAX = 6; // largest round of the s-step GMRES (register budget of its dot kernel)
+constexpr int BLK_BUF = 512;       // doubles per s-step result or coefficient buffer (>= 65 * 6 + 36)
 
 // Basis vectors are stored unnormalised: the true V_i is vs[i] * stored V_i.
 // out[i] = V_i . w (i < k), out[k] = w . w; reduced in fixed order.
@@ -279,6 +284,18 @@ rich_status launch_multidot(const double *V, int64_t ldv, int k, const double *v
 // w -= sum_i h_i V_i (i < k, h and vs on device); out[0] = ||w||^2 (after update)
 rich_status launch_update_norm(const double *V, int64_t ldv, int k, const double *h, const double *vs, double *w,
                                int64_t n, double *partial, double *out, hipStream_t s);
+// Block Gram-Schmidt of the s-step GMRES (S <= 6 raw block vectors Q_k at
+// stride ldv, nv <= 66 basis vectors with device scales vs).
+// launch_block_dot: out[i*S + k] = (vs_i V_i) . Q_k (i < nv, k < S), then the
+// upper triangle of Q^T Q by rows (S(S+1)/2 values); partial needs
+// RED_BLOCKS * block_partial_size(nv, S) doubles.  Deterministic.
+rich_status launch_block_dot(const double *V, int64_t ldv, int nv, const double *vs, const double *Q, int S,
+                             int64_t n, double *partial, double *out, hipStream_t s);
+int block_partial_size(int nv, int S);
+// Q_t <- sum_{k<=t} (Q_k - sum_i C_ik vs_i V_i) Rinv_kt in place; cf (device):
+// C row-major (nv x S), then Rinv row-major (S x S, upper triangular).
+rich_status launch_block_update(const double *V, int64_t ldv, int nv, const double *vs, const double *cf, double *Q,
+                                int S, int64_t n, hipStream_t s);
 // vs[0] = 1 / sqrt(ww[0]) on the device
 rich_status launch_set_scale(double *vs, const double *ww, hipStream_t s);
 // out[0] = x.y (deterministic)

@@ -535,10 +535,14 @@ __global__ void __launch_bounds__(FT_TPB) k_faces_tiled(Phys P, int kz, const do
     }
 }
 
-// y = J x, J in the 7-array stencil form; x may be FP32 (mixed path).
+// y = J x, J in the 7-array stencil form; x may be FP32 (mixed path).  With
+// a shift vector (sb non-null) y = J x - sig (sbs[0] sb): the shifted power
+// basis of the s-step GMRES, the subtraction after the stencil sum.
 template <class TX, class G>
 __device__ __forceinline__ void spmv_J_at(const G &P, uint32_t n, const double *__restrict__ J7,
-                                          const TX *__restrict__ x, double *__restrict__ y, uint32_t c) {
+                                          const TX *__restrict__ x, double *__restrict__ y, uint32_t c,
+                                          const double *__restrict__ sb = nullptr,
+                                          const double *__restrict__ sbs = nullptr, double sig = 0.0) {
     if (c >= n) return;
     Cell q = cell_of(P, c);
     uint32_t nx = P.nx, nxy = (uint32_t)P.nx * (uint32_t)P.ny;
@@ -563,13 +567,15 @@ __device__ __forceinline__ void spmv_J_at(const G &P, uint32_t n, const double *
     if (q.j < P.ny - 1) s += a4 * x4;
     if (q.k > 0) s += a5 * x5;
     if (q.k < P.nz - 1) s += a6 * x6;
+    if (sb) s -= sig * (sbs[0] * sb[c]);
     y[c] = s;
 }
 
 template <class TX>
 __global__ void k_spmv_J(Phys P, uint32_t n, const double *__restrict__ J7, const TX *__restrict__ x,
-                         double *__restrict__ y) {
-    spmv_J_at(P, n, J7, x, y, blockIdx.x * blockDim.x + threadIdx.x);
+                         double *__restrict__ y, const double *__restrict__ sb, const double *__restrict__ sbs,
+                         double sig) {
+    spmv_J_at(P, n, J7, x, y, blockIdx.x * blockDim.x + threadIdx.x, sb, sbs, sig);
 }
 
 // Symmetric stencil M: sum_j m_cj * v_j with the -d couplings read at the lower neighbour.
@@ -874,6 +880,8 @@ struct SpmvArgs {
     const double *J7;
     const TX *x;
     double *y;
+    const double *sb, *sbs;  // optional shift: y = J x - sig (sbs[0] sb)
+    double sig;
 };
 
 template <class TX>
@@ -881,7 +889,7 @@ __global__ void k_spmv_J_batch(Batch<SpmvArgs<TX>> B) {
     for_each_block(B, xcd_block(), [&](unsigned L) {
         const int e = batch_entry(B, L);
         const SpmvArgs<TX> &a = B.a[e];
-        spmv_J_at(a.g, a.n, a.J7, a.x, a.y, (L - B.begin[e]) * blockDim.x + threadIdx.x);
+        spmv_J_at(a.g, a.n, a.J7, a.x, a.y, (L - B.begin[e]) * blockDim.x + threadIdx.x, a.sb, a.sbs, a.sig);
     });
 }
 
@@ -1099,14 +1107,17 @@ rich_status launch_assemble(const Phys &P, const double *Ks, const double *p, do
 }
 
 template <class TX>
-rich_status launch_spmv_J(const Phys &P, const double *J7, const TX *x, double *y, hipStream_t s) {
+rich_status launch_spmv_J(const Phys &P, const double *J7, const TX *x, double *y, hipStream_t s, const double *sb,
+                          const double *sbs, double sig) {
     uint32_t n = ncells(P);
-    k_spmv_J<TX><<<(n + TPB - 1) / TPB, TPB, 0, s>>>(P, n, J7, x, y);
+    k_spmv_J<TX><<<(n + TPB - 1) / TPB, TPB, 0, s>>>(P, n, J7, x, y, sb, sbs, sig);
     LAUNCH_CHECK();
     return RICH_OK;
 }
-template rich_status launch_spmv_J<double>(const Phys &, const double *, const double *, double *, hipStream_t);
-template rich_status launch_spmv_J<float>(const Phys &, const double *, const float *, double *, hipStream_t);
+template rich_status launch_spmv_J<double>(const Phys &, const double *, const double *, double *, hipStream_t,
+                                           const double *, const double *, double);
+template rich_status launch_spmv_J<float>(const Phys &, const double *, const float *, double *, hipStream_t,
+                                          const double *, const double *, double);
 
 rich_status launch_spmv_M(const Phys &P, const double *M4, const double *x, double *y, hipStream_t s) {
     uint32_t n = ncells(P);
@@ -1269,7 +1280,7 @@ rich_status launch_spmv_J_batch(const std::vector<SpmvItem<TX>> &v, hipStream_t 
     std::vector<unsigned> nb;
     for (const auto &it : v) {
         const Phys &P = *it.P;
-        a.push_back(SpmvArgs<TX>{Grid3{P.nx, P.ny, P.nz}, ncells(P), it.J7, it.x, it.y});
+        a.push_back(SpmvArgs<TX>{Grid3{P.nx, P.ny, P.nz}, ncells(P), it.J7, it.x, it.y, it.sb, it.sbs, it.sig});
         nb.push_back((ncells(P) + TPB - 1) / TPB);
     }
     return launch_batches(a, nb, [&](const Batch<SpmvArgs<TX>> &bt, unsigned g) {

@@ -205,6 +205,220 @@ __global__ void __launch_bounds__(RED_THREADS) k_update_norm_small(const double 
     update_norm_body<K>(V, ldv, h, vs, w, n, partial);
 }
 
+// ---- block Gram-Schmidt of the s-step GMRES ----
+// Partial sums of C = V^T Q, the dots of the S raw block vectors Q_0..Q_{S-1}
+// with nv basis vectors (stored unnormalised: their scales are applied in the
+// reduction), and of the Gram matrix Q^T Q.  The four waves of a block walk
+// the same row pairs: wave g takes basis vectors [g GV, min(nv, (g+1) GV)),
+// the last wave also the Gram matrix, so the Q values of a row pair are
+// fetched from memory once and read by the other waves from the caches; the
+// basis is streamed past the caches.  Per block: C row-major (i S + k), then
+// (when gram) the upper triangle of the Gram matrix by rows.
+template <int S, int GV>
+__device__ __forceinline__ void block_dot_body(const double *__restrict__ V, int64_t ldv, int nv, bool gram,
+                                               const double *__restrict__ Q, int64_t n,
+                                               double *__restrict__ partial, int mout) {
+    constexpr int NG = S * (S + 1) / 2;
+    typedef double d2v __attribute__((ext_vector_type(2)));
+    const int lane = threadIdx.x % WAVE, g = threadIdx.x / WAVE;
+    const int i0 = g * GV;
+    const int ng = nv - i0 < GV ? (nv - i0 > 0 ? nv - i0 : 0) : GV;  // uniform in the wave
+    const bool dog = gram && g == RED_THREADS / WAVE - 1;
+    double acc[GV][S], gm[NG];
+#pragma unroll
+    for (int i = 0; i < GV; i++)
+#pragma unroll
+        for (int k = 0; k < S; k++) acc[i][k] = 0.0;
+#pragma unroll
+    for (int t = 0; t < NG; t++) gm[t] = 0.0;
+    const int64_t n2 = n >> 1;
+    for (int64_t c = (int64_t)blockIdx.x * WAVE + lane; c < n2; c += (int64_t)gridDim.x * WAVE) {
+        d2v q[S], v[GV];
+#pragma unroll
+        for (int k = 0; k < S; k++) q[k] = reinterpret_cast<const d2v *>(Q + (size_t)k * ldv)[c];
+#pragma unroll
+        for (int i = 0; i < GV; i++)
+            if (i < ng) v[i] = __builtin_nontemporal_load(reinterpret_cast<const d2v *>(V + (size_t)(i0 + i) * ldv) + c);
+#pragma unroll
+        for (int i = 0; i < GV; i++)
+            if (i < ng)
+#pragma unroll
+                for (int k = 0; k < S; k++) acc[i][k] += v[i].x * q[k].x + v[i].y * q[k].y;
+        if (dog) {
+            int t = 0;
+#pragma unroll
+            for (int k = 0; k < S; k++)
+#pragma unroll
+                for (int l = k; l < S; l++, t++) gm[t] += q[k].x * q[l].x + q[k].y * q[l].y;
+        }
+    }
+    if ((n & 1) && blockIdx.x == 0 && lane == 0) {
+        double q[S];
+#pragma unroll
+        for (int k = 0; k < S; k++) q[k] = Q[(size_t)k * ldv + n - 1];
+#pragma unroll
+        for (int i = 0; i < GV; i++)
+            if (i < ng) {
+                const double vi = V[(size_t)(i0 + i) * ldv + n - 1];
+#pragma unroll
+                for (int k = 0; k < S; k++) acc[i][k] += vi * q[k];
+            }
+        if (dog) {
+            int t = 0;
+#pragma unroll
+            for (int k = 0; k < S; k++)
+#pragma unroll
+                for (int l = k; l < S; l++, t++) gm[t] += q[k] * q[l];
+        }
+    }
+    double *out = partial + (size_t)blockIdx.x * mout;
+#pragma unroll
+    for (int i = 0; i < GV; i++)
+        if (i < ng)
+#pragma unroll
+            for (int k = 0; k < S; k++) {
+                const double r = wave_sum(acc[i][k]);
+                if (lane == 0) out[(i0 + i) * S + k] = r;
+            }
+    if (dog)
+#pragma unroll
+        for (int t = 0; t < NG; t++) {
+            const double r = wave_sum(gm[t]);
+            if (lane == 0) out[nv * S + t] = r;
+        }
+}
+
+template <int S, int GV>
+__global__ void __launch_bounds__(RED_THREADS) RED_WPE_ATTR k_block_dot(const double *__restrict__ V, int64_t ldv,
+                                                                      int nv, bool gram,
+                                                                      const double *__restrict__ Q, int64_t n,
+                                                                      double *__restrict__ partial, int mout) {
+    block_dot_body<S, GV>(V, ldv, nv, gram, Q, n, partial, mout);
+}
+
+template <int S, int GV>
+__global__ void __launch_bounds__(RED_THREADS) k_block_dot_small(const double *__restrict__ V, int64_t ldv, int nv,
+                                                                 bool gram, const double *__restrict__ Q, int64_t n,
+                                                                 double *__restrict__ partial, int mout) {
+    block_dot_body<S, GV>(V, ldv, nv, gram, Q, n, partial, mout);
+}
+
+// out_c[j] = vs[j / S] * sum_b partial[b*m + j] for j < nvs (the C entries),
+// out_g[j - nvs] = sum_b partial[b*m + j] after (the Gram matrix); b ascending.
+__global__ void k_reduce_block(const double *__restrict__ partial, int m, int nb, int S, int nvs,
+                               const double *__restrict__ vs, double *__restrict__ out_c,
+                               double *__restrict__ out_g) {
+    __shared__ double sh[RED_THREADS / WAVE];
+    const int j = blockIdx.x;
+    double a = 0.0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) a += partial[(size_t)b * m + j];
+    const double r = block_sum(a, sh);
+    if (threadIdx.x == 0) {
+        if (j < nvs)
+            out_c[j] = r * vs[j / S];
+        else
+            out_g[j - nvs] = r;
+    }
+}
+
+// The block vectors orthonormalised in place:
+//   Q_t <- sum_{k <= t} (Q_k - sum_i C_ik (vs_i V_i)) Rinv_kt,  t < S,
+// cf: C row-major (nv x S), then Rinv row-major (S x S, upper triangular).
+// The coefficients (with the basis scales folded in) sit in LDS; the basis
+// is streamed past the caches, the new vectors are stored cacheable (the
+// last one is the next preconditioner input, the others are read by the
+// next block's dots).
+constexpr int BLK_VCHUNK = 32;  // basis vectors per dot launch (4 waves x 8)
+template <int S>
+__device__ __forceinline__ void block_update_body(const double *__restrict__ V, int64_t ldv, int nv,
+                                                  const double *__restrict__ vs, const double *__restrict__ cf,
+                                                  double *__restrict__ Q, int64_t n) {
+    __shared__ double cs[(KMAX + GMRES_BLOCK_MAX) * GMRES_BLOCK_MAX];
+    for (int t = threadIdx.x; t < nv * S; t += blockDim.x) cs[t] = cf[t] * vs[t / S];
+    for (int t = threadIdx.x; t < S * S; t += blockDim.x) cs[nv * S + t] = cf[nv * S + t];
+    __syncthreads();
+    const double *__restrict__ ri = cs + nv * S;
+    typedef double d2v __attribute__((ext_vector_type(2)));
+    const int64_t n2 = n >> 1;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n2; c += (int64_t)gridDim.x * blockDim.x) {
+        d2v q[S];
+#pragma unroll
+        for (int k = 0; k < S; k++) q[k] = reinterpret_cast<const d2v *>(Q + (size_t)k * ldv)[c];
+        int i = 0;
+        for (; i + 8 <= nv; i += 8) {
+            d2v v[8];
+#pragma unroll
+            for (int u = 0; u < 8; u++)
+                v[u] = __builtin_nontemporal_load(reinterpret_cast<const d2v *>(V + (size_t)(i + u) * ldv) + c);
+#pragma unroll
+            for (int u = 0; u < 8; u++)
+#pragma unroll
+                for (int k = 0; k < S; k++) {
+                    const double a = cs[(i + u) * S + k];
+                    q[k].x -= a * v[u].x;
+                    q[k].y -= a * v[u].y;
+                }
+        }
+        for (; i < nv; i++) {
+            const d2v v = __builtin_nontemporal_load(reinterpret_cast<const d2v *>(V + (size_t)i * ldv) + c);
+#pragma unroll
+            for (int k = 0; k < S; k++) {
+                const double a = cs[i * S + k];
+                q[k].x -= a * v.x;
+                q[k].y -= a * v.y;
+            }
+        }
+        // times Rinv, in place from the last column down (column t uses k <= t)
+#pragma unroll
+        for (int t = S - 1; t >= 0; t--) {
+            d2v o = q[0] * ri[t];
+#pragma unroll
+            for (int k = 1; k <= t; k++) {
+                o.x += q[k].x * ri[k * S + t];
+                o.y += q[k].y * ri[k * S + t];
+            }
+            q[t] = o;
+        }
+#pragma unroll
+        for (int k = 0; k < S; k++) reinterpret_cast<d2v *>(Q + (size_t)k * ldv)[c] = q[k];
+    }
+    if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+        double q[S];
+#pragma unroll
+        for (int k = 0; k < S; k++) q[k] = Q[(size_t)k * ldv + n - 1];
+        for (int i = 0; i < nv; i++) {
+            const double v = V[(size_t)i * ldv + n - 1];
+#pragma unroll
+            for (int k = 0; k < S; k++) q[k] -= cs[i * S + k] * v;
+        }
+#pragma unroll
+        for (int t = S - 1; t >= 0; t--) {
+            double o = q[0] * ri[t];
+#pragma unroll
+            for (int k = 1; k <= t; k++) o += q[k] * ri[k * S + t];
+            q[t] = o;
+        }
+#pragma unroll
+        for (int k = 0; k < S; k++) Q[(size_t)k * ldv + n - 1] = q[k];
+    }
+}
+
+template <int S>
+__global__ void __launch_bounds__(RED_THREADS) RED_WPE_ATTR k_block_update(const double *__restrict__ V, int64_t ldv,
+                                                                         int nv, const double *__restrict__ vs,
+                                                                         const double *__restrict__ cf,
+                                                                         double *__restrict__ Q, int64_t n) {
+    block_update_body<S>(V, ldv, nv, vs, cf, Q, n);
+}
+
+template <int S>
+__global__ void __launch_bounds__(RED_THREADS) k_block_update_small(const double *__restrict__ V, int64_t ldv,
+                                                                    int nv, const double *__restrict__ vs,
+                                                                    const double *__restrict__ cf,
+                                                                    double *__restrict__ Q, int64_t n) {
+    block_update_body<S>(V, ldv, nv, vs, cf, Q, n);
+}
+
 __global__ void k_dot(const double *__restrict__ x, const double *__restrict__ y, int64_t n,
                       double *__restrict__ partial) {
     __shared__ double sh[RED_THREADS / WAVE];
@@ -449,6 +663,62 @@ rich_status launch_update_norm(const double *V, int64_t ldv, int k, const double
     LAUNCH_CHECK();
     return RICH_OK;
 }
+
+rich_status launch_block_dot(const double *V, int64_t ldv, int nv, const double *vs, const double *Q, int S,
+                             int64_t n, double *partial, double *out, hipStream_t s) {
+    if (nv < 1 || nv > KMAX || S < 1 || S > GMRES_BLOCK_MAX || (ldv & 1)) return RICH_EINVAL;
+    const bool wide = n >= RED_WIDE_MIN;
+    double *pc = partial;
+    for (int i0 = 0; i0 < nv; i0 += BLK_VCHUNK) {
+        const int nc = nv - i0 < BLK_VCHUNK ? nv - i0 : BLK_VCHUNK;
+        const bool gram = i0 == 0;
+        const int gv = (nc + 3) / 4;
+        const int mout = nc * S + (gram ? S * (S + 1) / 2 : 0);
+        const double *Vc = V + (size_t)i0 * ldv;
+        switch (S * 16 + gv) {
+#define XG(SS, G)                                                                                         \
+    case SS * 16 + G:                                                                                     \
+        if (wide)                                                                                         \
+            k_block_dot<SS, G><<<RED_BLOCKS, RED_THREADS, 0, s>>>(Vc, ldv, nc, gram, Q, n, pc, mout);       \
+        else                                                                                              \
+            k_block_dot_small<SS, G><<<RED_BLOCKS, RED_THREADS, 0, s>>>(Vc, ldv, nc, gram, Q, n, pc, mout); \
+        break;
+#define XS(SS) XG(SS, 1) XG(SS, 2) XG(SS, 3) XG(SS, 4) XG(SS, 5) XG(SS, 6) XG(SS, 7) XG(SS, 8)
+            XS(1) XS(2) XS(3) XS(4) XS(5) XS(6)
+#undef XS
+#undef XG
+        default: return RICH_EINVAL;
+        }
+        LAUNCH_CHECK();
+        k_reduce_block<<<mout, RED_THREADS, 0, s>>>(pc, mout, RED_BLOCKS, S, nc * S, vs + i0, out + (size_t)i0 * S,
+                                                    out + (size_t)nv * S);
+        LAUNCH_CHECK();
+        pc += (size_t)RED_BLOCKS * mout;
+    }
+    return RICH_OK;
+}
+
+rich_status launch_block_update(const double *V, int64_t ldv, int nv, const double *vs, const double *cf, double *Q,
+                                int S, int64_t n, hipStream_t s) {
+    if (nv < 1 || nv > KMAX || S < 1 || S > GMRES_BLOCK_MAX || (ldv & 1)) return RICH_EINVAL;
+    const bool wide = n >= RED_WIDE_MIN;
+    switch (S) {
+#define X(SS)                                                                                             \
+    case SS:                                                                                              \
+        if (wide)                                                                                         \
+            k_block_update<SS><<<RED_BLOCKS, RED_THREADS, 0, s>>>(V, ldv, nv, vs, cf, Q, n);              \
+        else                                                                                              \
+            k_block_update_small<SS><<<RED_BLOCKS, RED_THREADS, 0, s>>>(V, ldv, nv, vs, cf, Q, n);        \
+        break;
+        X(1) X(2) X(3) X(4) X(5) X(6)
+#undef X
+    default: return RICH_EINVAL;
+    }
+    LAUNCH_CHECK();
+    return RICH_OK;
+}
+
+int block_partial_size(int nv, int S) { return nv * S + S * (S + 1) / 2; }
 
 rich_status launch_dot(const double *x, const double *y, int64_t n, double *partial, double *out, hipStream_t s) {
     k_dot<<<RED_BLOCKS, RED_THREADS, 0, s>>>(x, y, n, partial);

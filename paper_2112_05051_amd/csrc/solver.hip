@@ -60,6 +60,8 @@ struct rich_ctx {
     double *one = nullptr;     // device constant 1.0
     double *hbuf = nullptr;    // device Arnoldi results, one row of (m + 4) per iteration
     double *hall = nullptr;    // pinned host mirror of hbuf
+    double *dblk = nullptr;    // s-step rounds: block dots [0, BLK_BUF), coefficients [BLK_BUF, 2 BLK_BUF)
+    double *hblk = nullptr;    // pinned host mirror of dblk
     double *bsc = nullptr;     // N: scaled right-hand side for a one-level hierarchy
     std::vector<hipEvent_t> iter_ev;  // one per Arnoldi iteration
     // fused serving launches: the batcher this simulation posts its
@@ -92,6 +94,7 @@ struct rich_ctx {
         delete H;
         if (hres) (void)hipHostFree(hres);
         if (hall) (void)hipHostFree(hall);
+        if (hblk) (void)hipHostFree(hblk);
         for (auto e : iter_ev) (void)hipEventDestroy(e);
         if (bev) (void)hipEventDestroy(bev);
         for (auto &k : prof)
@@ -483,11 +486,14 @@ rich_status apply_prec(rich_ctx *h, const double *b, const double *bs) {
     return vcycle<double>(h, b, bs, (double *)h->z);
 }
 
-rich_status spmv_J_z(rich_ctx *h, double *y) {
-    double bytes = (double)h->N * (56 + 8 + (h->mixed ? 4 : 8));
+// y = J z, or y = J z - sig (sbs[0] sb) with a shift vector
+rich_status spmv_J_z(rich_ctx *h, double *y, const double *sb = nullptr, const double *sbs = nullptr,
+                     double sig = 0.0) {
+    if (sig == 0.0) sb = nullptr;
+    double bytes = (double)h->N * (56 + 8 + (h->mixed ? 4 : 8) + (sb ? 8 : 0));
     return timed(h, RICH_K_SPMV_J, bytes, [&] {
-        if (h->mixed) return launch_spmv_J<float>(h->P, h->J7, (const float *)h->z, y, h->s);
-        return launch_spmv_J<double>(h->P, h->J7, (const double *)h->z, y, h->s);
+        if (h->mixed) return launch_spmv_J<float>(h->P, h->J7, (const float *)h->z, y, h->s, sb, sbs, sig);
+        return launch_spmv_J<double>(h->P, h->J7, (const double *)h->z, y, h->s, sb, sbs, sig);
     });
 }
 
@@ -511,6 +517,7 @@ struct BatchReq {
     rich_ctx *h;
     const double *b, *bs;
     double *w;
+    double sig;  // w = J M^{-1} (bs b) - sig (bs b)
     uint64_t ticket;
 };
 
@@ -616,7 +623,15 @@ rich_status apply_batch(const std::vector<BatchReq> &rq, hipStream_t s, WorkQueu
         Hierarchy &H = *q.h->H;
         f.push_back({&q.h->P, m4_of<T>(q.h), invd0_of<T>(q.h), q.b, q.bs, (const T *)H.L[1].x, H.L[0].agg,
                      (T *)H.L[0].r, (T *)q.h->z});
-        if (q.w) sp.push_back({&q.h->P, q.h->J7, (const T *)q.h->z, q.w});
+        if (q.w) {
+            SpmvItem<T> it{&q.h->P, q.h->J7, (const T *)q.h->z, q.w};
+            if (q.sig != 0.0) {
+                it.sb = q.b;
+                it.sbs = q.bs;
+                it.sig = q.sig;
+            }
+            sp.push_back(it);
+        }
     }
     RICH_TRY(launch_st_post_batch<double, T>(f, s, q));
     return launch_spmv_J_batch<T>(sp, s, q);
@@ -659,19 +674,20 @@ void batcher_main(rich_batcher *B, int device) {
     }
 }
 
-// w = J M^{-1} (bs b) (w null: z = M^{-1} (bs b) only), through the batcher
-// when the simulation is in a batched solve, else on its own stream.
-rich_status prec_product(rich_ctx *h, const double *b, const double *bs, double *w) {
+// w = J M^{-1} (bs b) - sig (bs b) (w null: z = M^{-1} (bs b) only), through
+// the batcher when the simulation is in a batched solve, else on its own
+// stream.
+rich_status prec_product(rich_ctx *h, const double *b, const double *bs, double *w, double sig = 0.0) {
     if (!h->in_batch) {
         RICH_TRY(apply_prec(h, b, bs));
-        return w ? spmv_J_z(h, w) : RICH_OK;
+        return w ? spmv_J_z(h, w, b, bs, sig) : RICH_OK;
     }
     rich_batcher *B = h->batcher;
     HIP_TRY(hipEventRecord(h->bev, h->s));
     std::unique_lock<std::mutex> lk(B->mu);
     const uint64_t t = B->posted++;
     if (B->pend.empty()) B->first = std::chrono::steady_clock::now();
-    B->pend.push_back({h, b, bs, w, t});
+    B->pend.push_back({h, b, bs, w, sig, t});
     B->cv.notify_all();
     B->cv.wait(lk, [&] { return B->issued > t; });
     return B->last;
@@ -714,7 +730,8 @@ rich_status add_z(rich_ctx *h, double *x) {
 constexpr double GMRES_SPEC_MARGIN = 4.0;
 constexpr int64_t GMRES_SPEC_MIN_ROWS = (int64_t)1 << 21;
 
-rich_status gmres(rich_ctx *h, const double *b, double *x, int *its_out, double *relres_out, bool *conv_out) {
+rich_status gmres_classic(rich_ctx *h, const double *b, double *x, int *its_out, double *relres_out,
+                          bool *conv_out) {
     int64_t N = h->N, ld = h->ldv;
     int m = h->m;
     const int W = m + 4;
@@ -856,6 +873,310 @@ rich_status gmres(rich_ctx *h, const double *b, double *x, int *its_out, double 
     *relres_out = relres;
     *conv_out = conv;
     return RICH_OK;
+}
+
+// ------------------------------------------------------------ s-step GMRES
+// The same restarted right-preconditioned GMRES(m) with the Arnoldi vectors
+// generated s at a time (gmres_block = s >= 2).  A round starting at basis
+// vector v_j0 applies the preconditioned operator s times to the shifted
+// power basis q_0 = v_j0, q_{t+1} = (J M^{-1} - sigma I) q_t (the shift is
+// fused into the J product), then orthogonalises q_1..q_s against
+// v_0..v_j0 and each other in one block round: one pass gives C = V^T Q and
+// the Gram matrix G = Q^T Q, the host factors the Pythagorean complement
+// G - C^T C = R^T R (Cholesky), and one pass writes (Q - V C) R^{-1}, the
+// next s orthonormal basis vectors.  A round in which some vector keeps less
+// than gmres_reorth of its norm, or whose complement is not positive
+// definite, is orthogonalised vector by vector with two classical passes
+// instead.  The Hessenberg columns j0..j0+s-1 follow from the coordinates of
+// the q_t in the new basis: with S the coordinates of q_0..q_s and H_prev
+// the earlier columns, J M^{-1} [v_j0..v_{j0+s-1}] =
+// (S_{:,1..s} + sigma S_{:,0..s-1} - H_prev S_{0..j0-1, 0..s-1}) Sb^{-1},
+// Sb the (upper triangular) rows j0..j0+s-1 of S's first s columns.  The
+// residual estimate is tested after every column, as one vector at a time
+// would, and the next round is cut to the steps the estimate's decay over
+// the last round predicts.
+rich_status gmres_sstep(rich_ctx *h, const double *b, double *x, int *its_out, double *relres_out,
+                        bool *conv_out) {
+    const int64_t N = h->N, ld = h->ldv;
+    const int m = h->m, S = h->O.gmres_block;
+    const double sig = h->O.gmres_shift, eta = h->O.eta, reorth = h->O.gmres_reorth;
+    hipStream_t s = h->s;
+    // Hr: the cycle's Hessenberg matrix as computed; Hm: its rotated copy
+    std::vector<double> Hr((size_t)(m + 1) * m), Hm((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+    double nb[3];
+    RICH_TRY(norms(h, b, nb));
+    const double bnorm = std::sqrt(nb[2]);
+    RICH_TRY(launch_fill_f64(x, 0.0, N, s));
+    charge(h, 16.0 * N);
+    int total = 0;
+    bool conv = false;
+    double relres = 0.0;
+    if (bnorm == 0.0) {
+        *its_out = 0;
+        *relres_out = 0.0;
+        *conv_out = true;
+        return RICH_OK;
+    }
+    if (!std::isfinite(bnorm)) return RICH_NONFINITE;
+    BatchScope batch_scope(h);
+    double *dout = h->dblk, *dcf = h->dblk + BLK_BUF;
+    double *hout = h->hblk, *hcf = h->hblk + BLK_BUF;
+    bool first = true;
+    for (;;) {
+        // true residual into V_0 (stored unnormalised, scale 1/beta on the device)
+        if (first) {
+            HIP_TRY(hipMemcpyAsync(h->V, b, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+            charge(h, 16.0 * N);
+        } else {
+            RICH_TRY(launch_spmv_J<double>(h->P, h->J7, x, h->V, s));
+            RICH_TRY(launch_b_minus(b, h->V, N, s));
+            charge(h, 72.0 * N + 24.0 * N);
+        }
+        charge(h, 8.0 * N);  // norms of V_0
+        first = false;
+        double rn[3];
+        RICH_TRY(norms(h, h->V, rn));
+        const double beta = std::sqrt(rn[2]);
+        if (!std::isfinite(beta)) return RICH_NONFINITE;
+        relres = beta / bnorm;
+        if (beta <= eta * bnorm) {
+            conv = true;
+            break;
+        }
+        if (total >= h->O.gmres_maxit) break;
+        RICH_TRY(launch_set_scale(h->vs, h->dres + 2, s));  // dres[2] = ||V_0||^2 from norms()
+        std::fill(g.begin(), g.end(), 0.0);
+        std::fill(Hr.begin(), Hr.end(), 0.0);
+        g[0] = beta;
+        int j0 = 0, k = 0, ss_next = S;
+        bool stop = false;
+        // Hessenberg column j (in Hr) into the rotated factor and the residual estimate
+        auto add_column = [&](int j) {
+            const double hn = Hr[(size_t)(j + 1) * m + j];
+            for (int i = 0; i <= j + 1; i++) Hm[(size_t)i * m + j] = Hr[(size_t)i * m + j];
+            for (int i = 0; i < j; i++) {
+                double a = Hm[(size_t)i * m + j], cc = Hm[(size_t)(i + 1) * m + j];
+                Hm[(size_t)i * m + j] = cs[i] * a + sn[i] * cc;
+                Hm[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * cc;
+            }
+            double a = Hm[(size_t)j * m + j], cc = Hm[(size_t)(j + 1) * m + j];
+            double rho = std::sqrt(a * a + cc * cc);
+            cs[j] = a / rho;
+            sn[j] = cc / rho;
+            Hm[(size_t)j * m + j] = rho;
+            Hm[(size_t)(j + 1) * m + j] = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            total++;
+            k = j + 1;
+            if (std::fabs(g[j + 1]) <= eta * bnorm || hn == 0.0 || total >= h->O.gmres_maxit) stop = true;
+        };
+        // one classical Arnoldi step per column (normalised inputs, second
+        // pass on cancellation): the round's power basis overflowed
+        auto classical_round = [&](int ss) -> rich_status {
+            for (int c = 0; c < ss && !stop; c++) {
+                const int j = j0 + c;
+                double *w = h->V + (size_t)(j + 1) * ld;
+                RICH_TRY(prec_product(h, h->V + (size_t)j * ld, h->vs + j, w));
+                std::vector<double> hv(j + 1, 0.0);
+                double ww0 = 0.0, ww = 0.0;
+                for (int pass = 0; pass < 2; pass++) {
+                    RICH_TRY(timed(h, pass ? RICH_K_COUNT : RICH_K_MULTIDOT, 8.0 * N * (j + 2), [&] {
+                        return launch_multidot(h->V, ld, j + 1, h->vs, w, N, h->partial, h->dres, s);
+                    }));
+                    RICH_TRY(timed(h, pass ? RICH_K_COUNT : RICH_K_UPDATE, 8.0 * N * (j + 3), [&] {
+                        return launch_update_norm(h->V, ld, j + 1, h->dres, h->vs, w, N, h->partial, h->dres2, s);
+                    }));
+                    HIP_TRY(hipMemcpyAsync(h->hres, h->dres, (j + 2) * sizeof(double), hipMemcpyDeviceToHost, s));
+                    HIP_TRY(hipMemcpyAsync(h->hres + (m + 8), h->dres2, sizeof(double), hipMemcpyDeviceToHost, s));
+                    RICH_TRY(sync(h));
+                    for (int i = 0; i <= j; i++) hv[i] += h->hres[i];
+                    if (pass == 0) ww0 = h->hres[j + 1];
+                    ww = h->hres[m + 8];
+                    if (!(std::sqrt(ww) < h->O.gmres_reorth * std::sqrt(ww0))) break;
+                }
+                RICH_TRY(launch_set_scale(h->vs + j + 1, h->dres2, s));
+                const double hn = std::sqrt(ww);
+                if (!std::isfinite(hn)) return RICH_NONFINITE;
+                for (int i = 0; i <= j; i++) Hr[(size_t)i * m + j] = hv[i];
+                Hr[(size_t)(j + 1) * m + j] = hn;
+                add_column(j);
+            }
+            return RICH_OK;
+        };
+        while (!stop && j0 < m && total < h->O.gmres_maxit) {
+            int ss = std::min(std::min(ss_next, m - j0), h->O.gmres_maxit - total);
+            const int nv = j0 + 1;
+            double *Q = h->V + (size_t)nv * ld;
+            const double g_start = std::fabs(g[j0]);
+            // the power basis: raw vectors (scale 1) in slots nv .. nv+ss-1
+            RICH_TRY(launch_fill_f64(h->vs + nv, 1.0, ss, s));
+            for (int t = 0; t < ss; t++)
+                RICH_TRY(prec_product(h, h->V + (size_t)(j0 + t) * ld, h->vs + j0 + t,
+                                      h->V + (size_t)(j0 + t + 1) * ld, sig));
+            const int nout = block_partial_size(nv, ss);
+            RICH_TRY(timed(h, RICH_K_BLOCK_DOT, 8.0 * N * (nv + ss), [&] {
+                return launch_block_dot(h->V, ld, nv, h->vs, Q, ss, N, h->partial, dout, s);
+            }));
+            HIP_TRY(hipMemcpyAsync(hout, dout, nout * sizeof(double), hipMemcpyDeviceToHost, s));
+            RICH_TRY(sync(h));
+            bool finite = true;
+            for (int t = 0; t < nout; t++) finite = finite && std::isfinite(hout[t]);
+            if (!finite) {
+                RICH_TRY(classical_round(ss));
+                j0 += ss;
+                ss_next = S;
+                continue;
+            }
+            // coordinates of q_1..q_ss in v_0..v_{j0+ss}: C (nv x ss), R (ss x ss, upper),
+            // row stride sw (ss may shrink below)
+            const int sw = ss;
+            std::vector<double> C((size_t)nv * sw), R((size_t)sw * sw, 0.0), Gm((size_t)sw * sw);
+            for (int t = 0; t < nv * ss; t++) C[t] = hout[t];
+            for (int a = 0, t = nv * ss; a < ss; a++)
+                for (int c = a; c < ss; c++, t++) Gm[a * ss + c] = Gm[c * ss + a] = hout[t];
+            bool ok = true, overflow = false;
+            for (int a = 0; a < ss && ok; a++) {
+                for (int c = a; c < ss; c++) {
+                    double pac = Gm[a * ss + c];
+                    for (int i = 0; i < nv; i++) pac -= C[i * ss + a] * C[i * ss + c];
+                    for (int r = 0; r < a; r++) pac -= R[r * ss + a] * R[r * ss + c];
+                    if (c == a) {
+                        if (!(pac > 0.0) || !(pac > reorth * reorth * Gm[a * ss + a])) {
+                            ok = false;
+                            break;
+                        }
+                        R[a * ss + a] = std::sqrt(pac);
+                    } else {
+                        R[a * ss + c] = pac / R[a * ss + a];
+                    }
+                }
+            }
+            if (ok) {
+                // coefficients: C, then R^{-1} (upper triangular)
+                for (int t = 0; t < nv * ss; t++) hcf[t] = C[t];
+                double *ri = hcf + nv * ss;
+                for (int t = 0; t < ss * ss; t++) ri[t] = 0.0;
+                for (int c = 0; c < ss; c++) {
+                    ri[c * ss + c] = 1.0 / R[c * ss + c];
+                    for (int a = c - 1; a >= 0; a--) {
+                        double acc = 0.0;
+                        for (int r = a + 1; r <= c; r++) acc += R[a * ss + r] * ri[r * ss + c];
+                        ri[a * ss + c] = -acc / R[a * ss + a];
+                    }
+                }
+                HIP_TRY(hipMemcpyAsync(dcf, hcf, (nv * ss + ss * ss) * sizeof(double), hipMemcpyHostToDevice, s));
+                RICH_TRY(timed(h, RICH_K_BLOCK_UPDATE, 8.0 * N * (nv + 2 * ss), [&] {
+                    return launch_block_update(h->V, ld, nv, h->vs, dcf, Q, ss, N, s);
+                }));
+            } else {
+                // vector by vector: two classical passes against everything before it
+                std::fill(C.begin(), C.end(), 0.0);
+                std::fill(R.begin(), R.end(), 0.0);
+                for (int t = 0; t < ss; t++) {
+                    const int slot = nv + t;
+                    double *w = h->V + (size_t)slot * ld;
+                    double ww = 0.0;
+                    for (int pass = 0; pass < 2; pass++) {
+                        RICH_TRY(timed(h, RICH_K_COUNT, 8.0 * N * (slot + 1), [&] {
+                            return launch_multidot(h->V, ld, slot, h->vs, w, N, h->partial, h->dres, s);
+                        }));
+                        RICH_TRY(timed(h, RICH_K_COUNT, 8.0 * N * (slot + 2), [&] {
+                            return launch_update_norm(h->V, ld, slot, h->dres, h->vs, w, N, h->partial, h->dres2, s);
+                        }));
+                        HIP_TRY(hipMemcpyAsync(h->hres, h->dres, slot * sizeof(double), hipMemcpyDeviceToHost, s));
+                        HIP_TRY(hipMemcpyAsync(h->hres + (m + 8), h->dres2, sizeof(double), hipMemcpyDeviceToHost, s));
+                        RICH_TRY(sync(h));
+                        for (int i = 0; i < nv; i++) C[i * sw + t] += h->hres[i];
+                        for (int r = 0; r < t; r++) R[r * sw + t] += h->hres[nv + r];
+                        ww = h->hres[m + 8];
+                    }
+                    RICH_TRY(launch_set_scale(h->vs + slot, h->dres2, s));
+                    R[t * sw + t] = std::sqrt(ww);
+                    if (!std::isfinite(R[t * sw + t])) {
+                        overflow = true;
+                        break;
+                    }
+                    if (!(ww > 0.0)) {  // q_{t+1} lies in the space spanned so far: the cycle ends here
+                        ss = t + 1;
+                        break;
+                    }
+                }
+            }
+            if (overflow) {
+                RICH_TRY(classical_round(ss));
+                j0 += ss;
+                ss_next = S;
+                continue;
+            }
+            // Hessenberg columns j0 .. j0+ss-1 from the coordinates
+            const int K = nv + ss, W1 = ss + 1;
+            std::vector<double> Sh((size_t)K * W1, 0.0), X((size_t)K * ss);
+            Sh[(size_t)j0 * W1] = 1.0;
+            for (int t = 0; t < ss; t++) {
+                for (int i = 0; i < nv; i++) Sh[(size_t)i * W1 + t + 1] = C[i * sw + t];
+                for (int r = 0; r <= t; r++) Sh[(size_t)(nv + r) * W1 + t + 1] = R[r * sw + t];
+            }
+            for (int r = 0; r < K; r++)
+                for (int c = 0; c < ss; c++) {
+                    double v = Sh[(size_t)r * W1 + c + 1] + sig * Sh[(size_t)r * W1 + c];
+                    for (int q = (r > 0 ? r - 1 : 0); q < j0; q++) v -= Hr[(size_t)r * m + q] * Sh[(size_t)q * W1 + c];
+                    X[(size_t)r * ss + c] = v;
+                }
+            // X <- X Sb^{-1}, Sb[a][c] = Sh[j0 + a][c] (upper triangular)
+            for (int c = 0; c < ss; c++) {
+                const double d = Sh[(size_t)(j0 + c) * W1 + c];
+                for (int r = 0; r < K; r++) {
+                    double v = X[(size_t)r * ss + c];
+                    for (int a = 0; a < c; a++) v -= X[(size_t)r * ss + a] * Sh[(size_t)(j0 + a) * W1 + c];
+                    X[(size_t)r * ss + c] = v / d;
+                }
+            }
+            bool xfinite = true;
+            for (int t = 0; t < K * ss; t++) xfinite = xfinite && std::isfinite(X[t]);
+            if (!xfinite) {
+                RICH_TRY(classical_round(ss));
+                j0 += ss;
+                ss_next = S;
+                continue;
+            }
+            for (int c = 0; c < ss && !stop; c++) {
+                const int j = j0 + c;
+                for (int r = 0; r <= j + 1; r++) Hr[(size_t)r * m + j] = X[(size_t)r * ss + c];
+                add_column(j);
+            }
+            j0 += ss;
+            // the next round: as many vectors as the decay of the residual
+            // estimate over this round predicts are still needed (at most s)
+            ss_next = S;
+            const double g_end = std::fabs(g[j0]);
+            if (!stop && g_end > 0.0 && g_end < g_start) {
+                const double need = std::log(eta * bnorm / g_end) / (std::log(g_end / g_start) / ss);
+                if (need < S) ss_next = std::max(1, (int)std::ceil(need));
+            }
+        }
+        for (int i = k - 1; i >= 0; i--) {
+            double sum = g[i];
+            for (int t = i + 1; t < k; t++) sum -= Hm[(size_t)i * m + t] * y[t];
+            y[i] = sum / Hm[(size_t)i * m + i];
+        }
+        memcpy(h->hres, y.data(), k * sizeof(double));
+        HIP_TRY(hipMemcpyAsync(h->dres, h->hres, k * sizeof(double), hipMemcpyHostToDevice, s));
+        RICH_TRY(launch_lincomb(h->V, ld, k, h->dres, h->vs, h->work, N, s));
+        RICH_TRY(prec_product(h, h->work, h->one, nullptr));
+        RICH_TRY(add_z(h, x));
+        charge(h, 8.0 * (k + 1) * N + (16.0 + (h->mixed ? 4 : 8)) * N);
+        RICH_TRY(sync(h));  // hres is reused before the next read
+    }
+    *its_out = total;
+    *relres_out = relres;
+    *conv_out = conv;
+    return RICH_OK;
+}
+
+rich_status gmres(rich_ctx *h, const double *b, double *x, int *its_out, double *relres_out, bool *conv_out) {
+    if (h->O.gmres_block >= 2) return gmres_sstep(h, b, x, its_out, relres_out, conv_out);
+    return gmres_classic(h, b, x, its_out, relres_out, conv_out);
 }
 
 // ----------------------------------------------------------------- Newton
@@ -1250,6 +1571,7 @@ rich_status validate(const rich_problem_t *P, const rich_solver_opts_t *O) {
     if (O->amg_aggregation == RICH_AGG_VMB && (!(O->amg_theta >= 0.0 && O->amg_theta <= 1.0) || O->amg_block < 1))
         return RICH_EINVAL;
     if (!(O->gmres_reorth >= 0.0 && O->gmres_reorth < 1.0)) return RICH_EINVAL;
+    if (O->gmres_block < 1 || O->gmres_block > GMRES_BLOCK_MAX || !std::isfinite(O->gmres_shift)) return RICH_EINVAL;
     if (!(O->eta > 0) || !(O->fnormtol > 0) || O->max_newton < 1 || O->msbset < 1) return RICH_EINVAL;
     return RICH_OK;
 }
@@ -1408,7 +1730,8 @@ rich_status rich_create(const rich_problem_t *prob, const rich_solver_opts_t *op
     G(&zt, N * 8);
     h->z = z;
     h->ztmp = zt;
-    G(&h->partial, (size_t)RED_BLOCKS * (h->m + 2) * 3);
+    G(&h->partial, (size_t)RED_BLOCKS * std::max(3 * (h->m + 2), block_partial_size(h->m + 1, GMRES_BLOCK_MAX)));
+    G(&h->dblk, 2 * BLK_BUF);
     G(&h->dres, h->m + 8);
     G(&h->dres2, 8);
     G(&h->vs, h->m + 2);
@@ -1419,6 +1742,8 @@ rich_status rich_create(const rich_problem_t *prob, const rich_solver_opts_t *op
         st = RICH_ENOMEM;
     if (st == RICH_OK &&
         hipHostMalloc((void **)&h->hall, (size_t)(h->m + 1) * (h->m + 4) * sizeof(double)) != hipSuccess)
+        st = RICH_ENOMEM;
+    if (st == RICH_OK && hipHostMalloc((void **)&h->hblk, 2 * BLK_BUF * sizeof(double)) != hipSuccess)
         st = RICH_ENOMEM;
     for (int j = 0; st == RICH_OK && j <= h->m; j++) {
         hipEvent_t e;
@@ -1464,6 +1789,7 @@ rich_status rich_step(rich_handle_t h, int nsteps, rich_step_stats_t *stats_host
     for (int t = 0; t < nsteps; t++) {
         rich_step_stats_t st;
         rich_status rc = newton_step(h, &st);
+        if (rc < 0 && st.status >= 0) st.status = rc;  // an error raised below the controller
         if (stats_host) stats_host[t] = st;
         if (rc < 0) return rc;
         warn = std::max(warn, rc);

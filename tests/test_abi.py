@@ -79,7 +79,7 @@ def test_server_rejects_over_budget_without_gpu():
 
 
 def test_option_domains_without_gpu():
-    """The smoother, aggregation and strength options are checked on the host."""
+    """The smoother, aggregation, strength and GMRES round options are checked on the host."""
     import ctypes as C
 
     import paper_2112_05051_amd as rich
@@ -90,7 +90,10 @@ def test_option_domains_without_gpu():
     b = C.c_size_t()
     for kw, ok in (({"smoother": 1}, True), ({"smoother": 2}, False), ({"amg_aggregation": 1}, True),
                    ({"amg_aggregation": 2}, False), ({"amg_aggregation": 1, "amg_theta": 1.5}, False),
-                   ({"amg_aggregation": 1, "amg_block": 0}, False), ({"amg_aggregation": 1, "amg_theta": 0.25}, True)):
+                   ({"amg_aggregation": 1, "amg_block": 0}, False), ({"amg_aggregation": 1, "amg_theta": 0.25}, True),
+                   ({"gmres_block": 0}, False), ({"gmres_block": 1}, True), ({"gmres_block": 6}, True),
+                   ({"gmres_block": 7}, False), ({"gmres_shift": float("nan")}, False),
+                   ({"gmres_shift": 0.0}, True)):
         O = synth.Options(**kw)
         rc = lib.rich_query_bytes(C.byref(_lib.make_problem(P)), C.byref(_lib.make_opts(O)), C.byref(b))
         assert (rc == 0) == ok, (kw, rc)

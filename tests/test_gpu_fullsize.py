@@ -9,6 +9,8 @@ step must satisfy the Newton tolerance of Section 3 whatever path led to it),
 and, at 128^3, the level-0 aggregates and level-1 matrix of the GPU's AMG set-up
 against the oracle's set-up on the same auxiliary matrix.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 import scipy.sparse as sp
@@ -114,11 +116,12 @@ def test_paper_3d_full_size_step(rich, torch, orc):
 
 
 def test_full_size_vcycle_and_gmres_c2(rich, torch, orc):
-    """128^3 (2^21 rows: the wide Gram-Schmidt kernels and the speculative
-    Arnoldi step of large grids): one FP64 V-cycle on the GPU's own auxiliary
-    matrix equals the oracle's V-cycle on that matrix (Section 5.2), and one
-    GMRES(30) solve of a Newton correction matches the oracle's (iterations
-    within one, solutions within 10 eta; Section 6's stopping rule)."""
+    """128^3 (2^21 rows: the wide Gram-Schmidt kernels of large grids): one
+    FP64 V-cycle on the GPU's own auxiliary matrix equals the oracle's V-cycle
+    on that matrix (Section 5.2), and one GMRES(30) solve of a Newton
+    correction, with s-step rounds and with the speculative one-vector
+    Arnoldi steps, matches the oracle's (iterations within one, solutions
+    within 10 eta; Section 6's stopping rule)."""
     rec = synth.recipe("c2")
     P, opts = rec.problem, rec.options
     assert P.n == 1 << 21 and opts.precision == synth.FP64
@@ -137,12 +140,21 @@ def test_full_size_vcycle_and_gmres_c2(rich, torch, orc):
     xg = s.apply_prec(torch.from_numpy(b).cuda()).cpu().numpy()
     xo = amg.apply(b)
     assert np.linalg.norm(xg - xo) <= 1e-10 * np.linalg.norm(xo)
-    x, its, rr, conv = s.gmres(torch.from_numpy(b).cuda())
-    x = x.cpu().numpy()
     J = orc.jacobian(P, ks, p1)
     xo, conv_o, its_o, rr_o = orc.gmres(J, b, amg, opts.gmres_restart, opts.eta, opts.gmres_maxit)
-    assert conv and conv_o and its_o > opts.gmres_restart  # at least one restart
-    assert abs(its - its_o) <= 1, (its, its_o)
-    assert np.linalg.norm(J @ x - b) <= opts.eta * np.linalg.norm(b) * (1 + 1e-6)
-    assert np.linalg.norm(x - xo) <= 10 * opts.eta * np.linalg.norm(xo)
+    assert conv_o and its_o > opts.gmres_restart  # at least one restart
+    # the s-step rounds of the default options, then one Arnoldi vector per round
+    assert opts.gmres_block > 1
+    for block in (opts.gmres_block, 1):
+        if block != opts.gmres_block:
+            s.close()
+            o1 = dataclasses.replace(opts, gmres_block=block)
+            s = rich.Solver(P, o1, torch.from_numpy(ks).cuda())
+            s.assemble(torch.from_numpy(p1).cuda())
+        x, its, rr, conv = s.gmres(torch.from_numpy(b).cuda())
+        x = x.cpu().numpy()
+        assert conv
+        assert abs(its - its_o) <= 1, (block, its, its_o)
+        assert np.linalg.norm(J @ x - b) <= opts.eta * np.linalg.norm(b) * (1 + 1e-6)
+        assert np.linalg.norm(x - xo) <= 10 * opts.eta * np.linalg.norm(xo)
     s.close()

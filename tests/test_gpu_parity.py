@@ -154,8 +154,19 @@ def test_hierarchy_bitexact(rich, torch, orc, mean, smoothed):
     assert np.linalg.norm(xg - xo) <= 1e-10 * np.linalg.norm(xo)
 
 
-def test_gmres_parity(rich, torch, orc):
-    r = smooth_recipe("c3", 24, precision=synth.FP64)
+# gmres_block 1: one Arnoldi vector per Gram-Schmidt round; >= 2: s-step rounds
+# (shifted power basis, one block round), also where the restart length cuts a
+# round short, on an odd number of rows (the kernels' row-pair tail), and with
+# every round redone vector by vector (gmres_reorth close to 1 rejects each
+# Cholesky factor), at the default tolerance and at one that needs restarts.
+@pytest.mark.parametrize("block,restart,reorth,n,eta", [
+    (1, 30, 0.01, 24, 1e-6), (5, 30, 0.01, 24, 1e-6), (2, 30, 0.01, 23, 1e-6), (6, 7, 0.01, 23, 1e-6),
+    (4, 30, 0.999, 24, 1e-6), (5, 30, 0.01, 24, 1e-10), (3, 10, 0.01, 21, 1e-10)])
+def test_gmres_parity(rich, torch, orc, block, restart, reorth, n, eta):
+    r = smooth_recipe("c3", n, precision=synth.FP64)
+    r.options.gmres_block, r.options.gmres_restart, r.options.gmres_reorth = block, restart, reorth
+    r.options.eta = eta
+    r.options.gmres_maxit = 400
     P = r.problem
     ks, p0 = r.ks(), r.p0()
     s = make_solver(rich, torch, P, ks, r.options)
@@ -170,7 +181,7 @@ def test_gmres_parity(rich, torch, orc):
     J = orc.jacobian(P, ks, p0)
     xo, conv_o, its_o, rr_o = orc.gmres(J, -F, amg, r.options.gmres_restart, r.options.eta, r.options.gmres_maxit)
     assert conv and conv_o
-    assert abs(its - its_o) <= 1
+    assert abs(its - its_o) <= 1, (its, its_o)
     assert np.linalg.norm(J @ x + F) <= r.options.eta * np.linalg.norm(F) * (1 + 1e-6)
     # both are eta-accurate solutions of the same system: their difference is
     # bounded by the two residuals through ||J^{-1}||; in practice it is far below eta.
