@@ -567,8 +567,11 @@ __device__ __forceinline__ void spmv_J_at(const G &P, uint32_t n, const double *
     if (q.j < P.ny - 1) s += a4 * x4;
     if (q.k > 0) s += a5 * x5;
     if (q.k < P.nz - 1) s += a6 * x6;
-    if (sb) s -= sig * (sbs[0] * sb[c]);
-    y[c] = s;
+    // the shift input is not read again before it leaves the caches: streamed;
+    // y is stored streaming too (the Gram-Schmidt dots that read it next run
+    // faster than with y left in the caches)
+    if (sb) s -= sig * (sbs[0] * __builtin_nontemporal_load(sb + c));
+    __builtin_nontemporal_store(s, y + c);
 }
 
 template <class TX>
