@@ -155,6 +155,8 @@ def cpu_baseline(rec, ks, timed_stats, gmres_sample=5):
 FAMILIES = {
     "update": ("k_update_norm<", "la.hip"),
     "multidot": ("k_multidot<", "la.hip"),
+    "block_dot": ("k_block_dot<", "la.hip"),
+    "block_update": ("k_block_update<", "la.hip"),
     "spmv_J": ("k_spmv_J<float>", "fine.hip"),
     "vc0_pre": ("k_st25<double, float, 0>", "fine.hip"),
     "vc0_post": ("k_st25<double, float, 1>", "fine.hip"),
@@ -175,13 +177,15 @@ def _xcd(blocks):
     return _ceil(blocks, 8) * 8
 
 
-def algorithmic_bytes(name, n, blocks=None, levels=None, mixed=True):
+def algorithmic_bytes(name, n, blocks=None, levels=None, mixed=True, shifted=True):
     """Algorithmic HBM bytes of one launch (the per-row figures of the kernel
     table of the design notes): fine-grid kernels from n alone; the coarse
     kernels of level l from that level's rows and entries, the level found by
     the launch's block count (CSR-stream: one block per 1536 entries, the
     restriction: one block per 256 coarse rows, both padded to a multiple of
-    8).  None when the launch cannot be placed."""
+    8).  shifted: the J products of GMRES form the s-step power basis (they
+    also read the shift vector).  None when the launch cannot be placed (the
+    block Gram-Schmidt kernels: their basis length is not in the launch)."""
     import re
     t = 4 if mixed else 8
     m = re.search(r"k_(multidot|update_norm)<(\d+)>", name)
@@ -189,7 +193,7 @@ def algorithmic_bytes(name, n, blocks=None, levels=None, mixed=True):
         k = int(m.group(2))
         return 8 * n * (k + 1) + (8 * n if m.group(1) == "update_norm" else 0)
     if "k_spmv_J<float>" in name:
-        return 68 * n
+        return (76 if shifted else 68) * n
     if "k_st25<double, float, 0>" in name or "k_st_pre<double, float>" in name:
         return 8 * n + 6 * t * n
     if "k_faces_tiled<false" in name or "k_residual" in name:
@@ -229,15 +233,20 @@ def source_digests():
     return {f: source_digest(f) for f in sorted({src for _, src in FAMILIES.values()})}
 
 
-def pmc_summary(fetch_csv, write_csv, n, digests=None, levels=None):
+def pmc_summary(fetch_csv, write_csv, n, digests=None, levels=None, info=None):
     """Per-kernel HBM traffic from rocprofv3 FETCH_SIZE / WRITE_SIZE counter runs,
     calibrated by the 1 GiB device copy of --calibrate-copy, per kernel and
     launch size.  The trailing 'family' lines (measured bytes over algorithmic
     bytes, summed over the family's launches, with the digest of the kernel's
     source file) are what the benchmark reads back to report measured traffic.
     `digests` are the source digests the profiled run printed, `levels` its
-    hierarchy ([rows, entries] per level)."""
+    hierarchy ([rows, entries] per level), `info` its JSON line: its options
+    say whether the J products were shifted, and its per-kernel event timings
+    give the block Gram-Schmidt kernels' algorithmic bytes (the library's own
+    count over the same launches)."""
     digests = digests or source_digests()
+    info = info or {}
+    shifted = info.get("options", {}).get("gmres_block", 1) > 1
     import collections
     import csv
     vals = {}
@@ -263,7 +272,7 @@ def pmc_summary(fetch_csv, write_csv, n, digests=None, levels=None):
         f_b = cal["FETCH_SIZE"] * sum(lst) / len(lst)
         w_b = cal["WRITE_SIZE"] * sum(w) / len(w)
         blocks = grid // 256 if grid else None
-        alg = algorithmic_bytes(k, n, blocks, levels)
+        alg = algorithmic_bytes(k, n, blocks, levels, shifted=shifted)
         rows.append((k, blocks, len(lst), f_b, w_b, alg))
     rows.sort(key=lambda r: -(r[3] + r[4]) * r[2])
     for k, blocks, cnt, f_b, w_b, alg in rows[:45]:
@@ -271,12 +280,22 @@ def pmc_summary(fetch_csv, write_csv, n, digests=None, levels=None):
         lines.append(f"{short:52s} {blocks if blocks else 0:7d} {cnt:8d} {f_b / 1e6:9.2f} {w_b / 1e6:9.2f} "
                      f"{(alg / 1e6 if alg else float('nan')):9.2f} {((f_b + w_b) / alg if alg else float('nan')):11.3f}")
     lines += ["", "family      launches  traffic/alg  source digest"]
+    kern = info.get("kernels", {})
     for fam, (prefix, src) in FAMILIES.items():
-        sel = [r for r in rows if prefix in r[0] and r[5]]
-        if not sel:
-            continue
-        meas = sum((r[3] + r[4]) * r[2] for r in sel)
-        alg = sum(r[5] * r[2] for r in sel)
+        if fam in ("block_dot", "block_update"):
+            # per-launch bytes vary with the basis length: the library's total over the run
+            sel = [r for r in rows if prefix in r[0]]
+            k = kern.get(fam)
+            if not sel or not k or k["launches"] != sum(r[2] for r in sel):
+                continue
+            meas = sum((r[3] + r[4]) * r[2] for r in sel)
+            alg = k["bytes_per_launch"] * k["launches"]
+        else:
+            sel = [r for r in rows if prefix in r[0] and r[5]]
+            if not sel:
+                continue
+            meas = sum((r[3] + r[4]) * r[2] for r in sel)
+            alg = sum(r[5] * r[2] for r in sel)
         lines.append(f"family {fam} {sum(r[2] for r in sel)} {meas / alg:.4f} {src} {digests[src]}")
     return "\n".join(lines)
 
@@ -317,6 +336,38 @@ def stats_summary(stats_csv):
     for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"]))[:20]:
         name = r["Name"].replace("void ", "").replace("rich::(anonymous namespace)::", "")[:70]
         lines.append(f"{name:70s} {int(r['Calls']):8d} {float(r['AverageNs']) / 1e3:9.1f}")
+    return "\n".join(lines)
+
+
+def trace_gaps(trace_csv):
+    """GPU idle time between kernels from a rocprofv3 --kernel-trace
+    kernel_trace.csv: the span from the first kernel's start to the last one's
+    end, the time no kernel ran, and that idle time by the pair of kernel
+    families it fell between."""
+    import collections
+    import csv
+    import re
+
+    def fam(k):
+        k = k.replace("void ", "").replace("rich::(anonymous namespace)::", "").replace("rich::", "")
+        return re.sub(r"<.*", "", k.split("(")[0])[:28]
+    ks = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), fam(r["Kernel_Name"]))
+                for r in csv.DictReader(open(trace_csv)))
+    t0, t1 = ks[0][0], max(e for _, e, _ in ks)
+    busy, last, prev = 0, t0, "start"
+    cnt, tot = collections.Counter(), collections.Counter()
+    for s, e, k in ks:
+        if s > last:
+            cnt[(prev, k)] += 1
+            tot[(prev, k)] += s - last
+        busy += max(0, e - max(s, last))
+        last, prev = max(last, e), k
+    span = t1 - t0
+    lines = [f"kernels {len(ks)}, span {span / 1e9:.3f} s, busy {busy / 1e9:.3f} s, "
+             f"idle {(span - busy) / 1e9:.3f} s ({100 * (span - busy) / span:.1f}%)",
+             f"{'idle between':62s} {'ms':>8s} {'gaps':>7s} {'avg us':>7s}"]
+    for (a, b), v in tot.most_common(20):
+        lines.append(f"{a + ' -> ' + b:62s} {v / 1e6:8.1f} {cnt[(a, b)]:7d} {v / cnt[(a, b)] / 1e3:7.1f}")
     return "\n".join(lines)
 
 
@@ -435,14 +486,19 @@ def main():
                     help="one interface mean for every request (default: drawn per request)")
     ap.add_argument("--stats-summary", metavar="KERNEL_STATS_CSV",
                     help="print kernel time by family from a rocprofv3 --stats run and exit")
+    ap.add_argument("--trace-gaps", metavar="KERNEL_TRACE_CSV",
+                    help="print the GPU idle time between kernels of a rocprofv3 --kernel-trace run and exit")
     args = ap.parse_args()
     if args.stats_summary:
         print(stats_summary(args.stats_summary))
         return
+    if args.trace_gaps:
+        print(trace_gaps(args.trace_gaps))
+        return
     if args.pmc_summary:
         info = json.loads(open(args.pmc_summary[2]).read().strip().splitlines()[-1])
         print(pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.n ** 3, info["source_digests"],
-                          info.get("hierarchy_n_nnz")))
+                          info.get("hierarchy_n_nnz"), info))
         return
     if args.gpus != 1:
         print(f"bench.py: the solver runs on one GPU; --gpus {args.gpus} is not supported "
