@@ -475,7 +475,7 @@ def main():
     ap.add_argument("--serve-count", type=int, default=64)
     ap.add_argument("--serve-steps", type=int, default=20)
     ap.add_argument("--serve-rate", type=float, default=4.0)
-    ap.add_argument("--serve-active", type=int, default=4)
+    ap.add_argument("--serve-active", type=int, default=8, help="resident simulations (server workers)")
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     ap.add_argument("--serve-fused", action="store_true",
                     help="fuse the preconditioned products of same-size simulations into batched launches")
