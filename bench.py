@@ -606,6 +606,10 @@ def main():
         "converged": converged,
         "max_newton": rec.options.max_newton,
         "linsolve_fails": sum(s["linsolve_fails"] for s in mixed["stats"]),
+        # discrete mass balance at each accepted state: dt * sum_c Phi_c (the
+        # storage change minus the boundary inflow), and the Newton residual there
+        "max_abs_mass_residual": max((abs(s["mass_residual"]) for s in mixed["stats"]), default=None),
+        "max_fnorm_inf": max((s["fnorm_inf"] for s in mixed["stats"]), default=None),
         "ls_backtracks": sum(s["ls_backtracks"] for s in mixed["stats"]),
         "hierarchy_n_nnz": mixed["levels"],
         "options": {k: getattr(rec.options, k) for k in vars(rec.options)},
