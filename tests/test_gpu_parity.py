@@ -211,6 +211,32 @@ def test_full_steps_fp64(rich, torch, orc, name, n, mean):
         assert err <= 1e-8, (step, err, sg, so)
 
 
+@pytest.mark.parametrize("block", [1, 3, 6])
+def test_full_steps_gmres_rounds(rich, torch, orc, block):
+    """Two FP64 steps of the rough c3 statistics at 16^3 with one-vector
+    GMRES rounds and with s-step rounds of 3 and 6 vectors (the default is
+    5, covered above): the same Newton iterations, Jacobian builds and
+    backtracks as the oracle, states within 1e-8."""
+    r = smooth_recipe("c3", 16, precision=synth.FP64)
+    r.options.fnormtol = 1e-12
+    r.options.gmres_block = block
+    P = r.problem
+    ks, p = r.ks(), r.p0()
+    s = make_solver(rich, torch, P, ks, r.options)
+    s.set_state(dev(torch, p))
+    o = orc.Solver(P, r.options, ks)
+    po = p.copy()
+    for step in range(2):
+        sg = s.step(1)[0]
+        so = o.step(po)
+        assert sg["status"] == 0 and so["status"] == 0, (step, sg, so)
+        for f in ("newton_its", "jac_builds", "ls_backtracks"):
+            assert sg[f] == so[f], (step, f, sg[f], so[f])
+        pg = s.get_state().cpu().numpy()
+        err = np.linalg.norm(pg - po) / np.linalg.norm(po)
+        assert err <= 1e-8, (step, err, sg, so)
+
+
 @pytest.mark.parametrize("smoothed", [0, 1])
 def test_full_steps_mixed(rich, torch, orc, smoothed):
     r = smooth_recipe("c3", 24)
