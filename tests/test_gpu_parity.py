@@ -188,6 +188,32 @@ def test_gmres_parity(rich, torch, orc, block, restart, reorth, n, eta):
     assert np.linalg.norm(x - xo) <= 10 * r.options.eta * np.linalg.norm(xo)
 
 
+@pytest.mark.parametrize("block,maxit", [(1, 13), (5, 13), (6, 7), (4, 1)])
+def test_gmres_iteration_limit(rich, torch, orc, block, maxit):
+    """A solve stopped by the iteration limit (mid-round for the s-step
+    rounds): the same number of Arnoldi steps as the oracle, neither side
+    converged, and the same iterate -- GMRES's k-th iterate is the minimal
+    residual point of the same Krylov space whatever the Gram-Schmidt form."""
+    r = smooth_recipe("c3", 20, precision=synth.FP64)
+    r.options.gmres_block, r.options.gmres_maxit = block, maxit
+    r.options.eta = 1e-13  # not reached in maxit steps
+    P = r.problem
+    ks, p0 = r.ks(), r.p0()
+    s = make_solver(rich, torch, P, ks, r.options)
+    th = orc.theta(P, p0)
+    F = orc.residual(P, ks, p0, th)
+    s.assemble(dev(torch, p0))
+    x, its, rr, conv = s.gmres(dev(torch, -F))
+    x = x.cpu().numpy()
+    rp, col, val = s.export_csr(rich.WHICH_A, 0)
+    amg = orc.AMG(r.options, sp.csr_matrix((val, col, rp), shape=(P.n, P.n)))
+    J = orc.jacobian(P, ks, p0)
+    xo, conv_o, its_o, rr_o = orc.gmres(J, -F, amg, r.options.gmres_restart, r.options.eta, maxit)
+    assert not conv and not conv_o
+    assert its == its_o == maxit
+    assert np.linalg.norm(x - xo) <= 1e-8 * np.linalg.norm(xo), np.linalg.norm(x - xo) / np.linalg.norm(xo)
+
+
 @pytest.mark.parametrize("name,n,mean", [("c1", 12, None), ("c1", 16, None), ("c2", 20, None),
                                          ("c1", 16, synth.GEOMETRIC), ("c2", 16, synth.INTEGRAL)])
 def test_full_steps_fp64(rich, torch, orc, name, n, mean):
