@@ -554,3 +554,43 @@ def test_degenerate_grids_steps(rich, torch, orc, shape, dense_max):
         pg = s.get_state().cpu().numpy()
         assert np.linalg.norm(pg - po) <= 1e-8 * np.linalg.norm(po), (step, pg[:4], po[:4])
     assert s.levels() == 1
+
+
+@pytest.mark.parametrize("precision", [synth.FP64, synth.MIXED])
+def test_failure_paths_match_oracle(rich, torch, orc, precision):
+    """A non-finite head and a Newton iteration limit end the step with the
+    oracle's status, and a failed step leaves the previous level in place
+    (the error travels back through rich_step's return code and the step's
+    statistics)."""
+    from paper_2112_05051_amd import _lib
+    r = synth.recipe("c1", n=6)
+    r.options.precision = precision
+    P = r.problem
+    ks, p = r.ks(), r.p0()
+    bad = p.copy()
+    bad[3] = np.nan
+    o = orc.Solver(P, r.options, ks)
+    assert o.step(bad.copy())["status"] == orc.NONFINITE
+    s = make_solver(rich, torch, P, ks, r.options)
+    s.set_state(dev(torch, bad))
+    with pytest.raises(rich.RichError) as e:
+        s.step(1)
+    assert e.value.status == _lib.NONFINITE
+    s.set_state(dev(torch, bad))
+    st = s.step(1, raise_on_error=False)[0]
+    assert st["status"] == _lib.NONFINITE
+    got = s.get_state().cpu().numpy()
+    assert np.array_equal(np.isnan(got), np.isnan(bad)) and np.array_equal(got[~np.isnan(bad)], bad[~np.isnan(bad)])
+    s.close()
+    # Newton iteration limit at an unreachable tolerance
+    r.options.max_newton = 1
+    r.options.fnormtol = 1e-30
+    o = orc.Solver(P, r.options, ks)
+    so = o.step(p.copy())
+    s = make_solver(rich, torch, P, ks, r.options)
+    s.set_state(dev(torch, p))
+    sg = s.step(1, raise_on_error=False)[0]
+    assert sg["status"] == so["status"], (sg, so)
+    if sg["status"] < 0:
+        assert np.array_equal(s.get_state().cpu().numpy(), p)
+    s.close()
