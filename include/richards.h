@@ -146,12 +146,12 @@ typedef struct rich_solver_opts {
                             larger values stall the coarsening where the storage term theta'/dt
                             dominates the diagonal) */
     int64_t amg_block;   /* rows per decoupled block of RICH_AGG_VMB, >= 1 (4096) */
-    int gmres_block;     /* Arnoldi vectors generated per Gram-Schmidt round of GMRES, 1..6.
+    int gmres_block;     /* Arnoldi vectors generated per Gram-Schmidt round of GMRES, 1..10 (10).
                             1: one vector per round (classical Gram-Schmidt, the second pass
                             governed by gmres_reorth).  s >= 2: s-step GMRES (Section 6's
                             right-preconditioned GMRES(m), the same Krylov space and minimal
-                            residual): s vectors of the shifted power basis
-                            q_{t+1} = (J M^{-1} - gmres_shift I) q_t are generated, then
+                            residual): s vectors of the shifted (Newton) power basis
+                            q_{t+1} = (J M^{-1} - sigma_t I) q_t are generated, then
                             orthogonalised against the basis and each other in one
                             block round (dots and Gram matrix in one pass, a Cholesky factor
                             of the Gram matrix's Pythagorean complement, one update pass), so
@@ -162,8 +162,13 @@ typedef struct rich_solver_opts {
                             convergence is tested after every column (the iteration count is
                             that of one-vector rounds), the next round's size is cut to the
                             steps the residual's decay predicts. */
-    double gmres_shift;  /* shift of the s-step power basis (> 0 keeps it well conditioned:
-                            the preconditioned spectrum lies near (0, 1]); 0.7 */
+    double gmres_shift;  /* centre c of the s-step basis shifts (0.65) */
+    double gmres_shift_span; /* half-width w >= 0 of the shift interval (0.55): sigma_0..sigma_{s-1}
+                            are the Leja points of [c - w, c + w] in Leja order (the first at
+                            c + w, each next one maximising the product of its distances to the
+                            earlier ones on a 4097-point grid); w = 0: every sigma_t = c.  Spread
+                            over the preconditioned spectrum (near (0, 1.3]) the shifts keep the
+                            basis of long rounds well conditioned. */
 } rich_solver_opts_t;
 #define RICH_SMOOTH_L1 0
 #define RICH_SMOOTH_MCGS 1

@@ -50,7 +50,7 @@ class Opts(C.Structure):
                 ("aux_dflux", C.c_int), ("amg_refresh", C.c_int), ("amg_smoothed", C.c_int),
                 ("tile_kz", C.c_int), ("smoother", C.c_int), ("amg_aggregation", C.c_int),
                 ("amg_theta", C.c_double), ("amg_block", C.c_int64),
-                ("gmres_block", C.c_int), ("gmres_shift", C.c_double)]
+                ("gmres_block", C.c_int), ("gmres_shift", C.c_double), ("gmres_shift_span", C.c_double)]
 
 
 class StepStats(C.Structure):

@@ -274,8 +274,8 @@ rich_status launch_st_sweeps(const Phys &P, const T *M4, const T *invd, const TB
 // ------------------------------------------------------------ vector kernels
 constexpr int RED_BLOCKS = 1024;   // fixed block count of every reduction (deterministic order)
 constexpr int RED_THREADS = 256;
-constexpr int GMRES_BLOCK_MAX = 6; // largest round of the s-step GMRES (register budget of its dot kernel)
-constexpr int BLK_BUF = 512;       // doubles per s-step result or coefficient buffer (>= 65 * 6 + 36)
+constexpr int GMRES_BLOCK_MAX = 10; // largest round of the s-step GMRES
+constexpr int BLK_BUF = 1024;       // doubles per s-step result or coefficient buffer (>= 65 * 10 + 100)
 
 // Basis vectors are stored unnormalised: the true V_i is vs[i] * stored V_i.
 // out[i] = V_i . w (i < k), out[k] = w . w; reduced in fixed order.

@@ -303,6 +303,120 @@ __global__ void __launch_bounds__(RED_THREADS) k_block_dot_small(const double *_
     block_dot_body<S, GV>(V, ldv, nv, gram, Q, n, partial, mout);
 }
 
+// The same sums for rounds of 7..10 vectors, with the Gram matrix spread
+// over the four waves (entry t by wave t mod 4) so that the accumulators of
+// GV <= 6 basis vectors stay within the register budget.  Same output layout.
+// The wave index is a template argument: each wave's Gram entries are fixed at
+// compile time and their accumulators stay in registers.
+template <int S, int GV, int G>
+__device__ __forceinline__ void block_dot_wave_wide(const double *__restrict__ V, int64_t ldv, int nv, bool gram,
+                                                    const double *__restrict__ Q, int64_t n,
+                                                    double *__restrict__ partial, int mout) {
+    constexpr int NG = S * (S + 1) / 2;
+    constexpr int NW = RED_THREADS / WAVE;
+    constexpr int NGW = (NG - G + NW - 1) / NW;  // Gram entries of this wave: t = G, G + NW, ...
+    typedef double d2v __attribute__((ext_vector_type(2)));
+    const int lane = threadIdx.x % WAVE;
+    constexpr int i0 = G * GV;
+    const int ng = nv - i0 < GV ? (nv - i0 > 0 ? nv - i0 : 0) : GV;
+    double acc[GV][S], gm[NGW > 0 ? NGW : 1];
+#pragma unroll
+    for (int i = 0; i < GV; i++)
+#pragma unroll
+        for (int k = 0; k < S; k++) acc[i][k] = 0.0;
+#pragma unroll
+    for (int u = 0; u < NGW; u++) gm[u] = 0.0;
+    const int64_t n2 = n >> 1;
+    for (int64_t c = (int64_t)blockIdx.x * WAVE + lane; c < n2; c += (int64_t)gridDim.x * WAVE) {
+        d2v q[S], v[GV];
+#pragma unroll
+        for (int k = 0; k < S; k++) q[k] = reinterpret_cast<const d2v *>(Q + (size_t)k * ldv)[c];
+#pragma unroll
+        for (int i = 0; i < GV; i++)
+            if (i < ng) v[i] = __builtin_nontemporal_load(reinterpret_cast<const d2v *>(V + (size_t)(i0 + i) * ldv) + c);
+#pragma unroll
+        for (int i = 0; i < GV; i++)
+            if (i < ng)
+#pragma unroll
+                for (int k = 0; k < S; k++) acc[i][k] += v[i].x * q[k].x + v[i].y * q[k].y;
+        if (gram) {
+#pragma unroll
+            for (int k = 0; k < S; k++)
+#pragma unroll
+                for (int l = k; l < S; l++) {
+                    const int t = k * S - k * (k - 1) / 2 + (l - k);  // row-major upper triangle
+                    if (t % NW == G) gm[t / NW] += q[k].x * q[l].x + q[k].y * q[l].y;
+                }
+        }
+    }
+    if ((n & 1) && blockIdx.x == 0 && lane == 0) {
+        double q[S];
+#pragma unroll
+        for (int k = 0; k < S; k++) q[k] = Q[(size_t)k * ldv + n - 1];
+#pragma unroll
+        for (int i = 0; i < GV; i++)
+            if (i < ng) {
+                const double vi = V[(size_t)(i0 + i) * ldv + n - 1];
+#pragma unroll
+                for (int k = 0; k < S; k++) acc[i][k] += vi * q[k];
+            }
+        if (gram) {
+#pragma unroll
+            for (int k = 0; k < S; k++)
+#pragma unroll
+                for (int l = k; l < S; l++) {
+                    const int t = k * S - k * (k - 1) / 2 + (l - k);
+                    if (t % NW == G) gm[t / NW] += q[k] * q[l];
+                }
+        }
+    }
+    double *out = partial + (size_t)blockIdx.x * mout;
+#pragma unroll
+    for (int i = 0; i < GV; i++)
+        if (i < ng)
+#pragma unroll
+            for (int k = 0; k < S; k++) {
+                const double r = wave_sum(acc[i][k]);
+                if (lane == 0) out[(i0 + i) * S + k] = r;
+            }
+    if (gram) {
+#pragma unroll
+        for (int u = 0; u < NGW; u++) {
+            const double r = wave_sum(gm[u]);
+            if (lane == 0) out[nv * S + G + u * NW] = r;
+        }
+    }
+}
+
+template <int S, int GV>
+__device__ __forceinline__ void block_dot_body_wide(const double *__restrict__ V, int64_t ldv, int nv, bool gram,
+                                                    const double *__restrict__ Q, int64_t n,
+                                                    double *__restrict__ partial, int mout) {
+    static_assert(RED_THREADS / WAVE == 4, "four waves per block");
+    switch (threadIdx.x / WAVE) {
+    case 0: block_dot_wave_wide<S, GV, 0>(V, ldv, nv, gram, Q, n, partial, mout); break;
+    case 1: block_dot_wave_wide<S, GV, 1>(V, ldv, nv, gram, Q, n, partial, mout); break;
+    case 2: block_dot_wave_wide<S, GV, 2>(V, ldv, nv, gram, Q, n, partial, mout); break;
+    default: block_dot_wave_wide<S, GV, 3>(V, ldv, nv, gram, Q, n, partial, mout); break;
+    }
+}
+
+template <int S, int GV>
+__global__ void __launch_bounds__(RED_THREADS) RED_WPE_ATTR k_block_dot_wide(const double *__restrict__ V,
+                                                                           int64_t ldv, int nv, bool gram,
+                                                                           const double *__restrict__ Q, int64_t n,
+                                                                           double *__restrict__ partial, int mout) {
+    block_dot_body_wide<S, GV>(V, ldv, nv, gram, Q, n, partial, mout);
+}
+
+template <int S, int GV>
+__global__ void __launch_bounds__(RED_THREADS) k_block_dot_wide_small(const double *__restrict__ V, int64_t ldv,
+                                                                      int nv, bool gram,
+                                                                      const double *__restrict__ Q, int64_t n,
+                                                                      double *__restrict__ partial, int mout) {
+    block_dot_body_wide<S, GV>(V, ldv, nv, gram, Q, n, partial, mout);
+}
+
 // out_c[j] = vs[j / S] * sum_b partial[b*m + j] for j < nvs (the C entries),
 // out_g[j - nvs] = sum_b partial[b*m + j] after (the Gram matrix); b ascending.
 __global__ void k_reduce_block(const double *__restrict__ partial, int m, int nb, int S, int nvs,
@@ -344,14 +458,17 @@ __device__ __forceinline__ void block_update_body(const double *__restrict__ V, 
         d2v q[S];
 #pragma unroll
         for (int k = 0; k < S; k++) q[k] = reinterpret_cast<const d2v *>(Q + (size_t)k * ldv)[c];
+        // CH basis values in flight at a time (fewer for wide rounds: their
+        // coefficients of a chunk are held in registers too)
+        constexpr int CH = S <= 6 ? 8 : 4;
         int i = 0;
-        for (; i + 8 <= nv; i += 8) {
-            d2v v[8];
+        for (; i + CH <= nv; i += CH) {
+            d2v v[CH];
 #pragma unroll
-            for (int u = 0; u < 8; u++)
+            for (int u = 0; u < CH; u++)
                 v[u] = __builtin_nontemporal_load(reinterpret_cast<const d2v *>(V + (size_t)(i + u) * ldv) + c);
 #pragma unroll
-            for (int u = 0; u < 8; u++)
+            for (int u = 0; u < CH; u++)
 #pragma unroll
                 for (int k = 0; k < S; k++) {
                     const double a = cs[(i + u) * S + k];
@@ -668,9 +785,11 @@ rich_status launch_block_dot(const double *V, int64_t ldv, int nv, const double 
                              int64_t n, double *partial, double *out, hipStream_t s) {
     if (nv < 1 || nv > KMAX || S < 1 || S > GMRES_BLOCK_MAX || (ldv & 1)) return RICH_EINVAL;
     const bool wide = n >= RED_WIDE_MIN;
+    // basis vectors per launch: 4 waves x 8, x 6 for rounds of 7..10
+    const int chunk = S <= 6 ? BLK_VCHUNK : 24;
     double *pc = partial;
-    for (int i0 = 0; i0 < nv; i0 += BLK_VCHUNK) {
-        const int nc = nv - i0 < BLK_VCHUNK ? nv - i0 : BLK_VCHUNK;
+    for (int i0 = 0; i0 < nv; i0 += chunk) {
+        const int nc = nv - i0 < chunk ? nv - i0 : chunk;
         const bool gram = i0 == 0;
         const int gv = (nc + 3) / 4;
         const int mout = nc * S + (gram ? S * (S + 1) / 2 : 0);
@@ -685,6 +804,17 @@ rich_status launch_block_dot(const double *V, int64_t ldv, int nv, const double 
         break;
 #define XS(SS) XG(SS, 1) XG(SS, 2) XG(SS, 3) XG(SS, 4) XG(SS, 5) XG(SS, 6) XG(SS, 7) XG(SS, 8)
             XS(1) XS(2) XS(3) XS(4) XS(5) XS(6)
+#undef XS
+#undef XG
+#define XG(SS, G)                                                                                              \
+    case SS * 16 + G:                                                                                          \
+        if (wide)                                                                                              \
+            k_block_dot_wide<SS, G><<<RED_BLOCKS, RED_THREADS, 0, s>>>(Vc, ldv, nc, gram, Q, n, pc, mout);       \
+        else                                                                                                   \
+            k_block_dot_wide_small<SS, G><<<RED_BLOCKS, RED_THREADS, 0, s>>>(Vc, ldv, nc, gram, Q, n, pc, mout); \
+        break;
+#define XS(SS) XG(SS, 1) XG(SS, 2) XG(SS, 3) XG(SS, 4) XG(SS, 5) XG(SS, 6)
+            XS(7) XS(8) XS(9) XS(10)
 #undef XS
 #undef XG
         default: return RICH_EINVAL;
@@ -710,7 +840,7 @@ rich_status launch_block_update(const double *V, int64_t ldv, int nv, const doub
         else                                                                                              \
             k_block_update_small<SS><<<RED_BLOCKS, RED_THREADS, 0, s>>>(V, ldv, nv, vs, cf, Q, n);        \
         break;
-        X(1) X(2) X(3) X(4) X(5) X(6)
+        X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10)
 #undef X
     default: return RICH_EINVAL;
     }

@@ -61,6 +61,7 @@ struct rich_ctx {
     double *hbuf = nullptr;    // device Arnoldi results, one row of (m + 4) per iteration
     double *hall = nullptr;    // pinned host mirror of hbuf
     double *dblk = nullptr;    // s-step rounds: block dots [0, BLK_BUF), coefficients [BLK_BUF, 2 BLK_BUF)
+    double shifts[GMRES_BLOCK_MAX] = {};  // s-step basis shifts sigma_t, in the order they are used
     double *hblk = nullptr;    // pinned host mirror of dblk
     double *bsc = nullptr;     // N: scaled right-hand side for a one-level hierarchy
     std::vector<hipEvent_t> iter_ev;  // one per Arnoldi iteration
@@ -879,8 +880,9 @@ rich_status gmres_classic(rich_ctx *h, const double *b, double *x, int *its_out,
 // The same restarted right-preconditioned GMRES(m) with the Arnoldi vectors
 // generated s at a time (gmres_block = s >= 2).  A round starting at basis
 // vector v_j0 applies the preconditioned operator s times to the shifted
-// power basis q_0 = v_j0, q_{t+1} = (J M^{-1} - sigma I) q_t (the shift is
-// fused into the J product), then orthogonalises q_1..q_s against
+// (Newton) power basis q_0 = v_j0, q_{t+1} = (J M^{-1} - sigma_t I) q_t (the
+// shifts Leja points of an interval over the preconditioned spectrum, fused
+// into the J product), then orthogonalises q_1..q_s against
 // v_0..v_j0 and each other in one block round: one pass gives C = V^T Q and
 // the Gram matrix G = Q^T Q, the host factors the Pythagorean complement
 // G - C^T C = R^T R (Cholesky), and one pass writes (Q - V C) R^{-1}, the
@@ -890,7 +892,7 @@ rich_status gmres_classic(rich_ctx *h, const double *b, double *x, int *its_out,
 // instead.  The Hessenberg columns j0..j0+s-1 follow from the coordinates of
 // the q_t in the new basis: with S the coordinates of q_0..q_s and H_prev
 // the earlier columns, J M^{-1} [v_j0..v_{j0+s-1}] =
-// (S_{:,1..s} + sigma S_{:,0..s-1} - H_prev S_{0..j0-1, 0..s-1}) Sb^{-1},
+// (S_{:,1..s} + S_{:,0..s-1} diag(sigma) - H_prev S_{0..j0-1, 0..s-1}) Sb^{-1},
 // Sb the (upper triangular) rows j0..j0+s-1 of S's first s columns.  The
 // residual estimate is tested after every column, as one vector at a time
 // would, and the next round is cut to the steps the estimate's decay over
@@ -899,7 +901,7 @@ rich_status gmres_sstep(rich_ctx *h, const double *b, double *x, int *its_out, d
                         bool *conv_out) {
     const int64_t N = h->N, ld = h->ldv;
     const int m = h->m, S = h->O.gmres_block;
-    const double sig = h->O.gmres_shift, eta = h->O.eta, reorth = h->O.gmres_reorth;
+    const double *sig = h->shifts, eta = h->O.eta, reorth = h->O.gmres_reorth;
     hipStream_t s = h->s;
     // Hr: the cycle's Hessenberg matrix as computed; Hm: its rotated copy
     std::vector<double> Hr((size_t)(m + 1) * m), Hm((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
@@ -1013,7 +1015,7 @@ rich_status gmres_sstep(rich_ctx *h, const double *b, double *x, int *its_out, d
             RICH_TRY(launch_fill_f64(h->vs + nv, 1.0, ss, s));
             for (int t = 0; t < ss; t++)
                 RICH_TRY(prec_product(h, h->V + (size_t)(j0 + t) * ld, h->vs + j0 + t,
-                                      h->V + (size_t)(j0 + t + 1) * ld, sig));
+                                      h->V + (size_t)(j0 + t + 1) * ld, sig[t]));
             const int nout = block_partial_size(nv, ss);
             RICH_TRY(timed(h, RICH_K_BLOCK_DOT, 8.0 * N * (nv + ss), [&] {
                 return launch_block_dot(h->V, ld, nv, h->vs, Q, ss, N, h->partial, dout, s);
@@ -1119,7 +1121,7 @@ rich_status gmres_sstep(rich_ctx *h, const double *b, double *x, int *its_out, d
             }
             for (int r = 0; r < K; r++)
                 for (int c = 0; c < ss; c++) {
-                    double v = Sh[(size_t)r * W1 + c + 1] + sig * Sh[(size_t)r * W1 + c];
+                    double v = Sh[(size_t)r * W1 + c + 1] + sig[c] * Sh[(size_t)r * W1 + c];
                     for (int q = (r > 0 ? r - 1 : 0); q < j0; q++) v -= Hr[(size_t)r * m + q] * Sh[(size_t)q * W1 + c];
                     X[(size_t)r * ss + c] = v;
                 }
@@ -1571,9 +1573,37 @@ rich_status validate(const rich_problem_t *P, const rich_solver_opts_t *O) {
     if (O->amg_aggregation == RICH_AGG_VMB && (!(O->amg_theta >= 0.0 && O->amg_theta <= 1.0) || O->amg_block < 1))
         return RICH_EINVAL;
     if (!(O->gmres_reorth >= 0.0 && O->gmres_reorth < 1.0)) return RICH_EINVAL;
-    if (O->gmres_block < 1 || O->gmres_block > GMRES_BLOCK_MAX || !std::isfinite(O->gmres_shift)) return RICH_EINVAL;
+    if (O->gmres_block < 1 || O->gmres_block > GMRES_BLOCK_MAX || !std::isfinite(O->gmres_shift) ||
+        !(O->gmres_shift_span >= 0.0) || !std::isfinite(O->gmres_shift_span))
+        return RICH_EINVAL;
     if (!(O->eta > 0) || !(O->fnormtol > 0) || O->max_newton < 1 || O->msbset < 1) return RICH_EINVAL;
     return RICH_OK;
+}
+
+// Leja points of [a, b] in Leja order: the first at b, each next one the point
+// of a 4097-point grid on [a, b] that maximises the product of its distances
+// to the earlier points (summed logarithms; the first maximum on ties).  The
+// s-step basis shifts: their products stay balanced over the interval for
+// every prefix, which keeps the power basis of a round well conditioned.
+// b <= a gives k copies of a.
+void leja_points(double a, double b, int k, double *out) {
+    constexpr int NPT = 4097;
+    for (int t = 0; t < k; t++) out[t] = b > a ? b : a;
+    if (!(b > a)) return;
+    std::vector<double> lsum(NPT, 0.0);
+    for (int t = 1; t < k; t++) {
+        int best = 0;
+        double bv = -INFINITY;
+        for (int g = 0; g < NPT; g++) {
+            const double x = a + (b - a) * g / (NPT - 1);
+            lsum[g] += std::log(std::fabs(x - out[t - 1]) + 1e-300);
+            if (lsum[g] > bv) {
+                bv = lsum[g];
+                best = g;
+            }
+        }
+        out[t] = a + (b - a) * best / (NPT - 1);
+    }
 }
 
 // Gauss-Legendre nodes and weights on [0, 1]: roots of the Legendre
@@ -1698,6 +1728,8 @@ rich_status rich_create(const rich_problem_t *prob, const rich_solver_opts_t *op
     h->s = (hipStream_t)hip_stream;
     h->mixed = opts->precision == RICH_PREC_MIXED;
     h->m = opts->gmres_restart;
+    leja_points(opts->gmres_shift - opts->gmres_shift_span, opts->gmres_shift + opts->gmres_shift_span,
+                GMRES_BLOCK_MAX, h->shifts);
     int64_t N = h->N;
     rich_status st = RICH_OK;
     auto G = [&](auto **p, size_t n) {

@@ -88,8 +88,9 @@ class Options:
     amg_aggregation: int = 0            # 0: pairwise matching sweeps; 1: decoupled greedy (VMB) aggregation
     amg_theta: float = 0.0              # strength threshold of the greedy aggregation (0: every coupling)
     amg_block: int = 4096               # rows per decoupled block of the greedy aggregation
-    gmres_block: int = 5                # Arnoldi vectors per Gram-Schmidt round (1: classical; 2..6: s-step)
-    gmres_shift: float = 0.7            # shift of the s-step power basis
+    gmres_block: int = 10               # Arnoldi vectors per Gram-Schmidt round (1: classical; 2..10: s-step)
+    gmres_shift: float = 0.65           # centre of the s-step basis shifts
+    gmres_shift_span: float = 0.55      # half-width of the shift interval (Leja points; 0: one shift)
 
 
 @dataclass

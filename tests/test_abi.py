@@ -91,9 +91,10 @@ def test_option_domains_without_gpu():
     for kw, ok in (({"smoother": 1}, True), ({"smoother": 2}, False), ({"amg_aggregation": 1}, True),
                    ({"amg_aggregation": 2}, False), ({"amg_aggregation": 1, "amg_theta": 1.5}, False),
                    ({"amg_aggregation": 1, "amg_block": 0}, False), ({"amg_aggregation": 1, "amg_theta": 0.25}, True),
-                   ({"gmres_block": 0}, False), ({"gmres_block": 1}, True), ({"gmres_block": 6}, True),
-                   ({"gmres_block": 7}, False), ({"gmres_shift": float("nan")}, False),
-                   ({"gmres_shift": 0.0}, True)):
+                   ({"gmres_block": 0}, False), ({"gmres_block": 1}, True), ({"gmres_block": 10}, True),
+                   ({"gmres_block": 11}, False), ({"gmres_shift": float("nan")}, False),
+                   ({"gmres_shift": 0.0}, True), ({"gmres_shift_span": -0.1}, False),
+                   ({"gmres_shift_span": 0.0}, True), ({"gmres_shift_span": float("inf")}, False)):
         O = synth.Options(**kw)
         rc = lib.rich_query_bytes(C.byref(_lib.make_problem(P)), C.byref(_lib.make_opts(O)), C.byref(b))
         assert (rc == 0) == ok, (kw, rc)

@@ -155,16 +155,21 @@ def test_hierarchy_bitexact(rich, torch, orc, mean, smoothed):
 
 
 # gmres_block 1: one Arnoldi vector per Gram-Schmidt round; >= 2: s-step rounds
-# (shifted power basis, one block round), also where the restart length cuts a
-# round short, on an odd number of rows (the kernels' row-pair tail), and with
-# every round redone vector by vector (gmres_reorth close to 1 rejects each
-# Cholesky factor), at the default tolerance and at one that needs restarts.
-@pytest.mark.parametrize("block,restart,reorth,n,eta", [
-    (1, 30, 0.01, 24, 1e-6), (5, 30, 0.01, 24, 1e-6), (2, 30, 0.01, 23, 1e-6), (6, 7, 0.01, 23, 1e-6),
-    (4, 30, 0.999, 24, 1e-6), (5, 30, 0.01, 24, 1e-10), (3, 10, 0.01, 21, 1e-10)])
-def test_gmres_parity(rich, torch, orc, block, restart, reorth, n, eta):
+# (shifted power basis, one block round; 7..10 take the wide-round kernels),
+# also where the restart length cuts a round short, on an odd number of rows
+# (the kernels' row-pair tail), with every round redone vector by vector
+# (gmres_reorth close to 1 rejects each Cholesky factor), with one shift
+# instead of the Leja set, at the default tolerance and at one that needs
+# restarts.
+@pytest.mark.parametrize("block,restart,reorth,n,eta,span", [
+    (1, 30, 0.01, 24, 1e-6, 0.55), (5, 30, 0.01, 24, 1e-6, 0.55), (2, 30, 0.01, 23, 1e-6, 0.55),
+    (6, 7, 0.01, 23, 1e-6, 0.55), (4, 30, 0.999, 24, 1e-6, 0.55), (5, 30, 0.01, 24, 1e-10, 0.55),
+    (3, 10, 0.01, 21, 1e-10, 0.55), (5, 30, 0.01, 24, 1e-6, 0.0), (8, 30, 0.01, 23, 1e-6, 0.55),
+    (10, 30, 0.01, 24, 1e-10, 0.55), (9, 30, 0.999, 21, 1e-6, 0.55)])
+def test_gmres_parity(rich, torch, orc, block, restart, reorth, n, eta, span):
     r = smooth_recipe("c3", n, precision=synth.FP64)
     r.options.gmres_block, r.options.gmres_restart, r.options.gmres_reorth = block, restart, reorth
+    r.options.gmres_shift_span = span
     r.options.eta = eta
     r.options.gmres_maxit = 400
     P = r.problem
@@ -188,7 +193,7 @@ def test_gmres_parity(rich, torch, orc, block, restart, reorth, n, eta):
     assert np.linalg.norm(x - xo) <= 10 * r.options.eta * np.linalg.norm(xo)
 
 
-@pytest.mark.parametrize("block,maxit", [(1, 13), (5, 13), (6, 7), (4, 1)])
+@pytest.mark.parametrize("block,maxit", [(1, 13), (5, 13), (6, 7), (4, 1), (10, 13)])
 def test_gmres_iteration_limit(rich, torch, orc, block, maxit):
     """A solve stopped by the iteration limit (mid-round for the s-step
     rounds): the same number of Arnoldi steps as the oracle, neither side
@@ -237,12 +242,12 @@ def test_full_steps_fp64(rich, torch, orc, name, n, mean):
         assert err <= 1e-8, (step, err, sg, so)
 
 
-@pytest.mark.parametrize("block", [1, 3, 6])
+@pytest.mark.parametrize("block", [1, 3, 5, 6, 8])
 def test_full_steps_gmres_rounds(rich, torch, orc, block):
     """Two FP64 steps of the rough c3 statistics at 16^3 with one-vector
-    GMRES rounds and with s-step rounds of 3 and 6 vectors (the default is
-    5, covered above): the same Newton iterations, Jacobian builds and
-    backtracks as the oracle, states within 1e-8."""
+    GMRES rounds and with s-step rounds of 3, 5, 6 and 8 vectors (the
+    default of 10 is covered above): the same Newton iterations, Jacobian
+    builds and backtracks as the oracle, states within 1e-8."""
     r = smooth_recipe("c3", 16, precision=synth.FP64)
     r.options.fnormtol = 1e-12
     r.options.gmres_block = block
