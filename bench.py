@@ -599,6 +599,9 @@ def main():
         "run_incl_warmup_s": mixed["t_warm"] + mixed["t_timed"],
         "newton_its": sum(s["newton_its"] for s in mixed["stats"]),
         "gmres_its": sum(s["gmres_its"] for s in mixed["stats"]),
+        # s-step block rounds, and those finished vector by vector
+        "gmres_rounds": sum(s["gmres_rounds"] for s in mixed["stats"]),
+        "gmres_redone": sum(s["gmres_redone"] for s in mixed["stats"]),
         "jac_builds": sum(s["jac_builds"] for s in mixed["stats"]),
         "levels": mixed["stats"][-1]["levels"] if mixed["stats"] else None,
         "opc": mixed["stats"][-1]["opc"] if mixed["stats"] else None,

@@ -156,19 +156,22 @@ typedef struct rich_solver_opts {
                             block round (dots and Gram matrix in one pass, a Cholesky factor
                             of the Gram matrix's Pythagorean complement, one update pass), so
                             the basis is read twice per s vectors instead of twice per vector.
-                            A round whose Cholesky factor loses more than gmres_reorth of a
-                            vector's norm is redone vector by vector with two classical
-                            passes.  The Hessenberg matrix follows from the basis change;
+                            From the first vector whose Cholesky pivot keeps less than
+                            gmres_reorth of its norm, a round is finished vector by vector
+                            with two classical passes, and the following rounds are capped at
+                            the vectors before it (at least one; every 8 whole rounds in a row
+                            raise the cap by one, up to s).  The Hessenberg matrix follows from the
+                            basis change;
                             convergence is tested after every column (the iteration count is
                             that of one-vector rounds), the next round's size is cut to the
                             steps the residual's decay predicts. */
     double gmres_shift;  /* centre c of the s-step basis shifts (0.65) */
     double gmres_shift_span; /* half-width w >= 0 of the shift interval (0.55): sigma_0..sigma_{s-1}
-                            are the Leja points of [c - w, c + w] in Leja order (the first at
-                            c + w, each next one maximising the product of its distances to the
-                            earlier ones on a 4097-point grid); w = 0: every sigma_t = c.  Spread
-                            over the preconditioned spectrum (near (0, 1.3]) the shifts keep the
-                            basis of long rounds well conditioned. */
+                            are the Leja points of [c - w, c + w] in Leja order (the end of
+                            larger modulus first, each next one maximising the product of its
+                            distances to the earlier ones on a 4097-point grid); w = 0: every
+                            sigma_t = c.  Spread over the spectrum of J M^{-1} (near (0, 1.3])
+                            the shifts keep the basis of long rounds well conditioned. */
 } rich_solver_opts_t;
 #define RICH_SMOOTH_L1 0
 #define RICH_SMOOTH_MCGS 1
@@ -189,6 +192,9 @@ typedef struct rich_solver_opts {
 typedef struct rich_step_stats {
     int status;
     int newton_its, jac_builds, gmres_its, ls_backtracks, amg_setups, linsolve_fails, levels;
+    int gmres_rounds;     /* s-step block rounds (gmres_block >= 2) */
+    int gmres_redone;     /* of which finished vector by vector from the first vector whose
+                             Cholesky pivot kept less than gmres_reorth of its norm */
     double fnorm_inf;     /* ||Phi||_inf at the accepted state */
     double mass_residual; /* dt * sum_c Phi_c at the accepted state */
     double min_lambda;    /* smallest accepted line-search step */

@@ -57,6 +57,7 @@ class StepStats(C.Structure):
     _fields_ = [("status", C.c_int), ("newton_its", C.c_int), ("jac_builds", C.c_int),
                 ("gmres_its", C.c_int), ("ls_backtracks", C.c_int), ("amg_setups", C.c_int),
                 ("linsolve_fails", C.c_int), ("levels", C.c_int),
+                ("gmres_rounds", C.c_int), ("gmres_redone", C.c_int),
                 ("fnorm_inf", C.c_double), ("mass_residual", C.c_double),
                 ("min_lambda", C.c_double), ("opc", C.c_double),
                 ("t_feval", C.c_double), ("t_jac", C.c_double), ("t_aux", C.c_double),

@@ -13,6 +13,7 @@
 #include <thread>
 
 #include "common.hpp"
+#include "krylov_host.hpp"
 
 namespace rich {
 
@@ -62,6 +63,8 @@ struct rich_ctx {
     double *hall = nullptr;    // pinned host mirror of hbuf
     double *dblk = nullptr;    // s-step rounds: block dots [0, BLK_BUF), coefficients [BLK_BUF, 2 BLK_BUF)
     double shifts[GMRES_BLOCK_MAX] = {};  // s-step basis shifts sigma_t, in the order they are used
+    int scap = 1;                          // s-step round size cap (gmres_block at first)
+    int sgood = 0;                         // rounds taken whole since the cap last changed
     double *hblk = nullptr;    // pinned host mirror of dblk
     double *bsc = nullptr;     // N: scaled right-hand side for a one-level hierarchy
     std::vector<hipEvent_t> iter_ev;  // one per Arnoldi iteration
@@ -881,22 +884,26 @@ rich_status gmres_classic(rich_ctx *h, const double *b, double *x, int *its_out,
 // generated s at a time (gmres_block = s >= 2).  A round starting at basis
 // vector v_j0 applies the preconditioned operator s times to the shifted
 // (Newton) power basis q_0 = v_j0, q_{t+1} = (J M^{-1} - sigma_t I) q_t (the
-// shifts Leja points of an interval over the preconditioned spectrum, fused
-// into the J product), then orthogonalises q_1..q_s against
+// shift term fused into the J product), then orthogonalises q_1..q_s against
 // v_0..v_j0 and each other in one block round: one pass gives C = V^T Q and
 // the Gram matrix G = Q^T Q, the host factors the Pythagorean complement
 // G - C^T C = R^T R (Cholesky), and one pass writes (Q - V C) R^{-1}, the
-// next s orthonormal basis vectors.  A round in which some vector keeps less
-// than gmres_reorth of its norm, or whose complement is not positive
-// definite, is orthogonalised vector by vector with two classical passes
-// instead.  The Hessenberg columns j0..j0+s-1 follow from the coordinates of
+// next s orthonormal basis vectors.  The vectors before the first whose
+// pivot keeps less than gmres_reorth of its norm (or is not positive) are
+// taken from the block round; that one and the rest are orthogonalised
+// vector by vector with two classical passes.  The Hessenberg columns j0..j0+s-1 follow from the coordinates of
 // the q_t in the new basis: with S the coordinates of q_0..q_s and H_prev
 // the earlier columns, J M^{-1} [v_j0..v_{j0+s-1}] =
 // (S_{:,1..s} + S_{:,0..s-1} diag(sigma) - H_prev S_{0..j0-1, 0..s-1}) Sb^{-1},
 // Sb the (upper triangular) rows j0..j0+s-1 of S's first s columns.  The
 // residual estimate is tested after every column, as one vector at a time
 // would, and the next round is cut to the steps the estimate's decay over
-// the last round predicts.
+// the last round predicts.  The shifts, Leja points of an interval over
+// the spectrum of J M^{-1}, keep the basis of long rounds well conditioned.
+// A round finished vector by vector from its (a+1)-th vector caps the next
+// rounds at max(a, 1) vectors; every SCAP_GROW rounds in a row taken whole
+// raise the cap by one, up to s (the cap is kept from call to call).
+constexpr int SCAP_GROW = 8;
 rich_status gmres_sstep(rich_ctx *h, const double *b, double *x, int *its_out, double *relres_out,
                         bool *conv_out) {
     const int64_t N = h->N, ld = h->ldv;
@@ -1007,7 +1014,7 @@ rich_status gmres_sstep(rich_ctx *h, const double *b, double *x, int *its_out, d
             return RICH_OK;
         };
         while (!stop && j0 < m && total < h->O.gmres_maxit) {
-            int ss = std::min(std::min(ss_next, m - j0), h->O.gmres_maxit - total);
+            int ss = std::min(std::min(std::min(ss_next, h->scap), m - j0), h->O.gmres_maxit - total);
             const int nv = j0 + 1;
             double *Q = h->V + (size_t)nv * ld;
             const double g_start = std::fabs(g[j0]);
@@ -1037,15 +1044,18 @@ rich_status gmres_sstep(rich_ctx *h, const double *b, double *x, int *its_out, d
             for (int t = 0; t < nv * ss; t++) C[t] = hout[t];
             for (int a = 0, t = nv * ss; a < ss; a++)
                 for (int c = a; c < ss; c++, t++) Gm[a * ss + c] = Gm[c * ss + a] = hout[t];
-            bool ok = true, overflow = false;
-            for (int a = 0; a < ss && ok; a++) {
+            // Cholesky factor of the complement, pivot by pivot: vectors 0..nok-1
+            // keep more than gmres_reorth of their norm
+            int nok = ss;
+            bool overflow = false;
+            for (int a = 0; a < ss && nok == ss; a++) {
                 for (int c = a; c < ss; c++) {
                     double pac = Gm[a * ss + c];
                     for (int i = 0; i < nv; i++) pac -= C[i * ss + a] * C[i * ss + c];
                     for (int r = 0; r < a; r++) pac -= R[r * ss + a] * R[r * ss + c];
                     if (c == a) {
                         if (!(pac > 0.0) || !(pac > reorth * reorth * Gm[a * ss + a])) {
-                            ok = false;
+                            nok = a;
                             break;
                         }
                         R[a * ss + a] = std::sqrt(pac);
@@ -1054,28 +1064,45 @@ rich_status gmres_sstep(rich_ctx *h, const double *b, double *x, int *its_out, d
                     }
                 }
             }
-            if (ok) {
-                // coefficients: C, then R^{-1} (upper triangular)
-                for (int t = 0; t < nv * ss; t++) hcf[t] = C[t];
-                double *ri = hcf + nv * ss;
-                for (int t = 0; t < ss * ss; t++) ri[t] = 0.0;
-                for (int c = 0; c < ss; c++) {
-                    ri[c * ss + c] = 1.0 / R[c * ss + c];
+            if (h->cur) {
+                h->cur->gmres_rounds++;
+                if (nok < ss) h->cur->gmres_redone++;
+            }
+            if (nok < ss) {
+                h->scap = std::max(nok, 1);
+                h->sgood = 0;
+            } else if (++h->sgood >= SCAP_GROW && h->scap < S) {
+                h->scap++;
+                h->sgood = 0;
+            }
+            if (nok > 0) {
+                // the leading nok vectors in one block update; coefficients: C's
+                // first nok columns, then the inverse of R's leading block
+                for (int i = 0; i < nv; i++)
+                    for (int t = 0; t < nok; t++) hcf[i * nok + t] = C[i * ss + t];
+                double *ri = hcf + nv * nok;
+                for (int t = 0; t < nok * nok; t++) ri[t] = 0.0;
+                for (int c = 0; c < nok; c++) {
+                    ri[c * nok + c] = 1.0 / R[c * ss + c];
                     for (int a = c - 1; a >= 0; a--) {
                         double acc = 0.0;
-                        for (int r = a + 1; r <= c; r++) acc += R[a * ss + r] * ri[r * ss + c];
-                        ri[a * ss + c] = -acc / R[a * ss + a];
+                        for (int r = a + 1; r <= c; r++) acc += R[a * ss + r] * ri[r * nok + c];
+                        ri[a * nok + c] = -acc / R[a * ss + a];
                     }
                 }
-                HIP_TRY(hipMemcpyAsync(dcf, hcf, (nv * ss + ss * ss) * sizeof(double), hipMemcpyHostToDevice, s));
-                RICH_TRY(timed(h, RICH_K_BLOCK_UPDATE, 8.0 * N * (nv + 2 * ss), [&] {
-                    return launch_block_update(h->V, ld, nv, h->vs, dcf, Q, ss, N, s);
+                HIP_TRY(hipMemcpyAsync(dcf, hcf, (nv * nok + nok * nok) * sizeof(double), hipMemcpyHostToDevice, s));
+                RICH_TRY(timed(h, RICH_K_BLOCK_UPDATE, 8.0 * N * (nv + 2 * nok), [&] {
+                    return launch_block_update(h->V, ld, nv, h->vs, dcf, Q, nok, N, s);
                 }));
-            } else {
-                // vector by vector: two classical passes against everything before it
-                std::fill(C.begin(), C.end(), 0.0);
-                std::fill(R.begin(), R.end(), 0.0);
-                for (int t = 0; t < ss; t++) {
+            }
+            if (nok < ss) {
+                // the rest vector by vector: two classical passes against
+                // everything before it (the block's new vectors included)
+                for (int t = nok; t < ss; t++) {
+                    for (int i = 0; i < nv; i++) C[i * sw + t] = 0.0;
+                    for (int r = 0; r < ss; r++) R[r * sw + t] = 0.0;
+                }
+                for (int t = nok; t < ss; t++) {
                     const int slot = nv + t;
                     double *w = h->V + (size_t)slot * ld;
                     double ww = 0.0;
@@ -1580,32 +1607,6 @@ rich_status validate(const rich_problem_t *P, const rich_solver_opts_t *O) {
     return RICH_OK;
 }
 
-// Leja points of [a, b] in Leja order: the first at b, each next one the point
-// of a 4097-point grid on [a, b] that maximises the product of its distances
-// to the earlier points (summed logarithms; the first maximum on ties).  The
-// s-step basis shifts: their products stay balanced over the interval for
-// every prefix, which keeps the power basis of a round well conditioned.
-// b <= a gives k copies of a.
-void leja_points(double a, double b, int k, double *out) {
-    constexpr int NPT = 4097;
-    for (int t = 0; t < k; t++) out[t] = b > a ? b : a;
-    if (!(b > a)) return;
-    std::vector<double> lsum(NPT, 0.0);
-    for (int t = 1; t < k; t++) {
-        int best = 0;
-        double bv = -INFINITY;
-        for (int g = 0; g < NPT; g++) {
-            const double x = a + (b - a) * g / (NPT - 1);
-            lsum[g] += std::log(std::fabs(x - out[t - 1]) + 1e-300);
-            if (lsum[g] > bv) {
-                bv = lsum[g];
-                best = g;
-            }
-        }
-        out[t] = a + (b - a) * best / (NPT - 1);
-    }
-}
-
 // Gauss-Legendre nodes and weights on [0, 1]: roots of the Legendre
 // polynomial P_n by Newton's method (three-term recurrence, cosine starting
 // values), weights 2 / ((1 - x^2) P_n'(x)^2), both mapped from [-1, 1].
@@ -1730,6 +1731,7 @@ rich_status rich_create(const rich_problem_t *prob, const rich_solver_opts_t *op
     h->m = opts->gmres_restart;
     leja_points(opts->gmres_shift - opts->gmres_shift_span, opts->gmres_shift + opts->gmres_shift_span,
                 GMRES_BLOCK_MAX, h->shifts);
+    h->scap = opts->gmres_block;
     int64_t N = h->N;
     rich_status st = RICH_OK;
     auto G = [&](auto **p, size_t n) {
