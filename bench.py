@@ -151,11 +151,11 @@ def cpu_baseline(rec, ks, timed_stats, gmres_sample=5):
 
 
 # Kernel families of the per-kernel table: the library's timer name, the
-# rocprofv3 kernel-name prefix and the source file that defines the kernel.
+# rocprofv3 kernel-name prefixes and the source file that defines the kernels.
 FAMILIES = {
     "update": ("k_update_norm<", "la.hip"),
     "multidot": ("k_multidot<", "la.hip"),
-    "block_dot": ("k_block_dot<", "la.hip"),
+    "block_dot": (("k_block_dot<", "k_block_dot_wide<"), "la.hip"),
     "block_update": ("k_block_update<", "la.hip"),
     "spmv_J": ("k_spmv_J<float>", "fine.hip"),
     "vc0_pre": ("k_st25<double, float, 0>", "fine.hip"),
@@ -282,16 +282,18 @@ def pmc_summary(fetch_csv, write_csv, n, digests=None, levels=None, info=None):
     lines += ["", "family      launches  traffic/alg  source digest"]
     kern = info.get("kernels", {})
     for fam, (prefix, src) in FAMILIES.items():
+        prefixes = prefix if isinstance(prefix, tuple) else (prefix,)
+        named = [r for r in rows if any(p in r[0] for p in prefixes)]
         if fam in ("block_dot", "block_update"):
             # per-launch bytes vary with the basis length: the library's total over the run
-            sel = [r for r in rows if prefix in r[0]]
+            sel = named
             k = kern.get(fam)
             if not sel or not k or k["launches"] != sum(r[2] for r in sel):
                 continue
             meas = sum((r[3] + r[4]) * r[2] for r in sel)
             alg = k["bytes_per_launch"] * k["launches"]
         else:
-            sel = [r for r in rows if prefix in r[0] and r[5]]
+            sel = [r for r in named if r[5]]
             if not sel:
                 continue
             meas = sum((r[3] + r[4]) * r[2] for r in sel)

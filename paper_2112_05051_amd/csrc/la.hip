@@ -307,15 +307,19 @@ __global__ void __launch_bounds__(RED_THREADS) k_block_dot_small(const double *_
 // over the four waves (entry t by wave t mod 4) so that the accumulators of
 // GV <= 6 basis vectors stay within the register budget.  Same output layout.
 // The wave index is a template argument: each wave's Gram entries are fixed at
-// compile time and their accumulators stay in registers.
+// compile time and their accumulators stay in registers.  The round's vectors
+// are read from HBM once per block (each wave loads every fourth one into
+// LDS) instead of once per wave.
+typedef double d2v_t __attribute__((ext_vector_type(2)));
 template <int S, int GV, int G>
 __device__ __forceinline__ void block_dot_wave_wide(const double *__restrict__ V, int64_t ldv, int nv, bool gram,
                                                     const double *__restrict__ Q, int64_t n,
-                                                    double *__restrict__ partial, int mout) {
+                                                    double *__restrict__ partial, int mout,
+                                                    d2v_t (*__restrict__ qs)[S][WAVE]) {
     constexpr int NG = S * (S + 1) / 2;
     constexpr int NW = RED_THREADS / WAVE;
     constexpr int NGW = (NG - G + NW - 1) / NW;  // Gram entries of this wave: t = G, G + NW, ...
-    typedef double d2v __attribute__((ext_vector_type(2)));
+    typedef d2v_t d2v;
     const int lane = threadIdx.x % WAVE;
     constexpr int i0 = G * GV;
     const int ng = nv - i0 < GV ? (nv - i0 > 0 ? nv - i0 : 0) : GV;
@@ -327,13 +331,25 @@ __device__ __forceinline__ void block_dot_wave_wide(const double *__restrict__ V
 #pragma unroll
     for (int u = 0; u < NGW; u++) gm[u] = 0.0;
     const int64_t n2 = n >> 1;
-    for (int64_t c = (int64_t)blockIdx.x * WAVE + lane; c < n2; c += (int64_t)gridDim.x * WAVE) {
+    // block-uniform trip count (the barrier below); lanes past the end add zeros
+    int buf = 0;
+    for (int64_t base = (int64_t)blockIdx.x * WAVE; base < n2; base += (int64_t)gridDim.x * WAVE) {
+        const int64_t c = base + lane;
+        const bool act = c < n2;
+        const d2v zero = {0.0, 0.0};
         d2v q[S], v[GV];
+        // this wave's share of the round's vectors (k = G, G + NW, ...) into LDS
 #pragma unroll
-        for (int k = 0; k < S; k++) q[k] = reinterpret_cast<const d2v *>(Q + (size_t)k * ldv)[c];
+        for (int k = G; k < S; k += NW) qs[buf][k][lane] = act ? reinterpret_cast<const d2v *>(Q + (size_t)k * ldv)[c] : zero;
 #pragma unroll
         for (int i = 0; i < GV; i++)
-            if (i < ng) v[i] = __builtin_nontemporal_load(reinterpret_cast<const d2v *>(V + (size_t)(i0 + i) * ldv) + c);
+            if (i < ng)
+                v[i] = act ? __builtin_nontemporal_load(reinterpret_cast<const d2v *>(V + (size_t)(i0 + i) * ldv) + c)
+                           : zero;
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < S; k++) q[k] = qs[buf][k][lane];
+        buf ^= 1;  // the other buffer is next written after the next barrier
 #pragma unroll
         for (int i = 0; i < GV; i++)
             if (i < ng)
@@ -393,11 +409,12 @@ __device__ __forceinline__ void block_dot_body_wide(const double *__restrict__ V
                                                     const double *__restrict__ Q, int64_t n,
                                                     double *__restrict__ partial, int mout) {
     static_assert(RED_THREADS / WAVE == 4, "four waves per block");
+    __shared__ d2v_t qs[2][S][WAVE];  // the round's vectors at the block's rows, double-buffered
     switch (threadIdx.x / WAVE) {
-    case 0: block_dot_wave_wide<S, GV, 0>(V, ldv, nv, gram, Q, n, partial, mout); break;
-    case 1: block_dot_wave_wide<S, GV, 1>(V, ldv, nv, gram, Q, n, partial, mout); break;
-    case 2: block_dot_wave_wide<S, GV, 2>(V, ldv, nv, gram, Q, n, partial, mout); break;
-    default: block_dot_wave_wide<S, GV, 3>(V, ldv, nv, gram, Q, n, partial, mout); break;
+    case 0: block_dot_wave_wide<S, GV, 0>(V, ldv, nv, gram, Q, n, partial, mout, qs); break;
+    case 1: block_dot_wave_wide<S, GV, 1>(V, ldv, nv, gram, Q, n, partial, mout, qs); break;
+    case 2: block_dot_wave_wide<S, GV, 2>(V, ldv, nv, gram, Q, n, partial, mout, qs); break;
+    default: block_dot_wave_wide<S, GV, 3>(V, ldv, nv, gram, Q, n, partial, mout, qs); break;
     }
 }
 
