@@ -100,22 +100,15 @@ def host_cpu():
     return {"nproc": os.cpu_count(), "usable_cores": len(os.sched_getaffinity(0)), "model": model}
 
 
-def cpu_baseline(rec, ks, timed_stats, gmres_sample=5):
-    """The oracle (plain C, one thread) timed on a bounded sample of the
-    benchmark's own workload: on the recipe's initial state at its full grid,
+def oracle_unit_times(rec, ks, gmres_sample=5):
+    """Per-unit oracle times on the recipe's initial state at its full grid:
     one residual evaluation, one assembly of J and the auxiliary matrix, the
-    AMG set-up, one numeric refresh of the hierarchy and the first
-    `gmres_sample` iterations of a GMRES solve.  These per-unit times, weighted
-    by the counts of the GPU's timed steps (residual evaluations, rebuilds,
-    GMRES iterations; the GPU's counts equal the oracle's in the parity tests),
-    give the oracle's time per step.  Optimistic for the CPU: the sampled
-    GMRES iterations have the shortest Gram-Schmidt of a cycle, and set-up,
-    norms and line-search vector work are not counted."""
+    AMG set-up, one numeric refresh of the hierarchy and the mean of the first
+    `gmres_sample` iterations of a GMRES solve."""
     from oracle import oracle as orc
-    P, N = rec.problem, rec.problem.n
+    P = rec.problem
     p0 = rec.p0()
     t = {}
-    t0 = time.perf_counter()
     th = orc.theta(P, p0)
     t1 = time.perf_counter()
     F = orc.residual(P, ks, p0, th)
@@ -133,21 +126,71 @@ def cpu_baseline(rec, ks, timed_stats, gmres_sample=5):
     t0 = time.perf_counter()
     orc.gmres(J, -F, amg, rec.options.gmres_restart, rec.options.eta, gmres_sample)
     t["gmres_iteration"] = (time.perf_counter() - t0) / gmres_sample
+    return t
+
+
+def oracle_omp_unit_times(rec, ks, threads, gmres_sample=5):
+    """The same per-unit times with the OpenMP build of the oracle (its
+    per-row loops on `threads` cores; reductions serial, results identical),
+    in a child process that loads that build."""
+    import pickle
+    import subprocess
+    import tempfile
+
+    import numpy as np
+    with tempfile.TemporaryDirectory() as d:
+        np.save(os.path.join(d, "ks.npy"), ks)
+        with open(os.path.join(d, "recipe.pkl"), "wb") as f:
+            pickle.dump({"recipe": rec, "gmres_sample": gmres_sample}, f)
+        env = dict(os.environ, RICH_ORACLE_OMP="1", OMP_NUM_THREADS=str(threads))
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--oracle-units", d], env=env,
+                           capture_output=True, text=True, timeout=600)
+    if r.returncode != 0:
+        raise RuntimeError(f"oracle OpenMP leg failed: {r.stderr[-2000:]}")
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
+def cpu_baseline(rec, ks, timed_stats, gmres_sample=5):
+    """The oracle (plain C, one thread) timed on a bounded sample of the
+    benchmark's own workload: per-unit times (oracle_unit_times) weighted by
+    the counts of the GPU's timed steps (residual evaluations, rebuilds, GMRES
+    iterations; the GPU's counts equal the oracle's in the parity tests) give
+    the oracle's time per step.  Optimistic for the CPU: the sampled GMRES
+    iterations have the shortest Gram-Schmidt of a cycle, and set-up, norms
+    and line-search vector work are not counted.  The same figure for the
+    OpenMP build of the oracle on the host's cores is reported beside it."""
+    N = rec.problem.n
+    P = rec.problem
+    t = oracle_unit_times(rec, ks, gmres_sample)
     steps = max(len(timed_stats), 1)
     n_res = sum(s["bytes_feval"] for s in timed_stats) / (32.0 * N)
     n_build = sum(s["jac_builds"] for s in timed_stats)
     n_gmres = sum(s["gmres_its"] for s in timed_stats)
-    per_step = (n_res * t["residual"] + n_build * (t["assembly"] + t["refresh"]) +
-                n_gmres * t["gmres_iteration"]) / steps
-    return {"value": 1.0 / per_step, "unit": "time-steps/s", "cores": 1, "kind": "oracle",
-            "host": host_cpu(),
-            "sample": (f"per-unit oracle times on the {P.nx}x{P.ny}x{P.nz} recipe at its initial state "
-                       f"(residual {t['residual']:.1f} s, J+M assembly {t['assembly']:.1f} s, AMG set-up "
-                       f"{t['amg_setup']:.1f} s (not counted: once per run), refresh {t['refresh']:.1f} s, "
-                       f"GMRES iteration {t['gmres_iteration']:.2f} s over the first {gmres_sample}) weighted by "
-                       f"the GPU's timed steps: {n_res / steps:.1f} residuals, {n_build / steps:.2f} rebuilds, "
-                       f"{n_gmres / steps:.0f} GMRES iterations per step"),
-            "unit_seconds": t, "per_step_s": per_step}
+
+    def per_step(u):
+        return (n_res * u["residual"] + n_build * (u["assembly"] + u["refresh"]) +
+                n_gmres * u["gmres_iteration"]) / steps
+
+    ps = per_step(t)
+    out = {"value": 1.0 / ps, "unit": "time-steps/s", "cores": 1, "kind": "oracle",
+           "host": host_cpu(),
+           "sample": (f"per-unit oracle times on the {P.nx}x{P.ny}x{P.nz} recipe at its initial state "
+                      f"(residual {t['residual']:.1f} s, J+M assembly {t['assembly']:.1f} s, AMG set-up "
+                      f"{t['amg_setup']:.1f} s (not counted: once per run), refresh {t['refresh']:.1f} s, "
+                      f"GMRES iteration {t['gmres_iteration']:.2f} s over the first {gmres_sample}) weighted by "
+                      f"the GPU's timed steps: {n_res / steps:.1f} residuals, {n_build / steps:.2f} rebuilds, "
+                      f"{n_gmres / steps:.0f} GMRES iterations per step"),
+           "unit_seconds": t, "per_step_s": ps}
+    threads = int(os.environ.get("OMP_NUM_THREADS", 0) or len(os.sched_getaffinity(0)))
+    try:
+        u = oracle_omp_unit_times(rec, ks, threads, gmres_sample)
+        out["openmp"] = {"value": 1.0 / per_step(u), "unit": "time-steps/s", "cores": threads,
+                         "sample": "the same units with the OpenMP build of the oracle (per-row loops on all "
+                                   "cores; dot products, restriction and Galerkin sums serial)",
+                         "unit_seconds": u, "per_step_s": per_step(u)}
+    except Exception as e:  # the single-thread figure stands on its own
+        out["openmp"] = {"error": repr(e)[:500]}
+    return out
 
 
 # Kernel families of the per-kernel table: the library's timer name, the
@@ -488,6 +531,7 @@ def main():
                     help="one interface mean for every request (default: drawn per request)")
     ap.add_argument("--stats-summary", metavar="KERNEL_STATS_CSV",
                     help="print kernel time by family from a rocprofv3 --stats run and exit")
+    ap.add_argument("--oracle-units", metavar="DIR", help=argparse.SUPPRESS)
     ap.add_argument("--trace-gaps", metavar="KERNEL_TRACE_CSV",
                     help="print the GPU idle time between kernels of a rocprofv3 --kernel-trace run and exit")
     args = ap.parse_args()
@@ -496,6 +540,16 @@ def main():
         return
     if args.trace_gaps:
         print(trace_gaps(args.trace_gaps))
+        return
+    if args.oracle_units:
+        # child of the CPU baseline's OpenMP leg (the oracle build is chosen by the environment)
+        import pickle
+
+        import numpy as np
+        with open(os.path.join(args.oracle_units, "recipe.pkl"), "rb") as f:
+            job = pickle.load(f)
+        ks = np.load(os.path.join(args.oracle_units, "ks.npy"))
+        print(json.dumps(oracle_unit_times(job["recipe"], ks, job["gmres_sample"])), flush=True)
         return
     if args.pmc_summary:
         info = json.loads(open(args.pmc_summary[2]).read().strip().splitlines()[-1])

@@ -34,6 +34,17 @@
 #include <stdlib.h>
 #include <string.h>
 
+/* Loops whose iterations are independent (one cell, row or vector element  */
+/* each) may run on several threads in the OpenMP build of this file         */
+/* (liboracle_omp.so, used only to time the oracle on all host cores).       */
+/* Reductions (dot products, norms) and scatter-adds (restriction, Galerkin  */
+/* products) stay serial, so both builds give the same results bit for bit.  */
+#ifdef _OPENMP
+#define ORC_PARALLEL_FOR _Pragma("omp parallel for schedule(static)")
+#else
+#define ORC_PARALLEL_FOR
+#endif
+
 /* ------------------------------------------------------------------------ */
 /* Constitutive laws: Section 2, eq. (s(p)) with rho*phi = 1 so s is the     */
 /* volumetric water content theta, eq. (K(p)) with K_s per cell, derivatives  */
@@ -71,8 +82,9 @@ void orc_laws_array(const orc_problem *P, int64_t n, const double *p, const doub
 void orc_theta(const orc_problem *P, const double *p, double *theta)
 {
     int64_t n = (int64_t)P->nx * P->ny * P->nz;
-    double L[4];
+    ORC_PARALLEL_FOR
     for (int64_t c = 0; c < n; c++) {
+        double L[4];
         orc_laws(P, p[c], 1.0, L);
         theta[c] = L[0];
     }
@@ -236,10 +248,12 @@ void orc_face_mean(const orc_problem *P, int axis, int dir, double pc, double Ks
 void orc_residual(const orc_problem *P, const double *Ks, const double *p, const double *theta_old,
                   double *F)
 {
-    double Lc[4], Ln[4];
+    gl_init(); /* before any thread evaluates an integral mean */
+    ORC_PARALLEL_FOR
     for (int k = 0; k < P->nz; k++)
         for (int j = 0; j < P->ny; j++)
             for (int i = 0; i < P->nx; i++) {
+                double Lc[4], Ln[4];
                 int64_t c = (int64_t)i + (int64_t)P->nx * ((int64_t)j + (int64_t)P->ny * k);
                 orc_laws(P, p[c], Ks[c], Lc);
                 double acc = (Lc[0] - theta_old[c]) / P->dt;
@@ -279,13 +293,23 @@ static const int ORDER_HI[3] = {1, 3, 5}; /* +x, +y, +z */
 static void assemble(const orc_problem *P, const double *Ks, const double *p, int which,
                      int64_t *rowptr, int32_t *col, double *val)
 {
-    double Lc[4], Ln[4];
-    int64_t e = 0;
+    /* row c holds the cell and its neighbours inside the grid */
     rowptr[0] = 0;
     for (int k = 0; k < P->nz; k++)
         for (int j = 0; j < P->ny; j++)
             for (int i = 0; i < P->nx; i++) {
                 int64_t c = (int64_t)i + (int64_t)P->nx * ((int64_t)j + (int64_t)P->ny * k);
+                rowptr[c + 1] = rowptr[c] + 1 + (i > 0) + (i + 1 < P->nx) + (j > 0) + (j + 1 < P->ny) +
+                                (k > 0) + (k + 1 < P->nz);
+            }
+    gl_init(); /* before any thread evaluates an integral mean */
+    ORC_PARALLEL_FOR
+    for (int k = 0; k < P->nz; k++)
+        for (int j = 0; j < P->ny; j++)
+            for (int i = 0; i < P->nx; i++) {
+                double Lc[4], Ln[4];
+                int64_t c = (int64_t)i + (int64_t)P->nx * ((int64_t)j + (int64_t)P->ny * k);
+                int64_t e = rowptr[c];
                 orc_laws(P, p[c], Ks[c], Lc);
                 double diag = Lc[1] / P->dt;
                 double off[6];
@@ -334,7 +358,6 @@ static void assemble(const orc_problem *P, const double *Ks, const double *p, in
                         col[e] = (int32_t)nb[ORDER_HI[t]];
                         val[e++] = off[ORDER_HI[t]];
                     }
-                rowptr[c + 1] = e;
             }
 }
 
@@ -359,6 +382,7 @@ void orc_auxiliary_dflux(const orc_problem *P, const double *Ks, const double *p
 void orc_csr_matvec(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
                     const double *x, double *y)
 {
+    ORC_PARALLEL_FOR
     for (int64_t i = 0; i < n; i++) {
         double s = 0.0;
         for (int64_t e = rowptr[i]; e < rowptr[i + 1]; e++) s += val[e] * x[col[e]];
@@ -1211,15 +1235,18 @@ static void vcycle(const orc_amg *H, int l, const double *b, double *x)
         for (int64_t i = 0; i < n; i++) x[i] = 0.0;
         orc_mcgs_sweep(n, A->rowptr, A->col, A->val, H->color, H->ncolor, -1, b, x);
     } else {
+        ORC_PARALLEL_FOR
         for (int64_t i = 0; i < n; i++) x[i] = b[i] / d[i];
     }
     orc_csr_matvec(n, A->rowptr, A->col, A->val, x, r);
+    ORC_PARALLEL_FOR
     for (int64_t i = 0; i < n; i++) r[i] = b[i] - r[i];
     if (H->P[l].rowptr) { /* b_c = P^T r, then x += P x_c */
         const orc_csr *Pl = &H->P[l];
         for (int64_t i = 0; i < n; i++)
             for (int64_t f = Pl->rowptr[i]; f < Pl->rowptr[i + 1]; f++) bc[Pl->col[f]] += Pl->val[f] * r[i];
         vcycle(H, l + 1, bc, xc);
+        ORC_PARALLEL_FOR
         for (int64_t i = 0; i < n; i++) {
             double t = 0.0;
             for (int64_t f = Pl->rowptr[i]; f < Pl->rowptr[i + 1]; f++) t += Pl->val[f] * xc[Pl->col[f]];
@@ -1228,12 +1255,14 @@ static void vcycle(const orc_amg *H, int l, const double *b, double *x)
     } else {
         for (int64_t i = 0; i < n; i++) bc[agg[i]] += r[i];
         vcycle(H, l + 1, bc, xc);
+        ORC_PARALLEL_FOR
         for (int64_t i = 0; i < n; i++) x[i] += xc[agg[i]];
     }
     if (gs) { /* forward Gauss-Seidel sweep */
         orc_mcgs_sweep(n, A->rowptr, A->col, A->val, H->color, H->ncolor, +1, b, x);
     } else {
         orc_csr_matvec(n, A->rowptr, A->col, A->val, x, r);
+        ORC_PARALLEL_FOR
         for (int64_t i = 0; i < n; i++) x[i] += (b[i] - r[i]) / d[i];
     }
     free(r);
@@ -1282,6 +1311,7 @@ int orc_gmres(int64_t n, const int64_t *rowptr, const int32_t *col, const double
     for (;;) {
         /* true residual r = b - J x, kept in V_0 */
         orc_csr_matvec(n, rowptr, col, val, x, w);
+        ORC_PARALLEL_FOR
         for (int64_t i = 0; i < n; i++) V[i] = b[i] - w[i];
         double beta = sqrt(dot(n, V, V));
         relres = beta / bnorm;
@@ -1290,6 +1320,7 @@ int orc_gmres(int64_t n, const int64_t *rowptr, const int32_t *col, const double
             break;
         }
         if (total >= maxit) break;
+        ORC_PARALLEL_FOR
         for (int64_t i = 0; i < n; i++) V[i] /= beta;
         for (int i = 0; i <= m; i++) g[i] = 0.0;
         g[0] = beta;
@@ -1303,12 +1334,14 @@ int orc_gmres(int64_t n, const int64_t *rowptr, const int32_t *col, const double
                 double *vi = V + (size_t)i * n;
                 double h = dot(n, w, vi);
                 Hm[i * m + j] = h;
+                ORC_PARALLEL_FOR
                 for (int64_t t = 0; t < n; t++) w[t] -= h * vi[t];
             }
             double hn = sqrt(dot(n, w, w));
             Hm[(j + 1) * m + j] = hn;
             if (hn > 0.0) {
                 double *vn = V + (size_t)(j + 1) * n;
+                ORC_PARALLEL_FOR
                 for (int64_t t = 0; t < n; t++) vn[t] = w[t] / hn;
             }
             for (int i = 0; i < j; i++) {
@@ -1333,13 +1366,15 @@ int orc_gmres(int64_t n, const int64_t *rowptr, const int32_t *col, const double
             for (int t = i + 1; t < k; t++) s -= Hm[i * m + t] * y[t];
             y[i] = s / Hm[i * m + i];
         }
-        for (int64_t t = 0; t < n; t++) w[t] = 0.0;
-        for (int i = 0; i < k; i++) {
-            double *vi = V + (size_t)i * n;
-            for (int64_t t = 0; t < n; t++) w[t] += y[i] * vi[t];
+        ORC_PARALLEL_FOR
+        for (int64_t t = 0; t < n; t++) {
+            double s = 0.0; /* the basis combination in ascending i, as a serial loop adds it */
+            for (int i = 0; i < k; i++) s += y[i] * V[(size_t)i * n + t];
+            w[t] = s;
         }
         if (H) orc_amg_apply(H, w, z);
         else memcpy(z, w, (size_t)n * sizeof(double));
+        ORC_PARALLEL_FOR
         for (int64_t t = 0; t < n; t++) x[t] += z[t];
     }
 done:

@@ -14,6 +14,7 @@ import scipy.sparse as sp
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
+OMP_LIB_PATH = os.path.join(HERE, "liboracle_omp.so")  # the same source built with OpenMP (timing only)
 SRC = os.path.join(HERE, "oracle.c")
 
 OK, EINVAL, ENOMEM, NONFINITE = 0, -1, -2, -4
@@ -21,12 +22,15 @@ LINSOLVE_FAIL, LINESEARCH_FAIL, MAXITER, STEP_TOO_SMALL, NOT_SPD = -5, -6, -7, 2
 
 
 def build(force: bool = False) -> str:
-    """Compile liboracle.so with gcc (plain -O2, no fast-math, no FMA contraction)."""
-    if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC):
-        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", SRC, "-o",
-               LIB_PATH + ".tmp", "-lm"]
-        subprocess.run(cmd, check=True)
-        os.replace(LIB_PATH + ".tmp", LIB_PATH)
+    """Compile liboracle.so with gcc (plain -O2, no fast-math, no FMA contraction),
+    and liboracle_omp.so, the same source with OpenMP (per-row loops on all
+    host cores, results identical bit for bit; used only for timing)."""
+    for path, extra in ((LIB_PATH, []), (OMP_LIB_PATH, ["-fopenmp"])):
+        if force or not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(SRC):
+            cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", *extra, SRC, "-o",
+                   path + ".tmp", "-lm"]
+            subprocess.run(cmd, check=True)
+            os.replace(path + ".tmp", path)
     return LIB_PATH
 
 
@@ -90,7 +94,8 @@ def lib():
     global _lib
     if _lib is None:
         build()
-        L = C.CDLL(LIB_PATH)
+        # RICH_ORACLE_OMP=1: the OpenMP build (the benchmark's multi-core CPU timing)
+        L = C.CDLL(OMP_LIB_PATH if os.environ.get("RICH_ORACLE_OMP") == "1" else LIB_PATH)
         P = C.POINTER
         d, i64, i32 = P(C.c_double), P(C.c_int64), P(C.c_int32)
         vp = C.c_void_p
