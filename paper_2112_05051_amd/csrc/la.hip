@@ -418,6 +418,14 @@ __device__ __forceinline__ void block_dot_body_wide(const double *__restrict__ V
     }
 }
 
+// Launches with at most this many basis vectors per wave take the copy
+// compiled for the default occupancy also on long vectors: their few
+// accumulators leave room for four waves per SIMD, whose loads in flight
+// pay more than the hoisted loads of the two-wave schedule (256^3, rounds of
+// up to 10: 621 -> 556 us per round's dots).
+#ifndef WIDE_DOT_DEFAULT_OCC_GV
+#define WIDE_DOT_DEFAULT_OCC_GV 2
+#endif
 template <int S, int GV>
 __global__ void __launch_bounds__(RED_THREADS) RED_WPE_ATTR k_block_dot_wide(const double *__restrict__ V,
                                                                            int64_t ldv, int nv, bool gram,
@@ -825,7 +833,7 @@ rich_status launch_block_dot(const double *V, int64_t ldv, int nv, const double 
 #undef XG
 #define XG(SS, G)                                                                                              \
     case SS * 16 + G:                                                                                          \
-        if (wide)                                                                                              \
+        if (wide && G > WIDE_DOT_DEFAULT_OCC_GV)                                                               \
             k_block_dot_wide<SS, G><<<RED_BLOCKS, RED_THREADS, 0, s>>>(Vc, ldv, nc, gram, Q, n, pc, mout);       \
         else                                                                                                   \
             k_block_dot_wide_small<SS, G><<<RED_BLOCKS, RED_THREADS, 0, s>>>(Vc, ldv, nc, gram, Q, n, pc, mout); \
