@@ -198,7 +198,7 @@ def cpu_baseline(rec, ks, timed_stats, gmres_sample=5):
 FAMILIES = {
     "update": ("k_update_norm<", "la.hip"),
     "multidot": ("k_multidot<", "la.hip"),
-    "block_dot": (("k_block_dot<", "k_block_dot_wide<"), "la.hip"),
+    "block_dot": (("k_block_dot<", "k_block_dot_wide<", "k_block_dot_wide_small<"), "la.hip"),
     "block_update": ("k_block_update<", "la.hip"),
     "spmv_J": ("k_spmv_J<float>", "fine.hip"),
     "vc0_pre": ("k_st25<double, float, 0>", "fine.hip"),
